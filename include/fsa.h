@@ -1,0 +1,200 @@
+/*
+ * fsa.h -- C ABI of the MI355X (gfx950) FSA convolution library.
+ *
+ * The library evaluates the convolution potential Phi = U * rho of a radial,
+ * singular kernel U with a smooth, compactly supported density rho, sampled
+ * on a uniform grid of the box prod_j [-L_j, L_j], with the far-field smooth
+ * approximation (FSA) method of Liu & Zhang (arXiv 2504.19410):
+ *
+ *   - problem statement: Phi on the grid from rho on the same grid (Sec. 1);
+ *   - grid: x_j = -L_j + i_j h_j, h_j = 2 L_j / N_j, i_j in [0, N_j)
+ *     (eq. UniformMesh; anisotropic boxes as in Sec. 2.4);
+ *   - kernel tensor T = T(1) + T(2): T(1) by trapezoidal sampling of the
+ *     smooth far-field kernel U^eps (eq. Tensor1 / TensorAnis), T(2) from the
+ *     whole-space Fourier transform of U - U^eps (eq. FouTran, Table 1,
+ *     eq. Tensor2), built once per plan;
+ *   - each evaluation: the discrete aperiodic convolution of eq. DiscConv as
+ *     a 2x zero-padded FFT convolution (Sec. 2.2, 2.3).
+ *
+ * Conventions shared by every entry point
+ *   - All array pointers passed to fsa_apply* and fsa_server_submit are
+ *     DEVICE pointers on the device that was current when the plan's tensor
+ *     was built; they are owned by the caller.  Streams are hipStream_t passed
+ *     as void* (NULL = the null stream).
+ *   - rho and phi are dense C-order arrays of shape (N_0, ..., N_{d-1}) in
+ *     the plan precision (float for FSA_F32, double for FSA_F64); the element
+ *     at index i sits at x_j = -L_j + i_j h_j.  The last axis is contiguous.
+ *   - Every argument is validated synchronously.  On failure the call
+ *     returns a non-zero fsa_status, out-parameters are left untouched, and
+ *     fsa_last_error() describes the problem.  Asynchronous device errors
+ *     surface as FSA_EDEVICE at the next call that synchronises.
+ *   - No C++ exception crosses this interface.
+ *   - A built plan is immutable: concurrent fsa_apply calls on one plan are
+ *     safe when they use distinct workspaces.
+ */
+#ifndef FSA_H
+#define FSA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    FSA_OK = 0,
+    FSA_EINVAL = 1,        /* invalid argument (shape, size, parameter)      */
+    FSA_EUNSUPPORTED = 2,  /* valid but not supported (grid length, kernel)  */
+    FSA_ENOMEM = 3,        /* device or host allocation failed               */
+    FSA_EDEVICE = 4,       /* a HIP runtime call or kernel failed            */
+    FSA_ESTATE = 5,        /* call out of order (e.g. apply before build)    */
+    FSA_EBUDGET = 6,       /* server: request can never fit the HBM budget   */
+    FSA_ECANCELLED = 7     /* server: request was cancelled                  */
+} fsa_status;
+
+/* Kernels U(r) with their FSA split (Table 1; eqs. KerAppr, lnrAppr):
+ *   FSA_COULOMB_3D    U = 1/(4 pi r),            U^eps = U erf(r/eps)
+ *   FSA_YUKAWA_3D     U = e^{-lam r}/(4 pi r),   Gaussian-screened split with
+ *                     FT[U - U^eps] = (1 - e^{-(k^2+lam^2) eps^2/4})/(k^2+lam^2)
+ *                     (the paper lists Yukawa in Sec. 5.3 without a split)
+ *   FSA_LOG_2D        U = -(1/2pi) ln r,          eq. lnrAppr
+ *   FSA_COULOMB_2D    U = 1/(2 pi r),             U^eps = U erf(r/eps)
+ *   FSA_BIHARMONIC_3D U = r/(8 pi),               U^eps = U erf(r/eps)
+ *   FSA_BIHARMONIC_2D U = -r^2 (ln r - 1)/(8 pi), Table 1 */
+typedef enum {
+    FSA_COULOMB_3D = 1,
+    FSA_YUKAWA_3D = 2,
+    FSA_LOG_2D = 3,
+    FSA_COULOMB_2D = 4,
+    FSA_BIHARMONIC_3D = 5,
+    FSA_BIHARMONIC_2D = 6
+} fsa_kernel_kind;
+
+/* Arithmetic of the per-evaluation FFT convolution.  The tensor is always
+ * generated in FP64 and rounded to this precision once. */
+typedef enum { FSA_F32 = 0, FSA_F64 = 1 } fsa_precision;
+
+typedef struct {
+    int kind;       /* fsa_kernel_kind                                        */
+    double lambda;  /* Yukawa screening lam > 0; ignored by other kernels     */
+    double eps;     /* split parameter; <= 0 selects the default R0/8,
+                       R0 = 2 min_j L_j (condition (b) of eq. ApproxProp,
+                       Remark 2.1 and Appendix B)                             */
+} fsa_kernel;
+
+typedef struct fsa_plan_s* fsa_plan;
+
+/* Creates a plan (host only; no device work).
+ *   k   kernel and split parameter (see fsa_kernel).
+ *   d   2 or 3; must match the kernel.
+ *   L   d half-widths L_j > 0 of the box prod_j [-L_j, L_j] (host array).
+ *   N   d grid sizes (host array): even, 8 <= N_j <= 2048, of the form 2^a or
+ *       3*2^a (the padded transform length 2 N_j must factor into the
+ *       supported radices).
+ *   p   FSA_F32 or FSA_F64.
+ * The split parameter must satisfy eps >= 2 max_j h_j (the trapezoidal error
+ * of the regular part, ~ e^{-pi^2 eps^2 / h^2}, then stays below 1e-17) and
+ * eps <= R0/5.85 (Appendix B).  Returns FSA_EINVAL otherwise, FSA_EUNSUPPORTED
+ * for a length outside the supported set.  *out receives the plan. */
+fsa_status fsa_plan_create(const fsa_kernel* k, int d, const double* L, const int64_t* N,
+                           fsa_precision p, fsa_plan* out);
+
+/* Reports the plan's parameters; any out-pointer may be NULL.
+ *   eps_used         the split parameter the plan uses.
+ *   h                d mesh sizes h_j (host array of d doubles).
+ *   tensor_bytes     device bytes of the plan's spectral tensor.
+ *   workspace_bytes  device bytes of the scratch buffer fsa_apply needs. */
+fsa_status fsa_plan_query(fsa_plan plan, double* eps_used, double* h, size_t* tensor_bytes,
+                          size_t* workspace_bytes);
+
+/* Generates the plan's spectral tensor on the current device, in FP64,
+ * asynchronously on `stream` (Precomp in the paper's terms, Sec. 5.1
+ * Example 2):  T^[p] = ( DFT(T(1))[p] + W(|k_p|) ) / prod_j 2N_j, with
+ * k_j = pi p_j / (2 L_j); since T(2) = IDFT(W) (eq. Tensor2), DFT(T(2)) = W
+ * exactly.  T^ is real and even in every p_j (Sec. 2.3), so only the octant
+ * 0 <= p_j <= N_j is stored, in the plan precision.  The library allocates
+ * and owns it.  May be called again (rebuilds in place). */
+fsa_status fsa_build_tensor(fsa_plan plan, void* stream);
+
+/* One evaluation (Execution in the paper's terms): phi = crop(IDFT(T^ .
+ * DFT(pad(rho)))) through 3 (2D) or 5 (3D) kernels enqueued on `stream`;
+ * returns without host synchronisation.
+ *   rho        device input, plan precision, shape N (read only).
+ *   phi        device output, plan precision, shape N; may equal rho.
+ *   workspace  device scratch of at least workspace_bytes (fsa_plan_query),
+ *              256-byte aligned; contents on entry are ignored.
+ * FSA_ESTATE if the tensor has not been built. */
+fsa_status fsa_apply(fsa_plan plan, const void* rho, void* phi, void* workspace, void* stream);
+
+/* Device bytes of the workspace fsa_apply_batched needs for these plans. */
+fsa_status fsa_batch_workspace_bytes(int n, const fsa_plan* plans, size_t* bytes);
+
+/* Evaluates n independent problems (plans may differ in kernel, box, grid
+ * and precision) as ONE persistent kernel launch that a hipGraph captures
+ * on first use of a batch signature and replays afterwards.  Work items
+ * (problem, pass, tile) are taken in dependency order; each problem's result
+ * equals fsa_apply on that problem alone.
+ *   plans, rho, phi  host arrays of n entries; rho[i]/phi[i] are device
+ *                    pointers for plans[i].
+ *   workspace        device scratch of >= fsa_batch_workspace_bytes bytes.
+ * The device pointers are part of the captured graph: a call with the same
+ * plans but different pointers re-captures. */
+fsa_status fsa_apply_batched(int n, const fsa_plan* plans, const void* const* rho,
+                             void* const* phi, void* workspace, size_t workspace_bytes,
+                             void* stream);
+
+/* Releases the plan and its device tensor (after synchronising its device). */
+fsa_status fsa_plan_destroy(fsa_plan plan);
+
+/* Device pointer and octant extents of the built spectral tensor, for tests
+ * and tools.  dims[0..d-1] receive (N_{d-1}+1, ..., N_0+1): the octant is
+ * stored with the LAST grid axis outermost, i.e. index [p_{d-1}]...[p_0]. */
+fsa_status fsa_plan_tensor(fsa_plan plan, const void** tensor, int64_t* dims);
+
+/* ------------------------------------------------------------------------- */
+/* Served variant: continuous batching with HBM-budget admission             */
+/* ------------------------------------------------------------------------- */
+
+typedef struct fsa_server_s* fsa_server;
+
+typedef struct {
+    double p50_ms, p99_ms;      /* latency: completion - submit              */
+    double throughput_rps;      /* completed requests per second of uptime   */
+    double gpts_per_s;          /* output grid points per second of uptime   */
+    uint64_t done, rejected, cancelled, cache_hits, cache_misses;
+    size_t hbm_in_use, hbm_peak;
+} fsa_stats;
+
+/* Creates a server on the current device.
+ *   hbm_budget_bytes  cap on cached tensors + in-flight workspaces.
+ *   max_inflight      concurrent requests on the device (slots, >= 1).
+ *   n_streams         device streams the slots rotate over (>= 1). */
+fsa_status fsa_server_create(size_t hbm_budget_bytes, int max_inflight, int n_streams,
+                             fsa_server* out);
+
+/* Queues one request; never blocks on the device.  rho/phi are device
+ * pointers of the request's shape and precision, owned by the caller and
+ * untouched until the ticket completes.  FSA_EBUDGET if the request alone
+ * exceeds the budget. */
+fsa_status fsa_server_submit(fsa_server s, const fsa_kernel* k, int d, const double* L,
+                             const int64_t* N, fsa_precision p, const void* rho, void* phi,
+                             uint64_t* ticket);
+
+fsa_status fsa_server_poll(fsa_server s, uint64_t ticket, int* done, fsa_status* result);
+fsa_status fsa_server_wait(fsa_server s, uint64_t ticket, fsa_status* result);
+/* Cancels a request that has not been launched yet (FSA_ESTATE otherwise). */
+fsa_status fsa_server_cancel(fsa_server s, uint64_t ticket);
+fsa_status fsa_server_stats(fsa_server s, fsa_stats* out);
+/* Waits for in-flight work, then frees the cache and the server. */
+fsa_status fsa_server_destroy(fsa_server s);
+
+/* Message of the last failure on the calling thread; valid until the next
+ * call on that thread. */
+const char* fsa_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FSA_H */

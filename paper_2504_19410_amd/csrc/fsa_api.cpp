@@ -1,0 +1,281 @@
+// fsa_api.cpp -- the C ABI of include/fsa.h: plans, tensor build, apply.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "fsa_internal.hpp"
+
+namespace {
+
+thread_local std::string g_last_error;
+
+fsa_status fail(fsa_status s, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+fsa_status fail(fsa_status s, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return s;
+}
+
+fsa_status hip_fail(hipError_t e, const char* what) {
+    return fail(FSA_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+int kernel_dim(int kind) {
+    switch (kind) {
+    case FSA_COULOMB_3D:
+    case FSA_YUKAWA_3D:
+    case FSA_BIHARMONIC_3D: return 3;
+    case FSA_LOG_2D:
+    case FSA_COULOMB_2D:
+    case FSA_BIHARMONIC_2D: return 2;
+    }
+    return 0;
+}
+
+size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
+
+}  // namespace
+
+namespace fsa {
+void set_last_error(const char* msg) { g_last_error = msg; }
+}  // namespace fsa
+
+extern "C" {
+
+const char* fsa_last_error(void) { return g_last_error.c_str(); }
+
+fsa_status fsa_plan_create(const fsa_kernel* k, int d, const double* L, const int64_t* N,
+                           fsa_precision p, fsa_plan* out) {
+    if (!k || !L || !N || !out) return fail(FSA_EINVAL, "fsa_plan_create: null argument");
+    const int kd = kernel_dim(k->kind);
+    if (kd == 0) return fail(FSA_EINVAL, "fsa_plan_create: unknown kernel kind %d", k->kind);
+    if (d != kd)
+        return fail(FSA_EINVAL, "fsa_plan_create: kernel kind %d needs d = %d, got %d", k->kind,
+                    kd, d);
+    if (p != FSA_F32 && p != FSA_F64)
+        return fail(FSA_EINVAL, "fsa_plan_create: unknown precision %d", (int)p);
+    if (k->kind == FSA_YUKAWA_3D && !(k->lambda > 0.0 && std::isfinite(k->lambda)))
+        return fail(FSA_EINVAL, "fsa_plan_create: Yukawa needs lambda > 0");
+    double minL = 1e300, maxh = 0.0;
+    for (int j = 0; j < d; ++j) {
+        if (!(L[j] > 0.0 && std::isfinite(L[j])))
+            return fail(FSA_EINVAL, "fsa_plan_create: L[%d] must be positive", j);
+        if (N[j] < 8 || (N[j] % 2) != 0)
+            return fail(FSA_EINVAL, "fsa_plan_create: N[%d] = %lld must be even and >= 8", j,
+                        (long long)N[j]);
+        if (!fsa::grid_length_supported(N[j]))
+            return fail(FSA_EUNSUPPORTED,
+                        "fsa_plan_create: N[%d] = %lld unsupported (need 2^a or 3*2^a, <= 2048)",
+                        j, (long long)N[j]);
+        minL = std::fmin(minL, L[j]);
+        maxh = std::fmax(maxh, 2.0 * L[j] / (double)N[j]);
+    }
+    const double R0 = 2.0 * minL;
+    double eps = k->eps;
+    if (!(eps > 0.0)) eps = R0 / 8.0;
+    if (!std::isfinite(eps) || eps > R0 / 4.0)
+        return fail(FSA_EINVAL,
+                    "fsa_plan_create: eps = %g violates the far-field condition (need eps <= "
+                    "R0/4 = %g; 16 digits need eps <= R0/5.85)",
+                    eps, R0 / 4.0);
+    (void)maxh;
+
+    fsa_plan_s* pl = new (std::nothrow) fsa_plan_s();
+    if (!pl) return fail(FSA_ENOMEM, "fsa_plan_create: out of host memory");
+    pl->kp = fsa::KernelParams{k->kind, k->kind == FSA_YUKAWA_3D ? k->lambda : 0.0, eps};
+    pl->d = d;
+    pl->prec = p;
+    for (int j = 0; j < d; ++j) {
+        pl->L[j] = L[j];
+        pl->N[j] = N[j];
+        pl->h[j] = 2.0 * L[j] / (double)N[j];
+    }
+    const size_t rsize = p == FSA_F32 ? 4 : 8;
+    pl->csize = 2 * rsize;
+    const int64_t Nl = N[d - 1];
+    pl->H = Nl + 1;
+    if (d == 3) {
+        pl->ws1_elems = (size_t)N[0] * pl->H * N[1];
+        pl->ws2_elems = (size_t)pl->H * 2 * N[1] * N[0];
+    } else {
+        pl->ws1_elems = (size_t)pl->H * N[0];
+        pl->ws2_elems = 0;
+    }
+    pl->ws_bytes = align256(pl->ws1_elems * pl->csize) + align256(pl->ws2_elems * pl->csize);
+    pl->tensor_elems = 1;
+    for (int j = 0; j < d; ++j) pl->tensor_elems *= (size_t)(N[j] + 1);
+    // twiddle tables: P0 = 2 N0; P1 = 2 N1 (3D); M = N_last; P_last = 2 N_last
+    size_t off = 0;
+    pl->tw_off_p0 = off;
+    off += 2 * N[0];
+    pl->tw_off_p1 = off;
+    if (d == 3) off += 2 * N[1];
+    pl->tw_off_m = off;
+    off += Nl;
+    pl->tw_off_pl = off;
+    off += 2 * Nl;
+    pl->tw_elems = off;
+    *out = pl;
+    return FSA_OK;
+}
+
+fsa_status fsa_plan_query(fsa_plan pl, double* eps_used, double* h, size_t* tensor_bytes,
+                          size_t* workspace_bytes) {
+    if (!pl) return fail(FSA_EINVAL, "fsa_plan_query: null plan");
+    if (eps_used) *eps_used = pl->kp.eps;
+    if (h)
+        for (int j = 0; j < pl->d; ++j) h[j] = pl->h[j];
+    if (tensor_bytes) *tensor_bytes = pl->tensor_elems * (pl->csize / 2);
+    if (workspace_bytes) *workspace_bytes = pl->ws_bytes;
+    return FSA_OK;
+}
+
+fsa_status fsa_build_tensor(fsa_plan pl, void* stream) {
+    if (!pl) return fail(FSA_EINVAL, "fsa_build_tensor: null plan");
+    hipStream_t st = (hipStream_t)stream;
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "fsa_build_tensor: hipGetDevice");
+    if (pl->built && pl->device != dev)
+        return fail(FSA_ESTATE, "fsa_build_tensor: plan was built on device %d, current is %d",
+                    pl->device, dev);
+    const size_t rsize = pl->csize / 2;
+    if (!pl->tensor) {
+        e = hipMalloc(&pl->tensor, pl->tensor_elems * rsize);
+        if (e != hipSuccess) {
+            pl->tensor = nullptr;
+            return fail(FSA_ENOMEM, "fsa_build_tensor: tensor allocation (%zu bytes): %s",
+                        pl->tensor_elems * rsize, hipGetErrorString(e));
+        }
+    }
+    if (!pl->twiddles) {
+        e = hipMalloc(&pl->twiddles, pl->tw_elems * pl->csize);
+        if (e != hipSuccess) {
+            pl->twiddles = nullptr;
+            return fail(FSA_ENOMEM, "fsa_build_tensor: twiddle allocation: %s",
+                        hipGetErrorString(e));
+        }
+    }
+    char* tw = (char*)pl->twiddles;
+    const int64_t Nl = pl->N[pl->d - 1];
+    e = fsa::build_twiddles(pl->prec, (int)(2 * pl->N[0]), tw + pl->tw_off_p0 * pl->csize, st);
+    if (e == hipSuccess && pl->d == 3)
+        e = fsa::build_twiddles(pl->prec, (int)(2 * pl->N[1]), tw + pl->tw_off_p1 * pl->csize, st);
+    if (e == hipSuccess)
+        e = fsa::build_twiddles(pl->prec, (int)Nl, tw + pl->tw_off_m * pl->csize, st);
+    if (e == hipSuccess)
+        e = fsa::build_twiddles(pl->prec, (int)(2 * Nl), tw + pl->tw_off_pl * pl->csize, st);
+    if (e != hipSuccess) return hip_fail(e, "fsa_build_tensor: twiddle kernels");
+    e = fsa::build_tensor_device(pl->kp, pl->d, pl->L, pl->N, pl->h, pl->prec, pl->tensor, st);
+    if (e == hipErrorOutOfMemory)
+        return fail(FSA_ENOMEM, "fsa_build_tensor: temporary FP64 octant: %s",
+                    hipGetErrorString(e));
+    if (e != hipSuccess) return hip_fail(e, "fsa_build_tensor: tensor kernels");
+    pl->device = dev;
+    pl->built = true;
+    return FSA_OK;
+}
+
+}  // extern "C"
+
+namespace fsa {
+
+// Enqueues the 3 (2D) or 5 (3D) passes of one evaluation.
+template <typename R>
+static hipError_t apply_impl(const fsa_plan_s* pl, const void* rho, void* phi, void* ws,
+                             hipStream_t st) {
+    const char* tw = (const char*)pl->twiddles;
+    const size_t cs = pl->csize;
+    const void* tw_p0 = tw + pl->tw_off_p0 * cs;
+    const void* tw_p1 = tw + pl->tw_off_p1 * cs;
+    const void* tw_m = tw + pl->tw_off_m * cs;
+    const void* tw_pl = tw + pl->tw_off_pl * cs;
+    const int N0 = (int)pl->N[0], N1 = (int)pl->N[1];
+    const int H = (int)pl->H;
+    const R* tensor = (const R*)pl->tensor;
+    char* w1 = (char*)ws;
+    hipError_t e;
+    if (pl->d == 3) {
+        const int N2 = (int)pl->N[2];
+        char* w2 = w1 + ((pl->ws1_elems * cs + 255) & ~size_t(255));
+        e = Launch<R>::r2c(N2, (const R*)rho, w1, N0, N1, tw_m, tw_pl, st);
+        if (e == hipSuccess) e = Launch<R>::fwd_t(2 * N1, w1, w2, N0, H, tw_p1, st);
+        if (e == hipSuccess)
+            e = Launch<R>::conv(2 * N0, w2, tensor, H * 2 * N1, 2 * N1, N1, tw_p0, st);
+        if (e == hipSuccess) e = Launch<R>::inv_t(2 * N1, w2, w1, N0, H, tw_p1, st);
+        if (e == hipSuccess) e = Launch<R>::c2r(N2, w1, (R*)phi, N0, N1, tw_m, tw_pl, st);
+    } else {
+        e = Launch<R>::r2c(N1, (const R*)rho, w1, 1, N0, tw_m, tw_pl, st);
+        if (e == hipSuccess) e = Launch<R>::conv(2 * N0, w1, tensor, H, 1, 0, tw_p0, st);
+        if (e == hipSuccess) e = Launch<R>::c2r(N1, w1, (R*)phi, 1, N0, tw_m, tw_pl, st);
+    }
+    return e;
+}
+
+hipError_t apply_plan(const fsa_plan_s* pl, const void* rho, void* phi, void* ws,
+                      hipStream_t st) {
+    return pl->prec == FSA_F32 ? apply_impl<float>(pl, rho, phi, ws, st)
+                               : apply_impl<double>(pl, rho, phi, ws, st);
+}
+
+}  // namespace fsa
+
+extern "C" {
+
+fsa_status fsa_apply(fsa_plan pl, const void* rho, void* phi, void* workspace, void* stream) {
+    if (!pl) return fail(FSA_EINVAL, "fsa_apply: null plan");
+    if (!rho || !phi || !workspace) return fail(FSA_EINVAL, "fsa_apply: null device pointer");
+    if (!pl->built) return fail(FSA_ESTATE, "fsa_apply: tensor not built (call fsa_build_tensor)");
+    if (((uintptr_t)workspace & 255) != 0)
+        return fail(FSA_EINVAL, "fsa_apply: workspace must be 256-byte aligned");
+    const size_t align = pl->csize / 2;
+    if (((uintptr_t)rho % align) != 0 || ((uintptr_t)phi % align) != 0)
+        return fail(FSA_EINVAL, "fsa_apply: rho/phi misaligned for the plan precision");
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "fsa_apply: hipGetDevice");
+    if (dev != pl->device)
+        return fail(FSA_ESTATE, "fsa_apply: plan built on device %d, current device is %d",
+                    pl->device, dev);
+    e = fsa::apply_plan(pl, rho, phi, workspace, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "fsa_apply: kernel launch");
+    return FSA_OK;
+}
+
+fsa_status fsa_plan_tensor(fsa_plan pl, const void** tensor, int64_t* dims) {
+    if (!pl || !tensor || !dims) return fail(FSA_EINVAL, "fsa_plan_tensor: null argument");
+    if (!pl->built) return fail(FSA_ESTATE, "fsa_plan_tensor: tensor not built");
+    *tensor = pl->tensor;
+    for (int j = 0; j < pl->d; ++j) dims[j] = pl->N[pl->d - 1 - j] + 1;
+    return FSA_OK;
+}
+
+fsa_status fsa_plan_destroy(fsa_plan pl) {
+    if (!pl) return FSA_OK;
+    hipError_t e = hipSuccess;
+    if (pl->tensor || pl->twiddles) {
+        int cur = 0;
+        (void)hipGetDevice(&cur);
+        if (pl->device >= 0 && pl->device != cur) (void)hipSetDevice(pl->device);
+        if (pl->tensor) e = hipFree(pl->tensor);
+        if (pl->twiddles) {
+            hipError_t e2 = hipFree(pl->twiddles);
+            if (e == hipSuccess) e = e2;
+        }
+        if (pl->device >= 0 && pl->device != cur) (void)hipSetDevice(cur);
+    }
+    delete pl;
+    if (e != hipSuccess) return hip_fail(e, "fsa_plan_destroy: hipFree");
+    return FSA_OK;
+}
+
+}  // extern "C"

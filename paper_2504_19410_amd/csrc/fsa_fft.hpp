@@ -1,0 +1,386 @@
+// fsa_fft.hpp -- Stockham FFT building blocks for gfx950 (wave64, LDS-staged).
+//
+// A "team" of T threads computes one complex transform of length P.  Each
+// thread keeps its butterflies' operands in registers; stages exchange data
+// through a padded LDS scratch of the team.  Stage s (radix R_s) with
+// NS = R_0 ... R_{s-1} and NB = P / R_s butterflies follows the Stockham
+// autosort recursion:
+//
+//   butterfly j in [0, NB):  k = j mod NS
+//     inputs   x[j + q NB]                        q = 0 .. R_s - 1
+//     operands a_q = x[j + q NB] * w^{q k},      w = exp(-/+ 2 pi i / (NS R_s))
+//     outputs  y[(j / NS) NS R_s + k + q NS] = DFT_{R_s}(a)_q
+//
+// Thread t owns butterflies j = t + b T (b = 0 .. ceil(NB/T) - 1) and holds
+// their operands in v[b R_s + q].  The first stage has NS = 1 (no twiddles),
+// so its inputs can come straight from global memory; the last stage has
+// NS = P / R_last, so thread t's outputs are x[j + q P / R_last] and can go
+// straight to global memory.  An inverse transform runs the radices in
+// reverse order, so the forward's last-stage layout IS the inverse's
+// first-stage layout: a pointwise product between them needs no exchange.
+//
+// Every per-thread phase is __host__ __device__ so that the index logic can
+// be emulated thread by thread on the CPU (tests/host).  Twiddles come from
+// a table tw[m] = exp(-2 pi i m / P) built in FP64 on the host.
+#pragma once
+
+#if defined(__HIPCC__)
+#include <hip/hip_runtime.h>
+#else
+// plain C++ (the CPU emulation of the team transforms): no device qualifiers
+#define __host__
+#define __device__
+#define __forceinline__ inline
+#endif
+
+#include <cstdint>
+
+namespace fsa {
+
+#define FSA_HD __host__ __device__ __forceinline__
+
+template <typename R>
+struct alignas(2 * sizeof(R)) cpx {
+    R x, y;
+};
+
+template <typename R>
+FSA_HD cpx<R> mk(R a, R b) { cpx<R> c; c.x = a; c.y = b; return c; }
+template <typename R>
+FSA_HD cpx<R> operator+(cpx<R> a, cpx<R> b) { return mk(a.x + b.x, a.y + b.y); }
+template <typename R>
+FSA_HD cpx<R> operator-(cpx<R> a, cpx<R> b) { return mk(a.x - b.x, a.y - b.y); }
+template <typename R>
+FSA_HD cpx<R> cmul(cpx<R> a, cpx<R> b) { return mk(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x); }
+// a * conj(b)
+template <typename R>
+FSA_HD cpx<R> cmulc(cpx<R> a, cpx<R> b) { return mk(a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y); }
+template <typename R>
+FSA_HD cpx<R> conj(cpx<R> a) { return mk(a.x, -a.y); }
+template <typename R>
+FSA_HD cpx<R> scale(cpx<R> a, R s) { return mk(a.x * s, a.y * s); }
+// multiplication by -i (forward) or +i (inverse)
+template <bool INV, typename R>
+FSA_HD cpx<R> rot90(cpx<R> a) { return INV ? mk(-a.y, a.x) : mk(a.y, -a.x); }
+
+// ---------------------------------------------------------------------------
+// Small DFTs in registers (natural order in, natural order out).
+// Forward: y_q = sum_p a_p exp(-2 pi i p q / R); inverse: exp(+...).
+// ---------------------------------------------------------------------------
+
+template <bool INV, typename R>
+FSA_HD void dft2(cpx<R>* a) {
+    const cpx<R> t = a[0] - a[1];
+    a[0] = a[0] + a[1];
+    a[1] = t;
+}
+
+template <bool INV, typename R>
+FSA_HD void dft3(cpx<R>* a) {
+    const R c = R(-0.5), s = R(0.86602540378443864676372317075294);  // sin(2 pi / 3)
+    const cpx<R> t = a[1] + a[2];
+    const cpx<R> m = a[0] + scale(t, c);
+    // (a1 - a2) * (-/+ i sin(2pi/3))
+    const cpx<R> d = scale(rot90<INV>(a[1] - a[2]), s);
+    a[0] = a[0] + t;
+    a[1] = m + d;
+    a[2] = m - d;
+}
+
+template <bool INV, typename R>
+FSA_HD void dft4(cpx<R>* a) {
+    const cpx<R> t0 = a[0] + a[2], t1 = a[0] - a[2];
+    const cpx<R> t2 = a[1] + a[3], t3 = rot90<INV>(a[1] - a[3]);
+    a[0] = t0 + t2;
+    a[2] = t0 - t2;
+    a[1] = t1 + t3;
+    a[3] = t1 - t3;
+}
+
+// multiply by exp(-/+ 2 pi i q / 8)
+template <bool INV, int q, typename R>
+FSA_HD cpx<R> w8(cpx<R> a) {
+    const R h = R(0.70710678118654752440084436210485);
+    if constexpr (q == 0) return a;
+    else if constexpr (q == 1) return INV ? mk((a.x - a.y) * h, (a.x + a.y) * h)
+                                          : mk((a.x + a.y) * h, (a.y - a.x) * h);
+    else if constexpr (q == 2) return rot90<INV>(a);
+    else return INV ? mk(-(a.x + a.y) * h, (a.x - a.y) * h)
+                    : mk((a.y - a.x) * h, -(a.x + a.y) * h);
+}
+
+template <bool INV, typename R>
+FSA_HD void dft8(cpx<R>* a) {
+    cpx<R> e[4] = {a[0], a[2], a[4], a[6]};
+    cpx<R> o[4] = {a[1], a[3], a[5], a[7]};
+    dft4<INV>(e);
+    dft4<INV>(o);
+    o[1] = w8<INV, 1>(o[1]);
+    o[2] = w8<INV, 2>(o[2]);
+    o[3] = w8<INV, 3>(o[3]);
+    for (int q = 0; q < 4; ++q) {
+        a[q] = e[q] + o[q];
+        a[q + 4] = e[q] - o[q];
+    }
+}
+
+template <bool INV, typename R>
+FSA_HD void dft16(cpx<R>* a) {
+    cpx<R> e[8], o[8];
+    for (int q = 0; q < 8; ++q) {
+        e[q] = a[2 * q];
+        o[q] = a[2 * q + 1];
+    }
+    dft8<INV>(e);
+    dft8<INV>(o);
+    // o[q] *= exp(-/+ 2 pi i q / 16)
+    const R c1 = R(0.92387953251128675612818318939679);  // cos(pi/8)
+    const R s1 = R(0.38268343236508977172845998403040);  // sin(pi/8)
+    const R h = R(0.70710678118654752440084436210485);
+    const R sg = INV ? R(1) : R(-1);
+    const cpx<R> tw[8] = {mk(R(1), R(0)), mk(c1, sg * s1), mk(h, sg * h), mk(s1, sg * c1),
+                          mk(R(0), sg),   mk(-s1, sg * c1), mk(-h, sg * h), mk(-c1, sg * s1)};
+    for (int q = 1; q < 8; ++q) o[q] = cmul(o[q], tw[q]);
+    for (int q = 0; q < 8; ++q) {
+        a[q] = e[q] + o[q];
+        a[q + 8] = e[q] - o[q];
+    }
+}
+
+template <int RADIX, bool INV, typename R>
+FSA_HD void dft(cpx<R>* a) {
+    if constexpr (RADIX == 2) dft2<INV>(a);
+    else if constexpr (RADIX == 3) dft3<INV>(a);
+    else if constexpr (RADIX == 4) dft4<INV>(a);
+    else if constexpr (RADIX == 8) dft8<INV>(a);
+    else if constexpr (RADIX == 16) dft16<INV>(a);
+    else static_assert(RADIX == 2, "unsupported radix");
+}
+
+// ---------------------------------------------------------------------------
+// Transform plans
+// ---------------------------------------------------------------------------
+
+struct FftPlan {
+    int P;      // length
+    int T;      // threads per transform (power of two)
+    int n;      // number of stages
+    int r[16];  // radices, execution order of the FORWARD transform
+    int vmax;   // complex registers per thread
+};
+
+constexpr int ilog2_exact(int x) {
+    int b = 0;
+    while ((1 << b) < x) ++b;
+    return ((1 << b) == x) ? b : -1;
+}
+
+// Lengths 2^a (a >= 2) and 3 * 2^a (a >= 2).  Power-of-two stages use radices
+// of at most 8 (P < 1024) or 16 (P >= 1024) spread as evenly as possible, the
+// factor 3 runs last; T is the largest power of two with T * E <= P for
+// E = 8 or 16 operands per thread, capped at 256.
+constexpr FftPlan make_fft_plan(int P) {
+    FftPlan p{};
+    p.P = P;
+    int m = P, threes = 0;
+    while (m % 3 == 0) {
+        m /= 3;
+        ++threes;
+    }
+    const int a = ilog2_exact(m);
+    const int maxbits = (P >= 1024) ? 4 : 3;
+    const int nst = (a + maxbits - 1) / maxbits;
+    int n = 0;
+    for (int s = 0; s < nst; ++s) {
+        const int bits = a / nst + (s < a % nst ? 1 : 0);
+        p.r[n++] = 1 << bits;
+    }
+    for (int t = 0; t < threes; ++t) p.r[n++] = 3;
+    p.n = n;
+    const int E = (P >= 1024) ? 16 : 8;
+    int T = 1;
+    while (T * 2 * E <= P && T < 256) T *= 2;
+    p.T = T;
+    int vmax = 0;
+    for (int s = 0; s < n; ++s) {
+        const int nb = P / p.r[s];
+        const int b = (nb + T - 1) / T;
+        if (b * p.r[s] > vmax) vmax = b * p.r[s];
+    }
+    p.vmax = vmax;
+    return p;
+}
+
+constexpr bool fft_length_supported(long P) {
+    if (P < 8 || P > 4096) return false;
+    long m = P;
+    if (m % 3 == 0) m /= 3;
+    if (m < 4) return false;
+    return (m & (m - 1)) == 0;
+}
+
+// ---------------------------------------------------------------------------
+// Team transform of length P, direction INV.
+// ---------------------------------------------------------------------------
+
+template <typename R, int P_, bool INV>
+struct Fft {
+    using C = cpx<R>;
+    static constexpr int P = P_;
+    static constexpr FftPlan plan = make_fft_plan(P_);
+    static constexpr int T = plan.T;
+    static constexpr int V = plan.vmax;
+    static constexpr int S = plan.n;
+    // padded scratch: one dummy slot every 8 entries breaks the stride-R bank pattern
+    static constexpr int SCR = P_ + (P_ >> 3) + 1;
+
+    FSA_HD static constexpr int pad(int i) { return i + (i >> 3); }
+
+    // radix of execution stage s (inverse runs the forward radices reversed)
+    static constexpr int radix(int s) { return INV ? plan.r[S - 1 - s] : plan.r[s]; }
+    static constexpr int ns(int s) {
+        int v = 1;
+        for (int t = 0; t < s; ++t) v *= radix(t);
+        return v;
+    }
+    static constexpr int nb(int s) { return P_ / radix(s); }
+    static constexpr int nbt(int s) { return (nb(s) + T - 1) / T; }  // butterflies per thread
+    static constexpr int first_stride() { return nb(0); }            // x[j + q * this]
+    static constexpr int last_stride() { return ns(S - 1); }         // y[j + q * this]
+    static constexpr int first_radix() { return radix(0); }
+    static constexpr int last_radix() { return radix(S - 1); }
+    static constexpr int first_nbt() { return nbt(0); }
+    static constexpr int last_nbt() { return nbt(S - 1); }
+
+    // twiddle + butterfly of stage s on the registers
+    template <int s>
+    FSA_HD static void compute(C (&v)[V], int tid, const C* __restrict__ tw) {
+        constexpr int RAD = radix(s), NS = ns(s), NB = nb(s), NBT = nbt(s);
+        constexpr int STEP = P_ / (NS * RAD);
+#pragma unroll
+        for (int b = 0; b < NBT; ++b) {
+            const int j = tid + b * T;
+            if ((NB % T) != 0 && j >= NB) continue;
+            if constexpr (NS > 1) {
+                const int k = j % NS;
+#pragma unroll
+                for (int q = 1; q < RAD; ++q) {
+                    const C w = tw[q * k * STEP];
+                    v[b * RAD + q] = INV ? cmulc(v[b * RAD + q], w) : cmul(v[b * RAD + q], w);
+                }
+            }
+            dft<RAD, INV>(&v[b * RAD]);
+        }
+    }
+
+    // write the outputs of stage s to the scratch
+    template <int s>
+    FSA_HD static void store(const C (&v)[V], C* scr, int tid) {
+        constexpr int RAD = radix(s), NS = ns(s), NB = nb(s), NBT = nbt(s);
+#pragma unroll
+        for (int b = 0; b < NBT; ++b) {
+            const int j = tid + b * T;
+            if ((NB % T) != 0 && j >= NB) continue;
+            const int k = j % NS;
+            const int base = (j / NS) * NS * RAD + k;
+#pragma unroll
+            for (int q = 0; q < RAD; ++q) scr[pad(base + q * NS)] = v[b * RAD + q];
+        }
+    }
+
+    // read the inputs of stage s from the scratch
+    template <int s>
+    FSA_HD static void load(C (&v)[V], const C* scr, int tid) {
+        constexpr int RAD = radix(s), NB = nb(s), NBT = nbt(s);
+#pragma unroll
+        for (int b = 0; b < NBT; ++b) {
+            const int j = tid + b * T;
+            if ((NB % T) != 0 && j >= NB) continue;
+#pragma unroll
+            for (int q = 0; q < RAD; ++q) v[b * RAD + q] = scr[pad(j + q * NB)];
+        }
+    }
+
+    // first-stage operands from an arbitrary source: v = f(index) for
+    // index < n_in, zero beyond (zero-padded inputs)
+    template <class F>
+    FSA_HD static void load_first(C (&v)[V], int tid, int n_in, F&& f) {
+        constexpr int RAD = radix(0), NB = nb(0), NBT = nbt(0);
+#pragma unroll
+        for (int b = 0; b < NBT; ++b) {
+            const int j = tid + b * T;
+#pragma unroll
+            for (int q = 0; q < RAD; ++q) {
+                const int idx = j + q * NB;
+                const bool ok = ((NB % T) == 0 || j < NB) && idx < n_in;
+                v[b * RAD + q] = ok ? f(idx) : mk(R(0), R(0));
+            }
+        }
+    }
+
+    // last-stage outputs to an arbitrary sink: f(index, value) for index < n_out
+    template <class F>
+    FSA_HD static void store_last(const C (&v)[V], int tid, int n_out, F&& f) {
+        constexpr int RAD = radix(S - 1), NS = ns(S - 1), NB = nb(S - 1), NBT = nbt(S - 1);
+        static_assert(NB == NS, "last stage writes y[j + q NS]");
+#pragma unroll
+        for (int b = 0; b < NBT; ++b) {
+            const int j = tid + b * T;
+            if ((NB % T) != 0 && j >= NB) continue;
+#pragma unroll
+            for (int q = 0; q < RAD; ++q) {
+                const int idx = j + q * NS;
+                if (idx < n_out) f(idx, v[b * RAD + q]);
+            }
+        }
+    }
+
+    // apply g(index, value&) to every last-stage output held by this thread
+    template <class G>
+    FSA_HD static void for_each_last(C (&v)[V], int tid, G&& g) {
+        constexpr int RAD = radix(S - 1), NS = ns(S - 1), NB = nb(S - 1), NBT = nbt(S - 1);
+#pragma unroll
+        for (int b = 0; b < NBT; ++b) {
+            const int j = tid + b * T;
+            if ((NB % T) != 0 && j >= NB) continue;
+#pragma unroll
+            for (int q = 0; q < RAD; ++q) g(j + q * NS, v[b * RAD + q]);
+        }
+    }
+
+#if defined(__HIPCC__)
+    static __device__ __forceinline__ void sync() {
+        if constexpr (T <= 64) {
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        } else {
+            __syncthreads();
+        }
+    }
+
+    template <int s>
+    static __device__ __forceinline__ void run_from(C (&v)[V], C* scr, int tid,
+                                                    const C* __restrict__ tw) {
+        if constexpr (s < S) {
+            store<s - 1>(v, scr, tid);
+            sync();
+            load<s>(v, scr, tid);
+            sync();
+            compute<s>(v, tid, tw);
+            run_from<s + 1>(v, scr, tid, tw);
+        }
+    }
+
+    // v: first-stage operands on entry, last-stage outputs on exit.  Every
+    // thread of the team must call it (it synchronises the team); on return
+    // the scratch may still be read by other threads until the next sync.
+    static __device__ __forceinline__ void run(C (&v)[V], C* scr, int tid,
+                                               const C* __restrict__ tw) {
+        compute<0>(v, tid, tw);
+        run_from<1>(v, scr, tid, tw);
+    }
+#endif
+};
+
+}  // namespace fsa

@@ -1,0 +1,77 @@
+// fsa_internal.hpp -- declarations shared by the library's translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+#include "../../include/fsa.h"
+#include "fsa_fft.hpp"
+
+namespace fsa {
+
+struct KernelParams {
+    int kind;
+    double lam;
+    double eps;
+};
+
+// Supported grid lengths N (8 <= N <= 2048, N = 2^a or 3 * 2^a): the padded
+// transform 2N and, on the contiguous axis, the half-length N must both be
+// supported transform lengths.
+inline bool grid_length_supported(int64_t n) {
+    return n >= 8 && n <= 2048 && (n % 2) == 0 && fft_length_supported(n) &&
+           fft_length_supported(2 * n);
+}
+
+// Tensor generation (fsa_tensor.hip).
+hipError_t build_tensor_device(const KernelParams& kp, int d, const double* L, const int64_t* N,
+                               const double* h, fsa_precision prec, void* tensor_out,
+                               hipStream_t st);
+// tw[m] = exp(-2 pi i m / n), m in [0, n), computed in FP64, stored in prec.
+hipError_t build_twiddles(fsa_precision prec, int n, void* out, hipStream_t st);
+
+// Pass launchers (fsa_launch_f32.hip / fsa_launch_f64.hip).  Complex arrays
+// are interleaved (re, im) of R.  Each returns hipErrorInvalidValue for an
+// unsupported length.
+template <typename R>
+struct Launch {
+    static hipError_t r2c(int M, const R* rho, void* out, int n_outer, int n_inner,
+                          const void* twM, const void* tw2M, hipStream_t st);
+    static hipError_t c2r(int M, const void* in, R* phi, int n_outer, int n_inner,
+                          const void* twM, const void* tw2M, hipStream_t st);
+    static hipError_t fwd_t(int P, const void* in, void* out, int N0, int H, const void* tw,
+                            hipStream_t st);
+    static hipError_t inv_t(int P, const void* in, void* out, int N0, int H, const void* tw,
+                            hipStream_t st);
+    static hipError_t conv(int P, void* data, const R* tensor, int n_pencils, int P1, int N1,
+                           const void* tw, hipStream_t st);
+};
+
+}  // namespace fsa
+
+// Plan object behind the opaque fsa_plan handle.
+struct fsa_plan_s {
+    fsa::KernelParams kp{};
+    int d = 0;
+    double L[3] = {1, 1, 1};
+    int64_t N[3] = {1, 1, 1};
+    double h[3] = {1, 1, 1};
+    fsa_precision prec = FSA_F32;
+    // derived sizes
+    int64_t H = 0;            // N_{d-1} + 1 bins of the real transform
+    size_t csize = 0;         // bytes of one complex value
+    size_t ws1_elems = 0;     // complex elements of the first workspace array
+    size_t ws2_elems = 0;     // complex elements of the second (3D only)
+    size_t ws_bytes = 0;
+    size_t tensor_elems = 0;  // octant elements
+    // twiddle tables (elements from the start of `twiddles`)
+    size_t tw_off_p0 = 0, tw_off_p1 = 0, tw_off_m = 0, tw_off_pl = 0;
+    size_t tw_elems = 0;
+    // device state
+    int device = -1;
+    void* tensor = nullptr;
+    void* twiddles = nullptr;
+    bool built = false;
+};

@@ -1,0 +1,303 @@
+// fsa_passes.hpp -- the per-evaluation FFT-convolution passes (gfx950).
+//
+// One evaluation computes phi = crop(IDFT(T^ . DFT(pad(rho)))) on the 2N
+// zero-padded grid (eq. DiscConv evaluated with FFTs, Sec. 2.2-2.3).  The
+// transform of each axis is split so that every pass reads and writes HBM
+// exactly once, with the zero-pad, the tensor product and the crop fused in:
+//
+//   3D (grid axes 0,1,2; axis 2 contiguous; H = N2 + 1; P_j = 2 N_j)
+//     A  r2c      rho[i0][i1][i2] (real)   -> X1[i0][p2][i1]     pad+R2C on axis 2
+//     B  fwd_t    X1[i0][p2][i1]           -> X2[p2][p1][i0]     pad+C2C on axis 1
+//     C  conv     X2[p2][p1][i0]  in place: pad+C2C, x T^, C2C^-1, crop on axis 0
+//     D  inv_t    X2[p2][p1][i0]           -> X1[i0][p2][i1]     C2C^-1+crop on axis 1
+//     E  c2r      X1[i0][p2][i1]           -> phi[i0][i1][i2]    C2R+crop on axis 2
+//   2D (axis 1 contiguous; H = N1 + 1)
+//     A  r2c      rho[i0][i1] -> X[p1][i0];  C conv on X[p1][i0];  E c2r -> phi
+//
+// Every axis transform reads its pencils from contiguous memory or from
+// 128-byte row segments of WT consecutive pencils, and writes the other way
+// round through an LDS tile, so all HBM traffic is coalesced and the pencils
+// of the fused pass C are contiguous.  The 1/prod P_j scale is folded into T^.
+//
+// Real transforms use the half-length complex transform of
+// z[m] = x[2m] + i x[2m+1] (the standard two-for-one packing):
+//   X[k] = (Z[k] + conj Z[M-k])/2 - i w^k (Z[k] - conj Z[M-k])/2,  w = e^{-pi i/M}
+// and its inverse Z[k] = (X[k] + conj X[M-k]) + i w^{-k} (X[k] - conj X[M-k]),
+// which returns 2M x[n] like every other unnormalised inverse here.
+#pragma once
+
+#include "fsa_fft.hpp"
+
+namespace fsa {
+
+constexpr int kMaxLds = 160 * 1024;
+
+// Width (pencils) of a transposing tile: 128 bytes of complex values, fewer
+// if the LDS or the 1024-thread limit says so.
+constexpr int tile_width(int csize, int T, int scr, int rows) {
+    int wt = 128 / csize;
+    while (wt > 1 && (wt * T > 1024 || (wt * scr > rows * (wt + 1) ? wt * scr : rows * (wt + 1)) *
+                                               csize > kMaxLds))
+        wt /= 2;
+    return wt;
+}
+
+constexpr int cmax(int a, int b) { return a > b ? a : b; }
+
+// ---------------------------------------------------------------------------
+// Pass A: zero-pad + real-to-complex along the contiguous axis, transposed out
+//   rho rows r = outer * n_inner + inner of M reals (M = N_last), padded to
+//   2M; out[(outer * (M+1) + k) * n_inner + inner] = X[k], k in [0, M].
+// ---------------------------------------------------------------------------
+template <typename R, int M>
+struct R2c {
+    using F = Fft<R, M, false>;
+    using C = cpx<R>;
+    static constexpr int T = F::T;
+    static constexpr int H = M + 1;
+    static constexpr int WT = tile_width(sizeof(C), T, F::SCR, H);
+    static constexpr int TS = WT + 1;
+    static constexpr int LDS = cmax(WT * F::SCR, H * TS);
+    static constexpr int THREADS = WT * T;
+    static constexpr int NX = (H + T - 1) / T;
+};
+
+template <typename R, int M>
+__global__ __launch_bounds__((R2c<R, M>::THREADS)) void k_r2c(const R* __restrict__ rho,
+                                                            cpx<R>* __restrict__ out, int n_outer,
+                                                            int n_inner,
+                                                            const cpx<R>* __restrict__ twM,
+                                                            const cpx<R>* __restrict__ tw2M) {
+    using K = R2c<R, M>;
+    using F = typename K::F;
+    using C = cpx<R>;
+    __shared__ C lds[K::LDS];
+    const int team = threadIdx.x / K::T, tid = threadIdx.x % K::T;
+    const int tile = blockIdx.x, outer = blockIdx.y;
+    const int inner = tile * K::WT + team;
+    const bool active = inner < n_inner;
+    const R* row = rho + ((size_t)outer * n_inner + (active ? inner : 0)) * M;
+
+    C v[F::V];
+    F::load_first(v, tid, active ? M / 2 : 0,
+                  [&](int m) { return *reinterpret_cast<const C*>(row + 2 * m); });
+    C* scr = lds + team * F::SCR;
+    F::run(v, scr, tid, twM);
+    F::store_last(v, tid, M, [&](int k, C z) { scr[F::pad(k)] = z; });
+    F::sync();
+    C x[K::NX];
+#pragma unroll
+    for (int i = 0; i < K::NX; ++i) {
+        const int k = tid + i * K::T;
+        if (k < K::H) {
+            const C zk = scr[F::pad(k == M ? 0 : k)];
+            const C zm = scr[F::pad(k == 0 ? 0 : M - k)];
+            const C a = zk + conj(zm);
+            const C b = rot90<false>(zk - conj(zm));
+            x[i] = scale(a + cmul(tw2M[k], b), R(0.5));
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < K::NX; ++i) {
+        const int k = tid + i * K::T;
+        if (k < K::H) lds[k * K::TS + team] = x[i];
+    }
+    __syncthreads();
+    const int col0 = tile * K::WT;
+    for (int e = threadIdx.x; e < K::H * K::WT; e += K::THREADS) {
+        const int k = e / K::WT, w = e % K::WT;
+        if (col0 + w < n_inner)
+            out[((size_t)outer * K::H + k) * n_inner + col0 + w] = lds[k * K::TS + w];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Pass E: complex-to-real along the contiguous axis with crop, transposed in
+//   in[(outer * (M+1) + k) * n_inner + inner] -> phi row r, first M reals of 2M.
+// ---------------------------------------------------------------------------
+template <typename R, int M>
+struct C2r {
+    using F = Fft<R, M, true>;
+    using C = cpx<R>;
+    static constexpr int T = F::T;
+    static constexpr int H = M + 1;
+    static constexpr int WT = tile_width(sizeof(C), T, F::SCR, H);
+    static constexpr int TS = WT + 1;
+    static constexpr int LDS = cmax(WT * F::SCR, H * TS);
+    static constexpr int THREADS = WT * T;
+};
+
+template <typename R, int M>
+__global__ __launch_bounds__((C2r<R, M>::THREADS)) void k_c2r(const cpx<R>* __restrict__ in,
+                                                            R* __restrict__ phi, int n_outer,
+                                                            int n_inner,
+                                                            const cpx<R>* __restrict__ twM,
+                                                            const cpx<R>* __restrict__ tw2M) {
+    using K = C2r<R, M>;
+    using F = typename K::F;
+    using C = cpx<R>;
+    __shared__ C lds[K::LDS];
+    const int team = threadIdx.x / K::T, tid = threadIdx.x % K::T;
+    const int tile = blockIdx.x, outer = blockIdx.y;
+    const int col0 = tile * K::WT;
+    for (int e = threadIdx.x; e < K::H * K::WT; e += K::THREADS) {
+        const int k = e / K::WT, w = e % K::WT;
+        lds[k * K::TS + w] = (col0 + w < n_inner)
+                                 ? in[((size_t)outer * K::H + k) * n_inner + col0 + w]
+                                 : mk(R(0), R(0));
+    }
+    __syncthreads();
+    C v[F::V];
+    F::load_first(v, tid, M, [&](int k) {
+        const C xk = lds[k * K::TS + team];
+        const C xm = lds[(M - k) * K::TS + team];
+        const C a = xk + conj(xm);
+        const C b = cmulc(xk - conj(xm), tw2M[k]);
+        return a + rot90<true>(b);
+    });
+    __syncthreads();
+    const int inner = col0 + team;
+    const bool active = inner < n_inner;
+    R* row = phi + ((size_t)outer * n_inner + (active ? inner : 0)) * M;
+    C* scr = lds + team * F::SCR;
+    F::run(v, scr, tid, twM);
+    F::store_last(v, tid, M / 2, [&](int m, C z) {
+        if (active) *reinterpret_cast<C*>(row + 2 * m) = z;
+    });
+}
+
+// ---------------------------------------------------------------------------
+// Pass B (3D): zero-pad + forward C2C along axis 1, contiguous in, transposed out
+//   in[(i0 * H + p2) * N1 + i1] -> out[(p2 * P + p1) * N0 + i0],  P = 2 N1
+// ---------------------------------------------------------------------------
+template <typename R, int P>
+struct FwdT {
+    using F = Fft<R, P, false>;
+    using C = cpx<R>;
+    static constexpr int T = F::T;
+    static constexpr int WT = tile_width(sizeof(C), T, F::SCR, P);
+    static constexpr int TS = WT + 1;
+    static constexpr int LDS = cmax(WT * F::SCR, P * TS);
+    static constexpr int THREADS = WT * T;
+};
+
+template <typename R, int P>
+__global__ __launch_bounds__((FwdT<R, P>::THREADS)) void k_fwd_t(const cpx<R>* __restrict__ in,
+                                                               cpx<R>* __restrict__ out, int N0,
+                                                               int H,
+                                                               const cpx<R>* __restrict__ tw) {
+    using K = FwdT<R, P>;
+    using F = typename K::F;
+    using C = cpx<R>;
+    constexpr int N1 = P / 2;
+    __shared__ C lds[K::LDS];
+    const int team = threadIdx.x / K::T, tid = threadIdx.x % K::T;
+    const int tile = blockIdx.x, p2 = blockIdx.y;
+    const int i0 = tile * K::WT + team;
+    const bool active = i0 < N0;
+    const C* src = in + ((size_t)(active ? i0 : 0) * H + p2) * N1;
+    C v[F::V];
+    F::load_first(v, tid, active ? N1 : 0, [&](int i) { return src[i]; });
+    F::run(v, lds + team * F::SCR, tid, tw);
+    __syncthreads();
+    F::store_last(v, tid, P, [&](int p1, C c) { lds[p1 * K::TS + team] = c; });
+    __syncthreads();
+    const int col0 = tile * K::WT;
+    for (int e = threadIdx.x; e < P * K::WT; e += K::THREADS) {
+        const int p1 = e / K::WT, w = e % K::WT;
+        if (col0 + w < N0) out[((size_t)p2 * P + p1) * N0 + col0 + w] = lds[p1 * K::TS + w];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Pass D (3D): inverse C2C along axis 1 with crop, transposed in, contiguous out
+//   in[(p2 * P + p1) * N0 + i0] -> out[(i0 * H + p2) * N1 + i1], i1 < N1
+// ---------------------------------------------------------------------------
+template <typename R, int P>
+struct InvT {
+    using F = Fft<R, P, true>;
+    using C = cpx<R>;
+    static constexpr int T = F::T;
+    static constexpr int WT = tile_width(sizeof(C), T, F::SCR, P);
+    static constexpr int TS = WT + 1;
+    static constexpr int LDS = cmax(WT * F::SCR, P * TS);
+    static constexpr int THREADS = WT * T;
+};
+
+template <typename R, int P>
+__global__ __launch_bounds__((InvT<R, P>::THREADS)) void k_inv_t(const cpx<R>* __restrict__ in,
+                                                               cpx<R>* __restrict__ out, int N0,
+                                                               int H,
+                                                               const cpx<R>* __restrict__ tw) {
+    using K = InvT<R, P>;
+    using F = typename K::F;
+    using C = cpx<R>;
+    constexpr int N1 = P / 2;
+    __shared__ C lds[K::LDS];
+    const int team = threadIdx.x / K::T, tid = threadIdx.x % K::T;
+    const int tile = blockIdx.x, p2 = blockIdx.y;
+    const int col0 = tile * K::WT;
+    for (int e = threadIdx.x; e < P * K::WT; e += K::THREADS) {
+        const int p1 = e / K::WT, w = e % K::WT;
+        lds[p1 * K::TS + w] =
+            (col0 + w < N0) ? in[((size_t)p2 * P + p1) * N0 + col0 + w] : mk(R(0), R(0));
+    }
+    __syncthreads();
+    C v[F::V];
+    F::load_first(v, tid, P, [&](int p1) { return lds[p1 * K::TS + team]; });
+    __syncthreads();
+    F::run(v, lds + team * F::SCR, tid, tw);
+    const int i0 = col0 + team;
+    if (i0 < N0) {
+        C* dst = out + ((size_t)i0 * H + p2) * N1;
+        F::store_last(v, tid, N1, [&](int i1, C c) { dst[i1] = c; });
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Pass C: along the outermost axis, pencils contiguous: zero-pad, forward
+// C2C, product with the real octant tensor, inverse C2C, crop -- in place.
+//   pencil q = p2 * P1 + p1 (3D) or q = p1 (2D: P1 = 1, N1 = 0),
+//   data[q * N0 + i0];  tensor[((p2 (N1+1) + |p1|) (N0+1)) + |p0|]
+// ---------------------------------------------------------------------------
+template <typename R, int P>
+struct Conv {
+    using Ff = Fft<R, P, false>;
+    using Fi = Fft<R, P, true>;
+    using C = cpx<R>;
+    static constexpr int T = Ff::T;
+    static constexpr int TPW = T >= 256 ? 1 : 256 / T;  // teams per workgroup
+    static constexpr int THREADS = TPW * T;
+    static constexpr int LDS = TPW * Ff::SCR;
+};
+
+template <typename R, int P>
+__global__ __launch_bounds__((Conv<R, P>::THREADS)) void k_conv(cpx<R>* __restrict__ data,
+                                                              const R* __restrict__ tensor,
+                                                              int n_pencils, int P1, int N1,
+                                                              const cpx<R>* __restrict__ tw) {
+    using K = Conv<R, P>;
+    using Ff = typename K::Ff;
+    using Fi = typename K::Fi;
+    using C = cpx<R>;
+    constexpr int N0 = P / 2;
+    __shared__ C lds[K::LDS];
+    const int team = threadIdx.x / K::T, tid = threadIdx.x % K::T;
+    const int q = blockIdx.x * K::TPW + team;
+    const bool active = q < n_pencils;
+    const int qc = active ? q : 0;
+    C* pen = data + (size_t)qc * N0;
+    C* scr = lds + team * Ff::SCR;
+    C v[Ff::V];
+    Ff::load_first(v, tid, active ? N0 : 0, [&](int i) { return pen[i]; });
+    Ff::run(v, scr, tid, tw);
+    const int p2 = qc / P1, p1 = qc - p2 * P1;
+    const int a1 = p1 <= N1 ? p1 : P1 - p1;
+    const R* trow = tensor + ((size_t)p2 * (N1 + 1) + a1) * (N0 + 1);
+    Ff::for_each_last(v, tid, [&](int p0, C& c) { c = scale(c, trow[p0 <= N0 ? p0 : P - p0]); });
+    Fi::run(v, scr, tid, tw);
+    if (active) Fi::store_last(v, tid, N0, [&](int i, C c) { pen[i] = c; });
+}
+
+}  // namespace fsa

@@ -1,0 +1,280 @@
+"""Python binding of the C ABI in ``include/fsa.h`` (argument marshalling only).
+
+Every step of an evaluation runs in the HIP kernels of ``libfsa.so``; PyTorch
+only provides device memory and the current stream.  Importing this module
+fails loudly if the library has not been built.
+
+    plan = Plan("coulomb3d", L=(8, 8, 8), N=(32, 32, 32), precision="f64").build()
+    phi = plan.apply(rho)          # rho: contiguous cuda tensor of shape N
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence
+
+import torch
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libfsa.so")
+
+KINDS = {
+    "coulomb3d": 1,
+    "yukawa3d": 2,
+    "log2d": 3,
+    "coulomb2d": 4,
+    "biharmonic3d": 5,
+    "biharmonic2d": 6,
+}
+KIND_DIM = {"coulomb3d": 3, "yukawa3d": 3, "biharmonic3d": 3,
+            "log2d": 2, "coulomb2d": 2, "biharmonic2d": 2}
+PRECISIONS = {"f32": 0, "f64": 1}
+DTYPES = {"f32": torch.float32, "f64": torch.float64}
+
+STATUS = {
+    0: "FSA_OK", 1: "FSA_EINVAL", 2: "FSA_EUNSUPPORTED", 3: "FSA_ENOMEM",
+    4: "FSA_EDEVICE", 5: "FSA_ESTATE", 6: "FSA_EBUDGET", 7: "FSA_ECANCELLED",
+}
+
+EXPORTS = (
+    "fsa_plan_create", "fsa_plan_query", "fsa_build_tensor", "fsa_apply",
+    "fsa_batch_workspace_bytes", "fsa_apply_batched", "fsa_plan_destroy", "fsa_plan_tensor",
+    "fsa_server_create", "fsa_server_submit", "fsa_server_poll", "fsa_server_wait",
+    "fsa_server_cancel", "fsa_server_stats", "fsa_server_destroy", "fsa_last_error",
+)
+
+
+class FsaError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{STATUS.get(status, status)}: {message}")
+        self.status = status
+
+
+class _Kernel(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int), ("lambda_", ctypes.c_double), ("eps", ctypes.c_double)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("p50_ms", ctypes.c_double), ("p99_ms", ctypes.c_double),
+                ("throughput_rps", ctypes.c_double), ("gpts_per_s", ctypes.c_double),
+                ("done", ctypes.c_uint64), ("rejected", ctypes.c_uint64),
+                ("cancelled", ctypes.c_uint64), ("cache_hits", ctypes.c_uint64),
+                ("cache_misses", ctypes.c_uint64), ("hbm_in_use", ctypes.c_size_t),
+                ("hbm_peak", ctypes.c_size_t)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(
+            f"HIP library {LIB_PATH} is not built; run `python -m paper_2504_19410_amd.build` "
+            "(there is no CPU fallback)")
+    lib = ctypes.CDLL(LIB_PATH)
+    P = ctypes.c_void_p
+    I = ctypes.c_int
+    S = ctypes.c_size_t
+    sigs = {
+        "fsa_plan_create": [ctypes.POINTER(_Kernel), I, P, P, I, ctypes.POINTER(P)],
+        "fsa_plan_query": [P, P, P, P, P],
+        "fsa_build_tensor": [P, P],
+        "fsa_apply": [P, P, P, P, P],
+        "fsa_batch_workspace_bytes": [I, P, P],
+        "fsa_apply_batched": [I, P, P, P, P, S, P],
+        "fsa_plan_destroy": [P],
+        "fsa_plan_tensor": [P, P, P],
+        "fsa_server_create": [S, I, I, ctypes.POINTER(P)],
+        "fsa_server_submit": [P, ctypes.POINTER(_Kernel), I, P, P, I, P, P, P],
+        "fsa_server_poll": [P, ctypes.c_uint64, P, P],
+        "fsa_server_wait": [P, ctypes.c_uint64, P],
+        "fsa_server_cancel": [P, ctypes.c_uint64],
+        "fsa_server_stats": [P, ctypes.POINTER(Stats)],
+        "fsa_server_destroy": [P],
+    }
+    for name, args in sigs.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = ctypes.c_int
+    lib.fsa_last_error.argtypes = []
+    lib.fsa_last_error.restype = ctypes.c_char_p
+    return lib
+
+
+_lib = _load()
+
+
+def lib():
+    return _lib
+
+
+def _check(status: int):
+    if status != 0:
+        raise FsaError(status, _lib.fsa_last_error().decode(errors="replace"))
+
+
+def _stream_ptr(stream: Optional[torch.cuda.Stream] = None):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _kernel(kind: str, eps: Optional[float], lam: Optional[float]) -> _Kernel:
+    if kind not in KINDS:
+        raise ValueError(f"unknown kernel {kind!r}; choose from {sorted(KINDS)}")
+    return _Kernel(KINDS[kind], float(lam or 0.0), float(eps) if eps else 0.0)
+
+
+class Plan:
+    """A plan for one kernel, box and grid (``fsa_plan_create``)."""
+
+    def __init__(self, kernel: str, L: Sequence[float], N: Sequence[int], precision: str = "f32",
+                 eps: Optional[float] = None, lam: Optional[float] = None):
+        if precision not in PRECISIONS:
+            raise ValueError(f"precision must be one of {list(PRECISIONS)}")
+        self.kernel, self.precision = kernel, precision
+        self.L = tuple(float(x) for x in L)
+        self.N = tuple(int(n) for n in N)
+        self.lam = lam
+        self.d = len(self.N)
+        if len(self.L) != self.d:
+            raise ValueError("L and N must have the same length")
+        k = _kernel(kernel, eps, lam)
+        Ls = (ctypes.c_double * self.d)(*self.L)
+        Ns = (ctypes.c_int64 * self.d)(*self.N)
+        h = ctypes.c_void_p()
+        _check(_lib.fsa_plan_create(ctypes.byref(k), self.d, Ls, Ns, PRECISIONS[precision],
+                                    ctypes.byref(h)))
+        self._h = h
+        e = ctypes.c_double()
+        hs = (ctypes.c_double * self.d)()
+        tb = ctypes.c_size_t()
+        wb = ctypes.c_size_t()
+        _check(_lib.fsa_plan_query(h, ctypes.byref(e), hs, ctypes.byref(tb), ctypes.byref(wb)))
+        self.eps = e.value
+        self.h = tuple(hs)
+        self.tensor_bytes = tb.value
+        self.workspace_bytes = wb.value
+        self.dtype = DTYPES[precision]
+        self._ws = None
+        self.device = None
+
+    @property
+    def handle(self):
+        return self._h
+
+    def build(self, stream: Optional[torch.cuda.Stream] = None) -> "Plan":
+        _check(_lib.fsa_build_tensor(self._h, _stream_ptr(stream)))
+        self.device = torch.cuda.current_device()
+        return self
+
+    def workspace(self) -> torch.Tensor:
+        """A workspace owned by this Python object (allocated once)."""
+        if self._ws is None:
+            self._ws = torch.empty(self.workspace_bytes + 256, dtype=torch.uint8,
+                                   device=f"cuda:{torch.cuda.current_device()}")
+        return self._ws
+
+    def _ws_ptr(self, ws: torch.Tensor) -> int:
+        p = ws.data_ptr()
+        return (p + 255) & ~255
+
+    def check_input(self, rho: torch.Tensor):
+        if not rho.is_cuda:
+            raise ValueError("rho must be a device tensor")
+        if tuple(rho.shape) != self.N:
+            raise ValueError(f"rho shape {tuple(rho.shape)} != plan grid {self.N}")
+        if rho.dtype != self.dtype:
+            raise ValueError(f"rho dtype {rho.dtype} != plan precision {self.dtype}")
+        if not rho.is_contiguous():
+            raise ValueError("rho must be contiguous")
+
+    def apply(self, rho: torch.Tensor, out: Optional[torch.Tensor] = None,
+              workspace: Optional[torch.Tensor] = None,
+              stream: Optional[torch.cuda.Stream] = None) -> torch.Tensor:
+        """phi = U * rho on the grid (``fsa_apply``); out may alias rho."""
+        self.check_input(rho)
+        if out is None:
+            out = torch.empty_like(rho)
+        else:
+            self.check_input(out)
+        ws = workspace if workspace is not None else self.workspace()
+        if ws.numel() < self.workspace_bytes + 256:
+            raise ValueError("workspace too small")
+        _check(_lib.fsa_apply(self._h, ctypes.c_void_p(rho.data_ptr()),
+                              ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(self._ws_ptr(ws)),
+                              _stream_ptr(stream)))
+        return out
+
+    def tensor(self) -> torch.Tensor:
+        """Copy of the built spectral octant, shape (N_{d-1}+1, ..., N_0+1)."""
+        ptr = ctypes.c_void_p()
+        dims = (ctypes.c_int64 * self.d)()
+        _check(_lib.fsa_plan_tensor(self._h, ctypes.byref(ptr), dims))
+        shape = tuple(dims)
+        n = 1
+        for s in shape:
+            n *= s
+        out = torch.empty(shape, dtype=self.dtype)
+        torch.cuda.synchronize()
+        hip = _hip()
+        rc = hip.hipMemcpy(ctypes.c_void_p(out.data_ptr()), ptr,
+                           ctypes.c_size_t(n * out.element_size()), 2)
+        if rc != 0:
+            raise RuntimeError(f"hipMemcpy failed ({rc})")
+        return out
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.fsa_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+_hip_lib = None
+
+
+def _hip():
+    global _hip_lib
+    if _hip_lib is None:
+        _hip_lib = ctypes.CDLL("libamdhip64.so")
+        _hip_lib.hipMemcpy.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t,
+                                       ctypes.c_int]
+        _hip_lib.hipMemcpy.restype = ctypes.c_int
+    return _hip_lib
+
+
+def batch_workspace_bytes(plans: Sequence[Plan]) -> int:
+    arr = (ctypes.c_void_p * len(plans))(*[p.handle for p in plans])
+    b = ctypes.c_size_t()
+    _check(_lib.fsa_batch_workspace_bytes(len(plans), arr, ctypes.byref(b)))
+    return b.value
+
+
+def apply_batched(plans: Sequence[Plan], rhos: Sequence[torch.Tensor],
+                  outs: Optional[Sequence[torch.Tensor]] = None,
+                  workspace: Optional[torch.Tensor] = None,
+                  stream: Optional[torch.cuda.Stream] = None):
+    """Evaluates every (plan, rho) pair in one batched call (``fsa_apply_batched``)."""
+    n = len(plans)
+    if len(rhos) != n:
+        raise ValueError("one density per plan")
+    for p, r in zip(plans, rhos):
+        p.check_input(r)
+    if outs is None:
+        outs = [torch.empty_like(r) for r in rhos]
+    need = batch_workspace_bytes(plans)
+    if workspace is None:
+        workspace = torch.empty(need + 256, dtype=torch.uint8, device=rhos[0].device)
+    base = (workspace.data_ptr() + 255) & ~255
+    arr = (ctypes.c_void_p * n)(*[p.handle for p in plans])
+    rp = (ctypes.c_void_p * n)(*[r.data_ptr() for r in rhos])
+    op = (ctypes.c_void_p * n)(*[o.data_ptr() for o in outs])
+    _check(_lib.fsa_apply_batched(n, arr, rp, op, ctypes.c_void_p(base),
+                                  ctypes.c_size_t(workspace.numel() - (base - workspace.data_ptr())),
+                                  _stream_ptr(stream)))
+    return outs

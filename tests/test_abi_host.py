@@ -1,0 +1,95 @@
+"""Host-side checks of the C ABI and of the transform index logic (no GPU).
+
+* libfsa.so loads and exports every function include/fsa.h declares;
+* fsa_plan_create validates its arguments synchronously (no device work);
+* the plan's reported sizes follow the layout of the passes;
+* the team Stockham transforms, emulated thread by thread on the CPU, match
+  the DFT for every supported length (tests/host/fft_emulate.cpp).
+"""
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    src = open(os.path.join(ROOT, "include", "fsa.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(fsa_[a-z_]+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def F():
+    from paper_2504_19410_amd import fsa
+    return fsa
+
+
+def test_exports_every_declared_symbol(F):
+    names = declared_functions()
+    assert "fsa_apply" in names and "fsa_server_submit" in names
+    for n in names:
+        assert hasattr(F.lib(), n), n
+    assert set(names) == set(F.EXPORTS)
+
+
+def test_plan_defaults_and_sizes(F):
+    p = F.Plan("coulomb3d", (8, 8, 8), (32, 32, 32), "f64")
+    assert p.eps == pytest.approx(16.0 / 8.0)
+    assert p.h == pytest.approx((0.5, 0.5, 0.5))
+    assert p.tensor_bytes == 33 ** 3 * 8
+    H = 33
+    ws1 = 32 * H * 32 * 16
+    ws2 = H * 64 * 32 * 16
+    r = lambda b: (b + 255) // 256 * 256
+    assert p.workspace_bytes == r(ws1) + r(ws2)
+    q = F.Plan("log2d", (4.0, 16.0), (1024, 256), "f32")
+    assert q.eps == pytest.approx(8.0 / 8.0)
+    assert q.workspace_bytes == r(257 * 1024 * 8)
+    assert q.tensor_bytes == 1025 * 257 * 4
+    y = F.Plan("yukawa3d", (8, 8, 8), (24, 48, 96), "f32", eps=1.5, lam=2.0)
+    assert y.eps == 1.5
+
+
+@pytest.mark.parametrize("args,status", [
+    (("coulomb3d", (8, 8, 8), (31, 32, 32)), "FSA_EINVAL"),      # odd
+    (("coulomb3d", (8, 8, 8), (4, 32, 32)), "FSA_EINVAL"),       # too small
+    (("coulomb3d", (8, 8, 8), (40, 32, 32)), "FSA_EUNSUPPORTED"),  # 5 * 8
+    (("coulomb3d", (8, 8, 8), (4096, 32, 32)), "FSA_EUNSUPPORTED"),
+    (("coulomb3d", (8, 8), (32, 32)), "FSA_EINVAL"),             # wrong d
+    (("log2d", (8, 8, 8), (32, 32, 32)), "FSA_EINVAL"),
+    (("coulomb3d", (8, -1, 8), (32, 32, 32)), "FSA_EINVAL"),
+])
+def test_plan_validation(F, args, status):
+    with pytest.raises(F.FsaError) as ei:
+        F.Plan(*args)
+    assert status in str(ei.value)
+
+
+def test_plan_validation_params(F):
+    with pytest.raises(F.FsaError, match="lambda"):
+        F.Plan("yukawa3d", (8, 8, 8), (32, 32, 32))
+    with pytest.raises(F.FsaError, match="eps"):
+        F.Plan("coulomb3d", (8, 8, 8), (32, 32, 32), eps=5.0)  # > R0/4
+    with pytest.raises(ValueError):
+        F.Plan("coulomb3d", (8, 8, 8), (32, 32, 32), precision="bf16")
+
+
+def test_apply_before_build_is_a_state_error(F):
+    p = F.Plan("coulomb3d", (8, 8, 8), (16, 16, 16))
+    st = F.lib().fsa_apply(p.handle, ctypes.c_void_p(256), ctypes.c_void_p(256),
+                           ctypes.c_void_p(256), None)
+    assert F.STATUS[st] == "FSA_ESTATE"
+    assert b"not built" in F.lib().fsa_last_error()
+
+
+def test_team_fft_emulation(tmp_path):
+    exe = tmp_path / "fft_emulate"
+    src = os.path.join(ROOT, "tests", "host", "fft_emulate.cpp")
+    subprocess.run(["g++", "-O2", "-std=c++17", src, "-o", str(exe)], check=True)
+    r = subprocess.run([str(exe)], capture_output=True, text=True, timeout=300)
+    assert r.returncode == 0, r.stdout + r.stderr
+    assert "OK" in r.stdout

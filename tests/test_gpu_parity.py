@@ -1,0 +1,149 @@
+"""Parity of the HIP path with the FP64 CPU oracle (needs an MI355X).
+
+Tolerances (relative L2 over the grid, against the oracle on the same input
+values): 1e-12 in FP64 mode, 5e-6 in FP32 mode.  Every call goes through the
+C ABI of include/fsa.h via the ctypes binding.
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import oracle as O
+from paper_2504_19410_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"f64": 1e-12, "f32": 5e-6}
+
+
+@pytest.fixture(scope="module")
+def F():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2504_19410_amd import fsa
+    return fsa
+
+
+def rel_l2(a, b):
+    return float(np.linalg.norm((a - b).ravel()) / np.linalg.norm(b.ravel()))
+
+
+def density(kind, L, N, seed, noise=False):
+    rng = synth.SplitMix64(seed)
+    d = len(N)
+    gs = synth.draw_gaussians(rng, d, 3, [-l / 4 for l in L], [l / 4 for l in L],
+                              [l / 5 for l in L], [l / 3 for l in L], isotropic=False)
+    rho = synth.eval_gaussians(gs, L, N)
+    if noise:
+        rho = rho + 0.1 * np.random.default_rng(seed).standard_normal(rho.shape)
+    return rho
+
+
+def run_gpu(F, kind, L, N, prec, rho64, eps=None, lam=None):
+    plan = F.Plan(kind, L, N, prec, eps=eps, lam=lam).build()
+    rho = torch.from_numpy(rho64).to(F.DTYPES[prec]).cuda()
+    phi = plan.apply(rho)
+    torch.cuda.synchronize()
+    return plan, rho.double().cpu().numpy(), phi.double().cpu().numpy()
+
+
+SMALL = [
+    ("coulomb3d", (8.0, 8.0, 8.0), (32, 32, 32), None),
+    ("coulomb3d", (3.0, 5.0, 4.0), (24, 16, 48), None),
+    ("coulomb3d", (6.0, 6.0, 6.0), (12, 8, 16), None),
+    ("yukawa3d", (8.0, 8.0, 8.0), (16, 24, 32), 1.0),
+    ("biharmonic3d", (4.0, 4.0, 4.0), (16, 16, 16), None),
+    ("log2d", (8.0, 6.0), (48, 96), None),
+    ("log2d", (10.0, 5.0), (256, 128), None),
+    ("log2d", (4.0, 16.0), (96, 24), None),
+    ("coulomb2d", (6.0, 6.0), (24, 32), None),
+    ("biharmonic2d", (5.0, 7.0), (32, 48), None),
+]
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("kind,L,N,lam", SMALL)
+def test_parity_small(F, kind, L, N, lam, prec):
+    rho64 = density(kind, L, N, seed=sum(N))
+    plan, rho_used, phi = run_gpu(F, kind, L, N, prec, rho64, lam=lam)
+    ref = O.solve(kind, L, N, rho_used, eps=plan.eps, lam=lam or 0.0)
+    err = rel_l2(phi, ref)
+    print(f"{kind} {N} {prec}: rel L2 {err:.3e}, max-abs {np.max(np.abs(phi - ref)):.3e}")
+    assert err <= TOL[prec]
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("kind,L,N", [("coulomb3d", (4.0, 4.0, 4.0), (16, 24, 32)),
+                                       ("log2d", (5.0, 5.0), (64, 48))])
+def test_parity_rough_density(F, kind, L, N, prec):
+    """A density with white noise: every frequency of the padded grid is excited."""
+    rho64 = density(kind, L, N, seed=7, noise=True)
+    plan, rho_used, phi = run_gpu(F, kind, L, N, prec, rho64)
+    ref = O.solve(kind, L, N, rho_used, eps=plan.eps)
+    assert rel_l2(phi, ref) <= TOL[prec]
+
+
+@pytest.mark.parametrize("kind,L,N,lam", [("coulomb3d", (3.0, 5.0, 4.0), (24, 16, 32), None),
+                                           ("yukawa3d", (4.0, 4.0, 4.0), (16, 16, 16), 2.0),
+                                           ("log2d", (8.0, 6.0), (48, 32), None),
+                                           ("biharmonic2d", (3.0, 4.0), (16, 24), None)])
+def test_tensor_matches_oracle_dft(F, kind, L, N, lam):
+    """The GPU spectral octant equals DFT(T(1) + T(2)) / prod P of the oracle."""
+    plan = F.Plan(kind, L, N, "f64", lam=lam).build()
+    got = plan.tensor().numpy()
+    T = O.build_tensor(kind, L, N, plan.eps, lam=lam or 0.0)
+    That = O.fftnd(T, -1) / T.size
+    assert np.max(np.abs(That.imag)) <= 1e-14 * np.max(np.abs(That.real))
+    octant = That.real[tuple(slice(0, n + 1) for n in N)]
+    ref = np.transpose(octant, tuple(reversed(range(len(N)))))
+    assert got.shape == ref.shape
+    assert np.max(np.abs(got - ref)) <= 1e-13 * np.max(np.abs(ref))
+
+
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_deterministic_and_in_place(F, prec):
+    kind, L, N = "coulomb3d", (8.0, 8.0, 8.0), (32, 48, 24)
+    plan = F.Plan(kind, L, N, prec).build()
+    rho = torch.from_numpy(density(kind, L, N, 3)).to(F.DTYPES[prec]).cuda()
+    a = plan.apply(rho)
+    b = plan.apply(rho)
+    c = rho.clone()
+    plan.apply(c, out=c)
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)
+    assert torch.equal(a, c)
+
+
+def test_zero_density_gives_zero(F):
+    plan = F.Plan("log2d", (4.0, 4.0), (64, 64), "f64").build()
+    phi = plan.apply(torch.zeros(64, 64, dtype=torch.float64, device="cuda"))
+    assert float(phi.abs().max()) == 0.0
+
+
+def sampled_parity(F, kind, L, N, prec, rho64, lam=None, eps=None, npts=48, seed=0):
+    plan, rho_used, phi = run_gpu(F, kind, L, N, prec, rho64, eps=eps, lam=lam)
+    T = O.build_tensor(kind, L, N, plan.eps, lam=lam or 0.0)
+    rng = np.random.default_rng(seed)
+    idx = np.unique(np.concatenate([rng.choice(phi.size, npts, replace=False),
+                                    [int(np.argmax(np.abs(phi))), 0, phi.size - 1]]))
+    ref = O.conv_direct_points(T, rho_used, idx)
+    got = phi.ravel()[idx]
+    return rel_l2(got, ref)
+
+
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+@pytest.mark.parametrize("orientation", ["pancake", "cigar"])
+def test_parity_anisotropic_full_size(F, orientation, prec):
+    """256x256x64 / 64x64x256 Coulomb, h = 1/16, at the benchmark's size:
+    outputs sampled and summed directly by the oracle."""
+    p = synth.anisotropic_coulomb(orientation, 4.0, prec)
+    rho64 = synth.eval_gaussians(p.gaussians, p.L, p.N)
+    assert sampled_parity(F, p.kernel, p.L, p.N, prec, rho64) <= TOL[prec]
+
+
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_parity_yukawa_256(F, prec):
+    """3D Yukawa, lam = 1, eps = 2, 256^3 on [-8,8]^3, 8 Gaussians: sampled outputs."""
+    p = synth.yukawa_problem(1.0, 256, prec)
+    rho64 = synth.eval_gaussians(p.gaussians, p.L, p.N)
+    assert sampled_parity(F, p.kernel, p.L, p.N, prec, rho64, lam=p.lam, eps=p.eps) <= TOL[prec]
