@@ -93,10 +93,13 @@ typedef struct fsa_plan_s* fsa_plan;
  *       3*2^a (the padded transform length 2 N_j must factor into the
  *       supported radices).
  *   p   FSA_F32 or FSA_F64.
- * The split parameter must satisfy eps >= 2 max_j h_j (the trapezoidal error
- * of the regular part, ~ e^{-pi^2 eps^2 / h^2}, then stays below 1e-17) and
- * eps <= R0/5.85 (Appendix B).  Returns FSA_EINVAL otherwise, FSA_EUNSUPPORTED
- * for a length outside the supported set.  *out receives the plan. */
+ * The split parameter must satisfy 0 < eps <= R0/4 (FSA_EINVAL otherwise).
+ * Double-precision accuracy needs eps <= R0/5.85 (condition (b) of eq.
+ * ApproxProp, Appendix B) and eps >= 2 max_j h_j, which keeps the
+ * trapezoidal error of the regular part, ~ e^{-pi^2 eps^2 / h^2}, below
+ * 1e-17; the paper's coarse-grid experiments deliberately violate the latter.
+ * FSA_EUNSUPPORTED for a grid length outside the supported set.  *out
+ * receives the plan. */
 fsa_status fsa_plan_create(const fsa_kernel* k, int d, const double* L, const int64_t* N,
                            fsa_precision p, fsa_plan* out);
 
@@ -126,6 +129,15 @@ fsa_status fsa_build_tensor(fsa_plan plan, void* stream);
  *              256-byte aligned; contents on entry are ignored.
  * FSA_ESTATE if the tensor has not been built. */
 fsa_status fsa_apply(fsa_plan plan, const void* rho, void* phi, void* workspace, void* stream);
+
+/* Profiling variant of fsa_apply: the same kernels on the same stream, plus
+ * hipEventRecord(events[i], stream) before pass i and of events[n_passes]
+ * after the last pass, so a caller can time every pass with
+ * hipEventElapsedTime.  The events are hipEvent_t handles created by the
+ * caller; n_events must equal n_passes + 1 = 6 (3D: passes A-E) or 4 (2D:
+ * passes A, C, E).  For profiling tools and benchmarks. */
+fsa_status fsa_apply_events(fsa_plan plan, const void* rho, void* phi, void* workspace,
+                            void* stream, void* const* events, int n_events);
 
 /* Device bytes of the workspace fsa_apply_batched needs for these plans. */
 fsa_status fsa_batch_workspace_bytes(int n, const fsa_plan* plans, size_t* bytes);

@@ -192,7 +192,11 @@ namespace fsa {
 // Enqueues the 3 (2D) or 5 (3D) passes of one evaluation.
 template <typename R>
 static hipError_t apply_impl(const fsa_plan_s* pl, const void* rho, void* phi, void* ws,
-                             hipStream_t st) {
+                             hipStream_t st, hipEvent_t const* ev) {
+    int pass = 0;
+    auto mark = [&]() -> hipError_t {
+        return ev ? hipEventRecord(ev[pass++], st) : hipSuccess;
+    };
     const char* tw = (const char*)pl->twiddles;
     const size_t cs = pl->csize;
     const void* tw_p0 = tw + pl->tw_off_p0 * cs;
@@ -207,31 +211,42 @@ static hipError_t apply_impl(const fsa_plan_s* pl, const void* rho, void* phi, v
     if (pl->d == 3) {
         const int N2 = (int)pl->N[2];
         char* w2 = w1 + ((pl->ws1_elems * cs + 255) & ~size_t(255));
-        e = Launch<R>::r2c(N2, (const R*)rho, w1, N0, N1, tw_m, tw_pl, st);
+        e = mark();
+        if (e == hipSuccess) e = Launch<R>::r2c(N2, (const R*)rho, w1, N0, N1, tw_m, tw_pl, st);
+        if (e == hipSuccess) e = mark();
         if (e == hipSuccess) e = Launch<R>::fwd_t(2 * N1, w1, w2, N0, H, tw_p1, st);
+        if (e == hipSuccess) e = mark();
         if (e == hipSuccess)
             e = Launch<R>::conv(2 * N0, w2, tensor, H * 2 * N1, 2 * N1, N1, tw_p0, st);
+        if (e == hipSuccess) e = mark();
         if (e == hipSuccess) e = Launch<R>::inv_t(2 * N1, w2, w1, N0, H, tw_p1, st);
+        if (e == hipSuccess) e = mark();
         if (e == hipSuccess) e = Launch<R>::c2r(N2, w1, (R*)phi, N0, N1, tw_m, tw_pl, st);
+        if (e == hipSuccess) e = mark();
     } else {
-        e = Launch<R>::r2c(N1, (const R*)rho, w1, 1, N0, tw_m, tw_pl, st);
+        e = mark();
+        if (e == hipSuccess) e = Launch<R>::r2c(N1, (const R*)rho, w1, 1, N0, tw_m, tw_pl, st);
+        if (e == hipSuccess) e = mark();
         if (e == hipSuccess) e = Launch<R>::conv(2 * N0, w1, tensor, H, 1, 0, tw_p0, st);
+        if (e == hipSuccess) e = mark();
         if (e == hipSuccess) e = Launch<R>::c2r(N1, w1, (R*)phi, 1, N0, tw_m, tw_pl, st);
+        if (e == hipSuccess) e = mark();
     }
     return e;
 }
 
 hipError_t apply_plan(const fsa_plan_s* pl, const void* rho, void* phi, void* ws,
-                      hipStream_t st) {
-    return pl->prec == FSA_F32 ? apply_impl<float>(pl, rho, phi, ws, st)
-                               : apply_impl<double>(pl, rho, phi, ws, st);
+                      hipStream_t st, hipEvent_t const* events) {
+    return pl->prec == FSA_F32 ? apply_impl<float>(pl, rho, phi, ws, st, events)
+                               : apply_impl<double>(pl, rho, phi, ws, st, events);
 }
 
 }  // namespace fsa
 
 extern "C" {
 
-fsa_status fsa_apply(fsa_plan pl, const void* rho, void* phi, void* workspace, void* stream) {
+static fsa_status apply_checked(fsa_plan pl, const void* rho, void* phi, void* workspace,
+                                void* stream, hipEvent_t const* events) {
     if (!pl) return fail(FSA_EINVAL, "fsa_apply: null plan");
     if (!rho || !phi || !workspace) return fail(FSA_EINVAL, "fsa_apply: null device pointer");
     if (!pl->built) return fail(FSA_ESTATE, "fsa_apply: tensor not built (call fsa_build_tensor)");
@@ -246,9 +261,25 @@ fsa_status fsa_apply(fsa_plan pl, const void* rho, void* phi, void* workspace, v
     if (dev != pl->device)
         return fail(FSA_ESTATE, "fsa_apply: plan built on device %d, current device is %d",
                     pl->device, dev);
-    e = fsa::apply_plan(pl, rho, phi, workspace, (hipStream_t)stream);
+    e = fsa::apply_plan(pl, rho, phi, workspace, (hipStream_t)stream, events);
     if (e != hipSuccess) return hip_fail(e, "fsa_apply: kernel launch");
     return FSA_OK;
+}
+
+fsa_status fsa_apply(fsa_plan pl, const void* rho, void* phi, void* workspace, void* stream) {
+    return apply_checked(pl, rho, phi, workspace, stream, nullptr);
+}
+
+fsa_status fsa_apply_events(fsa_plan pl, const void* rho, void* phi, void* workspace,
+                            void* stream, void* const* events, int n_events) {
+    if (!pl || !events) return fail(FSA_EINVAL, "fsa_apply_events: null argument");
+    const int need = (pl->d == 3 ? 5 : 3) + 1;
+    if (n_events != need)
+        return fail(FSA_EINVAL, "fsa_apply_events: need %d events for a %dD plan, got %d", need,
+                    pl->d, n_events);
+    for (int i = 0; i < need; ++i)
+        if (!events[i]) return fail(FSA_EINVAL, "fsa_apply_events: null event %d", i);
+    return apply_checked(pl, rho, phi, workspace, stream, (hipEvent_t const*)events);
 }
 
 fsa_status fsa_plan_tensor(fsa_plan pl, const void** tensor, int64_t* dims) {

@@ -5,7 +5,8 @@
 
 namespace fsa {
 void set_last_error(const char* msg);
-hipError_t apply_plan(const fsa_plan_s* pl, const void* rho, void* phi, void* ws, hipStream_t st);
+hipError_t apply_plan(const fsa_plan_s* pl, const void* rho, void* phi, void* ws, hipStream_t st,
+                      hipEvent_t const* events);
 }
 
 static size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
@@ -49,7 +50,7 @@ fsa_status fsa_apply_batched(int n, const fsa_plan* plans, const void* const* rh
             fsa::set_last_error("fsa_apply_batched: tensor not built");
             return FSA_ESTATE;
         }
-        hipError_t e = fsa::apply_plan(plans[i], rho[i], phi[i], ws, (hipStream_t)stream);
+        hipError_t e = fsa::apply_plan(plans[i], rho[i], phi[i], ws, (hipStream_t)stream, nullptr);
         if (e != hipSuccess) {
             fsa::set_last_error(hipGetErrorString(e));
             return FSA_EDEVICE;

@@ -37,7 +37,7 @@ STATUS = {
 }
 
 EXPORTS = (
-    "fsa_plan_create", "fsa_plan_query", "fsa_build_tensor", "fsa_apply",
+    "fsa_plan_create", "fsa_plan_query", "fsa_build_tensor", "fsa_apply", "fsa_apply_events",
     "fsa_batch_workspace_bytes", "fsa_apply_batched", "fsa_plan_destroy", "fsa_plan_tensor",
     "fsa_server_create", "fsa_server_submit", "fsa_server_poll", "fsa_server_wait",
     "fsa_server_cancel", "fsa_server_stats", "fsa_server_destroy", "fsa_last_error",
@@ -80,6 +80,7 @@ def _load():
         "fsa_plan_query": [P, P, P, P, P],
         "fsa_build_tensor": [P, P],
         "fsa_apply": [P, P, P, P, P],
+        "fsa_apply_events": [P, P, P, P, P, P, I],
         "fsa_batch_workspace_bytes": [I, P, P],
         "fsa_apply_batched": [I, P, P, P, P, S, P],
         "fsa_plan_destroy": [P],
@@ -203,6 +204,24 @@ class Plan:
         _check(_lib.fsa_apply(self._h, ctypes.c_void_p(rho.data_ptr()),
                               ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(self._ws_ptr(ws)),
                               _stream_ptr(stream)))
+        return out
+
+    @property
+    def n_passes(self) -> int:
+        return 5 if self.d == 3 else 3
+
+    def apply_events(self, rho: torch.Tensor, out: torch.Tensor, events,
+                     workspace: Optional[torch.Tensor] = None,
+                     stream: Optional[torch.cuda.Stream] = None) -> torch.Tensor:
+        """fsa_apply with caller-created hipEvent_t handles recorded around each pass."""
+        self.check_input(rho)
+        self.check_input(out)
+        ws = workspace if workspace is not None else self.workspace()
+        arr = (ctypes.c_void_p * len(events))(*events)
+        _check(_lib.fsa_apply_events(self._h, ctypes.c_void_p(rho.data_ptr()),
+                                     ctypes.c_void_p(out.data_ptr()),
+                                     ctypes.c_void_p(self._ws_ptr(ws)), _stream_ptr(stream), arr,
+                                     len(events)))
         return out
 
     def tensor(self) -> torch.Tensor:
