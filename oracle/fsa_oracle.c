@@ -450,6 +450,19 @@ int orc_build_tensor(int kind, double lam, double eps, int d, const double *L, c
 /* Discrete convolution Phi_i = sum_{i'} T_{i - i'} rho_{i'}  (eq. DiscConv)   */
 /* ------------------------------------------------------------------------- */
 
+/* Compensated (Neumaier) accumulation.  eq. DiscConv fixes the sum, not its
+ * rounding: a plain running sum of the ~10^7 same-signed terms of a 256^3
+ * grid drifts by ~1e-11 relative, so the direct sums carry the rounding error
+ * of each addition in a second accumulator. */
+typedef struct { double s, c; } kahan;
+static inline void kahan_add(kahan *k, double x)
+{
+    const double t = k->s + x;
+    if (fabs(k->s) >= fabs(x)) k->c += (k->s - t) + x;
+    else k->c += (x - t) + k->s;
+    k->s = t;
+}
+
 /* Direct O(prod N_j^2) sum over all output points. */
 int orc_conv_direct(int d, const int64_t *N, const double *T, const double *rho, double *phi)
 {
@@ -460,7 +473,7 @@ int orc_conv_direct(int d, const int64_t *N, const double *T, const double *rho,
 #pragma omp parallel for schedule(dynamic, 16)
     for (long i = 0; i < M; ++i) {
         const long i0 = i / (Nn[1] * Nn[2]), i1 = (i / Nn[2]) % Nn[1], i2 = i % Nn[2];
-        double acc = 0.0;
+        kahan acc = {0.0, 0.0};
         for (long a = 0; a < Nn[0]; ++a) {
             const long m0 = ((i0 - a) % P[0] + P[0]) % P[0];
             for (long b = 0; b < Nn[1]; ++b) {
@@ -469,11 +482,11 @@ int orc_conv_direct(int d, const int64_t *N, const double *T, const double *rho,
                 const double *rrow = rho + ((size_t)a * Nn[1] + (size_t)b) * Nn[2];
                 for (long c = 0; c < Nn[2]; ++c) {
                     const long m2 = ((i2 - c) % P[2] + P[2]) % P[2];
-                    acc += trow[m2] * rrow[c];
+                    kahan_add(&acc, trow[m2] * rrow[c]);
                 }
             }
         }
-        phi[i] = acc;
+        phi[i] = acc.s + acc.c;
     }
     return 0;
 }
@@ -489,7 +502,7 @@ int orc_conv_direct_points(int d, const int64_t *N, const double *T, const doubl
     for (long t = 0; t < npts; ++t) {
         const long i = (long)flat_idx[t];
         const long i0 = i / (Nn[1] * Nn[2]), i1 = (i / Nn[2]) % Nn[1], i2 = i % Nn[2];
-        double acc = 0.0;
+        kahan acc = {0.0, 0.0};
         for (long a = 0; a < Nn[0]; ++a) {
             const long m0 = ((i0 - a) % P[0] + P[0]) % P[0];
             for (long b = 0; b < Nn[1]; ++b) {
@@ -498,11 +511,11 @@ int orc_conv_direct_points(int d, const int64_t *N, const double *T, const doubl
                 const double *rrow = rho + ((size_t)a * Nn[1] + (size_t)b) * Nn[2];
                 for (long c = 0; c < Nn[2]; ++c) {
                     const long m2 = ((i2 - c) % P[2] + P[2]) % P[2];
-                    acc += trow[m2] * rrow[c];
+                    kahan_add(&acc, trow[m2] * rrow[c]);
                 }
             }
         }
-        out[t] = acc;
+        out[t] = acc.s + acc.c;
     }
     return 0;
 }

@@ -150,3 +150,19 @@ def test_rejects_bad_geometry():
         O.build_tensor("coulomb3d", (1.0, 1.0), (8, 8), 0.2)
     with pytest.raises(ValueError):
         O.build_tensor("log2d", (1.0, -1.0), (8, 8), 0.2)
+
+
+def test_direct_sum_is_compensated():
+    """Same-signed terms: the direct sum matches a long-double sum to a few ulps."""
+    rng = np.random.default_rng(21)
+    N = (40, 40, 40)
+    T = rng.uniform(0.5, 1.5, size=(80, 80, 80))
+    rho = rng.uniform(0.5, 1.5, size=N)
+    idx = rng.choice(rho.size, 6, replace=False)
+    got = O.conv_direct_points(T, rho, idx)
+    for v, i in zip(got, idx):
+        i0, i1, i2 = np.unravel_index(i, N)
+        sub = T[np.ix_((i0 - np.arange(40)) % 80, (i1 - np.arange(40)) % 80,
+                       (i2 - np.arange(40)) % 80)]
+        ref = np.sum((sub * rho).astype(np.longdouble), dtype=np.longdouble)
+        assert abs(v - float(ref)) <= 4e-16 * abs(float(ref))
