@@ -176,9 +176,12 @@ constexpr int ilog2_exact(int x) {
 }
 
 // Lengths 2^a (a >= 2) and 3 * 2^a (a >= 2).  Power-of-two stages use radices
-// of at most 8 (P < 1024) or 16 (P >= 1024) spread as evenly as possible, the
-// factor 3 runs last; T is the largest power of two with T * E <= P for
-// E = 8 or 16 operands per thread, capped at 256.
+// of at most 8 (P < 1024) or 16 (P >= 1024); the bits are spread so that the
+// radix sequence reads the same both ways whenever possible (the inverse runs
+// the radices reversed, so a palindromic plan lets the forward and inverse
+// transforms of the fused pass share one set of twiddles).  The factor 3 runs
+// last.  T is the largest power of two with T * E <= P for E = 8 or 16
+// operands per thread, capped at 256.
 constexpr FftPlan make_fft_plan(int P) {
     FftPlan p{};
     p.P = P;
@@ -190,11 +193,22 @@ constexpr FftPlan make_fft_plan(int P) {
     const int a = ilog2_exact(m);
     const int maxbits = (P >= 1024) ? 4 : 3;
     const int nst = (a + maxbits - 1) / maxbits;
-    int n = 0;
-    for (int s = 0; s < nst; ++s) {
-        const int bits = a / nst + (s < a % nst ? 1 : 0);
-        p.r[n++] = 1 << bits;
+    int bits[16] = {};
+    if (nst == 3) {
+        // ends e, middle m, 2e + m = a: palindromic by construction
+        int e = a / 3, m = a - 2 * e;
+        while (m > maxbits) {
+            ++e;
+            m -= 2;
+        }
+        bits[0] = e;
+        bits[1] = m;
+        bits[2] = e;
+    } else {
+        for (int s = 0; s < nst; ++s) bits[s] = a / nst + (s < a % nst ? 1 : 0);
     }
+    int n = 0;
+    for (int s = 0; s < nst; ++s) p.r[n++] = 1 << bits[s];
     for (int t = 0; t < threes; ++t) p.r[n++] = 3;
     p.n = n;
     const int E = (P >= 1024) ? 16 : 8;
@@ -271,6 +285,65 @@ struct Fft {
             }
             dft<RAD, INV>(&v[b * RAD]);
         }
+    }
+
+    // ---- twiddles held in registers ----------------------------------------
+    // Thread t's twiddles depend only on t, so a thread that transforms many
+    // pencils loads them once: stage s >= 1, butterfly b, q = 1..R_s-1.
+    static constexpr int tw_count(int s) { return nbt(s) * (radix(s) - 1); }
+    static constexpr int tw_off(int s) {
+        int o = 0;
+        for (int t = 1; t < s; ++t) o += tw_count(t);
+        return o;
+    }
+    static constexpr int NTW_ = tw_off(S) > 0 ? tw_off(S) : 1;
+    static constexpr int NTW = NTW_;
+
+    // forward-direction twiddles (the inverse conjugates them on use)
+    FSA_HD static void load_tw(C (&w)[NTW], int tid, const C* __restrict__ tw) {
+        load_tw_from<1>(w, tid, tw);
+    }
+    template <int s>
+    FSA_HD static void load_tw_from(C (&w)[NTW], int tid, const C* __restrict__ tw) {
+        if constexpr (s < S) {
+            constexpr int RAD = radix(s), NS = ns(s), NB = nb(s), NBT = nbt(s);
+            constexpr int STEP = P_ / (NS * RAD), OFF = tw_off(s);
+#pragma unroll
+            for (int b = 0; b < NBT; ++b) {
+                const int j = tid + b * T;
+                const int k = ((NB % T) != 0 && j >= NB) ? 0 : j % NS;
+#pragma unroll
+                for (int q = 1; q < RAD; ++q) w[OFF + b * (RAD - 1) + q - 1] = tw[q * k * STEP];
+            }
+            load_tw_from<s + 1>(w, tid, tw);
+        }
+    }
+
+    // stage s with twiddles from registers laid out like load_tw's
+    template <int s>
+    FSA_HD static void compute_r(C (&v)[V], int tid, const C (&w)[NTW]) {
+        constexpr int RAD = radix(s), NS = ns(s), NB = nb(s), NBT = nbt(s), OFF = tw_off(s);
+#pragma unroll
+        for (int b = 0; b < NBT; ++b) {
+            const int j = tid + b * T;
+            if ((NB % T) != 0 && j >= NB) continue;
+            if constexpr (NS > 1) {
+#pragma unroll
+                for (int q = 1; q < RAD; ++q) {
+                    const C t = w[OFF + b * (RAD - 1) + q - 1];
+                    v[b * RAD + q] = INV ? cmulc(v[b * RAD + q], t) : cmul(v[b * RAD + q], t);
+                }
+            }
+            dft<RAD, INV>(&v[b * RAD]);
+        }
+    }
+
+    // the inverse of a palindromic plan has the forward's (radix, NS) per
+    // stage, hence the same twiddles (conjugated on use)
+    static constexpr bool palindromic() {
+        for (int s = 0; s < S; ++s)
+            if (plan.r[s] != plan.r[S - 1 - s]) return false;
+        return true;
     }
 
     // write the outputs of stage s to the scratch
@@ -357,6 +430,34 @@ struct Fft {
         } else {
             __syncthreads();
         }
+    }
+
+    // Orders LDS only: waits for this wave's LDS operations, then a wave
+    // (T <= 64) or workgroup barrier; global loads in flight keep flying.
+    static __device__ __forceinline__ void sync_lds() {
+        __builtin_amdgcn_s_waitcnt(0xc07f);  // lgkmcnt(0), vmcnt/expcnt untouched
+        if constexpr (T <= 64) __builtin_amdgcn_wave_barrier();
+        else __builtin_amdgcn_s_barrier();
+        asm volatile("" ::: "memory");
+    }
+
+    template <int s>
+    static __device__ __forceinline__ void run_r_from(C (&v)[V], C* scr, int tid,
+                                                      const C (&w)[NTW]) {
+        if constexpr (s < S) {
+            store<s - 1>(v, scr, tid);
+            sync_lds();
+            load<s>(v, scr, tid);
+            sync_lds();
+            compute_r<s>(v, tid, w);
+            run_r_from<s + 1>(v, scr, tid, w);
+        }
+    }
+
+    // run() with register twiddles and LDS-only synchronisation
+    static __device__ __forceinline__ void run_r(C (&v)[V], C* scr, int tid, const C (&w)[NTW]) {
+        compute_r<0>(v, tid, w);
+        run_r_from<1>(v, scr, tid, w);
     }
 
     template <int s>

@@ -95,6 +95,35 @@ hipError_t Launch<R>::inv_t(int P, const void* in, void* out, int N0, int H, con
     return hipGetLastError();
 }
 
+// Compute units of the current device (the library drives one device).
+inline int device_cus() {
+    static const int cus = [] {
+        int dev = 0, n = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+            n <= 0)
+            n = 256;
+        return n;
+    }();
+    return cus;
+}
+
+// Resident workgroups per CU of a kernel at a block size.
+template <typename Kern>
+int blocks_per_cu(Kern kernel, int threads) {
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, threads, 0) != hipSuccess ||
+        per_cu <= 0)
+        per_cu = 1;
+    return per_cu;
+}
+
+// Workgroups that fill every CU once, but no more than the work needs.
+inline int persistent_grid(int per_cu, int work_groups_needed) {
+    const int g = device_cus() * per_cu;
+    return g < work_groups_needed ? g : (work_groups_needed > 0 ? work_groups_needed : 1);
+}
+
 template <typename R>
 hipError_t Launch<R>::conv(int P, void* data, const R* tensor, int n_pencils, int P1, int N1,
                            const void* tw, hipStream_t st) {
@@ -102,9 +131,10 @@ hipError_t Launch<R>::conv(int P, void* data, const R* tensor, int n_pencils, in
 #define FSA_CASE(p)                                                                              \
     case p: {                                                                                    \
         using K = Conv<R, p>;                                                                    \
-        dim3 grid((n_pencils + K::TPW - 1) / K::TPW);                                           \
-        hipLaunchKernelGGL((k_conv<R, p>), grid, dim3(K::THREADS), 0, st, (cpx<R>*)data, tensor, \
-                           n_pencils, P1, N1, (const cpx<R>*)tw);                                \
+        static const int per_cu = blocks_per_cu(k_conv<R, p>, K::THREADS);                      \
+        const int grid = persistent_grid(per_cu, (n_pencils + K::TPW - 1) / K::TPW);            \
+        hipLaunchKernelGGL((k_conv<R, p>), dim3(grid), dim3(K::THREADS), 0, st, (cpx<R>*)data,   \
+                           tensor, n_pencils, P1, N1, (const cpx<R>*)tw);                        \
         break;                                                                                   \
     }
         FSA_P_LIST(FSA_CASE)

@@ -260,6 +260,12 @@ __global__ __launch_bounds__((InvT<R, P>::THREADS)) void k_inv_t(const cpx<R>* _
 // C2C, product with the real octant tensor, inverse C2C, crop -- in place.
 //   pencil q = p2 * P1 + p1 (3D) or q = p1 (2D: P1 = 1, N1 = 0),
 //   data[q * N0 + i0];  tensor[((p2 (N1+1) + |p1|) (N0+1)) + |p0|]
+//
+// Persistent: the grid fills the GPU once; every team walks a contiguous
+// chunk of work items.  Its twiddles are loaded into registers once, the next
+// pencil's non-zero half is prefetched while the current one is transformed,
+// and items are ordered so that the mirror pencils p1 and P1 - p1, which read
+// the same tensor row, follow each other.
 // ---------------------------------------------------------------------------
 template <typename R, int P>
 struct Conv {
@@ -270,13 +276,31 @@ struct Conv {
     static constexpr int TPW = T >= 256 ? 1 : 256 / T;  // teams per workgroup
     static constexpr int THREADS = TPW * T;
     static constexpr int LDS = TPW * Ff::SCR;
+    static constexpr bool SHARED_TW = Ff::palindromic();
+    static constexpr int R0 = Ff::first_radix();
+    static constexpr int NB0 = Ff::first_stride();
+    static constexpr int NBT0 = Ff::first_nbt();
+    static constexpr int HALF = R0 / 2;  // first-stage operands with index < P/2
+    static constexpr int NPF = NBT0 * HALF;
+    static_assert(R0 % 2 == 0, "the zero half must be whole first-stage operands");
+    static_assert(Ff::last_radix() == Fi::first_radix(), "register hand-off");
 };
+
+// work item t -> pencil, ordered (p2; p1 = 0, N1, 1, P1-1, 2, P1-2, ...)
+__device__ __forceinline__ int conv_item_to_pencil(int t, int P1, int N1) {
+    const int p2 = t / P1, u = t - p2 * P1;
+    int p1;
+    if (P1 == 1) p1 = 0;
+    else if (u < 2) p1 = u ? N1 : 0;
+    else p1 = (u & 1) ? P1 - (u >> 1) : (u >> 1);
+    return p2 * P1 + p1;
+}
 
 template <typename R, int P>
 __global__ __launch_bounds__((Conv<R, P>::THREADS)) void k_conv(cpx<R>* __restrict__ data,
-                                                              const R* __restrict__ tensor,
-                                                              int n_pencils, int P1, int N1,
-                                                              const cpx<R>* __restrict__ tw) {
+                                                                const R* __restrict__ tensor,
+                                                                int n_pencils, int P1, int N1,
+                                                                const cpx<R>* __restrict__ tw) {
     using K = Conv<R, P>;
     using Ff = typename K::Ff;
     using Fi = typename K::Fi;
@@ -284,20 +308,59 @@ __global__ __launch_bounds__((Conv<R, P>::THREADS)) void k_conv(cpx<R>* __restri
     constexpr int N0 = P / 2;
     __shared__ C lds[K::LDS];
     const int team = threadIdx.x / K::T, tid = threadIdx.x % K::T;
-    const int q = blockIdx.x * K::TPW + team;
-    const bool active = q < n_pencils;
-    const int qc = active ? q : 0;
-    C* pen = data + (size_t)qc * N0;
     C* scr = lds + team * Ff::SCR;
-    C v[Ff::V];
-    Ff::load_first(v, tid, active ? N0 : 0, [&](int i) { return pen[i]; });
-    Ff::run(v, scr, tid, tw);
-    const int p2 = qc / P1, p1 = qc - p2 * P1;
-    const int a1 = p1 <= N1 ? p1 : P1 - p1;
-    const R* trow = tensor + ((size_t)p2 * (N1 + 1) + a1) * (N0 + 1);
-    Ff::for_each_last(v, tid, [&](int p0, C& c) { c = scale(c, trow[p0 <= N0 ? p0 : P - p0]); });
-    Fi::run(v, scr, tid, tw);
-    if (active) Fi::store_last(v, tid, N0, [&](int i, C c) { pen[i] = c; });
+
+    C wf[Ff::NTW];
+    Ff::load_tw(wf, tid, tw);
+    C wi[K::SHARED_TW ? 1 : Fi::NTW];
+    if constexpr (!K::SHARED_TW) Fi::load_tw(wi, tid, tw);
+
+    const int slots = gridDim.x * K::TPW;
+    const int chunk = (n_pencils + slots - 1) / slots;
+    const int first = (blockIdx.x * K::TPW + team) * chunk;
+
+    C pf[K::NPF];
+    auto prefetch = [&](int item) {
+        if (item < n_pencils) {
+            const C* pen = data + (size_t)conv_item_to_pencil(item, P1, N1) * N0;
+#pragma unroll
+            for (int b = 0; b < K::NBT0; ++b)
+#pragma unroll
+                for (int q = 0; q < K::HALF; ++q) pf[b * K::HALF + q] = pen[tid + b * K::T + q * K::NB0];
+        }
+    };
+    prefetch(first);
+    for (int it = 0; it < chunk; ++it) {
+        const int item = first + it;
+        const bool active = item < n_pencils;
+        C v[Ff::V];
+#pragma unroll
+        for (int b = 0; b < K::NBT0; ++b)
+#pragma unroll
+            for (int q = 0; q < K::R0; ++q)
+                v[b * K::R0 + q] = q < K::HALF ? pf[b * K::HALF + q] : mk(R(0), R(0));
+        if (it + 1 < chunk) prefetch(item + 1);
+        const int qp = active ? conv_item_to_pencil(item, P1, N1) : 0;
+        const int p2 = qp / P1, p1 = qp - p2 * P1;
+        const int a1 = p1 <= N1 ? p1 : P1 - p1;
+        const R* trow = tensor + ((size_t)p2 * (N1 + 1) + a1) * (N0 + 1);
+        R tv[Ff::V];
+        {
+            int i = 0;
+            Ff::for_each_last(v, tid, [&](int p0, C&) { tv[i++] = trow[p0 <= N0 ? p0 : P - p0]; });
+        }
+        Ff::run_r(v, scr, tid, wf);
+        {
+            int i = 0;
+            Ff::for_each_last(v, tid, [&](int, C& c) { c = scale(c, tv[i++]); });
+        }
+        if constexpr (K::SHARED_TW) Fi::run_r(v, scr, tid, wf);
+        else Fi::run_r(v, scr, tid, wi);
+        if (active) {
+            C* pen = data + (size_t)qp * N0;
+            Fi::store_last(v, tid, N0, [&](int i, C c) { pen[i] = c; });
+        }
+    }
 }
 
 }  // namespace fsa

@@ -45,11 +45,36 @@ static void emu_from(typename F::C (*v)[F::V], typename F::C* scr, const typenam
     }
 }
 
+// the register-twiddle path: twiddles loaded per thread once, stages take them from registers
+template <typename F, int s>
+static void emu_r_from(typename F::C (*v)[F::V], typename F::C* scr,
+                       const std::vector<std::vector<typename F::C>>& w) {
+    if constexpr (s < F::S) {
+        for (int t = 0; t < F::T; ++t) F::template store<s - 1>(v[t], scr, t);
+        for (int t = 0; t < F::T; ++t) F::template load<s>(v[t], scr, t);
+        for (int t = 0; t < F::T; ++t)
+            F::template compute_r<s>(v[t], t,
+                                     *reinterpret_cast<const typename F::C(*)[F::NTW]>(w[t].data()));
+        emu_r_from<F, s + 1>(v, scr, w);
+    }
+}
+
+static bool g_register_twiddles = false;
+
 template <typename F>
 static void emu_run(typename F::C (*v)[F::V], const typename F::C* tw) {
     std::vector<typename F::C> scr(F::SCR);
-    for (int t = 0; t < F::T; ++t) F::template compute<0>(v[t], t, tw);
-    emu_from<F, 1>(v, scr.data(), tw);
+    if (!g_register_twiddles) {
+        for (int t = 0; t < F::T; ++t) F::template compute<0>(v[t], t, tw);
+        emu_from<F, 1>(v, scr.data(), tw);
+        return;
+    }
+    std::vector<std::vector<typename F::C>> w(F::T, std::vector<typename F::C>(F::NTW));
+    for (int t = 0; t < F::T; ++t)
+        F::load_tw(*reinterpret_cast<typename F::C(*)[F::NTW]>(w[t].data()), t, tw);
+    for (int t = 0; t < F::T; ++t)
+        F::template compute_r<0>(v[t], t, *reinterpret_cast<const typename F::C(*)[F::NTW]>(w[t].data()));
+    emu_r_from<F, 1>(v, scr.data(), w);
 }
 
 template <typename R, int P>
@@ -155,10 +180,13 @@ static int check_all() {
 
 int main() {
     int f = 0;
+    for (int mode = 0; mode < 2; ++mode) {
+    g_register_twiddles = mode == 1;
     f += check_all<double, 8, 12, 16, 24, 32, 48, 64, 96, 128, 192, 256, 384, 512, 768, 1024, 1536,
                    2048, 3072, 4096>();
     f += check_all<float, 8, 12, 16, 24, 32, 48, 64, 96, 128, 192, 256, 384, 512, 768, 1024, 1536,
                    2048, 3072, 4096>();
+    }
     std::printf("%s (%d failures)\n", f ? "FAILED" : "OK", f);
     return f ? 1 : 0;
 }
