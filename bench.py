@@ -190,6 +190,27 @@ def bench_precision(F, torch, hip, prob, rho64, prec, steps, warmup):
     }, phi
 
 
+def stream_copy(torch, hip, nbytes=1 << 30, reps=10):
+    """Device-to-device copy of nbytes (torch copy_ kernel): the practical
+    bandwidth of the box, read + write bytes over time."""
+    x = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda").fill_(1.0)
+    y = torch.empty_like(x)
+    stream = torch.cuda.current_stream()
+    for _ in range(3):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    e0, e1 = hip.event(), hip.event()
+    hip.record(e0, stream)
+    for _ in range(reps):
+        y.copy_(x)
+    hip.record(e1, stream)
+    ms = hip.ms(e0, e1) / reps
+    hip.destroy(e0)
+    hip.destroy(e1)
+    del x, y
+    return 2.0 * nbytes / (ms * 1e-3)
+
+
 def cpu_baseline(synth):
     """The FP64 oracle on the host cores: one evaluation of the same Yukawa
     workload at 128^3 (tensor build + FFT convolution)."""
@@ -224,6 +245,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--n", type=int, default=256, help="grid points per axis")
+    ap.add_argument("--copy-only", action="store_true",
+                    help="only run the 1 GiB device copy (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print(f"bench.py: this build runs on exactly one GPU (asked for {args.gpus}); the "
@@ -240,6 +263,10 @@ def main():
         sys.exit(3)
     torch.cuda.set_device(0)
     hip = Hip()
+    copy_bps = stream_copy(torch, hip)
+    log(f"stream copy (1 GiB): {copy_bps / 1e9:.0f} GB/s")
+    if args.copy_only:
+        return
     prob = synth.yukawa_problem(1.0, args.n, "f32")
     log(f"density: {len(prob.gaussians)} Gaussians on {prob.N} ...")
     rho64 = synth.eval_gaussians(prob.gaussians, prob.L, prob.N)
@@ -288,6 +315,8 @@ def main():
         "precomp_ms": r32["precomp_ms"],
         "wall_ms_per_step": r32["wall_ms_per_step"],
         "f32_vs_f64_rel_l2": diff,
+        "stream_copy_GBps": copy_bps / 1e9,
+        "model_copy_frac": r32["model_bytes_per_step"] / (r32["ms_per_step"] * 1e-3) / copy_bps,
         "kernel_source_hash": kernel_source_hash(),
         "paper_context": "FSA Execution 2.24 s / Precomp 2.84 s at 192^3 in FP64, FORTRAN on one "
                          "Xeon Gold 6248R 3.0 GHz (Table 3); other hardware, context only",

@@ -391,6 +391,22 @@ struct Fft {
         }
     }
 
+    // as load_first, with the operand's register position: v[pos] = f(index, pos)
+    template <class F>
+    FSA_HD static void load_first_at(C (&v)[V], int tid, int n_in, F&& f) {
+        constexpr int RAD = radix(0), NB = nb(0), NBT = nbt(0);
+#pragma unroll
+        for (int b = 0; b < NBT; ++b) {
+            const int j = tid + b * T;
+#pragma unroll
+            for (int q = 0; q < RAD; ++q) {
+                const int idx = j + q * NB;
+                const bool ok = ((NB % T) == 0 || j < NB) && idx < n_in;
+                v[b * RAD + q] = ok ? f(idx, b * RAD + q) : mk(R(0), R(0));
+            }
+        }
+    }
+
     // last-stage outputs to an arbitrary sink: f(index, value) for index < n_out
     template <class F>
     FSA_HD static void store_last(const C (&v)[V], int tid, int n_out, F&& f) {

@@ -15,86 +15,6 @@
 
 namespace fsa {
 
-template <typename R>
-hipError_t Launch<R>::r2c(int M, const R* rho, void* out, int n_outer, int n_inner,
-                          const void* twM, const void* tw2M, hipStream_t st) {
-    switch (M) {
-#define FSA_CASE(m)                                                                              \
-    case m: {                                                                                    \
-        using K = R2c<R, m>;                                                                     \
-        dim3 grid((n_inner + K::WT - 1) / K::WT, n_outer);                                      \
-        hipLaunchKernelGGL((k_r2c<R, m>), grid, dim3(K::THREADS), 0, st, rho, (cpx<R>*)out,     \
-                           n_outer, n_inner, (const cpx<R>*)twM, (const cpx<R>*)tw2M);           \
-        break;                                                                                   \
-    }
-        FSA_M_LIST(FSA_CASE)
-#undef FSA_CASE
-    default:
-        return hipErrorInvalidValue;
-    }
-    return hipGetLastError();
-}
-
-template <typename R>
-hipError_t Launch<R>::c2r(int M, const void* in, R* phi, int n_outer, int n_inner,
-                          const void* twM, const void* tw2M, hipStream_t st) {
-    switch (M) {
-#define FSA_CASE(m)                                                                              \
-    case m: {                                                                                    \
-        using K = C2r<R, m>;                                                                     \
-        dim3 grid((n_inner + K::WT - 1) / K::WT, n_outer);                                      \
-        hipLaunchKernelGGL((k_c2r<R, m>), grid, dim3(K::THREADS), 0, st, (const cpx<R>*)in, phi, \
-                           n_outer, n_inner, (const cpx<R>*)twM, (const cpx<R>*)tw2M);           \
-        break;                                                                                   \
-    }
-        FSA_M_LIST(FSA_CASE)
-#undef FSA_CASE
-    default:
-        return hipErrorInvalidValue;
-    }
-    return hipGetLastError();
-}
-
-template <typename R>
-hipError_t Launch<R>::fwd_t(int P, const void* in, void* out, int N0, int H, const void* tw,
-                            hipStream_t st) {
-    switch (P) {
-#define FSA_CASE(p)                                                                              \
-    case p: {                                                                                    \
-        using K = FwdT<R, p>;                                                                    \
-        dim3 grid((N0 + K::WT - 1) / K::WT, H);                                                 \
-        hipLaunchKernelGGL((k_fwd_t<R, p>), grid, dim3(K::THREADS), 0, st, (const cpx<R>*)in,    \
-                           (cpx<R>*)out, N0, H, (const cpx<R>*)tw);                              \
-        break;                                                                                   \
-    }
-        FSA_P_LIST(FSA_CASE)
-#undef FSA_CASE
-    default:
-        return hipErrorInvalidValue;
-    }
-    return hipGetLastError();
-}
-
-template <typename R>
-hipError_t Launch<R>::inv_t(int P, const void* in, void* out, int N0, int H, const void* tw,
-                            hipStream_t st) {
-    switch (P) {
-#define FSA_CASE(p)                                                                              \
-    case p: {                                                                                    \
-        using K = InvT<R, p>;                                                                    \
-        dim3 grid((N0 + K::WT - 1) / K::WT, H);                                                 \
-        hipLaunchKernelGGL((k_inv_t<R, p>), grid, dim3(K::THREADS), 0, st, (const cpx<R>*)in,    \
-                           (cpx<R>*)out, N0, H, (const cpx<R>*)tw);                              \
-        break;                                                                                   \
-    }
-        FSA_P_LIST(FSA_CASE)
-#undef FSA_CASE
-    default:
-        return hipErrorInvalidValue;
-    }
-    return hipGetLastError();
-}
-
 // Compute units of the current device (the library drives one device).
 inline int device_cus() {
     static const int cus = [] {
@@ -122,6 +42,90 @@ int blocks_per_cu(Kern kernel, int threads) {
 inline int persistent_grid(int per_cu, int work_groups_needed) {
     const int g = device_cus() * per_cu;
     return g < work_groups_needed ? g : (work_groups_needed > 0 ? work_groups_needed : 1);
+}
+
+template <typename R>
+hipError_t Launch<R>::r2c(int M, const R* rho, void* out, int n_outer, int n_inner,
+                          const void* twM, const void* tw2M, hipStream_t st) {
+    switch (M) {
+#define FSA_CASE(m)                                                                              \
+    case m: {                                                                                    \
+        using K = R2c<R, m>;                                                                     \
+        static const int per_cu = blocks_per_cu(k_r2c<R, m>, K::THREADS);                       \
+        const int grid = persistent_grid(per_cu, ((n_inner + K::WT - 1) / K::WT) * n_outer);    \
+        hipLaunchKernelGGL((k_r2c<R, m>), dim3(grid), dim3(K::THREADS), 0, st, rho, (cpx<R>*)out,     \
+                           n_outer, n_inner, (const cpx<R>*)twM, (const cpx<R>*)tw2M);           \
+        break;                                                                                   \
+    }
+        FSA_M_LIST(FSA_CASE)
+#undef FSA_CASE
+    default:
+        return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+template <typename R>
+hipError_t Launch<R>::c2r(int M, const void* in, R* phi, int n_outer, int n_inner,
+                          const void* twM, const void* tw2M, hipStream_t st) {
+    switch (M) {
+#define FSA_CASE(m)                                                                              \
+    case m: {                                                                                    \
+        using K = C2r<R, m>;                                                                     \
+        static const int per_cu = blocks_per_cu(k_c2r<R, m>, K::THREADS);                       \
+        const int grid = persistent_grid(per_cu, ((n_inner + K::WT - 1) / K::WT) * n_outer);    \
+        hipLaunchKernelGGL((k_c2r<R, m>), dim3(grid), dim3(K::THREADS), 0, st, (const cpx<R>*)in, phi, \
+                           n_outer, n_inner, (const cpx<R>*)twM, (const cpx<R>*)tw2M);           \
+        break;                                                                                   \
+    }
+        FSA_M_LIST(FSA_CASE)
+#undef FSA_CASE
+    default:
+        return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+template <typename R>
+hipError_t Launch<R>::fwd_t(int P, const void* in, void* out, int N0, int H, const void* tw,
+                            hipStream_t st) {
+    switch (P) {
+#define FSA_CASE(p)                                                                              \
+    case p: {                                                                                    \
+        using K = FwdT<R, p>;                                                                    \
+        static const int per_cu = blocks_per_cu(k_fwd_t<R, p>, K::THREADS);                     \
+        const int grid = persistent_grid(per_cu, ((N0 + K::WT - 1) / K::WT) * H);               \
+        hipLaunchKernelGGL((k_fwd_t<R, p>), dim3(grid), dim3(K::THREADS), 0, st, (const cpx<R>*)in,    \
+                           (cpx<R>*)out, N0, H, (const cpx<R>*)tw);                              \
+        break;                                                                                   \
+    }
+        FSA_P_LIST(FSA_CASE)
+#undef FSA_CASE
+    default:
+        return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+template <typename R>
+hipError_t Launch<R>::inv_t(int P, const void* in, void* out, int N0, int H, const void* tw,
+                            hipStream_t st) {
+    switch (P) {
+#define FSA_CASE(p)                                                                              \
+    case p: {                                                                                    \
+        using K = InvT<R, p>;                                                                    \
+        static const int per_cu = blocks_per_cu(k_inv_t<R, p>, K::THREADS);                     \
+        const int grid = persistent_grid(per_cu, ((N0 + K::WT - 1) / K::WT) * H);               \
+        hipLaunchKernelGGL((k_inv_t<R, p>), dim3(grid), dim3(K::THREADS), 0, st, (const cpx<R>*)in,    \
+                           (cpx<R>*)out, N0, H, (const cpx<R>*)tw);                              \
+        break;                                                                                   \
+    }
+        FSA_P_LIST(FSA_CASE)
+#undef FSA_CASE
+    default:
+        return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
 }
 
 template <typename R>

@@ -43,11 +43,32 @@ constexpr int tile_width(int csize, int T, int scr, int rows) {
 }
 
 constexpr int cmax(int a, int b) { return a > b ? a : b; }
+constexpr int cdiv(int a, int b) { return (a + b - 1) / b; }
+
+// Workgroup barrier that orders LDS only: global loads in flight (prefetch)
+// and global stores keep flying.
+__device__ __forceinline__ void sync_wg_lds() {
+    __builtin_amdgcn_s_waitcnt(0xc07f);  // lgkmcnt(0)
+    __builtin_amdgcn_s_barrier();
+    asm volatile("" ::: "memory");
+}
+
+// Contiguous chunk of work items for this workgroup (uniform over the group).
+struct Chunk {
+    int first, last;
+    __device__ Chunk(int items) {
+        const int c = (items + (int)gridDim.x - 1) / (int)gridDim.x;
+        first = (int)blockIdx.x * c;
+        last = first + c < items ? first + c : items;
+    }
+};
 
 // ---------------------------------------------------------------------------
 // Pass A: zero-pad + real-to-complex along the contiguous axis, transposed out
 //   rho rows r = outer * n_inner + inner of M reals (M = N_last), padded to
 //   2M; out[(outer * (M+1) + k) * n_inner + inner] = X[k], k in [0, M].
+// Work item = (outer, tile of WT rows); team w of the workgroup owns row
+// tile * WT + w.  Persistent, with the next item's rows prefetched.
 // ---------------------------------------------------------------------------
 template <typename R, int M>
 struct R2c {
@@ -60,6 +81,9 @@ struct R2c {
     static constexpr int LDS = cmax(WT * F::SCR, H * TS);
     static constexpr int THREADS = WT * T;
     static constexpr int NX = (H + T - 1) / T;
+    static constexpr int R0 = F::first_radix(), NB0 = F::first_stride(), NBT0 = F::first_nbt();
+    static constexpr int HALF = R0 / 2;
+    static_assert(R0 % 2 == 0, "zero half = whole first-stage operands");
 };
 
 template <typename R, int M>
@@ -73,48 +97,76 @@ __global__ __launch_bounds__((R2c<R, M>::THREADS)) void k_r2c(const R* __restric
     using C = cpx<R>;
     __shared__ C lds[K::LDS];
     const int team = threadIdx.x / K::T, tid = threadIdx.x % K::T;
-    const int tile = blockIdx.x, outer = blockIdx.y;
-    const int inner = tile * K::WT + team;
-    const bool active = inner < n_inner;
-    const R* row = rho + ((size_t)outer * n_inner + (active ? inner : 0)) * M;
-
-    C v[F::V];
-    F::load_first(v, tid, active ? M / 2 : 0,
-                  [&](int m) { return *reinterpret_cast<const C*>(row + 2 * m); });
     C* scr = lds + team * F::SCR;
-    F::run(v, scr, tid, twM);
-    F::store_last(v, tid, M, [&](int k, C z) { scr[F::pad(k)] = z; });
-    F::sync();
-    C x[K::NX];
+    C w[F::NTW];
+    F::load_tw(w, tid, twM);
+    C w2[K::NX];  // post-processing twiddles e^{-i pi k / M}, k = tid + i T
 #pragma unroll
     for (int i = 0; i < K::NX; ++i) {
         const int k = tid + i * K::T;
-        if (k < K::H) {
-            const C zk = scr[F::pad(k == M ? 0 : k)];
-            const C zm = scr[F::pad(k == 0 ? 0 : M - k)];
-            const C a = zk + conj(zm);
-            const C b = rot90<false>(zk - conj(zm));
-            x[i] = scale(a + cmul(tw2M[k], b), R(0.5));
+        w2[i] = tw2M[k < K::H ? k : 0];
+    }
+    const int ntile = cdiv(n_inner, K::WT);
+    const Chunk ch(ntile * n_outer);
+    C pf[K::NBT0 * K::HALF];
+    auto prefetch = [&](int item) {
+        const int outer = item / ntile, inner = (item - outer * ntile) * K::WT + team;
+        if (inner < n_inner) {
+            const R* row = rho + ((size_t)outer * n_inner + inner) * M;
+#pragma unroll
+            for (int b = 0; b < K::NBT0; ++b)
+#pragma unroll
+                for (int q = 0; q < K::HALF; ++q)
+                    pf[b * K::HALF + q] =
+                        *reinterpret_cast<const C*>(row + 2 * (tid + b * K::T + q * K::NB0));
         }
-    }
-    __syncthreads();
+    };
+    if (ch.first < ch.last) prefetch(ch.first);
+    for (int item = ch.first; item < ch.last; ++item) {
+        const int outer = item / ntile, col0 = (item - outer * ntile) * K::WT;
+        const bool active = col0 + team < n_inner;
+        C v[F::V];
 #pragma unroll
-    for (int i = 0; i < K::NX; ++i) {
-        const int k = tid + i * K::T;
-        if (k < K::H) lds[k * K::TS + team] = x[i];
-    }
-    __syncthreads();
-    const int col0 = tile * K::WT;
-    for (int e = threadIdx.x; e < K::H * K::WT; e += K::THREADS) {
-        const int k = e / K::WT, w = e % K::WT;
-        if (col0 + w < n_inner)
-            out[((size_t)outer * K::H + k) * n_inner + col0 + w] = lds[k * K::TS + w];
+        for (int b = 0; b < K::NBT0; ++b)
+#pragma unroll
+            for (int q = 0; q < K::R0; ++q)
+                v[b * K::R0 + q] = (q < K::HALF && active) ? pf[b * K::HALF + q] : mk(R(0), R(0));
+        if (item + 1 < ch.last) prefetch(item + 1);
+        F::run_r(v, scr, tid, w);
+        F::store_last(v, tid, M, [&](int k, C z) { scr[F::pad(k)] = z; });
+        F::sync_lds();
+        C x[K::NX];
+#pragma unroll
+        for (int i = 0; i < K::NX; ++i) {
+            const int k = tid + i * K::T;
+            if (k < K::H) {
+                const C zk = scr[F::pad(k == M ? 0 : k)];
+                const C zm = scr[F::pad(k == 0 ? 0 : M - k)];
+                const C a = zk + conj(zm);
+                const C b = rot90<false>(zk - conj(zm));
+                x[i] = scale(a + cmul(w2[i], b), R(0.5));
+            }
+        }
+        sync_wg_lds();
+#pragma unroll
+        for (int i = 0; i < K::NX; ++i) {
+            const int k = tid + i * K::T;
+            if (k < K::H) lds[k * K::TS + team] = x[i];
+        }
+        sync_wg_lds();
+        for (int e = threadIdx.x; e < K::H * K::WT; e += K::THREADS) {
+            const int k = e / K::WT, ww = e - k * K::WT;
+            if (col0 + ww < n_inner)
+                out[((size_t)outer * K::H + k) * n_inner + col0 + ww] = lds[k * K::TS + ww];
+        }
+        sync_wg_lds();
     }
 }
 
 // ---------------------------------------------------------------------------
 // Pass E: complex-to-real along the contiguous axis with crop, transposed in
 //   in[(outer * (M+1) + k) * n_inner + inner] -> phi row r, first M reals of 2M.
+// Persistent; the next item's tile is prefetched into registers.
 // ---------------------------------------------------------------------------
 template <typename R, int M>
 struct C2r {
@@ -126,6 +178,8 @@ struct C2r {
     static constexpr int TS = WT + 1;
     static constexpr int LDS = cmax(WT * F::SCR, H * TS);
     static constexpr int THREADS = WT * T;
+    static constexpr int NT = (H * WT + THREADS - 1) / THREADS;  // tile elements per thread
+    static constexpr int R0 = F::first_radix(), NB0 = F::first_stride(), NBT0 = F::first_nbt();
 };
 
 template <typename R, int M>
@@ -139,37 +193,60 @@ __global__ __launch_bounds__((C2r<R, M>::THREADS)) void k_c2r(const cpx<R>* __re
     using C = cpx<R>;
     __shared__ C lds[K::LDS];
     const int team = threadIdx.x / K::T, tid = threadIdx.x % K::T;
-    const int tile = blockIdx.x, outer = blockIdx.y;
-    const int col0 = tile * K::WT;
-    for (int e = threadIdx.x; e < K::H * K::WT; e += K::THREADS) {
-        const int k = e / K::WT, w = e % K::WT;
-        lds[k * K::TS + w] = (col0 + w < n_inner)
-                                 ? in[((size_t)outer * K::H + k) * n_inner + col0 + w]
-                                 : mk(R(0), R(0));
-    }
-    __syncthreads();
-    C v[F::V];
-    F::load_first(v, tid, M, [&](int k) {
-        const C xk = lds[k * K::TS + team];
-        const C xm = lds[(M - k) * K::TS + team];
-        const C a = xk + conj(xm);
-        const C b = cmulc(xk - conj(xm), tw2M[k]);
-        return a + rot90<true>(b);
-    });
-    __syncthreads();
-    const int inner = col0 + team;
-    const bool active = inner < n_inner;
-    R* row = phi + ((size_t)outer * n_inner + (active ? inner : 0)) * M;
     C* scr = lds + team * F::SCR;
-    F::run(v, scr, tid, twM);
-    F::store_last(v, tid, M / 2, [&](int m, C z) {
-        if (active) *reinterpret_cast<C*>(row + 2 * m) = z;
-    });
+    C w[F::NTW];
+    F::load_tw(w, tid, twM);
+    C w2[F::V];  // e^{-i pi k / M} at this thread's first-stage operand indices k
+    F::load_first(w2, tid, M, [&](int k) { return tw2M[k]; });
+    const int ntile = cdiv(n_inner, K::WT);
+    const Chunk ch(ntile * n_outer);
+    C tp[K::NT];
+    auto prefetch = [&](int item) {
+        const int outer = item / ntile, col0 = (item - outer * ntile) * K::WT;
+#pragma unroll
+        for (int i = 0; i < K::NT; ++i) {
+            const int e = threadIdx.x + i * K::THREADS;
+            const int k = e / K::WT, ww = e - k * K::WT;
+            tp[i] = (e < K::H * K::WT && col0 + ww < n_inner)
+                        ? in[((size_t)outer * K::H + k) * n_inner + col0 + ww]
+                        : mk(R(0), R(0));
+        }
+    };
+    if (ch.first < ch.last) prefetch(ch.first);
+    for (int item = ch.first; item < ch.last; ++item) {
+        const int outer = item / ntile, col0 = (item - outer * ntile) * K::WT;
+#pragma unroll
+        for (int i = 0; i < K::NT; ++i) {
+            const int e = threadIdx.x + i * K::THREADS;
+            const int k = e / K::WT, ww = e - k * K::WT;
+            if (e < K::H * K::WT) lds[k * K::TS + ww] = tp[i];
+        }
+        sync_wg_lds();
+        if (item + 1 < ch.last) prefetch(item + 1);
+        C v[F::V];
+        F::load_first_at(v, tid, M, [&](int k, int pos) {
+            const C xk = lds[k * K::TS + team];
+            const C xm = lds[(M - k) * K::TS + team];
+            const C a = xk + conj(xm);
+            const C b = cmulc(xk - conj(xm), w2[pos]);
+            return a + rot90<true>(b);
+        });
+        sync_wg_lds();
+        F::run_r(v, scr, tid, w);
+        const int inner = col0 + team;
+        if (inner < n_inner) {
+            R* row = phi + ((size_t)outer * n_inner + inner) * M;
+            F::store_last(v, tid, M / 2,
+                          [&](int m, C z) { *reinterpret_cast<C*>(row + 2 * m) = z; });
+        }
+        sync_wg_lds();
+    }
 }
 
 // ---------------------------------------------------------------------------
 // Pass B (3D): zero-pad + forward C2C along axis 1, contiguous in, transposed out
 //   in[(i0 * H + p2) * N1 + i1] -> out[(p2 * P + p1) * N0 + i0],  P = 2 N1
+// Work item = (p2, tile of WT consecutive i0); persistent with prefetch.
 // ---------------------------------------------------------------------------
 template <typename R, int P>
 struct FwdT {
@@ -180,6 +257,9 @@ struct FwdT {
     static constexpr int TS = WT + 1;
     static constexpr int LDS = cmax(WT * F::SCR, P * TS);
     static constexpr int THREADS = WT * T;
+    static constexpr int R0 = F::first_radix(), NB0 = F::first_stride(), NBT0 = F::first_nbt();
+    static constexpr int HALF = R0 / 2;
+    static_assert(R0 % 2 == 0, "zero half = whole first-stage operands");
 };
 
 template <typename R, int P>
@@ -193,26 +273,50 @@ __global__ __launch_bounds__((FwdT<R, P>::THREADS)) void k_fwd_t(const cpx<R>* _
     constexpr int N1 = P / 2;
     __shared__ C lds[K::LDS];
     const int team = threadIdx.x / K::T, tid = threadIdx.x % K::T;
-    const int tile = blockIdx.x, p2 = blockIdx.y;
-    const int i0 = tile * K::WT + team;
-    const bool active = i0 < N0;
-    const C* src = in + ((size_t)(active ? i0 : 0) * H + p2) * N1;
-    C v[F::V];
-    F::load_first(v, tid, active ? N1 : 0, [&](int i) { return src[i]; });
-    F::run(v, lds + team * F::SCR, tid, tw);
-    __syncthreads();
-    F::store_last(v, tid, P, [&](int p1, C c) { lds[p1 * K::TS + team] = c; });
-    __syncthreads();
-    const int col0 = tile * K::WT;
-    for (int e = threadIdx.x; e < P * K::WT; e += K::THREADS) {
-        const int p1 = e / K::WT, w = e % K::WT;
-        if (col0 + w < N0) out[((size_t)p2 * P + p1) * N0 + col0 + w] = lds[p1 * K::TS + w];
+    C* scr = lds + team * F::SCR;
+    C w[F::NTW];
+    F::load_tw(w, tid, tw);
+    const int ntile = cdiv(N0, K::WT);
+    const Chunk ch(ntile * H);
+    C pf[K::NBT0 * K::HALF];
+    auto prefetch = [&](int item) {
+        const int p2 = item / ntile, i0 = (item - p2 * ntile) * K::WT + team;
+        if (i0 < N0) {
+            const C* src = in + ((size_t)i0 * H + p2) * N1;
+#pragma unroll
+            for (int b = 0; b < K::NBT0; ++b)
+#pragma unroll
+                for (int q = 0; q < K::HALF; ++q)
+                    pf[b * K::HALF + q] = src[tid + b * K::T + q * K::NB0];
+        }
+    };
+    if (ch.first < ch.last) prefetch(ch.first);
+    for (int item = ch.first; item < ch.last; ++item) {
+        const int p2 = item / ntile, col0 = (item - p2 * ntile) * K::WT;
+        const bool active = col0 + team < N0;
+        C v[F::V];
+#pragma unroll
+        for (int b = 0; b < K::NBT0; ++b)
+#pragma unroll
+            for (int q = 0; q < K::R0; ++q)
+                v[b * K::R0 + q] = (q < K::HALF && active) ? pf[b * K::HALF + q] : mk(R(0), R(0));
+        if (item + 1 < ch.last) prefetch(item + 1);
+        F::run_r(v, scr, tid, w);
+        sync_wg_lds();
+        F::store_last(v, tid, P, [&](int p1, C c) { lds[p1 * K::TS + team] = c; });
+        sync_wg_lds();
+        for (int e = threadIdx.x; e < P * K::WT; e += K::THREADS) {
+            const int p1 = e / K::WT, ww = e - p1 * K::WT;
+            if (col0 + ww < N0) out[((size_t)p2 * P + p1) * N0 + col0 + ww] = lds[p1 * K::TS + ww];
+        }
+        sync_wg_lds();
     }
 }
 
 // ---------------------------------------------------------------------------
 // Pass D (3D): inverse C2C along axis 1 with crop, transposed in, contiguous out
 //   in[(p2 * P + p1) * N0 + i0] -> out[(i0 * H + p2) * N1 + i1], i1 < N1
+// Persistent; the next item's tile is prefetched into registers.
 // ---------------------------------------------------------------------------
 template <typename R, int P>
 struct InvT {
@@ -223,6 +327,7 @@ struct InvT {
     static constexpr int TS = WT + 1;
     static constexpr int LDS = cmax(WT * F::SCR, P * TS);
     static constexpr int THREADS = WT * T;
+    static constexpr int NT = (P * WT + THREADS - 1) / THREADS;
 };
 
 template <typename R, int P>
@@ -236,22 +341,44 @@ __global__ __launch_bounds__((InvT<R, P>::THREADS)) void k_inv_t(const cpx<R>* _
     constexpr int N1 = P / 2;
     __shared__ C lds[K::LDS];
     const int team = threadIdx.x / K::T, tid = threadIdx.x % K::T;
-    const int tile = blockIdx.x, p2 = blockIdx.y;
-    const int col0 = tile * K::WT;
-    for (int e = threadIdx.x; e < P * K::WT; e += K::THREADS) {
-        const int p1 = e / K::WT, w = e % K::WT;
-        lds[p1 * K::TS + w] =
-            (col0 + w < N0) ? in[((size_t)p2 * P + p1) * N0 + col0 + w] : mk(R(0), R(0));
-    }
-    __syncthreads();
-    C v[F::V];
-    F::load_first(v, tid, P, [&](int p1) { return lds[p1 * K::TS + team]; });
-    __syncthreads();
-    F::run(v, lds + team * F::SCR, tid, tw);
-    const int i0 = col0 + team;
-    if (i0 < N0) {
-        C* dst = out + ((size_t)i0 * H + p2) * N1;
-        F::store_last(v, tid, N1, [&](int i1, C c) { dst[i1] = c; });
+    C* scr = lds + team * F::SCR;
+    C w[F::NTW];
+    F::load_tw(w, tid, tw);
+    const int ntile = cdiv(N0, K::WT);
+    const Chunk ch(ntile * H);
+    C tp[K::NT];
+    auto prefetch = [&](int item) {
+        const int p2 = item / ntile, col0 = (item - p2 * ntile) * K::WT;
+#pragma unroll
+        for (int i = 0; i < K::NT; ++i) {
+            const int e = threadIdx.x + i * K::THREADS;
+            const int p1 = e / K::WT, ww = e - p1 * K::WT;
+            tp[i] = (e < P * K::WT && col0 + ww < N0)
+                        ? in[((size_t)p2 * P + p1) * N0 + col0 + ww]
+                        : mk(R(0), R(0));
+        }
+    };
+    if (ch.first < ch.last) prefetch(ch.first);
+    for (int item = ch.first; item < ch.last; ++item) {
+        const int p2 = item / ntile, col0 = (item - p2 * ntile) * K::WT;
+#pragma unroll
+        for (int i = 0; i < K::NT; ++i) {
+            const int e = threadIdx.x + i * K::THREADS;
+            const int p1 = e / K::WT, ww = e - p1 * K::WT;
+            if (e < P * K::WT) lds[p1 * K::TS + ww] = tp[i];
+        }
+        sync_wg_lds();
+        if (item + 1 < ch.last) prefetch(item + 1);
+        C v[F::V];
+        F::load_first(v, tid, P, [&](int p1) { return lds[p1 * K::TS + team]; });
+        sync_wg_lds();
+        F::run_r(v, scr, tid, w);
+        const int i0 = col0 + team;
+        if (i0 < N0) {
+            C* dst = out + ((size_t)i0 * H + p2) * N1;
+            F::store_last(v, tid, N1, [&](int i1, C c) { dst[i1] = c; });
+        }
+        sync_wg_lds();
     }
 }
 
