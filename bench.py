@@ -21,6 +21,8 @@ import platform
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -211,6 +213,77 @@ def stream_copy(torch, hip, nbytes=1 << 30, reps=10):
     return 2.0 * nbytes / (ms * 1e-3)
 
 
+def bench_batch(F, torch, hip, synth, steps, warmup, count=256):
+    """The batched 2D log workload: `count` seeded densities on grids drawn
+    from {256^2, 512^2, 1024x256, 2048x512, 1024^2}, boxes L_j in U[4,16],
+    FP32 FFT with FP64-built tensors, one captured graph of persistent
+    launches; compared with the same problems issued one fsa_apply at a time."""
+    probs = synth.log2d_batch(count)
+    t0 = time.perf_counter()
+    plans = [F.Plan(p.kernel, p.L, p.N, "f32") for p in probs]
+    stream = torch.cuda.current_stream()
+    e0, e1 = hip.event(), hip.event()
+    hip.record(e0, stream)
+    for pl in plans:
+        pl.build()
+    hip.record(e1, stream)
+    build_ms = hip.ms(e0, e1)
+    rhos = [torch.from_numpy(synth.eval_gaussians(p.gaussians, p.L, p.N, dtype=np.float32)).cuda()
+            for p in probs]
+    outs = [torch.empty_like(r) for r in rhos]
+    ws = torch.empty(F.batch_workspace_bytes(plans) + 256, dtype=torch.uint8, device="cuda")
+    torch.cuda.synchronize()
+    log(f"  batch setup {time.perf_counter() - t0:.1f} s (tensor builds {build_ms:.1f} ms)")
+    t1 = time.perf_counter()
+    F.apply_batched(plans, rhos, outs, ws)  # captures the graph
+    torch.cuda.synchronize()
+    capture_ms = (time.perf_counter() - t1) * 1e3
+    launches = F.batch_launches(plans, rhos, outs, ws)
+    for _ in range(warmup):
+        F.apply_batched(plans, rhos, outs, ws)
+    torch.cuda.synchronize()
+    hip.record(e0, stream)
+    for _ in range(steps):
+        F.apply_batched(plans, rhos, outs, ws)
+    hip.record(e1, stream)
+    batch_ms = hip.ms(e0, e1) / steps
+    # the same problems, one fsa_apply each (3 launches per problem)
+    big = max(pl.workspace_bytes for pl in plans)
+    ws1 = torch.empty(big + 256, dtype=torch.uint8, device="cuda")
+    outs2 = [torch.empty_like(r) for r in rhos]
+    for pl, r, o in zip(plans, rhos, outs2):
+        pl.apply(r, o, ws1)
+    torch.cuda.synchronize()
+    hip.record(e0, stream)
+    for _ in range(steps):
+        for pl, r, o in zip(plans, rhos, outs2):
+            pl.apply(r, o, ws1)
+    hip.record(e1, stream)
+    percall_ms = hip.ms(e0, e1) / steps
+    same = all(torch.equal(a, b) for a, b in zip(outs, outs2))
+    hip.destroy(e0)
+    hip.destroy(e1)
+    pts = sum(p.points for p in probs)
+    mbytes = sum(sum(model_bytes(p.N, "f32").values()) for p in probs)
+    for pl in plans:
+        pl.close()
+    return {
+        "workload": f"{count} 2D log-kernel densities, grids from "
+                    "{256^2, 512^2, 1024x256, 2048x512, 1024^2}, L_j in U[4,16], FP32",
+        "grid_points": pts,
+        "value": pts / (batch_ms * 1e-3),
+        "unit": "grid pts/s",
+        "ms_per_batch": batch_ms,
+        "launches_in_graph": launches,
+        "graph_capture_ms": capture_ms,
+        "model_hbm_frac": mbytes / (batch_ms * 1e-3) / HBM_PEAK_BPS,
+        "per_call_ms": percall_ms,
+        "per_call_value": pts / (percall_ms * 1e-3),
+        "tensor_build_ms_total": build_ms,
+        "bitwise_equal_to_per_call": same,
+    }
+
+
 def cpu_baseline(synth):
     """The FP64 oracle on the host cores: one evaluation of the same Yukawa
     workload at 128^3 (tensor build + FFT convolution)."""
@@ -245,6 +318,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--n", type=int, default=256, help="grid points per axis")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched 2D workload")
     ap.add_argument("--copy-only", action="store_true",
                     help="only run the 1 GiB device copy (counter calibration)")
     args = ap.parse_args()
@@ -279,6 +353,13 @@ def main():
         log(f"  {prec}: {res[prec]['ms_per_step']:.4f} ms/eval, "
             f"{res[prec]['value'] / 1e9:.2f} Gpts/s, passes {res[prec]['pass_ms']}")
     diff = float(np.linalg.norm(phis["f32"] - phis["f64"]) / np.linalg.norm(phis["f64"]))
+    del phis
+    batch = None
+    if not args.no_batch:
+        log("batched 2D log workload (256 densities) ...")
+        batch = bench_batch(F, torch, hip, synth, max(3, args.steps // 2), 2)
+        log(f"  batch: {batch['ms_per_batch']:.3f} ms ({batch['value'] / 1e9:.2f} Gpts/s) in "
+            f"{batch['launches_in_graph']} launches; per-call {batch['per_call_ms']:.3f} ms")
     cpu = None
     if not args.no_cpu:
         log("cpu baseline (oracle) ...")
@@ -315,6 +396,7 @@ def main():
         "precomp_ms": r32["precomp_ms"],
         "wall_ms_per_step": r32["wall_ms_per_step"],
         "f32_vs_f64_rel_l2": diff,
+        "batch": batch,
         "stream_copy_GBps": copy_bps / 1e9,
         "model_copy_frac": r32["model_bytes_per_step"] / (r32["ms_per_step"] * 1e-3) / copy_bps,
         "kernel_source_hash": kernel_source_hash(),

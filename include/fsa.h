@@ -143,10 +143,12 @@ fsa_status fsa_apply_events(fsa_plan plan, const void* rho, void* phi, void* wor
 fsa_status fsa_batch_workspace_bytes(int n, const fsa_plan* plans, size_t* bytes);
 
 /* Evaluates n independent problems (plans may differ in kernel, box, grid
- * and precision) as ONE persistent kernel launch that a hipGraph captures
- * on first use of a batch signature and replays afterwards.  Work items
- * (problem, pass, tile) are taken in dependency order; each problem's result
- * equals fsa_apply on that problem alone.
+ * and precision) as one hipGraph of persistent launches: for each pass, in
+ * dependency order, and each transform length that pass uses, ONE launch
+ * walks the work items (problem, tile or pencil) of every problem that
+ * shares the length.  The graph is captured on first use of a batch
+ * signature and replayed afterwards.  Each problem's result is bitwise
+ * equal to fsa_apply on that problem alone.
  *   plans, rho, phi  host arrays of n entries; rho[i]/phi[i] are device
  *                    pointers for plans[i].
  *   workspace        device scratch of >= fsa_batch_workspace_bytes bytes.
@@ -155,6 +157,12 @@ fsa_status fsa_batch_workspace_bytes(int n, const fsa_plan* plans, size_t* bytes
 fsa_status fsa_apply_batched(int n, const fsa_plan* plans, const void* const* rho,
                              void* const* phi, void* workspace, size_t workspace_bytes,
                              void* stream);
+
+/* Number of persistent launches in the graph captured for this batch
+ * signature (one per pass and transform length); FSA_ESTATE if the batch
+ * has not been run yet.  For tests and tools. */
+fsa_status fsa_batch_launches(int n, const fsa_plan* plans, const void* const* rho,
+                              void* const* phi, void* workspace, int* launches);
 
 /* Releases the plan and its device tensor (after synchronising its device). */
 fsa_status fsa_plan_destroy(fsa_plan plan);

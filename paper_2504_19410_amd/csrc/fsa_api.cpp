@@ -5,6 +5,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <atomic>
 #include <new>
 #include <string>
 
@@ -91,6 +92,8 @@ fsa_status fsa_plan_create(const fsa_kernel* k, int d, const double* L, const in
 
     fsa_plan_s* pl = new (std::nothrow) fsa_plan_s();
     if (!pl) return fail(FSA_ENOMEM, "fsa_plan_create: out of host memory");
+    static std::atomic<uint64_t> next_id{1};
+    pl->id = next_id.fetch_add(1);
     pl->kp = fsa::KernelParams{k->kind, k->kind == FSA_YUKAWA_3D ? k->lambda : 0.0, eps};
     pl->d = d;
     pl->prec = p;
@@ -292,6 +295,7 @@ fsa_status fsa_plan_tensor(fsa_plan pl, const void** tensor, int64_t* dims) {
 
 fsa_status fsa_plan_destroy(fsa_plan pl) {
     if (!pl) return FSA_OK;
+    fsa::batch_forget_plan(pl->id);
     hipError_t e = hipSuccess;
     if (pl->tensor || pl->twiddles) {
         int cur = 0;

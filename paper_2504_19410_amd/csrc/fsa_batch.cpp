@@ -1,5 +1,28 @@
 // fsa_batch.cpp -- batched evaluation of independent problems.
+//
+// A batch of n problems (any mix of kernels, boxes, grid shapes and
+// precisions) runs as a hipGraph of persistent launches: for every pass
+// (A, B, C, D, E, in dependency order) and every transform length used by
+// that pass, ONE launch walks the work items of all problems that share the
+// length, through a device table of per-problem jobs.  Kernel boundaries
+// order the passes, so no cross-workgroup synchronisation (and no multi-XCD
+// L2 write-back/invalidate traffic) is needed inside a launch.  Each item
+// runs exactly the code of the single-problem path, so a batched result is
+// bitwise equal to fsa_apply on that problem alone.
+//
+// The graph (and the device job tables it reads) is built on the first call
+// with a given signature -- plans, device pointers, workspace -- and
+// replayed on later calls.
 #include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <tuple>
+#include <vector>
 
 #include "fsa_internal.hpp"
 
@@ -7,9 +30,196 @@ namespace fsa {
 void set_last_error(const char* msg);
 hipError_t apply_plan(const fsa_plan_s* pl, const void* rho, void* phi, void* ws, hipStream_t st,
                       hipEvent_t const* events);
+}  // namespace fsa
+
+namespace {
+
+size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
+
+struct Group {
+    fsa::Pass pass;
+    int len;
+    fsa_precision prec;
+    const void* tw = nullptr;   // twiddles of length len (any member plan's table)
+    const void* tw2 = nullptr;  // second table of the real transforms (length 2 len)
+    std::vector<unsigned char> jobs;  // packed job structs
+    std::vector<int> start{0};
+    size_t job_size = 0;
+    int n = 0;
+};
+
+struct Entry {
+    std::vector<uint64_t> key;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    void* tables = nullptr;
+    std::vector<uint64_t> plan_ids;
+    int launches = 0;
+    ~Entry() {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+        if (tables) (void)hipFree(tables);
+    }
+};
+
+std::mutex g_mu;
+// most recently used last; deliberately never destroyed, so that no HIP call
+// runs from static destructors after the runtime has shut down
+std::vector<std::unique_ptr<Entry>>& g_cache = *new std::vector<std::unique_ptr<Entry>>();
+constexpr size_t kCacheCap = 16;
+
+template <class Job>
+void add_job(std::map<std::tuple<int, int, int>, Group>& groups, fsa::Pass pass, int len,
+             fsa_precision prec, const void* tw, const void* tw2, const Job& job, int items) {
+    Group& g = groups[std::make_tuple((int)pass, len, (int)prec)];
+    if (g.n == 0) {
+        g.pass = pass;
+        g.len = len;
+        g.prec = prec;
+        g.tw = tw;
+        g.tw2 = tw2;
+        g.job_size = sizeof(Job);
+    }
+    const unsigned char* p = (const unsigned char*)&job;
+    g.jobs.insert(g.jobs.end(), p, p + sizeof(Job));
+    g.start.push_back(g.start.back() + items);
+    ++g.n;
 }
 
-static size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
+template <class Job>
+int items_of(fsa_precision prec, fsa::Pass pass, int len, const Job& job) {
+    return prec == FSA_F32 ? fsa::Launch<float>::items(pass, len, &job)
+                           : fsa::Launch<double>::items(pass, len, &job);
+}
+
+fsa_status build_entry(int n, const fsa_plan* plans, const void* const* rho, void* const* phi,
+                       char* ws, Entry& e) {
+    std::map<std::tuple<int, int, int>, Group> groups;
+    for (int i = 0; i < n; ++i) {
+        const fsa_plan_s* pl = plans[i];
+        const size_t cs = pl->csize;
+        const char* tw = (const char*)pl->twiddles;
+        const void* tw_p0 = tw + pl->tw_off_p0 * cs;
+        const void* tw_p1 = tw + pl->tw_off_p1 * cs;
+        const void* tw_m = tw + pl->tw_off_m * cs;
+        const void* tw_pl = tw + pl->tw_off_pl * cs;
+        const int N0 = (int)pl->N[0], N1 = (int)pl->N[1], H = (int)pl->H;
+        char* w1 = ws;
+        char* w2 = w1 + align256(pl->ws1_elems * cs);
+        ws += align256(pl->ws_bytes);
+        const fsa_precision pr = pl->prec;
+        auto add = [&](auto job, fsa::Pass pass, int len, const void* t1, const void* t2) {
+            const int it = items_of(pr, pass, len, job);
+            if (it < 0) return false;
+            add_job(groups, pass, len, pr, t1, t2, job, it);
+            return true;
+        };
+        bool ok;
+        if (pl->d == 3) {
+            const int N2 = (int)pl->N[2];
+            ok = add(fsa::JobR2c{rho[i], w1, N0, N1}, fsa::Pass::R2C, N2, tw_m, tw_pl) &&
+                 add(fsa::JobT{w1, w2, N0, H}, fsa::Pass::FWD_T, 2 * N1, tw_p1, nullptr) &&
+                 add(fsa::JobConv{w2, pl->tensor, H * 2 * N1, 2 * N1, N1}, fsa::Pass::CONV,
+                     2 * N0, tw_p0, nullptr) &&
+                 add(fsa::JobT{w2, w1, N0, H}, fsa::Pass::INV_T, 2 * N1, tw_p1, nullptr) &&
+                 add(fsa::JobC2r{w1, phi[i], N0, N1}, fsa::Pass::C2R, N2, tw_m, tw_pl);
+        } else {
+            ok = add(fsa::JobR2c{rho[i], w1, 1, N0}, fsa::Pass::R2C, N1, tw_m, tw_pl) &&
+                 add(fsa::JobConv{w1, pl->tensor, H, 1, 0}, fsa::Pass::CONV, 2 * N0, tw_p0,
+                     nullptr) &&
+                 add(fsa::JobC2r{w1, phi[i], 1, N0}, fsa::Pass::C2R, N1, tw_m, tw_pl);
+        }
+        if (!ok) {
+            fsa::set_last_error("fsa_apply_batched: unsupported transform length");
+            return FSA_EUNSUPPORTED;
+        }
+    }
+    // one device buffer: per group [jobs | start], each part 256-byte aligned
+    size_t bytes = 0;
+    std::vector<std::pair<size_t, size_t>> offs;
+    for (auto& kv : groups) {
+        const Group& g = kv.second;
+        const size_t oj = bytes;
+        bytes += align256(g.jobs.size());
+        const size_t os = bytes;
+        bytes += align256(g.start.size() * sizeof(int));
+        offs.emplace_back(oj, os);
+    }
+    std::vector<unsigned char> host(bytes, 0);
+    size_t gi = 0;
+    for (auto& kv : groups) {
+        const Group& g = kv.second;
+        std::memcpy(host.data() + offs[gi].first, g.jobs.data(), g.jobs.size());
+        std::memcpy(host.data() + offs[gi].second, g.start.data(), g.start.size() * sizeof(int));
+        ++gi;
+    }
+    hipError_t err = hipMalloc(&e.tables, bytes > 0 ? bytes : 256);
+    if (err != hipSuccess) {
+        e.tables = nullptr;
+        fsa::set_last_error("fsa_apply_batched: job table allocation failed");
+        return FSA_ENOMEM;
+    }
+    err = hipMemcpy(e.tables, host.data(), bytes, hipMemcpyHostToDevice);
+    if (err != hipSuccess) {
+        fsa::set_last_error(hipGetErrorString(err));
+        return FSA_EDEVICE;
+    }
+    // capture the stage-ordered launches on a private stream
+    hipStream_t cap = nullptr;
+    err = hipStreamCreateWithFlags(&cap, hipStreamNonBlocking);
+    if (err != hipSuccess) {
+        fsa::set_last_error(hipGetErrorString(err));
+        return FSA_EDEVICE;
+    }
+    err = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+    hipError_t lerr = hipSuccess;
+    if (err == hipSuccess) {
+        for (int stage = 0; stage <= (int)fsa::Pass::C2R; ++stage) {
+            gi = 0;
+            for (auto& kv : groups) {
+                const Group& g = kv.second;
+                const size_t oj = offs[gi].first, os = offs[gi].second;
+                ++gi;
+                if ((int)g.pass != stage || lerr != hipSuccess) continue;
+                const char* base = (const char*)e.tables;
+                const int total = g.start.back();
+                lerr = g.prec == FSA_F32
+                           ? fsa::Launch<float>::batch(g.pass, g.len, base + oj,
+                                                       (const int*)(base + os), g.n, total, g.tw,
+                                                       g.tw2, cap)
+                           : fsa::Launch<double>::batch(g.pass, g.len, base + oj,
+                                                        (const int*)(base + os), g.n, total, g.tw,
+                                                        g.tw2, cap);
+                ++e.launches;
+            }
+        }
+        hipError_t cerr = hipStreamEndCapture(cap, &e.graph);
+        if (err == hipSuccess) err = cerr;
+    }
+    if (err == hipSuccess) err = lerr;
+    if (err == hipSuccess) err = hipGraphInstantiate(&e.exec, e.graph, nullptr, nullptr, 0);
+    (void)hipStreamDestroy(cap);
+    if (err != hipSuccess) {
+        fsa::set_last_error(hipGetErrorString(err));
+        return FSA_EDEVICE;
+    }
+    return FSA_OK;
+}
+
+}  // namespace
+
+namespace fsa {
+// Drops cached batch graphs that reference a plan (called when it is destroyed).
+void batch_forget_plan(uint64_t plan_id) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    g_cache.erase(std::remove_if(g_cache.begin(), g_cache.end(),
+                                 [&](const std::unique_ptr<Entry>& e) {
+                                     return std::find(e->plan_ids.begin(), e->plan_ids.end(),
+                                                      plan_id) != e->plan_ids.end();
+                                 }),
+                  g_cache.end());
+}
+}  // namespace fsa
 
 extern "C" {
 
@@ -36,28 +246,90 @@ fsa_status fsa_apply_batched(int n, const fsa_plan* plans, const void* const* rh
     size_t need = 0;
     fsa_status s = fsa_batch_workspace_bytes(n, plans, &need);
     if (s != FSA_OK) return s;
-    if (n > 0 && (!rho || !phi || !workspace)) {
+    if (n == 0) return FSA_OK;
+    if (!rho || !phi || !workspace) {
         fsa::set_last_error("fsa_apply_batched: null array");
+        return FSA_EINVAL;
+    }
+    if (((uintptr_t)workspace & 255) != 0) {
+        fsa::set_last_error("fsa_apply_batched: workspace must be 256-byte aligned");
         return FSA_EINVAL;
     }
     if (workspace_bytes < need) {
         fsa::set_last_error("fsa_apply_batched: workspace too small");
         return FSA_EINVAL;
     }
-    char* ws = (char*)workspace;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) {
+        fsa::set_last_error("fsa_apply_batched: hipGetDevice failed");
+        return FSA_EDEVICE;
+    }
+    std::vector<uint64_t> key;
+    key.reserve(3 * (size_t)n + 3);
+    key.push_back((uint64_t)dev);
+    key.push_back((uint64_t)(uintptr_t)workspace);
+    key.push_back((uint64_t)n);
     for (int i = 0; i < n; ++i) {
-        if (!plans[i]->built) {
-            fsa::set_last_error("fsa_apply_batched: tensor not built");
+        if (!rho[i] || !phi[i]) {
+            fsa::set_last_error("fsa_apply_batched: null device pointer");
+            return FSA_EINVAL;
+        }
+        if (!plans[i]->built || plans[i]->device != dev) {
+            fsa::set_last_error("fsa_apply_batched: a plan is not built on the current device");
             return FSA_ESTATE;
         }
-        hipError_t e = fsa::apply_plan(plans[i], rho[i], phi[i], ws, (hipStream_t)stream, nullptr);
-        if (e != hipSuccess) {
-            fsa::set_last_error(hipGetErrorString(e));
-            return FSA_EDEVICE;
+        key.push_back(plans[i]->id);
+        key.push_back((uint64_t)(uintptr_t)rho[i]);
+        key.push_back((uint64_t)(uintptr_t)phi[i]);
+    }
+    std::lock_guard<std::mutex> lk(g_mu);
+    Entry* hit = nullptr;
+    for (size_t i = 0; i < g_cache.size(); ++i) {
+        if (g_cache[i]->key == key) {
+            std::unique_ptr<Entry> e = std::move(g_cache[i]);
+            g_cache.erase(g_cache.begin() + (long)i);
+            g_cache.push_back(std::move(e));
+            hit = g_cache.back().get();
+            break;
         }
-        ws += align256(plans[i]->ws_bytes);
+    }
+    if (!hit) {
+        auto e = std::make_unique<Entry>();
+        e->key = key;
+        for (int i = 0; i < n; ++i) e->plan_ids.push_back(plans[i]->id);
+        s = build_entry(n, plans, rho, phi, (char*)workspace, *e);
+        if (s != FSA_OK) return s;
+        if (g_cache.size() >= kCacheCap) g_cache.erase(g_cache.begin());
+        g_cache.push_back(std::move(e));
+        hit = g_cache.back().get();
+    }
+    hipError_t err = hipGraphLaunch(hit->exec, (hipStream_t)stream);
+    if (err != hipSuccess) {
+        fsa::set_last_error(hipGetErrorString(err));
+        return FSA_EDEVICE;
     }
     return FSA_OK;
+}
+
+fsa_status fsa_batch_launches(int n, const fsa_plan* plans, const void* const* rho,
+                              void* const* phi, void* workspace, int* launches) {
+    if (!launches) return FSA_EINVAL;
+    std::lock_guard<std::mutex> lk(g_mu);
+    for (auto& e : g_cache) {
+        if ((int)e->key[2] == n && e->key[1] == (uint64_t)(uintptr_t)workspace) {
+            bool same = true;
+            for (int i = 0; i < n && same; ++i)
+                same = e->key[3 + 3 * i] == plans[i]->id &&
+                       e->key[4 + 3 * i] == (uint64_t)(uintptr_t)rho[i] &&
+                       e->key[5 + 3 * i] == (uint64_t)(uintptr_t)phi[i];
+            if (same) {
+                *launches = e->launches;
+                return FSA_OK;
+            }
+        }
+    }
+    fsa::set_last_error("fsa_batch_launches: no captured graph for this batch");
+    return FSA_ESTATE;
 }
 
 }  // extern "C"

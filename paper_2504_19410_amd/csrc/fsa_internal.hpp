@@ -8,6 +8,7 @@
 
 #include "../../include/fsa.h"
 #include "fsa_fft.hpp"
+#include "fsa_jobs.hpp"
 
 namespace fsa {
 
@@ -24,6 +25,9 @@ inline bool grid_length_supported(int64_t n) {
     return n >= 8 && n <= 2048 && (n % 2) == 0 && fft_length_supported(n) &&
            fft_length_supported(2 * n);
 }
+
+// Forget cached batch graphs that use a plan (fsa_batch.cpp).
+void batch_forget_plan(uint64_t plan_id);
 
 // Tensor generation (fsa_tensor.hip).
 hipError_t build_tensor_device(const KernelParams& kp, int d, const double* L, const int64_t* N,
@@ -47,12 +51,19 @@ struct Launch {
                             hipStream_t st);
     static hipError_t conv(int P, void* data, const R* tensor, int n_pencils, int P1, int N1,
                            const void* tw, hipStream_t st);
+    // Work items of one job of `pass` at transform length `len` (-1: unsupported).
+    static int items(Pass pass, int len, const void* job);
+    // One persistent launch of `pass` over n jobs (device table `jobs` of the
+    // pass's job type, device prefix `start` of n + 1 item offsets).
+    static hipError_t batch(Pass pass, int len, const void* jobs, const int* start, int n,
+                            int total, const void* tw, const void* tw2, hipStream_t st);
 };
 
 }  // namespace fsa
 
 // Plan object behind the opaque fsa_plan handle.
 struct fsa_plan_s {
+    uint64_t id = 0;  // unique per plan for the lifetime of the process
     fsa::KernelParams kp{};
     int d = 0;
     double L[3] = {1, 1, 1};

@@ -51,10 +51,12 @@ hipError_t Launch<R>::r2c(int M, const R* rho, void* out, int n_outer, int n_inn
 #define FSA_CASE(m)                                                                              \
     case m: {                                                                                    \
         using K = R2c<R, m>;                                                                     \
-        static const int per_cu = blocks_per_cu(k_r2c<R, m>, K::THREADS);                       \
-        const int grid = persistent_grid(per_cu, ((n_inner + K::WT - 1) / K::WT) * n_outer);    \
-        hipLaunchKernelGGL((k_r2c<R, m>), dim3(grid), dim3(K::THREADS), 0, st, rho, (cpx<R>*)out,     \
-                           n_outer, n_inner, (const cpx<R>*)twM, (const cpx<R>*)tw2M);           \
+        using S = JobOne<JobR2c>;                                                                \
+        static const int per_cu = blocks_per_cu(k_r2c<R, m, S>, K::THREADS);                    \
+        const S src{JobR2c{rho, out, n_outer, n_inner}, cdiv(n_inner, K::WT) * n_outer};         \
+        hipLaunchKernelGGL((k_r2c<R, m, S>), dim3(persistent_grid(per_cu, src.total)),          \
+                           dim3(K::THREADS), 0, st, src, (const cpx<R>*)twM,                     \
+                           (const cpx<R>*)tw2M);                                                 \
         break;                                                                                   \
     }
         FSA_M_LIST(FSA_CASE)
@@ -72,10 +74,12 @@ hipError_t Launch<R>::c2r(int M, const void* in, R* phi, int n_outer, int n_inne
 #define FSA_CASE(m)                                                                              \
     case m: {                                                                                    \
         using K = C2r<R, m>;                                                                     \
-        static const int per_cu = blocks_per_cu(k_c2r<R, m>, K::THREADS);                       \
-        const int grid = persistent_grid(per_cu, ((n_inner + K::WT - 1) / K::WT) * n_outer);    \
-        hipLaunchKernelGGL((k_c2r<R, m>), dim3(grid), dim3(K::THREADS), 0, st, (const cpx<R>*)in, phi, \
-                           n_outer, n_inner, (const cpx<R>*)twM, (const cpx<R>*)tw2M);           \
+        using S = JobOne<JobC2r>;                                                                \
+        static const int per_cu = blocks_per_cu(k_c2r<R, m, S>, K::THREADS);                    \
+        const S src{JobC2r{in, phi, n_outer, n_inner}, cdiv(n_inner, K::WT) * n_outer};          \
+        hipLaunchKernelGGL((k_c2r<R, m, S>), dim3(persistent_grid(per_cu, src.total)),          \
+                           dim3(K::THREADS), 0, st, src, (const cpx<R>*)twM,                     \
+                           (const cpx<R>*)tw2M);                                                 \
         break;                                                                                   \
     }
         FSA_M_LIST(FSA_CASE)
@@ -93,10 +97,11 @@ hipError_t Launch<R>::fwd_t(int P, const void* in, void* out, int N0, int H, con
 #define FSA_CASE(p)                                                                              \
     case p: {                                                                                    \
         using K = FwdT<R, p>;                                                                    \
-        static const int per_cu = blocks_per_cu(k_fwd_t<R, p>, K::THREADS);                     \
-        const int grid = persistent_grid(per_cu, ((N0 + K::WT - 1) / K::WT) * H);               \
-        hipLaunchKernelGGL((k_fwd_t<R, p>), dim3(grid), dim3(K::THREADS), 0, st, (const cpx<R>*)in,    \
-                           (cpx<R>*)out, N0, H, (const cpx<R>*)tw);                              \
+        using S = JobOne<JobT>;                                                                  \
+        static const int per_cu = blocks_per_cu(k_fwd_t<R, p, S>, K::THREADS);                  \
+        const S src{JobT{in, out, N0, H}, cdiv(N0, K::WT) * H};                                  \
+        hipLaunchKernelGGL((k_fwd_t<R, p, S>), dim3(persistent_grid(per_cu, src.total)),        \
+                           dim3(K::THREADS), 0, st, src, (const cpx<R>*)tw);                     \
         break;                                                                                   \
     }
         FSA_P_LIST(FSA_CASE)
@@ -114,10 +119,11 @@ hipError_t Launch<R>::inv_t(int P, const void* in, void* out, int N0, int H, con
 #define FSA_CASE(p)                                                                              \
     case p: {                                                                                    \
         using K = InvT<R, p>;                                                                    \
-        static const int per_cu = blocks_per_cu(k_inv_t<R, p>, K::THREADS);                     \
-        const int grid = persistent_grid(per_cu, ((N0 + K::WT - 1) / K::WT) * H);               \
-        hipLaunchKernelGGL((k_inv_t<R, p>), dim3(grid), dim3(K::THREADS), 0, st, (const cpx<R>*)in,    \
-                           (cpx<R>*)out, N0, H, (const cpx<R>*)tw);                              \
+        using S = JobOne<JobT>;                                                                  \
+        static const int per_cu = blocks_per_cu(k_inv_t<R, p, S>, K::THREADS);                  \
+        const S src{JobT{in, out, N0, H}, cdiv(N0, K::WT) * H};                                  \
+        hipLaunchKernelGGL((k_inv_t<R, p, S>), dim3(persistent_grid(per_cu, src.total)),        \
+                           dim3(K::THREADS), 0, st, src, (const cpx<R>*)tw);                     \
         break;                                                                                   \
     }
         FSA_P_LIST(FSA_CASE)
@@ -135,10 +141,12 @@ hipError_t Launch<R>::conv(int P, void* data, const R* tensor, int n_pencils, in
 #define FSA_CASE(p)                                                                              \
     case p: {                                                                                    \
         using K = Conv<R, p>;                                                                    \
-        static const int per_cu = blocks_per_cu(k_conv<R, p>, K::THREADS);                      \
-        const int grid = persistent_grid(per_cu, (n_pencils + K::TPW - 1) / K::TPW);            \
-        hipLaunchKernelGGL((k_conv<R, p>), dim3(grid), dim3(K::THREADS), 0, st, (cpx<R>*)data,   \
-                           tensor, n_pencils, P1, N1, (const cpx<R>*)tw);                        \
+        using S = JobOne<JobConv>;                                                               \
+        static const int per_cu = blocks_per_cu(k_conv<R, p, S>, K::THREADS);                   \
+        const S src{JobConv{data, tensor, n_pencils, P1, N1}, n_pencils};                        \
+        hipLaunchKernelGGL((k_conv<R, p, S>),                                                    \
+                           dim3(persistent_grid(per_cu, cdiv(n_pencils, K::TPW))),               \
+                           dim3(K::THREADS), 0, st, src, (const cpx<R>*)tw);                     \
         break;                                                                                   \
     }
         FSA_P_LIST(FSA_CASE)
@@ -147,6 +155,134 @@ hipError_t Launch<R>::conv(int P, void* data, const R* tensor, int n_pencils, in
         return hipErrorInvalidValue;
     }
     return hipGetLastError();
+}
+
+template <typename R>
+int Launch<R>::items(Pass pass, int len, const void* job) {
+    switch (pass) {
+    case Pass::R2C: {
+        const JobR2c& j = *(const JobR2c*)job;
+        switch (len) {
+#define FSA_CASE(m) case m: return cdiv(j.n_inner, R2c<R, m>::WT) * j.n_outer;
+            FSA_M_LIST(FSA_CASE)
+#undef FSA_CASE
+        }
+        return -1;
+    }
+    case Pass::C2R: {
+        const JobC2r& j = *(const JobC2r*)job;
+        switch (len) {
+#define FSA_CASE(m) case m: return cdiv(j.n_inner, C2r<R, m>::WT) * j.n_outer;
+            FSA_M_LIST(FSA_CASE)
+#undef FSA_CASE
+        }
+        return -1;
+    }
+    case Pass::FWD_T:
+    case Pass::INV_T: {
+        const JobT& j = *(const JobT*)job;
+        switch (len) {
+#define FSA_CASE(p)                                                                              \
+    case p:                                                                                      \
+        return cdiv(j.N0, pass == Pass::FWD_T ? FwdT<R, p>::WT : InvT<R, p>::WT) * j.H;
+            FSA_P_LIST(FSA_CASE)
+#undef FSA_CASE
+        }
+        return -1;
+    }
+    case Pass::CONV:
+        return fft_length_supported(len) ? ((const JobConv*)job)->n_pencils : -1;
+    }
+    return -1;
+}
+
+template <typename R>
+hipError_t Launch<R>::batch(Pass pass, int len, const void* jobs, const int* start, int n,
+                            int total, const void* tw, const void* tw2, hipStream_t st) {
+    if (total <= 0) return hipSuccess;
+    switch (pass) {
+    case Pass::R2C:
+        switch (len) {
+#define FSA_CASE(m)                                                                              \
+    case m: {                                                                                    \
+        using K = R2c<R, m>;                                                                     \
+        using S = JobList<JobR2c>;                                                               \
+        static const int per_cu = blocks_per_cu(k_r2c<R, m, S>, K::THREADS);                    \
+        const S src{(const JobR2c*)jobs, start, n, total};                                       \
+        hipLaunchKernelGGL((k_r2c<R, m, S>), dim3(persistent_grid(per_cu, total)),              \
+                           dim3(K::THREADS), 0, st, src, (const cpx<R>*)tw, (const cpx<R>*)tw2); \
+        return hipGetLastError();                                                                \
+    }
+            FSA_M_LIST(FSA_CASE)
+#undef FSA_CASE
+        }
+        break;
+    case Pass::C2R:
+        switch (len) {
+#define FSA_CASE(m)                                                                              \
+    case m: {                                                                                    \
+        using K = C2r<R, m>;                                                                     \
+        using S = JobList<JobC2r>;                                                               \
+        static const int per_cu = blocks_per_cu(k_c2r<R, m, S>, K::THREADS);                    \
+        const S src{(const JobC2r*)jobs, start, n, total};                                       \
+        hipLaunchKernelGGL((k_c2r<R, m, S>), dim3(persistent_grid(per_cu, total)),              \
+                           dim3(K::THREADS), 0, st, src, (const cpx<R>*)tw, (const cpx<R>*)tw2); \
+        return hipGetLastError();                                                                \
+    }
+            FSA_M_LIST(FSA_CASE)
+#undef FSA_CASE
+        }
+        break;
+    case Pass::FWD_T:
+        switch (len) {
+#define FSA_CASE(p)                                                                              \
+    case p: {                                                                                    \
+        using K = FwdT<R, p>;                                                                    \
+        using S = JobList<JobT>;                                                                 \
+        static const int per_cu = blocks_per_cu(k_fwd_t<R, p, S>, K::THREADS);                  \
+        const S src{(const JobT*)jobs, start, n, total};                                         \
+        hipLaunchKernelGGL((k_fwd_t<R, p, S>), dim3(persistent_grid(per_cu, total)),            \
+                           dim3(K::THREADS), 0, st, src, (const cpx<R>*)tw);                     \
+        return hipGetLastError();                                                                \
+    }
+            FSA_P_LIST(FSA_CASE)
+#undef FSA_CASE
+        }
+        break;
+    case Pass::INV_T:
+        switch (len) {
+#define FSA_CASE(p)                                                                              \
+    case p: {                                                                                    \
+        using K = InvT<R, p>;                                                                    \
+        using S = JobList<JobT>;                                                                 \
+        static const int per_cu = blocks_per_cu(k_inv_t<R, p, S>, K::THREADS);                  \
+        const S src{(const JobT*)jobs, start, n, total};                                         \
+        hipLaunchKernelGGL((k_inv_t<R, p, S>), dim3(persistent_grid(per_cu, total)),            \
+                           dim3(K::THREADS), 0, st, src, (const cpx<R>*)tw);                     \
+        return hipGetLastError();                                                                \
+    }
+            FSA_P_LIST(FSA_CASE)
+#undef FSA_CASE
+        }
+        break;
+    case Pass::CONV:
+        switch (len) {
+#define FSA_CASE(p)                                                                              \
+    case p: {                                                                                    \
+        using K = Conv<R, p>;                                                                    \
+        using S = JobList<JobConv>;                                                              \
+        static const int per_cu = blocks_per_cu(k_conv<R, p, S>, K::THREADS);                   \
+        const S src{(const JobConv*)jobs, start, n, total};                                      \
+        hipLaunchKernelGGL((k_conv<R, p, S>), dim3(persistent_grid(per_cu, cdiv(total, K::TPW))), \
+                           dim3(K::THREADS), 0, st, src, (const cpx<R>*)tw);                     \
+        return hipGetLastError();                                                                \
+    }
+            FSA_P_LIST(FSA_CASE)
+#undef FSA_CASE
+        }
+        break;
+    }
+    return hipErrorInvalidValue;
 }
 
 }  // namespace fsa

@@ -27,6 +27,7 @@
 #pragma once
 
 #include "fsa_fft.hpp"
+#include "fsa_jobs.hpp"
 
 namespace fsa {
 
@@ -64,6 +65,41 @@ struct Chunk {
 };
 
 // ---------------------------------------------------------------------------
+// Work sources.  A pass kernel walks global work items; a source maps an
+// item to its job (one problem's arrays and extents) and the item's index
+// within that job.  JobOne serves a single evaluation (the job travels in
+// the kernel arguments); JobList serves a batch of problems that share the
+// transform length (device table of jobs plus the prefix of their item
+// counts), so one persistent launch covers the pass for every problem.
+// ---------------------------------------------------------------------------
+template <class Job>
+struct JobOne {
+    Job job;
+    int total;
+    __device__ __forceinline__ Job get(int item, int& local) const {
+        local = item;
+        return job;
+    }
+};
+
+template <class Job>
+struct JobList {
+    const Job* jobs;
+    const int* start;  // start[i] = first item of job i; start[n] = total
+    int n, total;
+    __device__ __forceinline__ Job get(int item, int& local) const {
+        int lo = 0, hi = n - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (start[mid] <= item) lo = mid;
+            else hi = mid - 1;
+        }
+        local = item - start[lo];
+        return jobs[lo];
+    }
+};
+
+// ---------------------------------------------------------------------------
 // Pass A: zero-pad + real-to-complex along the contiguous axis, transposed out
 //   rho rows r = outer * n_inner + inner of M reals (M = N_last), padded to
 //   2M; out[(outer * (M+1) + k) * n_inner + inner] = X[k], k in [0, M].
@@ -86,10 +122,8 @@ struct R2c {
     static_assert(R0 % 2 == 0, "zero half = whole first-stage operands");
 };
 
-template <typename R, int M>
-__global__ __launch_bounds__((R2c<R, M>::THREADS)) void k_r2c(const R* __restrict__ rho,
-                                                            cpx<R>* __restrict__ out, int n_outer,
-                                                            int n_inner,
+template <typename R, int M, class Src>
+__global__ __launch_bounds__((R2c<R, M>::THREADS)) void k_r2c(Src src,
                                                             const cpx<R>* __restrict__ twM,
                                                             const cpx<R>* __restrict__ tw2M) {
     using K = R2c<R, M>;
@@ -106,13 +140,15 @@ __global__ __launch_bounds__((R2c<R, M>::THREADS)) void k_r2c(const R* __restric
         const int k = tid + i * K::T;
         w2[i] = tw2M[k < K::H ? k : 0];
     }
-    const int ntile = cdiv(n_inner, K::WT);
-    const Chunk ch(ntile * n_outer);
+    const Chunk ch(src.total);
     C pf[K::NBT0 * K::HALF];
     auto prefetch = [&](int item) {
-        const int outer = item / ntile, inner = (item - outer * ntile) * K::WT + team;
-        if (inner < n_inner) {
-            const R* row = rho + ((size_t)outer * n_inner + inner) * M;
+        int loc;
+        const JobR2c jb = src.get(item, loc);
+        const int ntile = cdiv(jb.n_inner, K::WT);
+        const int outer = loc / ntile, inner = (loc - outer * ntile) * K::WT + team;
+        if (inner < jb.n_inner) {
+            const R* row = (const R*)jb.rho + ((size_t)outer * jb.n_inner + inner) * M;
 #pragma unroll
             for (int b = 0; b < K::NBT0; ++b)
 #pragma unroll
@@ -123,7 +159,11 @@ __global__ __launch_bounds__((R2c<R, M>::THREADS)) void k_r2c(const R* __restric
     };
     if (ch.first < ch.last) prefetch(ch.first);
     for (int item = ch.first; item < ch.last; ++item) {
-        const int outer = item / ntile, col0 = (item - outer * ntile) * K::WT;
+        int loc;
+        const JobR2c jb = src.get(item, loc);
+        const int n_inner = jb.n_inner;
+        const int ntile = cdiv(n_inner, K::WT);
+        const int outer = loc / ntile, col0 = (loc - outer * ntile) * K::WT;
         const bool active = col0 + team < n_inner;
         C v[F::V];
 #pragma unroll
@@ -154,6 +194,7 @@ __global__ __launch_bounds__((R2c<R, M>::THREADS)) void k_r2c(const R* __restric
             if (k < K::H) lds[k * K::TS + team] = x[i];
         }
         sync_wg_lds();
+        C* out = (C*)jb.out;
         for (int e = threadIdx.x; e < K::H * K::WT; e += K::THREADS) {
             const int k = e / K::WT, ww = e - k * K::WT;
             if (col0 + ww < n_inner)
@@ -182,10 +223,8 @@ struct C2r {
     static constexpr int R0 = F::first_radix(), NB0 = F::first_stride(), NBT0 = F::first_nbt();
 };
 
-template <typename R, int M>
-__global__ __launch_bounds__((C2r<R, M>::THREADS)) void k_c2r(const cpx<R>* __restrict__ in,
-                                                            R* __restrict__ phi, int n_outer,
-                                                            int n_inner,
+template <typename R, int M, class Src>
+__global__ __launch_bounds__((C2r<R, M>::THREADS)) void k_c2r(Src src,
                                                             const cpx<R>* __restrict__ twM,
                                                             const cpx<R>* __restrict__ tw2M) {
     using K = C2r<R, M>;
@@ -198,23 +237,30 @@ __global__ __launch_bounds__((C2r<R, M>::THREADS)) void k_c2r(const cpx<R>* __re
     F::load_tw(w, tid, twM);
     C w2[F::V];  // e^{-i pi k / M} at this thread's first-stage operand indices k
     F::load_first(w2, tid, M, [&](int k) { return tw2M[k]; });
-    const int ntile = cdiv(n_inner, K::WT);
-    const Chunk ch(ntile * n_outer);
+    const Chunk ch(src.total);
     C tp[K::NT];
     auto prefetch = [&](int item) {
-        const int outer = item / ntile, col0 = (item - outer * ntile) * K::WT;
+        int loc;
+        const JobC2r jb = src.get(item, loc);
+        const int ntile = cdiv(jb.n_inner, K::WT);
+        const int outer = loc / ntile, col0 = (loc - outer * ntile) * K::WT;
+        const C* in = (const C*)jb.in;
 #pragma unroll
         for (int i = 0; i < K::NT; ++i) {
             const int e = threadIdx.x + i * K::THREADS;
             const int k = e / K::WT, ww = e - k * K::WT;
-            tp[i] = (e < K::H * K::WT && col0 + ww < n_inner)
-                        ? in[((size_t)outer * K::H + k) * n_inner + col0 + ww]
+            tp[i] = (e < K::H * K::WT && col0 + ww < jb.n_inner)
+                        ? in[((size_t)outer * K::H + k) * jb.n_inner + col0 + ww]
                         : mk(R(0), R(0));
         }
     };
     if (ch.first < ch.last) prefetch(ch.first);
     for (int item = ch.first; item < ch.last; ++item) {
-        const int outer = item / ntile, col0 = (item - outer * ntile) * K::WT;
+        int loc;
+        const JobC2r jb = src.get(item, loc);
+        const int n_inner = jb.n_inner;
+        const int ntile = cdiv(n_inner, K::WT);
+        const int outer = loc / ntile, col0 = (loc - outer * ntile) * K::WT;
 #pragma unroll
         for (int i = 0; i < K::NT; ++i) {
             const int e = threadIdx.x + i * K::THREADS;
@@ -235,7 +281,7 @@ __global__ __launch_bounds__((C2r<R, M>::THREADS)) void k_c2r(const cpx<R>* __re
         F::run_r(v, scr, tid, w);
         const int inner = col0 + team;
         if (inner < n_inner) {
-            R* row = phi + ((size_t)outer * n_inner + inner) * M;
+            R* row = (R*)jb.phi + ((size_t)outer * n_inner + inner) * M;
             F::store_last(v, tid, M / 2,
                           [&](int m, C z) { *reinterpret_cast<C*>(row + 2 * m) = z; });
         }
@@ -262,10 +308,8 @@ struct FwdT {
     static_assert(R0 % 2 == 0, "zero half = whole first-stage operands");
 };
 
-template <typename R, int P>
-__global__ __launch_bounds__((FwdT<R, P>::THREADS)) void k_fwd_t(const cpx<R>* __restrict__ in,
-                                                               cpx<R>* __restrict__ out, int N0,
-                                                               int H,
+template <typename R, int P, class Src>
+__global__ __launch_bounds__((FwdT<R, P>::THREADS)) void k_fwd_t(Src src,
                                                                const cpx<R>* __restrict__ tw) {
     using K = FwdT<R, P>;
     using F = typename K::F;
@@ -276,23 +320,29 @@ __global__ __launch_bounds__((FwdT<R, P>::THREADS)) void k_fwd_t(const cpx<R>* _
     C* scr = lds + team * F::SCR;
     C w[F::NTW];
     F::load_tw(w, tid, tw);
-    const int ntile = cdiv(N0, K::WT);
-    const Chunk ch(ntile * H);
+    const Chunk ch(src.total);
     C pf[K::NBT0 * K::HALF];
     auto prefetch = [&](int item) {
-        const int p2 = item / ntile, i0 = (item - p2 * ntile) * K::WT + team;
-        if (i0 < N0) {
-            const C* src = in + ((size_t)i0 * H + p2) * N1;
+        int loc;
+        const JobT jb = src.get(item, loc);
+        const int ntile = cdiv(jb.N0, K::WT);
+        const int p2 = loc / ntile, i0 = (loc - p2 * ntile) * K::WT + team;
+        if (i0 < jb.N0) {
+            const C* in = (const C*)jb.in + ((size_t)i0 * jb.H + p2) * N1;
 #pragma unroll
             for (int b = 0; b < K::NBT0; ++b)
 #pragma unroll
                 for (int q = 0; q < K::HALF; ++q)
-                    pf[b * K::HALF + q] = src[tid + b * K::T + q * K::NB0];
+                    pf[b * K::HALF + q] = in[tid + b * K::T + q * K::NB0];
         }
     };
     if (ch.first < ch.last) prefetch(ch.first);
     for (int item = ch.first; item < ch.last; ++item) {
-        const int p2 = item / ntile, col0 = (item - p2 * ntile) * K::WT;
+        int loc;
+        const JobT jb = src.get(item, loc);
+        const int N0 = jb.N0;
+        const int ntile = cdiv(N0, K::WT);
+        const int p2 = loc / ntile, col0 = (loc - p2 * ntile) * K::WT;
         const bool active = col0 + team < N0;
         C v[F::V];
 #pragma unroll
@@ -305,6 +355,7 @@ __global__ __launch_bounds__((FwdT<R, P>::THREADS)) void k_fwd_t(const cpx<R>* _
         sync_wg_lds();
         F::store_last(v, tid, P, [&](int p1, C c) { lds[p1 * K::TS + team] = c; });
         sync_wg_lds();
+        C* out = (C*)jb.out;
         for (int e = threadIdx.x; e < P * K::WT; e += K::THREADS) {
             const int p1 = e / K::WT, ww = e - p1 * K::WT;
             if (col0 + ww < N0) out[((size_t)p2 * P + p1) * N0 + col0 + ww] = lds[p1 * K::TS + ww];
@@ -330,10 +381,8 @@ struct InvT {
     static constexpr int NT = (P * WT + THREADS - 1) / THREADS;
 };
 
-template <typename R, int P>
-__global__ __launch_bounds__((InvT<R, P>::THREADS)) void k_inv_t(const cpx<R>* __restrict__ in,
-                                                               cpx<R>* __restrict__ out, int N0,
-                                                               int H,
+template <typename R, int P, class Src>
+__global__ __launch_bounds__((InvT<R, P>::THREADS)) void k_inv_t(Src src,
                                                                const cpx<R>* __restrict__ tw) {
     using K = InvT<R, P>;
     using F = typename K::F;
@@ -344,23 +393,30 @@ __global__ __launch_bounds__((InvT<R, P>::THREADS)) void k_inv_t(const cpx<R>* _
     C* scr = lds + team * F::SCR;
     C w[F::NTW];
     F::load_tw(w, tid, tw);
-    const int ntile = cdiv(N0, K::WT);
-    const Chunk ch(ntile * H);
+    const Chunk ch(src.total);
     C tp[K::NT];
     auto prefetch = [&](int item) {
-        const int p2 = item / ntile, col0 = (item - p2 * ntile) * K::WT;
+        int loc;
+        const JobT jb = src.get(item, loc);
+        const int ntile = cdiv(jb.N0, K::WT);
+        const int p2 = loc / ntile, col0 = (loc - p2 * ntile) * K::WT;
+        const C* in = (const C*)jb.in;
 #pragma unroll
         for (int i = 0; i < K::NT; ++i) {
             const int e = threadIdx.x + i * K::THREADS;
             const int p1 = e / K::WT, ww = e - p1 * K::WT;
-            tp[i] = (e < P * K::WT && col0 + ww < N0)
-                        ? in[((size_t)p2 * P + p1) * N0 + col0 + ww]
+            tp[i] = (e < P * K::WT && col0 + ww < jb.N0)
+                        ? in[((size_t)p2 * P + p1) * jb.N0 + col0 + ww]
                         : mk(R(0), R(0));
         }
     };
     if (ch.first < ch.last) prefetch(ch.first);
     for (int item = ch.first; item < ch.last; ++item) {
-        const int p2 = item / ntile, col0 = (item - p2 * ntile) * K::WT;
+        int loc;
+        const JobT jb = src.get(item, loc);
+        const int N0 = jb.N0;
+        const int ntile = cdiv(N0, K::WT);
+        const int p2 = loc / ntile, col0 = (loc - p2 * ntile) * K::WT;
 #pragma unroll
         for (int i = 0; i < K::NT; ++i) {
             const int e = threadIdx.x + i * K::THREADS;
@@ -375,7 +431,7 @@ __global__ __launch_bounds__((InvT<R, P>::THREADS)) void k_inv_t(const cpx<R>* _
         F::run_r(v, scr, tid, w);
         const int i0 = col0 + team;
         if (i0 < N0) {
-            C* dst = out + ((size_t)i0 * H + p2) * N1;
+            C* dst = (C*)jb.out + ((size_t)i0 * jb.H + p2) * N1;
             F::store_last(v, tid, N1, [&](int i1, C c) { dst[i1] = c; });
         }
         sync_wg_lds();
@@ -423,10 +479,8 @@ __device__ __forceinline__ int conv_item_to_pencil(int t, int P1, int N1) {
     return p2 * P1 + p1;
 }
 
-template <typename R, int P>
-__global__ __launch_bounds__((Conv<R, P>::THREADS)) void k_conv(cpx<R>* __restrict__ data,
-                                                                const R* __restrict__ tensor,
-                                                                int n_pencils, int P1, int N1,
+template <typename R, int P, class Src>
+__global__ __launch_bounds__((Conv<R, P>::THREADS)) void k_conv(Src src,
                                                                 const cpx<R>* __restrict__ tw) {
     using K = Conv<R, P>;
     using Ff = typename K::Ff;
@@ -442,14 +496,18 @@ __global__ __launch_bounds__((Conv<R, P>::THREADS)) void k_conv(cpx<R>* __restri
     C wi[K::SHARED_TW ? 1 : Fi::NTW];
     if constexpr (!K::SHARED_TW) Fi::load_tw(wi, tid, tw);
 
+    const int total = src.total;
     const int slots = gridDim.x * K::TPW;
-    const int chunk = (n_pencils + slots - 1) / slots;
+    const int chunk = (total + slots - 1) / slots;
     const int first = (blockIdx.x * K::TPW + team) * chunk;
 
     C pf[K::NPF];
     auto prefetch = [&](int item) {
-        if (item < n_pencils) {
-            const C* pen = data + (size_t)conv_item_to_pencil(item, P1, N1) * N0;
+        if (item < total) {
+            int loc;
+            const JobConv jb = src.get(item, loc);
+            const C* pen =
+                (const C*)jb.data + (size_t)conv_item_to_pencil(loc, jb.P1, jb.N1) * N0;
 #pragma unroll
             for (int b = 0; b < K::NBT0; ++b)
 #pragma unroll
@@ -459,7 +517,9 @@ __global__ __launch_bounds__((Conv<R, P>::THREADS)) void k_conv(cpx<R>* __restri
     prefetch(first);
     for (int it = 0; it < chunk; ++it) {
         const int item = first + it;
-        const bool active = item < n_pencils;
+        const bool active = item < total;
+        int loc;
+        const JobConv jb = src.get(active ? item : 0, loc);
         C v[Ff::V];
 #pragma unroll
         for (int b = 0; b < K::NBT0; ++b)
@@ -467,10 +527,10 @@ __global__ __launch_bounds__((Conv<R, P>::THREADS)) void k_conv(cpx<R>* __restri
             for (int q = 0; q < K::R0; ++q)
                 v[b * K::R0 + q] = q < K::HALF ? pf[b * K::HALF + q] : mk(R(0), R(0));
         if (it + 1 < chunk) prefetch(item + 1);
-        const int qp = active ? conv_item_to_pencil(item, P1, N1) : 0;
-        const int p2 = qp / P1, p1 = qp - p2 * P1;
-        const int a1 = p1 <= N1 ? p1 : P1 - p1;
-        const R* trow = tensor + ((size_t)p2 * (N1 + 1) + a1) * (N0 + 1);
+        const int qp = conv_item_to_pencil(loc, jb.P1, jb.N1);
+        const int p2 = qp / jb.P1, p1 = qp - p2 * jb.P1;
+        const int a1 = p1 <= jb.N1 ? p1 : jb.P1 - p1;
+        const R* trow = (const R*)jb.tensor + ((size_t)p2 * (jb.N1 + 1) + a1) * (N0 + 1);
         R tv[Ff::V];
         {
             int i = 0;
@@ -484,7 +544,7 @@ __global__ __launch_bounds__((Conv<R, P>::THREADS)) void k_conv(cpx<R>* __restri
         if constexpr (K::SHARED_TW) Fi::run_r(v, scr, tid, wf);
         else Fi::run_r(v, scr, tid, wi);
         if (active) {
-            C* pen = data + (size_t)qp * N0;
+            C* pen = (C*)jb.data + (size_t)qp * N0;
             Fi::store_last(v, tid, N0, [&](int i, C c) { pen[i] = c; });
         }
     }

@@ -38,7 +38,8 @@ STATUS = {
 
 EXPORTS = (
     "fsa_plan_create", "fsa_plan_query", "fsa_build_tensor", "fsa_apply", "fsa_apply_events",
-    "fsa_batch_workspace_bytes", "fsa_apply_batched", "fsa_plan_destroy", "fsa_plan_tensor",
+    "fsa_batch_workspace_bytes", "fsa_apply_batched", "fsa_batch_launches", "fsa_plan_destroy",
+    "fsa_plan_tensor",
     "fsa_server_create", "fsa_server_submit", "fsa_server_poll", "fsa_server_wait",
     "fsa_server_cancel", "fsa_server_stats", "fsa_server_destroy", "fsa_last_error",
 )
@@ -83,6 +84,7 @@ def _load():
         "fsa_apply_events": [P, P, P, P, P, P, I],
         "fsa_batch_workspace_bytes": [I, P, P],
         "fsa_apply_batched": [I, P, P, P, P, S, P],
+        "fsa_batch_launches": [I, P, P, P, P, P],
         "fsa_plan_destroy": [P],
         "fsa_plan_tensor": [P, P, P],
         "fsa_server_create": [S, I, I, ctypes.POINTER(P)],
@@ -297,3 +299,15 @@ def apply_batched(plans: Sequence[Plan], rhos: Sequence[torch.Tensor],
                                   ctypes.c_size_t(workspace.numel() - (base - workspace.data_ptr())),
                                   _stream_ptr(stream)))
     return outs
+
+
+def batch_launches(plans: Sequence[Plan], rhos, outs, workspace: torch.Tensor) -> int:
+    """Persistent launches in the graph captured for this batch (fsa_batch_launches)."""
+    n = len(plans)
+    base = (workspace.data_ptr() + 255) & ~255
+    arr = (ctypes.c_void_p * n)(*[p.handle for p in plans])
+    rp = (ctypes.c_void_p * n)(*[r.data_ptr() for r in rhos])
+    op = (ctypes.c_void_p * n)(*[o.data_ptr() for o in outs])
+    k = ctypes.c_int()
+    _check(_lib.fsa_batch_launches(n, arr, rp, op, ctypes.c_void_p(base), ctypes.byref(k)))
+    return k.value
