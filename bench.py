@@ -319,6 +319,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--n", type=int, default=256, help="grid points per axis")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched 2D workload")
+    ap.add_argument("--batch-only", action="store_true", help="only the batched 2D workload")
     ap.add_argument("--copy-only", action="store_true",
                     help="only run the 1 GiB device copy (counter calibration)")
     args = ap.parse_args()
@@ -340,6 +341,12 @@ def main():
     copy_bps = stream_copy(torch, hip)
     log(f"stream copy (1 GiB): {copy_bps / 1e9:.0f} GB/s")
     if args.copy_only:
+        return
+    if args.batch_only:
+        b = bench_batch(F, torch, hip, synth, max(3, args.steps // 2), 2)
+        log(f"  batch: {b['ms_per_batch']:.3f} ms ({b['value'] / 1e9:.2f} Gpts/s) in "
+            f"{b['launches_in_graph']} launches; per-call {b['per_call_ms']:.3f} ms")
+        print(json.dumps({"batch": b}), flush=True)
         return
     prob = synth.yukawa_problem(1.0, args.n, "f32")
     log(f"density: {len(prob.gaussians)} Gaussians on {prob.N} ...")

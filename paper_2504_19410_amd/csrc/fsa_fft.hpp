@@ -470,6 +470,33 @@ struct Fft {
         }
     }
 
+    template <int s>
+    static __device__ __forceinline__ void run_g_from(C (&v)[V], C* scr, int tid,
+                                                      const C* __restrict__ tw) {
+        if constexpr (s < S) {
+            store<s - 1>(v, scr, tid);
+            sync_lds();
+            load<s>(v, scr, tid);
+            sync_lds();
+            compute<s>(v, tid, tw);
+            run_g_from<s + 1>(v, scr, tid, tw);
+        }
+    }
+
+    // twiddles from the (cached) global table, LDS-only synchronisation
+    static __device__ __forceinline__ void run_g(C (&v)[V], C* scr, int tid,
+                                                 const C* __restrict__ tw) {
+        compute<0>(v, tid, tw);
+        run_g_from<1>(v, scr, tid, tw);
+    }
+
+    // Whether this thread's twiddles fit a register budget of ~56 VGPRs; the
+    // kernels keep them in registers then, and read the table otherwise.
+    static constexpr bool reg_tw(int budget_vgprs) {
+        return NTW * (int)(sizeof(C) / 4) <= budget_vgprs;
+    }
+    static constexpr bool REG_TW = reg_tw(56);
+
     // run() with register twiddles and LDS-only synchronisation
     static __device__ __forceinline__ void run_r(C (&v)[V], C* scr, int tid, const C (&w)[NTW]) {
         compute_r<0>(v, tid, w);

@@ -34,11 +34,14 @@ namespace fsa {
 constexpr int kMaxLds = 160 * 1024;
 
 // Width (pencils) of a transposing tile: 128 bytes of complex values, fewer
-// if the LDS or the 1024-thread limit says so.
-constexpr int tile_width(int csize, int T, int scr, int rows) {
+// if the LDS or the thread budget says so.  The thread budget keeps the
+// per-thread register file large enough for the operands, the register
+// twiddles and the prefetch buffers: a 1024-thread workgroup leaves 128
+// VGPRs per thread, a 512-thread one 256.
+constexpr int tile_width(int csize, int T, int scr, int rows, int max_threads = 1024) {
     int wt = 128 / csize;
-    while (wt > 1 && (wt * T > 1024 || (wt * scr > rows * (wt + 1) ? wt * scr : rows * (wt + 1)) *
-                                               csize > kMaxLds))
+    while (wt > 1 && (wt * T > max_threads ||
+                      (wt * scr > rows * (wt + 1) ? wt * scr : rows * (wt + 1)) * csize > kMaxLds))
         wt /= 2;
     return wt;
 }
@@ -112,7 +115,7 @@ struct R2c {
     using C = cpx<R>;
     static constexpr int T = F::T;
     static constexpr int H = M + 1;
-    static constexpr int WT = tile_width(sizeof(C), T, F::SCR, H);
+    static constexpr int WT = tile_width(sizeof(C), T, F::SCR, H, 512);
     static constexpr int TS = WT + 1;
     static constexpr int LDS = cmax(WT * F::SCR, H * TS);
     static constexpr int THREADS = WT * T;
@@ -132,13 +135,15 @@ __global__ __launch_bounds__((R2c<R, M>::THREADS)) void k_r2c(Src src,
     __shared__ C lds[K::LDS];
     const int team = threadIdx.x / K::T, tid = threadIdx.x % K::T;
     C* scr = lds + team * F::SCR;
-    C w[F::NTW];
-    F::load_tw(w, tid, twM);
-    C w2[K::NX];  // post-processing twiddles e^{-i pi k / M}, k = tid + i T
+    C w[F::REG_TW ? F::NTW : 1];
+    if constexpr (F::REG_TW) F::load_tw(w, tid, twM);
+    C w2[F::REG_TW ? K::NX : 1];  // post-processing twiddles e^{-i pi k / M}, k = tid + i T
+    if constexpr (F::REG_TW) {
 #pragma unroll
-    for (int i = 0; i < K::NX; ++i) {
-        const int k = tid + i * K::T;
-        w2[i] = tw2M[k < K::H ? k : 0];
+        for (int i = 0; i < K::NX; ++i) {
+            const int k = tid + i * K::T;
+            w2[i] = tw2M[k < K::H ? k : 0];
+        }
     }
     const Chunk ch(src.total);
     C pf[K::NBT0 * K::HALF];
@@ -172,7 +177,8 @@ __global__ __launch_bounds__((R2c<R, M>::THREADS)) void k_r2c(Src src,
             for (int q = 0; q < K::R0; ++q)
                 v[b * K::R0 + q] = (q < K::HALF && active) ? pf[b * K::HALF + q] : mk(R(0), R(0));
         if (item + 1 < ch.last) prefetch(item + 1);
-        F::run_r(v, scr, tid, w);
+        if constexpr (F::REG_TW) F::run_r(v, scr, tid, w);
+        else F::run_g(v, scr, tid, twM);
         F::store_last(v, tid, M, [&](int k, C z) { scr[F::pad(k)] = z; });
         F::sync_lds();
         C x[K::NX];
@@ -184,7 +190,10 @@ __global__ __launch_bounds__((R2c<R, M>::THREADS)) void k_r2c(Src src,
                 const C zm = scr[F::pad(k == 0 ? 0 : M - k)];
                 const C a = zk + conj(zm);
                 const C b = rot90<false>(zk - conj(zm));
-                x[i] = scale(a + cmul(w2[i], b), R(0.5));
+                C t;
+                if constexpr (F::REG_TW) t = w2[i];
+                else t = tw2M[k];
+                x[i] = scale(a + cmul(t, b), R(0.5));
             }
         }
         sync_wg_lds();
@@ -215,11 +224,13 @@ struct C2r {
     using C = cpx<R>;
     static constexpr int T = F::T;
     static constexpr int H = M + 1;
-    static constexpr int WT = tile_width(sizeof(C), T, F::SCR, H);
+    static constexpr int WT = tile_width(sizeof(C), T, F::SCR, H, 512);
     static constexpr int TS = WT + 1;
     static constexpr int LDS = cmax(WT * F::SCR, H * TS);
     static constexpr int THREADS = WT * T;
     static constexpr int NT = (H * WT + THREADS - 1) / THREADS;  // tile elements per thread
+    // prefetch the next tile into registers only if it fits ~48 VGPRs
+    static constexpr bool PREFETCH = NT * (int)(sizeof(C) / 4) <= 48;
     static constexpr int R0 = F::first_radix(), NB0 = F::first_stride(), NBT0 = F::first_nbt();
 };
 
@@ -233,52 +244,66 @@ __global__ __launch_bounds__((C2r<R, M>::THREADS)) void k_c2r(Src src,
     __shared__ C lds[K::LDS];
     const int team = threadIdx.x / K::T, tid = threadIdx.x % K::T;
     C* scr = lds + team * F::SCR;
-    C w[F::NTW];
-    F::load_tw(w, tid, twM);
-    C w2[F::V];  // e^{-i pi k / M} at this thread's first-stage operand indices k
-    F::load_first(w2, tid, M, [&](int k) { return tw2M[k]; });
+    C w[F::REG_TW ? F::NTW : 1];
+    if constexpr (F::REG_TW) F::load_tw(w, tid, twM);
+    C w2[F::REG_TW ? F::V : 1];  // e^{-i pi k / M} at this thread's first-stage indices k
+    if constexpr (F::REG_TW) F::load_first(w2, tid, M, [&](int k) { return tw2M[k]; });
     const Chunk ch(src.total);
-    C tp[K::NT];
+    C tp[K::PREFETCH ? K::NT : 1];
+    auto tile_elem = [&](const JobC2r& jb, int outer, int col0, int e) {
+        const int k = e / K::WT, ww = e - k * K::WT;
+        return (e < K::H * K::WT && col0 + ww < jb.n_inner)
+                   ? ((const C*)jb.in)[((size_t)outer * K::H + k) * jb.n_inner + col0 + ww]
+                   : mk(R(0), R(0));
+    };
     auto prefetch = [&](int item) {
         int loc;
         const JobC2r jb = src.get(item, loc);
         const int ntile = cdiv(jb.n_inner, K::WT);
         const int outer = loc / ntile, col0 = (loc - outer * ntile) * K::WT;
-        const C* in = (const C*)jb.in;
 #pragma unroll
-        for (int i = 0; i < K::NT; ++i) {
-            const int e = threadIdx.x + i * K::THREADS;
-            const int k = e / K::WT, ww = e - k * K::WT;
-            tp[i] = (e < K::H * K::WT && col0 + ww < jb.n_inner)
-                        ? in[((size_t)outer * K::H + k) * jb.n_inner + col0 + ww]
-                        : mk(R(0), R(0));
-        }
+        for (int i = 0; i < K::NT; ++i) tp[i] = tile_elem(jb, outer, col0, threadIdx.x + i * K::THREADS);
     };
-    if (ch.first < ch.last) prefetch(ch.first);
+    if constexpr (K::PREFETCH) {
+        if (ch.first < ch.last) prefetch(ch.first);
+    }
     for (int item = ch.first; item < ch.last; ++item) {
         int loc;
         const JobC2r jb = src.get(item, loc);
         const int n_inner = jb.n_inner;
         const int ntile = cdiv(n_inner, K::WT);
         const int outer = loc / ntile, col0 = (loc - outer * ntile) * K::WT;
+        if constexpr (K::PREFETCH) {
 #pragma unroll
-        for (int i = 0; i < K::NT; ++i) {
-            const int e = threadIdx.x + i * K::THREADS;
-            const int k = e / K::WT, ww = e - k * K::WT;
-            if (e < K::H * K::WT) lds[k * K::TS + ww] = tp[i];
+            for (int i = 0; i < K::NT; ++i) {
+                const int e = threadIdx.x + i * K::THREADS;
+                const int k = e / K::WT, ww = e - k * K::WT;
+                if (e < K::H * K::WT) lds[k * K::TS + ww] = tp[i];
+            }
+        } else {
+            for (int e = threadIdx.x; e < K::H * K::WT; e += K::THREADS) {
+                const int k = e / K::WT, ww = e - k * K::WT;
+                lds[k * K::TS + ww] = tile_elem(jb, outer, col0, e);
+            }
         }
         sync_wg_lds();
-        if (item + 1 < ch.last) prefetch(item + 1);
+        if constexpr (K::PREFETCH) {
+            if (item + 1 < ch.last) prefetch(item + 1);
+        }
         C v[F::V];
         F::load_first_at(v, tid, M, [&](int k, int pos) {
             const C xk = lds[k * K::TS + team];
             const C xm = lds[(M - k) * K::TS + team];
             const C a = xk + conj(xm);
-            const C b = cmulc(xk - conj(xm), w2[pos]);
+            C t;
+            if constexpr (F::REG_TW) t = w2[pos];
+            else t = tw2M[k];
+            const C b = cmulc(xk - conj(xm), t);
             return a + rot90<true>(b);
         });
         sync_wg_lds();
-        F::run_r(v, scr, tid, w);
+        if constexpr (F::REG_TW) F::run_r(v, scr, tid, w);
+        else F::run_g(v, scr, tid, twM);
         const int inner = col0 + team;
         if (inner < n_inner) {
             R* row = (R*)jb.phi + ((size_t)outer * n_inner + inner) * M;
@@ -299,7 +324,7 @@ struct FwdT {
     using F = Fft<R, P, false>;
     using C = cpx<R>;
     static constexpr int T = F::T;
-    static constexpr int WT = tile_width(sizeof(C), T, F::SCR, P);
+    static constexpr int WT = tile_width(sizeof(C), T, F::SCR, P, F::V <= 8 ? 1024 : 512);
     static constexpr int TS = WT + 1;
     static constexpr int LDS = cmax(WT * F::SCR, P * TS);
     static constexpr int THREADS = WT * T;
@@ -318,8 +343,8 @@ __global__ __launch_bounds__((FwdT<R, P>::THREADS)) void k_fwd_t(Src src,
     __shared__ C lds[K::LDS];
     const int team = threadIdx.x / K::T, tid = threadIdx.x % K::T;
     C* scr = lds + team * F::SCR;
-    C w[F::NTW];
-    F::load_tw(w, tid, tw);
+    C w[F::REG_TW ? F::NTW : 1];
+    if constexpr (F::REG_TW) F::load_tw(w, tid, tw);
     const Chunk ch(src.total);
     C pf[K::NBT0 * K::HALF];
     auto prefetch = [&](int item) {
@@ -351,7 +376,8 @@ __global__ __launch_bounds__((FwdT<R, P>::THREADS)) void k_fwd_t(Src src,
             for (int q = 0; q < K::R0; ++q)
                 v[b * K::R0 + q] = (q < K::HALF && active) ? pf[b * K::HALF + q] : mk(R(0), R(0));
         if (item + 1 < ch.last) prefetch(item + 1);
-        F::run_r(v, scr, tid, w);
+        if constexpr (F::REG_TW) F::run_r(v, scr, tid, w);
+        else F::run_g(v, scr, tid, tw);
         sync_wg_lds();
         F::store_last(v, tid, P, [&](int p1, C c) { lds[p1 * K::TS + team] = c; });
         sync_wg_lds();
@@ -374,11 +400,12 @@ struct InvT {
     using F = Fft<R, P, true>;
     using C = cpx<R>;
     static constexpr int T = F::T;
-    static constexpr int WT = tile_width(sizeof(C), T, F::SCR, P);
+    static constexpr int WT = tile_width(sizeof(C), T, F::SCR, P, F::V <= 8 ? 1024 : 512);
     static constexpr int TS = WT + 1;
     static constexpr int LDS = cmax(WT * F::SCR, P * TS);
     static constexpr int THREADS = WT * T;
     static constexpr int NT = (P * WT + THREADS - 1) / THREADS;
+    static constexpr bool PREFETCH = NT * (int)(sizeof(C) / 4) <= 48;
 };
 
 template <typename R, int P, class Src>
@@ -391,44 +418,55 @@ __global__ __launch_bounds__((InvT<R, P>::THREADS)) void k_inv_t(Src src,
     __shared__ C lds[K::LDS];
     const int team = threadIdx.x / K::T, tid = threadIdx.x % K::T;
     C* scr = lds + team * F::SCR;
-    C w[F::NTW];
-    F::load_tw(w, tid, tw);
+    C w[F::REG_TW ? F::NTW : 1];
+    if constexpr (F::REG_TW) F::load_tw(w, tid, tw);
     const Chunk ch(src.total);
-    C tp[K::NT];
+    C tp[K::PREFETCH ? K::NT : 1];
+    auto tile_elem = [&](const JobT& jb, int p2, int col0, int e) {
+        const int p1 = e / K::WT, ww = e - p1 * K::WT;
+        return (e < P * K::WT && col0 + ww < jb.N0)
+                   ? ((const C*)jb.in)[((size_t)p2 * P + p1) * jb.N0 + col0 + ww]
+                   : mk(R(0), R(0));
+    };
     auto prefetch = [&](int item) {
         int loc;
         const JobT jb = src.get(item, loc);
         const int ntile = cdiv(jb.N0, K::WT);
         const int p2 = loc / ntile, col0 = (loc - p2 * ntile) * K::WT;
-        const C* in = (const C*)jb.in;
 #pragma unroll
-        for (int i = 0; i < K::NT; ++i) {
-            const int e = threadIdx.x + i * K::THREADS;
-            const int p1 = e / K::WT, ww = e - p1 * K::WT;
-            tp[i] = (e < P * K::WT && col0 + ww < jb.N0)
-                        ? in[((size_t)p2 * P + p1) * jb.N0 + col0 + ww]
-                        : mk(R(0), R(0));
-        }
+        for (int i = 0; i < K::NT; ++i) tp[i] = tile_elem(jb, p2, col0, threadIdx.x + i * K::THREADS);
     };
-    if (ch.first < ch.last) prefetch(ch.first);
+    if constexpr (K::PREFETCH) {
+        if (ch.first < ch.last) prefetch(ch.first);
+    }
     for (int item = ch.first; item < ch.last; ++item) {
         int loc;
         const JobT jb = src.get(item, loc);
         const int N0 = jb.N0;
         const int ntile = cdiv(N0, K::WT);
         const int p2 = loc / ntile, col0 = (loc - p2 * ntile) * K::WT;
+        if constexpr (K::PREFETCH) {
 #pragma unroll
-        for (int i = 0; i < K::NT; ++i) {
-            const int e = threadIdx.x + i * K::THREADS;
-            const int p1 = e / K::WT, ww = e - p1 * K::WT;
-            if (e < P * K::WT) lds[p1 * K::TS + ww] = tp[i];
+            for (int i = 0; i < K::NT; ++i) {
+                const int e = threadIdx.x + i * K::THREADS;
+                const int p1 = e / K::WT, ww = e - p1 * K::WT;
+                if (e < P * K::WT) lds[p1 * K::TS + ww] = tp[i];
+            }
+        } else {
+            for (int e = threadIdx.x; e < P * K::WT; e += K::THREADS) {
+                const int p1 = e / K::WT, ww = e - p1 * K::WT;
+                lds[p1 * K::TS + ww] = tile_elem(jb, p2, col0, e);
+            }
         }
         sync_wg_lds();
-        if (item + 1 < ch.last) prefetch(item + 1);
+        if constexpr (K::PREFETCH) {
+            if (item + 1 < ch.last) prefetch(item + 1);
+        }
         C v[F::V];
         F::load_first(v, tid, P, [&](int p1) { return lds[p1 * K::TS + team]; });
         sync_wg_lds();
-        F::run_r(v, scr, tid, w);
+        if constexpr (F::REG_TW) F::run_r(v, scr, tid, w);
+        else F::run_g(v, scr, tid, tw);
         const int i0 = col0 + team;
         if (i0 < N0) {
             C* dst = (C*)jb.out + ((size_t)i0 * jb.H + p2) * N1;
@@ -491,10 +529,14 @@ __global__ __launch_bounds__((Conv<R, P>::THREADS)) void k_conv(Src src,
     const int team = threadIdx.x / K::T, tid = threadIdx.x % K::T;
     C* scr = lds + team * Ff::SCR;
 
-    C wf[Ff::NTW];
-    Ff::load_tw(wf, tid, tw);
-    C wi[K::SHARED_TW ? 1 : Fi::NTW];
-    if constexpr (!K::SHARED_TW) Fi::load_tw(wi, tid, tw);
+    // register twiddles when they fit (shared by both directions if palindromic)
+    // (the 256-thread conv workgroups can spend up to ~64 VGPRs on them)
+    constexpr bool REG = K::SHARED_TW ? Ff::reg_tw(64)
+                                      : (Ff::NTW + Fi::NTW) * (int)(sizeof(C) / 4) <= 64;
+    C wf[REG ? Ff::NTW : 1];
+    if constexpr (REG) Ff::load_tw(wf, tid, tw);
+    C wi[(REG && !K::SHARED_TW) ? Fi::NTW : 1];
+    if constexpr (REG && !K::SHARED_TW) Fi::load_tw(wi, tid, tw);
 
     const int total = src.total;
     const int slots = gridDim.x * K::TPW;
@@ -536,13 +578,15 @@ __global__ __launch_bounds__((Conv<R, P>::THREADS)) void k_conv(Src src,
             int i = 0;
             Ff::for_each_last(v, tid, [&](int p0, C&) { tv[i++] = trow[p0 <= N0 ? p0 : P - p0]; });
         }
-        Ff::run_r(v, scr, tid, wf);
+        if constexpr (REG) Ff::run_r(v, scr, tid, wf);
+        else Ff::run_g(v, scr, tid, tw);
         {
             int i = 0;
             Ff::for_each_last(v, tid, [&](int, C& c) { c = scale(c, tv[i++]); });
         }
-        if constexpr (K::SHARED_TW) Fi::run_r(v, scr, tid, wf);
-        else Fi::run_r(v, scr, tid, wi);
+        if constexpr (REG && K::SHARED_TW) Fi::run_r(v, scr, tid, wf);
+        else if constexpr (REG) Fi::run_r(v, scr, tid, wi);
+        else Fi::run_g(v, scr, tid, tw);
         if (active) {
             C* pen = (C*)jb.data + (size_t)qp * N0;
             Fi::store_last(v, tid, N0, [&](int i, C c) { pen[i] = c; });
