@@ -1,0 +1,389 @@
+// fsa_sched.hpp -- device-independent core of the convolution server.
+//
+// Continuous batching under an HBM budget: requests queue in arrival order;
+// whenever a slot and enough budget are free, the request at the head is
+// admitted -- its kernel tensor taken from the cache (built on a miss), its
+// workspace reserved -- and launched; it then runs on the device alongside
+// every other admitted request.  Completions release their workspace and
+// slot, which admits the next requests.  Cached tensors that no in-flight
+// request uses are evicted least-recently-used first when the budget is
+// short.  The core knows nothing about HIP: a Backend builds plans, launches
+// requests and reports completions, so the same logic runs on the GPU and,
+// with a scripted backend and clock, in host-only tests.
+#pragma once
+
+#include <algorithm>
+#include <cstddef>
+#include <cstdint>
+#include <deque>
+#include <functional>
+#include <list>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+namespace fsa {
+namespace sched {
+
+enum Status { ST_OK = 0, ST_EINVAL = 1, ST_EUNSUPPORTED = 2, ST_ENOMEM = 3, ST_EDEVICE = 4, ST_ESTATE = 5,
+              ST_EBUDGET = 6, ST_ECANCELLED = 7 };
+
+// Identity of a kernel tensor: everything that determines it.
+struct Key {
+    int kind = 0, d = 0, prec = 0;
+    double lam = 0, eps = 0;
+    double L[3] = {0, 0, 0};
+    int64_t N[3] = {0, 0, 0};
+    bool operator<(const Key& o) const {
+        if (kind != o.kind) return kind < o.kind;
+        if (d != o.d) return d < o.d;
+        if (prec != o.prec) return prec < o.prec;
+        if (lam != o.lam) return lam < o.lam;
+        if (eps != o.eps) return eps < o.eps;
+        for (int j = 0; j < 3; ++j) {
+            if (L[j] != o.L[j]) return L[j] < o.L[j];
+            if (N[j] != o.N[j]) return N[j] < o.N[j];
+        }
+        return false;
+    }
+    int64_t points() const {
+        int64_t p = 1;
+        for (int j = 0; j < d; ++j) p *= N[j];
+        return p;
+    }
+};
+
+// What a backend reports about a plan it created (host-side, no device work).
+struct PlanInfo {
+    void* handle = nullptr;
+    size_t tensor_bytes = 0;     // device bytes the cached tensor occupies
+    size_t workspace_bytes = 0;  // device bytes one evaluation needs
+};
+
+struct Request {
+    uint64_t ticket = 0;
+    Key key;
+    const void* rho = nullptr;
+    void* phi = nullptr;
+    double t_submit = 0, t_admit = 0, t_done = 0;
+    int slot = -1;
+    bool done = false;
+    Status result = ST_OK;
+};
+
+class Backend {
+public:
+    virtual ~Backend() = default;
+    virtual double now() = 0;  // seconds, monotonic
+    // host-side plan creation and sizing; no device work
+    virtual Status create_plan(const Key& k, PlanInfo* out, std::string* err) = 0;
+    // asynchronous tensor generation for a new cache entry
+    virtual Status build_plan(const PlanInfo& p, std::string* err) = 0;
+    virtual void destroy_plan(const PlanInfo& p) = 0;
+    // asynchronous evaluation; the backend must later report its completion
+    // through Scheduler::complete (from a thread that does not hold the
+    // scheduler busy: the server drains a completion queue)
+    virtual Status launch(const Request& r, const PlanInfo& p, int slot, std::string* err) = 0;
+};
+
+struct Stats {
+    double p50_ms = 0, p99_ms = 0, throughput_rps = 0, gpts_per_s = 0;
+    uint64_t done = 0, rejected = 0, cancelled = 0, cache_hits = 0, cache_misses = 0;
+    size_t hbm_in_use = 0, hbm_peak = 0;
+};
+
+class Scheduler {
+public:
+    Scheduler(Backend* be, size_t budget, int max_inflight)
+        : be_(be), budget_(budget), slots_(std::max(1, max_inflight)), t0_(be->now()) {
+        free_slots_.resize(slots_);
+        for (int i = 0; i < slots_; ++i) free_slots_[i] = slots_ - 1 - i;
+    }
+
+    ~Scheduler() {
+        for (auto& kv : cache_) be_->destroy_plan(kv.second.info);
+    }
+
+    // Queues a request.  ST_EBUDGET if it could never fit: its workspace plus
+    // its tensor exceed the whole budget.
+    Status submit(const Key& k, const void* rho, void* phi, uint64_t* ticket, std::string* err) {
+        std::lock_guard<std::mutex> lk(mu_);
+        PlanInfo probe;
+        size_t tensor_bytes, ws_bytes;
+        auto it = cache_.find(k);
+        if (it != cache_.end()) {
+            tensor_bytes = it->second.info.tensor_bytes;
+            ws_bytes = it->second.info.workspace_bytes;
+        } else {
+            Status s = be_->create_plan(k, &probe, err);
+            if (s != ST_OK) return s;
+            tensor_bytes = probe.tensor_bytes;
+            ws_bytes = probe.workspace_bytes;
+            // keep the created (unbuilt) plan for admission
+            Entry e;
+            e.info = probe;
+            e.built = false;
+            cache_.emplace(k, e);
+        }
+        if (tensor_bytes + ws_bytes > budget_) {
+            ++rejected_;
+            if (err) *err = "request exceeds the HBM budget on its own";
+            drop_if_unused_unbuilt(k);
+            return ST_EBUDGET;
+        }
+        Request r;
+        r.ticket = next_ticket_++;
+        r.key = k;
+        r.rho = rho;
+        r.phi = phi;
+        r.t_submit = be_->now();
+        reqs_[r.ticket] = r;
+        queue_.push_back(r.ticket);
+        *ticket = r.ticket;
+        return ST_OK;
+    }
+
+    // Admits and launches as many queued requests as slots and budget allow,
+    // in arrival order (the head of the queue is never overtaken).  Returns
+    // the number launched.
+    int pump() {
+        std::lock_guard<std::mutex> lk(mu_);
+        int launched = 0;
+        while (!queue_.empty() && !free_slots_.empty()) {
+            Request& r = reqs_[queue_.front()];
+            Entry& e = cache_[r.key];
+            const size_t need = e.info.workspace_bytes + (e.built ? 0 : e.info.tensor_bytes);
+            if (in_use_ + need > budget_ && !evict_for(need, r.key)) break;
+            queue_.pop_front();
+            std::string err;
+            if (!e.built) {
+                ++misses_;
+                Status s = be_->build_plan(e.info, &err);
+                if (s != ST_OK) {
+                    finish_locked(r, s);
+                    continue;
+                }
+                e.built = true;
+                in_use_ += e.info.tensor_bytes;
+            } else {
+                ++hits_;
+            }
+            in_use_ += e.info.workspace_bytes;
+            peak_ = std::max(peak_, in_use_);
+            ++e.refs;
+            touch(r.key);
+            r.slot = free_slots_.back();
+            free_slots_.pop_back();
+            r.t_admit = be_->now();
+            ++inflight_;
+            Status s = be_->launch(r, e.info, r.slot, &err);
+            if (s != ST_OK) {
+                release_locked(r);
+                finish_locked(r, s);
+                continue;
+            }
+            ++launched;
+        }
+        return launched;
+    }
+
+    // A launched request's work has finished at time t_done (backend clock).
+    void complete(uint64_t ticket, Status s, double t_done) {
+        std::lock_guard<std::mutex> lk(mu_);
+        auto it = reqs_.find(ticket);
+        if (it == reqs_.end() || it->second.done) return;
+        release_locked(it->second);
+        finish_locked(it->second, s, t_done);
+    }
+
+    Status poll(uint64_t ticket, bool* done, Status* result) {
+        std::lock_guard<std::mutex> lk(mu_);
+        auto it = reqs_.find(ticket);
+        if (it == reqs_.end()) return ST_EINVAL;
+        *done = it->second.done;
+        if (it->second.done && result) *result = it->second.result;
+        return ST_OK;
+    }
+
+    // Cancels a request that is still queued (ST_ESTATE once it has launched).
+    Status cancel(uint64_t ticket) {
+        std::lock_guard<std::mutex> lk(mu_);
+        auto it = reqs_.find(ticket);
+        if (it == reqs_.end()) return ST_EINVAL;
+        auto q = std::find(queue_.begin(), queue_.end(), ticket);
+        if (q == queue_.end()) return ST_ESTATE;
+        queue_.erase(q);
+        ++cancelled_;
+        finish_locked(it->second, ST_ECANCELLED);
+        return ST_OK;
+    }
+
+    // Cancels every queued request (used when the server shuts down).
+    int cancel_all() {
+        std::lock_guard<std::mutex> lk(mu_);
+        int n = 0;
+        while (!queue_.empty()) {
+            Request& r = reqs_[queue_.front()];
+            queue_.pop_front();
+            ++cancelled_;
+            finish_locked(r, ST_ECANCELLED);
+            ++n;
+        }
+        return n;
+    }
+
+    // Forgets a finished request (frees its bookkeeping).
+    void forget(uint64_t ticket) {
+        std::lock_guard<std::mutex> lk(mu_);
+        auto it = reqs_.find(ticket);
+        if (it != reqs_.end() && it->second.done) reqs_.erase(it);
+    }
+
+    Stats stats() {
+        std::lock_guard<std::mutex> lk(mu_);
+        Stats s;
+        std::vector<double> v = lat_ms_;
+        if (!v.empty()) {
+            std::sort(v.begin(), v.end());
+            s.p50_ms = quantile(v, 0.50);
+            s.p99_ms = quantile(v, 0.99);
+        }
+        const double up = std::max(1e-9, last_done_ - t0_);
+        s.done = done_ok_;
+        s.throughput_rps = done_ok_ ? (double)done_ok_ / up : 0.0;
+        s.gpts_per_s = done_ok_ ? (double)points_ / up / 1e9 : 0.0;
+        s.rejected = rejected_;
+        s.cancelled = cancelled_;
+        s.cache_hits = hits_;
+        s.cache_misses = misses_;
+        s.hbm_in_use = in_use_;
+        s.hbm_peak = peak_;
+        return s;
+    }
+
+    bool idle() {
+        std::lock_guard<std::mutex> lk(mu_);
+        return queue_.empty() && inflight_ == 0;
+    }
+    bool has_queued() {
+        std::lock_guard<std::mutex> lk(mu_);
+        return !queue_.empty();
+    }
+    int inflight() {
+        std::lock_guard<std::mutex> lk(mu_);
+        return inflight_;
+    }
+    size_t cached_plans() {
+        std::lock_guard<std::mutex> lk(mu_);
+        size_t n = 0;
+        for (auto& kv : cache_) n += kv.second.built;
+        return n;
+    }
+    // Latency percentile over completed requests: linear interpolation
+    // between order statistics, q in [0, 1].
+    static double quantile(const std::vector<double>& sorted, double q) {
+        if (sorted.empty()) return 0.0;
+        const double pos = q * (double)(sorted.size() - 1);
+        const size_t i = (size_t)pos;
+        const double f = pos - (double)i;
+        return i + 1 < sorted.size() ? sorted[i] * (1 - f) + sorted[i + 1] * f : sorted[i];
+    }
+
+private:
+    struct Entry {
+        PlanInfo info;
+        bool built = false;
+        int refs = 0;
+        uint64_t lru = 0;
+    };
+
+    void touch(const Key& k) { cache_[k].lru = ++lru_clock_; }
+
+    void drop_if_unused_unbuilt(const Key& k) {
+        auto it = cache_.find(k);
+        if (it != cache_.end() && !it->second.built && it->second.refs == 0 &&
+            std::none_of(queue_.begin(), queue_.end(),
+                         [&](uint64_t t) { return !(reqs_[t].key < k) && !(k < reqs_[t].key); })) {
+            be_->destroy_plan(it->second.info);
+            cache_.erase(it);
+        }
+    }
+
+    // Evicts built, unreferenced tensors (least recently used first) until
+    // `need` more bytes fit; never evicts the key about to be used.
+    bool evict_for(size_t need, const Key& keep) {
+        while (in_use_ + need > budget_) {
+            auto victim = cache_.end();
+            for (auto it = cache_.begin(); it != cache_.end(); ++it) {
+                const bool same = !(it->first < keep) && !(keep < it->first);
+                if (!it->second.built || it->second.refs > 0 || same) continue;
+                if (victim == cache_.end() || it->second.lru < victim->second.lru) victim = it;
+            }
+            if (victim == cache_.end()) return false;
+            in_use_ -= victim->second.info.tensor_bytes;
+            be_->destroy_plan(victim->second.info);
+            // an evicted key may be re-created later by submit()
+            const bool queued = std::any_of(queue_.begin(), queue_.end(), [&](uint64_t t) {
+                return !(reqs_[t].key < victim->first) && !(victim->first < reqs_[t].key);
+            });
+            if (queued) {
+                PlanInfo fresh;
+                std::string err;
+                if (be_->create_plan(victim->first, &fresh, &err) == ST_OK) {
+                    victim->second.info = fresh;
+                    victim->second.built = false;
+                    continue;
+                }
+            }
+            cache_.erase(victim);
+        }
+        return true;
+    }
+
+    void release_locked(Request& r) {
+        auto it = cache_.find(r.key);
+        if (it != cache_.end()) {
+            in_use_ -= it->second.info.workspace_bytes;
+            --it->second.refs;
+        }
+        if (r.slot >= 0) {
+            free_slots_.push_back(r.slot);
+            r.slot = -1;
+        }
+        --inflight_;
+    }
+
+    void finish_locked(Request& r, Status s, double t_done = -1.0) {
+        r.done = true;
+        r.result = s;
+        r.t_done = t_done >= 0 ? t_done : be_->now();
+        if (s == ST_OK) {
+            ++done_ok_;
+            points_ += (double)r.key.points();
+            lat_ms_.push_back((r.t_done - r.t_submit) * 1e3);
+            last_done_ = std::max(last_done_, r.t_done);
+        }
+    }
+
+    Backend* be_;
+    size_t budget_;
+    int slots_;
+    double t0_;
+    std::mutex mu_;
+    std::map<Key, Entry> cache_;
+    std::unordered_map<uint64_t, Request> reqs_;
+    std::deque<uint64_t> queue_;
+    std::vector<int> free_slots_;
+    uint64_t next_ticket_ = 1, lru_clock_ = 0;
+    size_t in_use_ = 0, peak_ = 0;
+    int inflight_ = 0;
+    uint64_t done_ok_ = 0, rejected_ = 0, cancelled_ = 0, hits_ = 0, misses_ = 0;
+    double points_ = 0, last_done_ = 0;
+    std::vector<double> lat_ms_;
+};
+
+}  // namespace sched
+}  // namespace fsa

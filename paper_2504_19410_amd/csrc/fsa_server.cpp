@@ -1,37 +1,363 @@
-// fsa_server.cpp -- served variant (continuous batching with HBM-budget
-// admission).  Placeholder entry points until the scheduler lands.
+// fsa_server.cpp -- the served variant: continuous batching of convolution
+// requests on one GPU under an HBM budget (scheduling logic in fsa_sched.hpp).
+//
+// Device side of a request: on its slot's stream the request waits for its
+// cached tensor's build event, takes a stream-ordered workspace
+// (hipMallocAsync), runs the evaluation passes, frees the workspace
+// (hipFreeAsync) and enqueues a host callback that time-stamps the
+// completion.  Requests on different slots run concurrently on the device.
+// A server thread drains completions and admits queued requests.
+#include <hip/hip_runtime.h>
+
+#include <atomic>
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <thread>
+#include <vector>
+
 #include "fsa_internal.hpp"
+#include "fsa_sched.hpp"
 
 namespace fsa {
 void set_last_error(const char* msg);
 }
 
-static fsa_status unsupported(const char* what) {
-    fsa::set_last_error(what);
-    return FSA_EUNSUPPORTED;
+namespace {
+
+using fsa::sched::Key;
+using fsa::sched::PlanInfo;
+using fsa::sched::Request;
+using fsa::sched::Scheduler;
+using Status = fsa::sched::Status;
+
+double steady_now() {
+    return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch())
+        .count();
 }
 
+struct Completion {
+    uint64_t ticket;
+    Status status;
+    double t_done;
+};
+
+class HipBackend : public fsa::sched::Backend {
+public:
+    HipBackend(int device, int n_streams) : device_(device) {
+        for (int i = 0; i < n_streams; ++i) {
+            hipStream_t s = nullptr;
+            if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) == hipSuccess)
+                streams_.push_back(s);
+        }
+        (void)hipStreamCreateWithFlags(&build_stream_, hipStreamNonBlocking);
+    }
+    ~HipBackend() override {
+        for (auto s : streams_) (void)hipStreamDestroy(s);
+        if (build_stream_) (void)hipStreamDestroy(build_stream_);
+    }
+    bool ok() const { return !streams_.empty() && build_stream_ != nullptr; }
+
+    double now() override { return steady_now(); }
+
+    Status create_plan(const Key& k, PlanInfo* out, std::string* err) override {
+        fsa_kernel kk{k.kind, k.lam, k.eps};
+        fsa_plan pl = nullptr;
+        fsa_status s = fsa_plan_create(&kk, k.d, k.L, k.N, (fsa_precision)k.prec, &pl);
+        if (s != FSA_OK) {
+            if (err) *err = fsa_last_error();
+            return (Status)s;
+        }
+        size_t tb = 0, wb = 0;
+        fsa_plan_query(pl, nullptr, nullptr, &tb, &wb);
+        out->handle = pl;
+        out->tensor_bytes = tb + pl->tw_elems * pl->csize;  // tensor + twiddle tables
+        out->workspace_bytes = wb + 256;                      // + alignment slack
+        return fsa::sched::ST_OK;
+    }
+
+    Status build_plan(const PlanInfo& p, std::string* err) override {
+        fsa_plan pl = (fsa_plan)p.handle;
+        fsa_status s = fsa_build_tensor(pl, build_stream_);
+        if (s != FSA_OK) {
+            if (err) *err = fsa_last_error();
+            return (Status)s;
+        }
+        hipEvent_t ev = nullptr;
+        if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess ||
+            hipEventRecord(ev, build_stream_) != hipSuccess) {
+            if (err) *err = "build event";
+            return fsa::sched::ST_EDEVICE;
+        }
+        std::lock_guard<std::mutex> lk(ev_mu_);
+        built_[pl] = ev;
+        return fsa::sched::ST_OK;
+    }
+
+    void destroy_plan(const PlanInfo& p) override {
+        fsa_plan pl = (fsa_plan)p.handle;
+        {
+            std::lock_guard<std::mutex> lk(ev_mu_);
+            auto it = built_.find(pl);
+            if (it != built_.end()) {
+                (void)hipEventSynchronize(it->second);
+                (void)hipEventDestroy(it->second);
+                built_.erase(it);
+            }
+        }
+        fsa_plan_destroy(pl);
+    }
+
+    Status launch(const Request& r, const PlanInfo& p, int slot, std::string* err) override {
+        hipStream_t st = streams_[(size_t)slot % streams_.size()];
+        fsa_plan pl = (fsa_plan)p.handle;
+        hipEvent_t ev = nullptr;
+        {
+            std::lock_guard<std::mutex> lk(ev_mu_);
+            auto it = built_.find(pl);
+            if (it != built_.end()) ev = it->second;
+        }
+        if (ev && hipStreamWaitEvent(st, ev, 0) != hipSuccess) {
+            if (err) *err = "hipStreamWaitEvent failed";
+            return fsa::sched::ST_EDEVICE;
+        }
+        void* raw = nullptr;
+        if (hipMallocAsync(&raw, p.workspace_bytes, st) != hipSuccess) {
+            if (err) *err = "workspace allocation failed";
+            return fsa::sched::ST_ENOMEM;
+        }
+        void* ws = (void*)(((uintptr_t)raw + 255) & ~(uintptr_t)255);
+        fsa_status s = fsa_apply(pl, r.rho, r.phi, ws, st);
+        (void)hipFreeAsync(raw, st);
+        if (s != FSA_OK) {
+            if (err) *err = fsa_last_error();
+            return (Status)s;
+        }
+        auto* ctx = new CallbackCtx{this, r.ticket};
+        if (hipLaunchHostFunc(st, &HipBackend::on_done, ctx) != hipSuccess) {
+            delete ctx;
+            if (err) *err = "hipLaunchHostFunc failed";
+            return fsa::sched::ST_EDEVICE;
+        }
+        return fsa::sched::ST_OK;
+    }
+
+    // completions reported by host callbacks, drained by the server thread
+    std::vector<Completion> take_completions() {
+        std::lock_guard<std::mutex> lk(c_mu_);
+        std::vector<Completion> out;
+        out.swap(done_);
+        return out;
+    }
+    std::mutex c_mu_;
+    std::condition_variable* wake = nullptr;
+
+private:
+    struct CallbackCtx {
+        HipBackend* be;
+        uint64_t ticket;
+    };
+    static void on_done(void* p) {
+        CallbackCtx* c = (CallbackCtx*)p;
+        const double t = steady_now();
+        {
+            std::lock_guard<std::mutex> lk(c->be->c_mu_);
+            c->be->done_.push_back(Completion{c->ticket, fsa::sched::ST_OK, t});
+            if (c->be->wake) c->be->wake->notify_all();
+        }
+        delete c;
+    }
+
+    int device_;
+    std::vector<hipStream_t> streams_;
+    hipStream_t build_stream_ = nullptr;
+    std::mutex ev_mu_;
+    std::map<fsa_plan, hipEvent_t> built_;
+    std::vector<Completion> done_;
+};
+
+}  // namespace
+
+struct fsa_server_s {
+    int device = 0;
+    std::unique_ptr<HipBackend> be;
+    std::unique_ptr<Scheduler> sched;
+    std::thread worker;
+    std::atomic<bool> stop{false};
+    std::condition_variable wake;       // new submissions / completions (with be->c_mu_)
+    std::mutex done_mu;                 // for waiters
+    std::condition_variable done_cv;
+
+    void run() {
+        (void)hipSetDevice(device);
+        for (;;) {
+            std::vector<Completion> done = be->take_completions();
+            for (const Completion& c : done) sched->complete(c.ticket, c.status, c.t_done);
+            if (!done.empty()) {
+                std::lock_guard<std::mutex> lk(done_mu);
+                done_cv.notify_all();
+            }
+            sched->pump();
+            {
+                std::lock_guard<std::mutex> lk(done_mu);
+                done_cv.notify_all();  // requests finished at admission (errors)
+            }
+            if (stop.load() && sched->idle()) break;
+            std::unique_lock<std::mutex> lk(be->c_mu_);
+            wake.wait_for(lk, std::chrono::microseconds(200));
+        }
+    }
+};
+
 extern "C" {
-fsa_status fsa_server_create(size_t, int, int, fsa_server*) {
-    return unsupported("fsa_server_create: not available in this build");
+
+fsa_status fsa_server_create(size_t hbm_budget_bytes, int max_inflight, int n_streams,
+                             fsa_server* out) {
+    if (!out || hbm_budget_bytes == 0 || max_inflight < 1 || n_streams < 1) {
+        fsa::set_last_error("fsa_server_create: bad arguments");
+        return FSA_EINVAL;
+    }
+    auto s = std::make_unique<fsa_server_s>();
+    if (hipGetDevice(&s->device) != hipSuccess) {
+        fsa::set_last_error("fsa_server_create: no device");
+        return FSA_EDEVICE;
+    }
+    s->be = std::make_unique<HipBackend>(s->device, n_streams);
+    if (!s->be->ok()) {
+        fsa::set_last_error("fsa_server_create: stream creation failed");
+        return FSA_EDEVICE;
+    }
+    s->be->wake = &s->wake;
+    s->sched = std::make_unique<Scheduler>(s->be.get(), hbm_budget_bytes, max_inflight);
+    fsa_server_s* raw = s.get();
+    s->worker = std::thread([raw] { raw->run(); });
+    *out = s.release();
+    return FSA_OK;
 }
-fsa_status fsa_server_submit(fsa_server, const fsa_kernel*, int, const double*, const int64_t*,
-                             fsa_precision, const void*, void*, uint64_t*) {
-    return unsupported("fsa_server_submit: not available in this build");
+
+fsa_status fsa_server_submit(fsa_server s, const fsa_kernel* k, int d, const double* L,
+                             const int64_t* N, fsa_precision p, const void* rho, void* phi,
+                             uint64_t* ticket) {
+    if (!s || !k || !L || !N || !rho || !phi || !ticket || d < 2 || d > 3) {
+        fsa::set_last_error("fsa_server_submit: bad arguments");
+        return FSA_EINVAL;
+    }
+    Key key;
+    key.kind = k->kind;
+    key.d = d;
+    key.prec = (int)p;
+    key.lam = k->kind == FSA_YUKAWA_3D ? k->lambda : 0.0;
+    key.eps = k->eps > 0 ? k->eps : 0.0;
+    for (int j = 0; j < d; ++j) {
+        key.L[j] = L[j];
+        key.N[j] = N[j];
+    }
+    std::string err;
+    Status st = s->sched->submit(key, rho, phi, ticket, &err);
+    if (st != fsa::sched::ST_OK) {
+        fsa::set_last_error(err.c_str());
+        return (fsa_status)st;
+    }
+    {
+        std::lock_guard<std::mutex> lk(s->be->c_mu_);
+        s->wake.notify_all();
+    }
+    return FSA_OK;
 }
-fsa_status fsa_server_poll(fsa_server, uint64_t, int*, fsa_status*) {
-    return unsupported("fsa_server_poll: not available in this build");
+
+fsa_status fsa_server_poll(fsa_server s, uint64_t ticket, int* done, fsa_status* result) {
+    if (!s || !done) {
+        fsa::set_last_error("fsa_server_poll: bad arguments");
+        return FSA_EINVAL;
+    }
+    bool d = false;
+    Status r = fsa::sched::ST_OK;
+    if (s->sched->poll(ticket, &d, &r) != fsa::sched::ST_OK) {
+        fsa::set_last_error("fsa_server_poll: unknown ticket");
+        return FSA_EINVAL;
+    }
+    *done = d ? 1 : 0;
+    if (d && result) *result = (fsa_status)r;
+    return FSA_OK;
 }
-fsa_status fsa_server_wait(fsa_server, uint64_t, fsa_status*) {
-    return unsupported("fsa_server_wait: not available in this build");
+
+fsa_status fsa_server_wait(fsa_server s, uint64_t ticket, fsa_status* result) {
+    if (!s) {
+        fsa::set_last_error("fsa_server_wait: bad arguments");
+        return FSA_EINVAL;
+    }
+    for (;;) {
+        bool d = false;
+        Status r = fsa::sched::ST_OK;
+        if (s->sched->poll(ticket, &d, &r) != fsa::sched::ST_OK) {
+            fsa::set_last_error("fsa_server_wait: unknown ticket");
+            return FSA_EINVAL;
+        }
+        if (d) {
+            if (result) *result = (fsa_status)r;
+            return FSA_OK;
+        }
+        std::unique_lock<std::mutex> lk(s->done_mu);
+        s->done_cv.wait_for(lk, std::chrono::microseconds(500));
+    }
 }
-fsa_status fsa_server_cancel(fsa_server, uint64_t) {
-    return unsupported("fsa_server_cancel: not available in this build");
+
+fsa_status fsa_server_cancel(fsa_server s, uint64_t ticket) {
+    if (!s) {
+        fsa::set_last_error("fsa_server_cancel: bad arguments");
+        return FSA_EINVAL;
+    }
+    Status st = s->sched->cancel(ticket);
+    if (st == fsa::sched::ST_ESTATE) {
+        fsa::set_last_error("fsa_server_cancel: request already launched or finished");
+        return FSA_ESTATE;
+    }
+    if (st != fsa::sched::ST_OK) {
+        fsa::set_last_error("fsa_server_cancel: unknown ticket");
+        return FSA_EINVAL;
+    }
+    std::lock_guard<std::mutex> lk(s->done_mu);
+    s->done_cv.notify_all();
+    return FSA_OK;
 }
-fsa_status fsa_server_stats(fsa_server, fsa_stats*) {
-    return unsupported("fsa_server_stats: not available in this build");
+
+fsa_status fsa_server_stats(fsa_server s, fsa_stats* out) {
+    if (!s || !out) {
+        fsa::set_last_error("fsa_server_stats: bad arguments");
+        return FSA_EINVAL;
+    }
+    fsa::sched::Stats st = s->sched->stats();
+    out->p50_ms = st.p50_ms;
+    out->p99_ms = st.p99_ms;
+    out->throughput_rps = st.throughput_rps;
+    out->gpts_per_s = st.gpts_per_s;
+    out->done = st.done;
+    out->rejected = st.rejected;
+    out->cancelled = st.cancelled;
+    out->cache_hits = st.cache_hits;
+    out->cache_misses = st.cache_misses;
+    out->hbm_in_use = st.hbm_in_use;
+    out->hbm_peak = st.hbm_peak;
+    return FSA_OK;
 }
-fsa_status fsa_server_destroy(fsa_server) {
-    return unsupported("fsa_server_destroy: not available in this build");
+
+fsa_status fsa_server_destroy(fsa_server s) {
+    if (!s) return FSA_OK;
+    s->sched->cancel_all();
+    s->stop.store(true);
+    {
+        std::lock_guard<std::mutex> lk(s->be->c_mu_);
+        s->wake.notify_all();
+    }
+    if (s->worker.joinable()) s->worker.join();
+    (void)hipDeviceSynchronize();
+    s->sched.reset();  // destroys cached plans through the backend
+    s->be.reset();
+    delete s;
+    return FSA_OK;
 }
-}
+
+}  // extern "C"

@@ -311,3 +311,68 @@ def batch_launches(plans: Sequence[Plan], rhos, outs, workspace: torch.Tensor) -
     k = ctypes.c_int()
     _check(_lib.fsa_batch_launches(n, arr, rp, op, ctypes.c_void_p(base), ctypes.byref(k)))
     return k.value
+
+
+class Server:
+    """Continuous-batching convolution server on the current device
+    (``fsa_server_*``): requests are admitted as slots and HBM budget free up
+    and run concurrently; kernel tensors are cached per (kernel, box, grid,
+    precision)."""
+
+    def __init__(self, hbm_budget_bytes: int, max_inflight: int = 16, n_streams: int = 4):
+        h = ctypes.c_void_p()
+        _check(_lib.fsa_server_create(ctypes.c_size_t(int(hbm_budget_bytes)), int(max_inflight),
+                                      int(n_streams), ctypes.byref(h)))
+        self._h = h
+
+    def submit(self, kernel: str, L: Sequence[float], N: Sequence[int], rho: torch.Tensor,
+               phi: torch.Tensor, precision: str = "f32", eps: Optional[float] = None,
+               lam: Optional[float] = None) -> int:
+        """Queues phi = U * rho; returns a ticket.  rho and phi must stay alive
+        (and phi untouched) until the ticket completes."""
+        d = len(N)
+        if tuple(rho.shape) != tuple(N) or tuple(phi.shape) != tuple(N):
+            raise ValueError("rho/phi shape must equal N")
+        if rho.dtype != DTYPES[precision] or phi.dtype != DTYPES[precision]:
+            raise ValueError("rho/phi dtype must match the precision")
+        if not (rho.is_cuda and phi.is_cuda and rho.is_contiguous() and phi.is_contiguous()):
+            raise ValueError("rho/phi must be contiguous device tensors")
+        k = _kernel(kernel, eps, lam)
+        Ls = (ctypes.c_double * d)(*[float(x) for x in L])
+        Ns = (ctypes.c_int64 * d)(*[int(n) for n in N])
+        t = ctypes.c_uint64()
+        _check(_lib.fsa_server_submit(self._h, ctypes.byref(k), d, Ls, Ns, PRECISIONS[precision],
+                                      ctypes.c_void_p(rho.data_ptr()),
+                                      ctypes.c_void_p(phi.data_ptr()), ctypes.byref(t)))
+        return t.value
+
+    def poll(self, ticket: int):
+        done = ctypes.c_int()
+        st = ctypes.c_int()
+        _check(_lib.fsa_server_poll(self._h, ctypes.c_uint64(ticket), ctypes.byref(done),
+                                    ctypes.byref(st)))
+        return bool(done.value), (STATUS[st.value] if done.value else None)
+
+    def wait(self, ticket: int) -> str:
+        st = ctypes.c_int()
+        _check(_lib.fsa_server_wait(self._h, ctypes.c_uint64(ticket), ctypes.byref(st)))
+        return STATUS[st.value]
+
+    def cancel(self, ticket: int):
+        _check(_lib.fsa_server_cancel(self._h, ctypes.c_uint64(ticket)))
+
+    def stats(self) -> dict:
+        s = Stats()
+        _check(_lib.fsa_server_stats(self._h, ctypes.byref(s)))
+        return s.as_dict()
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.fsa_server_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,87 @@
+"""The served variant (fsa_server_*) on the GPU.
+
+Requests submitted together run concurrently under the HBM budget; every
+result must be bitwise equal to the same problem evaluated alone with
+fsa_apply.
+"""
+import pytest
+import torch
+
+from paper_2504_19410_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+REQS = [
+    ("coulomb3d", (8.0, 8.0, 8.0), (64, 64, 64), "f32", None),
+    ("yukawa3d", (8.0, 8.0, 8.0), (64, 64, 64), "f32", 0.5),
+    ("yukawa3d", (8.0, 8.0, 8.0), (32, 32, 32), "f64", 4.0),
+    ("coulomb3d", (8.0, 1.0, 1.0), (128, 16, 16), "f32", None),
+    ("coulomb3d", (1.0, 1.0, 8.0), (16, 16, 128), "f32", None),
+    ("coulomb3d", (8.0, 8.0, 8.0), (64, 64, 64), "f32", None),     # cache hit
+    ("log2d", (6.0, 6.0), (128, 64), "f64", None),
+]
+
+
+@pytest.fixture(scope="module")
+def F():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2504_19410_amd import fsa
+    return fsa
+
+
+def density(spec, seed):
+    kind, L, N, prec, lam = spec
+    rng = synth.SplitMix64(seed)
+    gs = synth.draw_gaussians(rng, len(N), 3, [-l / 4 for l in L], [l / 4 for l in L],
+                              [l / 6 for l in L], [l / 3 for l in L], isotropic=False)
+    import paper_2504_19410_amd.fsa as F
+    return torch.from_numpy(synth.eval_gaussians(gs, L, N)).to(F.DTYPES[prec]).cuda()
+
+
+def solo(F, spec, rho):
+    kind, L, N, prec, lam = spec
+    return F.Plan(kind, L, N, prec, lam=lam).build().apply(rho)
+
+
+@pytest.mark.parametrize("budget,inflight", [(8 << 30, 8), (64 << 20, 2)])
+def test_mixed_requests_equal_solo(F, budget, inflight):
+    srv = F.Server(budget, max_inflight=inflight, n_streams=4)
+    rhos = [density(s, 10 + i) for i, s in enumerate(REQS)]
+    outs = [torch.full_like(r, float("nan")) for r in rhos]
+    tickets = [srv.submit(s[0], s[1], s[2], r, o, precision=s[3], lam=s[4])
+               for s, r, o in zip(REQS, rhos, outs)]
+    for t in tickets:
+        assert srv.wait(t) == "FSA_OK"
+    torch.cuda.synchronize()
+    for s, r, o in zip(REQS, rhos, outs):
+        assert torch.equal(o, solo(F, s, r)), s
+    st = srv.stats()
+    assert st["done"] == len(REQS)
+    assert st["cache_hits"] >= 1
+    assert st["hbm_peak"] <= budget
+    assert 0 < st["p50_ms"] <= st["p99_ms"]
+    srv.close()
+
+
+def test_budget_rejection_and_cancel(F):
+    srv = F.Server(64 << 20, max_inflight=1, n_streams=1)
+    big = torch.zeros(256, 256, 256, device="cuda")
+    with pytest.raises(F.FsaError, match="EBUDGET"):
+        srv.submit("coulomb3d", (8.0, 8.0, 8.0), (256, 256, 256), big, big)
+    spec = REQS[0]
+    rho = density(spec, 3)
+    outs = [torch.empty_like(rho) for _ in range(6)]
+    ts = [srv.submit(spec[0], spec[1], spec[2], rho, o) for o in outs]
+    cancelled = 0
+    for t in ts[2:]:
+        try:
+            srv.cancel(t)
+            cancelled += 1
+        except F.FsaError:
+            pass  # already launched
+    res = [srv.wait(t) for t in ts]
+    assert res[0] == "FSA_OK"
+    assert res.count("FSA_ECANCELLED") == cancelled >= 1
+    assert srv.stats()["rejected"] == 1
+    srv.close()
