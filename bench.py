@@ -284,6 +284,122 @@ def bench_batch(F, torch, hip, synth, steps, warmup, count=256):
     }
 
 
+def bench_serve(F, torch, hip, synth, duration=3.0, rate=2000.0, budget=200 << 30,
+                inflight=32, streams=8):
+    """Served workload: seeded Poisson arrivals (mean `rate` req/s) of 3D
+    Coulomb / Yukawa requests on {64^3, 128^3, 256^3, 512x64x64, 64x64x512}
+    grids with 1-8 Gaussian densities, 5% FP64, tensors cached, HBM budget
+    200 GB; latency = completion - submission.  The same arrival stream is
+    also replayed through the plain per-call path (one synchronous
+    fsa_apply at a time), in FP64 and in FP32."""
+    reqs = synth.serve_stream(seed=5000, rate=rate, duration=duration)
+    kinds = {}
+    for _, p in reqs:
+        kinds.setdefault((p.N, p.L, p.precision), p)
+    dens = {}
+    outs = {}
+    for key, p in kinds.items():
+        dt = F.DTYPES[p.precision]
+        dens[key] = torch.from_numpy(synth.eval_gaussians(p.gaussians, p.L, p.N)).to(dt).cuda()
+        pool = inflight + 8 if p.points <= 128 ** 3 else 12
+        outs[key] = [[torch.empty_like(dens[key]), None] for _ in range(pool)]
+    srv = F.Server(budget, max_inflight=inflight, n_streams=streams)
+    # warm the tensor cache: one request per distinct tensor key, untimed
+    seen = set()
+    for _, p in reqs:
+        k = (p.kernel, p.lam, p.N, p.L, p.precision)
+        if k in seen:
+            continue
+        seen.add(k)
+        key = (p.N, p.L, p.precision)
+        t = srv.submit(p.kernel, p.L, p.N, dens[key], outs[key][0][0], precision=p.precision,
+                       lam=p.lam or None)
+        srv.wait(t)
+    srv.reset_stats()
+
+    def take(key):
+        pool = outs[key]
+        while True:
+            for slot in pool:
+                if slot[1] is None or srv.poll(slot[1])[0]:
+                    return slot
+            time.sleep(20e-6)
+
+    t0 = time.perf_counter()
+    tickets = []
+    late = 0
+    for t_arr, p in reqs:
+        while time.perf_counter() - t0 < t_arr:
+            pass
+        if time.perf_counter() - t0 > t_arr + 1e-3:
+            late += 1
+        key = (p.N, p.L, p.precision)
+        slot = take(key)
+        slot[1] = srv.submit(p.kernel, p.L, p.N, dens[key], slot[0], precision=p.precision,
+                             lam=p.lam or None)
+        tickets.append(slot[1])
+    bad = sum(srv.wait(t) != "FSA_OK" for t in tickets)
+    st = srv.stats()
+    srv.close()
+
+    def per_call(prec_override):
+        plans = {}
+        ws = {}
+        lat = []
+        e0, e1 = hip.event(), hip.event()
+        stream = torch.cuda.current_stream()
+        for _, p in reqs:  # build plans and time nothing yet
+            prec = prec_override or p.precision
+            k = (p.kernel, p.lam, p.N, p.L, prec)
+            if k not in plans:
+                plans[k] = F.Plan(p.kernel, p.L, p.N, prec, lam=p.lam or None).build()
+                ws[k] = plans[k].workspace()
+        inputs = {}
+        for key, d in dens.items():
+            for prec in ("f32", "f64"):
+                inputs[(key[0], key[1], prec)] = d.to(F.DTYPES[prec])
+        torch.cuda.synchronize()
+        out_cache = {}
+        t0 = time.perf_counter()
+        for t_arr, p in reqs:
+            while time.perf_counter() - t0 < t_arr:
+                pass
+            prec = prec_override or p.precision
+            k = (p.kernel, p.lam, p.N, p.L, prec)
+            x = inputs[(p.N, p.L, prec)]
+            o = out_cache.setdefault((p.N, p.L, prec), torch.empty_like(x))
+            plans[k].apply(x, o, ws[k])
+            torch.cuda.synchronize()
+            lat.append((time.perf_counter() - t0 - t_arr) * 1e3)
+        span = time.perf_counter() - t0
+        hip.destroy(e0)
+        hip.destroy(e1)
+        for pl in plans.values():
+            pl.close()
+        lat.sort()
+        n = len(lat)
+        return {"p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+                "throughput_rps": n / span, "requests": n}
+
+    fp64 = per_call("f64")
+    fp32 = per_call("f32")
+    pts = sum(p.points for _, p in reqs)
+    return {
+        "workload": f"Poisson arrivals at {rate:.0f} req/s for {duration:.1f} s (seed 5000): "
+                    "3D Coulomb (1/2) / Yukawa lam in {0.5,1,4}; grids 64^3, 128^3, 256^3, "
+                    "512x64x64, 64x64x512; 5% FP64; HBM budget 200 GB",
+        "requests": len(reqs),
+        "grid_points": pts,
+        "server": {"p50_ms": st["p50_ms"], "p99_ms": st["p99_ms"],
+                   "throughput_rps": st["throughput_rps"], "gpts_per_s": st["gpts_per_s"],
+                   "failed": bad, "late_submissions": late, "cache_hits": st["cache_hits"],
+                   "cache_misses": st["cache_misses"], "hbm_peak_GB": st["hbm_peak"] / 1e9,
+                   "max_inflight": inflight, "streams": streams},
+        "per_call_fp64": fp64,
+        "per_call_fp32": fp32,
+    }
+
+
 def cpu_baseline(synth):
     """The FP64 oracle on the host cores: one evaluation of the same Yukawa
     workload at 128^3 (tensor build + FFT convolution)."""
@@ -320,6 +436,9 @@ def main():
     ap.add_argument("--n", type=int, default=256, help="grid points per axis")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched 2D workload")
     ap.add_argument("--batch-only", action="store_true", help="only the batched 2D workload")
+    ap.add_argument("--no-serve", action="store_true", help="skip the served workload")
+    ap.add_argument("--serve-only", action="store_true", help="only the served workload")
+    ap.add_argument("--serve-seconds", type=float, default=3.0)
     ap.add_argument("--copy-only", action="store_true",
                     help="only run the 1 GiB device copy (counter calibration)")
     args = ap.parse_args()
@@ -341,6 +460,11 @@ def main():
     copy_bps = stream_copy(torch, hip)
     log(f"stream copy (1 GiB): {copy_bps / 1e9:.0f} GB/s")
     if args.copy_only:
+        return
+    if args.serve_only:
+        sv = bench_serve(F, torch, hip, synth, duration=args.serve_seconds)
+        log(f"  serve: {json.dumps(sv)}")
+        print(json.dumps({"serve": sv}), flush=True)
         return
     if args.batch_only:
         b = bench_batch(F, torch, hip, synth, max(3, args.steps // 2), 2)
@@ -367,6 +491,13 @@ def main():
         batch = bench_batch(F, torch, hip, synth, max(3, args.steps // 2), 2)
         log(f"  batch: {batch['ms_per_batch']:.3f} ms ({batch['value'] / 1e9:.2f} Gpts/s) in "
             f"{batch['launches_in_graph']} launches; per-call {batch['per_call_ms']:.3f} ms")
+    serve = None
+    if not args.no_serve:
+        log("served workload (Poisson arrivals) ...")
+        serve = bench_serve(F, torch, hip, synth, duration=args.serve_seconds)
+        log(f"  server p50/p99 {serve['server']['p50_ms']:.3f}/{serve['server']['p99_ms']:.3f} ms, "
+            f"per-call FP64 p50/p99 {serve['per_call_fp64']['p50_ms']:.3f}/"
+            f"{serve['per_call_fp64']['p99_ms']:.3f} ms")
     cpu = None
     if not args.no_cpu:
         log("cpu baseline (oracle) ...")
@@ -404,6 +535,7 @@ def main():
         "wall_ms_per_step": r32["wall_ms_per_step"],
         "f32_vs_f64_rel_l2": diff,
         "batch": batch,
+        "serve": serve,
         "stream_copy_GBps": copy_bps / 1e9,
         "model_copy_frac": r32["model_bytes_per_step"] / (r32["ms_per_step"] * 1e-3) / copy_bps,
         "kernel_source_hash": kernel_source_hash(),

@@ -206,6 +206,9 @@ fsa_status fsa_server_wait(fsa_server s, uint64_t ticket, fsa_status* result);
 /* Cancels a request that has not been launched yet (FSA_ESTATE otherwise). */
 fsa_status fsa_server_cancel(fsa_server s, uint64_t ticket);
 fsa_status fsa_server_stats(fsa_server s, fsa_stats* out);
+/* Starts a new statistics window: clears latency samples, counters and the
+ * HBM peak; cached tensors and queued or in-flight requests are kept. */
+fsa_status fsa_server_reset_stats(fsa_server s);
 /* Waits for in-flight work, then frees the cache and the server. */
 fsa_status fsa_server_destroy(fsa_server s);
 

@@ -235,6 +235,18 @@ public:
         return n;
     }
 
+    // Starts a new statistics window (latencies, counters, peak); the cache
+    // and any queued or in-flight work are kept.
+    void reset_stats() {
+        std::lock_guard<std::mutex> lk(mu_);
+        lat_ms_.clear();
+        done_ok_ = rejected_ = cancelled_ = hits_ = misses_ = 0;
+        points_ = 0;
+        t0_ = be_->now();
+        last_done_ = t0_;
+        peak_ = in_use_;
+    }
+
     // Forgets a finished request (frees its bookkeeping).
     void forget(uint64_t ticket) {
         std::lock_guard<std::mutex> lk(mu_);

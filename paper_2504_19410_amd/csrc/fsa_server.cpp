@@ -2,11 +2,12 @@
 // requests on one GPU under an HBM budget (scheduling logic in fsa_sched.hpp).
 //
 // Device side of a request: on its slot's stream the request waits for its
-// cached tensor's build event, takes a stream-ordered workspace
-// (hipMallocAsync), runs the evaluation passes, frees the workspace
-// (hipFreeAsync) and enqueues a host callback that time-stamps the
-// completion.  Requests on different slots run concurrently on the device.
-// A server thread drains completions and admits queued requests.
+// cached tensor's build event, runs the evaluation passes in the slot's
+// resident workspace and records a completion event.  A slot's workspace is
+// sized to the largest request it has run (grown, rarely, between requests,
+// when the slot is idle), so the steady state allocates nothing.  Requests on different slots run concurrently on the device.  A
+// server thread polls the in-flight events (time-stamping completions as it
+// sees them) and admits queued requests.
 #include <hip/hip_runtime.h>
 
 #include <atomic>
@@ -56,6 +57,9 @@ public:
         (void)hipStreamCreateWithFlags(&build_stream_, hipStreamNonBlocking);
     }
     ~HipBackend() override {
+        for (auto w : slot_ws_)
+            if (w) (void)hipFree(w);
+        for (auto e : all_events_) (void)hipEventDestroy(e);
         for (auto s : streams_) (void)hipStreamDestroy(s);
         if (build_stream_) (void)hipStreamDestroy(build_stream_);
     }
@@ -124,59 +128,95 @@ public:
             if (err) *err = "hipStreamWaitEvent failed";
             return fsa::sched::ST_EDEVICE;
         }
-        void* raw = nullptr;
-        if (hipMallocAsync(&raw, p.workspace_bytes, st) != hipSuccess) {
-            if (err) *err = "workspace allocation failed";
-            return fsa::sched::ST_ENOMEM;
+        if ((size_t)slot >= slot_ws_.size()) {
+            slot_ws_.resize(slot + 1, nullptr);
+            slot_bytes_.resize(slot + 1, 0);
         }
-        void* ws = (void*)(((uintptr_t)raw + 255) & ~(uintptr_t)255);
+        if (slot_bytes_[slot] < p.workspace_bytes) {
+            // the slot is idle (its previous request completed), so the old
+            // buffer can go; this happens once per slot and size class
+            if (slot_ws_[slot]) (void)hipFree(slot_ws_[slot]);
+            slot_ws_[slot] = nullptr;
+            slot_bytes_[slot] = 0;
+            if (hipMalloc(&slot_ws_[slot], p.workspace_bytes) != hipSuccess) {
+                slot_ws_[slot] = nullptr;
+                if (err) *err = "workspace allocation failed";
+                return fsa::sched::ST_ENOMEM;
+            }
+            slot_bytes_[slot] = p.workspace_bytes;
+        }
+        void* ws = (void*)(((uintptr_t)slot_ws_[slot] + 255) & ~(uintptr_t)255);
         fsa_status s = fsa_apply(pl, r.rho, r.phi, ws, st);
-        (void)hipFreeAsync(raw, st);
         if (s != FSA_OK) {
             if (err) *err = fsa_last_error();
             return (Status)s;
         }
-        auto* ctx = new CallbackCtx{this, r.ticket};
-        if (hipLaunchHostFunc(st, &HipBackend::on_done, ctx) != hipSuccess) {
-            delete ctx;
-            if (err) *err = "hipLaunchHostFunc failed";
+        hipEvent_t done = take_event();
+        if (!done || hipEventRecord(done, st) != hipSuccess) {
+            if (err) *err = "completion event";
             return fsa::sched::ST_EDEVICE;
         }
+        std::lock_guard<std::mutex> lk(c_mu_);
+        inflight_.push_back(Inflight{r.ticket, done});
         return fsa::sched::ST_OK;
     }
 
-    // completions reported by host callbacks, drained by the server thread
+    // Completed requests, in the order the server thread observed them.
     std::vector<Completion> take_completions() {
-        std::lock_guard<std::mutex> lk(c_mu_);
         std::vector<Completion> out;
-        out.swap(done_);
+        std::lock_guard<std::mutex> lk(c_mu_);
+        for (size_t i = 0; i < inflight_.size();) {
+            const hipError_t q = hipEventQuery(inflight_[i].ev);
+            if (q == hipErrorNotReady) {
+                ++i;
+                continue;
+            }
+            out.push_back(Completion{inflight_[i].ticket,
+                                     q == hipSuccess ? fsa::sched::ST_OK : fsa::sched::ST_EDEVICE,
+                                     steady_now()});
+            free_events_.push_back(inflight_[i].ev);
+            inflight_[i] = inflight_.back();
+            inflight_.pop_back();
+        }
         return out;
+    }
+    bool any_inflight() {
+        std::lock_guard<std::mutex> lk(c_mu_);
+        return !inflight_.empty();
     }
     std::mutex c_mu_;
     std::condition_variable* wake = nullptr;
 
 private:
-    struct CallbackCtx {
-        HipBackend* be;
+    struct Inflight {
         uint64_t ticket;
+        hipEvent_t ev;
     };
-    static void on_done(void* p) {
-        CallbackCtx* c = (CallbackCtx*)p;
-        const double t = steady_now();
+    hipEvent_t take_event() {
         {
-            std::lock_guard<std::mutex> lk(c->be->c_mu_);
-            c->be->done_.push_back(Completion{c->ticket, fsa::sched::ST_OK, t});
-            if (c->be->wake) c->be->wake->notify_all();
+            std::lock_guard<std::mutex> lk(c_mu_);
+            if (!free_events_.empty()) {
+                hipEvent_t e = free_events_.back();
+                free_events_.pop_back();
+                return e;
+            }
         }
-        delete c;
+        hipEvent_t e = nullptr;
+        if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) return nullptr;
+        std::lock_guard<std::mutex> lk(c_mu_);
+        all_events_.push_back(e);
+        return e;
     }
 
+    std::vector<Inflight> inflight_;
+    std::vector<void*> slot_ws_;  // resident workspace per slot
+    std::vector<size_t> slot_bytes_;
+    std::vector<hipEvent_t> free_events_, all_events_;
     int device_;
     std::vector<hipStream_t> streams_;
     hipStream_t build_stream_ = nullptr;
     std::mutex ev_mu_;
     std::map<fsa_plan, hipEvent_t> built_;
-    std::vector<Completion> done_;
 };
 
 }  // namespace
@@ -206,8 +246,13 @@ struct fsa_server_s {
                 done_cv.notify_all();  // requests finished at admission (errors)
             }
             if (stop.load() && sched->idle()) break;
+            if (be->any_inflight()) {
+                // completions are observed by polling: stay responsive
+                std::this_thread::sleep_for(std::chrono::microseconds(10));
+                continue;
+            }
             std::unique_lock<std::mutex> lk(be->c_mu_);
-            wake.wait_for(lk, std::chrono::microseconds(200));
+            wake.wait_for(lk, std::chrono::microseconds(500));
         }
     }
 };
@@ -341,6 +386,15 @@ fsa_status fsa_server_stats(fsa_server s, fsa_stats* out) {
     out->cache_misses = st.cache_misses;
     out->hbm_in_use = st.hbm_in_use;
     out->hbm_peak = st.hbm_peak;
+    return FSA_OK;
+}
+
+fsa_status fsa_server_reset_stats(fsa_server s) {
+    if (!s) {
+        fsa::set_last_error("fsa_server_reset_stats: bad arguments");
+        return FSA_EINVAL;
+    }
+    s->sched->reset_stats();
     return FSA_OK;
 }
 

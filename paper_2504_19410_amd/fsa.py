@@ -41,7 +41,8 @@ EXPORTS = (
     "fsa_batch_workspace_bytes", "fsa_apply_batched", "fsa_batch_launches", "fsa_plan_destroy",
     "fsa_plan_tensor",
     "fsa_server_create", "fsa_server_submit", "fsa_server_poll", "fsa_server_wait",
-    "fsa_server_cancel", "fsa_server_stats", "fsa_server_destroy", "fsa_last_error",
+    "fsa_server_cancel", "fsa_server_stats", "fsa_server_reset_stats", "fsa_server_destroy",
+    "fsa_last_error",
 )
 
 
@@ -93,6 +94,7 @@ def _load():
         "fsa_server_wait": [P, ctypes.c_uint64, P],
         "fsa_server_cancel": [P, ctypes.c_uint64],
         "fsa_server_stats": [P, ctypes.POINTER(Stats)],
+        "fsa_server_reset_stats": [P],
         "fsa_server_destroy": [P],
     }
     for name, args in sigs.items():
@@ -365,6 +367,9 @@ class Server:
         s = Stats()
         _check(_lib.fsa_server_stats(self._h, ctypes.byref(s)))
         return s.as_dict()
+
+    def reset_stats(self):
+        _check(_lib.fsa_server_reset_stats(self._h))
 
     def close(self):
         if getattr(self, "_h", None):
