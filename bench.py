@@ -285,7 +285,7 @@ def bench_batch(F, torch, hip, synth, steps, warmup, count=256):
 
 
 def bench_serve(F, torch, hip, synth, duration=3.0, rate=2000.0, budget=200 << 30,
-                inflight=32, streams=8):
+                inflight=32, streams=8, per_call=True):
     """Served workload: seeded Poisson arrivals (mean `rate` req/s) of 3D
     Coulomb / Yukawa requests on {64^3, 128^3, 256^3, 512x64x64, 64x64x512}
     grids with 1-8 Gaussian densities, 5% FP64, tensors cached, HBM budget
@@ -342,6 +342,8 @@ def bench_serve(F, torch, hip, synth, duration=3.0, rate=2000.0, budget=200 << 3
     st = srv.stats()
     srv.close()
 
+    per_call_ok = per_call
+
     def per_call(prec_override):
         plans = {}
         ws = {}
@@ -381,8 +383,8 @@ def bench_serve(F, torch, hip, synth, duration=3.0, rate=2000.0, budget=200 << 3
         return {"p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
                 "throughput_rps": n / span, "requests": n}
 
-    fp64 = per_call("f64")
-    fp32 = per_call("f32")
+    fp64 = per_call("f64") if per_call_ok else None
+    fp32 = per_call("f32") if per_call_ok else None
     pts = sum(p.points for _, p in reqs)
     return {
         "workload": f"Poisson arrivals at {rate:.0f} req/s for {duration:.1f} s (seed 5000): "
@@ -464,7 +466,9 @@ def main():
     if args.serve_only:
         sv = bench_serve(F, torch, hip, synth, duration=args.serve_seconds)
         log(f"  serve: {json.dumps(sv)}")
-        print(json.dumps({"serve": sv}), flush=True)
+        burst = bench_serve(F, torch, hip, synth, duration=1.0, rate=6000.0)
+        log(f"  burst: {json.dumps(burst)}")
+        print(json.dumps({"serve": sv, "serve_burst": burst}), flush=True)
         return
     if args.batch_only:
         b = bench_batch(F, torch, hip, synth, max(3, args.steps // 2), 2)

@@ -247,8 +247,10 @@ struct fsa_server_s {
             }
             if (stop.load() && sched->idle()) break;
             if (be->any_inflight()) {
-                // completions are observed by polling: stay responsive
-                std::this_thread::sleep_for(std::chrono::microseconds(10));
+                // completions are observed by polling: spin (yielding) while
+                // work is in flight; a timed sleep would add the kernel's
+                // timer slack (tens of microseconds) to every latency
+                std::this_thread::yield();
                 continue;
             }
             std::unique_lock<std::mutex> lk(be->c_mu_);
