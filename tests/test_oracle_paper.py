@@ -173,14 +173,36 @@ def test_case2_shifted_coulomb3d():
     assert R.rel_max_err(phi, ex) <= 1e-13
 
 
-def test_eps_independence():
+@pytest.mark.parametrize("kind,lam", [("coulomb3d", 0.0), ("yukawa3d", 0.7), ("biharmonic3d", 0.0),
+                                      ("log2d", 0.0), ("coulomb2d", 0.0), ("biharmonic2d", 0.0)])
+def test_eps_independence(kind, lam):
     """Theorem 1: once eps meets condition (b) of eq. ApproxProp and the grid
-    resolves U^eps, the result does not depend on eps."""
-    L, N = [8.0] * 3, [48] * 3
-    r, rho = iso_setup(3, 8.0, 48, 2.0)
-    a = O.solve("coulomb3d", L, N, rho, eps=16.0 / 8.0)
-    b = O.solve("coulomb3d", L, N, rho, eps=16.0 / 6.0)
+    resolves U^eps, the result does not depend on eps.  U^eps enters through
+    T(1) and W through T(2), so a slip in either (a dropped term, a wrong
+    sign or scale) leaves an eps-dependent residue: this pins the pair for
+    every kernel, including those with no printed error table."""
+    d = O.KIND_DIM[kind]
+    n = 48 if d == 3 else 64
+    L, N = [8.0] * d, [n] * d
+    r, rho = iso_setup(d, 8.0, n, 2.0)
+    a = O.solve(kind, L, N, rho, eps=16.0 / 8.0, lam=lam)
+    b = O.solve(kind, L, N, rho, eps=16.0 / 6.0, lam=lam)
     assert R.rel_l2_err(a, b) <= 1e-13
+
+
+@pytest.mark.parametrize("kind,lam", [("yukawa3d", 0.7), ("coulomb2d", 0.0), ("biharmonic2d", 0.0)])
+def test_eps_independence_detects_a_planted_w_error(kind, lam):
+    """The pin above is sensitive: W scaled by 1.01 (planted in T(2), on the
+    CPU) moves the two eps results apart by many orders above 1e-13."""
+    d = O.KIND_DIM[kind]
+    n = 48 if d == 3 else 64
+    L, N = [8.0] * d, [n] * d
+    r, rho = iso_setup(d, 8.0, n, 2.0)
+    out = []
+    for eps in (16.0 / 8.0, 16.0 / 6.0):
+        _, t1, t2, _ = O.build_tensor(kind, L, N, eps, lam=lam, parts=True)
+        out.append(O.conv_fft(t1 + 1.01 * t2, rho))
+    assert R.rel_l2_err(out[0], out[1]) > 1e-6
 
 
 def test_isotropic_coulomb_32_against_closed_form():
