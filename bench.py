@@ -117,7 +117,7 @@ def measured_traffic(kernel, prec):
         return None
 
 
-def bench_precision(F, torch, hip, prob, rho64, prec, steps, warmup):
+def bench_precision(F, torch, hip, prob, rho64, prec, steps, warmup, tune=True):
     dtype = F.DTYPES[prec]
     stream = torch.cuda.current_stream()
     plan = F.Plan(prob.kernel, prob.L, prob.N, prec, eps=prob.eps, lam=prob.lam)
@@ -132,6 +132,8 @@ def bench_precision(F, torch, hip, prob, rho64, prec, steps, warmup):
     rho = torch.from_numpy(rho64).to(dtype).cuda()
     out = torch.empty_like(rho)
     ws = plan.workspace()
+    # launch choices per pass from the autotuner (untimed, before warm-up)
+    tuned = plan.autotune(rho, reps=5) if tune else {}
     for _ in range(warmup):
         plan.apply(rho, out, ws)
     torch.cuda.synchronize()
@@ -176,6 +178,8 @@ def bench_precision(F, torch, hip, prob, rho64, prec, steps, warmup):
         "wall_ms_per_step": wall_ms / steps,
         "precomp_ms": precomp_ms,
         "pass_ms": {k: round(v, 5) for k, v in pass_ms.items()},
+        "tuned": {f"{name}_{n}": {"variant": v, "occupancy": o, "us": round(us, 2)}
+                  for (name, n), (v, o, us) in tuned.items()},
         "model_bytes_per_step": sum(mb.values()),
         "model_hbm_frac": sum(mb.values()) / (ms * 1e-3) / HBM_PEAK_BPS,
         "roofline": {
@@ -213,7 +217,7 @@ def stream_copy(torch, hip, nbytes=1 << 30, reps=10):
     return 2.0 * nbytes / (ms * 1e-3)
 
 
-def bench_batch(F, torch, hip, synth, steps, warmup, count=256):
+def bench_batch(F, torch, hip, synth, steps, warmup, count=256, tune=True):
     """The batched 2D log workload: `count` seeded densities on grids drawn
     from {256^2, 512^2, 1024x256, 2048x512, 1024^2}, boxes L_j in U[4,16],
     FP32 FFT with FP64-built tensors, one captured graph of persistent
@@ -232,8 +236,18 @@ def bench_batch(F, torch, hip, synth, steps, warmup, count=256):
             for p in probs]
     outs = [torch.empty_like(r) for r in rhos]
     ws = torch.empty(F.batch_workspace_bytes(plans) + 256, dtype=torch.uint8, device="cuda")
+    # autotune one plan per grid shape (the choices are keyed by transform length)
+    t_tune = time.perf_counter()
+    if tune:
+        seen = set()
+        for pl, r in zip(plans, rhos):
+            if pl.N not in seen:
+                seen.add(pl.N)
+                pl.autotune(r, reps=5)
     torch.cuda.synchronize()
-    log(f"  batch setup {time.perf_counter() - t0:.1f} s (tensor builds {build_ms:.1f} ms)")
+    tune_s = time.perf_counter() - t_tune
+    log(f"  batch setup {time.perf_counter() - t0:.1f} s (tensor builds {build_ms:.1f} ms, "
+        f"autotune {tune_s:.1f} s)")
     t1 = time.perf_counter()
     F.apply_batched(plans, rhos, outs, ws)  # captures the graph
     torch.cuda.synchronize()
@@ -280,6 +294,7 @@ def bench_batch(F, torch, hip, synth, steps, warmup, count=256):
         "per_call_ms": percall_ms,
         "per_call_value": pts / (percall_ms * 1e-3),
         "tensor_build_ms_total": build_ms,
+        "autotune_s": tune_s,
         "bitwise_equal_to_per_call": same,
     }
 
@@ -288,8 +303,8 @@ def bench_serve(F, torch, hip, synth, duration=3.0, rate=2000.0, budget=200 << 3
                 inflight=32, streams=8, per_call=True):
     """Served workload: seeded Poisson arrivals (mean `rate` req/s) of 3D
     Coulomb / Yukawa requests on {64^3, 128^3, 256^3, 512x64x64, 64x64x512}
-    grids with 1-8 Gaussian densities, 5% FP64, tensors cached, HBM budget
-    200 GB; latency = completion - submission.  The same arrival stream is
+    grids with 1-8 Gaussian densities, 5% FP64, tensors cached under an HBM
+    budget (200 GiB by default); latency = completion - submission.  The same arrival stream is
     also replayed through the plain per-call path (one synchronous
     fsa_apply at a time), in FP64 and in FP32."""
     reqs = synth.serve_stream(seed=5000, rate=rate, duration=duration)
@@ -389,7 +404,7 @@ def bench_serve(F, torch, hip, synth, duration=3.0, rate=2000.0, budget=200 << 3
     return {
         "workload": f"Poisson arrivals at {rate:.0f} req/s for {duration:.1f} s (seed 5000): "
                     "3D Coulomb (1/2) / Yukawa lam in {0.5,1,4}; grids 64^3, 128^3, 256^3, "
-                    "512x64x64, 64x64x512; 5% FP64; HBM budget 200 GB",
+                    f"512x64x64, 64x64x512; 5% FP64; HBM budget {budget / 2**30:.0f} GiB",
         "requests": len(reqs),
         "grid_points": pts,
         "server": {"p50_ms": st["p50_ms"], "p99_ms": st["p99_ms"],
@@ -441,6 +456,8 @@ def main():
     ap.add_argument("--no-serve", action="store_true", help="skip the served workload")
     ap.add_argument("--serve-only", action="store_true", help="only the served workload")
     ap.add_argument("--serve-seconds", type=float, default=3.0)
+    ap.add_argument("--no-tune", action="store_true",
+                    help="skip the autotuner (every pass at its default launch variant)")
     ap.add_argument("--copy-only", action="store_true",
                     help="only run the 1 GiB device copy (counter calibration)")
     args = ap.parse_args()
@@ -466,12 +483,12 @@ def main():
     if args.serve_only:
         sv = bench_serve(F, torch, hip, synth, duration=args.serve_seconds)
         log(f"  serve: {json.dumps(sv)}")
-        burst = bench_serve(F, torch, hip, synth, duration=1.0, rate=6000.0)
+        burst = bench_serve(F, torch, hip, synth, duration=1.0, rate=6000.0, budget=2 << 30)
         log(f"  burst: {json.dumps(burst)}")
         print(json.dumps({"serve": sv, "serve_burst": burst}), flush=True)
         return
     if args.batch_only:
-        b = bench_batch(F, torch, hip, synth, max(3, args.steps // 2), 2)
+        b = bench_batch(F, torch, hip, synth, max(3, args.steps // 2), 2, tune=not args.no_tune)
         log(f"  batch: {b['ms_per_batch']:.3f} ms ({b['value'] / 1e9:.2f} Gpts/s) in "
             f"{b['launches_in_graph']} launches; per-call {b['per_call_ms']:.3f} ms")
         print(json.dumps({"batch": b}), flush=True)
@@ -484,7 +501,7 @@ def main():
     for prec in ("f32", "f64"):
         log(f"bench {prec}: {args.warmup} warmup + {args.steps} timed evaluations")
         res[prec], phis[prec] = bench_precision(F, torch, hip, prob, rho64, prec, args.steps,
-                                                args.warmup)
+                                                args.warmup, tune=not args.no_tune)
         log(f"  {prec}: {res[prec]['ms_per_step']:.4f} ms/eval, "
             f"{res[prec]['value'] / 1e9:.2f} Gpts/s, passes {res[prec]['pass_ms']}")
     diff = float(np.linalg.norm(phis["f32"] - phis["f64"]) / np.linalg.norm(phis["f64"]))
@@ -492,16 +509,22 @@ def main():
     batch = None
     if not args.no_batch:
         log("batched 2D log workload (256 densities) ...")
-        batch = bench_batch(F, torch, hip, synth, max(3, args.steps // 2), 2)
+        batch = bench_batch(F, torch, hip, synth, max(3, args.steps // 2), 2,
+                            tune=not args.no_tune)
         log(f"  batch: {batch['ms_per_batch']:.3f} ms ({batch['value'] / 1e9:.2f} Gpts/s) in "
             f"{batch['launches_in_graph']} launches; per-call {batch['per_call_ms']:.3f} ms")
-    serve = None
+    serve = serve_burst = None
     if not args.no_serve:
         log("served workload (Poisson arrivals) ...")
         serve = bench_serve(F, torch, hip, synth, duration=args.serve_seconds)
         log(f"  server p50/p99 {serve['server']['p50_ms']:.3f}/{serve['server']['p99_ms']:.3f} ms, "
             f"per-call FP64 p50/p99 {serve['per_call_fp64']['p50_ms']:.3f}/"
             f"{serve['per_call_fp64']['p99_ms']:.3f} ms")
+        log("burst: 6000 req/s for 1 s under a 2 GB HBM budget ...")
+        serve_burst = bench_serve(F, torch, hip, synth, duration=1.0, rate=6000.0,
+                                  budget=2 << 30, per_call=False)
+        log(f"  burst server p50/p99 {serve_burst['server']['p50_ms']:.3f}/"
+            f"{serve_burst['server']['p99_ms']:.3f} ms")
     cpu = None
     if not args.no_cpu:
         log("cpu baseline (oracle) ...")
@@ -531,8 +554,10 @@ def main():
         "cpu_baseline": cpu,
         "fp64": {"value": r64["value"], "ms_per_step": r64["ms_per_step"],
                  "roofline": r64["roofline"], "pass_ms": r64["pass_ms"],
-                 "model_hbm_frac": r64["model_hbm_frac"], "precomp_ms": r64["precomp_ms"]},
+                 "model_hbm_frac": r64["model_hbm_frac"], "precomp_ms": r64["precomp_ms"],
+                 "tuned": r64["tuned"]},
         "pass_ms": r32["pass_ms"],
+        "tuned": r32["tuned"],
         "model_bytes_per_step": r32["model_bytes_per_step"],
         "model_hbm_frac": r32["model_hbm_frac"],
         "precomp_ms": r32["precomp_ms"],
@@ -540,6 +565,7 @@ def main():
         "f32_vs_f64_rel_l2": diff,
         "batch": batch,
         "serve": serve,
+        "serve_burst": serve_burst,
         "stream_copy_GBps": copy_bps / 1e9,
         "model_copy_frac": r32["model_bytes_per_step"] / (r32["ms_per_step"] * 1e-3) / copy_bps,
         "kernel_source_hash": kernel_source_hash(),

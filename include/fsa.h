@@ -173,6 +173,62 @@ fsa_status fsa_plan_destroy(fsa_plan plan);
 fsa_status fsa_plan_tensor(fsa_plan plan, const void** tensor, int64_t* dims);
 
 /* ------------------------------------------------------------------------- */
+/* Autotuner: launch choices per (precision, pass, transform length)          */
+/* ------------------------------------------------------------------------- */
+
+/* Passes of one evaluation (Sec. 2.3: the forward FFT, the pointwise
+ * product with the tensor and the inverse FFT of eq. DiscConv, split by
+ * axis).  Transform length: the half length M = N_{d-1} of the padded row
+ * for FSA_PASS_R2C / FSA_PASS_C2R, the padded length P = 2 N_j otherwise. */
+typedef enum {
+    FSA_PASS_R2C = 0,   /* A: zero-pad + real FFT along the last axis       */
+    FSA_PASS_FWD_T = 1, /* B (3D): zero-pad + FFT along axis 1              */
+    FSA_PASS_CONV = 2,  /* C: FFT along axis 0, x tensor, inverse FFT, crop */
+    FSA_PASS_INV_T = 3, /* D (3D): inverse FFT along axis 1, crop           */
+    FSA_PASS_C2R = 4    /* E: inverse real FFT along the last axis, crop    */
+} fsa_pass;
+
+/* Every pass kernel exists in up to three compiled variants per length:
+ *   0  default radix plan and workgroup size;
+ *   1  alternate radix family (another radix split and number of threads
+ *      per transform);
+ *   2  half-size workgroups (half the lines per tile, or teams per group).
+ * and its persistent grid may use `occupancy` resident workgroups per CU
+ * (0 = as many as fit).  The library keeps one process-wide table of
+ * choices; untuned entries use variant 0 at full occupancy.  fsa_apply,
+ * fsa_apply_batched and the server read the table when they launch.  All
+ * variants compute the same transform; results differ only by rounding.
+ * On first use the table is loaded from the JSON file named by the
+ * environment variable FSA_TUNE_CACHE, when that is set and exists. */
+
+/* Times every distinct (variant, occupancy) candidate of every pass of a
+ * built plan on `stream` with hipEvents (median of `reps`, 1..1000, after
+ * one warm-up each) and stores the fastest in the table.  Synchronous.
+ *   rho, phi, workspace  device buffers as for fsa_apply; on return phi holds
+ *                        a valid evaluation of rho with the tuned choices.
+ * Batch graphs captured before the call are re-captured on their next use. */
+fsa_status fsa_autotune(fsa_plan plan, const void* rho, void* phi, void* workspace, void* stream,
+                        int reps);
+
+/* Sets / reads one entry (precision: fsa_precision, pass: fsa_pass).  A
+ * variant that does not exist at that pass and length is FSA_EINVAL.  `us`
+ * receives the measured time of the chosen candidate (0 if set by hand or
+ * untuned; may be NULL). */
+fsa_status fsa_tune_set(int precision, int pass, int length, int variant, int occupancy);
+fsa_status fsa_tune_get(int precision, int pass, int length, int* variant, int* occupancy,
+                        double* us);
+/* Bit mask of the variants that exist at (precision, pass, length). */
+fsa_status fsa_tune_variants(int precision, int pass, int length, int* mask);
+/* Writes the table as JSON (format "fsa-tune-1", tagged with the device's
+ * architecture name) / merges a saved table into the current one.  Loading
+ * rejects, as a whole, a file that is malformed, was tuned on another
+ * architecture or names a variant that does not exist (FSA_EINVAL). */
+fsa_status fsa_tune_save(const char* path);
+fsa_status fsa_tune_load(const char* path);
+/* Forgets every entry (all passes back to variant 0, full occupancy). */
+fsa_status fsa_tune_reset(void);
+
+/* ------------------------------------------------------------------------- */
 /* Served variant: continuous batching with HBM-budget admission             */
 /* ------------------------------------------------------------------------- */
 

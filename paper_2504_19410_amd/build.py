@@ -22,8 +22,13 @@ SOURCES = [
     "fsa_batch.cpp",
     "fsa_server.cpp",
     "fsa_tensor.hip",
-    "fsa_launch_f32.hip",
-    "fsa_launch_f64.hip",
+    "fsa_tune.cpp",
+    "fsa_launch_f32_v0.hip",
+    "fsa_launch_f32_v1.hip",
+    "fsa_launch_f32_v2.hip",
+    "fsa_launch_f64_v0.hip",
+    "fsa_launch_f64_v1.hip",
+    "fsa_launch_f64_v2.hip",
 ]
 
 CXXFLAGS = [
@@ -53,7 +58,7 @@ def _compile(src: str, force: bool) -> str:
     return obj
 
 
-def build(force: bool = False, jobs: int = 6) -> str:
+def build(force: bool = False, jobs: int = 8) -> str:
     os.makedirs(BUILD, exist_ok=True)
     with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
         objs = list(ex.map(lambda s: _compile(s, force), SOURCES))

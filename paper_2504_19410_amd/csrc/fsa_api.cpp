@@ -192,14 +192,27 @@ fsa_status fsa_build_tensor(fsa_plan pl, void* stream) {
 
 namespace fsa {
 
-// Enqueues the 3 (2D) or 5 (3D) passes of one evaluation.
+int n_passes(const fsa_plan_s* pl) { return pl->d == 3 ? 5 : 3; }
+
+void pass_of(const fsa_plan_s* pl, int k, Pass* pass, int* len) {
+    const int N0 = (int)pl->N[0], N1 = (int)pl->N[1];
+    if (pl->d == 3) {
+        const int N2 = (int)pl->N[2];
+        static const Pass kind[5] = {Pass::R2C, Pass::FWD_T, Pass::CONV, Pass::INV_T, Pass::C2R};
+        const int lens[5] = {N2, 2 * N1, 2 * N0, 2 * N1, N2};
+        *pass = kind[k];
+        *len = lens[k];
+    } else {
+        static const Pass kind[3] = {Pass::R2C, Pass::CONV, Pass::C2R};
+        const int lens[3] = {N1, 2 * N0, N1};
+        *pass = kind[k];
+        *len = lens[k];
+    }
+}
+
 template <typename R>
-static hipError_t apply_impl(const fsa_plan_s* pl, const void* rho, void* phi, void* ws,
-                             hipStream_t st, hipEvent_t const* ev) {
-    int pass = 0;
-    auto mark = [&]() -> hipError_t {
-        return ev ? hipEventRecord(ev[pass++], st) : hipSuccess;
-    };
+static hipError_t launch_pass_t(const fsa_plan_s* pl, int k, const void* rho, void* phi,
+                                void* ws, Choice c, hipStream_t st) {
     const char* tw = (const char*)pl->twiddles;
     const size_t cs = pl->csize;
     const void* tw_p0 = tw + pl->tw_off_p0 * cs;
@@ -210,38 +223,53 @@ static hipError_t apply_impl(const fsa_plan_s* pl, const void* rho, void* phi, v
     const int H = (int)pl->H;
     const R* tensor = (const R*)pl->tensor;
     char* w1 = (char*)ws;
-    hipError_t e;
     if (pl->d == 3) {
         const int N2 = (int)pl->N[2];
         char* w2 = w1 + ((pl->ws1_elems * cs + 255) & ~size_t(255));
-        e = mark();
-        if (e == hipSuccess) e = Launch<R>::r2c(N2, (const R*)rho, w1, N0, N1, tw_m, tw_pl, st);
-        if (e == hipSuccess) e = mark();
-        if (e == hipSuccess) e = Launch<R>::fwd_t(2 * N1, w1, w2, N0, H, tw_p1, st);
-        if (e == hipSuccess) e = mark();
-        if (e == hipSuccess)
-            e = Launch<R>::conv(2 * N0, w2, tensor, H * 2 * N1, 2 * N1, N1, tw_p0, st);
-        if (e == hipSuccess) e = mark();
-        if (e == hipSuccess) e = Launch<R>::inv_t(2 * N1, w2, w1, N0, H, tw_p1, st);
-        if (e == hipSuccess) e = mark();
-        if (e == hipSuccess) e = Launch<R>::c2r(N2, w1, (R*)phi, N0, N1, tw_m, tw_pl, st);
-        if (e == hipSuccess) e = mark();
+        switch (k) {
+        case 0: return Launch<R>::r2c(N2, (const R*)rho, w1, N0, N1, tw_m, tw_pl, c, st);
+        case 1: return Launch<R>::fwd_t(2 * N1, w1, w2, N0, H, tw_p1, c, st);
+        case 2: return Launch<R>::conv(2 * N0, w2, tensor, H * 2 * N1, 2 * N1, N1, tw_p0, c, st);
+        case 3: return Launch<R>::inv_t(2 * N1, w2, w1, N0, H, tw_p1, c, st);
+        case 4: return Launch<R>::c2r(N2, w1, (R*)phi, N0, N1, tw_m, tw_pl, c, st);
+        }
     } else {
-        e = mark();
-        if (e == hipSuccess) e = Launch<R>::r2c(N1, (const R*)rho, w1, 1, N0, tw_m, tw_pl, st);
-        if (e == hipSuccess) e = mark();
-        if (e == hipSuccess) e = Launch<R>::conv(2 * N0, w1, tensor, H, 1, 0, tw_p0, st);
-        if (e == hipSuccess) e = mark();
-        if (e == hipSuccess) e = Launch<R>::c2r(N1, w1, (R*)phi, 1, N0, tw_m, tw_pl, st);
-        if (e == hipSuccess) e = mark();
+        switch (k) {
+        case 0: return Launch<R>::r2c(N1, (const R*)rho, w1, 1, N0, tw_m, tw_pl, c, st);
+        case 1: return Launch<R>::conv(2 * N0, w1, tensor, H, 1, 0, tw_p0, c, st);
+        case 2: return Launch<R>::c2r(N1, w1, (R*)phi, 1, N0, tw_m, tw_pl, c, st);
+        }
     }
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_pass(const fsa_plan_s* pl, int k, const void* rho, void* phi, void* ws,
+                       Choice c, hipStream_t st) {
+    return pl->prec == FSA_F32 ? launch_pass_t<float>(pl, k, rho, phi, ws, c, st)
+                               : launch_pass_t<double>(pl, k, rho, phi, ws, c, st);
+}
+
+// Enqueues the 3 (2D) or 5 (3D) passes of one evaluation with the tuned
+// launch choices; with events, records ev[k] before pass k and one more at
+// the end.
+static hipError_t apply_impl(const fsa_plan_s* pl, const void* rho, void* phi, void* ws,
+                             hipStream_t st, hipEvent_t const* ev) {
+    const int np = n_passes(pl);
+    hipError_t e = hipSuccess;
+    for (int k = 0; k < np && e == hipSuccess; ++k) {
+        if (ev) e = hipEventRecord(ev[k], st);
+        Pass pass;
+        int len;
+        pass_of(pl, k, &pass, &len);
+        if (e == hipSuccess) e = launch_pass(pl, k, rho, phi, ws, tune::get(pl->prec, pass, len), st);
+    }
+    if (e == hipSuccess && ev) e = hipEventRecord(ev[np], st);
     return e;
 }
 
 hipError_t apply_plan(const fsa_plan_s* pl, const void* rho, void* phi, void* ws,
                       hipStream_t st, hipEvent_t const* events) {
-    return pl->prec == FSA_F32 ? apply_impl<float>(pl, rho, phi, ws, st, events)
-                               : apply_impl<double>(pl, rho, phi, ws, st, events);
+    return apply_impl(pl, rho, phi, ws, st, events);
 }
 
 }  // namespace fsa

@@ -11,7 +11,8 @@
 // bitwise equal to fsa_apply on that problem alone.
 //
 // The graph (and the device job tables it reads) is built on the first call
-// with a given signature -- plans, device pointers, workspace -- and
+// with a given signature -- plans, device pointers, workspace, and the
+// generation of the tuning table whose launch choices it snapshots -- and
 // replayed on later calls.
 #include <hip/hip_runtime.h>
 
@@ -28,8 +29,6 @@
 
 namespace fsa {
 void set_last_error(const char* msg);
-hipError_t apply_plan(const fsa_plan_s* pl, const void* rho, void* phi, void* ws, hipStream_t st,
-                      hipEvent_t const* events);
 }  // namespace fsa
 
 namespace {
@@ -42,6 +41,7 @@ struct Group {
     fsa_precision prec;
     const void* tw = nullptr;   // twiddles of length len (any member plan's table)
     const void* tw2 = nullptr;  // second table of the real transforms (length 2 len)
+    fsa::Choice ch;             // launch choice, fixed when the group is formed
     std::vector<unsigned char> jobs;  // packed job structs
     std::vector<int> start{0};
     size_t job_size = 0;
@@ -68,9 +68,12 @@ std::mutex g_mu;
 std::vector<std::unique_ptr<Entry>>& g_cache = *new std::vector<std::unique_ptr<Entry>>();
 constexpr size_t kCacheCap = 16;
 
+// Adds one problem's job to its (pass, length, precision) group; the group
+// takes the tuned launch choice when it is formed, and the job's item count
+// follows that choice.  Returns false for an unsupported length.
 template <class Job>
-void add_job(std::map<std::tuple<int, int, int>, Group>& groups, fsa::Pass pass, int len,
-             fsa_precision prec, const void* tw, const void* tw2, const Job& job, int items) {
+bool add_job(std::map<std::tuple<int, int, int>, Group>& groups, fsa::Pass pass, int len,
+             fsa_precision prec, const void* tw, const void* tw2, const Job& job) {
     Group& g = groups[std::make_tuple((int)pass, len, (int)prec)];
     if (g.n == 0) {
         g.pass = pass;
@@ -79,17 +82,16 @@ void add_job(std::map<std::tuple<int, int, int>, Group>& groups, fsa::Pass pass,
         g.tw = tw;
         g.tw2 = tw2;
         g.job_size = sizeof(Job);
+        g.ch = fsa::tune::get(prec, pass, len);
     }
+    const int items = prec == FSA_F32 ? fsa::Launch<float>::items(pass, len, &job, g.ch)
+                                      : fsa::Launch<double>::items(pass, len, &job, g.ch);
+    if (items < 0) return false;
     const unsigned char* p = (const unsigned char*)&job;
     g.jobs.insert(g.jobs.end(), p, p + sizeof(Job));
     g.start.push_back(g.start.back() + items);
     ++g.n;
-}
-
-template <class Job>
-int items_of(fsa_precision prec, fsa::Pass pass, int len, const Job& job) {
-    return prec == FSA_F32 ? fsa::Launch<float>::items(pass, len, &job)
-                           : fsa::Launch<double>::items(pass, len, &job);
+    return true;
 }
 
 fsa_status build_entry(int n, const fsa_plan* plans, const void* const* rho, void* const* phi,
@@ -109,10 +111,7 @@ fsa_status build_entry(int n, const fsa_plan* plans, const void* const* rho, voi
         ws += align256(pl->ws_bytes);
         const fsa_precision pr = pl->prec;
         auto add = [&](auto job, fsa::Pass pass, int len, const void* t1, const void* t2) {
-            const int it = items_of(pr, pass, len, job);
-            if (it < 0) return false;
-            add_job(groups, pass, len, pr, t1, t2, job, it);
-            return true;
+            return add_job(groups, pass, len, pr, t1, t2, job);
         };
         bool ok;
         if (pl->d == 3) {
@@ -186,10 +185,10 @@ fsa_status build_entry(int n, const fsa_plan* plans, const void* const* rho, voi
                 lerr = g.prec == FSA_F32
                            ? fsa::Launch<float>::batch(g.pass, g.len, base + oj,
                                                        (const int*)(base + os), g.n, total, g.tw,
-                                                       g.tw2, cap)
+                                                       g.tw2, g.ch, cap)
                            : fsa::Launch<double>::batch(g.pass, g.len, base + oj,
                                                         (const int*)(base + os), g.n, total, g.tw,
-                                                        g.tw2, cap);
+                                                        g.tw2, g.ch, cap);
                 ++e.launches;
             }
         }
@@ -282,6 +281,7 @@ fsa_status fsa_apply_batched(int n, const fsa_plan* plans, const void* const* rh
         key.push_back((uint64_t)(uintptr_t)rho[i]);
         key.push_back((uint64_t)(uintptr_t)phi[i]);
     }
+    key.push_back(fsa::tune::generation());
     std::lock_guard<std::mutex> lk(g_mu);
     Entry* hit = nullptr;
     for (size_t i = 0; i < g_cache.size(); ++i) {
@@ -315,7 +315,10 @@ fsa_status fsa_batch_launches(int n, const fsa_plan* plans, const void* const* r
                               void* const* phi, void* workspace, int* launches) {
     if (!launches) return FSA_EINVAL;
     std::lock_guard<std::mutex> lk(g_mu);
-    for (auto& e : g_cache) {
+    // most recent first: an older entry may hold the same batch under an
+    // earlier tuning generation
+    for (auto it = g_cache.rbegin(); it != g_cache.rend(); ++it) {
+        const auto& e = *it;
         if ((int)e->key[2] == n && e->key[1] == (uint64_t)(uintptr_t)workspace) {
             bool same = true;
             for (int i = 0; i < n && same; ++i)

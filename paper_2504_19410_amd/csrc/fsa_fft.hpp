@@ -175,14 +175,19 @@ constexpr int ilog2_exact(int x) {
     return ((1 << b) == x) ? b : -1;
 }
 
-// Lengths 2^a (a >= 2) and 3 * 2^a (a >= 2).  Power-of-two stages use radices
-// of at most 8 (P < 1024) or 16 (P >= 1024); the bits are spread so that the
-// radix sequence reads the same both ways whenever possible (the inverse runs
-// the radices reversed, so a palindromic plan lets the forward and inverse
-// transforms of the fused pass share one set of twiddles).  The factor 3 runs
-// last.  T is the largest power of two with T * E <= P for E = 8 or 16
-// operands per thread, capped at 256.
-constexpr FftPlan make_fft_plan(int P) {
+// Lengths 2^a (a >= 2) and 3 * 2^a (a >= 2).  The default family (alt = 0)
+// uses power-of-two radices of at most 8 (P < 1024) or 16 (P >= 1024), with
+// the bits spread so that the radix sequence reads the same both ways
+// whenever possible (the inverse runs the radices reversed, so a palindromic
+// plan lets the forward and inverse transforms of the fused pass share one
+// set of twiddles); the factor 3 runs last; T is the largest power of two
+// with T * E <= P for E = 8 (P < 1024) or 16 operands per thread, capped at
+// 256.  The alternate family (alt = 1) swaps both choices -- radices up to 16
+// and E = 16 below 1024, radices up to 8 and E = 8 from 1024 -- which changes
+// the radix split and the threads per transform; the autotuner times both.
+// It falls back to the default where it would leave teams of fewer than 8
+// threads or more than 16 operands per thread.
+constexpr FftPlan make_fft_plan_rule(int P, int maxbits, int E) {
     FftPlan p{};
     p.P = P;
     int m = P, threes = 0;
@@ -191,18 +196,17 @@ constexpr FftPlan make_fft_plan(int P) {
         ++threes;
     }
     const int a = ilog2_exact(m);
-    const int maxbits = (P >= 1024) ? 4 : 3;
     const int nst = (a + maxbits - 1) / maxbits;
     int bits[16] = {};
     if (nst == 3) {
         // ends e, middle m, 2e + m = a: palindromic by construction
-        int e = a / 3, m = a - 2 * e;
-        while (m > maxbits) {
+        int e = a / 3, mid = a - 2 * e;
+        while (mid > maxbits) {
             ++e;
-            m -= 2;
+            mid -= 2;
         }
         bits[0] = e;
-        bits[1] = m;
+        bits[1] = mid;
         bits[2] = e;
     } else {
         for (int s = 0; s < nst; ++s) bits[s] = a / nst + (s < a % nst ? 1 : 0);
@@ -211,7 +215,6 @@ constexpr FftPlan make_fft_plan(int P) {
     for (int s = 0; s < nst; ++s) p.r[n++] = 1 << bits[s];
     for (int t = 0; t < threes; ++t) p.r[n++] = 3;
     p.n = n;
-    const int E = (P >= 1024) ? 16 : 8;
     int T = 1;
     while (T * 2 * E <= P && T < 256) T *= 2;
     p.T = T;
@@ -223,6 +226,23 @@ constexpr FftPlan make_fft_plan(int P) {
     }
     p.vmax = vmax;
     return p;
+}
+
+constexpr FftPlan make_fft_plan(int P, int alt = 0) {
+    const bool big = P >= 1024;
+    const FftPlan def = make_fft_plan_rule(P, big ? 4 : 3, big ? 16 : 8);
+    if (!alt) return def;
+    const FftPlan p = make_fft_plan_rule(P, big ? 3 : 4, big ? 8 : 16);
+    return (p.T >= 8 && p.vmax <= 16) ? p : def;
+}
+
+// Whether the alternate family gives a different transform at length P.
+constexpr bool fft_alt_distinct(int P) {
+    const FftPlan a = make_fft_plan(P, 0), b = make_fft_plan(P, 1);
+    if (a.T != b.T || a.n != b.n) return true;
+    for (int s = 0; s < a.n; ++s)
+        if (a.r[s] != b.r[s]) return true;
+    return false;
 }
 
 constexpr bool fft_length_supported(long P) {
@@ -237,11 +257,11 @@ constexpr bool fft_length_supported(long P) {
 // Team transform of length P, direction INV.
 // ---------------------------------------------------------------------------
 
-template <typename R, int P_, bool INV>
+template <typename R, int P_, bool INV, int ALT = 0>
 struct Fft {
     using C = cpx<R>;
     static constexpr int P = P_;
-    static constexpr FftPlan plan = make_fft_plan(P_);
+    static constexpr FftPlan plan = make_fft_plan(P_, ALT);
     static constexpr int T = plan.T;
     static constexpr int V = plan.vmax;
     static constexpr int S = plan.n;

@@ -10,6 +10,8 @@
 #include "fsa_fft.hpp"
 #include "fsa_jobs.hpp"
 
+struct fsa_plan_s;
+
 namespace fsa {
 
 struct KernelParams {
@@ -36,28 +38,123 @@ hipError_t build_tensor_device(const KernelParams& kp, int d, const double* L, c
 // tw[m] = exp(-2 pi i m / n), m in [0, n), computed in FP64, stored in prec.
 hipError_t build_twiddles(fsa_precision prec, int n, void* out, hipStream_t st);
 
-// Pass launchers (fsa_launch_f32.hip / fsa_launch_f64.hip).  Complex arrays
-// are interleaved (re, im) of R.  Each returns hipErrorInvalidValue for an
-// unsupported length.
-template <typename R>
-struct Launch {
+// Launch configuration of one pass: compile-time variant (0 default, 1
+// alternate radix family, 2 half-size workgroups) and the number of resident
+// workgroups per CU the persistent grid uses (0: as many as fit).
+struct Choice {
+    int var = 0;
+    int occ = 0;
+};
+constexpr int kNumVariants = 3;
+
+// Pass launchers of one variant (fsa_launch_<prec>_v<var>.hip).  Complex
+// arrays are interleaved (re, im) of R.  Each returns hipErrorInvalidValue
+// for an unsupported length, or for a variant that is not distinct from
+// variant 0 at that length.
+template <typename R, int VAR>
+struct LaunchV {
     static hipError_t r2c(int M, const R* rho, void* out, int n_outer, int n_inner,
-                          const void* twM, const void* tw2M, hipStream_t st);
+                          const void* twM, const void* tw2M, int occ, hipStream_t st);
     static hipError_t c2r(int M, const void* in, R* phi, int n_outer, int n_inner,
-                          const void* twM, const void* tw2M, hipStream_t st);
+                          const void* twM, const void* tw2M, int occ, hipStream_t st);
     static hipError_t fwd_t(int P, const void* in, void* out, int N0, int H, const void* tw,
-                            hipStream_t st);
+                            int occ, hipStream_t st);
     static hipError_t inv_t(int P, const void* in, void* out, int N0, int H, const void* tw,
-                            hipStream_t st);
+                            int occ, hipStream_t st);
     static hipError_t conv(int P, void* data, const R* tensor, int n_pencils, int P1, int N1,
-                           const void* tw, hipStream_t st);
+                           const void* tw, int occ, hipStream_t st);
     // Work items of one job of `pass` at transform length `len` (-1: unsupported).
     static int items(Pass pass, int len, const void* job);
     // One persistent launch of `pass` over n jobs (device table `jobs` of the
     // pass's job type, device prefix `start` of n + 1 item offsets).
     static hipError_t batch(Pass pass, int len, const void* jobs, const int* start, int n,
-                            int total, const void* tw, const void* tw2, hipStream_t st);
+                            int total, const void* tw, const void* tw2, int occ,
+                            hipStream_t st);
+    // Whether this variant exists (differs from variant 0) at (pass, len).
+    static bool distinct(Pass pass, int len);
+    // Resident workgroups per CU of the single-evaluation kernel (0: none).
+    static int max_occ(Pass pass, int len);
 };
+
+// Dispatch on the run-time choice.
+template <typename R>
+struct Launch {
+#define FSA_DISPATCH(call)                                      \
+    switch (c.var) {                                            \
+    case 0: return LaunchV<R, 0>::call;                         \
+    case 1: return LaunchV<R, 1>::call;                         \
+    case 2: return LaunchV<R, 2>::call;                         \
+    }                                                           \
+    return hipErrorInvalidValue;
+    static hipError_t r2c(int M, const R* rho, void* out, int n_outer, int n_inner,
+                          const void* twM, const void* tw2M, Choice c, hipStream_t st) {
+        FSA_DISPATCH(r2c(M, rho, out, n_outer, n_inner, twM, tw2M, c.occ, st))
+    }
+    static hipError_t c2r(int M, const void* in, R* phi, int n_outer, int n_inner,
+                          const void* twM, const void* tw2M, Choice c, hipStream_t st) {
+        FSA_DISPATCH(c2r(M, in, phi, n_outer, n_inner, twM, tw2M, c.occ, st))
+    }
+    static hipError_t fwd_t(int P, const void* in, void* out, int N0, int H, const void* tw,
+                            Choice c, hipStream_t st) {
+        FSA_DISPATCH(fwd_t(P, in, out, N0, H, tw, c.occ, st))
+    }
+    static hipError_t inv_t(int P, const void* in, void* out, int N0, int H, const void* tw,
+                            Choice c, hipStream_t st) {
+        FSA_DISPATCH(inv_t(P, in, out, N0, H, tw, c.occ, st))
+    }
+    static hipError_t conv(int P, void* data, const R* tensor, int n_pencils, int P1, int N1,
+                           const void* tw, Choice c, hipStream_t st) {
+        FSA_DISPATCH(conv(P, data, tensor, n_pencils, P1, N1, tw, c.occ, st))
+    }
+    static hipError_t batch(Pass pass, int len, const void* jobs, const int* start, int n,
+                            int total, const void* tw, const void* tw2, Choice c,
+                            hipStream_t st) {
+        FSA_DISPATCH(batch(pass, len, jobs, start, n, total, tw, tw2, c.occ, st))
+    }
+#undef FSA_DISPATCH
+    static int items(Pass pass, int len, const void* job, Choice c) {
+        switch (c.var) {
+        case 0: return LaunchV<R, 0>::items(pass, len, job);
+        case 1: return LaunchV<R, 1>::items(pass, len, job);
+        case 2: return LaunchV<R, 2>::items(pass, len, job);
+        }
+        return -1;
+    }
+    static bool distinct(Pass pass, int len, int var) {
+        switch (var) {
+        case 0: return LaunchV<R, 0>::distinct(pass, len);
+        case 1: return LaunchV<R, 1>::distinct(pass, len);
+        case 2: return LaunchV<R, 2>::distinct(pass, len);
+        }
+        return false;
+    }
+    static int max_occ(Pass pass, int len, int var) {
+        switch (var) {
+        case 0: return LaunchV<R, 0>::max_occ(pass, len);
+        case 1: return LaunchV<R, 1>::max_occ(pass, len);
+        case 2: return LaunchV<R, 2>::max_occ(pass, len);
+        }
+        return 0;
+    }
+};
+
+// Tuning table (fsa_tune.cpp): the launch choice for (precision, pass,
+// transform length); variant 0 at full occupancy unless tuned or loaded.
+namespace tune {
+Choice get(fsa_precision prec, Pass pass, int len);
+void set(fsa_precision prec, Pass pass, int len, Choice c, double us);
+// Bumped on every change; batch graphs captured under another generation
+// are re-captured.
+uint64_t generation();
+}  // namespace tune
+
+// Enqueues pass `k` (0-based, in execution order) of one evaluation with an
+// explicit choice; the apply path calls it with the tuned choices.
+hipError_t launch_pass(const fsa_plan_s* pl, int k, const void* rho, void* phi, void* ws,
+                       Choice c, hipStream_t st);
+// (pass kind, transform length) of pass k of a plan.
+void pass_of(const fsa_plan_s* pl, int k, Pass* pass, int* len);
+int n_passes(const fsa_plan_s* pl);
 
 }  // namespace fsa
 

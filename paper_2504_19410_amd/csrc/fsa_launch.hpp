@@ -1,5 +1,5 @@
-// fsa_launch.hpp -- compile-time length dispatch of the pass kernels.
-// Included by one translation unit per precision.
+// fsa_launch.hpp -- compile-time length dispatch of the pass kernels of one
+// variant.  Included by one translation unit per (precision, variant).
 #pragma once
 
 #include "fsa_internal.hpp"
@@ -38,132 +38,186 @@ int blocks_per_cu(Kern kernel, int threads) {
     return per_cu;
 }
 
-// Workgroups that fill every CU once, but no more than the work needs.
-inline int persistent_grid(int per_cu, int work_groups_needed) {
-    const int g = device_cus() * per_cu;
+// Workgroups that fill every CU `occ` times (occ <= 0 or above what fits:
+// as many as fit), but no more than the work needs.
+inline int persistent_grid(int per_cu, int occ, int work_groups_needed) {
+    const int k = (occ > 0 && occ < per_cu) ? occ : per_cu;
+    const int g = device_cus() * k;
     return g < work_groups_needed ? g : (work_groups_needed > 0 ? work_groups_needed : 1);
 }
 
-template <typename R>
-hipError_t Launch<R>::r2c(int M, const R* rho, void* out, int n_outer, int n_inner,
-                          const void* twM, const void* tw2M, hipStream_t st) {
+namespace detail {
+
+template <typename R, int VAR, int M, class S>
+hipError_t go_r2c(const S& src, const void* tw, const void* tw2, int occ, hipStream_t st) {
+    using K = R2c<R, M, VAR>;
+    if constexpr (!K::DISTINCT) {
+        return hipErrorInvalidValue;
+    } else {
+        static const int per_cu = blocks_per_cu(k_r2c<R, M, VAR, S>, K::THREADS);
+        hipLaunchKernelGGL((k_r2c<R, M, VAR, S>), dim3(persistent_grid(per_cu, occ, src.total)),
+                           dim3(K::THREADS), 0, st, src, (const cpx<R>*)tw, (const cpx<R>*)tw2);
+        return hipGetLastError();
+    }
+}
+
+template <typename R, int VAR, int M, class S>
+hipError_t go_c2r(const S& src, const void* tw, const void* tw2, int occ, hipStream_t st) {
+    using K = C2r<R, M, VAR>;
+    if constexpr (!K::DISTINCT) {
+        return hipErrorInvalidValue;
+    } else {
+        static const int per_cu = blocks_per_cu(k_c2r<R, M, VAR, S>, K::THREADS);
+        hipLaunchKernelGGL((k_c2r<R, M, VAR, S>), dim3(persistent_grid(per_cu, occ, src.total)),
+                           dim3(K::THREADS), 0, st, src, (const cpx<R>*)tw, (const cpx<R>*)tw2);
+        return hipGetLastError();
+    }
+}
+
+template <typename R, int VAR, int P, class S>
+hipError_t go_fwd_t(const S& src, const void* tw, int occ, hipStream_t st) {
+    using K = FwdT<R, P, VAR>;
+    if constexpr (!K::DISTINCT) {
+        return hipErrorInvalidValue;
+    } else {
+        static const int per_cu = blocks_per_cu(k_fwd_t<R, P, VAR, S>, K::THREADS);
+        hipLaunchKernelGGL((k_fwd_t<R, P, VAR, S>),
+                           dim3(persistent_grid(per_cu, occ, src.total)), dim3(K::THREADS), 0, st,
+                           src, (const cpx<R>*)tw);
+        return hipGetLastError();
+    }
+}
+
+template <typename R, int VAR, int P, class S>
+hipError_t go_inv_t(const S& src, const void* tw, int occ, hipStream_t st) {
+    using K = InvT<R, P, VAR>;
+    if constexpr (!K::DISTINCT) {
+        return hipErrorInvalidValue;
+    } else {
+        static const int per_cu = blocks_per_cu(k_inv_t<R, P, VAR, S>, K::THREADS);
+        hipLaunchKernelGGL((k_inv_t<R, P, VAR, S>),
+                           dim3(persistent_grid(per_cu, occ, src.total)), dim3(K::THREADS), 0, st,
+                           src, (const cpx<R>*)tw);
+        return hipGetLastError();
+    }
+}
+
+template <typename R, int VAR, int P, class S>
+hipError_t go_conv(const S& src, const void* tw, int occ, hipStream_t st) {
+    using K = Conv<R, P, VAR>;
+    if constexpr (!K::DISTINCT) {
+        return hipErrorInvalidValue;
+    } else {
+        static const int per_cu = blocks_per_cu(k_conv<R, P, VAR, S>, K::THREADS);
+        hipLaunchKernelGGL((k_conv<R, P, VAR, S>),
+                           dim3(persistent_grid(per_cu, occ, cdiv(src.total, K::TPW))),
+                           dim3(K::THREADS), 0, st, src, (const cpx<R>*)tw);
+        return hipGetLastError();
+    }
+}
+
+// Resident workgroups per CU of a variant's single-evaluation kernel (the
+// kernel is named only where the variant exists).
+#define FSA_OCC_HELPER(name, Cfg, kern, Job)                                                    \
+    template <typename R, int VAR, int LEN>                                                      \
+    int name() {                                                                                 \
+        using K = Cfg<R, LEN, VAR>;                                                              \
+        if constexpr (!K::DISTINCT) return 0;                                                    \
+        else return blocks_per_cu(kern<R, LEN, VAR, JobOne<Job>>, K::THREADS);                   \
+    }
+FSA_OCC_HELPER(occ_r2c, R2c, k_r2c, JobR2c)
+FSA_OCC_HELPER(occ_c2r, C2r, k_c2r, JobC2r)
+FSA_OCC_HELPER(occ_fwd_t, FwdT, k_fwd_t, JobT)
+FSA_OCC_HELPER(occ_inv_t, InvT, k_inv_t, JobT)
+FSA_OCC_HELPER(occ_conv, Conv, k_conv, JobConv)
+#undef FSA_OCC_HELPER
+
+}  // namespace detail
+
+template <typename R, int VAR>
+hipError_t LaunchV<R, VAR>::r2c(int M, const R* rho, void* out, int n_outer, int n_inner,
+                                const void* twM, const void* tw2M, int occ, hipStream_t st) {
+    using S = JobOne<JobR2c>;
     switch (M) {
 #define FSA_CASE(m)                                                                              \
-    case m: {                                                                                    \
-        using K = R2c<R, m>;                                                                     \
-        using S = JobOne<JobR2c>;                                                                \
-        static const int per_cu = blocks_per_cu(k_r2c<R, m, S>, K::THREADS);                    \
-        const S src{JobR2c{rho, out, n_outer, n_inner}, cdiv(n_inner, K::WT) * n_outer};         \
-        hipLaunchKernelGGL((k_r2c<R, m, S>), dim3(persistent_grid(per_cu, src.total)),          \
-                           dim3(K::THREADS), 0, st, src, (const cpx<R>*)twM,                     \
-                           (const cpx<R>*)tw2M);                                                 \
-        break;                                                                                   \
-    }
+    case m:                                                                                      \
+        return detail::go_r2c<R, VAR, m>(                                                        \
+            S{JobR2c{rho, out, n_outer, n_inner}, cdiv(n_inner, R2c<R, m, VAR>::WT) * n_outer},  \
+            twM, tw2M, occ, st);
         FSA_M_LIST(FSA_CASE)
 #undef FSA_CASE
-    default:
-        return hipErrorInvalidValue;
     }
-    return hipGetLastError();
+    return hipErrorInvalidValue;
 }
 
-template <typename R>
-hipError_t Launch<R>::c2r(int M, const void* in, R* phi, int n_outer, int n_inner,
-                          const void* twM, const void* tw2M, hipStream_t st) {
+template <typename R, int VAR>
+hipError_t LaunchV<R, VAR>::c2r(int M, const void* in, R* phi, int n_outer, int n_inner,
+                                const void* twM, const void* tw2M, int occ, hipStream_t st) {
+    using S = JobOne<JobC2r>;
     switch (M) {
 #define FSA_CASE(m)                                                                              \
-    case m: {                                                                                    \
-        using K = C2r<R, m>;                                                                     \
-        using S = JobOne<JobC2r>;                                                                \
-        static const int per_cu = blocks_per_cu(k_c2r<R, m, S>, K::THREADS);                    \
-        const S src{JobC2r{in, phi, n_outer, n_inner}, cdiv(n_inner, K::WT) * n_outer};          \
-        hipLaunchKernelGGL((k_c2r<R, m, S>), dim3(persistent_grid(per_cu, src.total)),          \
-                           dim3(K::THREADS), 0, st, src, (const cpx<R>*)twM,                     \
-                           (const cpx<R>*)tw2M);                                                 \
-        break;                                                                                   \
-    }
+    case m:                                                                                      \
+        return detail::go_c2r<R, VAR, m>(                                                        \
+            S{JobC2r{in, phi, n_outer, n_inner}, cdiv(n_inner, C2r<R, m, VAR>::WT) * n_outer},   \
+            twM, tw2M, occ, st);
         FSA_M_LIST(FSA_CASE)
 #undef FSA_CASE
-    default:
-        return hipErrorInvalidValue;
     }
-    return hipGetLastError();
+    return hipErrorInvalidValue;
 }
 
-template <typename R>
-hipError_t Launch<R>::fwd_t(int P, const void* in, void* out, int N0, int H, const void* tw,
-                            hipStream_t st) {
+template <typename R, int VAR>
+hipError_t LaunchV<R, VAR>::fwd_t(int P, const void* in, void* out, int N0, int H,
+                                  const void* tw, int occ, hipStream_t st) {
+    using S = JobOne<JobT>;
     switch (P) {
 #define FSA_CASE(p)                                                                              \
-    case p: {                                                                                    \
-        using K = FwdT<R, p>;                                                                    \
-        using S = JobOne<JobT>;                                                                  \
-        static const int per_cu = blocks_per_cu(k_fwd_t<R, p, S>, K::THREADS);                  \
-        const S src{JobT{in, out, N0, H}, cdiv(N0, K::WT) * H};                                  \
-        hipLaunchKernelGGL((k_fwd_t<R, p, S>), dim3(persistent_grid(per_cu, src.total)),        \
-                           dim3(K::THREADS), 0, st, src, (const cpx<R>*)tw);                     \
-        break;                                                                                   \
-    }
+    case p:                                                                                      \
+        return detail::go_fwd_t<R, VAR, p>(                                                      \
+            S{JobT{in, out, N0, H}, cdiv(N0, FwdT<R, p, VAR>::WT) * H}, tw, occ, st);
         FSA_P_LIST(FSA_CASE)
 #undef FSA_CASE
-    default:
-        return hipErrorInvalidValue;
     }
-    return hipGetLastError();
+    return hipErrorInvalidValue;
 }
 
-template <typename R>
-hipError_t Launch<R>::inv_t(int P, const void* in, void* out, int N0, int H, const void* tw,
-                            hipStream_t st) {
+template <typename R, int VAR>
+hipError_t LaunchV<R, VAR>::inv_t(int P, const void* in, void* out, int N0, int H,
+                                  const void* tw, int occ, hipStream_t st) {
+    using S = JobOne<JobT>;
     switch (P) {
 #define FSA_CASE(p)                                                                              \
-    case p: {                                                                                    \
-        using K = InvT<R, p>;                                                                    \
-        using S = JobOne<JobT>;                                                                  \
-        static const int per_cu = blocks_per_cu(k_inv_t<R, p, S>, K::THREADS);                  \
-        const S src{JobT{in, out, N0, H}, cdiv(N0, K::WT) * H};                                  \
-        hipLaunchKernelGGL((k_inv_t<R, p, S>), dim3(persistent_grid(per_cu, src.total)),        \
-                           dim3(K::THREADS), 0, st, src, (const cpx<R>*)tw);                     \
-        break;                                                                                   \
-    }
+    case p:                                                                                      \
+        return detail::go_inv_t<R, VAR, p>(                                                      \
+            S{JobT{in, out, N0, H}, cdiv(N0, InvT<R, p, VAR>::WT) * H}, tw, occ, st);
         FSA_P_LIST(FSA_CASE)
 #undef FSA_CASE
-    default:
-        return hipErrorInvalidValue;
     }
-    return hipGetLastError();
+    return hipErrorInvalidValue;
 }
 
-template <typename R>
-hipError_t Launch<R>::conv(int P, void* data, const R* tensor, int n_pencils, int P1, int N1,
-                           const void* tw, hipStream_t st) {
+template <typename R, int VAR>
+hipError_t LaunchV<R, VAR>::conv(int P, void* data, const R* tensor, int n_pencils, int P1,
+                                 int N1, const void* tw, int occ, hipStream_t st) {
+    using S = JobOne<JobConv>;
     switch (P) {
 #define FSA_CASE(p)                                                                              \
-    case p: {                                                                                    \
-        using K = Conv<R, p>;                                                                    \
-        using S = JobOne<JobConv>;                                                               \
-        static const int per_cu = blocks_per_cu(k_conv<R, p, S>, K::THREADS);                   \
-        const S src{JobConv{data, tensor, n_pencils, P1, N1}, n_pencils};                        \
-        hipLaunchKernelGGL((k_conv<R, p, S>),                                                    \
-                           dim3(persistent_grid(per_cu, cdiv(n_pencils, K::TPW))),               \
-                           dim3(K::THREADS), 0, st, src, (const cpx<R>*)tw);                     \
-        break;                                                                                   \
-    }
+    case p:                                                                                      \
+        return detail::go_conv<R, VAR, p>(S{JobConv{data, tensor, n_pencils, P1, N1}, n_pencils}, \
+                                          tw, occ, st);
         FSA_P_LIST(FSA_CASE)
 #undef FSA_CASE
-    default:
-        return hipErrorInvalidValue;
     }
-    return hipGetLastError();
+    return hipErrorInvalidValue;
 }
 
-template <typename R>
-int Launch<R>::items(Pass pass, int len, const void* job) {
+template <typename R, int VAR>
+int LaunchV<R, VAR>::items(Pass pass, int len, const void* job) {
     switch (pass) {
     case Pass::R2C: {
         const JobR2c& j = *(const JobR2c*)job;
         switch (len) {
-#define FSA_CASE(m) case m: return cdiv(j.n_inner, R2c<R, m>::WT) * j.n_outer;
+#define FSA_CASE(m) case m: return cdiv(j.n_inner, R2c<R, m, VAR>::WT) * j.n_outer;
             FSA_M_LIST(FSA_CASE)
 #undef FSA_CASE
         }
@@ -172,7 +226,7 @@ int Launch<R>::items(Pass pass, int len, const void* job) {
     case Pass::C2R: {
         const JobC2r& j = *(const JobC2r*)job;
         switch (len) {
-#define FSA_CASE(m) case m: return cdiv(j.n_inner, C2r<R, m>::WT) * j.n_outer;
+#define FSA_CASE(m) case m: return cdiv(j.n_inner, C2r<R, m, VAR>::WT) * j.n_outer;
             FSA_M_LIST(FSA_CASE)
 #undef FSA_CASE
         }
@@ -184,7 +238,7 @@ int Launch<R>::items(Pass pass, int len, const void* job) {
         switch (len) {
 #define FSA_CASE(p)                                                                              \
     case p:                                                                                      \
-        return cdiv(j.N0, pass == Pass::FWD_T ? FwdT<R, p>::WT : InvT<R, p>::WT) * j.H;
+        return cdiv(j.N0, pass == Pass::FWD_T ? FwdT<R, p, VAR>::WT : InvT<R, p, VAR>::WT) * j.H;
             FSA_P_LIST(FSA_CASE)
 #undef FSA_CASE
         }
@@ -196,93 +250,158 @@ int Launch<R>::items(Pass pass, int len, const void* job) {
     return -1;
 }
 
-template <typename R>
-hipError_t Launch<R>::batch(Pass pass, int len, const void* jobs, const int* start, int n,
-                            int total, const void* tw, const void* tw2, hipStream_t st) {
+template <typename R, int VAR>
+hipError_t LaunchV<R, VAR>::batch(Pass pass, int len, const void* jobs, const int* start, int n,
+                                  int total, const void* tw, const void* tw2, int occ,
+                                  hipStream_t st) {
     if (total <= 0) return hipSuccess;
+    switch (pass) {
+    case Pass::R2C: {
+        using S = JobList<JobR2c>;
+        const S src{(const JobR2c*)jobs, start, n, total};
+        switch (len) {
+#define FSA_CASE(m) case m: return detail::go_r2c<R, VAR, m>(src, tw, tw2, occ, st);
+            FSA_M_LIST(FSA_CASE)
+#undef FSA_CASE
+        }
+        break;
+    }
+    case Pass::C2R: {
+        using S = JobList<JobC2r>;
+        const S src{(const JobC2r*)jobs, start, n, total};
+        switch (len) {
+#define FSA_CASE(m) case m: return detail::go_c2r<R, VAR, m>(src, tw, tw2, occ, st);
+            FSA_M_LIST(FSA_CASE)
+#undef FSA_CASE
+        }
+        break;
+    }
+    case Pass::FWD_T: {
+        using S = JobList<JobT>;
+        const S src{(const JobT*)jobs, start, n, total};
+        switch (len) {
+#define FSA_CASE(p) case p: return detail::go_fwd_t<R, VAR, p>(src, tw, occ, st);
+            FSA_P_LIST(FSA_CASE)
+#undef FSA_CASE
+        }
+        break;
+    }
+    case Pass::INV_T: {
+        using S = JobList<JobT>;
+        const S src{(const JobT*)jobs, start, n, total};
+        switch (len) {
+#define FSA_CASE(p) case p: return detail::go_inv_t<R, VAR, p>(src, tw, occ, st);
+            FSA_P_LIST(FSA_CASE)
+#undef FSA_CASE
+        }
+        break;
+    }
+    case Pass::CONV: {
+        using S = JobList<JobConv>;
+        const S src{(const JobConv*)jobs, start, n, total};
+        switch (len) {
+#define FSA_CASE(p) case p: return detail::go_conv<R, VAR, p>(src, tw, occ, st);
+            FSA_P_LIST(FSA_CASE)
+#undef FSA_CASE
+        }
+        break;
+    }
+    }
+    return hipErrorInvalidValue;
+}
+
+template <typename R, int VAR>
+bool LaunchV<R, VAR>::distinct(Pass pass, int len) {
+    switch (pass) {
+    case Pass::R2C:
+        switch (len) {
+#define FSA_CASE(m) case m: return R2c<R, m, VAR>::DISTINCT;
+            FSA_M_LIST(FSA_CASE)
+#undef FSA_CASE
+        }
+        return false;
+    case Pass::C2R:
+        switch (len) {
+#define FSA_CASE(m) case m: return C2r<R, m, VAR>::DISTINCT;
+            FSA_M_LIST(FSA_CASE)
+#undef FSA_CASE
+        }
+        return false;
+    case Pass::FWD_T:
+        switch (len) {
+#define FSA_CASE(p) case p: return FwdT<R, p, VAR>::DISTINCT;
+            FSA_P_LIST(FSA_CASE)
+#undef FSA_CASE
+        }
+        return false;
+    case Pass::INV_T:
+        switch (len) {
+#define FSA_CASE(p) case p: return InvT<R, p, VAR>::DISTINCT;
+            FSA_P_LIST(FSA_CASE)
+#undef FSA_CASE
+        }
+        return false;
+    case Pass::CONV:
+        switch (len) {
+#define FSA_CASE(p) case p: return Conv<R, p, VAR>::DISTINCT;
+            FSA_P_LIST(FSA_CASE)
+#undef FSA_CASE
+        }
+        return false;
+    }
+    return false;
+}
+
+template <typename R, int VAR>
+int LaunchV<R, VAR>::max_occ(Pass pass, int len) {
     switch (pass) {
     case Pass::R2C:
         switch (len) {
 #define FSA_CASE(m)                                                                              \
-    case m: {                                                                                    \
-        using K = R2c<R, m>;                                                                     \
-        using S = JobList<JobR2c>;                                                               \
-        static const int per_cu = blocks_per_cu(k_r2c<R, m, S>, K::THREADS);                    \
-        const S src{(const JobR2c*)jobs, start, n, total};                                       \
-        hipLaunchKernelGGL((k_r2c<R, m, S>), dim3(persistent_grid(per_cu, total)),              \
-                           dim3(K::THREADS), 0, st, src, (const cpx<R>*)tw, (const cpx<R>*)tw2); \
-        return hipGetLastError();                                                                \
-    }
+    case m:                                                                                      \
+        return detail::occ_r2c<R, VAR, m>();
             FSA_M_LIST(FSA_CASE)
 #undef FSA_CASE
         }
-        break;
+        return 0;
     case Pass::C2R:
         switch (len) {
 #define FSA_CASE(m)                                                                              \
-    case m: {                                                                                    \
-        using K = C2r<R, m>;                                                                     \
-        using S = JobList<JobC2r>;                                                               \
-        static const int per_cu = blocks_per_cu(k_c2r<R, m, S>, K::THREADS);                    \
-        const S src{(const JobC2r*)jobs, start, n, total};                                       \
-        hipLaunchKernelGGL((k_c2r<R, m, S>), dim3(persistent_grid(per_cu, total)),              \
-                           dim3(K::THREADS), 0, st, src, (const cpx<R>*)tw, (const cpx<R>*)tw2); \
-        return hipGetLastError();                                                                \
-    }
+    case m:                                                                                      \
+        return detail::occ_c2r<R, VAR, m>();
             FSA_M_LIST(FSA_CASE)
 #undef FSA_CASE
         }
-        break;
+        return 0;
     case Pass::FWD_T:
         switch (len) {
 #define FSA_CASE(p)                                                                              \
-    case p: {                                                                                    \
-        using K = FwdT<R, p>;                                                                    \
-        using S = JobList<JobT>;                                                                 \
-        static const int per_cu = blocks_per_cu(k_fwd_t<R, p, S>, K::THREADS);                  \
-        const S src{(const JobT*)jobs, start, n, total};                                         \
-        hipLaunchKernelGGL((k_fwd_t<R, p, S>), dim3(persistent_grid(per_cu, total)),            \
-                           dim3(K::THREADS), 0, st, src, (const cpx<R>*)tw);                     \
-        return hipGetLastError();                                                                \
-    }
+    case p:                                                                                      \
+        return detail::occ_fwd_t<R, VAR, p>();
             FSA_P_LIST(FSA_CASE)
 #undef FSA_CASE
         }
-        break;
+        return 0;
     case Pass::INV_T:
         switch (len) {
 #define FSA_CASE(p)                                                                              \
-    case p: {                                                                                    \
-        using K = InvT<R, p>;                                                                    \
-        using S = JobList<JobT>;                                                                 \
-        static const int per_cu = blocks_per_cu(k_inv_t<R, p, S>, K::THREADS);                  \
-        const S src{(const JobT*)jobs, start, n, total};                                         \
-        hipLaunchKernelGGL((k_inv_t<R, p, S>), dim3(persistent_grid(per_cu, total)),            \
-                           dim3(K::THREADS), 0, st, src, (const cpx<R>*)tw);                     \
-        return hipGetLastError();                                                                \
-    }
+    case p:                                                                                      \
+        return detail::occ_inv_t<R, VAR, p>();
             FSA_P_LIST(FSA_CASE)
 #undef FSA_CASE
         }
-        break;
+        return 0;
     case Pass::CONV:
         switch (len) {
 #define FSA_CASE(p)                                                                              \
-    case p: {                                                                                    \
-        using K = Conv<R, p>;                                                                    \
-        using S = JobList<JobConv>;                                                              \
-        static const int per_cu = blocks_per_cu(k_conv<R, p, S>, K::THREADS);                   \
-        const S src{(const JobConv*)jobs, start, n, total};                                      \
-        hipLaunchKernelGGL((k_conv<R, p, S>), dim3(persistent_grid(per_cu, cdiv(total, K::TPW))), \
-                           dim3(K::THREADS), 0, st, src, (const cpx<R>*)tw);                     \
-        return hipGetLastError();                                                                \
-    }
+    case p:                                                                                      \
+        return detail::occ_conv<R, VAR, p>();
             FSA_P_LIST(FSA_CASE)
 #undef FSA_CASE
         }
-        break;
+        return 0;
     }
-    return hipErrorInvalidValue;
+    return 0;
 }
 
 }  // namespace fsa

@@ -49,6 +49,17 @@ constexpr int tile_width(int csize, int T, int scr, int rows, int max_threads = 
 constexpr int cmax(int a, int b) { return a > b ? a : b; }
 constexpr int cdiv(int a, int b) { return (a + b - 1) / b; }
 
+// Compile-time variants of every pass; the autotuner picks one per (pass,
+// transform length, precision) at run time.  0: default.  1: the alternate
+// radix family of make_fft_plan (another radix split and number of threads
+// per transform).  2: half-size workgroups (half the lines per tile, or half
+// the teams per workgroup): less LDS and fewer threads per group, more
+// resident groups per CU.  A variant that comes out identical to variant 0
+// at some length is marked not DISTINCT and never instantiated there.
+constexpr int kVariants = 3;
+constexpr int var_alt(int var) { return var == 1 ? 1 : 0; }
+constexpr int var_cap(int var, int cap) { return var == 2 ? cap / 2 : cap; }
+
 // Workgroup barrier that orders LDS only: global loads in flight (prefetch)
 // and global stores keep flying.
 __device__ __forceinline__ void sync_wg_lds() {
@@ -109,13 +120,13 @@ struct JobList {
 // Work item = (outer, tile of WT rows); team w of the workgroup owns row
 // tile * WT + w.  Persistent, with the next item's rows prefetched.
 // ---------------------------------------------------------------------------
-template <typename R, int M>
+template <typename R, int M, int VAR = 0>
 struct R2c {
-    using F = Fft<R, M, false>;
+    using F = Fft<R, M, false, var_alt(VAR)>;
     using C = cpx<R>;
     static constexpr int T = F::T;
     static constexpr int H = M + 1;
-    static constexpr int WT = tile_width(sizeof(C), T, F::SCR, H, 512);
+    static constexpr int WT = tile_width(sizeof(C), T, F::SCR, H, var_cap(VAR, 512));
     static constexpr int TS = WT + 1;
     static constexpr int LDS = cmax(WT * F::SCR, H * TS);
     static constexpr int THREADS = WT * T;
@@ -123,13 +134,14 @@ struct R2c {
     static constexpr int R0 = F::first_radix(), NB0 = F::first_stride(), NBT0 = F::first_nbt();
     static constexpr int HALF = R0 / 2;
     static_assert(R0 % 2 == 0, "zero half = whole first-stage operands");
+    static constexpr bool DISTINCT =
+        VAR == 0 || (VAR == 1 ? fft_alt_distinct(M) : WT != R2c<R, M, 0>::WT);
 };
 
-template <typename R, int M, class Src>
-__global__ __launch_bounds__((R2c<R, M>::THREADS)) void k_r2c(Src src,
-                                                            const cpx<R>* __restrict__ twM,
-                                                            const cpx<R>* __restrict__ tw2M) {
-    using K = R2c<R, M>;
+template <typename R, int M, int VAR, class Src>
+__global__ __launch_bounds__((R2c<R, M, VAR>::THREADS)) void k_r2c(
+    Src src, const cpx<R>* __restrict__ twM, const cpx<R>* __restrict__ tw2M) {
+    using K = R2c<R, M, VAR>;
     using F = typename K::F;
     using C = cpx<R>;
     __shared__ C lds[K::LDS];
@@ -218,13 +230,13 @@ __global__ __launch_bounds__((R2c<R, M>::THREADS)) void k_r2c(Src src,
 //   in[(outer * (M+1) + k) * n_inner + inner] -> phi row r, first M reals of 2M.
 // Persistent; the next item's tile is prefetched into registers.
 // ---------------------------------------------------------------------------
-template <typename R, int M>
+template <typename R, int M, int VAR = 0>
 struct C2r {
-    using F = Fft<R, M, true>;
+    using F = Fft<R, M, true, var_alt(VAR)>;
     using C = cpx<R>;
     static constexpr int T = F::T;
     static constexpr int H = M + 1;
-    static constexpr int WT = tile_width(sizeof(C), T, F::SCR, H, 512);
+    static constexpr int WT = tile_width(sizeof(C), T, F::SCR, H, var_cap(VAR, 512));
     static constexpr int TS = WT + 1;
     static constexpr int LDS = cmax(WT * F::SCR, H * TS);
     static constexpr int THREADS = WT * T;
@@ -232,13 +244,14 @@ struct C2r {
     // prefetch the next tile into registers only if it fits ~48 VGPRs
     static constexpr bool PREFETCH = NT * (int)(sizeof(C) / 4) <= 48;
     static constexpr int R0 = F::first_radix(), NB0 = F::first_stride(), NBT0 = F::first_nbt();
+    static constexpr bool DISTINCT =
+        VAR == 0 || (VAR == 1 ? fft_alt_distinct(M) : WT != C2r<R, M, 0>::WT);
 };
 
-template <typename R, int M, class Src>
-__global__ __launch_bounds__((C2r<R, M>::THREADS)) void k_c2r(Src src,
-                                                            const cpx<R>* __restrict__ twM,
-                                                            const cpx<R>* __restrict__ tw2M) {
-    using K = C2r<R, M>;
+template <typename R, int M, int VAR, class Src>
+__global__ __launch_bounds__((C2r<R, M, VAR>::THREADS)) void k_c2r(
+    Src src, const cpx<R>* __restrict__ twM, const cpx<R>* __restrict__ tw2M) {
+    using K = C2r<R, M, VAR>;
     using F = typename K::F;
     using C = cpx<R>;
     __shared__ C lds[K::LDS];
@@ -319,24 +332,27 @@ __global__ __launch_bounds__((C2r<R, M>::THREADS)) void k_c2r(Src src,
 //   in[(i0 * H + p2) * N1 + i1] -> out[(p2 * P + p1) * N0 + i0],  P = 2 N1
 // Work item = (p2, tile of WT consecutive i0); persistent with prefetch.
 // ---------------------------------------------------------------------------
-template <typename R, int P>
+template <typename R, int P, int VAR = 0>
 struct FwdT {
-    using F = Fft<R, P, false>;
+    using F = Fft<R, P, false, var_alt(VAR)>;
     using C = cpx<R>;
     static constexpr int T = F::T;
-    static constexpr int WT = tile_width(sizeof(C), T, F::SCR, P, F::V <= 8 ? 1024 : 512);
+    static constexpr int WT =
+        tile_width(sizeof(C), T, F::SCR, P, var_cap(VAR, F::V <= 8 ? 1024 : 512));
     static constexpr int TS = WT + 1;
     static constexpr int LDS = cmax(WT * F::SCR, P * TS);
     static constexpr int THREADS = WT * T;
     static constexpr int R0 = F::first_radix(), NB0 = F::first_stride(), NBT0 = F::first_nbt();
     static constexpr int HALF = R0 / 2;
     static_assert(R0 % 2 == 0, "zero half = whole first-stage operands");
+    static constexpr bool DISTINCT =
+        VAR == 0 || (VAR == 1 ? fft_alt_distinct(P) : WT != FwdT<R, P, 0>::WT);
 };
 
-template <typename R, int P, class Src>
-__global__ __launch_bounds__((FwdT<R, P>::THREADS)) void k_fwd_t(Src src,
-                                                               const cpx<R>* __restrict__ tw) {
-    using K = FwdT<R, P>;
+template <typename R, int P, int VAR, class Src>
+__global__ __launch_bounds__((FwdT<R, P, VAR>::THREADS)) void k_fwd_t(
+    Src src, const cpx<R>* __restrict__ tw) {
+    using K = FwdT<R, P, VAR>;
     using F = typename K::F;
     using C = cpx<R>;
     constexpr int N1 = P / 2;
@@ -395,23 +411,26 @@ __global__ __launch_bounds__((FwdT<R, P>::THREADS)) void k_fwd_t(Src src,
 //   in[(p2 * P + p1) * N0 + i0] -> out[(i0 * H + p2) * N1 + i1], i1 < N1
 // Persistent; the next item's tile is prefetched into registers.
 // ---------------------------------------------------------------------------
-template <typename R, int P>
+template <typename R, int P, int VAR = 0>
 struct InvT {
-    using F = Fft<R, P, true>;
+    using F = Fft<R, P, true, var_alt(VAR)>;
     using C = cpx<R>;
     static constexpr int T = F::T;
-    static constexpr int WT = tile_width(sizeof(C), T, F::SCR, P, F::V <= 8 ? 1024 : 512);
+    static constexpr int WT =
+        tile_width(sizeof(C), T, F::SCR, P, var_cap(VAR, F::V <= 8 ? 1024 : 512));
     static constexpr int TS = WT + 1;
     static constexpr int LDS = cmax(WT * F::SCR, P * TS);
     static constexpr int THREADS = WT * T;
     static constexpr int NT = (P * WT + THREADS - 1) / THREADS;
     static constexpr bool PREFETCH = NT * (int)(sizeof(C) / 4) <= 48;
+    static constexpr bool DISTINCT =
+        VAR == 0 || (VAR == 1 ? fft_alt_distinct(P) : WT != InvT<R, P, 0>::WT);
 };
 
-template <typename R, int P, class Src>
-__global__ __launch_bounds__((InvT<R, P>::THREADS)) void k_inv_t(Src src,
-                                                               const cpx<R>* __restrict__ tw) {
-    using K = InvT<R, P>;
+template <typename R, int P, int VAR, class Src>
+__global__ __launch_bounds__((InvT<R, P, VAR>::THREADS)) void k_inv_t(
+    Src src, const cpx<R>* __restrict__ tw) {
+    using K = InvT<R, P, VAR>;
     using F = typename K::F;
     using C = cpx<R>;
     constexpr int N1 = P / 2;
@@ -488,13 +507,13 @@ __global__ __launch_bounds__((InvT<R, P>::THREADS)) void k_inv_t(Src src,
 // and items are ordered so that the mirror pencils p1 and P1 - p1, which read
 // the same tensor row, follow each other.
 // ---------------------------------------------------------------------------
-template <typename R, int P>
+template <typename R, int P, int VAR = 0>
 struct Conv {
-    using Ff = Fft<R, P, false>;
-    using Fi = Fft<R, P, true>;
+    using Ff = Fft<R, P, false, var_alt(VAR)>;
+    using Fi = Fft<R, P, true, var_alt(VAR)>;
     using C = cpx<R>;
     static constexpr int T = Ff::T;
-    static constexpr int TPW = T >= 256 ? 1 : 256 / T;  // teams per workgroup
+    static constexpr int TPW = cmax(1, var_cap(VAR, 256) / T);  // teams per workgroup
     static constexpr int THREADS = TPW * T;
     static constexpr int LDS = TPW * Ff::SCR;
     static constexpr bool SHARED_TW = Ff::palindromic();
@@ -505,6 +524,8 @@ struct Conv {
     static constexpr int NPF = NBT0 * HALF;
     static_assert(R0 % 2 == 0, "the zero half must be whole first-stage operands");
     static_assert(Ff::last_radix() == Fi::first_radix(), "register hand-off");
+    static constexpr bool DISTINCT =
+        VAR == 0 || (VAR == 1 ? fft_alt_distinct(P) : TPW != Conv<R, P, 0>::TPW);
 };
 
 // work item t -> pencil, ordered (p2; p1 = 0, N1, 1, P1-1, 2, P1-2, ...)
@@ -517,10 +538,10 @@ __device__ __forceinline__ int conv_item_to_pencil(int t, int P1, int N1) {
     return p2 * P1 + p1;
 }
 
-template <typename R, int P, class Src>
-__global__ __launch_bounds__((Conv<R, P>::THREADS)) void k_conv(Src src,
-                                                                const cpx<R>* __restrict__ tw) {
-    using K = Conv<R, P>;
+template <typename R, int P, int VAR, class Src>
+__global__ __launch_bounds__((Conv<R, P, VAR>::THREADS)) void k_conv(
+    Src src, const cpx<R>* __restrict__ tw) {
+    using K = Conv<R, P, VAR>;
     using Ff = typename K::Ff;
     using Fi = typename K::Fi;
     using C = cpx<R>;

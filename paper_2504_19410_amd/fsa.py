@@ -42,8 +42,13 @@ EXPORTS = (
     "fsa_plan_tensor",
     "fsa_server_create", "fsa_server_submit", "fsa_server_poll", "fsa_server_wait",
     "fsa_server_cancel", "fsa_server_stats", "fsa_server_reset_stats", "fsa_server_destroy",
+    "fsa_autotune", "fsa_tune_set", "fsa_tune_get", "fsa_tune_variants", "fsa_tune_save",
+    "fsa_tune_load", "fsa_tune_reset",
     "fsa_last_error",
 )
+
+# fsa_pass: the passes of one evaluation, in execution order for 3D
+PASSES = {"r2c": 0, "fwd_t": 1, "conv": 2, "inv_t": 3, "c2r": 4}
 
 
 class FsaError(RuntimeError):
@@ -96,6 +101,13 @@ def _load():
         "fsa_server_stats": [P, ctypes.POINTER(Stats)],
         "fsa_server_reset_stats": [P],
         "fsa_server_destroy": [P],
+        "fsa_autotune": [P, P, P, P, P, I],
+        "fsa_tune_set": [I, I, I, I, I],
+        "fsa_tune_get": [I, I, I, P, P, P],
+        "fsa_tune_variants": [I, I, I, P],
+        "fsa_tune_save": [ctypes.c_char_p],
+        "fsa_tune_load": [ctypes.c_char_p],
+        "fsa_tune_reset": [],
     }
     for name, args in sigs.items():
         fn = getattr(lib, name)
@@ -214,6 +226,29 @@ class Plan:
     def n_passes(self) -> int:
         return 5 if self.d == 3 else 3
 
+    def passes(self):
+        """(pass name, transform length) of each pass, in execution order."""
+        N = self.N
+        if self.d == 3:
+            return [("r2c", N[2]), ("fwd_t", 2 * N[1]), ("conv", 2 * N[0]),
+                    ("inv_t", 2 * N[1]), ("c2r", N[2])]
+        return [("r2c", N[1]), ("conv", 2 * N[0]), ("c2r", N[1])]
+
+    def autotune(self, rho: Optional[torch.Tensor] = None, reps: int = 10,
+                 stream: Optional[torch.cuda.Stream] = None) -> dict:
+        """Times every launch variant of every pass (``fsa_autotune``) and
+        returns the chosen {(pass, length): (variant, occupancy, us)}."""
+        if rho is None:
+            rho = torch.rand(self.N, dtype=self.dtype, device="cuda")
+        self.check_input(rho)
+        out = torch.empty_like(rho)
+        ws = self.workspace()
+        _check(_lib.fsa_autotune(self._h, ctypes.c_void_p(rho.data_ptr()),
+                                 ctypes.c_void_p(out.data_ptr()),
+                                 ctypes.c_void_p(self._ws_ptr(ws)), _stream_ptr(stream),
+                                 int(reps)))
+        return {(name, n): tune_get(self.precision, name, n) for name, n in self.passes()}
+
     def apply_events(self, rho: torch.Tensor, out: torch.Tensor, events,
                      workspace: Optional[torch.Tensor] = None,
                      stream: Optional[torch.cuda.Stream] = None) -> torch.Tensor:
@@ -269,6 +304,39 @@ def _hip():
                                        ctypes.c_int]
         _hip_lib.hipMemcpy.restype = ctypes.c_int
     return _hip_lib
+
+
+def tune_get(precision: str, pass_name: str, length: int):
+    """(variant, occupancy, us) of one entry of the tuning table."""
+    v, o, us = ctypes.c_int(), ctypes.c_int(), ctypes.c_double()
+    _check(_lib.fsa_tune_get(PRECISIONS[precision], PASSES[pass_name], int(length),
+                             ctypes.byref(v), ctypes.byref(o), ctypes.byref(us)))
+    return v.value, o.value, us.value
+
+
+def tune_set(precision: str, pass_name: str, length: int, variant: int, occupancy: int = 0):
+    _check(_lib.fsa_tune_set(PRECISIONS[precision], PASSES[pass_name], int(length),
+                             int(variant), int(occupancy)))
+
+
+def tune_variants(precision: str, pass_name: str, length: int):
+    """Variants compiled (distinct) at this pass and length."""
+    m = ctypes.c_int()
+    _check(_lib.fsa_tune_variants(PRECISIONS[precision], PASSES[pass_name], int(length),
+                                  ctypes.byref(m)))
+    return [v for v in range(3) if m.value >> v & 1]
+
+
+def tune_save(path: str):
+    _check(_lib.fsa_tune_save(os.fsencode(path)))
+
+
+def tune_load(path: str):
+    _check(_lib.fsa_tune_load(os.fsencode(path)))
+
+
+def tune_reset():
+    _check(_lib.fsa_tune_reset())
 
 
 def batch_workspace_bytes(plans: Sequence[Plan]) -> int:

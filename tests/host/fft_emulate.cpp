@@ -77,10 +77,10 @@ static void emu_run(typename F::C (*v)[F::V], const typename F::C* tw) {
     emu_r_from<F, 1>(v, scr.data(), w);
 }
 
-template <typename R, int P>
+template <typename R, int P, int ALT>
 static int check() {
-    using Ff = Fft<R, P, false>;
-    using Fi = Fft<R, P, true>;
+    using Ff = Fft<R, P, false, ALT>;
+    using Fi = Fft<R, P, true, ALT>;
     static_assert(Ff::T == Fi::T && Ff::V == Fi::V, "same team shape");
     static_assert(Ff::last_radix() == Fi::first_radix(), "register hand-off");
     using C = cpx<R>;
@@ -123,8 +123,8 @@ static int check() {
         }
         const long double tol = (sizeof(R) == 4 ? 2e-6L : 1e-14L) * mag;
         if (!(err <= tol)) {
-            std::printf("FAIL P=%d %s pass=%d err=%Lg mag=%Lg\n", P, sizeof(R) == 4 ? "f32" : "f64",
-                        pass, err, mag);
+            std::printf("FAIL P=%d alt=%d %s pass=%d err=%Lg mag=%Lg\n", P, ALT,
+                        sizeof(R) == 4 ? "f32" : "f64", pass, err, mag);
             ++fails;
         }
     }
@@ -166,16 +166,26 @@ static int check() {
         }
         const long double tol = (sizeof(R) == 4 ? 4e-6L : 2e-14L) * mag;
         if (!(err <= tol)) {
-            std::printf("FAIL P=%d %s fused err=%Lg mag=%Lg\n", P, sizeof(R) == 4 ? "f32" : "f64", err, mag);
+            std::printf("FAIL P=%d alt=%d %s fused err=%Lg mag=%Lg\n", P, ALT,
+                        sizeof(R) == 4 ? "f32" : "f64", err, mag);
             ++fails;
         }
     }
     return fails;
 }
 
+// every length with the default radix family, and with the alternate family
+// where that gives a different transform
+template <typename R, int P>
+static int check_both() {
+    int f = check<R, P, 0>();
+    if constexpr (fft_alt_distinct(P)) f += check<R, P, 1>();
+    return f;
+}
+
 template <typename R, int... Ps>
 static int check_all() {
-    return (check<R, Ps>() + ...);
+    return (check_both<R, Ps>() + ...);
 }
 
 int main() {

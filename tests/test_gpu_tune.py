@@ -1,0 +1,131 @@
+"""The autotuner and every compiled launch variant on the GPU.
+
+Each variant (default; alternate radix family; half-size workgroups) and a
+reduced occupancy must reach the same parity with the FP64 oracle as the
+default path (relative L2 <= 1e-12 FP64, <= 5e-6 FP32); after fsa_autotune the
+tuned path must still match, the batched path must stay bitwise equal to the
+solo path, and a saved table must load back on the same device.
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import oracle as O
+from paper_2504_19410_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"f64": 1e-12, "f32": 5e-6}
+
+
+@pytest.fixture(scope="module")
+def F():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2504_19410_amd import fsa
+    return fsa
+
+
+@pytest.fixture(autouse=True)
+def clean_table(F):
+    F.tune_reset()
+    yield
+    F.tune_reset()
+
+
+def rel_l2(a, b):
+    return float(np.linalg.norm((a - b).ravel()) / np.linalg.norm(b.ravel()))
+
+
+def density(L, N, seed):
+    rng = synth.SplitMix64(seed)
+    gs = synth.draw_gaussians(rng, len(N), 3, [-l / 4 for l in L], [l / 4 for l in L],
+                              [l / 5 for l in L], [l / 3 for l in L], isotropic=False)
+    return synth.eval_gaussians(gs, L, N)
+
+
+# shapes whose pass lengths have alternate-radix and half-workgroup variants
+SHAPES = [
+    ("coulomb3d", (6.0, 8.0, 8.0), (32, 64, 128)),
+    ("yukawa3d", (8.0, 8.0, 4.0), (64, 128, 64)),
+    ("log2d", (10.0, 6.0), (512, 256)),
+    ("log2d", (12.0, 8.0), (1024, 512)),
+]
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("kind,L,N", SHAPES)
+def test_every_variant_matches_the_oracle(F, kind, L, N, prec):
+    lam = 1.0 if kind == "yukawa3d" else None
+    plan = F.Plan(kind, L, N, prec, lam=lam).build()
+    rho = torch.from_numpy(density(L, N, sum(N))).to(F.DTYPES[prec]).cuda()
+    ref = O.solve(kind, L, N, rho.double().cpu().numpy(), eps=plan.eps, lam=lam or 0.0)
+    tried = set()
+    for var in (0, 1, 2):
+        for occ in (0, 1):
+            F.tune_reset()
+            used = []
+            for name, n in plan.passes():
+                v = var if var in F.tune_variants(prec, name, n) else 0
+                F.tune_set(prec, name, n, v, occ)
+                used.append(v)
+            if (tuple(used), occ) in tried:
+                continue
+            tried.add((tuple(used), occ))
+            phi = plan.apply(rho)
+            torch.cuda.synchronize()
+            err = rel_l2(phi.double().cpu().numpy(), ref)
+            print(f"{kind} {N} {prec} variants {used} occ {occ}: rel L2 {err:.3e}")
+            assert err <= TOL[prec], (used, occ, err)
+    assert len(tried) >= 4   # the shapes above exercise non-default variants
+
+
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_autotune_keeps_parity_and_batch_bitwise(F, prec, tmp_path):
+    kind, L, N = "coulomb3d", (6.0, 8.0, 8.0), (32, 64, 128)
+    plan = F.Plan(kind, L, N, prec).build()
+    rho = torch.from_numpy(density(L, N, 7)).to(F.DTYPES[prec]).cuda()
+    table = plan.autotune(rho, reps=3)
+    assert set(table) == set(plan.passes())
+    for (name, n), (v, occ, us) in table.items():
+        assert v in F.tune_variants(prec, name, n)
+        assert us > 0.0
+    phi = plan.apply(rho)
+    torch.cuda.synchronize()
+    ref = O.solve(kind, L, N, rho.double().cpu().numpy(), eps=plan.eps)
+    assert rel_l2(phi.double().cpu().numpy(), ref) <= TOL[prec]
+    # batched path with the tuned choices: bitwise equal to the solo path
+    plan2 = F.Plan("log2d", (8.0, 8.0), (256, 512), prec).build()
+    rho2 = torch.from_numpy(density((8.0, 8.0), (256, 512), 8)).to(F.DTYPES[prec]).cuda()
+    plan2.autotune(rho2, reps=3)
+    solo = [plan.apply(rho), plan2.apply(rho2)]
+    outs = F.apply_batched([plan, plan2], [rho, rho2])
+    torch.cuda.synchronize()
+    for a, b in zip(solo, outs):
+        assert torch.equal(a, b)
+    # the table survives a save / reset / load on this device
+    path = tmp_path / "tune.json"
+    F.tune_save(str(path))
+    before = {k: F.tune_get(prec, *k)[:2] for k in plan.passes()}
+    F.tune_reset()
+    F.tune_load(str(path))
+    assert {k: F.tune_get(prec, *k)[:2] for k in plan.passes()} == before
+
+
+def test_batch_recaptures_after_a_table_change(F):
+    plan = F.Plan("log2d", (8.0, 8.0), (128, 256), "f32").build()
+    rho = torch.from_numpy(density((8.0, 8.0), (128, 256), 9)).float().cuda()
+    ws = torch.empty(F.batch_workspace_bytes([plan]) + 256, dtype=torch.uint8, device="cuda")
+    outs = [torch.empty_like(rho)]
+    a = F.apply_batched([plan], [rho], outs=outs, workspace=ws)[0].clone()
+    # same plans, buffers and workspace: only the table generation changes,
+    # and the replayed graph must follow it
+    F.tune_set("f32", "conv", 256, 1, 0)      # radices 16.16 instead of 8.4.8
+    b = F.apply_batched([plan], [rho], outs=outs, workspace=ws)[0]
+    c = plan.apply(rho)
+    torch.cuda.synchronize()
+    assert torch.equal(b, c)
+    assert not torch.equal(a, b)   # another radix split rounds differently
+    ref = O.solve("log2d", (8.0, 8.0), (128, 256), rho.double().cpu().numpy(), eps=plan.eps)
+    assert rel_l2(a.double().cpu().numpy(), ref) <= TOL["f32"]
+    assert rel_l2(b.double().cpu().numpy(), ref) <= TOL["f32"]

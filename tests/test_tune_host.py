@@ -1,0 +1,90 @@
+"""The autotuner's table without a GPU: set / get / reset, the variants
+compiled per pass and length, and the JSON cache (save, load, rejection of
+malformed or impossible entries).  Timing itself needs the device
+(tests/test_gpu_tune.py)."""
+import json
+
+import pytest
+
+from paper_2504_19410_amd import fsa as F
+
+
+@pytest.fixture(autouse=True)
+def clean_table():
+    F.tune_reset()
+    yield
+    F.tune_reset()
+
+
+def test_defaults_and_set_get():
+    assert F.tune_get("f32", "conv", 512) == (0, 0, 0.0)
+    F.tune_set("f32", "conv", 512, 1, 2)
+    assert F.tune_get("f32", "conv", 512)[:2] == (1, 2)
+    assert F.tune_get("f64", "conv", 512)[:2] == (0, 0)   # per precision
+    F.tune_reset()
+    assert F.tune_get("f32", "conv", 512)[:2] == (0, 0)
+
+
+def test_variant_sets_follow_the_radix_plans():
+    # the alternate radix family differs from the default at these lengths
+    for n in (128, 256, 512, 1024, 2048, 4096):
+        assert 1 in F.tune_variants("f32", "conv", n), n
+    # and falls back to it (so is not compiled) at small lengths
+    for n in (16, 32, 64, 96):
+        assert 1 not in F.tune_variants("f32", "conv", n), n
+    for p in F.PASSES:
+        assert 0 in F.tune_variants("f64", p, 256)
+
+
+def test_rejects_impossible_entries():
+    with pytest.raises(F.FsaError, match="EINVAL"):
+        F.tune_set("f32", "conv", 64, 1)          # variant 1 not compiled at 64
+    with pytest.raises(F.FsaError, match="EINVAL"):
+        F.tune_set("f32", "conv", 100, 0)         # unsupported length
+    with pytest.raises(F.FsaError, match="EINVAL"):
+        F.tune_set("f32", "r2c", 4096, 0)         # real passes stop at 2048
+    with pytest.raises(F.FsaError, match="EINVAL"):
+        F.tune_set("f32", "conv", 512, 0, -1)     # negative occupancy
+
+
+def test_save_load_roundtrip(tmp_path):
+    F.tune_set("f32", "conv", 512, 1, 0)
+    F.tune_set("f32", "fwd_t", 512, 2, 1)
+    F.tune_set("f32", "c2r", 1024, 1, 3)
+    path = tmp_path / "tune.json"
+    F.tune_save(str(path))
+    doc = json.loads(path.read_text())
+    assert doc["format"] == "fsa-tune-1"
+    assert len(doc["entries"]) == 3
+    F.tune_reset()
+    F.tune_load(str(path))
+    assert F.tune_get("f32", "conv", 512)[:2] == (1, 0)
+    assert F.tune_get("f32", "fwd_t", 512)[:2] == (2, 1)
+    assert F.tune_get("f32", "c2r", 1024)[:2] == (1, 3)
+
+
+@pytest.mark.parametrize("text", [
+    "",
+    "{",
+    '{"format": "other", "arch": "", "entries": []}',
+    '{"format": "fsa-tune-1", "arch": "", "entries": [{"precision": "f32", "pass": "conv", '
+    '"length": 64, "variant": 1, "occupancy": 0, "us": 1.0}]}',
+    '{"format": "fsa-tune-1", "arch": "", "entries": [{"precision": "f16", "pass": "conv", '
+    '"length": 512, "variant": 0, "occupancy": 0, "us": 1.0}]}',
+    '{"format": "fsa-tune-1", "arch": "", "entries": [{"precision": "f32", "pass": "conv", '
+    '"length": 512.5, "variant": 0, "occupancy": 0, "us": 1.0}]}',
+    '{"format": "fsa-tune-1", "arch": "", "entries": [{"precision": "f32", "pass": "conv", '
+    '"length": 1e300, "variant": 0, "occupancy": 0, "us": 1.0}]}',
+])
+def test_load_rejects_bad_files_as_a_whole(tmp_path, text):
+    F.tune_set("f32", "conv", 512, 1, 0)
+    path = tmp_path / "bad.json"
+    path.write_text(text)
+    with pytest.raises(F.FsaError, match="EINVAL"):
+        F.tune_load(str(path))
+    assert F.tune_get("f32", "conv", 512)[:2] == (1, 0)   # table untouched
+
+
+def test_load_missing_file():
+    with pytest.raises(F.FsaError, match="EINVAL"):
+        F.tune_load("/nonexistent/tune.json")
