@@ -100,9 +100,10 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(kernel, prec):
-    """HBM bytes per launch from the committed rocprofv3 counter summary, if it
-    was taken on the current kernel sources; else None."""
+def measured_traffic(key):
+    """HBM bytes per launch of one kernel instance (key: pass_prec_len_vVAR)
+    from the committed rocprofv3 counter summary, if it was taken on the
+    current kernel sources; else None."""
     path = os.path.join(ROOT, "profiles", "traffic_counters.json")
     if not os.path.exists(path):
         return None
@@ -111,7 +112,7 @@ def measured_traffic(kernel, prec):
             d = json.load(f)
         if d.get("kernel_source_hash") != kernel_source_hash():
             return None
-        ent = d["kernels"][f"{kernel}_{prec}"]
+        ent = d["kernels"][key]
         return int(ent["fetch_bytes"] + ent["write_bytes"])
     except Exception:
         return None
@@ -171,7 +172,10 @@ def bench_precision(F, torch, hip, prob, rho64, prec, steps, warmup, tune=True):
     mb = model_bytes(prob.N, prec)
     dom = max(pass_ms, key=pass_ms.get)
     achieved = mb[dom] / (pass_ms[dom] * 1e-3)
-    traffic = measured_traffic(dom, prec)
+    dom_pass, dom_len = plan.passes()[names.index(dom)]
+    dom_var = F.tune_get(prec, dom_pass, dom_len)[0]
+    dom_key = f"{dom_pass}_{prec}_{dom_len}_v{dom_var}"
+    traffic = measured_traffic(dom_key)
     return {
         "value": pts / (ms * 1e-3),
         "ms_per_step": ms,
@@ -190,6 +194,7 @@ def bench_precision(F, torch, hip, prob, rho64, prec, steps, warmup, tune=True):
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_BPS,
             "traffic": traffic,
+            "instance": dom_key,
             "algorithmic_bytes": mb[dom],
             "avg_launch_ms": pass_ms[dom],
         },
