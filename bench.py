@@ -134,7 +134,12 @@ def bench_precision(F, torch, hip, prob, rho64, prec, steps, warmup, tune=True):
     out = torch.empty_like(rho)
     ws = plan.workspace()
     # launch choices per pass from the autotuner (untimed, before warm-up)
-    tuned = plan.autotune(rho, reps=5) if tune else {}
+    if tune:
+        tuned = plan.autotune(rho, reps=5)
+    else:   # report the table in force (defaults, or a loaded one)
+        tuned = {(name, n): F.tune_get(prec, name, n) for name, n in plan.passes()}
+        if plan.d == 3:
+            tuned[("slabs", 0)] = F.tune_get_slabs(prec, plan.N)
     for _ in range(warmup):
         plan.apply(rho, out, ws)
     torch.cuda.synchronize()
@@ -147,17 +152,22 @@ def bench_precision(F, torch, hip, prob, rho64, prec, steps, warmup, tune=True):
     total_ms = hip.ms(e0, e1)
     torch.cuda.synchronize()
     wall_ms = (time.perf_counter() - t0) * 1e3
-    # per-pass durations: the same K evaluations with events around each pass
-    npass = plan.n_passes
-    evs = [[hip.event() for _ in range(npass + 1)] for _ in range(steps)]
+    # per-pass durations: the same K evaluations with events around each
+    # launch (the 3D middle passes launch once per slab of the schedule)
+    launches = plan.launches()
+    evs = [[hip.event() for _ in range(len(launches) + 1)] for _ in range(steps)]
     for k in range(steps):
         plan.apply_events(rho, out, evs[k], ws)
     torch.cuda.synchronize()
     names = PASS_NAMES_3D if plan.d == 3 else PASS_NAMES_2D
+    by_short = {n.split("_", 1)[1]: n for n in names}
     pass_ms = {n: 0.0 for n in names}
+    pass_launches = {n: 0 for n in names}
+    for i, ln in enumerate(launches):
+        pass_launches[by_short[ln]] += 1
     for k in range(steps):
-        for i, n in enumerate(names):
-            pass_ms[n] += hip.ms(evs[k][i], evs[k][i + 1]) / steps
+        for i, ln in enumerate(launches):
+            pass_ms[by_short[ln]] += hip.ms(evs[k][i], evs[k][i + 1]) / steps
     for row in evs:
         for e in row:
             hip.destroy(e)
@@ -171,6 +181,8 @@ def bench_precision(F, torch, hip, prob, rho64, prec, steps, warmup, tune=True):
         pts *= n
     mb = model_bytes(prob.N, prec)
     dom = max(pass_ms, key=pass_ms.get)
+    # per launch: the pass's bytes and time split over its launches
+    nl = pass_launches[dom]
     achieved = mb[dom] / (pass_ms[dom] * 1e-3)
     dom_pass, dom_len = plan.passes()[names.index(dom)]
     dom_var = F.tune_get(prec, dom_pass, dom_len)[0]
@@ -182,8 +194,11 @@ def bench_precision(F, torch, hip, prob, rho64, prec, steps, warmup, tune=True):
         "wall_ms_per_step": wall_ms / steps,
         "precomp_ms": precomp_ms,
         "pass_ms": {k: round(v, 5) for k, v in pass_ms.items()},
-        "tuned": {f"{name}_{n}": {"variant": v, "occupancy": o, "us": round(us, 2)}
-                  for (name, n), (v, o, us) in tuned.items()},
+        "tuned": {(f"{name}_{n}" if name != "slabs" else "slabs"):
+                  ({"variant": t[0], "occupancy": t[1], "us": round(t[2], 2)} if name != "slabs"
+                   else {"slabs": t[0], "us": round(t[1], 2)})
+                  for (name, n), t in tuned.items()},
+        "launches_per_step": len(launches),
         "model_bytes_per_step": sum(mb.values()),
         "model_hbm_frac": sum(mb.values()) / (ms * 1e-3) / HBM_PEAK_BPS,
         "roofline": {
@@ -193,10 +208,11 @@ def bench_precision(F, torch, hip, prob, rho64, prec, steps, warmup, tune=True):
             "peak": HBM_PEAK_BPS / 1e9,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_BPS,
-            "traffic": traffic,
+            "traffic": None if traffic is None or nl != 1 else traffic,
             "instance": dom_key,
-            "algorithmic_bytes": mb[dom],
-            "avg_launch_ms": pass_ms[dom],
+            "launches_per_step": nl,
+            "algorithmic_bytes": mb[dom] / nl,
+            "avg_launch_ms": pass_ms[dom] / nl,
         },
     }, phi
 
@@ -463,6 +479,10 @@ def main():
     ap.add_argument("--serve-seconds", type=float, default=3.0)
     ap.add_argument("--no-tune", action="store_true",
                     help="skip the autotuner (every pass at its default launch variant)")
+    ap.add_argument("--tune-file", default=None,
+                    help="load this saved tuning table instead of autotuning")
+    ap.add_argument("--save-tune", default=None,
+                    help="save the tuning table to this path at the end")
     ap.add_argument("--copy-only", action="store_true",
                     help="only run the 1 GiB device copy (counter calibration)")
     args = ap.parse_args()
@@ -480,6 +500,9 @@ def main():
         print("bench.py: no GPU visible", file=sys.stderr)
         sys.exit(3)
     torch.cuda.set_device(0)
+    if args.tune_file:
+        F.tune_load(args.tune_file)
+        args.no_tune = True
     hip = Hip()
     copy_bps = stream_copy(torch, hip)
     log(f"stream copy (1 GiB): {copy_bps / 1e9:.0f} GB/s")
@@ -577,6 +600,8 @@ def main():
         "paper_context": "FSA Execution 2.24 s / Precomp 2.84 s at 192^3 in FP64, FORTRAN on one "
                          "Xeon Gold 6248R 3.0 GHz (Table 3); other hardware, context only",
     }
+    if args.save_tune:
+        F.tune_save(args.save_tune)
     print(json.dumps(line), flush=True)
 
 

@@ -130,12 +130,18 @@ fsa_status fsa_build_tensor(fsa_plan plan, void* stream);
  * FSA_ESTATE if the tensor has not been built. */
 fsa_status fsa_apply(fsa_plan plan, const void* rho, void* phi, void* workspace, void* stream);
 
+/* Number of kernel launches of one evaluation with the plan's current
+ * schedule (3 in 2D; 2 + 3 x slabs in 3D, see fsa_tune_set_slabs) and, if
+ * `passes` is not NULL, the fsa_pass of each launch in order (cap entries
+ * available). */
+fsa_status fsa_plan_launches(fsa_plan plan, int* n, int* passes, int cap);
+
 /* Profiling variant of fsa_apply: the same kernels on the same stream, plus
- * hipEventRecord(events[i], stream) before pass i and of events[n_passes]
- * after the last pass, so a caller can time every pass with
- * hipEventElapsedTime.  The events are hipEvent_t handles created by the
- * caller; n_events must equal n_passes + 1 = 6 (3D: passes A-E) or 4 (2D:
- * passes A, C, E).  For profiling tools and benchmarks. */
+ * hipEventRecord(events[i], stream) before launch i and of events[n] after
+ * the last launch (n from fsa_plan_launches), so a caller can time every
+ * launch with hipEventElapsedTime.  The events are hipEvent_t handles created
+ * by the caller; n_events must equal n + 1.  For profiling tools and
+ * benchmarks. */
 fsa_status fsa_apply_events(fsa_plan plan, const void* rho, void* phi, void* workspace,
                             void* stream, void* const* events, int n_events);
 
@@ -203,7 +209,9 @@ typedef enum {
 
 /* Times every distinct (variant, occupancy) candidate of every pass of a
  * built plan on `stream` with hipEvents (median of `reps`, 1..1000, after
- * one warm-up each) and stores the fastest in the table.  Synchronous.
+ * one warm-up each) and stores the fastest in the table; for a 3D plan then
+ * times the slab schedules (fsa_tune_set_slabs) and keeps the fastest.
+ * Synchronous.
  *   rho, phi, workspace  device buffers as for fsa_apply; on return phi holds
  *                        a valid evaluation of rho with the tuned choices.
  * Batch graphs captured before the call are re-captured on their next use. */
@@ -217,6 +225,15 @@ fsa_status fsa_autotune(fsa_plan plan, const void* rho, void* phi, void* workspa
 fsa_status fsa_tune_set(int precision, int pass, int length, int variant, int occupancy);
 fsa_status fsa_tune_get(int precision, int pass, int length, int* variant, int* occupancy,
                         double* us);
+/* Schedule of a 3D grid: passes B, C, D run in `slabs` (1..16) slabs of the
+ * bins p2 of the last axis, B-C-D of one slab back to back, so that the slab's
+ * spectrum can stay in the device's memory-side cache between them (slabs = 1:
+ * each pass over the whole grid).  Same results for every slab count.
+ * N: the three grid lengths.  fsa_autotune times 1, 2, 4, 8, 16 slabs after
+ * tuning the passes.  `us` (may be NULL) receives the measured evaluation
+ * time of the chosen schedule (0 if set by hand or untuned). */
+fsa_status fsa_tune_set_slabs(int precision, const int64_t* N, int slabs);
+fsa_status fsa_tune_get_slabs(int precision, const int64_t* N, int* slabs, double* us);
 /* Bit mask of the variants that exist at (precision, pass, length). */
 fsa_status fsa_tune_variants(int precision, int pass, int length, int* mask);
 /* Writes the table as JSON (format "fsa-tune-1", tagged with the device's

@@ -211,8 +211,8 @@ void pass_of(const fsa_plan_s* pl, int k, Pass* pass, int* len) {
 }
 
 template <typename R>
-static hipError_t launch_pass_t(const fsa_plan_s* pl, int k, const void* rho, void* phi,
-                                void* ws, Choice c, hipStream_t st) {
+static hipError_t launch_pass_t(const fsa_plan_s* pl, int k, int lo, int n, const void* rho,
+                                void* phi, void* ws, Choice c, hipStream_t st) {
     const char* tw = (const char*)pl->twiddles;
     const size_t cs = pl->csize;
     const void* tw_p0 = tw + pl->tw_off_p0 * cs;
@@ -228,42 +228,69 @@ static hipError_t launch_pass_t(const fsa_plan_s* pl, int k, const void* rho, vo
         char* w2 = w1 + ((pl->ws1_elems * cs + 255) & ~size_t(255));
         switch (k) {
         case 0: return Launch<R>::r2c(N2, (const R*)rho, w1, N0, N1, tw_m, tw_pl, c, st);
-        case 1: return Launch<R>::fwd_t(2 * N1, w1, w2, N0, H, tw_p1, c, st);
-        case 2: return Launch<R>::conv(2 * N0, w2, tensor, H * 2 * N1, 2 * N1, N1, tw_p0, c, st);
-        case 3: return Launch<R>::inv_t(2 * N1, w2, w1, N0, H, tw_p1, c, st);
+        case 1: return Launch<R>::fwd_t(2 * N1, w1, w2, N0, H, lo, n, tw_p1, c, st);
+        case 2:
+            return Launch<R>::conv(2 * N0, w2, tensor, n * 2 * N1, 2 * N1, N1, lo, tw_p0, c, st);
+        case 3: return Launch<R>::inv_t(2 * N1, w2, w1, N0, H, lo, n, tw_p1, c, st);
         case 4: return Launch<R>::c2r(N2, w1, (R*)phi, N0, N1, tw_m, tw_pl, c, st);
         }
     } else {
         switch (k) {
         case 0: return Launch<R>::r2c(N1, (const R*)rho, w1, 1, N0, tw_m, tw_pl, c, st);
-        case 1: return Launch<R>::conv(2 * N0, w1, tensor, H, 1, 0, tw_p0, c, st);
+        case 1: return Launch<R>::conv(2 * N0, w1, tensor, H, 1, 0, 0, tw_p0, c, st);
         case 2: return Launch<R>::c2r(N1, w1, (R*)phi, 1, N0, tw_m, tw_pl, c, st);
         }
     }
     return hipErrorInvalidValue;
 }
 
-hipError_t launch_pass(const fsa_plan_s* pl, int k, const void* rho, void* phi, void* ws,
+hipError_t launch_step(const fsa_plan_s* pl, const Step& s, const void* rho, void* phi, void* ws,
                        Choice c, hipStream_t st) {
-    return pl->prec == FSA_F32 ? launch_pass_t<float>(pl, k, rho, phi, ws, c, st)
-                               : launch_pass_t<double>(pl, k, rho, phi, ws, c, st);
+    return pl->prec == FSA_F32
+               ? launch_pass_t<float>(pl, s.k, s.lo, s.n, rho, phi, ws, c, st)
+               : launch_pass_t<double>(pl, s.k, s.lo, s.n, rho, phi, ws, c, st);
 }
 
-// Enqueues the 3 (2D) or 5 (3D) passes of one evaluation with the tuned
-// launch choices; with events, records ev[k] before pass k and one more at
-// the end.
+int schedule(const fsa_plan_s* pl, int slabs, Step* out) {
+    int m = 0;
+    const int H = (int)pl->H;
+    if (pl->d != 3) {
+        for (int k = 0; k < 3; ++k) out[m++] = Step{k, 0, H};
+        return m;
+    }
+    if (slabs < 1) slabs = 1;
+    if (slabs > kMaxSlabs) slabs = kMaxSlabs;
+    if (slabs > H) slabs = H;
+    out[m++] = Step{0, 0, H};
+    for (int c = 0; c < slabs; ++c) {
+        const int lo = (int)((long)H * c / slabs), hi = (int)((long)H * (c + 1) / slabs);
+        for (int k = 1; k <= 3; ++k) out[m++] = Step{k, lo, hi - lo};
+    }
+    out[m++] = Step{4, 0, H};
+    return m;
+}
+
+Choice step_choice(const fsa_plan_s* pl, const Step& s) {
+    Pass pass;
+    int len;
+    pass_of(pl, s.k, &pass, &len);
+    return tune::get(pl->prec, pass, len);
+}
+
+// Enqueues one evaluation: pass A, then passes B, C, D per slab of bins p2
+// (3D; the slab count is the tuned schedule of the grid), then pass E, each
+// with its tuned launch choice.  With events, records ev[i] before launch i
+// and one more after the last.
 static hipError_t apply_impl(const fsa_plan_s* pl, const void* rho, void* phi, void* ws,
                              hipStream_t st, hipEvent_t const* ev) {
-    const int np = n_passes(pl);
+    Step steps[kMaxSteps];
+    const int ns = schedule(pl, tune::get_slabs(pl), steps);
     hipError_t e = hipSuccess;
-    for (int k = 0; k < np && e == hipSuccess; ++k) {
-        if (ev) e = hipEventRecord(ev[k], st);
-        Pass pass;
-        int len;
-        pass_of(pl, k, &pass, &len);
-        if (e == hipSuccess) e = launch_pass(pl, k, rho, phi, ws, tune::get(pl->prec, pass, len), st);
+    for (int i = 0; i < ns && e == hipSuccess; ++i) {
+        if (ev) e = hipEventRecord(ev[i], st);
+        if (e == hipSuccess) e = launch_step(pl, steps[i], rho, phi, ws, step_choice(pl, steps[i]), st);
     }
-    if (e == hipSuccess && ev) e = hipEventRecord(ev[np], st);
+    if (e == hipSuccess && ev) e = hipEventRecord(ev[ns], st);
     return e;
 }
 
@@ -301,13 +328,31 @@ fsa_status fsa_apply(fsa_plan pl, const void* rho, void* phi, void* workspace, v
     return apply_checked(pl, rho, phi, workspace, stream, nullptr);
 }
 
+fsa_status fsa_plan_launches(fsa_plan pl, int* n, int* passes, int cap) {
+    if (!pl || !n) return fail(FSA_EINVAL, "fsa_plan_launches: null argument");
+    fsa::Step steps[fsa::kMaxSteps];
+    const int ns = fsa::schedule(pl, fsa::tune::get_slabs(pl), steps);
+    if (passes) {
+        if (cap < ns) return fail(FSA_EINVAL, "fsa_plan_launches: need room for %d entries", ns);
+        for (int i = 0; i < ns; ++i) {
+            fsa::Pass pass;
+            int len;
+            fsa::pass_of(pl, steps[i].k, &pass, &len);
+            passes[i] = (int)pass;
+        }
+    }
+    *n = ns;
+    return FSA_OK;
+}
+
 fsa_status fsa_apply_events(fsa_plan pl, const void* rho, void* phi, void* workspace,
                             void* stream, void* const* events, int n_events) {
     if (!pl || !events) return fail(FSA_EINVAL, "fsa_apply_events: null argument");
-    const int need = (pl->d == 3 ? 5 : 3) + 1;
+    fsa::Step steps[fsa::kMaxSteps];
+    const int need = fsa::schedule(pl, fsa::tune::get_slabs(pl), steps) + 1;
     if (n_events != need)
-        return fail(FSA_EINVAL, "fsa_apply_events: need %d events for a %dD plan, got %d", need,
-                    pl->d, n_events);
+        return fail(FSA_EINVAL, "fsa_apply_events: need %d events (launches + 1), got %d", need,
+                    n_events);
     for (int i = 0; i < need; ++i)
         if (!events[i]) return fail(FSA_EINVAL, "fsa_apply_events: null event %d", i);
     return apply_checked(pl, rho, phi, workspace, stream, (hipEvent_t const*)events);

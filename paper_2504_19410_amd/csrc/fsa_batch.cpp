@@ -117,14 +117,14 @@ fsa_status build_entry(int n, const fsa_plan* plans, const void* const* rho, voi
         if (pl->d == 3) {
             const int N2 = (int)pl->N[2];
             ok = add(fsa::JobR2c{rho[i], w1, N0, N1}, fsa::Pass::R2C, N2, tw_m, tw_pl) &&
-                 add(fsa::JobT{w1, w2, N0, H}, fsa::Pass::FWD_T, 2 * N1, tw_p1, nullptr) &&
-                 add(fsa::JobConv{w2, pl->tensor, H * 2 * N1, 2 * N1, N1}, fsa::Pass::CONV,
+                 add(fsa::JobT{w1, w2, N0, H, 0, H}, fsa::Pass::FWD_T, 2 * N1, tw_p1, nullptr) &&
+                 add(fsa::JobConv{w2, pl->tensor, H * 2 * N1, 2 * N1, N1, 0}, fsa::Pass::CONV,
                      2 * N0, tw_p0, nullptr) &&
-                 add(fsa::JobT{w2, w1, N0, H}, fsa::Pass::INV_T, 2 * N1, tw_p1, nullptr) &&
+                 add(fsa::JobT{w2, w1, N0, H, 0, H}, fsa::Pass::INV_T, 2 * N1, tw_p1, nullptr) &&
                  add(fsa::JobC2r{w1, phi[i], N0, N1}, fsa::Pass::C2R, N2, tw_m, tw_pl);
         } else {
             ok = add(fsa::JobR2c{rho[i], w1, 1, N0}, fsa::Pass::R2C, N1, tw_m, tw_pl) &&
-                 add(fsa::JobConv{w1, pl->tensor, H, 1, 0}, fsa::Pass::CONV, 2 * N0, tw_p0,
+                 add(fsa::JobConv{w1, pl->tensor, H, 1, 0, 0}, fsa::Pass::CONV, 2 * N0, tw_p0,
                      nullptr) &&
                  add(fsa::JobC2r{w1, phi[i], 1, N0}, fsa::Pass::C2R, N1, tw_m, tw_pl);
         }

@@ -57,12 +57,12 @@ struct LaunchV {
                           const void* twM, const void* tw2M, int occ, hipStream_t st);
     static hipError_t c2r(int M, const void* in, R* phi, int n_outer, int n_inner,
                           const void* twM, const void* tw2M, int occ, hipStream_t st);
-    static hipError_t fwd_t(int P, const void* in, void* out, int N0, int H, const void* tw,
-                            int occ, hipStream_t st);
-    static hipError_t inv_t(int P, const void* in, void* out, int N0, int H, const void* tw,
-                            int occ, hipStream_t st);
+    static hipError_t fwd_t(int P, const void* in, void* out, int N0, int H, int p2_lo, int p2_n,
+                            const void* tw, int occ, hipStream_t st);
+    static hipError_t inv_t(int P, const void* in, void* out, int N0, int H, int p2_lo, int p2_n,
+                            const void* tw, int occ, hipStream_t st);
     static hipError_t conv(int P, void* data, const R* tensor, int n_pencils, int P1, int N1,
-                           const void* tw, int occ, hipStream_t st);
+                           int p2_lo, const void* tw, int occ, hipStream_t st);
     // Work items of one job of `pass` at transform length `len` (-1: unsupported).
     static int items(Pass pass, int len, const void* job);
     // One persistent launch of `pass` over n jobs (device table `jobs` of the
@@ -94,17 +94,17 @@ struct Launch {
                           const void* twM, const void* tw2M, Choice c, hipStream_t st) {
         FSA_DISPATCH(c2r(M, in, phi, n_outer, n_inner, twM, tw2M, c.occ, st))
     }
-    static hipError_t fwd_t(int P, const void* in, void* out, int N0, int H, const void* tw,
-                            Choice c, hipStream_t st) {
-        FSA_DISPATCH(fwd_t(P, in, out, N0, H, tw, c.occ, st))
+    static hipError_t fwd_t(int P, const void* in, void* out, int N0, int H, int p2_lo, int p2_n,
+                            const void* tw, Choice c, hipStream_t st) {
+        FSA_DISPATCH(fwd_t(P, in, out, N0, H, p2_lo, p2_n, tw, c.occ, st))
     }
-    static hipError_t inv_t(int P, const void* in, void* out, int N0, int H, const void* tw,
-                            Choice c, hipStream_t st) {
-        FSA_DISPATCH(inv_t(P, in, out, N0, H, tw, c.occ, st))
+    static hipError_t inv_t(int P, const void* in, void* out, int N0, int H, int p2_lo, int p2_n,
+                            const void* tw, Choice c, hipStream_t st) {
+        FSA_DISPATCH(inv_t(P, in, out, N0, H, p2_lo, p2_n, tw, c.occ, st))
     }
     static hipError_t conv(int P, void* data, const R* tensor, int n_pencils, int P1, int N1,
-                           const void* tw, Choice c, hipStream_t st) {
-        FSA_DISPATCH(conv(P, data, tensor, n_pencils, P1, N1, tw, c.occ, st))
+                           int p2_lo, const void* tw, Choice c, hipStream_t st) {
+        FSA_DISPATCH(conv(P, data, tensor, n_pencils, P1, N1, p2_lo, tw, c.occ, st))
     }
     static hipError_t batch(Pass pass, int len, const void* jobs, const int* start, int n,
                             int total, const void* tw, const void* tw2, Choice c,
@@ -148,13 +148,29 @@ void set(fsa_precision prec, Pass pass, int len, Choice c, double us);
 uint64_t generation();
 }  // namespace tune
 
-// Enqueues pass `k` (0-based, in execution order) of one evaluation with an
-// explicit choice; the apply path calls it with the tuned choices.
-hipError_t launch_pass(const fsa_plan_s* pl, int k, const void* rho, void* phi, void* ws,
+// One launch of an evaluation: pass k (0-based, in execution order) over
+// the bins p2 in [lo, lo + n) (passes B, C, D of a 3D plan; the other passes
+// cover everything).
+struct Step {
+    int k, lo, n;
+};
+constexpr int kMaxSlabs = 16;
+constexpr int kMaxSteps = 2 + 3 * kMaxSlabs;
+// Launch order of one evaluation with `slabs` slabs of bins (clamped to
+// [1, min(H, kMaxSlabs)]; 2D plans always have 3 launches).
+int schedule(const fsa_plan_s* pl, int slabs, Step* out);
+hipError_t launch_step(const fsa_plan_s* pl, const Step& s, const void* rho, void* phi, void* ws,
                        Choice c, hipStream_t st);
+Choice step_choice(const fsa_plan_s* pl, const Step& s);
 // (pass kind, transform length) of pass k of a plan.
 void pass_of(const fsa_plan_s* pl, int k, Pass* pass, int* len);
 int n_passes(const fsa_plan_s* pl);
+
+namespace tune {
+// Slabs of the schedule for the plan's (precision, grid); 1 unless tuned.
+int get_slabs(const fsa_plan_s* pl);
+void set_slabs(const fsa_plan_s* pl, int slabs, double us);
+}  // namespace tune
 
 }  // namespace fsa
 

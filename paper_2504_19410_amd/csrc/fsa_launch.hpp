@@ -167,14 +167,15 @@ hipError_t LaunchV<R, VAR>::c2r(int M, const void* in, R* phi, int n_outer, int 
 }
 
 template <typename R, int VAR>
-hipError_t LaunchV<R, VAR>::fwd_t(int P, const void* in, void* out, int N0, int H,
-                                  const void* tw, int occ, hipStream_t st) {
+hipError_t LaunchV<R, VAR>::fwd_t(int P, const void* in, void* out, int N0, int H, int p2_lo,
+                                  int p2_n, const void* tw, int occ, hipStream_t st) {
     using S = JobOne<JobT>;
     switch (P) {
 #define FSA_CASE(p)                                                                              \
     case p:                                                                                      \
         return detail::go_fwd_t<R, VAR, p>(                                                      \
-            S{JobT{in, out, N0, H}, cdiv(N0, FwdT<R, p, VAR>::WT) * H}, tw, occ, st);
+            S{JobT{in, out, N0, H, p2_lo, p2_n}, cdiv(N0, FwdT<R, p, VAR>::WT) * p2_n}, tw, occ,  \
+            st);
         FSA_P_LIST(FSA_CASE)
 #undef FSA_CASE
     }
@@ -182,14 +183,15 @@ hipError_t LaunchV<R, VAR>::fwd_t(int P, const void* in, void* out, int N0, int 
 }
 
 template <typename R, int VAR>
-hipError_t LaunchV<R, VAR>::inv_t(int P, const void* in, void* out, int N0, int H,
-                                  const void* tw, int occ, hipStream_t st) {
+hipError_t LaunchV<R, VAR>::inv_t(int P, const void* in, void* out, int N0, int H, int p2_lo,
+                                  int p2_n, const void* tw, int occ, hipStream_t st) {
     using S = JobOne<JobT>;
     switch (P) {
 #define FSA_CASE(p)                                                                              \
     case p:                                                                                      \
         return detail::go_inv_t<R, VAR, p>(                                                      \
-            S{JobT{in, out, N0, H}, cdiv(N0, InvT<R, p, VAR>::WT) * H}, tw, occ, st);
+            S{JobT{in, out, N0, H, p2_lo, p2_n}, cdiv(N0, InvT<R, p, VAR>::WT) * p2_n}, tw, occ,  \
+            st);
         FSA_P_LIST(FSA_CASE)
 #undef FSA_CASE
     }
@@ -198,13 +200,13 @@ hipError_t LaunchV<R, VAR>::inv_t(int P, const void* in, void* out, int N0, int 
 
 template <typename R, int VAR>
 hipError_t LaunchV<R, VAR>::conv(int P, void* data, const R* tensor, int n_pencils, int P1,
-                                 int N1, const void* tw, int occ, hipStream_t st) {
+                                 int N1, int p2_lo, const void* tw, int occ, hipStream_t st) {
     using S = JobOne<JobConv>;
     switch (P) {
 #define FSA_CASE(p)                                                                              \
     case p:                                                                                      \
-        return detail::go_conv<R, VAR, p>(S{JobConv{data, tensor, n_pencils, P1, N1}, n_pencils}, \
-                                          tw, occ, st);
+        return detail::go_conv<R, VAR, p>(                                                       \
+            S{JobConv{data, tensor, n_pencils, P1, N1, p2_lo}, n_pencils}, tw, occ, st);
         FSA_P_LIST(FSA_CASE)
 #undef FSA_CASE
     }
@@ -238,7 +240,8 @@ int LaunchV<R, VAR>::items(Pass pass, int len, const void* job) {
         switch (len) {
 #define FSA_CASE(p)                                                                              \
     case p:                                                                                      \
-        return cdiv(j.N0, pass == Pass::FWD_T ? FwdT<R, p, VAR>::WT : InvT<R, p, VAR>::WT) * j.H;
+        return cdiv(j.N0, pass == Pass::FWD_T ? FwdT<R, p, VAR>::WT : InvT<R, p, VAR>::WT) *     \
+               j.p2_n;
             FSA_P_LIST(FSA_CASE)
 #undef FSA_CASE
         }

@@ -330,7 +330,8 @@ __global__ __launch_bounds__((C2r<R, M, VAR>::THREADS)) void k_c2r(
 // ---------------------------------------------------------------------------
 // Pass B (3D): zero-pad + forward C2C along axis 1, contiguous in, transposed out
 //   in[(i0 * H + p2) * N1 + i1] -> out[(p2 * P + p1) * N0 + i0],  P = 2 N1
-// Work item = (p2, tile of WT consecutive i0); persistent with prefetch.
+// for the bins p2 in [p2_lo, p2_lo + p2_n) of the job.  Work item = (p2,
+// tile of WT consecutive i0); persistent with prefetch.
 // ---------------------------------------------------------------------------
 template <typename R, int P, int VAR = 0>
 struct FwdT {
@@ -367,7 +368,8 @@ __global__ __launch_bounds__((FwdT<R, P, VAR>::THREADS)) void k_fwd_t(
         int loc;
         const JobT jb = src.get(item, loc);
         const int ntile = cdiv(jb.N0, K::WT);
-        const int p2 = loc / ntile, i0 = (loc - p2 * ntile) * K::WT + team;
+        const int t2 = loc / ntile, i0 = (loc - t2 * ntile) * K::WT + team;
+        const int p2 = jb.p2_lo + t2;
         if (i0 < jb.N0) {
             const C* in = (const C*)jb.in + ((size_t)i0 * jb.H + p2) * N1;
 #pragma unroll
@@ -383,7 +385,8 @@ __global__ __launch_bounds__((FwdT<R, P, VAR>::THREADS)) void k_fwd_t(
         const JobT jb = src.get(item, loc);
         const int N0 = jb.N0;
         const int ntile = cdiv(N0, K::WT);
-        const int p2 = loc / ntile, col0 = (loc - p2 * ntile) * K::WT;
+        const int t2 = loc / ntile, col0 = (loc - t2 * ntile) * K::WT;
+        const int p2 = jb.p2_lo + t2;
         const bool active = col0 + team < N0;
         C v[F::V];
 #pragma unroll
@@ -451,9 +454,10 @@ __global__ __launch_bounds__((InvT<R, P, VAR>::THREADS)) void k_inv_t(
         int loc;
         const JobT jb = src.get(item, loc);
         const int ntile = cdiv(jb.N0, K::WT);
-        const int p2 = loc / ntile, col0 = (loc - p2 * ntile) * K::WT;
+        const int t2 = loc / ntile, col0 = (loc - t2 * ntile) * K::WT;
 #pragma unroll
-        for (int i = 0; i < K::NT; ++i) tp[i] = tile_elem(jb, p2, col0, threadIdx.x + i * K::THREADS);
+        for (int i = 0; i < K::NT; ++i)
+            tp[i] = tile_elem(jb, jb.p2_lo + t2, col0, threadIdx.x + i * K::THREADS);
     };
     if constexpr (K::PREFETCH) {
         if (ch.first < ch.last) prefetch(ch.first);
@@ -463,7 +467,8 @@ __global__ __launch_bounds__((InvT<R, P, VAR>::THREADS)) void k_inv_t(
         const JobT jb = src.get(item, loc);
         const int N0 = jb.N0;
         const int ntile = cdiv(N0, K::WT);
-        const int p2 = loc / ntile, col0 = (loc - p2 * ntile) * K::WT;
+        const int t2 = loc / ntile, col0 = (loc - t2 * ntile) * K::WT;
+        const int p2 = jb.p2_lo + t2;
         if constexpr (K::PREFETCH) {
 #pragma unroll
             for (int i = 0; i < K::NT; ++i) {
@@ -569,8 +574,8 @@ __global__ __launch_bounds__((Conv<R, P, VAR>::THREADS)) void k_conv(
         if (item < total) {
             int loc;
             const JobConv jb = src.get(item, loc);
-            const C* pen =
-                (const C*)jb.data + (size_t)conv_item_to_pencil(loc, jb.P1, jb.N1) * N0;
+            const int qp = conv_item_to_pencil(loc, jb.P1, jb.N1) + jb.p2_lo * jb.P1;
+            const C* pen = (const C*)jb.data + (size_t)qp * N0;
 #pragma unroll
             for (int b = 0; b < K::NBT0; ++b)
 #pragma unroll
@@ -590,7 +595,7 @@ __global__ __launch_bounds__((Conv<R, P, VAR>::THREADS)) void k_conv(
             for (int q = 0; q < K::R0; ++q)
                 v[b * K::R0 + q] = q < K::HALF ? pf[b * K::HALF + q] : mk(R(0), R(0));
         if (it + 1 < chunk) prefetch(item + 1);
-        const int qp = conv_item_to_pencil(loc, jb.P1, jb.N1);
+        const int qp = conv_item_to_pencil(loc, jb.P1, jb.N1) + jb.p2_lo * jb.P1;
         const int p2 = qp / jb.P1, p1 = qp - p2 * jb.P1;
         const int a1 = p1 <= jb.N1 ? p1 : jb.P1 - p1;
         const R* trow = (const R*)jb.tensor + ((size_t)p2 * (jb.N1 + 1) + a1) * (N0 + 1);

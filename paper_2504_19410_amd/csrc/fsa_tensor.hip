@@ -9,7 +9,8 @@
 //   T^[p] = ( DFT(T(1))[p] + W(|k_p|) ) / prod_j P_j
 // is generated directly.  T(1) is real and even on every axis (Sec. 2.3), so
 // its DFT is a DCT-I of the octant 0 <= n_j <= N_j along each axis:
-//   DFT(T1)[p] = sum_{n=0}^{N} c_n T1[n] cos(pi p n / N),  c_0 = c_N = 1, else 2.
+//   DFT(T1)[p] = sum_{n=0}^{N} c_n T1[n] cos(pi p n / N),  c_0 = c_N = 1, else 2,
+// computed as the length-2N FFT of the even extension of each line.
 // Octant storage: axis 0 innermost, index ((a2 D1 + a1) D0 + a0), D_j = N_j + 1.
 #include <hip/hip_runtime.h>
 
@@ -148,35 +149,99 @@ __global__ void k_sample(double* __restrict__ out, Oct o, double h0, double h1, 
     }
 }
 
-// tab[m] = cos(pi m / N), m in [0, 2N)
-__global__ void k_costab(double* __restrict__ tab, int N) {
-    const int m = blockIdx.x * blockDim.x + threadIdx.x;
-    if (m < 2 * N) tab[m] = cospi((double)m / (double)N);
+// DCT-I of every octant line along one axis, as the real part of the
+// length-2N DFT of the line's even extension (x[n] for n <= N, x[2N - n]
+// above), which is sum_n c_n x[n] cos(pi p n / N), c_0 = c_N = 1, else 2.
+// A workgroup takes WT lines that are adjacent in the array, stages them
+// through LDS (coalesced along the contiguous direction), and each of its
+// teams runs the FP64 team FFT of length P = 2N on one line.
+constexpr int dct_lines_per_group(int T, int scr, int D) {
+    int wt = 8;
+    while (wt > 1 && (wt * T > 1024 || wt * scr * 16 + D * (wt + 1) * 8 > 160 * 1024)) wt /= 2;
+    return wt;
 }
 
-// DCT-I along one octant axis; stride/length of that axis given.
-__global__ void k_dct_axis(const double* __restrict__ in, double* __restrict__ out, Oct o,
-                           int axis, const double* __restrict__ costab) {
-    const long n = o.size();
-    const int D = axis == 0 ? o.D0 : axis == 1 ? o.D1 : o.D2;
-    const long stride = axis == 0 ? 1 : axis == 1 ? o.D0 : (long)o.D0 * o.D1;
-    const int N = D - 1, twoN = 2 * N;
-    for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n;
-         i += (long)gridDim.x * blockDim.x) {
-        int a[3];
-        o.split(i, a[0], a[1], a[2]);
-        const int p = a[axis];
-        const double* base = in + (i - (long)p * stride);
-        // n = 0 and n = N carry weight 1, interior points weight 2
-        double acc = 0.5 * (base[0] + base[(long)N * stride] * costab[((long)p * N) % twoN]);
-        int m = p;
-        for (int t = 1; t < N; ++t) {
-            acc += base[(long)t * stride] * costab[m];
-            m += p;
-            if (m >= twoN) m -= twoN;
+template <int P>
+struct Dct {
+    using F = Fft<double, P, false>;
+    static constexpr int N = P / 2, D = N + 1;
+    static constexpr int T = F::T;
+    static constexpr int WT = dct_lines_per_group(T, F::SCR, D);
+    static constexpr int TS = WT + 1;
+    static constexpr int THREADS = WT * T;
+};
+
+// Lines of one axis: line (u, v) starts at u * u_stride + v * v_stride and
+// its element t sits at + t * es; groups take WT consecutive u.
+struct Lines {
+    int n_u, n_v;
+    long u_stride, v_stride, es;
+};
+
+template <int P>
+__global__ __launch_bounds__(Dct<P>::THREADS) void k_dct(const double* __restrict__ in,
+                                                        double* __restrict__ out, Lines ln,
+                                                        const cpx<double>* __restrict__ tw) {
+    using K = Dct<P>;
+    using F = typename K::F;
+    using C = cpx<double>;
+    __shared__ C scr[K::WT * F::SCR];
+    __shared__ double tile[K::D * K::TS];
+    const int team = threadIdx.x / K::T, tid = threadIdx.x % K::T;
+    const int ntu = (ln.n_u + K::WT - 1) / K::WT;
+    const int tu = blockIdx.x % ntu, v = blockIdx.x / ntu;
+    const long base = (long)tu * K::WT * ln.u_stride + (long)v * ln.v_stride;
+    const int nw = ln.n_u - tu * K::WT < K::WT ? ln.n_u - tu * K::WT : K::WT;
+    // element e of the tile -> (t, w), contiguous direction fastest
+    auto at = [&](int e, int& t, int& w) {
+        if (ln.es == 1) {
+            w = e / K::D;
+            t = e - w * K::D;
+        } else {
+            t = e / K::WT;
+            w = e - t * K::WT;
         }
-        out[i] = 2.0 * acc;
+    };
+    for (int e = threadIdx.x; e < K::D * K::WT; e += K::THREADS) {
+        int t, w;
+        at(e, t, w);
+        tile[t * K::TS + w] = w < nw ? in[base + w * ln.u_stride + t * ln.es] : 0.0;
     }
+    __syncthreads();
+    C x[F::V];
+    F::load_first(x, tid, P, [&](int i) {
+        const int t = i <= K::N ? i : P - i;
+        return mk(tile[t * K::TS + team], 0.0);
+    });
+    __syncthreads();
+    F::run_g(x, scr + team * F::SCR, tid, tw);
+    F::store_last(x, tid, K::D, [&](int p, C c) { tile[p * K::TS + team] = c.x; });
+    __syncthreads();
+    for (int e = threadIdx.x; e < K::D * K::WT; e += K::THREADS) {
+        int t, w;
+        at(e, t, w);
+        if (w < nw) out[base + w * ln.u_stride + t * ln.es] = tile[t * K::TS + w];
+    }
+}
+
+hipError_t dct_axis(const double* in, double* out, Lines ln, int N, const void* tw,
+                    hipStream_t st) {
+    switch (2 * N) {
+#define FSA_DCT_CASE(p)                                                                         \
+    case p: {                                                                                   \
+        using K = Dct<p>;                                                                       \
+        const int groups = (ln.n_u + K::WT - 1) / K::WT * ln.n_v;                               \
+        hipLaunchKernelGGL(k_dct<p>, dim3(groups), dim3(K::THREADS), 0, st, in, out, ln,        \
+                           (const cpx<double>*)tw);                                             \
+        return hipGetLastError();                                                               \
+    }
+        FSA_DCT_CASE(16) FSA_DCT_CASE(24) FSA_DCT_CASE(32) FSA_DCT_CASE(48) FSA_DCT_CASE(64)
+        FSA_DCT_CASE(96) FSA_DCT_CASE(128) FSA_DCT_CASE(192) FSA_DCT_CASE(256) FSA_DCT_CASE(384)
+        FSA_DCT_CASE(512) FSA_DCT_CASE(768) FSA_DCT_CASE(1024) FSA_DCT_CASE(1536)
+        FSA_DCT_CASE(2048) FSA_DCT_CASE(3072) FSA_DCT_CASE(4096)
+#undef FSA_DCT_CASE
+    }
+    return hipErrorInvalidValue;
 }
 
 template <typename R>
@@ -227,10 +292,11 @@ hipError_t build_tensor_device(const KernelParams& kp, int d, const double* L, c
     const long n = (long)o.D0 * o.D1 * o.D2;
     int maxN = 0;
     for (int j = 0; j < d; ++j) maxN = (int)N[j] > maxN ? (int)N[j] : maxN;
-    double *a = nullptr, *b = nullptr, *tab = nullptr;
+    double *a = nullptr, *b = nullptr;
+    void* tw = nullptr;
     hipError_t e = hipMallocAsync((void**)&a, sizeof(double) * n, st);
     if (e == hipSuccess) e = hipMallocAsync((void**)&b, sizeof(double) * n, st);
-    if (e == hipSuccess) e = hipMallocAsync((void**)&tab, sizeof(double) * 2 * maxN, st);
+    if (e == hipSuccess) e = hipMallocAsync(&tw, 2 * sizeof(double) * 2 * maxN, st);
     if (e != hipSuccess) {
         if (a) (void)hipFreeAsync(a, st);
         if (b) (void)hipFreeAsync(b, st);
@@ -243,11 +309,15 @@ hipError_t build_tensor_device(const KernelParams& kp, int d, const double* L, c
                        d == 3 ? h[2] : 0.0, hprod, kp);
     double* src = a;
     double* dst = b;
-    for (int ax = 0; ax < d; ++ax) {
-        const int Nax = (int)N[ax];
-        hipLaunchKernelGGL(k_costab, dim3((2 * Nax + 255) / 256), dim3(256), 0, st, tab, Nax);
-        hipLaunchKernelGGL(k_dct_axis, dim3(grid), dim3(block), 0, st, (const double*)src, dst, o,
-                           ax, (const double*)tab);
+    const long D0 = o.D0, D1 = o.D1, D2 = o.D2;
+    for (int ax = 0; ax < d && e == hipSuccess; ++ax) {
+        // lines along axis ax; groups take lines adjacent in memory
+        Lines ln;
+        if (ax == 0) ln = Lines{(int)D1, (int)D2, D0, D0 * D1, 1};
+        else if (ax == 1) ln = Lines{(int)D0, (int)D2, 1, D0 * D1, D0};
+        else ln = Lines{(int)D0, (int)D1, 1, D0, D0 * D1};
+        e = build_twiddles(FSA_F64, (int)(2 * N[ax]), tw, st);
+        if (e == hipSuccess) e = dct_axis(src, dst, ln, (int)N[ax], tw, st);
         double* t = src;
         src = dst;
         dst = t;
@@ -262,10 +332,10 @@ hipError_t build_tensor_device(const KernelParams& kp, int d, const double* L, c
     else
         hipLaunchKernelGGL(k_finalize<double>, dim3(grid), dim3(block), 0, st, (const double*)src,
                            (double*)tensor_out, o, c0, c1, c2, 1.0 / prodP, kp);
-    e = hipGetLastError();
+    if (e == hipSuccess) e = hipGetLastError();
     (void)hipFreeAsync(a, st);
     (void)hipFreeAsync(b, st);
-    (void)hipFreeAsync(tab, st);
+    (void)hipFreeAsync(tw, st);
     return e;
 }
 

@@ -7,10 +7,13 @@
 // resident workgroups per CU than fit.  fsa_autotune times every distinct
 // (variant, occupancy) candidate of every pass of a plan on the device with
 // hipEvents and keeps the fastest per (precision, pass, length) in a
-// process-wide table; fsa_apply, fsa_apply_batched and the server read the
-// table at launch time.  The table can be saved to and loaded from a JSON
-// file, and is loaded on first use from the file named by the environment
-// variable FSA_TUNE_CACHE when that is set.
+// process-wide table; for a 3D grid it then times the schedule, i.e. how many
+// slabs of bins p2 the middle passes B, C, D are run in (B, C, D of one slab
+// back to back, so the slab's spectrum can stay in the memory-side cache
+// between them), and keeps the fastest per (precision, grid).  fsa_apply,
+// fsa_apply_batched and the server read the tables at launch time.  They can
+// be saved to and loaded from a JSON file, and are loaded on first use from
+// the file named by the environment variable FSA_TUNE_CACHE when that is set.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -39,9 +42,16 @@ struct TuneEntry {
 };
 
 using Key = std::tuple<int, int, int>;  // precision, pass, length
+using GridKey = std::tuple<int, int64_t, int64_t, int64_t>;  // precision, N0, N1, N2
+
+struct SlabEntry {
+    int slabs = 1;
+    double us = 0.0;
+};
 
 std::mutex g_mu;
 std::map<Key, TuneEntry>& g_table = *new std::map<Key, TuneEntry>();
+std::map<GridKey, SlabEntry>& g_slabs = *new std::map<GridKey, SlabEntry>();
 std::atomic<uint64_t> g_generation{1};
 std::once_flag g_env_once;
 
@@ -124,8 +134,11 @@ struct Parsed {
     struct Row {
         std::string prec, pass;
         double len = -1, var = -1, occ = -1, us = 0;
+        double slabs = -1;
+        std::vector<double> grid;
     };
-    std::vector<Row> rows;
+    std::vector<Row> rows;   // "entries"
+    std::vector<Row> sched;  // "schedules"
 };
 
 bool parse_row(Reader& r, Parsed::Row& row) {
@@ -138,6 +151,14 @@ bool parse_row(Reader& r, Parsed::Row& row) {
             std::string v;
             if (!r.str(v)) return false;
             (k == "precision" ? row.prec : row.pass) = v;
+        } else if (k == "grid") {
+            if (!r.eat('[')) return false;
+            do {
+                double v;
+                if (!r.num(v)) return false;
+                row.grid.push_back(v);
+            } while (r.eat(','));
+            if (!r.eat(']')) return false;
         } else {
             double v;
             if (!r.num(v)) return false;
@@ -145,6 +166,7 @@ bool parse_row(Reader& r, Parsed::Row& row) {
             else if (k == "variant") row.var = v;
             else if (k == "occupancy") row.occ = v;
             else if (k == "us") row.us = v;
+            else if (k == "slabs") row.slabs = v;
             else return false;
         }
     } while (r.eat(','));
@@ -162,13 +184,14 @@ bool parse(const std::string& text, Parsed& out) {
             std::string v;
             if (!r.str(v)) return false;
             (k == "format" ? out.format : out.arch) = v;
-        } else if (k == "entries") {
+        } else if (k == "entries" || k == "schedules") {
+            auto& dst = k == "entries" ? out.rows : out.sched;
             if (!r.eat('[')) return false;
             if (!r.eat(']')) {
                 do {
                     Parsed::Row row;
                     if (!parse_row(r, row)) return false;
-                    out.rows.push_back(row);
+                    dst.push_back(row);
                 } while (r.eat(','));
                 if (!r.eat(']')) return false;
             }
@@ -198,12 +221,12 @@ fsa_status load_file(const char* path) {
         return fail(FSA_EINVAL, "fsa_tune_load: table was tuned on '" + p.arch +
                                     "', this device is '" + arch + "'");
     std::map<Key, TuneEntry> fresh;
+    auto small_int = [](double v) { return v >= 0.0 && v <= 1e6 && v == (double)(int)v; };
     for (const auto& row : p.rows) {
         int prec = row.prec == "f32" ? FSA_F32 : row.prec == "f64" ? FSA_F64 : -1;
         int pass = -1;
         for (int k = 0; k < 5; ++k)
             if (row.pass == kPassNames[k]) pass = k;
-        auto small_int = [](double v) { return v >= 0.0 && v <= 1e6 && v == (double)(int)v; };
         const bool ints = small_int(row.len) && small_int(row.var) && small_int(row.occ);
         const int len = ints ? (int)row.len : -1, var = ints ? (int)row.var : -1;
         const int occ = ints ? (int)row.occ : -1;
@@ -213,9 +236,21 @@ fsa_status load_file(const char* path) {
                                         row.pass + ", " + std::to_string(len) + ")");
         fresh[Key(prec, pass, len)] = TuneEntry{fsa::Choice{var, occ}, row.us};
     }
+    std::map<GridKey, SlabEntry> fresh_slabs;
+    for (const auto& row : p.sched) {
+        const int prec = row.prec == "f32" ? FSA_F32 : row.prec == "f64" ? FSA_F64 : -1;
+        bool ok = prec >= 0 && row.grid.size() == 3 && small_int(row.slabs) && row.slabs >= 1 &&
+                  row.slabs <= fsa::kMaxSlabs;
+        for (double g : row.grid) ok = ok && small_int(g) && fsa::grid_length_supported((int64_t)g);
+        if (!ok)
+            return fail(FSA_EINVAL, "fsa_tune_load: invalid schedule entry (" + row.prec + ")");
+        fresh_slabs[GridKey(prec, (int64_t)row.grid[0], (int64_t)row.grid[1],
+                            (int64_t)row.grid[2])] = SlabEntry{(int)row.slabs, row.us};
+    }
     {
         std::lock_guard<std::mutex> lk(g_mu);
         for (const auto& kv : fresh) g_table[kv.first] = kv.second;
+        for (const auto& kv : fresh_slabs) g_slabs[kv.first] = kv.second;
     }
     ++g_generation;
     return FSA_OK;
@@ -254,6 +289,23 @@ void set(fsa_precision prec, Pass pass, int len, Choice c, double us) {
 }
 
 uint64_t generation() { return g_generation.load(); }
+
+int get_slabs(const fsa_plan_s* pl) {
+    if (pl->d != 3) return 1;
+    load_env_once();
+    std::lock_guard<std::mutex> lk(g_mu);
+    auto it = g_slabs.find(GridKey((int)pl->prec, pl->N[0], pl->N[1], pl->N[2]));
+    return it == g_slabs.end() ? 1 : it->second.slabs;
+}
+
+void set_slabs(const fsa_plan_s* pl, int slabs, double us) {
+    if (pl->d != 3) return;
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        g_slabs[GridKey((int)pl->prec, pl->N[0], pl->N[1], pl->N[2])] = SlabEntry{slabs, us};
+    }
+    ++g_generation;
+}
 
 }  // namespace tune
 }  // namespace fsa
@@ -304,6 +356,7 @@ fsa_status fsa_tune_reset(void) {
     {
         std::lock_guard<std::mutex> lk(g_mu);
         g_table.clear();
+        g_slabs.clear();
     }
     ++g_generation;
     return FSA_OK;
@@ -329,6 +382,22 @@ fsa_status fsa_tune_save(const char* path) {
             first = false;
         }
     }
+    out += "\n  ],\n  \"schedules\": [";
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        bool first = true;
+        for (const auto& kv : g_slabs) {
+            char line[256];
+            std::snprintf(line, sizeof line,
+                          "%s\n    {\"precision\": \"%s\", \"grid\": [%lld, %lld, %lld], "
+                          "\"slabs\": %d, \"us\": %.3f}",
+                          first ? "" : ",", std::get<0>(kv.first) == FSA_F32 ? "f32" : "f64",
+                          (long long)std::get<1>(kv.first), (long long)std::get<2>(kv.first),
+                          (long long)std::get<3>(kv.first), kv.second.slabs, kv.second.us);
+            out += line;
+            first = false;
+        }
+    }
     out += "\n  ]\n}\n";
     const std::string tmp = std::string(path) + ".tmp";
     FILE* f = std::fopen(tmp.c_str(), "wb");
@@ -345,6 +414,34 @@ fsa_status fsa_tune_load(const char* path) {
     if (!path) return fail(FSA_EINVAL, "fsa_tune_load: null path");
     load_env_once();
     return load_file(path);
+}
+
+fsa_status fsa_tune_set_slabs(int precision, const int64_t* N, int slabs) {
+    if ((precision != FSA_F32 && precision != FSA_F64) || !N || slabs < 1 ||
+        slabs > fsa::kMaxSlabs)
+        return fail(FSA_EINVAL, "fsa_tune_set_slabs: bad precision, grid or slab count");
+    for (int j = 0; j < 3; ++j)
+        if (!fsa::grid_length_supported(N[j]))
+            return fail(FSA_EINVAL, "fsa_tune_set_slabs: unsupported grid length");
+    load_env_once();
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        g_slabs[GridKey(precision, N[0], N[1], N[2])] = SlabEntry{slabs, 0.0};
+    }
+    ++g_generation;
+    return FSA_OK;
+}
+
+fsa_status fsa_tune_get_slabs(int precision, const int64_t* N, int* slabs, double* us) {
+    if ((precision != FSA_F32 && precision != FSA_F64) || !N || !slabs)
+        return fail(FSA_EINVAL, "fsa_tune_get_slabs: bad arguments");
+    load_env_once();
+    std::lock_guard<std::mutex> lk(g_mu);
+    auto it = g_slabs.find(GridKey(precision, N[0], N[1], N[2]));
+    const SlabEntry e = it == g_slabs.end() ? SlabEntry{} : it->second;
+    *slabs = e.slabs;
+    if (us) *us = e.us;
+    return FSA_OK;
 }
 
 fsa_status fsa_autotune(fsa_plan pl, const void* rho, void* phi, void* workspace, void* stream,
@@ -364,21 +461,45 @@ fsa_status fsa_autotune(fsa_plan pl, const void* rho, void* phi, void* workspace
     hipError_t e = hipEventCreate(&ev[0]);
     if (e == hipSuccess) e = hipEventCreate(&ev[1]);
     const int np = fsa::n_passes(pl);
-    auto tuned = [&](int k) {
-        fsa::Pass pass;
-        int len;
-        fsa::pass_of(pl, k, &pass, &len);
-        return fsa::tune::get(pl->prec, pass, len);
+    const int H = (int)pl->H;
+    auto whole = [&](int k) { return fsa::Step{k, 0, H}; };
+    auto run_all = [&](int slabs) {
+        fsa::Step steps[fsa::kMaxSteps];
+        const int ns = fsa::schedule(pl, slabs, steps);
+        hipError_t r = hipSuccess;
+        for (int i = 0; i < ns && r == hipSuccess; ++i)
+            r = fsa::launch_step(pl, steps[i], rho, phi, workspace,
+                                 fsa::step_choice(pl, steps[i]), st);
+        return r;
     };
+    // median time (us) of `reps` timed runs of `body` after one warm-up;
+    // `prep` runs untimed before each
+    auto time_us = [&](auto&& prep, auto&& body, double* us) {
+        std::vector<float> ms;
+        hipError_t r = hipSuccess;
+        for (int i = -1; i < reps && r == hipSuccess; ++i) {
+            r = prep();
+            if (r == hipSuccess) r = hipEventRecord(ev[0], st);
+            if (r == hipSuccess) r = body();
+            if (r == hipSuccess) r = hipEventRecord(ev[1], st);
+            if (r == hipSuccess) r = hipEventSynchronize(ev[1]);
+            float t = 0.0f;
+            if (r == hipSuccess) r = hipEventElapsedTime(&t, ev[0], ev[1]);
+            if (r == hipSuccess && i >= 0) ms.push_back(t);
+        }
+        if (r == hipSuccess) {
+            std::sort(ms.begin(), ms.end());
+            *us = 1e3 * ms[ms.size() / 2];
+        }
+        return r;
+    };
+    auto nothing = [] { return hipSuccess; };
     // one evaluation with the current choices fills every buffer with data
-    for (int k = 0; k < np && e == hipSuccess; ++k)
-        e = fsa::launch_pass(pl, k, rho, phi, workspace, tuned(k), st);
+    if (e == hipSuccess) e = run_all(1);
     for (int k = 0; k < np && e == hipSuccess; ++k) {
         fsa::Pass pass;
         int len;
         fsa::pass_of(pl, k, &pass, &len);
-        // the fused pass works in place: re-create its input before each run
-        const bool refill = pass == fsa::Pass::CONV;
         std::vector<fsa::Choice> cands;
         for (int v = 0; v < fsa::kNumVariants; ++v) {
             if (!variant_ok(pl->prec, (int)pass, len, v)) continue;
@@ -387,33 +508,53 @@ fsa_status fsa_autotune(fsa_plan pl, const void* rho, void* phi, void* workspace
             cands.push_back(fsa::Choice{v, 0});
             if (mo >= 2) cands.push_back(fsa::Choice{v, mo / 2});
         }
+        // the fused pass works in place: its producer re-creates the input
+        // before each run
+        auto prep = [&] {
+            if (pass != fsa::Pass::CONV) return hipSuccess;
+            const fsa::Step prev = whole(k - 1);
+            return fsa::launch_step(pl, prev, rho, phi, workspace, fsa::step_choice(pl, prev), st);
+        };
         double best = 1e300;
         fsa::Choice best_c;
         for (const fsa::Choice& c : cands) {
-            std::vector<float> ms;
-            for (int r = -1; r < reps && e == hipSuccess; ++r) {  // r = -1: warm-up
-                if (refill) e = fsa::launch_pass(pl, k - 1, rho, phi, workspace, tuned(k - 1), st);
-                if (e == hipSuccess) e = hipEventRecord(ev[0], st);
-                if (e == hipSuccess) e = fsa::launch_pass(pl, k, rho, phi, workspace, c, st);
-                if (e == hipSuccess) e = hipEventRecord(ev[1], st);
-                if (e == hipSuccess) e = hipEventSynchronize(ev[1]);
-                float t = 0.0f;
-                if (e == hipSuccess) e = hipEventElapsedTime(&t, ev[0], ev[1]);
-                if (e == hipSuccess && r >= 0) ms.push_back(t);
-            }
+            double us = 0.0;
+            e = time_us(prep,
+                        [&] { return fsa::launch_step(pl, whole(k), rho, phi, workspace, c, st); },
+                        &us);
             if (e != hipSuccess) break;
-            std::sort(ms.begin(), ms.end());
-            const double med = 1e3 * ms[ms.size() / 2];
-            if (med < best) {
-                best = med;
+            if (us < best) {
+                best = us;
                 best_c = c;
             }
         }
         if (e == hipSuccess) fsa::tune::set(pl->prec, pass, len, best_c, best);
     }
+    // schedule: slabs of bins for the middle passes (3D)
+    if (e == hipSuccess && pl->d == 3) {
+        double best = 1e300;
+        int best_s = 1;
+        // evaluations back to back, as a caller streams them
+        constexpr int kBack = 4;
+        for (int slabs = 1; slabs <= fsa::kMaxSlabs && slabs <= H && e == hipSuccess; slabs *= 2) {
+            double us = 0.0;
+            e = time_us(nothing,
+                        [&] {
+                            hipError_t r = hipSuccess;
+                            for (int i = 0; i < kBack && r == hipSuccess; ++i) r = run_all(slabs);
+                            return r;
+                        },
+                        &us);
+            us /= kBack;
+            if (e == hipSuccess && us < best) {
+                best = us;
+                best_s = slabs;
+            }
+        }
+        if (e == hipSuccess) fsa::tune::set_slabs(pl, best_s, best);
+    }
     // leave the caller's buffers holding a valid evaluation
-    for (int k = 0; k < np && e == hipSuccess; ++k)
-        e = fsa::launch_pass(pl, k, rho, phi, workspace, tuned(k), st);
+    if (e == hipSuccess) e = run_all(fsa::tune::get_slabs(pl));
     if (e == hipSuccess) e = hipStreamSynchronize(st);
     for (hipEvent_t x : ev)
         if (x) (void)hipEventDestroy(x);

@@ -42,8 +42,9 @@ EXPORTS = (
     "fsa_plan_tensor",
     "fsa_server_create", "fsa_server_submit", "fsa_server_poll", "fsa_server_wait",
     "fsa_server_cancel", "fsa_server_stats", "fsa_server_reset_stats", "fsa_server_destroy",
+    "fsa_plan_launches",
     "fsa_autotune", "fsa_tune_set", "fsa_tune_get", "fsa_tune_variants", "fsa_tune_save",
-    "fsa_tune_load", "fsa_tune_reset",
+    "fsa_tune_load", "fsa_tune_reset", "fsa_tune_set_slabs", "fsa_tune_get_slabs",
     "fsa_last_error",
 )
 
@@ -108,6 +109,9 @@ def _load():
         "fsa_tune_save": [ctypes.c_char_p],
         "fsa_tune_load": [ctypes.c_char_p],
         "fsa_tune_reset": [],
+        "fsa_tune_set_slabs": [I, P, I],
+        "fsa_tune_get_slabs": [I, P, P, P],
+        "fsa_plan_launches": [P, P, P, I],
     }
     for name, args in sigs.items():
         fn = getattr(lib, name)
@@ -226,6 +230,16 @@ class Plan:
     def n_passes(self) -> int:
         return 5 if self.d == 3 else 3
 
+    def launches(self):
+        """Pass name of every kernel launch of one evaluation, in order (the
+        3D middle passes repeat once per slab of the tuned schedule)."""
+        n = ctypes.c_int()
+        _check(_lib.fsa_plan_launches(self._h, ctypes.byref(n), None, 0))
+        arr = (ctypes.c_int * n.value)()
+        _check(_lib.fsa_plan_launches(self._h, ctypes.byref(n), arr, n.value))
+        names = {v: k for k, v in PASSES.items()}
+        return [names[a] for a in arr]
+
     def passes(self):
         """(pass name, transform length) of each pass, in execution order."""
         N = self.N
@@ -247,7 +261,10 @@ class Plan:
                                  ctypes.c_void_p(out.data_ptr()),
                                  ctypes.c_void_p(self._ws_ptr(ws)), _stream_ptr(stream),
                                  int(reps)))
-        return {(name, n): tune_get(self.precision, name, n) for name, n in self.passes()}
+        out = {(name, n): tune_get(self.precision, name, n) for name, n in self.passes()}
+        if self.d == 3:
+            out[("slabs", 0)] = tune_get_slabs(self.precision, self.N)
+        return out
 
     def apply_events(self, rho: torch.Tensor, out: torch.Tensor, events,
                      workspace: Optional[torch.Tensor] = None,
@@ -325,6 +342,19 @@ def tune_variants(precision: str, pass_name: str, length: int):
     _check(_lib.fsa_tune_variants(PRECISIONS[precision], PASSES[pass_name], int(length),
                                   ctypes.byref(m)))
     return [v for v in range(3) if m.value >> v & 1]
+
+
+def tune_set_slabs(precision: str, N, slabs: int):
+    arr = (ctypes.c_int64 * 3)(*N)
+    _check(_lib.fsa_tune_set_slabs(PRECISIONS[precision], arr, int(slabs)))
+
+
+def tune_get_slabs(precision: str, N):
+    """(slabs, us) of the schedule of a 3D grid."""
+    arr = (ctypes.c_int64 * 3)(*N)
+    sl, us = ctypes.c_int(), ctypes.c_double()
+    _check(_lib.fsa_tune_get_slabs(PRECISIONS[precision], arr, ctypes.byref(sl), ctypes.byref(us)))
+    return sl.value, us.value
 
 
 def tune_save(path: str):

@@ -6,6 +6,8 @@ default path (relative L2 <= 1e-12 FP64, <= 5e-6 FP32); after fsa_autotune the
 tuned path must still match, the batched path must stay bitwise equal to the
 solo path, and a saved table must load back on the same device.
 """
+import ctypes
+
 import numpy as np
 import pytest
 import torch
@@ -86,6 +88,8 @@ def test_autotune_keeps_parity_and_batch_bitwise(F, prec, tmp_path):
     plan = F.Plan(kind, L, N, prec).build()
     rho = torch.from_numpy(density(L, N, 7)).to(F.DTYPES[prec]).cuda()
     table = plan.autotune(rho, reps=3)
+    slabs, slab_us = table.pop(("slabs", 0))
+    assert slabs in (1, 2, 4, 8, 16) and slab_us > 0.0
     assert set(table) == set(plan.passes())
     for (name, n), (v, occ, us) in table.items():
         assert v in F.tune_variants(prec, name, n)
@@ -110,6 +114,7 @@ def test_autotune_keeps_parity_and_batch_bitwise(F, prec, tmp_path):
     F.tune_reset()
     F.tune_load(str(path))
     assert {k: F.tune_get(prec, *k)[:2] for k in plan.passes()} == before
+    assert F.tune_get_slabs(prec, N)[0] == slabs
 
 
 def test_batch_recaptures_after_a_table_change(F):
@@ -129,3 +134,49 @@ def test_batch_recaptures_after_a_table_change(F):
     ref = O.solve("log2d", (8.0, 8.0), (128, 256), rho.double().cpu().numpy(), eps=plan.eps)
     assert rel_l2(a.double().cpu().numpy(), ref) <= TOL["f32"]
     assert rel_l2(b.double().cpu().numpy(), ref) <= TOL["f32"]
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_slab_schedules_are_bitwise_equal(F, prec):
+    """Passes B, C, D in slabs of bins: the same kernels on the same pencils,
+    so every slab count gives the same bits, and the oracle's result."""
+    kind, L, N = "yukawa3d", (8.0, 6.0, 8.0), (48, 32, 64)
+    plan = F.Plan(kind, L, N, prec, lam=0.5).build()
+    rho = torch.from_numpy(density(L, N, 11)).to(F.DTYPES[prec]).cuda()
+    base = plan.apply(rho)
+    torch.cuda.synchronize()
+    for slabs in (2, 3, 5, 16):
+        F.tune_set_slabs(prec, N, slabs)
+        assert F.tune_get_slabs(prec, N)[0] == slabs
+        launches = plan.launches()
+        assert len(launches) == 2 + 3 * slabs
+        assert launches[0] == "r2c" and launches[-1] == "c2r"
+        phi = plan.apply(rho)
+        torch.cuda.synchronize()
+        assert torch.equal(phi, base), slabs
+    ref = O.solve(kind, L, N, rho.double().cpu().numpy(), eps=plan.eps, lam=0.5)
+    assert rel_l2(base.double().cpu().numpy(), ref) <= TOL[prec]
+
+
+def test_apply_events_follow_the_schedule(F):
+    plan = F.Plan("coulomb3d", (8.0, 8.0, 8.0), (32, 32, 32), "f32").build()
+    rho = torch.from_numpy(density((8.0,) * 3, (32,) * 3, 12)).float().cuda()
+    F.tune_set_slabs("f32", (32, 32, 32), 4)
+    n = len(plan.launches())
+    assert n == 14
+    lib = ctypes.CDLL("libamdhip64.so")
+    evs = []
+    for _ in range(n + 1):
+        e = ctypes.c_void_p()
+        assert lib.hipEventCreate(ctypes.byref(e)) == 0
+        evs.append(e.value)
+    out = torch.empty_like(rho)
+    with pytest.raises(F.FsaError, match="EINVAL"):
+        plan.apply_events(rho, out, evs[:n])          # one event short
+    plan.apply_events(rho, out, evs)
+    torch.cuda.synchronize()
+    ref = plan.apply(rho)
+    torch.cuda.synchronize()
+    assert torch.equal(out, ref)
+    for e in evs:
+        lib.hipEventDestroy(ctypes.c_void_p(e))

@@ -88,3 +88,22 @@ def test_load_rejects_bad_files_as_a_whole(tmp_path, text):
 def test_load_missing_file():
     with pytest.raises(F.FsaError, match="EINVAL"):
         F.tune_load("/nonexistent/tune.json")
+
+
+def test_slab_schedule_table(tmp_path):
+    assert F.tune_get_slabs("f32", (256, 256, 256)) == (1, 0.0)
+    F.tune_set_slabs("f32", (256, 256, 256), 4)
+    F.tune_set_slabs("f64", (128, 64, 256), 2)
+    assert F.tune_get_slabs("f32", (256, 256, 256))[0] == 4
+    assert F.tune_get_slabs("f64", (256, 256, 256))[0] == 1
+    with pytest.raises(F.FsaError, match="EINVAL"):
+        F.tune_set_slabs("f32", (256, 256, 256), 17)
+    with pytest.raises(F.FsaError, match="EINVAL"):
+        F.tune_set_slabs("f32", (250, 256, 256), 2)
+    path = tmp_path / "t.json"
+    F.tune_save(str(path))
+    F.tune_reset()
+    assert F.tune_get_slabs("f32", (256, 256, 256))[0] == 1
+    F.tune_load(str(path))
+    assert F.tune_get_slabs("f32", (256, 256, 256))[0] == 4
+    assert F.tune_get_slabs("f64", (128, 64, 256))[0] == 2
