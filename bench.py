@@ -100,10 +100,10 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(key):
+def measured_traffic(key, prec, slabs):
     """HBM bytes per launch of one kernel instance (key: pass_prec_len_vVAR)
     from the committed rocprofv3 counter summary, if it was taken on the
-    current kernel sources; else None."""
+    current kernel sources with the same slab schedule; else None."""
     path = os.path.join(ROOT, "profiles", "traffic_counters.json")
     if not os.path.exists(path):
         return None
@@ -111,6 +111,8 @@ def measured_traffic(key):
         with open(path) as f:
             d = json.load(f)
         if d.get("kernel_source_hash") != kernel_source_hash():
+            return None
+        if d.get("slabs", {}).get(prec, 1) != slabs:
             return None
         ent = d["kernels"][key]
         return int(ent["fetch_bytes"] + ent["write_bytes"])
@@ -137,7 +139,7 @@ def bench_precision(F, torch, hip, prob, rho64, prec, steps, warmup, tune=True):
     if tune:
         tuned = plan.autotune(rho, reps=5)
     else:   # report the table in force (defaults, or a loaded one)
-        tuned = {(name, n): F.tune_get(prec, name, n) for name, n in plan.passes()}
+        tuned = plan.tuned()
         if plan.d == 3:
             tuned[("slabs", 0)] = F.tune_get_slabs(prec, plan.N)
     for _ in range(warmup):
@@ -185,9 +187,10 @@ def bench_precision(F, torch, hip, prob, rho64, prec, steps, warmup, tune=True):
     nl = pass_launches[dom]
     achieved = mb[dom] / (pass_ms[dom] * 1e-3)
     dom_pass, dom_len = plan.passes()[names.index(dom)]
-    dom_var = F.tune_get(prec, dom_pass, dom_len)[0]
+    dom_var = F.tune_get(prec, dom_pass, dom_len, plan.pass_lines()[names.index(dom)] // nl)[0]
     dom_key = f"{dom_pass}_{prec}_{dom_len}_v{dom_var}"
-    traffic = measured_traffic(dom_key)
+    slabs = F.tune_get_slabs(prec, plan.N)[0] if plan.d == 3 else 1
+    traffic = measured_traffic(dom_key, prec, slabs)
     return {
         "value": pts / (ms * 1e-3),
         "ms_per_step": ms,
@@ -208,13 +211,36 @@ def bench_precision(F, torch, hip, prob, rho64, prec, steps, warmup, tune=True):
             "peak": HBM_PEAK_BPS / 1e9,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_BPS,
-            "traffic": None if traffic is None or nl != 1 else traffic,
+            "traffic": traffic,
             "instance": dom_key,
             "launches_per_step": nl,
             "algorithmic_bytes": mb[dom] / nl,
             "avg_launch_ms": pass_ms[dom] / nl,
         },
     }, phi
+
+
+def precomp_sweep(F, torch, hip, n=256, gammas=(1, 2, 4, 8, 16), reps=3):
+    """Tensor generation (Precomp) time against anisotropy: 3D Coulomb on
+    [-8,8]^2 x [-8/g, 8/g] at n^3 (h_z = h/g), eps = R0/8; the paper reports
+    FSA's precomputation as independent of the anisotropy (Sec. 5.1)."""
+    stream = torch.cuda.current_stream()
+    out = {}
+    for g in gammas:
+        plan = F.Plan("coulomb3d", (8.0, 8.0, 8.0 / g), (n, n, n), "f32").build()
+        torch.cuda.synchronize()
+        e0, e1 = hip.event(), hip.event()
+        ts = []
+        for _ in range(reps):
+            hip.record(e0, stream)
+            plan.build()
+            hip.record(e1, stream)
+            ts.append(hip.ms(e0, e1))
+        hip.destroy(e0)
+        hip.destroy(e1)
+        plan.close()
+        out[str(g)] = round(sorted(ts)[reps // 2], 3)
+    return {"grid": [n, n, n], "kernel": "coulomb3d", "ms_by_anisotropy": out}
 
 
 def stream_copy(torch, hip, nbytes=1 << 30, reps=10):
@@ -468,8 +494,8 @@ def cpu_baseline(synth):
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawTextHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=30)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--n", type=int, default=256, help="grid points per axis")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched 2D workload")
@@ -481,6 +507,8 @@ def main():
                     help="skip the autotuner (every pass at its default launch variant)")
     ap.add_argument("--tune-file", default=None,
                     help="load this saved tuning table instead of autotuning")
+    ap.add_argument("--retune", action="store_true",
+                    help="autotune in this run instead of loading the shipped table")
     ap.add_argument("--save-tune", default=None,
                     help="save the tuning table to this path at the end")
     ap.add_argument("--copy-only", action="store_true",
@@ -500,9 +528,21 @@ def main():
         print("bench.py: no GPU visible", file=sys.stderr)
         sys.exit(3)
     torch.cuda.set_device(0)
+    # launch choices: the table fsa_autotune wrote for this GPU type and ships
+    # with the package (paper_2504_19410_amd/tune/<arch>.json), unless asked
+    # to retune here, to load another table, or to run untuned
+    arch = torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
+    shipped = os.path.join(ROOT, "paper_2504_19410_amd", "tune", f"{arch}.json")
+    if args.tune_file is None and not args.retune and not args.no_tune and os.path.exists(shipped):
+        args.tune_file = shipped
     if args.tune_file:
         F.tune_load(args.tune_file)
         args.no_tune = True
+        tuning = f"table loaded from {os.path.relpath(args.tune_file, ROOT)} (written by fsa_autotune)"
+    elif args.no_tune:
+        tuning = "untuned: every pass at variant 0, full occupancy"
+    else:
+        tuning = "fsa_autotune in this run (untimed, before warm-up)"
     hip = Hip()
     copy_bps = stream_copy(torch, hip)
     log(f"stream copy (1 GiB): {copy_bps / 1e9:.0f} GB/s")
@@ -534,6 +574,8 @@ def main():
             f"{res[prec]['value'] / 1e9:.2f} Gpts/s, passes {res[prec]['pass_ms']}")
     diff = float(np.linalg.norm(phis["f32"] - phis["f64"]) / np.linalg.norm(phis["f64"]))
     del phis
+    sweep = precomp_sweep(F, torch, hip, n=args.n)
+    log(f"  precomp vs anisotropy (ms): {sweep['ms_by_anisotropy']}")
     batch = None
     if not args.no_batch:
         log("batched 2D log workload (256 densities) ...")
@@ -586,9 +628,11 @@ def main():
                  "tuned": r64["tuned"]},
         "pass_ms": r32["pass_ms"],
         "tuned": r32["tuned"],
+        "tuning": tuning,
         "model_bytes_per_step": r32["model_bytes_per_step"],
         "model_hbm_frac": r32["model_hbm_frac"],
         "precomp_ms": r32["precomp_ms"],
+        "precomp_vs_anisotropy": sweep,
         "wall_ms_per_step": r32["wall_ms_per_step"],
         "f32_vs_f64_rel_l2": diff,
         "batch": batch,

@@ -218,13 +218,20 @@ typedef enum {
 fsa_status fsa_autotune(fsa_plan plan, const void* rho, void* phi, void* workspace, void* stream,
                         int reps);
 
-/* Sets / reads one entry (precision: fsa_precision, pass: fsa_pass).  A
- * variant that does not exist at that pass and length is FSA_EINVAL.  `us`
- * receives the measured time of the chosen candidate (0 if set by hand or
- * untuned; may be NULL). */
-fsa_status fsa_tune_set(int precision, int pass, int length, int variant, int occupancy);
-fsa_status fsa_tune_get(int precision, int pass, int length, int* variant, int* occupancy,
-                        double* us);
+/* Sets / reads one entry (precision: fsa_precision, pass: fsa_pass).
+ * Entries are kept per size class floor(log2(lines)), `lines` being the
+ * number of transforms one launch runs (rows of the last axis for the real
+ * passes, axis-1 lines for B and D, axis-0 pencils for C; summed over the
+ * problems of a batched launch): the best variant of a length depends on the
+ * amount of work.  A launch uses the entry of the nearest tuned class of its
+ * (precision, pass, length); fsa_tune_get reports that choice.  A variant
+ * that does not exist at that pass and length is FSA_EINVAL.  `us` receives
+ * the measured time of the entry of exactly that class (0 if set by hand or
+ * not tuned at that class; may be NULL). */
+fsa_status fsa_tune_set(int precision, int pass, int length, int64_t lines, int variant,
+                        int occupancy);
+fsa_status fsa_tune_get(int precision, int pass, int length, int64_t lines, int* variant,
+                        int* occupancy, double* us);
 /* Schedule of a 3D grid: passes B, C, D run in `slabs` (1..16) slabs of the
  * bins p2 of the last axis, B-C-D of one slab back to back, so that the slab's
  * spectrum can stay in the device's memory-side cache between them (slabs = 1:

@@ -270,11 +270,25 @@ int schedule(const fsa_plan_s* pl, int slabs, Step* out) {
     return m;
 }
 
+long step_lines(const fsa_plan_s* pl, const Step& s) {
+    const long N0 = pl->N[0], N1 = pl->N[1];
+    if (pl->d == 3) {
+        switch (s.k) {
+        case 0:
+        case 4: return N0 * N1;             // rows of the last axis
+        case 1:
+        case 3: return N0 * (long)s.n;      // axis-1 lines of the slab
+        case 2: return 2 * N1 * (long)s.n;  // axis-0 pencils of the slab
+        }
+    }
+    return s.k == 1 ? (long)pl->H : N0;     // 2D: pencils, else rows
+}
+
 Choice step_choice(const fsa_plan_s* pl, const Step& s) {
     Pass pass;
     int len;
     pass_of(pl, s.k, &pass, &len);
-    return tune::get(pl->prec, pass, len);
+    return tune::get(pl->prec, pass, len, step_lines(pl, s));
 }
 
 // Enqueues one evaluation: pass A, then passes B, C, D per slab of bins p2

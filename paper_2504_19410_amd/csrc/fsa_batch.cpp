@@ -35,13 +35,21 @@ namespace {
 
 size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
 
+// Lengths the pass kernels are compiled for.
+bool fft_length_ok(fsa::Pass pass, int len) {
+    if (!fsa::fft_length_supported(len)) return false;
+    if (pass == fsa::Pass::R2C || pass == fsa::Pass::C2R) return len >= 8 && len <= 2048;
+    return len >= 16 && len <= 4096;
+}
+
 struct Group {
     fsa::Pass pass;
     int len;
     fsa_precision prec;
     const void* tw = nullptr;   // twiddles of length len (any member plan's table)
     const void* tw2 = nullptr;  // second table of the real transforms (length 2 len)
-    fsa::Choice ch;             // launch choice, fixed when the group is formed
+    fsa::Choice ch;             // launch choice, fixed when the groups are complete
+    long lines = 0;             // transforms of all member jobs (the size class)
     std::vector<unsigned char> jobs;  // packed job structs
     std::vector<int> start{0};
     size_t job_size = 0;
@@ -68,12 +76,12 @@ std::mutex g_mu;
 std::vector<std::unique_ptr<Entry>>& g_cache = *new std::vector<std::unique_ptr<Entry>>();
 constexpr size_t kCacheCap = 16;
 
-// Adds one problem's job to its (pass, length, precision) group; the group
-// takes the tuned launch choice when it is formed, and the job's item count
-// follows that choice.  Returns false for an unsupported length.
+// Adds one problem's job to its (pass, length, precision) group.  Returns
+// false for an unsupported length.
 template <class Job>
 bool add_job(std::map<std::tuple<int, int, int>, Group>& groups, fsa::Pass pass, int len,
-             fsa_precision prec, const void* tw, const void* tw2, const Job& job) {
+             fsa_precision prec, const void* tw, const void* tw2, const Job& job, long lines) {
+    if (!fft_length_ok(pass, len)) return false;
     Group& g = groups[std::make_tuple((int)pass, len, (int)prec)];
     if (g.n == 0) {
         g.pass = pass;
@@ -82,16 +90,27 @@ bool add_job(std::map<std::tuple<int, int, int>, Group>& groups, fsa::Pass pass,
         g.tw = tw;
         g.tw2 = tw2;
         g.job_size = sizeof(Job);
-        g.ch = fsa::tune::get(prec, pass, len);
     }
-    const int items = prec == FSA_F32 ? fsa::Launch<float>::items(pass, len, &job, g.ch)
-                                      : fsa::Launch<double>::items(pass, len, &job, g.ch);
-    if (items < 0) return false;
     const unsigned char* p = (const unsigned char*)&job;
     g.jobs.insert(g.jobs.end(), p, p + sizeof(Job));
-    g.start.push_back(g.start.back() + items);
+    g.lines += lines;
     ++g.n;
     return true;
+}
+
+// Fixes each group's launch choice (tuned for the group's total size) and
+// the item prefix its jobs follow under that choice.
+template <class Job>
+void finish_group(Group& g) {
+    g.ch = fsa::tune::get(g.prec, g.pass, g.len, g.lines);
+    g.start.assign(1, 0);
+    for (int i = 0; i < g.n; ++i) {
+        Job job;
+        std::memcpy(&job, g.jobs.data() + (size_t)i * sizeof(Job), sizeof(Job));
+        const int items = g.prec == FSA_F32 ? fsa::Launch<float>::items(g.pass, g.len, &job, g.ch)
+                                            : fsa::Launch<double>::items(g.pass, g.len, &job, g.ch);
+        g.start.push_back(g.start.back() + items);
+    }
 }
 
 fsa_status build_entry(int n, const fsa_plan* plans, const void* const* rho, void* const* phi,
@@ -110,27 +129,39 @@ fsa_status build_entry(int n, const fsa_plan* plans, const void* const* rho, voi
         char* w2 = w1 + align256(pl->ws1_elems * cs);
         ws += align256(pl->ws_bytes);
         const fsa_precision pr = pl->prec;
-        auto add = [&](auto job, fsa::Pass pass, int len, const void* t1, const void* t2) {
-            return add_job(groups, pass, len, pr, t1, t2, job);
-        };
+        auto add = [&](auto job, fsa::Pass pass, int len, const void* t1, const void* t2,
+                       long lines) { return add_job(groups, pass, len, pr, t1, t2, job, lines); };
+        const long n0 = N0, n1 = N1, h = H;
         bool ok;
         if (pl->d == 3) {
             const int N2 = (int)pl->N[2];
-            ok = add(fsa::JobR2c{rho[i], w1, N0, N1}, fsa::Pass::R2C, N2, tw_m, tw_pl) &&
-                 add(fsa::JobT{w1, w2, N0, H, 0, H}, fsa::Pass::FWD_T, 2 * N1, tw_p1, nullptr) &&
+            ok = add(fsa::JobR2c{rho[i], w1, N0, N1}, fsa::Pass::R2C, N2, tw_m, tw_pl, n0 * n1) &&
+                 add(fsa::JobT{w1, w2, N0, H, 0, H}, fsa::Pass::FWD_T, 2 * N1, tw_p1, nullptr,
+                     n0 * h) &&
                  add(fsa::JobConv{w2, pl->tensor, H * 2 * N1, 2 * N1, N1, 0}, fsa::Pass::CONV,
-                     2 * N0, tw_p0, nullptr) &&
-                 add(fsa::JobT{w2, w1, N0, H, 0, H}, fsa::Pass::INV_T, 2 * N1, tw_p1, nullptr) &&
-                 add(fsa::JobC2r{w1, phi[i], N0, N1}, fsa::Pass::C2R, N2, tw_m, tw_pl);
+                     2 * N0, tw_p0, nullptr, h * 2 * n1) &&
+                 add(fsa::JobT{w2, w1, N0, H, 0, H}, fsa::Pass::INV_T, 2 * N1, tw_p1, nullptr,
+                     n0 * h) &&
+                 add(fsa::JobC2r{w1, phi[i], N0, N1}, fsa::Pass::C2R, N2, tw_m, tw_pl, n0 * n1);
         } else {
-            ok = add(fsa::JobR2c{rho[i], w1, 1, N0}, fsa::Pass::R2C, N1, tw_m, tw_pl) &&
+            ok = add(fsa::JobR2c{rho[i], w1, 1, N0}, fsa::Pass::R2C, N1, tw_m, tw_pl, n0) &&
                  add(fsa::JobConv{w1, pl->tensor, H, 1, 0, 0}, fsa::Pass::CONV, 2 * N0, tw_p0,
-                     nullptr) &&
-                 add(fsa::JobC2r{w1, phi[i], 1, N0}, fsa::Pass::C2R, N1, tw_m, tw_pl);
+                     nullptr, h) &&
+                 add(fsa::JobC2r{w1, phi[i], 1, N0}, fsa::Pass::C2R, N1, tw_m, tw_pl, n0);
         }
         if (!ok) {
             fsa::set_last_error("fsa_apply_batched: unsupported transform length");
             return FSA_EUNSUPPORTED;
+        }
+    }
+    for (auto& kv : groups) {
+        Group& g = kv.second;
+        switch (g.pass) {
+        case fsa::Pass::R2C: finish_group<fsa::JobR2c>(g); break;
+        case fsa::Pass::C2R: finish_group<fsa::JobC2r>(g); break;
+        case fsa::Pass::FWD_T:
+        case fsa::Pass::INV_T: finish_group<fsa::JobT>(g); break;
+        case fsa::Pass::CONV: finish_group<fsa::JobConv>(g); break;
         }
     }
     // one device buffer: per group [jobs | start], each part 256-byte aligned

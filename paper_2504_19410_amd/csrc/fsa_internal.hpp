@@ -139,10 +139,15 @@ struct Launch {
 };
 
 // Tuning table (fsa_tune.cpp): the launch choice for (precision, pass,
-// transform length); variant 0 at full occupancy unless tuned or loaded.
+// transform length, size class), the size class being floor(log2(lines)) of
+// the transforms one launch runs (rows, lines or pencils): the best variant
+// of a length differs between a few hundred lines and a hundred thousand.
+// A lookup takes the entry of the nearest tuned size class of that (precision,
+// pass, length); variant 0 at full occupancy if there is none.
 namespace tune {
-Choice get(fsa_precision prec, Pass pass, int len);
-void set(fsa_precision prec, Pass pass, int len, Choice c, double us);
+int size_class(long lines);
+Choice get(fsa_precision prec, Pass pass, int len, long lines);
+void set(fsa_precision prec, Pass pass, int len, long lines, Choice c, double us);
 // Bumped on every change; batch graphs captured under another generation
 // are re-captured.
 uint64_t generation();
@@ -164,6 +169,8 @@ hipError_t launch_step(const fsa_plan_s* pl, const Step& s, const void* rho, voi
 Choice step_choice(const fsa_plan_s* pl, const Step& s);
 // (pass kind, transform length) of pass k of a plan.
 void pass_of(const fsa_plan_s* pl, int k, Pass* pass, int* len);
+// Transforms (rows, lines or pencils) one launch of a step runs.
+long step_lines(const fsa_plan_s* pl, const Step& s);
 int n_passes(const fsa_plan_s* pl);
 
 namespace tune {

@@ -41,7 +41,7 @@ struct TuneEntry {
     double us = 0.0;  // measured time of the chosen candidate (0: set by hand)
 };
 
-using Key = std::tuple<int, int, int>;  // precision, pass, length
+using Key = std::tuple<int, int, int, int>;  // precision, pass, length, size class
 using GridKey = std::tuple<int, int64_t, int64_t, int64_t>;  // precision, N0, N1, N2
 
 struct SlabEntry {
@@ -134,6 +134,7 @@ struct Parsed {
     struct Row {
         std::string prec, pass;
         double len = -1, var = -1, occ = -1, us = 0;
+        double cls = -1;
         double slabs = -1;
         std::vector<double> grid;
     };
@@ -166,6 +167,7 @@ bool parse_row(Reader& r, Parsed::Row& row) {
             else if (k == "variant") row.var = v;
             else if (k == "occupancy") row.occ = v;
             else if (k == "us") row.us = v;
+            else if (k == "class") row.cls = v;
             else if (k == "slabs") row.slabs = v;
             else return false;
         }
@@ -227,14 +229,15 @@ fsa_status load_file(const char* path) {
         int pass = -1;
         for (int k = 0; k < 5; ++k)
             if (row.pass == kPassNames[k]) pass = k;
-        const bool ints = small_int(row.len) && small_int(row.var) && small_int(row.occ);
+        const bool ints = small_int(row.len) && small_int(row.var) && small_int(row.occ) &&
+                          small_int(row.cls) && row.cls <= 62;
         const int len = ints ? (int)row.len : -1, var = ints ? (int)row.var : -1;
         const int occ = ints ? (int)row.occ : -1;
         if (prec < 0 || pass < 0 || !ints || !length_ok(pass, len) ||
             !variant_ok((fsa_precision)prec, pass, len, var))
             return fail(FSA_EINVAL, "fsa_tune_load: invalid entry (" + row.prec + ", " +
                                         row.pass + ", " + std::to_string(len) + ")");
-        fresh[Key(prec, pass, len)] = TuneEntry{fsa::Choice{var, occ}, row.us};
+        fresh[Key(prec, pass, len, (int)row.cls)] = TuneEntry{fsa::Choice{var, occ}, row.us};
     }
     std::map<GridKey, SlabEntry> fresh_slabs;
     for (const auto& row : p.sched) {
@@ -273,17 +276,37 @@ void load_env_once() {
 namespace fsa {
 namespace tune {
 
-Choice get(fsa_precision prec, Pass pass, int len) {
-    load_env_once();
-    std::lock_guard<std::mutex> lk(g_mu);
-    auto it = g_table.find(Key((int)prec, (int)pass, len));
-    return it == g_table.end() ? Choice{} : it->second.ch;
+int size_class(long lines) {
+    int c = 0;
+    while (c < 62 && (2L << c) <= lines) ++c;
+    return c;
 }
 
-void set(fsa_precision prec, Pass pass, int len, Choice c, double us) {
+Choice get(fsa_precision prec, Pass pass, int len, long lines) {
+    load_env_once();
+    const int cls = size_class(lines);
+    std::lock_guard<std::mutex> lk(g_mu);
+    // entries of (prec, pass, len) are adjacent in the map, ordered by class
+    auto lo = g_table.lower_bound(Key((int)prec, (int)pass, len, 0));
+    Choice best;
+    int dist = 1 << 30;
+    for (auto it = lo; it != g_table.end(); ++it) {
+        if (std::get<0>(it->first) != (int)prec || std::get<1>(it->first) != (int)pass ||
+            std::get<2>(it->first) != len)
+            break;
+        const int d = std::abs(std::get<3>(it->first) - cls);
+        if (d < dist) {
+            dist = d;
+            best = it->second.ch;
+        }
+    }
+    return best;
+}
+
+void set(fsa_precision prec, Pass pass, int len, long lines, Choice c, double us) {
     {
         std::lock_guard<std::mutex> lk(g_mu);
-        g_table[Key((int)prec, (int)pass, len)] = TuneEntry{c, us};
+        g_table[Key((int)prec, (int)pass, len, size_class(lines))] = TuneEntry{c, us};
     }
     ++g_generation;
 }
@@ -312,31 +335,37 @@ void set_slabs(const fsa_plan_s* pl, int slabs, double us) {
 
 extern "C" {
 
-fsa_status fsa_tune_set(int precision, int pass, int length, int variant, int occupancy) {
+fsa_status fsa_tune_set(int precision, int pass, int length, int64_t lines, int variant,
+                        int occupancy) {
     if ((precision != FSA_F32 && precision != FSA_F64) || !pass_ok(pass) ||
-        !length_ok(pass, length))
-        return fail(FSA_EINVAL, "fsa_tune_set: bad precision, pass or length");
+        !length_ok(pass, length) || lines < 1)
+        return fail(FSA_EINVAL, "fsa_tune_set: bad precision, pass, length or line count");
     if (occupancy < 0 || !variant_ok((fsa_precision)precision, pass, length, variant))
         return fail(FSA_EINVAL, "fsa_tune_set: variant " + std::to_string(variant) +
                                     " does not exist at this pass and length");
     load_env_once();
-    fsa::tune::set((fsa_precision)precision, (fsa::Pass)pass, length,
+    fsa::tune::set((fsa_precision)precision, (fsa::Pass)pass, length, (long)lines,
                    fsa::Choice{variant, occupancy}, 0.0);
     return FSA_OK;
 }
 
-fsa_status fsa_tune_get(int precision, int pass, int length, int* variant, int* occupancy,
-                        double* us) {
+fsa_status fsa_tune_get(int precision, int pass, int length, int64_t lines, int* variant,
+                        int* occupancy, double* us) {
     if ((precision != FSA_F32 && precision != FSA_F64) || !pass_ok(pass) ||
-        !length_ok(pass, length) || !variant || !occupancy)
+        !length_ok(pass, length) || lines < 1 || !variant || !occupancy)
         return fail(FSA_EINVAL, "fsa_tune_get: bad arguments");
     load_env_once();
-    std::lock_guard<std::mutex> lk(g_mu);
-    auto it = g_table.find(Key(precision, pass, length));
-    const TuneEntry e = it == g_table.end() ? TuneEntry{} : it->second;
-    *variant = e.ch.var;
-    *occupancy = e.ch.occ;
-    if (us) *us = e.us;
+    const fsa::Choice c = fsa::tune::get((fsa_precision)precision, (fsa::Pass)pass, length,
+                                         (long)lines);
+    double t = 0.0;
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        auto it = g_table.find(Key(precision, pass, length, fsa::tune::size_class((long)lines)));
+        if (it != g_table.end()) t = it->second.us;
+    }
+    *variant = c.var;
+    *occupancy = c.occ;
+    if (us) *us = t;
     return FSA_OK;
 }
 
@@ -374,10 +403,11 @@ fsa_status fsa_tune_save(const char* path) {
             char line[256];
             std::snprintf(line, sizeof line,
                           "%s\n    {\"precision\": \"%s\", \"pass\": \"%s\", \"length\": %d, "
-                          "\"variant\": %d, \"occupancy\": %d, \"us\": %.3f}",
+                          "\"class\": %d, \"variant\": %d, \"occupancy\": %d, \"us\": %.3f}",
                           first ? "" : ",", std::get<0>(kv.first) == FSA_F32 ? "f32" : "f64",
                           kPassNames[std::get<1>(kv.first)], std::get<2>(kv.first),
-                          kv.second.ch.var, kv.second.ch.occ, kv.second.us);
+                          std::get<3>(kv.first), kv.second.ch.var, kv.second.ch.occ,
+                          kv.second.us);
             out += line;
             first = false;
         }
@@ -528,7 +558,8 @@ fsa_status fsa_autotune(fsa_plan pl, const void* rho, void* phi, void* workspace
                 best_c = c;
             }
         }
-        if (e == hipSuccess) fsa::tune::set(pl->prec, pass, len, best_c, best);
+        if (e == hipSuccess)
+            fsa::tune::set(pl->prec, pass, len, fsa::step_lines(pl, whole(k)), best_c, best);
     }
     // schedule: slabs of bins for the middle passes (3D)
     if (e == hipSuccess && pl->d == 3) {

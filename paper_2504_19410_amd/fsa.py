@@ -103,8 +103,8 @@ def _load():
         "fsa_server_reset_stats": [P],
         "fsa_server_destroy": [P],
         "fsa_autotune": [P, P, P, P, P, I],
-        "fsa_tune_set": [I, I, I, I, I],
-        "fsa_tune_get": [I, I, I, P, P, P],
+        "fsa_tune_set": [I, I, I, ctypes.c_int64, I, I],
+        "fsa_tune_get": [I, I, I, ctypes.c_int64, P, P, P],
         "fsa_tune_variants": [I, I, I, P],
         "fsa_tune_save": [ctypes.c_char_p],
         "fsa_tune_load": [ctypes.c_char_p],
@@ -248,6 +248,20 @@ class Plan:
                     ("inv_t", 2 * N[1]), ("c2r", N[2])]
         return [("r2c", N[1]), ("conv", 2 * N[0]), ("c2r", N[1])]
 
+    def pass_lines(self):
+        """Transforms one whole-grid launch of each pass runs (the size the
+        tuning table is keyed by), in execution order."""
+        N = self.N
+        if self.d == 3:
+            H = N[2] + 1
+            return [N[0] * N[1], N[0] * H, H * 2 * N[1], N[0] * H, N[0] * N[1]]
+        return [N[0], N[1] + 1, N[0]]
+
+    def tuned(self):
+        """{(pass, length): (variant, occupancy, us)} in force for this plan."""
+        return {(name, n): tune_get(self.precision, name, n, lines)
+                for (name, n), lines in zip(self.passes(), self.pass_lines())}
+
     def autotune(self, rho: Optional[torch.Tensor] = None, reps: int = 10,
                  stream: Optional[torch.cuda.Stream] = None) -> dict:
         """Times every launch variant of every pass (``fsa_autotune``) and
@@ -261,7 +275,7 @@ class Plan:
                                  ctypes.c_void_p(out.data_ptr()),
                                  ctypes.c_void_p(self._ws_ptr(ws)), _stream_ptr(stream),
                                  int(reps)))
-        out = {(name, n): tune_get(self.precision, name, n) for name, n in self.passes()}
+        out = self.tuned()
         if self.d == 3:
             out[("slabs", 0)] = tune_get_slabs(self.precision, self.N)
         return out
@@ -323,16 +337,17 @@ def _hip():
     return _hip_lib
 
 
-def tune_get(precision: str, pass_name: str, length: int):
-    """(variant, occupancy, us) of one entry of the tuning table."""
+def tune_get(precision: str, pass_name: str, length: int, lines: int = 1):
+    """(variant, occupancy, us) a launch of `lines` transforms would use."""
     v, o, us = ctypes.c_int(), ctypes.c_int(), ctypes.c_double()
-    _check(_lib.fsa_tune_get(PRECISIONS[precision], PASSES[pass_name], int(length),
+    _check(_lib.fsa_tune_get(PRECISIONS[precision], PASSES[pass_name], int(length), int(lines),
                              ctypes.byref(v), ctypes.byref(o), ctypes.byref(us)))
     return v.value, o.value, us.value
 
 
-def tune_set(precision: str, pass_name: str, length: int, variant: int, occupancy: int = 0):
-    _check(_lib.fsa_tune_set(PRECISIONS[precision], PASSES[pass_name], int(length),
+def tune_set(precision: str, pass_name: str, length: int, variant: int, occupancy: int = 0,
+             lines: int = 1):
+    _check(_lib.fsa_tune_set(PRECISIONS[precision], PASSES[pass_name], int(length), int(lines),
                              int(variant), int(occupancy)))
 
 

@@ -1,0 +1,56 @@
+"""Writes the shipped tuning table for this GPU: runs fsa_autotune on every
+grid shape of the standard workloads (3D Coulomb/Yukawa grids of the single
+evaluation and served workloads, the 2D log-kernel batch shapes) in FP32 and
+FP64, and saves the table next to this script as <arch>.json (the arch name
+reported by the device, e.g. gfx950).  Load it with fsa.tune_load(path) or by
+pointing FSA_TUNE_CACHE at it.
+
+Usage (on the GPU): python -m paper_2504_19410_amd.tune.make_table [--reps 7]
+"""
+import argparse
+import os
+
+import torch
+
+from paper_2504_19410_amd import fsa as F
+from paper_2504_19410_amd import synth
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+SHAPES_3D = [
+    ("yukawa3d", (8.0, 8.0, 8.0), (256, 256, 256), 1.0),
+    ("coulomb3d", (8.0, 8.0, 8.0), (128, 128, 128), None),
+    ("coulomb3d", (8.0, 8.0, 8.0), (64, 64, 64), None),
+    ("coulomb3d", (8.0, 1.0, 1.0), (512, 64, 64), None),
+    ("coulomb3d", (1.0, 1.0, 8.0), (64, 64, 512), None),
+    ("coulomb3d", (8.0, 8.0, 2.0), (256, 256, 64), None),
+    ("coulomb3d", (2.0, 2.0, 8.0), (64, 64, 256), None),
+]
+
+
+def arch_name():
+    name = torch.cuda.get_device_properties(0).gcnArchName
+    return name.split(":")[0]
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--reps", type=int, default=7)
+    ap.add_argument("--out", default=None)
+    args = ap.parse_args()
+    F.tune_reset()
+    jobs = [(k, L, N, lam, prec) for k, L, N, lam in SHAPES_3D for prec in ("f32", "f64")]
+    jobs += [("log2d", (8.0, 8.0), N, None, "f32") for N in synth.LOG2D_SHAPES]
+    for kind, L, N, lam, prec in jobs:
+        plan = F.Plan(kind, L, N, prec, lam=lam).build()
+        rho = torch.rand(N, dtype=F.DTYPES[prec], device="cuda")
+        table = plan.autotune(rho, reps=args.reps)
+        print(kind, N, prec, {f"{a}_{b}": v for (a, b), v in table.items()}, flush=True)
+        plan.close()
+    out = args.out or os.path.join(HERE, f"{arch_name()}.json")
+    F.tune_save(out)
+    print("wrote", out)
+
+
+if __name__ == "__main__":
+    main()

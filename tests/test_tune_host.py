@@ -107,3 +107,16 @@ def test_slab_schedule_table(tmp_path):
     F.tune_load(str(path))
     assert F.tune_get_slabs("f32", (256, 256, 256))[0] == 4
     assert F.tune_get_slabs("f64", (128, 64, 256))[0] == 2
+
+
+def test_entries_are_kept_per_size_class():
+    # a 256^3 grid's pencils (131584) and a 256^2 grid's (257) fall in
+    # different classes; each launch takes the nearest tuned class
+    F.tune_set("f32", "conv", 512, 2, 0, lines=131584)
+    F.tune_set("f32", "conv", 512, 1, 0, lines=257)
+    assert F.tune_get("f32", "conv", 512, 131584)[:2] == (2, 0)
+    assert F.tune_get("f32", "conv", 512, 100000)[:2] == (2, 0)   # same class
+    assert F.tune_get("f32", "conv", 512, 257)[:2] == (1, 0)
+    assert F.tune_get("f32", "conv", 512, 300)[:2] == (1, 0)      # nearest: 2^8
+    assert F.tune_get("f32", "conv", 512, 13000)[:2] == (2, 0)    # nearest: 2^17 vs 2^8
+    assert F.tune_get("f32", "conv", 1024, 257)[:2] == (0, 0)     # other length: default
