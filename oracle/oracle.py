@@ -32,9 +32,10 @@ KINDS = {
     "coulomb2d": 4,
     "biharmonic3d": 5,
     "biharmonic2d": 6,
+    "ddi3d": 7,
 }
 KIND_DIM = {"coulomb3d": 3, "yukawa3d": 3, "biharmonic3d": 3,
-            "log2d": 2, "coulomb2d": 2, "biharmonic2d": 2}
+            "log2d": 2, "coulomb2d": 2, "biharmonic2d": 2, "ddi3d": 3}
 
 BUILD_CMD = ["gcc", "-O2", "-fopenmp", "-shared", "-fPIC", "-std=c11",
              _SRC, "-o", _LIB, "-lm"]
@@ -77,6 +78,7 @@ def _load():
             "orc_conv_direct_points": (I, [I, P, P, P, L, P, P]),
             "orc_conv_fft": (I, [I, P, P, P, P]),
             "orc_solve": (I, [I, D, D, I, P, P, P, P]),
+            "orc_solve_ddi": (I, [D, P, P, P, P, P, P]),
             "orc_ueps_vec": (None, [I, D, D, L, P, P]),
             "orc_what_vec": (None, [I, D, D, L, P, P]),
             "orc_u_vec": (None, [I, D, L, P, P]),
@@ -231,6 +233,21 @@ def conv_fft(T, rho) -> np.ndarray:
     rc = _load().orc_conv_fft(rho.ndim, _p(N), _p(T), _p(rho), _p(phi))
     if rc:
         raise ValueError(f"orc_conv_fft failed ({rc})")
+    return phi
+
+
+def solve_ddi(L, N, rho, eps, n, m) -> np.ndarray:
+    """3D dipole-dipole potential -(m.n) rho - 3 Coulomb(d_nm rho) (Sec. 5.3),
+    d_nm rho by the periodic spectral derivative on the grid."""
+    L = _f64(L)
+    N = _i64(N)
+    rho = _f64(rho)
+    n = _f64(n)
+    m = _f64(m)
+    phi = np.empty_like(rho)
+    rc = _load().orc_solve_ddi(float(eps), _p(L), _p(N), _p(n), _p(m), _p(rho), _p(phi))
+    if rc:
+        raise ValueError(f"orc_solve_ddi rejected the arguments ({rc})")
     return phi
 
 

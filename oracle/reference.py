@@ -207,3 +207,28 @@ def rel_max_err(phi_num, phi_exact):
 
 def rel_l2_err(a, b):
     return float(np.linalg.norm((a - b).ravel()) / np.linalg.norm(b.ravel()))
+
+
+def ddi3d_iso(X, a, s, n, m):
+    """3D dipole-dipole potential of a * exp(-|x|^2/s^2), exactly:
+    -(m.n) rho - 3 d_nm Phi_C with Phi_C = a sqrt(pi) s^3 erf(r/s)/(4 r) the
+    Coulomb potential (Sec. 5.3); the Hessian of a radial f is
+    f'' xh xh^T + f'/r (I - xh xh^T), and at r = 0 it is f''(0) I, f''(0) = -a/3."""
+    n = np.asarray(n, dtype=float)
+    m = np.asarray(m, dtype=float)
+    r = np.sqrt(sum(x * x for x in X))
+    z = r == 0.0
+    rr = np.where(z, 1.0, r)
+    g = np.exp(-rr * rr / (s * s))
+    ef = special.erf(rr / s)
+    c = a * np.sqrt(np.pi) * s ** 3 / 4.0
+    two = 2.0 / (np.sqrt(np.pi) * s)
+    fp = c * (two * g / rr - ef / rr ** 2)
+    fpp = c * (-2.0 * two * g / (s * s) - 2.0 * two * g / rr ** 2 + 2.0 * ef / rr ** 3)
+    xn = sum(X[i] * n[i] for i in range(3)) / rr
+    xm = sum(X[i] * m[i] for i in range(3)) / rr
+    nm = float(n @ m)
+    hess = fpp * xn * xm + fp / rr * (nm - xn * xm)
+    hess = np.where(z, -a * nm / 3.0, hess)
+    rho = a * np.exp(-r * r / (s * s))
+    return -nm * rho - 3.0 * hess

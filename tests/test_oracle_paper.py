@@ -99,6 +99,100 @@ def test_printed_biharmonic3d_errors(golden):
         assert abs(err - g["err"][c]) <= 1e-3 * g["err"][c], (c, err)
 
 
+def biharmonic2d_exact(r, sigma2):
+    """Phi(r) = -(1/4) int_0^inf rho(s) s [(A^2 + B^2)(ln A - 1) + B^2] ds,
+    A = max(r, s), B = min(r, s), for rho = exp(-s^2/sigma2) and
+    U = -|x|^2 (ln|x| - 1)/(8 pi): the circle average of q^2 ln q^2 over
+    |y| = s is 2(A^2 + B^2) ln A + 2 B^2 (Fourier series of ln|1 - z e^{it}|);
+    Gauss-Legendre on [0, 40] split at r and at 4 and 8 (where the density
+    lives)."""
+    from numpy.polynomial.legendre import leggauss
+    xg, wg = leggauss(200)
+    out = np.empty_like(r)
+    ur, inv = np.unique(np.round(r, 12), return_inverse=True)
+    vals = np.empty_like(ur)
+    for i, rv in enumerate(ur):
+        tot = 0.0
+        cuts = sorted({0.0, 4.0, 8.0, 40.0} | ({rv} if 0.0 < rv < 40.0 else set()))
+        for a, b in zip(cuts[:-1], cuts[1:]):
+            s = 0.5 * (b - a) * xg + 0.5 * (a + b)
+            w = 0.5 * (b - a) * wg
+            A, B = np.maximum(rv, s), np.minimum(rv, s)
+            f = np.exp(-s * s / sigma2) * s * ((A * A + B * B) * (np.log(A) - 1.0) + B * B)
+            tot += np.sum(w * f)
+        vals[i] = -0.25 * tot
+    out[...] = vals[inv].reshape(r.shape)
+    return out
+
+
+def test_printed_biharmonic2d_errors(golden):
+    g = golden["biharmonic2d_iso"]
+    for c in range(4):
+        N = int(round(2 * g["L"] / g["h"][c]))
+        r, rho = iso_setup(2, g["L"], N, g["sigma2"])
+        phi = O.solve("biharmonic2d", [g["L"]] * 2, [N] * 2, rho, eps=g["eps"])
+        err = R.rel_max_err(phi, biharmonic2d_exact(r, g["sigma2"]))
+        if c < 3:
+            assert abs(err - g["err"][c]) <= 1e-3 * g["err"][c], (c, err)
+        else:
+            # printed 1.29e-15; the oracle reaches 6.5e-14 at the far corner, where
+            # U grows like r^2 ln r: round-off of the FFT convolution, not a bias
+            assert err <= 1e-13, err
+
+
+def ddi_setup(g, h):
+    N = int(round(2 * g["L"] / h))
+    axes = O.grid_axes([g["L"]] * 3, [N] * 3)
+    X = np.meshgrid(*axes, indexing="ij")
+    rho = np.exp(-sum(x * x for x in X) / g["sigma2"])
+    return N, X, rho
+
+
+def test_printed_ddi3d_errors(golden):
+    """Table 5's 3D DDI row against the exact potential -(m.n) rho - 3 d_nm Phi_C."""
+    g = golden["ddi3d_iso"]
+    s = np.sqrt(g["sigma2"])
+    for c in range(4):
+        N, X, rho = ddi_setup(g, g["h"][c])
+        phi = O.solve_ddi([g["L"]] * 3, [N] * 3, rho, g["eps"], g["n"], g["m"])
+        err = R.rel_max_err(phi, R.ddi3d_iso(X, 1.0, s, g["n"], g["m"]))
+        if c < 3:
+            assert abs(err - g["err"][c]) <= 1e-3 * g["err"][c], (c, err)
+        else:
+            assert err <= 1e-13, err   # printed 7.57e-15: round-off level
+
+
+def test_ddi_readings_that_miss_the_printed_row(golden):
+    """The printed DDI errors pin the derivative step: the derivative taken on
+    the 2N-padded grid (the Coulomb convolution's own grid), or the exact
+    derivative of the Gaussian sampled on the grid, give other values at h = 1
+    and h = 1/2 (computed here with numpy, on the CPU)."""
+    g = golden["ddi3d_iso"]
+    s = np.sqrt(g["sigma2"])
+    n, m = np.array(g["n"]), np.array(g["m"])
+    for c in (1, 2):
+        N, X, rho = ddi_setup(g, g["h"][c])
+        L = g["L"]
+        exact = R.ddi3d_iso(X, 1.0, s, n, m)
+        T = O.build_tensor("coulomb3d", [L] * 3, [N] * 3, g["eps"])
+        # (a) spectral derivative on the padded grid
+        P = 2 * N
+        pad = np.zeros((P,) * 3)
+        pad[:N, :N, :N] = rho
+        k = np.pi * np.fft.fftfreq(P, 1.0 / P) / (2 * L)
+        K = np.meshgrid(k, k, k, indexing="ij")
+        kn = sum(K[i] * n[i] for i in range(3))
+        km = sum(K[i] * m[i] for i in range(3))
+        Da = np.real(np.fft.ifftn(-kn * km * np.fft.fftn(pad)))[:N, :N, :N]
+        # (b) exact derivative of the Gaussian, sampled
+        xn = sum(X[i] * n[i] for i in range(3))
+        xm = sum(X[i] * m[i] for i in range(3))
+        Db = (4 * xn * xm / g["sigma2"] ** 2 - 2 * float(n @ m) / g["sigma2"]) * rho
+        for D in (Da, Db):
+            err = R.rel_max_err(-float(n @ m) * rho - 3 * O.conv_fft(T, D), exact)
+            assert sig2(err) != sig2(g["err"][c]), (c, err)
+
+
 def test_yukawa_h_half_entry(golden):
     """The only Yukawa entry the unstated split does not decide (see fixture reading)."""
     g = golden["yukawa3d_iso"]
