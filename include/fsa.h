@@ -61,14 +61,21 @@ typedef enum {
  *   FSA_LOG_2D        U = -(1/2pi) ln r,          eq. lnrAppr
  *   FSA_COULOMB_2D    U = 1/(2 pi r),             U^eps = U erf(r/eps)
  *   FSA_BIHARMONIC_3D U = r/(8 pi),               U^eps = U erf(r/eps)
- *   FSA_BIHARMONIC_2D U = -r^2 (ln r - 1)/(8 pi), Table 1 */
+ *   FSA_BIHARMONIC_2D U = -r^2 (ln r - 1)/(8 pi), Table 1
+ *   FSA_DDI_3D        dipole-dipole interaction with dipole orientations n, m
+ *                     (Sec. 5.3): Phi = -(m.n) rho - 3 Coulomb(d_nm rho),
+ *                     d_nm = (n.grad)(m.grad), the Coulomb part by FSA and
+ *                     d_nm rho as the spectral derivative of rho on its own
+ *                     grid, periodic on the box (q_j = i_j for i_j < N_j/2,
+ *                     else i_j - N_j; k_j = pi q_j / L_j; real part). */
 typedef enum {
     FSA_COULOMB_3D = 1,
     FSA_YUKAWA_3D = 2,
     FSA_LOG_2D = 3,
     FSA_COULOMB_2D = 4,
     FSA_BIHARMONIC_3D = 5,
-    FSA_BIHARMONIC_2D = 6
+    FSA_BIHARMONIC_2D = 6,
+    FSA_DDI_3D = 7
 } fsa_kernel_kind;
 
 /* Arithmetic of the per-evaluation FFT convolution.  The tensor is always
@@ -81,6 +88,8 @@ typedef struct {
     double eps;     /* split parameter; <= 0 selects the default R0/8,
                        R0 = 2 min_j L_j (condition (b) of eq. ApproxProp,
                        Remark 2.1 and Appendix B)                             */
+    double n[3];    /* FSA_DDI_3D: dipole orientations n and m (finite, non-  */
+    double m[3];    /* zero; used as given); ignored by other kernels         */
 } fsa_kernel;
 
 typedef struct fsa_plan_s* fsa_plan;
@@ -191,7 +200,8 @@ typedef enum {
     FSA_PASS_FWD_T = 1, /* B (3D): zero-pad + FFT along axis 1              */
     FSA_PASS_CONV = 2,  /* C: FFT along axis 0, x tensor, inverse FFT, crop */
     FSA_PASS_INV_T = 3, /* D (3D): inverse FFT along axis 1, crop           */
-    FSA_PASS_C2R = 4    /* E: inverse real FFT along the last axis, crop    */
+    FSA_PASS_C2R = 4,   /* E: inverse real FFT along the last axis, crop    */
+    FSA_PASS_SPECTRAL = 5 /* FSA_DDI_3D: the d_nm rho derivative launches   */
 } fsa_pass;
 
 /* Every pass kernel exists in up to three compiled variants per length:

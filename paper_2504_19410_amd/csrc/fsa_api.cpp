@@ -34,7 +34,8 @@ int kernel_dim(int kind) {
     switch (kind) {
     case FSA_COULOMB_3D:
     case FSA_YUKAWA_3D:
-    case FSA_BIHARMONIC_3D: return 3;
+    case FSA_BIHARMONIC_3D:
+    case FSA_DDI_3D: return 3;
     case FSA_LOG_2D:
     case FSA_COULOMB_2D:
     case FSA_BIHARMONIC_2D: return 2;
@@ -66,6 +67,17 @@ fsa_status fsa_plan_create(const fsa_kernel* k, int d, const double* L, const in
         return fail(FSA_EINVAL, "fsa_plan_create: unknown precision %d", (int)p);
     if (k->kind == FSA_YUKAWA_3D && !(k->lambda > 0.0 && std::isfinite(k->lambda)))
         return fail(FSA_EINVAL, "fsa_plan_create: Yukawa needs lambda > 0");
+    if (k->kind == FSA_DDI_3D) {
+        double nn = 0.0, mm = 0.0;
+        bool finite = true;
+        for (int j = 0; j < 3; ++j) {
+            finite = finite && std::isfinite(k->n[j]) && std::isfinite(k->m[j]);
+            nn += k->n[j] * k->n[j];
+            mm += k->m[j] * k->m[j];
+        }
+        if (!finite || !(nn > 0.0) || !(mm > 0.0))
+            return fail(FSA_EINVAL, "fsa_plan_create: DDI needs finite, nonzero n and m");
+    }
     double minL = 1e300, maxh = 0.0;
     for (int j = 0; j < d; ++j) {
         if (!(L[j] > 0.0 && std::isfinite(L[j])))
@@ -94,7 +106,15 @@ fsa_status fsa_plan_create(const fsa_kernel* k, int d, const double* L, const in
     if (!pl) return fail(FSA_ENOMEM, "fsa_plan_create: out of host memory");
     static std::atomic<uint64_t> next_id{1};
     pl->id = next_id.fetch_add(1);
-    pl->kp = fsa::KernelParams{k->kind, k->kind == FSA_YUKAWA_3D ? k->lambda : 0.0, eps};
+    // a dipole-dipole plan convolves with the Coulomb tensor
+    pl->ddi = k->kind == FSA_DDI_3D;
+    pl->kp = fsa::KernelParams{pl->ddi ? FSA_COULOMB_3D : k->kind,
+                               k->kind == FSA_YUKAWA_3D ? k->lambda : 0.0, eps};
+    if (pl->ddi)
+        for (int j = 0; j < 3; ++j) {
+            pl->dn[j] = k->n[j];
+            pl->dm[j] = k->m[j];
+        }
     pl->d = d;
     pl->prec = p;
     for (int j = 0; j < d; ++j) {
@@ -126,6 +146,12 @@ fsa_status fsa_plan_create(const fsa_kernel* k, int d, const double* L, const in
     off += Nl;
     pl->tw_off_pl = off;
     off += 2 * Nl;
+    if (pl->ddi) {  // unpadded transforms of the derivative on the N-grid
+        pl->tw_off_n0 = off;
+        off += N[0];
+        pl->tw_off_n1 = off;
+        off += N[1];
+    }
     pl->tw_elems = off;
     *out = pl;
     return FSA_OK;
@@ -177,6 +203,10 @@ fsa_status fsa_build_tensor(fsa_plan pl, void* stream) {
         e = fsa::build_twiddles(pl->prec, (int)Nl, tw + pl->tw_off_m * pl->csize, st);
     if (e == hipSuccess)
         e = fsa::build_twiddles(pl->prec, (int)(2 * Nl), tw + pl->tw_off_pl * pl->csize, st);
+    if (e == hipSuccess && pl->ddi)
+        e = fsa::build_twiddles(pl->prec, (int)pl->N[0], tw + pl->tw_off_n0 * pl->csize, st);
+    if (e == hipSuccess && pl->ddi)
+        e = fsa::build_twiddles(pl->prec, (int)pl->N[1], tw + pl->tw_off_n1 * pl->csize, st);
     if (e != hipSuccess) return hip_fail(e, "fsa_build_tensor: twiddle kernels");
     e = fsa::build_tensor_device(pl->kp, pl->d, pl->L, pl->N, pl->h, pl->prec, pl->tensor, st);
     if (e == hipErrorOutOfMemory)
@@ -226,19 +256,29 @@ static hipError_t launch_pass_t(const fsa_plan_s* pl, int k, int lo, int n, cons
     if (pl->d == 3) {
         const int N2 = (int)pl->N[2];
         char* w2 = w1 + ((pl->ws1_elems * cs + 255) & ~size_t(255));
+        // dipole-dipole: pass A convolves -3 d_nm rho (left in the second
+        // workspace array by the derivative launches) and pass E adds
+        // -(m.n) rho
+        const void* src = pl->ddi ? (const void*)w2 : rho;
+        const void* add = pl->ddi ? rho : nullptr;
+        const double alpha =
+            pl->ddi ? -(pl->dn[0] * pl->dm[0] + pl->dn[1] * pl->dm[1] + pl->dn[2] * pl->dm[2])
+                    : 0.0;
         switch (k) {
-        case 0: return Launch<R>::r2c(N2, (const R*)rho, w1, N0, N1, tw_m, tw_pl, c, st);
+        case 0: return Launch<R>::r2c(N2, (const R*)src, w1, N0, N1, tw_m, tw_pl, c, st);
         case 1: return Launch<R>::fwd_t(2 * N1, w1, w2, N0, H, lo, n, tw_p1, c, st);
         case 2:
             return Launch<R>::conv(2 * N0, w2, tensor, n * 2 * N1, 2 * N1, N1, lo, tw_p0, c, st);
         case 3: return Launch<R>::inv_t(2 * N1, w2, w1, N0, H, lo, n, tw_p1, c, st);
-        case 4: return Launch<R>::c2r(N2, w1, (R*)phi, N0, N1, tw_m, tw_pl, c, st);
+        case 4:
+            return Launch<R>::c2r(N2, w1, (R*)phi, N0, N1, add, alpha, tw_m, tw_pl, c, st);
         }
     } else {
         switch (k) {
         case 0: return Launch<R>::r2c(N1, (const R*)rho, w1, 1, N0, tw_m, tw_pl, c, st);
         case 1: return Launch<R>::conv(2 * N0, w1, tensor, H, 1, 0, 0, tw_p0, c, st);
-        case 2: return Launch<R>::c2r(N1, w1, (R*)phi, 1, N0, tw_m, tw_pl, c, st);
+        case 2:
+            return Launch<R>::c2r(N1, w1, (R*)phi, 1, N0, nullptr, 0.0, tw_m, tw_pl, c, st);
         }
     }
     return hipErrorInvalidValue;
@@ -246,6 +286,11 @@ static hipError_t launch_pass_t(const fsa_plan_s* pl, int k, int lo, int n, cons
 
 hipError_t launch_step(const fsa_plan_s* pl, const Step& s, const void* rho, void* phi, void* ws,
                        Choice c, hipStream_t st) {
+    if (s.k >= kSpectralStep) {  // derivative of a dipole-dipole plan
+        char* w1 = (char*)ws;
+        char* w2 = w1 + ((pl->ws1_elems * pl->csize + 255) & ~size_t(255));
+        return spectral_step(pl, s.k - kSpectralStep, rho, w1, w2, st);
+    }
     return pl->prec == FSA_F32
                ? launch_pass_t<float>(pl, s.k, s.lo, s.n, rho, phi, ws, c, st)
                : launch_pass_t<double>(pl, s.k, s.lo, s.n, rho, phi, ws, c, st);
@@ -261,6 +306,8 @@ int schedule(const fsa_plan_s* pl, int slabs, Step* out) {
     if (slabs < 1) slabs = 1;
     if (slabs > kMaxSlabs) slabs = kMaxSlabs;
     if (slabs > H) slabs = H;
+    if (pl->ddi)
+        for (int i = 0; i < kSpectralSteps; ++i) out[m++] = Step{kSpectralStep + i, 0, 0};
     out[m++] = Step{0, 0, H};
     for (int c = 0; c < slabs; ++c) {
         const int lo = (int)((long)H * c / slabs), hi = (int)((long)H * (c + 1) / slabs);
@@ -285,6 +332,7 @@ long step_lines(const fsa_plan_s* pl, const Step& s) {
 }
 
 Choice step_choice(const fsa_plan_s* pl, const Step& s) {
+    if (s.k >= kSpectralStep) return Choice{};
     Pass pass;
     int len;
     pass_of(pl, s.k, &pass, &len);
@@ -349,6 +397,10 @@ fsa_status fsa_plan_launches(fsa_plan pl, int* n, int* passes, int cap) {
     if (passes) {
         if (cap < ns) return fail(FSA_EINVAL, "fsa_plan_launches: need room for %d entries", ns);
         for (int i = 0; i < ns; ++i) {
+            if (steps[i].k >= fsa::kSpectralStep) {
+                passes[i] = FSA_PASS_SPECTRAL;
+                continue;
+            }
             fsa::Pass pass;
             int len;
             fsa::pass_of(pl, steps[i].k, &pass, &len);

@@ -31,6 +31,12 @@ inline bool grid_length_supported(int64_t n) {
 // Forget cached batch graphs that use a plan (fsa_batch.cpp).
 void batch_forget_plan(uint64_t plan_id);
 
+// The d_nm rho launches of a dipole-dipole plan (fsa_spectral.hip): step s
+// in [0, 5) of the spectral derivative on the N-grid, reading rho and
+// leaving -3 d_nm rho (real, plan precision) at dst.
+hipError_t spectral_step(const fsa_plan_s* pl, int s, const void* rho, void* z, void* dst,
+                         hipStream_t st);
+
 // Tensor generation (fsa_tensor.hip).
 hipError_t build_tensor_device(const KernelParams& kp, int d, const double* L, const int64_t* N,
                                const double* h, fsa_precision prec, void* tensor_out,
@@ -56,7 +62,8 @@ struct LaunchV {
     static hipError_t r2c(int M, const R* rho, void* out, int n_outer, int n_inner,
                           const void* twM, const void* tw2M, int occ, hipStream_t st);
     static hipError_t c2r(int M, const void* in, R* phi, int n_outer, int n_inner,
-                          const void* twM, const void* tw2M, int occ, hipStream_t st);
+                          const void* add, double alpha, const void* twM, const void* tw2M,
+                          int occ, hipStream_t st);
     static hipError_t fwd_t(int P, const void* in, void* out, int N0, int H, int p2_lo, int p2_n,
                             const void* tw, int occ, hipStream_t st);
     static hipError_t inv_t(int P, const void* in, void* out, int N0, int H, int p2_lo, int p2_n,
@@ -91,8 +98,9 @@ struct Launch {
         FSA_DISPATCH(r2c(M, rho, out, n_outer, n_inner, twM, tw2M, c.occ, st))
     }
     static hipError_t c2r(int M, const void* in, R* phi, int n_outer, int n_inner,
-                          const void* twM, const void* tw2M, Choice c, hipStream_t st) {
-        FSA_DISPATCH(c2r(M, in, phi, n_outer, n_inner, twM, tw2M, c.occ, st))
+                          const void* add, double alpha, const void* twM, const void* tw2M,
+                          Choice c, hipStream_t st) {
+        FSA_DISPATCH(c2r(M, in, phi, n_outer, n_inner, add, alpha, twM, tw2M, c.occ, st))
     }
     static hipError_t fwd_t(int P, const void* in, void* out, int N0, int H, int p2_lo, int p2_n,
                             const void* tw, Choice c, hipStream_t st) {
@@ -160,7 +168,10 @@ struct Step {
     int k, lo, n;
 };
 constexpr int kMaxSlabs = 16;
-constexpr int kMaxSteps = 2 + 3 * kMaxSlabs;
+// a dipole-dipole plan runs kSpectralSteps derivative launches first, as
+// steps k = kSpectralStep + i
+constexpr int kSpectralStep = 5, kSpectralSteps = 5;
+constexpr int kMaxSteps = 2 + 3 * kMaxSlabs + kSpectralSteps;
 // Launch order of one evaluation with `slabs` slabs of bins (clamped to
 // [1, min(H, kMaxSlabs)]; 2D plans always have 3 launches).
 int schedule(const fsa_plan_s* pl, int slabs, Step* out);
@@ -199,7 +210,12 @@ struct fsa_plan_s {
     size_t tensor_elems = 0;  // octant elements
     // twiddle tables (elements from the start of `twiddles`)
     size_t tw_off_p0 = 0, tw_off_p1 = 0, tw_off_m = 0, tw_off_pl = 0;
+    size_t tw_off_n0 = 0, tw_off_n1 = 0;  // DDI: lengths N_0, N_1 (N_2 is tw_off_m)
     size_t tw_elems = 0;
+    // dipole-dipole plans: the tensor is the Coulomb one (kp.kind), the
+    // derivative d_nm runs before the passes
+    bool ddi = false;
+    double dn[3] = {0, 0, 0}, dm[3] = {0, 0, 0};
     // device state
     int device = -1;
     void* tensor = nullptr;

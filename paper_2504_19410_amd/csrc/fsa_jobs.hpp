@@ -13,6 +13,8 @@ struct JobC2r {   // pass E: X -> phi rows
     const void* in;
     void* phi;
     int n_outer, n_inner;
+    const void* add = nullptr;  // if set: phi += alpha * add (same layout as phi)
+    double alpha = 0.0;
 };
 struct JobT {     // passes B and D (3D): X1[i0][p2][i1] <-> X2[p2][p1][i0]
     const void* in;

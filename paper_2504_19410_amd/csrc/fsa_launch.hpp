@@ -152,14 +152,15 @@ hipError_t LaunchV<R, VAR>::r2c(int M, const R* rho, void* out, int n_outer, int
 
 template <typename R, int VAR>
 hipError_t LaunchV<R, VAR>::c2r(int M, const void* in, R* phi, int n_outer, int n_inner,
-                                const void* twM, const void* tw2M, int occ, hipStream_t st) {
+                                const void* add, double alpha, const void* twM,
+                                const void* tw2M, int occ, hipStream_t st) {
     using S = JobOne<JobC2r>;
     switch (M) {
 #define FSA_CASE(m)                                                                              \
     case m:                                                                                      \
-        return detail::go_c2r<R, VAR, m>(                                                        \
-            S{JobC2r{in, phi, n_outer, n_inner}, cdiv(n_inner, C2r<R, m, VAR>::WT) * n_outer},   \
-            twM, tw2M, occ, st);
+        return detail::go_c2r<R, VAR, m>(S{JobC2r{in, phi, n_outer, n_inner, add, alpha},        \
+                                           cdiv(n_inner, C2r<R, m, VAR>::WT) * n_outer},         \
+                                         twM, tw2M, occ, st);
         FSA_M_LIST(FSA_CASE)
 #undef FSA_CASE
     }

@@ -227,7 +227,8 @@ __global__ __launch_bounds__((R2c<R, M, VAR>::THREADS)) void k_r2c(
 
 // ---------------------------------------------------------------------------
 // Pass E: complex-to-real along the contiguous axis with crop, transposed in
-//   in[(outer * (M+1) + k) * n_inner + inner] -> phi row r, first M reals of 2M.
+//   in[(outer * (M+1) + k) * n_inner + inner] -> phi row r, first M reals of 2M
+// (plus alpha times the same row of `add` when the job carries one).
 // Persistent; the next item's tile is prefetched into registers.
 // ---------------------------------------------------------------------------
 template <typename R, int M, int VAR = 0>
@@ -319,9 +320,19 @@ __global__ __launch_bounds__((C2r<R, M, VAR>::THREADS)) void k_c2r(
         else F::run_g(v, scr, tid, twM);
         const int inner = col0 + team;
         if (inner < n_inner) {
-            R* row = (R*)jb.phi + ((size_t)outer * n_inner + inner) * M;
-            F::store_last(v, tid, M / 2,
-                          [&](int m, C z) { *reinterpret_cast<C*>(row + 2 * m) = z; });
+            const size_t r0 = ((size_t)outer * n_inner + inner) * M;
+            R* row = (R*)jb.phi + r0;
+            if (jb.add) {  // phi += alpha * add, element by element (add may be phi)
+                const R* arow = (const R*)jb.add + r0;
+                const R al = (R)jb.alpha;
+                F::store_last(v, tid, M / 2, [&](int m, C z) {
+                    const C a = *reinterpret_cast<const C*>(arow + 2 * m);
+                    *reinterpret_cast<C*>(row + 2 * m) = mk(z.x + al * a.x, z.y + al * a.y);
+                });
+            } else {
+                F::store_last(v, tid, M / 2,
+                              [&](int m, C z) { *reinterpret_cast<C*>(row + 2 * m) = z; });
+            }
         }
         sync_wg_lds();
     }

@@ -292,6 +292,11 @@ fsa_status fsa_server_submit(fsa_server s, const fsa_kernel* k, int d, const dou
         fsa::set_last_error("fsa_server_submit: bad arguments");
         return FSA_EINVAL;
     }
+    if (k->kind == FSA_DDI_3D) {
+        fsa::set_last_error("fsa_server_submit: dipole-dipole requests are not served "
+                            "(use a plan and fsa_apply)");
+        return FSA_EUNSUPPORTED;
+    }
     Key key;
     key.kind = k->kind;
     key.d = d;

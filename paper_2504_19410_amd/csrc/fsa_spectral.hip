@@ -1,0 +1,209 @@
+// fsa_spectral.hip -- the source term of the dipole-dipole potential.
+//
+// The 3D DDI is evaluated through the Coulomb kernel with the source
+// d_nm rho = (n.grad)(m.grad) rho (Sec. 5.3):
+//   Phi = -(m.n) rho - 3 Coulomb(d_nm rho).
+// d_nm rho is the spectral derivative of rho on its own N-point grid,
+// periodic on the box: a 3D DFT, the product with -(k.n)(k.m),
+// k_j = pi q_j / L_j (q_j = i_j for i_j < N_j/2, else i_j - N_j), an inverse
+// DFT and the real part.  Five launches on a complex N0 x N1 x N2 array Z in
+// the first workspace array, leaving -3 d_nm rho (real, plan precision) in
+// the second one, where pass A of the Coulomb convolution reads it:
+//   0  rows of rho (last axis, real) -> forward FFT -> Z
+//   1  Z along axis 1, forward
+//   2  Z along axis 0: forward, x 3 (k.n)(k.m) / (N0 N1 N2), inverse
+//   3  Z along axis 1, inverse
+//   4  Z rows, inverse, real part -> -3 d_nm rho
+// (3 (k.n)(k.m) / prod N folds the -3, the sign of the derivative and the
+// normalisation of the inverse DFT into one factor.)  Every launch stages a
+// tile of WT lines adjacent in memory through LDS, so the strided axes are
+// read and written in rows of WT consecutive elements; each team of the
+// workgroup transforms one line with the team FFT.  Launches 1-3 work in
+// place (each workgroup reads its whole tile before it writes it back).
+#include <hip/hip_runtime.h>
+
+#include "fsa_internal.hpp"
+
+namespace fsa {
+
+namespace {
+
+enum SpecKind { ROW_FWD_REAL = 0, COL_FWD = 1, COL_MUL = 2, COL_INV = 3, ROW_INV_REAL = 4 };
+
+constexpr int spec_lines_per_group(int T, int scr, int P, int csize) {
+    int wt = 128 / csize;
+    while (wt > 1 && (wt * T > 1024 || (wt * scr + P * (wt + 1)) * csize > 160 * 1024)) wt /= 2;
+    return wt;
+}
+
+template <typename R, int P>
+struct Spec {
+    using Ff = Fft<R, P, false>;
+    using Fi = Fft<R, P, true>;
+    static constexpr int T = Ff::T;
+    static constexpr int WT = spec_lines_per_group(T, Ff::SCR, P, (int)sizeof(cpx<R>));
+    static constexpr int TS = WT + 1;
+    static constexpr int THREADS = WT * T;
+    static_assert(Ff::last_radix() == Fi::first_radix(), "register hand-off");
+};
+
+// Lines of one launch: line (u, v) starts at u * u_stride + v * v_stride
+// (elements), its element t at + t * es; groups take WT consecutive u.
+struct SLines {
+    int n_u, n_v;
+    long u_stride, v_stride, es;
+};
+
+// The derivative factor of the axis-0 launch.
+struct SMul {
+    double c[3];      // pi / L_j
+    double n[3], m[3];
+    double scale;     // 3 / (N0 N1 N2)
+    int N[3];
+};
+
+template <typename R, int P, int KIND>
+__global__ __launch_bounds__((Spec<R, P>::THREADS)) void k_spec(const void* in,
+                                                             void* out, SLines ln,
+                                                             const cpx<R>* __restrict__ tw,
+                                                             SMul mul) {
+    using K = Spec<R, P>;
+    using Ff = typename K::Ff;
+    using Fi = typename K::Fi;
+    using C = cpx<R>;
+    __shared__ C scr[K::WT * Ff::SCR];
+    __shared__ C tile[P * K::TS];
+    const int team = threadIdx.x / K::T, tid = threadIdx.x % K::T;
+    const int ntu = (ln.n_u + K::WT - 1) / K::WT;
+    const int tu = blockIdx.x % ntu, v = blockIdx.x / ntu;
+    const long base = (long)tu * K::WT * ln.u_stride + (long)v * ln.v_stride;
+    const int nw = ln.n_u - tu * K::WT < K::WT ? ln.n_u - tu * K::WT : K::WT;
+    // tile element e -> (t, w), the contiguous direction fastest
+    auto at = [&](int e, int& t, int& w) {
+        if (ln.es == 1) {
+            w = e / P;
+            t = e - w * P;
+        } else {
+            t = e / K::WT;
+            w = e - t * K::WT;
+        }
+    };
+    for (int e = threadIdx.x; e < P * K::WT; e += K::THREADS) {
+        int t, w;
+        at(e, t, w);
+        C x = mk(R(0), R(0));
+        if (w < nw) {
+            const long i = base + w * ln.u_stride + t * ln.es;
+            if constexpr (KIND == ROW_FWD_REAL) x = mk(((const R*)in)[i], R(0));
+            else x = ((const C*)in)[i];
+        }
+        tile[t * K::TS + w] = x;
+    }
+    __syncthreads();
+    C x[Ff::V];
+    // the inverse runs the radices in reverse: its first stage has its own layout
+    if constexpr (KIND == COL_INV || KIND == ROW_INV_REAL)
+        Fi::load_first(x, tid, P, [&](int t) { return tile[t * K::TS + team]; });
+    else
+        Ff::load_first(x, tid, P, [&](int t) { return tile[t * K::TS + team]; });
+    __syncthreads();
+    C* sc = scr + team * Ff::SCR;
+    if constexpr (KIND == ROW_FWD_REAL || KIND == COL_FWD) {
+        Ff::run_g(x, sc, tid, tw);
+        Ff::store_last(x, tid, P, [&](int t, C c) { tile[t * K::TS + team] = c; });
+    } else if constexpr (KIND == COL_MUL) {
+        Ff::run_g(x, sc, tid, tw);
+        // line (u = i2, v = i1) along axis 0; the register holds output i0
+        const int i2 = tu * K::WT + team, i1 = v;
+        const int q1 = i1 < mul.N[1] / 2 ? i1 : i1 - mul.N[1];
+        const int q2 = i2 < mul.N[2] / 2 ? i2 : i2 - mul.N[2];
+        const double k1 = mul.c[1] * q1, k2 = mul.c[2] * q2;
+        Ff::for_each_last(x, tid, [&](int i0, C& c) {
+            const int q0 = i0 < mul.N[0] / 2 ? i0 : i0 - mul.N[0];
+            const double k0 = mul.c[0] * q0;
+            const double kn = k0 * mul.n[0] + k1 * mul.n[1] + k2 * mul.n[2];
+            const double km = k0 * mul.m[0] + k1 * mul.m[1] + k2 * mul.m[2];
+            c = scale(c, (R)(mul.scale * kn * km));
+        });
+        Fi::run_g(x, sc, tid, tw);
+        Fi::store_last(x, tid, P, [&](int t, C c) { tile[t * K::TS + team] = c; });
+    } else {
+        Fi::run_g(x, sc, tid, tw);
+        Fi::store_last(x, tid, P, [&](int t, C c) { tile[t * K::TS + team] = c; });
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < P * K::WT; e += K::THREADS) {
+        int t, w;
+        at(e, t, w);
+        if (w < nw) {
+            const long i = base + w * ln.u_stride + t * ln.es;
+            if constexpr (KIND == ROW_INV_REAL) ((R*)out)[i] = tile[t * K::TS + w].x;
+            else ((C*)out)[i] = tile[t * K::TS + w];
+        }
+    }
+}
+
+template <typename R, int KIND>
+hipError_t go(int P, const void* in, void* out, SLines ln, const void* tw, const SMul& mul,
+              hipStream_t st) {
+    switch (P) {
+#define FSA_SPEC_CASE(p)                                                                        \
+    case p: {                                                                                   \
+        using K = Spec<R, p>;                                                                   \
+        const int groups = (ln.n_u + K::WT - 1) / K::WT * ln.n_v;                               \
+        hipLaunchKernelGGL((k_spec<R, p, KIND>), dim3(groups), dim3(K::THREADS), 0, st, in,     \
+                           out, ln, (const cpx<R>*)tw, mul);                                    \
+        return hipGetLastError();                                                               \
+    }
+        FSA_SPEC_CASE(8) FSA_SPEC_CASE(12) FSA_SPEC_CASE(16) FSA_SPEC_CASE(24) FSA_SPEC_CASE(32)
+        FSA_SPEC_CASE(48) FSA_SPEC_CASE(64) FSA_SPEC_CASE(96) FSA_SPEC_CASE(128)
+        FSA_SPEC_CASE(192) FSA_SPEC_CASE(256) FSA_SPEC_CASE(384) FSA_SPEC_CASE(512)
+        FSA_SPEC_CASE(768) FSA_SPEC_CASE(1024) FSA_SPEC_CASE(1536) FSA_SPEC_CASE(2048)
+#undef FSA_SPEC_CASE
+    }
+    return hipErrorInvalidValue;
+}
+
+template <typename R>
+hipError_t step_t(const fsa_plan_s* pl, int s, const void* rho, void* z, void* dst,
+                  hipStream_t st) {
+    const long N0 = pl->N[0], N1 = pl->N[1], N2 = pl->N[2];
+    const char* tw = (const char*)pl->twiddles;
+    const void* tw0 = tw + pl->tw_off_n0 * pl->csize;
+    const void* tw1 = tw + pl->tw_off_n1 * pl->csize;
+    const void* tw2 = tw + pl->tw_off_m * pl->csize;  // length N2
+    SMul mul{};
+    double prodN = 1.0;
+    for (int j = 0; j < 3; ++j) {
+        mul.c[j] = 3.14159265358979323846264338327950288 / pl->L[j];
+        mul.n[j] = pl->dn[j];
+        mul.m[j] = pl->dm[j];
+        mul.N[j] = (int)pl->N[j];
+        prodN *= (double)pl->N[j];
+    }
+    mul.scale = 3.0 / prodN;
+    // rows: lines along axis 2, groups of consecutive rows
+    const SLines rows{(int)N1, (int)N0, N2, N1 * N2, 1};
+    // axis 1: lines at fixed (i0, i2), groups of consecutive i2
+    const SLines ax1{(int)N2, (int)N0, 1, N1 * N2, N2};
+    // axis 0: lines at fixed (i1, i2), groups of consecutive i2
+    const SLines ax0{(int)N2, (int)N1, 1, N2, N1 * N2};
+    switch (s) {
+    case 0: return go<R, ROW_FWD_REAL>((int)N2, rho, z, rows, tw2, mul, st);
+    case 1: return go<R, COL_FWD>((int)N1, z, z, ax1, tw1, mul, st);
+    case 2: return go<R, COL_MUL>((int)N0, z, z, ax0, tw0, mul, st);
+    case 3: return go<R, COL_INV>((int)N1, z, z, ax1, tw1, mul, st);
+    case 4: return go<R, ROW_INV_REAL>((int)N2, z, dst, rows, tw2, mul, st);
+    }
+    return hipErrorInvalidValue;
+}
+
+}  // namespace
+
+hipError_t spectral_step(const fsa_plan_s* pl, int s, const void* rho, void* z, void* dst,
+                         hipStream_t st) {
+    return pl->prec == FSA_F32 ? step_t<float>(pl, s, rho, z, dst, st)
+                               : step_t<double>(pl, s, rho, z, dst, st);
+}
+
+}  // namespace fsa

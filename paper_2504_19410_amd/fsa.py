@@ -25,9 +25,10 @@ KINDS = {
     "coulomb2d": 4,
     "biharmonic3d": 5,
     "biharmonic2d": 6,
+    "ddi3d": 7,
 }
 KIND_DIM = {"coulomb3d": 3, "yukawa3d": 3, "biharmonic3d": 3,
-            "log2d": 2, "coulomb2d": 2, "biharmonic2d": 2}
+            "log2d": 2, "coulomb2d": 2, "biharmonic2d": 2, "ddi3d": 3}
 PRECISIONS = {"f32": 0, "f64": 1}
 DTYPES = {"f32": torch.float32, "f64": torch.float64}
 
@@ -50,6 +51,7 @@ EXPORTS = (
 
 # fsa_pass: the passes of one evaluation, in execution order for 3D
 PASSES = {"r2c": 0, "fwd_t": 1, "conv": 2, "inv_t": 3, "c2r": 4}
+LAUNCH_KINDS = dict(PASSES, spectral=5)
 
 
 class FsaError(RuntimeError):
@@ -59,7 +61,8 @@ class FsaError(RuntimeError):
 
 
 class _Kernel(ctypes.Structure):
-    _fields_ = [("kind", ctypes.c_int), ("lambda_", ctypes.c_double), ("eps", ctypes.c_double)]
+    _fields_ = [("kind", ctypes.c_int), ("lambda_", ctypes.c_double), ("eps", ctypes.c_double),
+                ("n", ctypes.c_double * 3), ("m", ctypes.c_double * 3)]
 
 
 class Stats(ctypes.Structure):
@@ -139,17 +142,24 @@ def _stream_ptr(stream: Optional[torch.cuda.Stream] = None):
     return ctypes.c_void_p(s.cuda_stream)
 
 
-def _kernel(kind: str, eps: Optional[float], lam: Optional[float]) -> _Kernel:
+def _kernel(kind: str, eps: Optional[float], lam: Optional[float], n=None, m=None) -> _Kernel:
     if kind not in KINDS:
         raise ValueError(f"unknown kernel {kind!r}; choose from {sorted(KINDS)}")
-    return _Kernel(KINDS[kind], float(lam or 0.0), float(eps) if eps else 0.0)
+    k = _Kernel(KINDS[kind], float(lam or 0.0), float(eps) if eps else 0.0)
+    for j, v in enumerate(n if n is not None else (0.0, 0.0, 0.0)):
+        k.n[j] = float(v)
+    for j, v in enumerate(m if m is not None else (0.0, 0.0, 0.0)):
+        k.m[j] = float(v)
+    return k
 
 
 class Plan:
     """A plan for one kernel, box and grid (``fsa_plan_create``)."""
 
     def __init__(self, kernel: str, L: Sequence[float], N: Sequence[int], precision: str = "f32",
-                 eps: Optional[float] = None, lam: Optional[float] = None):
+                 eps: Optional[float] = None, lam: Optional[float] = None,
+                 n: Optional[Sequence[float]] = None, m: Optional[Sequence[float]] = None):
+        """n, m: dipole orientations of the "ddi3d" kernel (ignored otherwise)."""
         if precision not in PRECISIONS:
             raise ValueError(f"precision must be one of {list(PRECISIONS)}")
         self.kernel, self.precision = kernel, precision
@@ -159,7 +169,7 @@ class Plan:
         self.d = len(self.N)
         if len(self.L) != self.d:
             raise ValueError("L and N must have the same length")
-        k = _kernel(kernel, eps, lam)
+        k = _kernel(kernel, eps, lam, n, m)
         Ls = (ctypes.c_double * self.d)(*self.L)
         Ns = (ctypes.c_int64 * self.d)(*self.N)
         h = ctypes.c_void_p()
@@ -237,7 +247,7 @@ class Plan:
         _check(_lib.fsa_plan_launches(self._h, ctypes.byref(n), None, 0))
         arr = (ctypes.c_int * n.value)()
         _check(_lib.fsa_plan_launches(self._h, ctypes.byref(n), arr, n.value))
-        names = {v: k for k, v in PASSES.items()}
+        names = {v: k for k, v in LAUNCH_KINDS.items()}
         return [names[a] for a in arr]
 
     def passes(self):

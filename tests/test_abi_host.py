@@ -76,6 +76,17 @@ def test_plan_validation_params(F):
         F.Plan("coulomb3d", (8, 8, 8), (32, 32, 32), eps=5.0)  # > R0/4
     with pytest.raises(ValueError):
         F.Plan("coulomb3d", (8, 8, 8), (32, 32, 32), precision="bf16")
+    with pytest.raises(F.FsaError, match="DDI"):
+        F.Plan("ddi3d", (8, 8, 8), (32, 32, 32), n=(0, 0, 0), m=(0, 0, 1))
+    with pytest.raises(F.FsaError, match="DDI"):
+        F.Plan("ddi3d", (8, 8, 8), (32, 32, 32), n=(1, 0, float("nan")), m=(0, 0, 1))
+    with pytest.raises(F.FsaError, match="EINVAL"):
+        F.Plan("ddi3d", (8, 8), (32, 32), n=(1, 0, 0), m=(0, 0, 1))   # 3D only
+    # a dipole-dipole plan uses the Coulomb tensor and the same workspace
+    a = F.Plan("ddi3d", (8, 8, 8), (32, 32, 32), n=(1, 0, 0), m=(0, 0, 1))
+    b = F.Plan("coulomb3d", (8, 8, 8), (32, 32, 32))
+    assert (a.eps, a.tensor_bytes, a.workspace_bytes) == (b.eps, b.tensor_bytes,
+                                                          b.workspace_bytes)
 
 
 def test_apply_before_build_is_a_state_error(F):

@@ -147,3 +147,54 @@ def test_parity_yukawa_256(F, prec):
     p = synth.yukawa_problem(1.0, 256, prec)
     rho64 = synth.eval_gaussians(p.gaussians, p.L, p.N)
     assert sampled_parity(F, p.kernel, p.L, p.N, prec, rho64, lam=p.lam, eps=p.eps) <= TOL[prec]
+
+
+DDI_N = (0.82778, 0.41505, -0.37751)
+DDI_M = (0.3118, 0.9378, -0.15214)
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("L,N", [((8.0, 8.0, 8.0), (32, 32, 32)),
+                                 ((3.0, 5.0, 4.0), (24, 16, 48)),
+                                 ((6.0, 6.0, 3.0), (64, 48, 32))])
+def test_parity_ddi(F, L, N, prec):
+    """3D dipole-dipole: -(m.n) rho - 3 Coulomb(d_nm rho), the derivative on
+    the GPU (five spectral launches) and the Coulomb convolution (five passes,
+    the identity term added by pass E), against the oracle."""
+    rho64 = density("coulomb3d", L, N, seed=sum(N) + 7)
+    plan = F.Plan("ddi3d", L, N, prec, n=DDI_N, m=DDI_M).build()
+    launches = plan.launches()
+    assert launches[:5] == ["spectral"] * 5 and launches[5:] == ["r2c", "fwd_t", "conv",
+                                                                  "inv_t", "c2r"]
+    rho = torch.from_numpy(rho64).to(F.DTYPES[prec]).cuda()
+    phi = plan.apply(rho)
+    torch.cuda.synchronize()
+    ref = O.solve_ddi(L, N, rho.double().cpu().numpy(), plan.eps, DDI_N, DDI_M)
+    err = rel_l2(phi.double().cpu().numpy(), ref)
+    print(f"ddi {N} {prec}: rel L2 {err:.3e}")
+    assert err <= TOL[prec]
+    # in place (phi aliases rho): pass E reads each rho value before writing it
+    rho2 = rho.clone()
+    plan.apply(rho2, out=rho2)
+    torch.cuda.synchronize()
+    assert torch.equal(rho2, phi)
+
+
+def test_ddi_not_batched_or_served(F):
+    plan = F.Plan("ddi3d", (8.0,) * 3, (16,) * 3, "f32", n=DDI_N, m=DDI_M).build()
+    r = torch.zeros(16, 16, 16, device="cuda")
+    with pytest.raises(F.FsaError, match="EUNSUPPORTED"):
+        F.apply_batched([plan], [r])
+    srv = F.Server(1 << 30)
+    try:
+        k = F._kernel("ddi3d", None, None, DDI_N, DDI_M)
+        import ctypes
+        t = ctypes.c_uint64()
+        Ls = (ctypes.c_double * 3)(8.0, 8.0, 8.0)
+        Ns = (ctypes.c_int64 * 3)(16, 16, 16)
+        st = F.lib().fsa_server_submit(srv._h, ctypes.byref(k), 3, Ls, Ns, 0,
+                                       ctypes.c_void_p(r.data_ptr()),
+                                       ctypes.c_void_p(r.data_ptr()), ctypes.byref(t))
+        assert F.STATUS[st] == "FSA_EUNSUPPORTED"
+    finally:
+        srv.close()
