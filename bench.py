@@ -243,6 +243,37 @@ def precomp_sweep(F, torch, hip, n=256, gammas=(1, 2, 4, 8, 16), reps=3):
     return {"grid": [n, n, n], "kernel": "coulomb3d", "ms_by_anisotropy": out}
 
 
+def bench_ddi(F, torch, hip, synth, n=256, steps=50, warmup=10):
+    """3D dipole-dipole evaluation at n^3 (FP32 and FP64): the derivative
+    launches plus the Coulomb passes, with the paper's dipole orientations
+    (Sec. 5.3) on the Yukawa workload's density."""
+    prob = synth.yukawa_problem(1.0, n, "f32")
+    rho64 = synth.eval_gaussians(prob.gaussians, prob.L, prob.N)
+    stream = torch.cuda.current_stream()
+    out = {}
+    for prec in ("f32", "f64"):
+        plan = F.Plan("ddi3d", prob.L, prob.N, prec, eps=prob.eps,
+                      n=(0.82778, 0.41505, -0.37751), m=(0.3118, 0.9378, -0.15214)).build()
+        rho = torch.from_numpy(rho64).to(F.DTYPES[prec]).cuda()
+        o = torch.empty_like(rho)
+        ws = plan.workspace()
+        for _ in range(warmup):
+            plan.apply(rho, o, ws)
+        torch.cuda.synchronize()
+        e0, e1 = hip.event(), hip.event()
+        hip.record(e0, stream)
+        for _ in range(steps):
+            plan.apply(rho, o, ws)
+        hip.record(e1, stream)
+        ms = hip.ms(e0, e1) / steps
+        hip.destroy(e0)
+        hip.destroy(e1)
+        plan.close()
+        out[prec] = {"ms_per_step": ms, "value": prob.points / (ms * 1e-3)}
+    return {"workload": f"3D dipole-dipole on the {n}^3 Yukawa-workload density, paper's n and m",
+            "unit": "grid pts/s", **out}
+
+
 def stream_copy(torch, hip, nbytes=1 << 30, reps=10):
     """Device-to-device copy of nbytes (torch copy_ kernel): the practical
     bandwidth of the box, read + write bytes over time."""
@@ -576,6 +607,9 @@ def main():
     del phis
     sweep = precomp_sweep(F, torch, hip, n=args.n)
     log(f"  precomp vs anisotropy (ms): {sweep['ms_by_anisotropy']}")
+    ddi = bench_ddi(F, torch, hip, synth, n=args.n)
+    log(f"  dipole-dipole: FP32 {ddi['f32']['ms_per_step']:.4f} ms, "
+        f"FP64 {ddi['f64']['ms_per_step']:.4f} ms")
     batch = None
     if not args.no_batch:
         log("batched 2D log workload (256 densities) ...")
@@ -633,6 +667,7 @@ def main():
         "model_hbm_frac": r32["model_hbm_frac"],
         "precomp_ms": r32["precomp_ms"],
         "precomp_vs_anisotropy": sweep,
+        "ddi": ddi,
         "wall_ms_per_step": r32["wall_ms_per_step"],
         "f32_vs_f64_rel_l2": diff,
         "batch": batch,

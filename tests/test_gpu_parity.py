@@ -198,3 +198,35 @@ def test_ddi_not_batched_or_served(F):
         assert F.STATUS[st] == "FSA_EUNSUPPORTED"
     finally:
         srv.close()
+
+
+_LARGEST_REF = {}
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("kind,L,N", [
+    ("log2d", (12.0, 10.0), (2048, 2048)),          # the largest grid length on both axes
+    ("coulomb2d", (9.0, 4.0), (1536, 96)),          # 3 * 2^9 padded to 3072
+    ("coulomb3d", (8.0, 2.0, 2.0), (2048, 16, 8)),  # longest pencils of the fused pass
+    ("coulomb3d", (2.0, 2.0, 8.0), (8, 16, 2048)),  # longest rows of the real passes
+    ("coulomb3d", (2.0, 8.0, 2.0), (8, 2048, 16)),  # longest transposed lines
+])
+def test_parity_largest_lengths(F, kind, L, N, prec):
+    """Grid lengths at the 2048 maximum on each axis (and a 3 * 2^a one):
+    transform lengths 2048 (real passes) and 4096 (complex passes), whole-grid
+    relative L2 against the oracle's FFT route."""
+    rho64 = density(kind, L, N, seed=sum(N) + 11)
+    plan, rho_used, phi = run_gpu(F, kind, L, N, prec, rho64)
+    key = (kind, L, N)
+    if key not in _LARGEST_REF:   # one oracle solve per grid (the FP64 density;
+        _LARGEST_REF[key] = O.solve(kind, L, N, rho64, eps=plan.eps)  # FP32 rounding of
+    err = rel_l2(phi, _LARGEST_REF[key])                               # rho is ~1e-7)
+    print(f"{kind} {N} {prec}: rel L2 {err:.3e}")
+    assert err <= TOL[prec]
+
+
+def test_rejects_lengths_beyond_the_maximum(F):
+    with pytest.raises(F.FsaError, match="EUNSUPPORTED"):
+        F.Plan("coulomb3d", (8.0,) * 3, (4096, 8, 8))
+    with pytest.raises(F.FsaError, match="EUNSUPPORTED"):
+        F.Plan("log2d", (8.0, 8.0), (40, 40))    # 5 * 8: radix 5 not supported
