@@ -532,6 +532,7 @@ def main():
     ap.add_argument("--no-batch", action="store_true", help="skip the batched 2D workload")
     ap.add_argument("--batch-only", action="store_true", help="only the batched 2D workload")
     ap.add_argument("--no-serve", action="store_true", help="skip the served workload")
+    ap.add_argument("--no-ddi", action="store_true", help="skip the dipole-dipole timing")
     ap.add_argument("--serve-only", action="store_true", help="only the served workload")
     ap.add_argument("--serve-seconds", type=float, default=3.0)
     ap.add_argument("--no-tune", action="store_true",
@@ -607,9 +608,11 @@ def main():
     del phis
     sweep = precomp_sweep(F, torch, hip, n=args.n)
     log(f"  precomp vs anisotropy (ms): {sweep['ms_by_anisotropy']}")
-    ddi = bench_ddi(F, torch, hip, synth, n=args.n)
-    log(f"  dipole-dipole: FP32 {ddi['f32']['ms_per_step']:.4f} ms, "
-        f"FP64 {ddi['f64']['ms_per_step']:.4f} ms")
+    ddi = None
+    if not args.no_ddi:
+        ddi = bench_ddi(F, torch, hip, synth, n=args.n)
+        log(f"  dipole-dipole: FP32 {ddi['f32']['ms_per_step']:.4f} ms, "
+            f"FP64 {ddi['f64']['ms_per_step']:.4f} ms")
     batch = None
     if not args.no_batch:
         log("batched 2D log workload (256 densities) ...")
