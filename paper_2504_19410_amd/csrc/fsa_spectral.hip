@@ -30,9 +30,14 @@ namespace {
 
 enum SpecKind { ROW_FWD_REAL = 0, COL_FWD = 1, COL_MUL = 2, COL_INV = 3, ROW_INV_REAL = 4 };
 
+// The team scratch and the tile share one LDS array (the tile is idle while
+// the teams transform, the lines being in registers), so a group needs
+// max(WT * SCR, P * (WT + 1)) complex values.
 constexpr int spec_lines_per_group(int T, int scr, int P, int csize) {
     int wt = 128 / csize;
-    while (wt > 1 && (wt * T > 1024 || (wt * scr + P * (wt + 1)) * csize > 160 * 1024)) wt /= 2;
+    while (wt > 1 && (wt * T > 1024 || (wt * scr > P * (wt + 1) ? wt * scr : P * (wt + 1)) *
+                                               csize > 160 * 1024))
+        wt /= 2;
     return wt;
 }
 
@@ -44,6 +49,7 @@ struct Spec {
     static constexpr int WT = spec_lines_per_group(T, Ff::SCR, P, (int)sizeof(cpx<R>));
     static constexpr int TS = WT + 1;
     static constexpr int THREADS = WT * T;
+    static constexpr int LDS = WT * Ff::SCR > P * TS ? WT * Ff::SCR : P * TS;
     static_assert(Ff::last_radix() == Fi::first_radix(), "register hand-off");
 };
 
@@ -71,8 +77,8 @@ __global__ __launch_bounds__((Spec<R, P>::THREADS)) void k_spec(const void* in,
     using Ff = typename K::Ff;
     using Fi = typename K::Fi;
     using C = cpx<R>;
-    __shared__ C scr[K::WT * Ff::SCR];
-    __shared__ C tile[P * K::TS];
+    __shared__ C lds[K::LDS];
+    C* const tile = lds;  // [t][w], also the teams' scratch while they transform
     const int team = threadIdx.x / K::T, tid = threadIdx.x % K::T;
     const int ntu = (ln.n_u + K::WT - 1) / K::WT;
     const int tu = blockIdx.x % ntu, v = blockIdx.x / ntu;
@@ -107,9 +113,11 @@ __global__ __launch_bounds__((Spec<R, P>::THREADS)) void k_spec(const void* in,
     else
         Ff::load_first(x, tid, P, [&](int t) { return tile[t * K::TS + team]; });
     __syncthreads();
-    C* sc = scr + team * Ff::SCR;
+    C* sc = lds + team * Ff::SCR;
+    // every team has finished with its scratch before the tile is rewritten
     if constexpr (KIND == ROW_FWD_REAL || KIND == COL_FWD) {
         Ff::run_g(x, sc, tid, tw);
+        __syncthreads();
         Ff::store_last(x, tid, P, [&](int t, C c) { tile[t * K::TS + team] = c; });
     } else if constexpr (KIND == COL_MUL) {
         Ff::run_g(x, sc, tid, tw);
@@ -126,9 +134,11 @@ __global__ __launch_bounds__((Spec<R, P>::THREADS)) void k_spec(const void* in,
             c = scale(c, (R)(mul.scale * kn * km));
         });
         Fi::run_g(x, sc, tid, tw);
+        __syncthreads();
         Fi::store_last(x, tid, P, [&](int t, C c) { tile[t * K::TS + team] = c; });
     } else {
         Fi::run_g(x, sc, tid, tw);
+        __syncthreads();
         Fi::store_last(x, tid, P, [&](int t, C c) { tile[t * K::TS + team] = c; });
     }
     __syncthreads();
