@@ -7,6 +7,7 @@ tuned path must still match, the batched path must stay bitwise equal to the
 solo path, and a saved table must load back on the same device.
 """
 import ctypes
+import os
 
 import numpy as np
 import pytest
@@ -180,3 +181,63 @@ def test_apply_events_follow_the_schedule(F):
     assert torch.equal(out, ref)
     for e in evs:
         lib.hipEventDestroy(ctypes.c_void_p(e))
+
+
+SHIPPED = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))),
+                       "paper_2504_19410_amd", "tune", "gfx950.json")
+
+
+def sampled_rel_l2(kind, L, N, eps, lam, rho_used, phi, npts=40, seed=0):
+    T = O.build_tensor(kind, L, N, eps, lam=lam or 0.0)
+    rng = np.random.default_rng(seed)
+    idx = np.unique(np.concatenate([rng.choice(phi.size, npts, replace=False),
+                                    [int(np.argmax(np.abs(phi))), 0, phi.size - 1]]))
+    ref = O.conv_direct_points(T, rho_used, idx)
+    return rel_l2(phi.ravel()[idx], ref)
+
+
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_bench_configuration_parity(F, prec):
+    """The 256^3 Yukawa evaluation in the launch configuration bench.py times:
+    the shipped tuning table (variants, occupancy, slab schedule) loaded,
+    outputs sampled and summed directly by the oracle."""
+    if not os.path.exists(SHIPPED):
+        pytest.skip("no shipped table")
+    F.tune_load(SHIPPED)
+    p = synth.yukawa_problem(1.0, 256, prec)
+    plan = F.Plan(p.kernel, p.L, p.N, prec, eps=p.eps, lam=p.lam).build()
+    rho = torch.from_numpy(synth.eval_gaussians(p.gaussians, p.L, p.N)).to(F.DTYPES[prec]).cuda()
+    phi = plan.apply(rho)
+    torch.cuda.synchronize()
+    err = sampled_rel_l2(p.kernel, p.L, p.N, plan.eps, p.lam, rho.double().cpu().numpy(),
+                         phi.double().cpu().numpy())
+    print(f"bench configuration {prec}: launches {plan.launches()}, sampled rel L2 {err:.3e}")
+    assert err <= TOL[prec]
+
+
+def test_bench_batch_configuration_parity(F):
+    """The 256-problem 2D log batch as bench.py runs it (shipped table, one
+    captured graph): four problems of different shapes checked on sampled
+    outputs against the oracle's direct sum."""
+    if not os.path.exists(SHIPPED):
+        pytest.skip("no shipped table")
+    F.tune_load(SHIPPED)
+    probs = synth.log2d_batch(256)
+    plans = [F.Plan(q.kernel, q.L, q.N, "f32") for q in probs]
+    for pl in plans:
+        pl.build()
+    rhos = [torch.from_numpy(synth.eval_gaussians(q.gaussians, q.L, q.N, dtype=np.float32)).cuda()
+            for q in probs]
+    outs = F.apply_batched(plans, rhos)
+    torch.cuda.synchronize()
+    seen = {}
+    for i, q in enumerate(probs):
+        if q.N not in seen and len(seen) < 4:
+            seen[q.N] = i
+    for N, i in seen.items():
+        q = probs[i]
+        err = sampled_rel_l2(q.kernel, q.L, q.N, plans[i].eps, None,
+                             rhos[i].double().cpu().numpy(), outs[i].double().cpu().numpy(),
+                             npts=24, seed=i)
+        print(f"batch problem {i} {N}: sampled rel L2 {err:.3e}")
+        assert err <= TOL["f32"]
