@@ -15,10 +15,11 @@
 //   3  Z along axis 1, inverse
 //   4  Z rows, inverse, real part -> -3 d_nm rho
 // (3 (k.n)(k.m) / prod N folds the -3, the sign of the derivative and the
-// normalisation of the inverse DFT into one factor.)  Every launch stages a
-// tile of WT lines adjacent in memory through LDS, so the strided axes are
-// read and written in rows of WT consecutive elements; each team of the
-// workgroup transforms one line with the team FFT.  Launches 1-3 work in
+// normalisation of the inverse DFT into one factor.)  Each team of a
+// workgroup transforms one line with the team FFT.  Launches along the
+// strided axes stage a tile of WT lines adjacent in memory through LDS, so
+// they read and write rows of WT consecutive elements; the row launches read
+// and write their contiguous rows directly.  Launches 1-3 work in
 // place (each workgroup reads its whole tile before it writes it back).
 #include <hip/hip_runtime.h>
 
@@ -84,6 +85,27 @@ __global__ __launch_bounds__((Spec<R, P>::THREADS)) void k_spec(const void* in,
     const int tu = blockIdx.x % ntu, v = blockIdx.x / ntu;
     const long base = (long)tu * K::WT * ln.u_stride + (long)v * ln.v_stride;
     const int nw = ln.n_u - tu * K::WT < K::WT ? ln.n_u - tu * K::WT : K::WT;
+    if constexpr (KIND == ROW_FWD_REAL || KIND == ROW_INV_REAL) {
+        // rows are contiguous: each team reads and writes its own row straight
+        // from and to global memory (the team's accesses are consecutive)
+        const bool act = team < nw;
+        const long rb = base + team * ln.u_stride;
+        C* sc = lds + team * Ff::SCR;
+        C x[Ff::V];
+        if constexpr (KIND == ROW_FWD_REAL) {
+            Ff::load_first(x, tid, P, [&](int t) {
+                return act ? mk(((const R*)in)[rb + t], R(0)) : mk(R(0), R(0));
+            });
+            Ff::run_g(x, sc, tid, tw);
+            if (act) Ff::store_last(x, tid, P, [&](int t, C c) { ((C*)out)[rb + t] = c; });
+        } else {
+            Fi::load_first(x, tid, P,
+                           [&](int t) { return act ? ((const C*)in)[rb + t] : mk(R(0), R(0)); });
+            Fi::run_g(x, sc, tid, tw);
+            if (act) Fi::store_last(x, tid, P, [&](int t, C c) { ((R*)out)[rb + t] = c.x; });
+        }
+        return;
+    }
     // tile element e -> (t, w), the contiguous direction fastest
     auto at = [&](int e, int& t, int& w) {
         if (ln.es == 1) {
@@ -100,22 +122,21 @@ __global__ __launch_bounds__((Spec<R, P>::THREADS)) void k_spec(const void* in,
         C x = mk(R(0), R(0));
         if (w < nw) {
             const long i = base + w * ln.u_stride + t * ln.es;
-            if constexpr (KIND == ROW_FWD_REAL) x = mk(((const R*)in)[i], R(0));
-            else x = ((const C*)in)[i];
+            x = ((const C*)in)[i];
         }
         tile[t * K::TS + w] = x;
     }
     __syncthreads();
     C x[Ff::V];
     // the inverse runs the radices in reverse: its first stage has its own layout
-    if constexpr (KIND == COL_INV || KIND == ROW_INV_REAL)
+    if constexpr (KIND == COL_INV)
         Fi::load_first(x, tid, P, [&](int t) { return tile[t * K::TS + team]; });
     else
         Ff::load_first(x, tid, P, [&](int t) { return tile[t * K::TS + team]; });
     __syncthreads();
     C* sc = lds + team * Ff::SCR;
     // every team has finished with its scratch before the tile is rewritten
-    if constexpr (KIND == ROW_FWD_REAL || KIND == COL_FWD) {
+    if constexpr (KIND == COL_FWD) {
         Ff::run_g(x, sc, tid, tw);
         __syncthreads();
         Ff::store_last(x, tid, P, [&](int t, C c) { tile[t * K::TS + team] = c; });
@@ -147,11 +168,11 @@ __global__ __launch_bounds__((Spec<R, P>::THREADS)) void k_spec(const void* in,
         at(e, t, w);
         if (w < nw) {
             const long i = base + w * ln.u_stride + t * ln.es;
-            if constexpr (KIND == ROW_INV_REAL) ((R*)out)[i] = tile[t * K::TS + w].x;
-            else ((C*)out)[i] = tile[t * K::TS + w];
+            ((C*)out)[i] = tile[t * K::TS + w];
         }
     }
 }
+
 
 template <typename R, int KIND>
 hipError_t go(int P, const void* in, void* out, SLines ln, const void* tw, const SMul& mul,
