@@ -78,7 +78,7 @@ fsa_status fsa_plan_create(const fsa_kernel* k, int d, const double* L, const in
         if (!finite || !(nn > 0.0) || !(mm > 0.0))
             return fail(FSA_EINVAL, "fsa_plan_create: DDI needs finite, nonzero n and m");
     }
-    double minL = 1e300, maxh = 0.0;
+    double minL = 1e300;
     for (int j = 0; j < d; ++j) {
         if (!(L[j] > 0.0 && std::isfinite(L[j])))
             return fail(FSA_EINVAL, "fsa_plan_create: L[%d] must be positive", j);
@@ -90,7 +90,6 @@ fsa_status fsa_plan_create(const fsa_kernel* k, int d, const double* L, const in
                         "fsa_plan_create: N[%d] = %lld unsupported (need 2^a or 3*2^a, <= 2048)",
                         j, (long long)N[j]);
         minL = std::fmin(minL, L[j]);
-        maxh = std::fmax(maxh, 2.0 * L[j] / (double)N[j]);
     }
     const double R0 = 2.0 * minL;
     double eps = k->eps;
@@ -100,7 +99,6 @@ fsa_status fsa_plan_create(const fsa_kernel* k, int d, const double* L, const in
                     "fsa_plan_create: eps = %g violates the far-field condition (need eps <= "
                     "R0/4 = %g; 16 digits need eps <= R0/5.85)",
                     eps, R0 / 4.0);
-    (void)maxh;
 
     fsa_plan_s* pl = new (std::nothrow) fsa_plan_s();
     if (!pl) return fail(FSA_ENOMEM, "fsa_plan_create: out of host memory");
