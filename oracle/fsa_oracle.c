@@ -29,10 +29,19 @@
  *
  *  - 3D DDI (Sec. 5.3): the source d_nm rho is the spectral derivative of rho
  *    on its own grid, periodic on the box (see orc_solve_ddi).
+ *  - General construction (Sec. 4, eq. GeneralApprox1): U^eps = U erf(r/eps)
+ *    (1 - xi(r)) with the window xi(r) = erfc((r - 6 eps)/eps)/2 where
+ *    U erf(r/eps) is not smooth at 0 (2D Yukawa, quasi-2D DDI, and on request
+ *    3D Yukawa, 2D log, 2D biharmonic), xi = 0 otherwise; W by adaptive
+ *    Gauss-Legendre quadrature of eq. Fourier-Symmetric.  With lambda = 2 it
+ *    reproduces Table 5's 2D and 3D Yukawa rows.
+ *  - Quasi-2D DDI (Sec. 5.3): source -(3/2)(d_{n_perp n_perp} - n_3^2 Lap) rho
+ *    by the spectral derivative on the grid, as for the 3D DDI.
  *
  * Parity pins (tests/): the printed error tables (Tables 2, 4, 5), closed-form
- * Gaussian potentials, a direct O(N^2d) sum, an O(n^2) DFT, Ein/E1 against a
- * library routine, W against quadrature of eq. Fourier-Symmetric.
+ * Gaussian potentials, a direct O(N^2d) sum, an O(n^2) DFT, Ein/E1/K0/J0
+ * against a library routine, W against quadrature of eq. Fourier-Symmetric,
+ * the quadrature W against Table 1's closed forms.
  * The 2D/3D biharmonic and 2D Coulomb rows of Table 1 are pinned only by
  * quadrature of eq. Fourier-Symmetric and, for 3D biharmonic, Table 5.
  */
@@ -55,6 +64,8 @@ enum {
     ORC_BIHARMONIC_3D = 5,
     ORC_BIHARMONIC_2D = 6,
     ORC_DDI_3D = 7, /* through the Coulomb kernel, see orc_solve_ddi */
+    ORC_YUKAWA_2D = 8,    /* general construction only */
+    ORC_QUASI2D_DDI = 9,  /* general construction only, see orc_solve_q2d */
 };
 
 static const double ORC_PI = 3.14159265358979323846264338327950288;
@@ -246,9 +257,314 @@ int orc_kernel_dim(int kind)
     case ORC_DDI_3D: return 3;
     case ORC_LOG_2D:
     case ORC_COULOMB_2D:
-    case ORC_BIHARMONIC_2D: return 2;
+    case ORC_BIHARMONIC_2D:
+    case ORC_YUKAWA_2D:
+    case ORC_QUASI2D_DDI: return 2;
     }
     return 0;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Bessel functions K0 and J0                                                 */
+/* ------------------------------------------------------------------------- */
+
+/* Gauss-Legendre nodes and weights on [-1, 1] by Newton's method on the
+ * three-term recurrence of the Legendre polynomials. */
+#define ORC_GL_N 20
+static double g_glx[ORC_GL_N], g_glw[ORC_GL_N];
+static int g_gl_ready = 0;
+
+static void gl_init(void)
+{
+    if (g_gl_ready) return;
+    const int n = ORC_GL_N;
+    for (int i = 0; i < n; ++i) {
+        double x = cos(ORC_PI * ((double)i + 0.75) / ((double)n + 0.5));
+        double dp = 1.0;
+        for (int it = 0; it < 100; ++it) {
+            double p0 = 1.0, p1 = x;
+            for (int k = 2; k <= n; ++k) {
+                const double p2 = ((2.0 * k - 1.0) * x * p1 - (k - 1.0) * p0) / (double)k;
+                p0 = p1;
+                p1 = p2;
+            }
+            dp = (double)n * (x * p1 - p0) / (x * x - 1.0);
+            const double dx = p1 / dp;
+            x -= dx;
+            if (fabs(dx) < 1e-17) break;
+        }
+        g_glx[i] = x;
+        g_glw[i] = 2.0 / ((1.0 - x * x) * dp * dp);
+    }
+    g_gl_ready = 1;
+}
+
+typedef double (*orc_fn)(double x, const void *ctx);
+
+/* One Gauss-Legendre panel; *absum gets the rule applied to |f|. */
+static double gl_panel(orc_fn f, const void *ctx, double a, double b, double *absum)
+{
+    const double c = 0.5 * (a + b), hw = 0.5 * (b - a);
+    double s = 0.0, sa = 0.0;
+    for (int i = 0; i < ORC_GL_N; ++i) {
+        const double v = g_glw[i] * f(c + hw * g_glx[i], ctx);
+        s += v;
+        sa += fabs(v);
+    }
+    if (absum) *absum = fabs(hw) * sa;
+    return hw * s;
+}
+
+/* Adaptive Gauss-Legendre: bisect until the two halves agree with the whole
+ * to within the panel's share of the tolerance, or to `noise` times the
+ * halves' integral of |f| -- the relative accuracy to which f itself is
+ * evaluated (rounding of its arguments included), below which the comparison
+ * carries no information.  Depth is capped at 40. */
+static double gl_adapt(orc_fn f, const void *ctx, double a, double b, double whole, double tol,
+                       double noise, int depth)
+{
+    const double m = 0.5 * (a + b);
+    double al, ar;
+    const double l = gl_panel(f, ctx, a, m, &al), r = gl_panel(f, ctx, m, b, &ar);
+    const double diff = fabs(l + r - whole);
+    if (!(diff > tol) || diff <= noise * (al + ar) || depth >= 40) return l + r;
+    return gl_adapt(f, ctx, a, m, l, 0.5 * tol, noise, depth + 1) +
+           gl_adapt(f, ctx, m, b, r, 0.5 * tol, noise, depth + 1);
+}
+
+/* int_a^b f over `np` equal initial panels, each refined adaptively to an
+ * absolute tolerance rel * int_a^b |f| (the latter from the initial rule),
+ * or to the evaluation noise of f (see gl_adapt). */
+static double orc_integrate(orc_fn f, const void *ctx, double a, double b, int np, double rel,
+                            double noise)
+{
+    gl_init();
+    if (np < 1) np = 1;
+    const double w = (b - a) / (double)np;
+    double mass = 0.0;
+    for (int p = 0; p < np; ++p) {
+        const double c = a + (p + 0.5) * w, hw = 0.5 * w;
+        for (int i = 0; i < ORC_GL_N; ++i) mass += hw * g_glw[i] * fabs(f(c + hw * g_glx[i], ctx));
+    }
+    const double tol = rel * (mass > 0.0 ? mass : 1e-300);
+    double s = 0.0;
+    for (int p = 0; p < np; ++p) {
+        const double lo = a + p * w, hi = (p == np - 1) ? b : lo + w;
+        s += gl_adapt(f, ctx, lo, hi, gl_panel(f, ctx, lo, hi, NULL), tol / (double)np, noise, 0);
+    }
+    return s;
+}
+
+/* e^x K0(x) = int_0^inf e^{-x (cosh t - 1)} dt  (A&S 9.6.24), for x > 2:
+ * composite 20-point Gauss-Legendre on 6 equal panels of [0, t_max], where
+ * e^{-x (cosh t_max - 1)} < 1e-20.  The integrand is analytic and spans at
+ * most ~10 of its own widths (1/sqrt(x) for large x) there. */
+static double k0e_quad(double x)
+{
+    gl_init();
+    const double tmax = acosh(1.0 + 46.0 / x);
+    const int np = 6;
+    const double w = tmax / np;
+    double s = 0.0;
+    for (int p = 0; p < np; ++p) {
+        const double c = (p + 0.5) * w, hw = 0.5 * w;
+        double q = 0.0;
+        for (int i = 0; i < ORC_GL_N; ++i) {
+            const double sh = sinh(0.5 * (c + hw * g_glx[i])); /* cosh t - 1 = 2 sinh^2(t/2) */
+            q += g_glw[i] * exp(-2.0 * x * sh * sh);
+        }
+        s += hw * q;
+    }
+    return s;
+}
+
+/* K0 for 0 < x <= 2 by its ascending series (A&S 9.6.13 with 9.6.12):
+ * K0(x) = -(ln(x/2) + gamma) I0(x) + sum_{k>=1} H_k (x^2/4)^k / (k!)^2,
+ * H_k the harmonic numbers. */
+static double k0_series(double x)
+{
+    const double q = 0.25 * x * x;
+    double term = 1.0, i0 = 1.0, tail = 0.0, hk = 0.0;
+    for (int k = 1; k < 60; ++k) {
+        term *= q / ((double)k * (double)k);
+        hk += 1.0 / (double)k;
+        i0 += term;
+        tail += hk * term;
+        if (term < 1e-18 * i0) break;
+    }
+    return -(log(0.5 * x) + ORC_EULER_GAMMA) * i0 + tail;
+}
+
+/* e^x K0(x), x > 0. */
+double orc_k0e(double x)
+{
+    if (!(x > 0.0)) return INFINITY;
+    if (x <= 2.0) return exp(x) * k0_series(x);
+    return k0e_quad(x);
+}
+
+double orc_k0(double x)
+{
+    if (!(x > 0.0)) return INFINITY;
+    if (x <= 2.0) return k0_series(x);
+    return exp(-x) * orc_k0e(x);
+}
+
+/* J0(x).  For |x| < 25: Bessel's integral (2/pi) int_0^{pi/2} cos(x sin t) dt
+ * (A&S 9.1.18) by the trapezoidal rule with m panels.  The integrand extends
+ * to a smooth periodic function, so the rule is the 4m-point periodic one,
+ * whose error is the aliased Bessel tail 2 sum_j J_{4mj}(x): negligible once
+ * 4m >= |x| + 12 |x|^{1/3} + 40.  For |x| >= 25: Hankel's asymptotic
+ * expansion (A&S 9.2.5, 9.2.9, 9.2.10 with mu = 0),
+ *   J0 = sqrt(2/(pi x)) (P cos chi - Q sin chi),  chi = x - pi/4,
+ *   P = sum_k (-1)^k c_{2k},  Q = sum_k (-1)^{k+1} c_{2k+1},
+ *   c_j = prod_{i=1}^{j} (2i-1)^2 / (j! (8x)^j),
+ * summed while the terms decrease and exceed 1e-18 (the remainder is below
+ * the first omitted term). */
+double orc_j0(double x)
+{
+    x = fabs(x);
+    if (x >= 25.0) {
+        double c = 1.0, P = 1.0, Q = 0.0;
+        for (int j = 1; j < 60; ++j) {
+            const double cn = c * (2.0 * j - 1.0) * (2.0 * j - 1.0) / (j * 8.0 * x);
+            if (cn > c || cn < 1e-18) break;
+            c = cn;
+            /* j odd -> Q term with sign (-1)^{(j+1)/2}; j even -> P, (-1)^{j/2} */
+            if (j & 1) Q += ((((j - 1) / 2) & 1) ? c : -c);
+            else P += (((j / 2) & 1) ? -c : c);
+        }
+        const double chi = x - 0.25 * ORC_PI;
+        return sqrt(2.0 / (ORC_PI * x)) * (P * cos(chi) - Q * sin(chi));
+    }
+    const int m = (int)ceil((x + 12.0 * cbrt(x) + 40.0) / 4.0);
+    const double dt = 0.5 * ORC_PI / (double)m;
+    double s = 0.5 * (1.0 + cos(x));
+    for (int j = 1; j < m; ++j) s += cos(x * sin(j * dt));
+    return s / (double)m;
+}
+
+/* ------------------------------------------------------------------------- */
+/* General construction (Sec. 4, eq. GeneralApprox1; Sec. 2.2 eq.             */
+/* Fourier-Symmetric): U^eps = U erf(r/eps) (1 - xi(r)) with a smooth window   */
+/* xi where U erf(r/eps) is not smooth, W by quadrature of the radial Fourier */
+/* transform of U - U^eps.  The window is xi(r) = erfc((r - 6 eps)/eps)/2     */
+/* (the paper leaves it open): 1 - xi(0) = erfc(6)/2 ~ 1e-17, and xi(R0)      */
+/* ~ 1e-17 when eps <= R0/12.                                                 */
+/* `par` is lambda for the Yukawa kinds and eta for the quasi-2D DDI.         */
+/* ------------------------------------------------------------------------- */
+
+/* whether U erf(r/eps) is smooth at r = 0 (then xi = 0) */
+int orc_windowed(int kind)
+{
+    switch (kind) {
+    case ORC_COULOMB_3D:
+    case ORC_DDI_3D:
+    case ORC_COULOMB_2D:
+    case ORC_BIHARMONIC_3D: return 0;
+    }
+    return 1;
+}
+
+/* U(r) of every kind, r > 0 */
+double orc_u_any(int kind, double par, double r)
+{
+    switch (kind) {
+    case ORC_YUKAWA_2D: return orc_k0(par * r) / (2.0 * ORC_PI);
+    case ORC_QUASI2D_DDI: {
+        /* (2 pi)^{-3/2} int_R e^{-s^2/2} / sqrt(r^2 + eta^2 s^2) ds
+         *   = (2 pi)^{-3/2} eta^{-1} e^{x} K0(x),  x = r^2 / (4 eta^2) */
+        const double x = r * r / (4.0 * par * par);
+        return orc_k0e(x) / (pow(2.0 * ORC_PI, 1.5) * par);
+    }
+    }
+    return orc_u(kind, par, r);
+}
+
+static double window_keep(double eps, double r) /* 1 - xi(r) */
+{
+    return 0.5 * erfc((6.0 * eps - r) / eps);
+}
+
+static double window_xi(double eps, double r)
+{
+    return 0.5 * erfc((r - 6.0 * eps) / eps);
+}
+
+double orc_ueps_general(int kind, double par, double eps, double r)
+{
+    const int win = orc_windowed(kind);
+    if (r == 0.0) {
+        /* limits of U erf(r/eps) at 0 (times 1 - xi(0) when windowed) */
+        double lim = 0.0;
+        switch (kind) {
+        case ORC_COULOMB_3D:
+        case ORC_DDI_3D:
+        case ORC_YUKAWA_3D: lim = 1.0 / (2.0 * pow(ORC_PI, 1.5) * eps); break;
+        case ORC_COULOMB_2D: lim = 1.0 / (pow(ORC_PI, 1.5) * eps); break;
+        default: lim = 0.0; /* r ln r, r, r^3 ln r -> 0 */
+        }
+        return win ? lim * window_keep(eps, 0.0) : lim;
+    }
+    const double v = orc_u_any(kind, par, r) * erf(r / eps);
+    return win ? v * window_keep(eps, r) : v;
+}
+
+/* (U - U^eps)(r) = U(r) [erfc(r/eps) + erf(r/eps) xi(r)], r > 0 */
+double orc_remainder(int kind, double par, double eps, double r)
+{
+    const double g = orc_windowed(kind) ? erfc(r / eps) + erf(r / eps) * window_xi(eps, r)
+                                        : erfc(r / eps);
+    return orc_u_any(kind, par, r) * g;
+}
+
+/* radius beyond which U - U^eps is below 1e-20 of its scale */
+static double remainder_end(int kind, double eps)
+{
+    return orc_windowed(kind) ? 13.0 * eps : 7.0 * eps;
+}
+
+typedef struct { int kind, d; double par, eps, k; } what_ctx;
+
+static double what_integrand(double r, const void *vctx)
+{
+    const what_ctx *c = (const what_ctx *)vctx;
+    if (r <= 0.0) return 0.0;
+    const double f = orc_remainder(c->kind, c->par, c->eps, r);
+    if (c->d == 2) return 2.0 * ORC_PI * f * orc_j0(c->k * r) * r;
+    const double kr = c->k * r;
+    const double sinc = kr == 0.0 ? 1.0 : sin(kr) / kr;
+    return 4.0 * ORC_PI * f * sinc * r * r;
+}
+
+/* W(k) = FT[U - U^eps](k) by adaptive quadrature of eq. Fourier-Symmetric */
+double orc_what_general(int kind, double par, double eps, double k)
+{
+    const int d = orc_kernel_dim(kind);
+    what_ctx c = {kind, d, par, eps, k};
+    const double R = remainder_end(kind, eps);
+    /* initial panels resolve the window (width eps/2) and the oscillation
+     * (k * width <= 4); adaptivity does the rest, including r -> 0 */
+    double w = 0.5 * eps;
+    if (k > 0.0 && 4.0 / k < w) w = 4.0 / k;
+    if (kind == ORC_QUASI2D_DDI && par < w) w = par;
+    const int np = (int)ceil(R / w);
+    /* f carries the rounding of its phase k r: relative noise ~ k R eps */
+    const double noise = (64.0 + 4.0 * k * R) * 2.220446049250313e-16;
+    return orc_integrate(what_integrand, &c, 0.0, R, np, 1e-17, noise);
+}
+
+/* U^eps of a plan: the general construction for kinds that need it or when
+ * asked, else Table 1 / the closed forms above. */
+static int uses_general(int kind, int general)
+{
+    return general || kind == ORC_YUKAWA_2D || kind == ORC_QUASI2D_DDI;
+}
+
+static double ueps_plan(int kind, double par, double eps, int general, double r)
+{
+    return uses_general(kind, general) ? orc_ueps_general(kind, par, eps, r)
+                                       : orc_ueps(kind, par, eps, r);
 }
 
 /* ------------------------------------------------------------------------- */
@@ -400,11 +716,14 @@ static inline long signed_index(long m, long N) { return m < N ? m : m - 2 * N; 
  * signed index n_j stored at n_j mod P_j).  Optional outputs: T1 and T2
  * separately, and max |Im T(2)| (the imaginary part must be round-off).
  */
-int orc_build_tensor(int kind, double lam, double eps, int d, const double *L, const int64_t *N,
-                     double *T, double *T1_out, double *T2_out, double *t2_imag_max)
+int orc_build_tensor_g(int kind, double lam, double eps, int general, int d, const double *L,
+                       const int64_t *N, double *T, double *T1_out, double *T2_out,
+                       double *t2_imag_max)
 {
     if (check_geometry(kind, d, L, N)) return -1;
     if (!(eps > 0.0)) return -1;
+    const int gen = uses_general(kind, general);
+    gl_init();
     int64_t P[3] = {1, 1, 1};
     double h[3] = {1, 1, 1};
     double hprod = 1.0;
@@ -418,11 +737,35 @@ int orc_build_tensor(int kind, double lam, double eps, int d, const double *L, c
     cplx *w = (cplx *)malloc(sizeof(cplx) * total);
     if (!w) return -2;
 
+    /* The quadrature W of the general construction depends on |p_j| only:
+     * it is evaluated once per point of the octant 0 <= p_j <= N_j. */
+    double *woct = NULL;
+    int64_t D[3] = {1, 1, 1};
+    if (gen) {
+        size_t noct = 1;
+        for (int j = 0; j < d; ++j) { D[j] = N[j] + 1; noct *= (size_t)D[j]; }
+        woct = (double *)malloc(sizeof(double) * noct);
+        if (!woct) { free(w); return -2; }
+#pragma omp parallel for schedule(dynamic, 4)
+        for (long q = 0; q < (long)noct; ++q) {
+            size_t rem = (size_t)q;
+            double k2 = 0.0;
+            for (int j = d - 1; j >= 0; --j) {
+                const long pj = (long)(rem % (size_t)D[j]);
+                rem /= (size_t)D[j];
+                const double k = ORC_PI * (double)pj / (2.0 * L[j]);
+                k2 += k * k;
+            }
+            woct[q] = orc_what_general(kind, lam, eps, sqrt(k2));
+        }
+    }
+
     /* T(1)_n = prod h_j U^eps(|n h|)  and  W_p = W(|k_p|), k_j = pi p_j / (2 L_j) */
 #pragma omp parallel for schedule(static)
     for (long q = 0; q < (long)total; ++q) {
         size_t rem = (size_t)q;
         double r2 = 0.0, k2 = 0.0;
+        size_t oi = 0, ostride = 1;
         for (int j = d - 1; j >= 0; --j) {
             const long m = (long)(rem % (size_t)P[j]);
             rem /= (size_t)P[j];
@@ -431,10 +774,13 @@ int orc_build_tensor(int kind, double lam, double eps, int d, const double *L, c
             const double k = ORC_PI * (double)n / (2.0 * L[j]);
             r2 += x * x;
             k2 += k * k;
+            oi += (size_t)labs(n) * ostride;
+            ostride *= (size_t)D[j];
         }
-        T[q] = hprod * orc_ueps(kind, lam, eps, sqrt(r2));
-        w[q] = orc_what(kind, lam, eps, sqrt(k2));
+        T[q] = hprod * ueps_plan(kind, lam, eps, gen, sqrt(r2));
+        w[q] = gen ? woct[oi] : orc_what(kind, lam, eps, sqrt(k2));
     }
+    free(woct);
     if (T1_out) memcpy(T1_out, T, sizeof(double) * total);
 
     /* T(2) = inverse DFT of W with the 1/prod P_j normalisation */
@@ -452,6 +798,12 @@ int orc_build_tensor(int kind, double lam, double eps, int d, const double *L, c
     if (t2_imag_max) *t2_imag_max = imax;
     free(w);
     return 0;
+}
+
+int orc_build_tensor(int kind, double lam, double eps, int d, const double *L, const int64_t *N,
+                     double *T, double *T1_out, double *T2_out, double *t2_imag_max)
+{
+    return orc_build_tensor_g(kind, lam, eps, 0, d, L, N, T, T1_out, T2_out, t2_imag_max);
 }
 
 /* ------------------------------------------------------------------------- */
@@ -569,18 +921,24 @@ int orc_conv_fft(int d, const int64_t *N, const double *T, const double *rho, do
 }
 
 /* Convenience: build T and evaluate Phi by the FFT route. */
-int orc_solve(int kind, double lam, double eps, int d, const double *L, const int64_t *N,
-              const double *rho, double *phi)
+int orc_solve_g(int kind, double lam, double eps, int general, int d, const double *L,
+                const int64_t *N, const double *rho, double *phi)
 {
     if (check_geometry(kind, d, L, N)) return -1;
     size_t total = 1;
     for (int j = 0; j < d; ++j) total *= (size_t)(2 * N[j]);
     double *T = (double *)malloc(sizeof(double) * total);
     if (!T) return -2;
-    int rc = orc_build_tensor(kind, lam, eps, d, L, N, T, NULL, NULL, NULL);
+    int rc = orc_build_tensor_g(kind, lam, eps, general, d, L, N, T, NULL, NULL, NULL);
     if (!rc) rc = orc_conv_fft(d, N, T, rho, phi);
     free(T);
     return rc;
+}
+
+int orc_solve(int kind, double lam, double eps, int d, const double *L, const int64_t *N,
+              const double *rho, double *phi)
+{
+    return orc_solve_g(kind, lam, eps, 0, d, L, N, rho, phi);
 }
 
 /* ------------------------------------------------------------------------- */
@@ -599,8 +957,8 @@ int orc_solve(int kind, double lam, double eps, int d, const double *L, const in
  * DDI errors of Table 5.)  The Coulomb convolution is the FSA discrete
  * convolution of orc_solve.
  */
-int orc_solve_ddi(double eps, const double *L, const int64_t *N, const double *nv,
-                  const double *mv, const double *rho, double *phi)
+int orc_solve_ddi_g(double eps, int general, const double *L, const int64_t *N,
+                    const double *nv, const double *mv, const double *rho, double *phi)
 {
     if (check_geometry(ORC_COULOMB_3D, 3, L, N)) return -1;
     const size_t total = (size_t)N[0] * (size_t)N[1] * (size_t)N[2];
@@ -629,7 +987,7 @@ int orc_solve_ddi(double eps, const double *L, const int64_t *N, const double *n
     }
     if (!rc) {
         for (size_t i = 0; i < total; ++i) src[i] = creal(a[i]) / (double)total;
-        rc = orc_solve(ORC_COULOMB_3D, 0.0, eps, 3, L, N, src, conv);
+        rc = orc_solve_g(ORC_COULOMB_3D, 0.0, eps, general, 3, L, N, src, conv);
     }
     if (!rc) {
         const double nm = nv[0] * mv[0] + nv[1] * mv[1] + nv[2] * mv[2];
@@ -638,6 +996,55 @@ int orc_solve_ddi(double eps, const double *L, const int64_t *N, const double *n
     free(a);
     free(src);
     free(conv);
+    return rc;
+}
+
+int orc_solve_ddi(double eps, const double *L, const int64_t *N, const double *nv,
+                  const double *mv, const double *rho, double *phi)
+{
+    return orc_solve_ddi_g(eps, 0, L, N, nv, mv, rho, phi);
+}
+
+/* ------------------------------------------------------------------------- */
+/* Quasi-2D dipole-dipole interaction (Sec. 5.3, Example 4)                   */
+/* ------------------------------------------------------------------------- */
+
+/*
+ * Phi = U~ conv S,  S = -(3/2) (d_{n_perp n_perp} - n_3^2 Lap_perp) rho, with
+ * U~ the quasi-2D kernel of orc_u_any (width eta) in the general
+ * construction.  S is the spectral derivative on the grid, periodic on the
+ * box, as for the 3D DDI: d_{n_perp} -> i k.n_perp and Lap_perp -> -|k|^2 give
+ * S^ = (3/2) ((k.n_perp)^2 - n_3^2 |k|^2) rho^,  k_j = pi q_j / L_j.
+ */
+int orc_solve_q2d(double eps, double eta, const double *L, const int64_t *N, const double *nv,
+                  const double *rho, double *phi)
+{
+    if (check_geometry(ORC_QUASI2D_DDI, 2, L, N)) return -1;
+    if (!(eta > 0.0)) return -1;
+    const size_t total = (size_t)N[0] * (size_t)N[1];
+    cplx *a = (cplx *)malloc(sizeof(cplx) * total);
+    double *src = (double *)malloc(sizeof(double) * total);
+    if (!a || !src) { free(a); free(src); return -2; }
+    for (size_t i = 0; i < total; ++i) a[i] = rho[i];
+    int rc = fft_nd(2, N, a, -1);
+    if (!rc) {
+        const double n3sq = nv[2] * nv[2];
+        for (long i0 = 0; i0 < N[0]; ++i0)
+            for (long i1 = 0; i1 < N[1]; ++i1) {
+                const long q0 = i0 < N[0] / 2 ? i0 : i0 - N[0];
+                const long q1 = i1 < N[1] / 2 ? i1 : i1 - N[1];
+                const double k0 = ORC_PI * (double)q0 / L[0], k1 = ORC_PI * (double)q1 / L[1];
+                const double kn = k0 * nv[0] + k1 * nv[1];
+                a[(size_t)i0 * N[1] + (size_t)i1] *= 1.5 * (kn * kn - n3sq * (k0 * k0 + k1 * k1));
+            }
+        rc = fft_nd(2, N, a, +1);
+    }
+    if (!rc) {
+        for (size_t i = 0; i < total; ++i) src[i] = creal(a[i]) / (double)total;
+        rc = orc_solve_g(ORC_QUASI2D_DDI, eta, eps, 1, 2, L, N, src, phi);
+    }
+    free(a);
+    free(src);
     return rc;
 }
 
@@ -668,4 +1075,40 @@ void orc_e1_vec(long n, const double *x, double *out)
 void orc_ein_vec(long n, const double *x, double *out)
 {
     for (long i = 0; i < n; ++i) out[i] = orc_ein(x[i]);
+}
+
+void orc_k0_vec(long n, const double *x, double *out)
+{
+    gl_init();
+    for (long i = 0; i < n; ++i) out[i] = orc_k0(x[i]);
+}
+
+void orc_k0e_vec(long n, const double *x, double *out)
+{
+    gl_init();
+    for (long i = 0; i < n; ++i) out[i] = orc_k0e(x[i]);
+}
+
+void orc_j0_vec(long n, const double *x, double *out)
+{
+    for (long i = 0; i < n; ++i) out[i] = orc_j0(x[i]);
+}
+
+void orc_u_any_vec(int kind, double par, long n, const double *r, double *out)
+{
+    gl_init();
+    for (long i = 0; i < n; ++i) out[i] = orc_u_any(kind, par, r[i]);
+}
+
+void orc_ueps_general_vec(int kind, double par, double eps, long n, const double *r, double *out)
+{
+    gl_init();
+    for (long i = 0; i < n; ++i) out[i] = orc_ueps_general(kind, par, eps, r[i]);
+}
+
+void orc_what_general_vec(int kind, double par, double eps, long n, const double *k, double *out)
+{
+    gl_init();
+#pragma omp parallel for schedule(dynamic, 1)
+    for (long i = 0; i < n; ++i) out[i] = orc_what_general(kind, par, eps, k[i]);
 }

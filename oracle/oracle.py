@@ -10,7 +10,12 @@ arXiv 2504.19410):
 * ``build_tensor``: T = T(1) + T(2), Sec. 2.1 eq. Tensor1 / TensorAnis,
   Sec. 2.2 eqs. FouTran and Tensor2, on the full periodic grid prod_j 2N_j;
 * ``conv_direct`` / ``conv_fft`` / ``conv_direct_points``: eq. DiscConv;
-* ``ueps`` / ``what`` / ``u``: Table 1 and eqs. KerAppr, lnrAppr.
+* ``ueps`` / ``what`` / ``u``: Table 1 and eqs. KerAppr, lnrAppr;
+* ``ueps_general`` / ``what_general``: the general construction of Sec. 4
+  (eq. GeneralApprox1, W by quadrature of eq. Fourier-Symmetric), with its
+  own K0 (``k0``, ``k0e``) and J0 (``j0``);
+* ``solve_ddi`` / ``solve_q2d``: the 3D and quasi-2D dipole-dipole
+  potentials of Sec. 5.3.
 """
 from __future__ import annotations
 
@@ -33,9 +38,14 @@ KINDS = {
     "biharmonic3d": 5,
     "biharmonic2d": 6,
     "ddi3d": 7,
+    "yukawa2d": 8,
+    "quasi2d_ddi": 9,
 }
 KIND_DIM = {"coulomb3d": 3, "yukawa3d": 3, "biharmonic3d": 3,
-            "log2d": 2, "coulomb2d": 2, "biharmonic2d": 2, "ddi3d": 3}
+            "log2d": 2, "coulomb2d": 2, "biharmonic2d": 2, "ddi3d": 3,
+            "yukawa2d": 2, "quasi2d_ddi": 2}
+# kinds that only exist in the general construction (window + quadrature W)
+GENERAL_ONLY = ("yukawa2d", "quasi2d_ddi")
 
 BUILD_CMD = ["gcc", "-O2", "-fopenmp", "-shared", "-fPIC", "-std=c11",
              _SRC, "-o", _LIB, "-lm"]
@@ -74,6 +84,20 @@ def _load():
             "orc_fft1d": (I, [I, P, P, I]),
             "orc_fftnd": (I, [I, P, P, I]),
             "orc_build_tensor": (I, [I, D, D, I, P, P, P, P, P, P]),
+            "orc_build_tensor_g": (I, [I, D, D, I, I, P, P, P, P, P, P]),
+            "orc_solve_g": (I, [I, D, D, I, I, P, P, P, P]),
+            "orc_solve_ddi_g": (I, [D, I, P, P, P, P, P, P]),
+            "orc_solve_q2d": (I, [D, D, P, P, P, P, P]),
+            "orc_windowed": (I, [I]),
+            "orc_k0": (D, [D]),
+            "orc_k0e": (D, [D]),
+            "orc_j0": (D, [D]),
+            "orc_k0_vec": (None, [L, P, P]),
+            "orc_k0e_vec": (None, [L, P, P]),
+            "orc_j0_vec": (None, [L, P, P]),
+            "orc_u_any_vec": (None, [I, D, L, P, P]),
+            "orc_ueps_general_vec": (None, [I, D, D, L, P, P]),
+            "orc_what_general_vec": (None, [I, D, D, L, P, P]),
             "orc_conv_direct": (I, [I, P, P, P, P]),
             "orc_conv_direct_points": (I, [I, P, P, P, L, P, P]),
             "orc_conv_fft": (I, [I, P, P, P, P]),
@@ -177,10 +201,71 @@ def fftnd(a, sign: int = -1) -> np.ndarray:
     return a
 
 
-def build_tensor(kind, L, N, eps, lam=0.0, parts=False):
+def _par(kind, lam, eta):
+    """The kernel parameter the C oracle takes: eta for the quasi-2D DDI, else lambda."""
+    if kind == "quasi2d_ddi" or kind == KINDS["quasi2d_ddi"]:
+        return float(eta)
+    return float(lam)
+
+
+def k0(x) -> np.ndarray:
+    x = _f64(x)
+    out = np.empty_like(x)
+    _load().orc_k0_vec(x.size, _p(x), _p(out))
+    return out
+
+
+def k0e(x) -> np.ndarray:
+    """e^x K0(x)."""
+    x = _f64(x)
+    out = np.empty_like(x)
+    _load().orc_k0e_vec(x.size, _p(x), _p(out))
+    return out
+
+
+def j0(x) -> np.ndarray:
+    x = _f64(x)
+    out = np.empty_like(x)
+    _load().orc_j0_vec(x.size, _p(x), _p(out))
+    return out
+
+
+def windowed(kind) -> bool:
+    """Whether the general construction needs the window xi for this kind."""
+    return bool(_load().orc_windowed(_kind(kind)))
+
+
+def u_any(kind, r, lam=0.0, eta=None) -> np.ndarray:
+    r = _f64(r)
+    out = np.empty_like(r)
+    _load().orc_u_any_vec(_kind(kind), _par(kind, lam, eta), r.size, _p(r), _p(out))
+    return out
+
+
+def ueps_general(kind, r, eps, lam=0.0, eta=None) -> np.ndarray:
+    """U^eps = U erf(r/eps) (1 - xi(r)) of the general construction (eq. GeneralApprox1)."""
+    r = _f64(r)
+    out = np.empty_like(r)
+    _load().orc_ueps_general_vec(_kind(kind), _par(kind, lam, eta), float(eps), r.size,
+                                 _p(r), _p(out))
+    return out
+
+
+def what_general(kind, k, eps, lam=0.0, eta=None) -> np.ndarray:
+    """W(k) by quadrature of the radial transform (eq. Fourier-Symmetric)."""
+    k = _f64(k)
+    out = np.empty_like(k)
+    _load().orc_what_general_vec(_kind(kind), _par(kind, lam, eta), float(eps), k.size,
+                                 _p(k), _p(out))
+    return out
+
+
+def build_tensor(kind, L, N, eps, lam=0.0, parts=False, general=False, eta=None):
     """T on the periodic grid prod_j 2N_j (C order, n_j stored at n_j mod 2N_j).
 
-    With ``parts=True`` returns (T, T1, T2, max|Im T2|).
+    ``general`` selects the general construction (window + quadrature W);
+    the yukawa2d and quasi2d_ddi kinds always use it.  With ``parts=True``
+    returns (T, T1, T2, max|Im T2|).
     """
     L = _f64(L)
     N = _i64(N)
@@ -190,8 +275,9 @@ def build_tensor(kind, L, N, eps, lam=0.0, parts=False):
     T1 = np.empty(shape, dtype=np.float64) if parts else None
     T2 = np.empty(shape, dtype=np.float64) if parts else None
     imax = ctypes.c_double(0.0)
-    rc = _load().orc_build_tensor(
-        _kind(kind), float(lam), float(eps), d, _p(L), _p(N), _p(T),
+    rc = _load().orc_build_tensor_g(
+        _kind(kind), _par(kind, lam, eta), float(eps), int(bool(general)), d, _p(L), _p(N),
+        _p(T),
         _p(T1) if parts else None, _p(T2) if parts else None,
         ctypes.cast(ctypes.pointer(imax), ctypes.c_void_p))
     if rc:
@@ -236,7 +322,7 @@ def conv_fft(T, rho) -> np.ndarray:
     return phi
 
 
-def solve_ddi(L, N, rho, eps, n, m) -> np.ndarray:
+def solve_ddi(L, N, rho, eps, n, m, general=False) -> np.ndarray:
     """3D dipole-dipole potential -(m.n) rho - 3 Coulomb(d_nm rho) (Sec. 5.3),
     d_nm rho by the periodic spectral derivative on the grid."""
     L = _f64(L)
@@ -245,20 +331,35 @@ def solve_ddi(L, N, rho, eps, n, m) -> np.ndarray:
     n = _f64(n)
     m = _f64(m)
     phi = np.empty_like(rho)
-    rc = _load().orc_solve_ddi(float(eps), _p(L), _p(N), _p(n), _p(m), _p(rho), _p(phi))
+    rc = _load().orc_solve_ddi_g(float(eps), int(bool(general)), _p(L), _p(N), _p(n), _p(m),
+                                 _p(rho), _p(phi))
     if rc:
         raise ValueError(f"orc_solve_ddi rejected the arguments ({rc})")
     return phi
 
 
-def solve(kind, L, N, rho, eps, lam=0.0) -> np.ndarray:
+def solve_q2d(L, N, rho, eps, eta, n) -> np.ndarray:
+    """Quasi-2D dipole-dipole potential U~ conv [-(3/2)(d_{n_perp n_perp} -
+    n_3^2 Lap_perp) rho] (Sec. 5.3), the derivative spectral on the grid."""
+    L = _f64(L)
+    N = _i64(N)
+    rho = _f64(rho)
+    n = _f64(n)
+    phi = np.empty_like(rho)
+    rc = _load().orc_solve_q2d(float(eps), float(eta), _p(L), _p(N), _p(n), _p(rho), _p(phi))
+    if rc:
+        raise ValueError(f"orc_solve_q2d rejected the arguments ({rc})")
+    return phi
+
+
+def solve(kind, L, N, rho, eps, lam=0.0, general=False, eta=None) -> np.ndarray:
     """Phi on the grid: build T, then the FFT route of eq. DiscConv."""
     L = _f64(L)
     N = _i64(N)
     rho = _f64(rho)
     phi = np.empty_like(rho)
-    rc = _load().orc_solve(_kind(kind), float(lam), float(eps), L.size, _p(L), _p(N),
-                           _p(rho), _p(phi))
+    rc = _load().orc_solve_g(_kind(kind), _par(kind, lam, eta), float(eps),
+                             int(bool(general)), L.size, _p(L), _p(N), _p(rho), _p(phi))
     if rc:
         raise ValueError(f"orc_solve rejected the arguments ({rc})")
     return phi

@@ -11,6 +11,7 @@ For rho(x) = a exp(-sum_j (x_j - c_j)^2 / s_j^2), y = x - c and
 
 * 3D Coulomb 1/(4 pi r):     Phi = a int_0^inf G(t) dt
 * 3D Yukawa e^{-lam r}/(4 pi r): Phi = a int_0^inf e^{-lam^2 t} G(t) dt
+* 2D Yukawa K0(lam r)/(2 pi):    the same integral with the 2D G(t)
 * 2D log -(1/2pi) ln r:      Phi = a int_0^inf [G(t) - s_0 s_1 e^{-1/(4t)}/(4t)] dt
 * 2D Coulomb 1/(2 pi r):     Phi = a/sqrt(pi) int_0^inf t^{-1/2} G(t) dt
 
@@ -136,7 +137,7 @@ def heat_integral(kind, y, s, lam=0.0, n_nodes=400, panels=8):
             g *= (s[j] / np.sqrt(q))[:, None] * np.exp(-(yy[j][None, :] ** 2) / q[:, None])
         if kind == "coulomb3d":
             f = g
-        elif kind == "yukawa3d":
+        elif kind in ("yukawa3d", "yukawa2d"):
             f = g * np.exp(-lam * lam * t)[:, None]
         elif kind == "log2d":
             f = g - (np.prod(s) * np.exp(-0.25 / t) / (4.0 * t))[:, None]
@@ -232,3 +233,49 @@ def ddi3d_iso(X, a, s, n, m):
     hess = np.where(z, -a * nm / 3.0, hess)
     rho = a * np.exp(-r * r / (s * s))
     return -nm * rho - 3.0 * hess
+
+
+def quasi2d_ddi_iso(X, a, s, eta, n, panels=60, n_nodes=24):
+    """Quasi-2D dipole-dipole potential of a * exp(-|x|^2/s^2) (Sec. 5.3):
+    Phi = -(3/2) (d_{n_perp n_perp} - n_3^2 Lap) F with F = U~ conv rho.
+
+    U~ has the 2D transform erfcx(k eta / sqrt 2) / k (its s-integral done in
+    closed form), so the radial F and its derivatives are Hankel integrals
+      F   =  (a s^2/2) int g(k) J0(kr) dk,
+      F'  = -(a s^2/2) int g(k) k J1(kr) dk,
+      F'' =  (a s^2/2) int g(k) k^2 (J1(kr)/(kr) - J0(kr)) dk,
+    g(k) = erfcx(k eta/sqrt 2) e^{-k^2 s^2/4}, by composite Gauss-Legendre on
+    [0, K], e^{-K^2 s^2/4} = e^{-46}.  The Hessian of a radial F is
+    F'' xh xh^T + F'/r (I - xh xh^T), and F''(0) I at r = 0."""
+    n = np.asarray(n, dtype=float)
+    x0, x1 = np.asarray(X[0], dtype=float), np.asarray(X[1], dtype=float)
+    r = np.sqrt(x0 * x0 + x1 * x1)
+    K = 2.0 * np.sqrt(46.0) / s
+    xg, wg = _gauss_legendre(n_nodes)
+    edges = np.linspace(0.0, K, panels + 1)
+    k = np.concatenate([a0 + (a1 - a0) * xg for a0, a1 in zip(edges[:-1], edges[1:])])
+    wk = np.concatenate([(a1 - a0) * wg for a0, a1 in zip(edges[:-1], edges[1:])])
+    g = special.erfcx(k * eta / np.sqrt(2.0)) * np.exp(-k * k * s * s / 4.0) * wk
+    c = a * s * s / 2.0
+    rf = r.ravel()
+    fp = np.empty_like(rf)
+    fpp = np.empty_like(rf)
+    for i0 in range(0, rf.size, 4096):
+        rr = rf[i0:i0 + 4096]
+        kr = np.outer(rr, k)
+        j0 = special.j0(kr)
+        j1 = special.j1(kr)
+        with np.errstate(divide="ignore", invalid="ignore"):
+            j1_over = np.where(kr > 0, j1 / np.where(kr > 0, kr, 1.0), 0.5)
+        fp[i0:i0 + 4096] = -c * (j1 * k) @ g
+        fpp[i0:i0 + 4096] = c * ((j1_over - j0) * k * k) @ g
+    fp = fp.reshape(r.shape)
+    fpp = fpp.reshape(r.shape)
+    z = r == 0.0
+    rr = np.where(z, 1.0, r)
+    fp_over_r = np.where(z, fpp, fp / rr)
+    xn = np.where(z, 0.0, (x0 * n[0] + x1 * n[1]) / rr)
+    nperp2 = n[0] * n[0] + n[1] * n[1]
+    d_nn = fpp * xn * xn + fp_over_r * (nperp2 - xn * xn)
+    lap = fpp + fp_over_r
+    return -1.5 * (d_nn - n[2] * n[2] * lap)
