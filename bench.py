@@ -274,6 +274,70 @@ def bench_ddi(F, torch, hip, synth, n=256, steps=50, warmup=10):
             "unit": "grid pts/s", **out}
 
 
+def _time_build(plan, torch, hip, reps=3):
+    stream = torch.cuda.current_stream()
+    plan.build()
+    torch.cuda.synchronize()
+    e0, e1 = hip.event(), hip.event()
+    ts = []
+    for _ in range(reps):
+        hip.record(e0, stream)
+        plan.build()
+        hip.record(e1, stream)
+        ts.append(hip.ms(e0, e1))
+    hip.destroy(e0)
+    hip.destroy(e1)
+    return sorted(ts)[reps // 2]
+
+
+def _time_apply(plan, rho, torch, hip, steps=20, warmup=5):
+    stream = torch.cuda.current_stream()
+    o = torch.empty_like(rho)
+    ws = plan.workspace()
+    for _ in range(warmup):
+        plan.apply(rho, o, ws)
+    torch.cuda.synchronize()
+    e0, e1 = hip.event(), hip.event()
+    hip.record(e0, stream)
+    for _ in range(steps):
+        plan.apply(rho, o, ws)
+    hip.record(e1, stream)
+    ms = hip.ms(e0, e1) / steps
+    hip.destroy(e0)
+    hip.destroy(e1)
+    return ms
+
+
+def bench_general(F, torch, hip, n=256, n2=2048):
+    """The general construction (window + quadrature W, Sec. 4): tensor
+    generation of 3D Yukawa at n^3 against the closed-form split, 2D Yukawa
+    and the quasi-2D DDI at n2^2 (Table 5's L = 12, lambda = 2, eta =
+    1/sqrt(32)); evaluation times of the two 2D kernels."""
+    out = {}
+    for general in (False, True):
+        plan = F.Plan("yukawa3d", (8.0,) * 3, (n,) * 3, "f32", eps=1.0, lam=2.0,
+                      general=general)
+        out["yukawa3d_%d_precomp_ms_%s" % (n, "general" if general else "closed")] = round(
+            _time_build(plan, torch, hip), 3)
+        plan.close()
+    axes = [(-12.0 + np.arange(n2) * (24.0 / n2)) for _ in range(2)]
+    X = np.meshgrid(*axes, indexing="ij")
+    rho64 = np.exp(-(X[0] ** 2 + X[1] ** 2) / 1.2)
+    for kind, kw in (("yukawa2d", {"lam": 2.0}),
+                     ("quasi2d_ddi", {"eta": 1 / np.sqrt(32), "n": (0.0, 0.0, 1.0)})):
+        for prec in ("f32", "f64"):
+            plan = F.Plan(kind, (12.0, 12.0), (n2, n2), prec, eps=1.0, **kw)
+            if prec == "f32":
+                out["%s_%d_precomp_ms" % (kind, n2)] = round(_time_build(plan, torch, hip), 3)
+            else:
+                plan.build()
+            rho = torch.from_numpy(rho64).to(F.DTYPES[prec]).cuda()
+            ms = _time_apply(plan, rho, torch, hip)
+            out["%s_%d_%s_ms" % (kind, n2, prec)] = round(ms, 4)
+            plan.close()
+    return out
+
+
 def stream_copy(torch, hip, nbytes=1 << 30, reps=10):
     """Device-to-device copy of nbytes (torch copy_ kernel): the practical
     bandwidth of the box, read + write bytes over time."""
@@ -533,6 +597,8 @@ def main():
     ap.add_argument("--batch-only", action="store_true", help="only the batched 2D workload")
     ap.add_argument("--no-serve", action="store_true", help="skip the served workload")
     ap.add_argument("--no-ddi", action="store_true", help="skip the dipole-dipole timing")
+    ap.add_argument("--no-general", action="store_true",
+                    help="skip the general-construction timings")
     ap.add_argument("--serve-only", action="store_true", help="only the served workload")
     ap.add_argument("--serve-seconds", type=float, default=3.0)
     ap.add_argument("--no-tune", action="store_true",
@@ -613,6 +679,10 @@ def main():
         ddi = bench_ddi(F, torch, hip, synth, n=args.n)
         log(f"  dipole-dipole: FP32 {ddi['f32']['ms_per_step']:.4f} ms, "
             f"FP64 {ddi['f64']['ms_per_step']:.4f} ms")
+    general = None
+    if not args.no_general:
+        general = bench_general(F, torch, hip, n=args.n)
+        log(f"  general construction: {general}")
     batch = None
     if not args.no_batch:
         log("batched 2D log workload (256 densities) ...")
@@ -671,6 +741,7 @@ def main():
         "precomp_ms": r32["precomp_ms"],
         "precomp_vs_anisotropy": sweep,
         "ddi": ddi,
+        "general": general,
         "wall_ms_per_step": r32["wall_ms_per_step"],
         "f32_vs_f64_rel_l2": diff,
         "batch": batch,

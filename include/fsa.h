@@ -67,7 +67,26 @@ typedef enum {
  *                     d_nm = (n.grad)(m.grad), the Coulomb part by FSA and
  *                     d_nm rho as the spectral derivative of rho on its own
  *                     grid, periodic on the box (q_j = i_j for i_j < N_j/2,
- *                     else i_j - N_j; k_j = pi q_j / L_j; real part). */
+ *                     else i_j - N_j; k_j = pi q_j / L_j; real part).
+ *   FSA_YUKAWA_2D     U = K0(lam r)/(2 pi) (Sec. 5.3); general construction.
+ *   FSA_QUASI2D_DDI   quasi-2D dipole-dipole interaction (Sec. 5.3) with the
+ *                     confinement width eta and dipole orientation n:
+ *                     Phi = U~ conv S,
+ *                     U~(r) = (2 pi)^{-3/2} int e^{-s^2/2} (r^2 + eta^2 s^2)^{-1/2} ds
+ *                           = (2 pi)^{-3/2} eta^{-1} e^x K0(x),  x = r^2/(4 eta^2),
+ *                     S = -(3/2)(d_{n_perp n_perp} - n_3^2 Lap) rho, n_perp =
+ *                     (n_0, n_1), as the spectral derivative on the grid (as for
+ *                     FSA_DDI_3D); U~ by the general construction.
+ *
+ * General construction (Sec. 4, eq. GeneralApprox1; fsa_kernel.general != 0
+ * for kinds 1-7, always for kinds 8 and 9):
+ *   U^eps = U erf(r/eps) (1 - xi(r)),  xi(r) = erfc((r - 6 eps)/eps)/2 where
+ *   U erf(r/eps) is not smooth at r = 0 (3D Yukawa, 2D log, 2D biharmonic,
+ *   kinds 8 and 9), xi = 0 otherwise (then U^eps is Table 1's);
+ *   W(k) = FT[U - U^eps](k) by quadrature of the radial transform (eq.
+ *   Fourier-Symmetric), in FP64 on the device.  A windowed plan needs
+ *   eps <= R0/12 (the window has decayed to 1e-17 at R0); its default eps is
+ *   R0/16. */
 typedef enum {
     FSA_COULOMB_3D = 1,
     FSA_YUKAWA_3D = 2,
@@ -75,7 +94,9 @@ typedef enum {
     FSA_COULOMB_2D = 4,
     FSA_BIHARMONIC_3D = 5,
     FSA_BIHARMONIC_2D = 6,
-    FSA_DDI_3D = 7
+    FSA_DDI_3D = 7,
+    FSA_YUKAWA_2D = 8,
+    FSA_QUASI2D_DDI = 9
 } fsa_kernel_kind;
 
 /* Arithmetic of the per-evaluation FFT convolution.  The tensor is always
@@ -85,11 +106,15 @@ typedef enum { FSA_F32 = 0, FSA_F64 = 1 } fsa_precision;
 typedef struct {
     int kind;       /* fsa_kernel_kind                                        */
     double lambda;  /* Yukawa screening lam > 0; ignored by other kernels     */
-    double eps;     /* split parameter; <= 0 selects the default R0/8,
-                       R0 = 2 min_j L_j (condition (b) of eq. ApproxProp,
-                       Remark 2.1 and Appendix B)                             */
+    double eps;     /* split parameter; <= 0 selects the default R0/8 (R0/16
+                       for the windowed general construction), R0 = 2 min_j
+                       L_j (condition (b) of eq. ApproxProp, Remark 2.1 and
+                       Appendix B)                                            */
     double n[3];    /* FSA_DDI_3D: dipole orientations n and m (finite, non-  */
-    double m[3];    /* zero; used as given); ignored by other kernels         */
+    double m[3];    /* zero; used as given); FSA_QUASI2D_DDI: n (m ignored);
+                       ignored by other kernels                               */
+    double eta;     /* FSA_QUASI2D_DDI: confinement width eta > 0            */
+    int general;    /* non-zero: the general construction for kinds 1-7      */
 } fsa_kernel;
 
 typedef struct fsa_plan_s* fsa_plan;
@@ -102,7 +127,8 @@ typedef struct fsa_plan_s* fsa_plan;
  *       3*2^a (the padded transform length 2 N_j must factor into the
  *       supported radices).
  *   p   FSA_F32 or FSA_F64.
- * The split parameter must satisfy 0 < eps <= R0/4 (FSA_EINVAL otherwise).
+ * The split parameter must satisfy 0 < eps <= R0/4, and eps <= R0/12 for a
+ * windowed general construction (FSA_EINVAL otherwise).
  * Double-precision accuracy needs eps <= R0/5.85 (condition (b) of eq.
  * ApproxProp, Appendix B) and eps >= 2 max_j h_j, which keeps the
  * trapezoidal error of the regular part, ~ e^{-pi^2 eps^2 / h^2}, below
@@ -168,7 +194,8 @@ fsa_status fsa_batch_workspace_bytes(int n, const fsa_plan* plans, size_t* bytes
  *                    pointers for plans[i].
  *   workspace        device scratch of >= fsa_batch_workspace_bytes bytes.
  * The device pointers are part of the captured graph: a call with the same
- * plans but different pointers re-captures. */
+ * plans but different pointers re-captures.  Dipole-dipole plans
+ * (FSA_DDI_3D, FSA_QUASI2D_DDI) are not batched: FSA_EUNSUPPORTED. */
 fsa_status fsa_apply_batched(int n, const fsa_plan* plans, const void* const* rho,
                              void* const* phi, void* workspace, size_t workspace_bytes,
                              void* stream);
@@ -201,7 +228,7 @@ typedef enum {
     FSA_PASS_CONV = 2,  /* C: FFT along axis 0, x tensor, inverse FFT, crop */
     FSA_PASS_INV_T = 3, /* D (3D): inverse FFT along axis 1, crop           */
     FSA_PASS_C2R = 4,   /* E: inverse real FFT along the last axis, crop    */
-    FSA_PASS_SPECTRAL = 5 /* FSA_DDI_3D: the d_nm rho derivative launches   */
+    FSA_PASS_SPECTRAL = 5 /* dipole-dipole kinds: the source derivative     */
 } fsa_pass;
 
 /* Every pass kernel exists in up to three compiled variants per length:
@@ -286,7 +313,7 @@ fsa_status fsa_server_create(size_t hbm_budget_bytes, int max_inflight, int n_st
 /* Queues one request; never blocks on the device.  rho/phi are device
  * pointers of the request's shape and precision, owned by the caller and
  * untouched until the ticket completes.  FSA_EBUDGET if the request alone
- * exceeds the budget. */
+ * exceeds the budget; FSA_EUNSUPPORTED for the dipole-dipole kinds. */
 fsa_status fsa_server_submit(fsa_server s, const fsa_kernel* k, int d, const double* L,
                              const int64_t* N, fsa_precision p, const void* rho, void* phi,
                              uint64_t* ticket);

@@ -38,9 +38,20 @@ int kernel_dim(int kind) {
     case FSA_DDI_3D: return 3;
     case FSA_LOG_2D:
     case FSA_COULOMB_2D:
-    case FSA_BIHARMONIC_2D: return 2;
+    case FSA_BIHARMONIC_2D:
+    case FSA_YUKAWA_2D:
+    case FSA_QUASI2D_DDI: return 2;
     }
     return 0;
+}
+
+bool finite_nonzero(const double* v) {
+    double s = 0.0;
+    for (int j = 0; j < 3; ++j) {
+        if (!std::isfinite(v[j])) return false;
+        s += v[j] * v[j];
+    }
+    return s > 0.0;
 }
 
 size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
@@ -65,19 +76,20 @@ fsa_status fsa_plan_create(const fsa_kernel* k, int d, const double* L, const in
                     kd, d);
     if (p != FSA_F32 && p != FSA_F64)
         return fail(FSA_EINVAL, "fsa_plan_create: unknown precision %d", (int)p);
-    if (k->kind == FSA_YUKAWA_3D && !(k->lambda > 0.0 && std::isfinite(k->lambda)))
+    const bool yukawa = k->kind == FSA_YUKAWA_3D || k->kind == FSA_YUKAWA_2D;
+    if (yukawa && !(k->lambda > 0.0 && std::isfinite(k->lambda)))
         return fail(FSA_EINVAL, "fsa_plan_create: Yukawa needs lambda > 0");
-    if (k->kind == FSA_DDI_3D) {
-        double nn = 0.0, mm = 0.0;
-        bool finite = true;
-        for (int j = 0; j < 3; ++j) {
-            finite = finite && std::isfinite(k->n[j]) && std::isfinite(k->m[j]);
-            nn += k->n[j] * k->n[j];
-            mm += k->m[j] * k->m[j];
-        }
-        if (!finite || !(nn > 0.0) || !(mm > 0.0))
-            return fail(FSA_EINVAL, "fsa_plan_create: DDI needs finite, nonzero n and m");
+    if (k->kind == FSA_DDI_3D && !(finite_nonzero(k->n) && finite_nonzero(k->m)))
+        return fail(FSA_EINVAL, "fsa_plan_create: DDI needs finite, nonzero n and m");
+    if (k->kind == FSA_QUASI2D_DDI) {
+        if (!finite_nonzero(k->n))
+            return fail(FSA_EINVAL, "fsa_plan_create: quasi-2D DDI needs a finite, nonzero n");
+        if (!(k->eta > 0.0 && std::isfinite(k->eta)))
+            return fail(FSA_EINVAL, "fsa_plan_create: quasi-2D DDI needs eta > 0");
     }
+    const bool general =
+        k->general != 0 || k->kind == FSA_YUKAWA_2D || k->kind == FSA_QUASI2D_DDI;
+    const bool windowed = general && fsa::kernel_windowed(k->kind);
     double minL = 1e300;
     for (int j = 0; j < d; ++j) {
         if (!(L[j] > 0.0 && std::isfinite(L[j])))
@@ -93,25 +105,33 @@ fsa_status fsa_plan_create(const fsa_kernel* k, int d, const double* L, const in
     }
     const double R0 = 2.0 * minL;
     double eps = k->eps;
-    if (!(eps > 0.0)) eps = R0 / 8.0;
+    if (!(eps > 0.0)) eps = windowed ? R0 / 16.0 : R0 / 8.0;
     if (!std::isfinite(eps) || eps > R0 / 4.0)
         return fail(FSA_EINVAL,
                     "fsa_plan_create: eps = %g violates the far-field condition (need eps <= "
                     "R0/4 = %g; 16 digits need eps <= R0/5.85)",
                     eps, R0 / 4.0);
+    // the window erfc((r - 6 eps)/eps)/2 must have decayed at R0
+    if (windowed && eps > R0 / 12.0)
+        return fail(FSA_EINVAL,
+                    "fsa_plan_create: eps = %g too large for the windowed general construction "
+                    "(need eps <= R0/12 = %g)",
+                    eps, R0 / 12.0);
 
     fsa_plan_s* pl = new (std::nothrow) fsa_plan_s();
     if (!pl) return fail(FSA_ENOMEM, "fsa_plan_create: out of host memory");
     static std::atomic<uint64_t> next_id{1};
     pl->id = next_id.fetch_add(1);
-    // a dipole-dipole plan convolves with the Coulomb tensor
+    // a 3D dipole-dipole plan convolves with the Coulomb tensor
     pl->ddi = k->kind == FSA_DDI_3D;
-    pl->kp = fsa::KernelParams{pl->ddi ? FSA_COULOMB_3D : k->kind,
-                               k->kind == FSA_YUKAWA_3D ? k->lambda : 0.0, eps};
-    if (pl->ddi)
+    pl->n_spectral = pl->ddi ? 5 : (k->kind == FSA_QUASI2D_DDI ? 3 : 0);
+    pl->kp = fsa::KernelParams{pl->ddi ? FSA_COULOMB_3D : k->kind, yukawa ? k->lambda : 0.0, eps,
+                               general ? 1 : 0,
+                               k->kind == FSA_QUASI2D_DDI ? k->eta : 0.0};
+    if (pl->n_spectral)
         for (int j = 0; j < 3; ++j) {
             pl->dn[j] = k->n[j];
-            pl->dm[j] = k->m[j];
+            pl->dm[j] = pl->ddi ? k->m[j] : 0.0;
         }
     pl->d = d;
     pl->prec = p;
@@ -129,7 +149,9 @@ fsa_status fsa_plan_create(const fsa_kernel* k, int d, const double* L, const in
         pl->ws2_elems = (size_t)pl->H * 2 * N[1] * N[0];
     } else {
         pl->ws1_elems = (size_t)pl->H * N[0];
-        pl->ws2_elems = 0;
+        // quasi-2D DDI: the real source N_0 x N_1 (the complex N-grid array of
+        // the derivative fits the first array, H > N_1)
+        pl->ws2_elems = pl->n_spectral ? (size_t)N[0] * N[1] / 2 : 0;
     }
     pl->ws_bytes = align256(pl->ws1_elems * pl->csize) + align256(pl->ws2_elems * pl->csize);
     pl->tensor_elems = 1;
@@ -144,7 +166,7 @@ fsa_status fsa_plan_create(const fsa_kernel* k, int d, const double* L, const in
     off += Nl;
     pl->tw_off_pl = off;
     off += 2 * Nl;
-    if (pl->ddi) {  // unpadded transforms of the derivative on the N-grid
+    if (pl->n_spectral) {  // unpadded transforms of the derivative on the N-grid
         pl->tw_off_n0 = off;
         off += N[0];
         pl->tw_off_n1 = off;
@@ -201,9 +223,9 @@ fsa_status fsa_build_tensor(fsa_plan pl, void* stream) {
         e = fsa::build_twiddles(pl->prec, (int)Nl, tw + pl->tw_off_m * pl->csize, st);
     if (e == hipSuccess)
         e = fsa::build_twiddles(pl->prec, (int)(2 * Nl), tw + pl->tw_off_pl * pl->csize, st);
-    if (e == hipSuccess && pl->ddi)
+    if (e == hipSuccess && pl->n_spectral)
         e = fsa::build_twiddles(pl->prec, (int)pl->N[0], tw + pl->tw_off_n0 * pl->csize, st);
-    if (e == hipSuccess && pl->ddi)
+    if (e == hipSuccess && pl->n_spectral)
         e = fsa::build_twiddles(pl->prec, (int)pl->N[1], tw + pl->tw_off_n1 * pl->csize, st);
     if (e != hipSuccess) return hip_fail(e, "fsa_build_tensor: twiddle kernels");
     e = fsa::build_tensor_device(pl->kp, pl->d, pl->L, pl->N, pl->h, pl->prec, pl->tensor, st);
@@ -272,8 +294,13 @@ static hipError_t launch_pass_t(const fsa_plan_s* pl, int k, int lo, int n, cons
             return Launch<R>::c2r(N2, w1, (R*)phi, N0, N1, add, alpha, tw_m, tw_pl, c, st);
         }
     } else {
+        // quasi-2D dipole-dipole: pass A convolves the source the derivative
+        // launches left in the second workspace array
+        const void* src =
+            pl->n_spectral ? (const void*)(w1 + ((pl->ws1_elems * cs + 255) & ~size_t(255)))
+                           : rho;
         switch (k) {
-        case 0: return Launch<R>::r2c(N1, (const R*)rho, w1, 1, N0, tw_m, tw_pl, c, st);
+        case 0: return Launch<R>::r2c(N1, (const R*)src, w1, 1, N0, tw_m, tw_pl, c, st);
         case 1: return Launch<R>::conv(2 * N0, w1, tensor, H, 1, 0, 0, tw_p0, c, st);
         case 2:
             return Launch<R>::c2r(N1, w1, (R*)phi, 1, N0, nullptr, 0.0, tw_m, tw_pl, c, st);
@@ -297,6 +324,7 @@ hipError_t launch_step(const fsa_plan_s* pl, const Step& s, const void* rho, voi
 int schedule(const fsa_plan_s* pl, int slabs, Step* out) {
     int m = 0;
     const int H = (int)pl->H;
+    for (int i = 0; i < pl->n_spectral; ++i) out[m++] = Step{kSpectralStep + i, 0, 0};
     if (pl->d != 3) {
         for (int k = 0; k < 3; ++k) out[m++] = Step{k, 0, H};
         return m;
@@ -304,8 +332,6 @@ int schedule(const fsa_plan_s* pl, int slabs, Step* out) {
     if (slabs < 1) slabs = 1;
     if (slabs > kMaxSlabs) slabs = kMaxSlabs;
     if (slabs > H) slabs = H;
-    if (pl->ddi)
-        for (int i = 0; i < kSpectralSteps; ++i) out[m++] = Step{kSpectralStep + i, 0, 0};
     out[m++] = Step{0, 0, H};
     for (int c = 0; c < slabs; ++c) {
         const int lo = (int)((long)H * c / slabs), hi = (int)((long)H * (c + 1) / slabs);

@@ -18,7 +18,16 @@ struct KernelParams {
     int kind;
     double lam;
     double eps;
+    int general = 0;   // general construction: U^eps = U erf(r/eps)(1 - xi), W by quadrature
+    double eta = 0.0;  // quasi-2D DDI confinement width
 };
+
+// Whether U erf(r/eps) is not smooth at r = 0, so that the general
+// construction multiplies it by the window 1 - xi(r).
+inline bool kernel_windowed(int kind) {
+    return !(kind == FSA_COULOMB_3D || kind == FSA_COULOMB_2D || kind == FSA_BIHARMONIC_3D ||
+             kind == FSA_DDI_3D);
+}
 
 // Supported grid lengths N (8 <= N <= 2048, N = 2^a or 3 * 2^a): the padded
 // transform 2N and, on the contiguous axis, the half-length N must both be
@@ -31,9 +40,10 @@ inline bool grid_length_supported(int64_t n) {
 // Forget cached batch graphs that use a plan (fsa_batch.cpp).
 void batch_forget_plan(uint64_t plan_id);
 
-// The d_nm rho launches of a dipole-dipole plan (fsa_spectral.hip): step s
-// in [0, 5) of the spectral derivative on the N-grid, reading rho and
-// leaving -3 d_nm rho (real, plan precision) at dst.
+// The source launches of a dipole-dipole plan (fsa_spectral.hip): step s in
+// [0, n_spectral) of the spectral derivative on the N-grid, reading rho and
+// leaving the real source (plan precision) at dst: -3 d_nm rho (3D, five
+// launches) or -(3/2)(d_{n_perp n_perp} - n_3^2 Lap) rho (quasi-2D, three).
 hipError_t spectral_step(const fsa_plan_s* pl, int s, const void* rho, void* z, void* dst,
                          hipStream_t st);
 
@@ -168,8 +178,8 @@ struct Step {
     int k, lo, n;
 };
 constexpr int kMaxSlabs = 16;
-// a dipole-dipole plan runs kSpectralSteps derivative launches first, as
-// steps k = kSpectralStep + i
+// a dipole-dipole plan runs its n_spectral (at most kSpectralSteps)
+// derivative launches first, as steps k = kSpectralStep + i
 constexpr int kSpectralStep = 5, kSpectralSteps = 5;
 constexpr int kMaxSteps = 2 + 3 * kMaxSlabs + kSpectralSteps;
 // Launch order of one evaluation with `slabs` slabs of bins (clamped to
@@ -210,11 +220,13 @@ struct fsa_plan_s {
     size_t tensor_elems = 0;  // octant elements
     // twiddle tables (elements from the start of `twiddles`)
     size_t tw_off_p0 = 0, tw_off_p1 = 0, tw_off_m = 0, tw_off_pl = 0;
-    size_t tw_off_n0 = 0, tw_off_n1 = 0;  // DDI: lengths N_0, N_1 (N_2 is tw_off_m)
+    size_t tw_off_n0 = 0, tw_off_n1 = 0;  // DDI: lengths N_0, N_1 (N_last is tw_off_m)
     size_t tw_elems = 0;
-    // dipole-dipole plans: the tensor is the Coulomb one (kp.kind), the
-    // derivative d_nm runs before the passes
+    // dipole-dipole plans: the source derivative runs before the passes
+    // (n_spectral launches); the 3D one convolves with the Coulomb tensor
+    // (kp.kind) and adds -(m.n) rho in its last pass
     bool ddi = false;
+    int n_spectral = 0;
     double dn[3] = {0, 0, 0}, dm[3] = {0, 0, 0};
     // device state
     int device = -1;

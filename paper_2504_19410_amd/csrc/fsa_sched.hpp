@@ -34,6 +34,7 @@ enum Status { ST_OK = 0, ST_EINVAL = 1, ST_EUNSUPPORTED = 2, ST_ENOMEM = 3, ST_E
 // Identity of a kernel tensor: everything that determines it.
 struct Key {
     int kind = 0, d = 0, prec = 0;
+    int general = 0;  // general construction requested
     double lam = 0, eps = 0;
     double L[3] = {0, 0, 0};
     int64_t N[3] = {0, 0, 0};
@@ -41,6 +42,7 @@ struct Key {
         if (kind != o.kind) return kind < o.kind;
         if (d != o.d) return d < o.d;
         if (prec != o.prec) return prec < o.prec;
+        if (general != o.general) return general < o.general;
         if (lam != o.lam) return lam < o.lam;
         if (eps != o.eps) return eps < o.eps;
         for (int j = 0; j < 3; ++j) {

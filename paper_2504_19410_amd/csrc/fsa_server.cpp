@@ -68,7 +68,11 @@ public:
     double now() override { return steady_now(); }
 
     Status create_plan(const Key& k, PlanInfo* out, std::string* err) override {
-        fsa_kernel kk{k.kind, k.lam, k.eps};
+        fsa_kernel kk{};
+        kk.kind = k.kind;
+        kk.lambda = k.lam;
+        kk.eps = k.eps;
+        kk.general = k.general;
         fsa_plan pl = nullptr;
         fsa_status s = fsa_plan_create(&kk, k.d, k.L, k.N, (fsa_precision)k.prec, &pl);
         if (s != FSA_OK) {
@@ -292,7 +296,7 @@ fsa_status fsa_server_submit(fsa_server s, const fsa_kernel* k, int d, const dou
         fsa::set_last_error("fsa_server_submit: bad arguments");
         return FSA_EINVAL;
     }
-    if (k->kind == FSA_DDI_3D) {
+    if (k->kind == FSA_DDI_3D || k->kind == FSA_QUASI2D_DDI) {
         fsa::set_last_error("fsa_server_submit: dipole-dipole requests are not served "
                             "(use a plan and fsa_apply)");
         return FSA_EUNSUPPORTED;
@@ -301,8 +305,9 @@ fsa_status fsa_server_submit(fsa_server s, const fsa_kernel* k, int d, const dou
     key.kind = k->kind;
     key.d = d;
     key.prec = (int)p;
-    key.lam = k->kind == FSA_YUKAWA_3D ? k->lambda : 0.0;
+    key.lam = (k->kind == FSA_YUKAWA_3D || k->kind == FSA_YUKAWA_2D) ? k->lambda : 0.0;
     key.eps = k->eps > 0 ? k->eps : 0.0;
+    key.general = k->general != 0 ? 1 : 0;
     for (int j = 0; j < d; ++j) {
         key.L[j] = L[j];
         key.N[j] = N[j];

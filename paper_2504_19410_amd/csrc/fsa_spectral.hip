@@ -1,4 +1,4 @@
-// fsa_spectral.hip -- the source term of the dipole-dipole potential.
+// fsa_spectral.hip -- the source terms of the dipole-dipole potentials.
 //
 // The 3D DDI is evaluated through the Coulomb kernel with the source
 // d_nm rho = (n.grad)(m.grad) rho (Sec. 5.3):
@@ -15,7 +15,11 @@
 //   3  Z along axis 1, inverse
 //   4  Z rows, inverse, real part -> -3 d_nm rho
 // (3 (k.n)(k.m) / prod N folds the -3, the sign of the derivative and the
-// normalisation of the inverse DFT into one factor.)  Each team of a
+// normalisation of the inverse DFT into one factor.)  The quasi-2D DDI
+// (Sec. 5.3) convolves S = -(3/2)(d_{n_perp n_perp} - n_3^2 Lap) rho, whose
+// transform is (3/2)((k.n_perp)^2 - n_3^2 |k|^2) rho^, in three launches:
+// rows forward, axis 0 forward x factor x inverse, rows inverse.  Both
+// factors are a scale times a quadratic form k^T A k.  Each team of a
 // workgroup transforms one line with the team FFT.  Launches along the
 // strided axes stage a tile of WT lines adjacent in memory through LDS, so
 // they read and write rows of WT consecutive elements; the row launches read
@@ -61,11 +65,13 @@ struct SLines {
     long u_stride, v_stride, es;
 };
 
-// The derivative factor of the axis-0 launch.
+// The derivative factor scale * k^T A k of the axis-0 launch, k = (k0, k1,
+// k2) with k0 along the launch's lines, k2 from the line index u and k1 from
+// v (a 2D plan maps its axis 1 to slot 2 and leaves slot 1 empty: c[1] = 0).
 struct SMul {
-    double c[3];      // pi / L_j
-    double n[3], m[3];
-    double scale;     // 3 / (N0 N1 N2)
+    double c[3];  // pi / L_j
+    double A[3][3];
+    double scale;
     int N[3];
 };
 
@@ -149,10 +155,11 @@ __global__ __launch_bounds__((Spec<R, P>::THREADS)) void k_spec(const void* in,
         const double k1 = mul.c[1] * q1, k2 = mul.c[2] * q2;
         Ff::for_each_last(x, tid, [&](int i0, C& c) {
             const int q0 = i0 < mul.N[0] / 2 ? i0 : i0 - mul.N[0];
-            const double k0 = mul.c[0] * q0;
-            const double kn = k0 * mul.n[0] + k1 * mul.n[1] + k2 * mul.n[2];
-            const double km = k0 * mul.m[0] + k1 * mul.m[1] + k2 * mul.m[2];
-            c = scale(c, (R)(mul.scale * kn * km));
+            const double k[3] = {mul.c[0] * q0, k1, k2};
+            double q = 0.0;
+            for (int a = 0; a < 3; ++a)
+                for (int b = 0; b < 3; ++b) q += mul.A[a][b] * k[a] * k[b];
+            c = scale(c, (R)(mul.scale * q));
         });
         Fi::run_g(x, sc, tid, tw);
         __syncthreads();
@@ -195,9 +202,42 @@ hipError_t go(int P, const void* in, void* out, SLines ln, const void* tw, const
     return hipErrorInvalidValue;
 }
 
+constexpr double kPi = 3.14159265358979323846264338327950288;
+
+// quasi-2D DDI: rows, axis 0 with the factor, rows inverse
+template <typename R>
+hipError_t step_2d(const fsa_plan_s* pl, int s, const void* rho, void* z, void* dst,
+                   hipStream_t st) {
+    const long N0 = pl->N[0], N1 = pl->N[1];
+    const char* tw = (const char*)pl->twiddles;
+    const void* tw0 = tw + pl->tw_off_n0 * pl->csize;
+    const void* tw1 = tw + pl->tw_off_m * pl->csize;  // length N1
+    SMul mul{};
+    // 2D axes 0, 1 in slots 0, 2; (3/2)((k.n_perp)^2 - n_3^2 |k|^2) / (N0 N1)
+    const double n0 = pl->dn[0], n1 = pl->dn[1], n3sq = pl->dn[2] * pl->dn[2];
+    mul.c[0] = kPi / pl->L[0];
+    mul.c[2] = kPi / pl->L[1];
+    mul.N[0] = (int)N0;
+    mul.N[1] = 1;
+    mul.N[2] = (int)N1;
+    mul.A[0][0] = n0 * n0 - n3sq;
+    mul.A[2][2] = n1 * n1 - n3sq;
+    mul.A[0][2] = mul.A[2][0] = n0 * n1;
+    mul.scale = 1.5 / ((double)N0 * (double)N1);
+    const SLines rows{(int)N0, 1, N1, 0, 1};
+    const SLines ax0{(int)N1, 1, 1, 0, N1};
+    switch (s) {
+    case 0: return go<R, ROW_FWD_REAL>((int)N1, rho, z, rows, tw1, mul, st);
+    case 1: return go<R, COL_MUL>((int)N0, z, z, ax0, tw0, mul, st);
+    case 2: return go<R, ROW_INV_REAL>((int)N1, z, dst, rows, tw1, mul, st);
+    }
+    return hipErrorInvalidValue;
+}
+
 template <typename R>
 hipError_t step_t(const fsa_plan_s* pl, int s, const void* rho, void* z, void* dst,
                   hipStream_t st) {
+    if (pl->d == 2) return step_2d<R>(pl, s, rho, z, dst, st);
     const long N0 = pl->N[0], N1 = pl->N[1], N2 = pl->N[2];
     const char* tw = (const char*)pl->twiddles;
     const void* tw0 = tw + pl->tw_off_n0 * pl->csize;
@@ -206,12 +246,14 @@ hipError_t step_t(const fsa_plan_s* pl, int s, const void* rho, void* z, void* d
     SMul mul{};
     double prodN = 1.0;
     for (int j = 0; j < 3; ++j) {
-        mul.c[j] = 3.14159265358979323846264338327950288 / pl->L[j];
-        mul.n[j] = pl->dn[j];
-        mul.m[j] = pl->dm[j];
+        mul.c[j] = kPi / pl->L[j];
         mul.N[j] = (int)pl->N[j];
         prodN *= (double)pl->N[j];
     }
+    // (k.n)(k.m) = k^T A k with A the symmetric part of n m^T
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b)
+            mul.A[a][b] = 0.5 * (pl->dn[a] * pl->dm[b] + pl->dm[a] * pl->dn[b]);
     mul.scale = 3.0 / prodN;
     // rows: lines along axis 2, groups of consecutive rows
     const SLines rows{(int)N1, (int)N0, N2, N1 * N2, 1};

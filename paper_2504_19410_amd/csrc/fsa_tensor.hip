@@ -12,7 +12,26 @@
 //   DFT(T1)[p] = sum_{n=0}^{N} c_n T1[n] cos(pi p n / N),  c_0 = c_N = 1, else 2,
 // computed as the length-2N FFT of the even extension of each line.
 // Octant storage: axis 0 innermost, index ((a2 D1 + a1) D0 + a0), D_j = N_j + 1.
+//
+// General construction (Sec. 4, eq. GeneralApprox1): U^eps = U erf(r/eps)
+// (1 - xi(r)) with the window xi(r) = erfc((r - 6 eps)/eps)/2 where
+// U erf(r/eps) is not smooth at r = 0, and W(k) the radial transform of
+// U - U^eps (eq. Fourier-Symmetric) by quadrature.  W depends on |k| only and
+// is smooth (analytic) in it, so it is computed at Chebyshev points of short
+// panels of |k| and the finalize kernel evaluates the panel's Chebyshev
+// interpolant at each lattice |k|:
+//   k_wq_nodes   quadrature weights g_i = c_d w_i r_i^{d-1} (U - U^eps)(r_i)
+//                on composite 16-point Gauss-Legendre panels of [0, R_end]
+//                (geometrically graded towards r = 0 for the 2D kernels with
+//                a logarithm there);
+//   k_wq_sum     W(kappa) = sum_i g_i J0(kappa r_i)  (2D)  or
+//                           sum_i g_i sin(kappa r_i)/(kappa r_i)  (3D),
+//                one workgroup per Chebyshev node kappa;
+//   k_cheb       Chebyshev coefficients of each panel's interpolant.
 #include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <vector>
 
 #include "fsa_internal.hpp"
 
@@ -126,6 +145,201 @@ __device__ double d_what(const KernelParams& kp, double k) {
     return 0.0;
 }
 
+// ---------------------------------------------------------------------------
+// General construction
+// ---------------------------------------------------------------------------
+
+// K0(x), 0 < x <= 1, by its ascending series (A&S 9.6.13 with 9.6.12):
+// K0 = -(ln(x/2) + gamma) I0(x) + sum_{k>=1} H_k (x^2/4)^k / (k!)^2.
+__device__ double d_k0_series(double x) {
+    const double q = 0.25 * x * x;
+    double term = 1.0, i0 = 1.0, tail = 0.0, hk = 0.0;
+    for (int k = 1; k < 30; ++k) {
+        term *= q / ((double)k * (double)k);
+        hk += 1.0 / (double)k;
+        i0 += term;
+        tail += hk * term;
+        if (term < 1e-18 * i0) break;
+    }
+    return -(log(0.5 * x) + kEulerGamma) * i0 + tail;
+}
+
+// e^x K0(x), x > 1: the trapezoidal rule on
+// e^x K0(x) = int_0^inf e^{-2 x sinh^2(t/2)} dt  (A&S 9.6.24).  The integrand
+// is analytic in a strip and decays double-exponentially, so the rule
+// converges geometrically; the step min(0.2, 0.65/sqrt(x)) also resolves its
+// width 1/sqrt(x) at large x (relative error below 1e-15 for all x > 1, at
+// most ~25 terms).
+__device__ double d_k0e_large(double x) {
+    const double tau = fmin(0.2, 0.65 / sqrt(x));
+    double s = 0.5;
+    for (int j = 1; j < 64; ++j) {
+        const double sh = sinh(0.5 * j * tau);
+        const double v = exp(-2.0 * x * sh * sh);
+        s += v;
+        if (v < 1e-18) break;
+    }
+    return tau * s;
+}
+
+__device__ double d_k0(double x) { return x <= 1.0 ? d_k0_series(x) : exp(-x) * d_k0e_large(x); }
+__device__ double d_k0e(double x) {
+    return x <= 1.0 ? exp(x) * d_k0_series(x) : d_k0e_large(x);
+}
+
+// U(r), r > 0
+__device__ double d_u(const KernelParams& kp, double r) {
+    switch (kp.kind) {
+    case FSA_COULOMB_3D: return 1.0 / (4.0 * kPi * r);
+    case FSA_YUKAWA_3D: return exp(-kp.lam * r) / (4.0 * kPi * r);
+    case FSA_LOG_2D: return -log(r) / (2.0 * kPi);
+    case FSA_COULOMB_2D: return 1.0 / (2.0 * kPi * r);
+    case FSA_BIHARMONIC_3D: return r / (8.0 * kPi);
+    case FSA_BIHARMONIC_2D: return -r * r * (log(r) - 1.0) / (8.0 * kPi);
+    case FSA_YUKAWA_2D: return d_k0(kp.lam * r) / (2.0 * kPi);
+    case FSA_QUASI2D_DDI: {
+        const double x = r * r / (4.0 * kp.eta * kp.eta);
+        return d_k0e(x) / (2.0 * kPi * sqrt(2.0 * kPi) * kp.eta);
+    }
+    }
+    return 0.0;
+}
+
+__device__ bool d_windowed(int kind) {
+    return !(kind == FSA_COULOMB_3D || kind == FSA_COULOMB_2D || kind == FSA_BIHARMONIC_3D);
+}
+
+// U^eps of the general construction; r = 0 takes the limit of
+// U erf(r/eps) (1 - xi(r)).
+__device__ double d_ueps_general(const KernelParams& kp, double r) {
+    const double eps = kp.eps;
+    const bool win = d_windowed(kp.kind);
+    const double keep0 = 0.5 * erfc(6.0);  // 1 - xi(0)
+    if (r == 0.0) {
+        double lim = 0.0;  // r ln r, r and r^3 ln r vanish
+        if (kp.kind == FSA_COULOMB_3D || kp.kind == FSA_YUKAWA_3D)
+            lim = 1.0 / (2.0 * kPi * sqrt(kPi) * eps);
+        else if (kp.kind == FSA_COULOMB_2D)
+            lim = 1.0 / (kPi * sqrt(kPi) * eps);
+        return win ? lim * keep0 : lim;
+    }
+    const double v = d_u(kp, r) * erf(r / eps);
+    return win ? v * 0.5 * erfc((6.0 * eps - r) / eps) : v;
+}
+
+// (U - U^eps)(r) = U(r) [erfc(r/eps) + erf(r/eps) xi(r)], r > 0
+__device__ double d_remainder(const KernelParams& kp, double r) {
+    const double eps = kp.eps;
+    double g = erfc(r / eps);
+    if (d_windowed(kp.kind)) g += erf(r / eps) * 0.5 * erfc((r - 6.0 * eps) / eps);
+    return d_u(kp, r) * g;
+}
+
+constexpr int kGl = 16;  // Gauss-Legendre points per panel
+constexpr int kCheb = 24;  // Chebyshev degree per |k| panel
+
+struct Gl16 {
+    double x[kGl], w[kGl];  // nodes and weights on [-1, 1]
+};
+
+// Panels of [0, R_end]: n_uni uniform panels of width wu; with `graded`
+// levels the first of them is replaced by [0, wu s^G], [wu s^{m+1}, wu s^m]
+// (m = G-1 .. 0).
+struct QMesh {
+    double wu, sigma;
+    int n_uni, graded;
+    __device__ int n_panels() const { return graded ? n_uni + graded : n_uni; }
+    __device__ void panel(int p, double& a, double& b) const {
+        if (graded) {
+            if (p == 0) {
+                a = 0.0;
+                b = wu * pow(sigma, (double)graded);
+                return;
+            }
+            if (p <= graded) {
+                a = wu * pow(sigma, (double)(graded - p + 1));
+                b = wu * pow(sigma, (double)(graded - p));
+                return;
+            }
+            p -= graded;
+        }
+        a = wu * p;
+        b = wu * (p + 1);
+    }
+};
+
+__global__ void k_wq_nodes(double* __restrict__ g, double* __restrict__ rn, QMesh m, Gl16 gl,
+                           int d, KernelParams kp) {
+    const int n = m.n_panels() * kGl;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double a, b;
+    m.panel(i / kGl, a, b);
+    const int j = i % kGl;
+    const double hw = 0.5 * (b - a), r = 0.5 * (a + b) + hw * gl.x[j];
+    const double cd = d == 2 ? 2.0 * kPi * r : 4.0 * kPi * r * r;
+    rn[i] = r;
+    g[i] = hw * gl.w[j] * cd * d_remainder(kp, r);
+}
+
+// Chebyshev point l of |k| panel q
+__device__ double cheb_node(int q, int l, double dk) {
+    return dk * (q + 0.5 * (1.0 + cospi((double)l / kCheb)));
+}
+
+__global__ __launch_bounds__(256) void k_wq_sum(const double* __restrict__ g,
+                                                const double* __restrict__ rn, int n, int d,
+                                                double dk, double* __restrict__ out) {
+    __shared__ double red[256];
+    const int node = blockIdx.x;
+    const double kap = cheb_node(node / (kCheb + 1), node % (kCheb + 1), dk);
+    double s = 0.0;
+    for (int i = threadIdx.x; i < n; i += 256) {
+        const double x = kap * rn[i];
+        const double f = d == 2 ? j0(x) : (x == 0.0 ? 1.0 : sin(x) / x);
+        s += g[i] * f;
+    }
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[node] = red[0];
+}
+
+// c_j = a_j (halved for j = 0 and j = n), a_j = (2/n) sum''_l f_l cos(pi j l/n):
+// the interpolant at the Chebyshev-Lobatto points is sum_j c_j T_j(s).
+__global__ void k_cheb(const double* __restrict__ v, double* __restrict__ c, int nq) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nq * (kCheb + 1)) return;
+    const int q = i / (kCheb + 1), j = i % (kCheb + 1);
+    const double* f = v + (long)q * (kCheb + 1);
+    double a = 0.0;
+    for (int l = 0; l <= kCheb; ++l) {
+        const double w = (l == 0 || l == kCheb) ? 0.5 : 1.0;
+        a += w * f[l] * cospi((double)(j * l % (2 * kCheb)) / kCheb);
+    }
+    a *= 2.0 / kCheb;
+    if (j == 0 || j == kCheb) a *= 0.5;
+    c[i] = a;
+}
+
+// W(kappa) from the panel's Chebyshev coefficients (Clenshaw)
+__device__ double d_what_cheb(const double* __restrict__ cf, double dk, int nq, double kap) {
+    int q = (int)(kap / dk);
+    if (q >= nq) q = nq - 1;
+    const double s = 2.0 * (kap / dk - q) - 1.0;
+    const double* c = cf + (long)q * (kCheb + 1);
+    double b1 = 0.0, b2 = 0.0;
+    for (int j = kCheb; j >= 1; --j) {
+        const double b0 = c[j] + 2.0 * s * b1 - b2;
+        b2 = b1;
+        b1 = b0;
+    }
+    return c[0] + s * b1 - b2;
+}
+
 struct Oct {
     int D0, D1, D2;
     __device__ void split(long i, int& a0, int& a1, int& a2) const {
@@ -145,7 +359,8 @@ __global__ void k_sample(double* __restrict__ out, Oct o, double h0, double h1, 
         int a0, a1, a2;
         o.split(i, a0, a1, a2);
         const double x = a0 * h0, y = a1 * h1, z = a2 * h2;
-        out[i] = hprod * d_ueps(kp, sqrt(x * x + y * y + z * z));
+        const double r = sqrt(x * x + y * y + z * z);
+        out[i] = hprod * (kp.general ? d_ueps_general(kp, r) : d_ueps(kp, r));
     }
 }
 
@@ -244,9 +459,17 @@ hipError_t dct_axis(const double* in, double* out, Lines ln, int N, const void* 
     return hipErrorInvalidValue;
 }
 
+// W of the general construction: Chebyshev coefficients cf of nq panels of
+// width dk (null for the closed forms).
+struct WTable {
+    const double* cf;
+    double dk;
+    int nq;
+};
+
 template <typename R>
 __global__ void k_finalize(const double* __restrict__ dct, R* __restrict__ out, Oct o, double c0,
-                           double c1, double c2, double inv_prod_p, KernelParams kp) {
+                           double c1, double c2, double inv_prod_p, KernelParams kp, WTable wt) {
     const long n = o.size();
     for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n;
          i += (long)gridDim.x * blockDim.x) {
@@ -254,8 +477,87 @@ __global__ void k_finalize(const double* __restrict__ dct, R* __restrict__ out, 
         o.split(i, a0, a1, a2);
         const double kx = a0 * c0, ky = a1 * c1, kz = a2 * c2;
         const double k = sqrt(kx * kx + ky * ky + kz * kz);
-        out[i] = (R)((dct[i] + d_what(kp, k)) * inv_prod_p);
+        const double w = wt.cf ? d_what_cheb(wt.cf, wt.dk, wt.nq, k) : d_what(kp, k);
+        out[i] = (R)((dct[i] + w) * inv_prod_p);
     }
+}
+
+// Gauss-Legendre nodes and weights by Newton's method on the Legendre
+// recurrence (host, FP64).
+Gl16 gauss_legendre16() {
+    Gl16 g{};
+    const int n = kGl;
+    for (int i = 0; i < n; ++i) {
+        double x = std::cos(kPi * (i + 0.75) / (n + 0.5)), dp = 1.0;
+        for (int it = 0; it < 100; ++it) {
+            double p0 = 1.0, p1 = x;
+            for (int k = 2; k <= n; ++k) {
+                const double p2 = ((2.0 * k - 1.0) * x * p1 - (k - 1.0) * p0) / k;
+                p0 = p1;
+                p1 = p2;
+            }
+            dp = n * (x * p1 - p0) / (x * x - 1.0);
+            const double dx = p1 / dp;
+            x -= dx;
+            if (std::fabs(dx) < 1e-16) break;
+        }
+        g.x[i] = x;
+        g.w[i] = 2.0 / ((1.0 - x * x) * dp * dp);
+    }
+    return g;
+}
+
+// The general construction's W table, on the stream; device buffers are
+// returned in bufs for the caller to free after the finalize launch.
+hipError_t build_w_table(const KernelParams& kp, int d, const double* L, const int64_t* N,
+                         hipStream_t st, WTable* wt, std::vector<void*>* bufs) {
+    const double eps = kp.eps;
+    const bool win = !(kp.kind == FSA_COULOMB_3D || kp.kind == FSA_COULOMB_2D ||
+                       kp.kind == FSA_BIHARMONIC_3D);
+    // largest lattice |k| of the octant: k_j = pi p_j / (2 L_j), p_j <= N_j
+    double k2 = 0.0;
+    for (int j = 0; j < d; ++j) {
+        const double kj = kPi * (double)N[j] / (2.0 * L[j]);
+        k2 += kj * kj;
+    }
+    const double kmax = std::sqrt(k2);
+    // U - U^eps is below 1e-20 of its scale beyond R_end
+    const double r_end = win ? 13.0 * eps : 7.0 * eps;
+    // panel width: the oscillation (kmax w <= 6), the window and erfc (eps/4),
+    // the Yukawa decay and the quasi-2D kernel's scale eta
+    double w = std::fmin(6.0 / kmax, 0.25 * eps);
+    if (kp.kind == FSA_YUKAWA_3D || kp.kind == FSA_YUKAWA_2D) w = std::fmin(w, 4.0 / kp.lam);
+    if (kp.kind == FSA_QUASI2D_DDI) w = std::fmin(w, 0.5 * kp.eta);
+    QMesh m{};
+    m.n_uni = (int)std::ceil(r_end / w);
+    m.wu = r_end / m.n_uni;
+    m.sigma = 0.15;
+    // 2D kernels with a logarithm at r = 0: grade the first panel
+    const bool log0 = kp.kind == FSA_LOG_2D || kp.kind == FSA_BIHARMONIC_2D ||
+                      kp.kind == FSA_YUKAWA_2D || kp.kind == FSA_QUASI2D_DDI;
+    m.graded = log0 ? 14 : 0;
+    const int n_nodes = (m.graded ? m.n_uni + m.graded : m.n_uni) * kGl;
+    // |k| panels of width 0.5/eps, kCheb + 1 Chebyshev-Lobatto points each
+    wt->dk = 0.5 / eps;
+    wt->nq = (int)std::ceil(kmax / wt->dk);
+    if (wt->nq < 1) wt->nq = 1;
+    const int n_k = wt->nq * (kCheb + 1);
+    double *g = nullptr, *rn = nullptr, *v = nullptr, *cf = nullptr;
+    hipError_t e = hipMallocAsync((void**)&g, sizeof(double) * n_nodes, st);
+    if (e == hipSuccess) bufs->push_back(g), e = hipMallocAsync((void**)&rn, sizeof(double) * n_nodes, st);
+    if (e == hipSuccess) bufs->push_back(rn), e = hipMallocAsync((void**)&v, sizeof(double) * n_k, st);
+    if (e == hipSuccess) bufs->push_back(v), e = hipMallocAsync((void**)&cf, sizeof(double) * n_k, st);
+    if (e != hipSuccess) return e;
+    bufs->push_back(cf);
+    const Gl16 gl = gauss_legendre16();
+    hipLaunchKernelGGL(k_wq_nodes, dim3((n_nodes + 255) / 256), dim3(256), 0, st, g, rn, m, gl,
+                       d, kp);
+    hipLaunchKernelGGL(k_wq_sum, dim3(n_k), dim3(256), 0, st, (const double*)g,
+                       (const double*)rn, n_nodes, d, wt->dk, v);
+    hipLaunchKernelGGL(k_cheb, dim3((n_k + 255) / 256), dim3(256), 0, st, (const double*)v, cf,
+                       wt->nq);
+    wt->cf = cf;
+    return hipGetLastError();
 }
 
 template <typename R>
@@ -322,17 +624,25 @@ hipError_t build_tensor_device(const KernelParams& kp, int d, const double* L, c
         src = dst;
         dst = t;
     }
+    WTable wt{nullptr, 0.0, 0};
+    std::vector<void*> wbufs;
+    if (e == hipSuccess && kp.general) e = build_w_table(kp, d, L, N, st, &wt, &wbufs);
     double prodP = 1.0;
     for (int j = 0; j < d; ++j) prodP *= 2.0 * (double)N[j];
     const double c0 = kPi / (2.0 * L[0]), c1 = kPi / (2.0 * L[1]);
     const double c2 = d == 3 ? kPi / (2.0 * L[2]) : 0.0;
-    if (prec == FSA_F32)
-        hipLaunchKernelGGL(k_finalize<float>, dim3(grid), dim3(block), 0, st, (const double*)src,
-                           (float*)tensor_out, o, c0, c1, c2, 1.0 / prodP, kp);
-    else
-        hipLaunchKernelGGL(k_finalize<double>, dim3(grid), dim3(block), 0, st, (const double*)src,
-                           (double*)tensor_out, o, c0, c1, c2, 1.0 / prodP, kp);
-    if (e == hipSuccess) e = hipGetLastError();
+    if (e == hipSuccess) {
+        if (prec == FSA_F32)
+            hipLaunchKernelGGL(k_finalize<float>, dim3(grid), dim3(block), 0, st,
+                               (const double*)src, (float*)tensor_out, o, c0, c1, c2,
+                               1.0 / prodP, kp, wt);
+        else
+            hipLaunchKernelGGL(k_finalize<double>, dim3(grid), dim3(block), 0, st,
+                               (const double*)src, (double*)tensor_out, o, c0, c1, c2,
+                               1.0 / prodP, kp, wt);
+        e = hipGetLastError();
+    }
+    for (void* p : wbufs) (void)hipFreeAsync(p, st);
     (void)hipFreeAsync(a, st);
     (void)hipFreeAsync(b, st);
     (void)hipFreeAsync(tw, st);

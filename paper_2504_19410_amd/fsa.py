@@ -26,9 +26,12 @@ KINDS = {
     "biharmonic3d": 5,
     "biharmonic2d": 6,
     "ddi3d": 7,
+    "yukawa2d": 8,
+    "quasi2d_ddi": 9,
 }
 KIND_DIM = {"coulomb3d": 3, "yukawa3d": 3, "biharmonic3d": 3,
-            "log2d": 2, "coulomb2d": 2, "biharmonic2d": 2, "ddi3d": 3}
+            "log2d": 2, "coulomb2d": 2, "biharmonic2d": 2, "ddi3d": 3,
+            "yukawa2d": 2, "quasi2d_ddi": 2}
 PRECISIONS = {"f32": 0, "f64": 1}
 DTYPES = {"f32": torch.float32, "f64": torch.float64}
 
@@ -62,7 +65,8 @@ class FsaError(RuntimeError):
 
 class _Kernel(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int), ("lambda_", ctypes.c_double), ("eps", ctypes.c_double),
-                ("n", ctypes.c_double * 3), ("m", ctypes.c_double * 3)]
+                ("n", ctypes.c_double * 3), ("m", ctypes.c_double * 3),
+                ("eta", ctypes.c_double), ("general", ctypes.c_int)]
 
 
 class Stats(ctypes.Structure):
@@ -142,7 +146,8 @@ def _stream_ptr(stream: Optional[torch.cuda.Stream] = None):
     return ctypes.c_void_p(s.cuda_stream)
 
 
-def _kernel(kind: str, eps: Optional[float], lam: Optional[float], n=None, m=None) -> _Kernel:
+def _kernel(kind: str, eps: Optional[float], lam: Optional[float], n=None, m=None,
+            eta: Optional[float] = None, general: bool = False) -> _Kernel:
     if kind not in KINDS:
         raise ValueError(f"unknown kernel {kind!r}; choose from {sorted(KINDS)}")
     k = _Kernel(KINDS[kind], float(lam or 0.0), float(eps) if eps else 0.0)
@@ -150,6 +155,8 @@ def _kernel(kind: str, eps: Optional[float], lam: Optional[float], n=None, m=Non
         k.n[j] = float(v)
     for j, v in enumerate(m if m is not None else (0.0, 0.0, 0.0)):
         k.m[j] = float(v)
+    k.eta = float(eta or 0.0)
+    k.general = 1 if general else 0
     return k
 
 
@@ -158,8 +165,13 @@ class Plan:
 
     def __init__(self, kernel: str, L: Sequence[float], N: Sequence[int], precision: str = "f32",
                  eps: Optional[float] = None, lam: Optional[float] = None,
-                 n: Optional[Sequence[float]] = None, m: Optional[Sequence[float]] = None):
-        """n, m: dipole orientations of the "ddi3d" kernel (ignored otherwise)."""
+                 n: Optional[Sequence[float]] = None, m: Optional[Sequence[float]] = None,
+                 eta: Optional[float] = None, general: bool = False):
+        """n, m: dipole orientations of the "ddi3d" kernel, n of "quasi2d_ddi"
+        (ignored otherwise); eta: confinement width of "quasi2d_ddi";
+        general: the general construction (window + quadrature W) for the
+        kernels that also have a closed-form one ("yukawa2d" and
+        "quasi2d_ddi" always use it)."""
         if precision not in PRECISIONS:
             raise ValueError(f"precision must be one of {list(PRECISIONS)}")
         self.kernel, self.precision = kernel, precision
@@ -169,7 +181,8 @@ class Plan:
         self.d = len(self.N)
         if len(self.L) != self.d:
             raise ValueError("L and N must have the same length")
-        k = _kernel(kernel, eps, lam, n, m)
+        k = _kernel(kernel, eps, lam, n, m, eta, general)
+        self.general = bool(general) or kernel in ("yukawa2d", "quasi2d_ddi")
         Ls = (ctypes.c_double * self.d)(*self.L)
         Ns = (ctypes.c_int64 * self.d)(*self.N)
         h = ctypes.c_void_p()
@@ -452,7 +465,7 @@ class Server:
 
     def submit(self, kernel: str, L: Sequence[float], N: Sequence[int], rho: torch.Tensor,
                phi: torch.Tensor, precision: str = "f32", eps: Optional[float] = None,
-               lam: Optional[float] = None) -> int:
+               lam: Optional[float] = None, general: bool = False) -> int:
         """Queues phi = U * rho; returns a ticket.  rho and phi must stay alive
         (and phi untouched) until the ticket completes."""
         d = len(N)
@@ -462,7 +475,7 @@ class Server:
             raise ValueError("rho/phi dtype must match the precision")
         if not (rho.is_cuda and phi.is_cuda and rho.is_contiguous() and phi.is_contiguous()):
             raise ValueError("rho/phi must be contiguous device tensors")
-        k = _kernel(kernel, eps, lam)
+        k = _kernel(kernel, eps, lam, general=general)
         Ls = (ctypes.c_double * d)(*[float(x) for x in L])
         Ns = (ctypes.c_int64 * d)(*[int(n) for n in N])
         t = ctypes.c_uint64()

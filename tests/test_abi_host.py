@@ -89,6 +89,35 @@ def test_plan_validation_params(F):
                                                           b.workspace_bytes)
 
 
+def test_general_construction_validation(F):
+    """Kinds 8 and 9 and the general flag (host-side plan creation only)."""
+    with pytest.raises(F.FsaError, match="lambda"):
+        F.Plan("yukawa2d", (8, 8), (32, 32))
+    with pytest.raises(F.FsaError, match="EINVAL"):
+        F.Plan("yukawa2d", (8, 8, 8), (32, 32, 32), lam=1.0)        # 2D only
+    with pytest.raises(F.FsaError, match="eta"):
+        F.Plan("quasi2d_ddi", (8, 8), (32, 32), n=(0, 0, 1))
+    with pytest.raises(F.FsaError, match="quasi-2D"):
+        F.Plan("quasi2d_ddi", (8, 8), (32, 32), n=(0, 0, 0), eta=0.3)
+    with pytest.raises(F.FsaError, match="R0/12"):                    # window must decay by R0
+        F.Plan("yukawa2d", (8, 8), (32, 32), lam=1.0, eps=1.4)
+    with pytest.raises(F.FsaError, match="R0/12"):
+        F.Plan("log2d", (8, 8), (32, 32), eps=1.4, general=True)
+    # without the window (U erf(r/eps) smooth) the general flag keeps R0/4
+    assert F.Plan("coulomb3d", (8, 8, 8), (32,) * 3, eps=3.0, general=True).eps == 3.0
+    # defaults: R0/16 with the window, R0/8 without
+    assert F.Plan("yukawa2d", (8, 6), (32, 32), lam=1.0).eps == pytest.approx(12.0 / 16.0)
+    assert F.Plan("yukawa3d", (8,) * 3, (32,) * 3, lam=1.0, general=True).eps == \
+        pytest.approx(1.0)
+    assert F.Plan("coulomb2d", (8, 8), (32, 32), general=True).eps == pytest.approx(2.0)
+    # quasi-2D: the real source needs a second workspace array of N0 N1 reals
+    q = F.Plan("quasi2d_ddi", (8, 8), (32, 48), "f64", n=(0, 0, 1), eta=0.3)
+    y = F.Plan("yukawa2d", (8, 8), (32, 48), "f64", lam=1.0)
+    r = lambda b: (b + 255) // 256 * 256
+    assert q.workspace_bytes == y.workspace_bytes + r(32 * 48 * 8)
+    assert q.tensor_bytes == y.tensor_bytes
+
+
 def test_apply_before_build_is_a_state_error(F):
     p = F.Plan("coulomb3d", (8, 8, 8), (16, 16, 16))
     st = F.lib().fsa_apply(p.handle, ctypes.c_void_p(256), ctypes.c_void_p(256),
