@@ -29,6 +29,8 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "fsa_oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
+_SRC_Q = os.path.join(_HERE, "fsa_oracle_q.c")
+_LIB_Q = os.path.join(_HERE, "liboracle_q.so")
 
 KINDS = {
     "coulomb3d": 1,
@@ -49,15 +51,38 @@ GENERAL_ONLY = ("yukawa2d", "quasi2d_ddi")
 
 BUILD_CMD = ["gcc", "-O2", "-fopenmp", "-shared", "-fPIC", "-std=c11",
              _SRC, "-o", _LIB, "-lm"]
+# quad-precision oracle of the extended-precision mode (libquadmath)
+BUILD_CMD_Q = ["gcc", "-O2", "-fopenmp", "-shared", "-fPIC", "-std=gnu11",
+               _SRC_Q, "-o", _LIB_Q, "-lquadmath", "-lm"]
 
 _lock = threading.Lock()
 _lib = None
+_lib_q = None
 
 
 def build() -> str:
-    """Compile the oracle library in place; returns its path."""
+    """Compile the oracle libraries (FP64 and quad) in place; returns the FP64 one's path."""
     subprocess.run(BUILD_CMD, check=True)
+    subprocess.run(BUILD_CMD_Q, check=True)
     return _LIB
+
+
+def _load_q():
+    global _lib_q
+    with _lock:
+        if _lib_q is not None:
+            return _lib_q
+        if (not os.path.exists(_LIB_Q)
+                or os.path.getmtime(_LIB_Q) < os.path.getmtime(_SRC_Q)):
+            subprocess.run(BUILD_CMD_Q, check=True)
+        lib = ctypes.CDLL(_LIB_Q)
+        P = ctypes.c_void_p
+        lib.orcq_solve.restype = ctypes.c_int
+        lib.orcq_solve.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_int, P, P, P, P]
+        lib.orcq_fft1d.restype = ctypes.c_int
+        lib.orcq_fft1d.argtypes = [ctypes.c_int, P, P, ctypes.c_int]
+        _lib_q = lib
+        return lib
 
 
 def _load():
@@ -368,3 +393,33 @@ def solve(kind, L, N, rho, eps, lam=0.0, general=False, eta=None) -> np.ndarray:
 def grid_axes(L, N):
     """Grid coordinates x_j = -L_j + i h_j, i in [0, N_j) (eq. UniformMesh)."""
     return [(-float(l) + np.arange(int(n)) * (2.0 * float(l) / int(n))) for l, n in zip(L, N)]
+
+
+# --------------------------------------------------------------------------- #
+# Quad precision (Coulomb kernels), double-double pairs in and out            #
+# --------------------------------------------------------------------------- #
+
+def solve_quad(kind, L, N, rho_dd, eps) -> np.ndarray:
+    """Phi in quadruple precision (fsa_oracle_q.c) for the 3D / 2D Coulomb
+    kernels; ``rho_dd`` has shape N + (2,) (hi, lo pairs), so has the result."""
+    L = _f64(L)
+    N = _i64(N)
+    rho = _f64(rho_dd)
+    if rho.shape != tuple(int(n) for n in N) + (2,):
+        raise ValueError("rho_dd must have shape N + (2,)")
+    phi = np.empty_like(rho)
+    rc = _load_q().orcq_solve(_kind(kind), float(eps), L.size, _p(L), _p(N), _p(rho), _p(phi))
+    if rc:
+        raise ValueError(f"orcq_solve rejected the arguments ({rc})")
+    return phi
+
+
+def fft1d_quad(x_dd, sign: int = -1) -> np.ndarray:
+    """The quad oracle's own FFT of one complex vector given as (re_hi, re_lo,
+    im_hi, im_lo) rows."""
+    x = _f64(x_dd)
+    out = np.empty_like(x)
+    rc = _load_q().orcq_fft1d(x.shape[0], _p(x), _p(out), int(sign))
+    if rc:
+        raise RuntimeError(f"orcq_fft1d failed ({rc})")
+    return out

@@ -94,6 +94,33 @@ def eval_gaussians(gaussians: Sequence[Gaussian], L, N, dtype=np.float64) -> np.
     return out.astype(dtype, copy=False)
 
 
+def gaussian_dd(L, N, sigma2: float, center=None) -> np.ndarray:
+    """exp(-|x - c|^2 / sigma^2) on the grid as double-double pairs, shape
+    N + (2,): hi + lo carries the value to ~1e-32.  sigma^2 is taken as the
+    decimal its repr shows (0.8 means 4/5, not the nearest double), and each
+    distinct |x - c|^2 (an exact double for grid offsets that are short
+    binary fractions) is evaluated once with mpmath at 40 digits."""
+    import mpmath as mp
+
+    axes = grid_axes(L, N)
+    c = np.zeros(len(N)) if center is None else np.asarray(center, dtype=np.float64)
+    X = np.meshgrid(*[a - ci for a, ci in zip(axes, c)], indexing="ij")
+    q = sum(x * x for x in X)
+    uq, inv = np.unique(q.ravel(), return_inverse=True)
+    hi = np.empty(uq.size)
+    lo = np.empty(uq.size)
+    with mp.workdps(40):
+        s2 = mp.mpf(repr(float(sigma2)))
+        for i, v in enumerate(uq):
+            e = mp.exp(-mp.mpf(float(v)) / s2)
+            hi[i] = float(e)
+            lo[i] = float(e - mp.mpf(hi[i]))
+    out = np.empty(tuple(int(n) for n in N) + (2,))
+    out[..., 0] = hi[inv].reshape(q.shape)
+    out[..., 1] = lo[inv].reshape(q.shape)
+    return out
+
+
 def draw_gaussians(rng: SplitMix64, d: int, count: int, center_lo, center_hi,
                    width_lo, width_hi, amp_lo=0.5, amp_hi=2.0, isotropic=True) -> List[Gaussian]:
     """``count`` Gaussians; bounds may be scalars or per-axis sequences."""
