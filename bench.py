@@ -338,6 +338,21 @@ def bench_general(F, torch, hip, n=256, n2=2048):
     return out
 
 
+def bench_dd(F, torch, hip, synth, n=128):
+    """The extended-precision (double-double) mode: Table 2's 3D Coulomb
+    problem (L = 8, sigma^2 = 0.8, eps = 1) at n^3 = 128^3 (h = 1/8); tensor
+    build and evaluation times."""
+    L, N = (8.0,) * 3, (n,) * 3
+    plan = F.Plan("coulomb3d", L, N, "dd", eps=1.0)
+    pre = _time_build(plan, torch, hip)
+    rho = torch.from_numpy(synth.gaussian_dd(L, N, 0.8)).cuda()
+    ms = _time_apply(plan, rho, torch, hip, steps=5, warmup=2)
+    plan.close()
+    return {"workload": f"3D Coulomb {n}^3, double-double (Table 2's quad problem)",
+            "precomp_ms": round(pre, 3), "ms_per_step": round(ms, 3),
+            "value": n ** 3 / (ms * 1e-3), "unit": "grid pts/s"}
+
+
 def stream_copy(torch, hip, nbytes=1 << 30, reps=10):
     """Device-to-device copy of nbytes (torch copy_ kernel): the practical
     bandwidth of the box, read + write bytes over time."""
@@ -683,6 +698,10 @@ def main():
     if not args.no_general:
         general = bench_general(F, torch, hip, n=args.n)
         log(f"  general construction: {general}")
+    dd = None
+    if not args.no_general:
+        dd = bench_dd(F, torch, hip, synth)
+        log(f"  double-double 128^3: build {dd['precomp_ms']} ms, {dd['ms_per_step']} ms/eval")
     batch = None
     if not args.no_batch:
         log("batched 2D log workload (256 densities) ...")
@@ -742,6 +761,7 @@ def main():
         "precomp_vs_anisotropy": sweep,
         "ddi": ddi,
         "general": general,
+        "double_double": dd,
         "wall_ms_per_step": r32["wall_ms_per_step"],
         "f32_vs_f64_rel_l2": diff,
         "batch": batch,

@@ -99,9 +99,18 @@ typedef enum {
     FSA_QUASI2D_DDI = 9
 } fsa_kernel_kind;
 
-/* Arithmetic of the per-evaluation FFT convolution.  The tensor is always
- * generated in FP64 and rounded to this precision once. */
-typedef enum { FSA_F32 = 0, FSA_F64 = 1 } fsa_precision;
+/* Arithmetic of the per-evaluation FFT convolution.  For FSA_F32 and
+ * FSA_F64 the tensor is generated in FP64 and rounded to this precision once.
+ *
+ * FSA_DD is the extended-precision mode (the paper's quadruple-precision
+ * runs, Sec. 5.1, Table 2): every real is a double-double pair (hi, lo) of
+ * doubles, interleaved, value hi + lo (106-bit significand, rounding
+ * ~1.2e-32).  rho and phi are arrays of N_0 x ... x N_{d-1} such pairs; the
+ * tensor is generated and the convolution runs in double-double.  Only the
+ * Coulomb kernels (FSA_COULOMB_3D, FSA_COULOMB_2D, closed-form construction)
+ * and grids N_j = 2^a in [8, 1024] are supported (FSA_EUNSUPPORTED
+ * otherwise); plans in this precision are not batched, served or tuned. */
+typedef enum { FSA_F32 = 0, FSA_F64 = 1, FSA_DD = 2 } fsa_precision;
 
 typedef struct {
     int kind;       /* fsa_kernel_kind                                        */

@@ -23,6 +23,7 @@ SOURCES = [
     "fsa_server.cpp",
     "fsa_tensor.hip",
     "fsa_spectral.hip",
+    "fsa_dd.hip",
     "fsa_tune.cpp",
     "fsa_launch_f32_v0.hip",
     "fsa_launch_f32_v1.hip",

@@ -74,8 +74,20 @@ fsa_status fsa_plan_create(const fsa_kernel* k, int d, const double* L, const in
     if (d != kd)
         return fail(FSA_EINVAL, "fsa_plan_create: kernel kind %d needs d = %d, got %d", k->kind,
                     kd, d);
-    if (p != FSA_F32 && p != FSA_F64)
+    if (p != FSA_F32 && p != FSA_F64 && p != FSA_DD)
         return fail(FSA_EINVAL, "fsa_plan_create: unknown precision %d", (int)p);
+    if (p == FSA_DD) {
+        if ((k->kind != FSA_COULOMB_3D && k->kind != FSA_COULOMB_2D) || k->general)
+            return fail(FSA_EUNSUPPORTED,
+                        "fsa_plan_create: double-double precision supports the Coulomb "
+                        "kernels (closed-form construction) only");
+        for (int j = 0; j < d; ++j)
+            if (N[j] < 8 || N[j] > 1024 || (N[j] & (N[j] - 1)) != 0)
+                return fail(FSA_EUNSUPPORTED,
+                            "fsa_plan_create: double-double precision needs N[%d] = 2^a in "
+                            "[8, 1024], got %lld",
+                            j, (long long)N[j]);
+    }
     const bool yukawa = k->kind == FSA_YUKAWA_3D || k->kind == FSA_YUKAWA_2D;
     if (yukawa && !(k->lambda > 0.0 && std::isfinite(k->lambda)))
         return fail(FSA_EINVAL, "fsa_plan_create: Yukawa needs lambda > 0");
@@ -140,7 +152,7 @@ fsa_status fsa_plan_create(const fsa_kernel* k, int d, const double* L, const in
         pl->N[j] = N[j];
         pl->h[j] = 2.0 * L[j] / (double)N[j];
     }
-    const size_t rsize = p == FSA_F32 ? 4 : 8;
+    const size_t rsize = p == FSA_F32 ? 4 : (p == FSA_F64 ? 8 : 16);
     pl->csize = 2 * rsize;
     const int64_t Nl = N[d - 1];
     pl->H = Nl + 1;
@@ -153,9 +165,19 @@ fsa_status fsa_plan_create(const fsa_kernel* k, int d, const double* L, const in
         // the derivative fits the first array, H > N_1)
         pl->ws2_elems = pl->n_spectral ? (size_t)N[0] * N[1] / 2 : 0;
     }
+    if (p == FSA_DD) {  // the whole padded complex spectrum
+        pl->ws1_elems = 1;
+        for (int j = 0; j < d; ++j) pl->ws1_elems *= (size_t)(2 * N[j]);
+        pl->ws2_elems = 0;
+    }
     pl->ws_bytes = align256(pl->ws1_elems * pl->csize) + align256(pl->ws2_elems * pl->csize);
     pl->tensor_elems = 1;
     for (int j = 0; j < d; ++j) pl->tensor_elems *= (size_t)(N[j] + 1);
+    if (p == FSA_DD) {  // complex DD twiddles of every axis
+        pl->tw_elems = fsa::dd_twiddle_elems(pl);
+        *out = pl;
+        return FSA_OK;
+    }
     // twiddle tables: P0 = 2 N0; P1 = 2 N1 (3D); M = N_last; P_last = 2 N_last
     size_t off = 0;
     pl->tw_off_p0 = off;
@@ -213,6 +235,16 @@ fsa_status fsa_build_tensor(fsa_plan pl, void* stream) {
             return fail(FSA_ENOMEM, "fsa_build_tensor: twiddle allocation: %s",
                         hipGetErrorString(e));
         }
+    }
+    if (pl->prec == FSA_DD) {
+        e = fsa::build_tensor_dd(pl, st);
+        if (e == hipErrorOutOfMemory)
+            return fail(FSA_ENOMEM, "fsa_build_tensor: temporary DD octant: %s",
+                        hipGetErrorString(e));
+        if (e != hipSuccess) return hip_fail(e, "fsa_build_tensor: double-double kernels");
+        pl->device = dev;
+        pl->built = true;
+        return FSA_OK;
     }
     char* tw = (char*)pl->twiddles;
     const int64_t Nl = pl->N[pl->d - 1];
@@ -311,6 +343,7 @@ static hipError_t launch_pass_t(const fsa_plan_s* pl, int k, int lo, int n, cons
 
 hipError_t launch_step(const fsa_plan_s* pl, const Step& s, const void* rho, void* phi, void* ws,
                        Choice c, hipStream_t st) {
+    if (pl->prec == FSA_DD) return launch_dd_step(pl, s.k, rho, phi, ws, st);
     if (s.k >= kSpectralStep) {  // derivative of a dipole-dipole plan
         char* w1 = (char*)ws;
         char* w2 = w1 + ((pl->ws1_elems * pl->csize + 255) & ~size_t(255));
@@ -324,6 +357,10 @@ hipError_t launch_step(const fsa_plan_s* pl, const Step& s, const void* rho, voi
 int schedule(const fsa_plan_s* pl, int slabs, Step* out) {
     int m = 0;
     const int H = (int)pl->H;
+    if (pl->prec == FSA_DD) {  // one launch per pass, no slabs
+        for (int k = 0; k < n_passes(pl); ++k) out[m++] = Step{k, 0, 0};
+        return m;
+    }
     for (int i = 0; i < pl->n_spectral; ++i) out[m++] = Step{kSpectralStep + i, 0, 0};
     if (pl->d != 3) {
         for (int k = 0; k < 3; ++k) out[m++] = Step{k, 0, H};
@@ -356,7 +393,7 @@ long step_lines(const fsa_plan_s* pl, const Step& s) {
 }
 
 Choice step_choice(const fsa_plan_s* pl, const Step& s) {
-    if (s.k >= kSpectralStep) return Choice{};
+    if (s.k >= kSpectralStep || pl->prec == FSA_DD) return Choice{};
     Pass pass;
     int len;
     pass_of(pl, s.k, &pass, &len);

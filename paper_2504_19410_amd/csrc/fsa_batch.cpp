@@ -308,6 +308,11 @@ fsa_status fsa_apply_batched(int n, const fsa_plan* plans, const void* const* rh
             fsa::set_last_error("fsa_apply_batched: a plan is not built on the current device");
             return FSA_ESTATE;
         }
+        if (plans[i]->prec == FSA_DD) {
+            fsa::set_last_error("fsa_apply_batched: double-double plans are not batched "
+                                "(use fsa_apply)");
+            return FSA_EUNSUPPORTED;
+        }
         if (plans[i]->n_spectral) {
             fsa::set_last_error(
                 "fsa_apply_batched: dipole-dipole plans are not batched (use fsa_apply)");

@@ -47,6 +47,13 @@ void batch_forget_plan(uint64_t plan_id);
 hipError_t spectral_step(const fsa_plan_s* pl, int s, const void* rho, void* z, void* dst,
                          hipStream_t st);
 
+// Double-double mode (fsa_dd.hip): twiddle elements (complex DD) of a plan,
+// its tensor build, and step k of its 2d - 1 evaluation launches.
+size_t dd_twiddle_elems(const fsa_plan_s* pl);
+hipError_t build_tensor_dd(const fsa_plan_s* pl, hipStream_t st);
+hipError_t launch_dd_step(const fsa_plan_s* pl, int k, const void* rho, void* phi, void* ws,
+                          hipStream_t st);
+
 // Tensor generation (fsa_tensor.hip).
 hipError_t build_tensor_device(const KernelParams& kp, int d, const double* L, const int64_t* N,
                                const double* h, fsa_precision prec, void* tensor_out,

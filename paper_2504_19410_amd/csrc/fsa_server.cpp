@@ -296,6 +296,11 @@ fsa_status fsa_server_submit(fsa_server s, const fsa_kernel* k, int d, const dou
         fsa::set_last_error("fsa_server_submit: bad arguments");
         return FSA_EINVAL;
     }
+    if (p == FSA_DD) {
+        fsa::set_last_error("fsa_server_submit: double-double requests are not served "
+                            "(use a plan and fsa_apply)");
+        return FSA_EUNSUPPORTED;
+    }
     if (k->kind == FSA_DDI_3D || k->kind == FSA_QUASI2D_DDI) {
         fsa::set_last_error("fsa_server_submit: dipole-dipole requests are not served "
                             "(use a plan and fsa_apply)");

@@ -479,6 +479,8 @@ fsa_status fsa_autotune(fsa_plan pl, const void* rho, void* phi, void* workspace
     if (!pl || !rho || !phi || !workspace)
         return fail(FSA_EINVAL, "fsa_autotune: null argument");
     if (!pl->built) return fail(FSA_ESTATE, "fsa_autotune: tensor not built");
+    if (pl->prec == FSA_DD)
+        return fail(FSA_EUNSUPPORTED, "fsa_autotune: double-double plans have no launch choices");
     if (((uintptr_t)workspace & 255) != 0)
         return fail(FSA_EINVAL, "fsa_autotune: workspace must be 256-byte aligned");
     if (reps < 1 || reps > 1000) return fail(FSA_EINVAL, "fsa_autotune: reps must be 1..1000");

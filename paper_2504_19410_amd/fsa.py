@@ -32,8 +32,10 @@ KINDS = {
 KIND_DIM = {"coulomb3d": 3, "yukawa3d": 3, "biharmonic3d": 3,
             "log2d": 2, "coulomb2d": 2, "biharmonic2d": 2, "ddi3d": 3,
             "yukawa2d": 2, "quasi2d_ddi": 2}
-PRECISIONS = {"f32": 0, "f64": 1}
-DTYPES = {"f32": torch.float32, "f64": torch.float64}
+# "dd": double-double, each real an interleaved (hi, lo) pair of float64, so
+# rho / phi tensors have shape N + (2,)
+PRECISIONS = {"f32": 0, "f64": 1, "dd": 2}
+DTYPES = {"f32": torch.float32, "f64": torch.float64, "dd": torch.float64}
 
 STATUS = {
     0: "FSA_OK", 1: "FSA_EINVAL", 2: "FSA_EUNSUPPORTED", 3: "FSA_ENOMEM",
@@ -222,11 +224,16 @@ class Plan:
         p = ws.data_ptr()
         return (p + 255) & ~255
 
+    @property
+    def shape(self):
+        """Shape of rho and phi: N, or N + (2,) for double-double pairs."""
+        return self.N + ((2,) if self.precision == "dd" else ())
+
     def check_input(self, rho: torch.Tensor):
         if not rho.is_cuda:
             raise ValueError("rho must be a device tensor")
-        if tuple(rho.shape) != self.N:
-            raise ValueError(f"rho shape {tuple(rho.shape)} != plan grid {self.N}")
+        if tuple(rho.shape) != self.shape:
+            raise ValueError(f"rho shape {tuple(rho.shape)} != plan grid {self.shape}")
         if rho.dtype != self.dtype:
             raise ValueError(f"rho dtype {rho.dtype} != plan precision {self.dtype}")
         if not rho.is_contiguous():
@@ -290,7 +297,7 @@ class Plan:
         """Times every launch variant of every pass (``fsa_autotune``) and
         returns the chosen {(pass, length): (variant, occupancy, us)}."""
         if rho is None:
-            rho = torch.rand(self.N, dtype=self.dtype, device="cuda")
+            rho = torch.rand(self.shape, dtype=self.dtype, device="cuda")
         self.check_input(rho)
         out = torch.empty_like(rho)
         ws = self.workspace()
@@ -322,7 +329,7 @@ class Plan:
         ptr = ctypes.c_void_p()
         dims = (ctypes.c_int64 * self.d)()
         _check(_lib.fsa_plan_tensor(self._h, ctypes.byref(ptr), dims))
-        shape = tuple(dims)
+        shape = tuple(dims) + ((2,) if self.precision == "dd" else ())
         n = 1
         for s in shape:
             n *= s

@@ -118,6 +118,24 @@ def test_general_construction_validation(F):
     assert q.tensor_bytes == y.tensor_bytes
 
 
+def test_double_double_plans(F):
+    """Extended precision (host-side plan creation only): sizes and limits."""
+    p = F.Plan("coulomb3d", (8, 8, 8), (64, 32, 16), "dd")
+    assert p.shape == (64, 32, 16, 2)
+    assert p.tensor_bytes == 65 * 33 * 17 * 16
+    assert p.workspace_bytes == 128 * 64 * 32 * 32
+    assert p.launches() == ["r2c", "fwd_t", "conv", "inv_t", "c2r"]
+    q = F.Plan("coulomb2d", (8, 6), (128, 8), "dd")
+    assert q.launches() == ["r2c", "conv", "c2r"]
+    for args, kw in [(("yukawa3d", (8,) * 3, (32,) * 3), {"lam": 1.0}),
+                     (("log2d", (8, 8), (32, 32)), {}),
+                     (("coulomb3d", (8,) * 3, (32,) * 3), {"general": True}),
+                     (("coulomb3d", (8,) * 3, (48, 32, 32)), {}),      # 3 * 2^4
+                     (("coulomb2d", (8, 8), (2048, 32)), {})]:           # beyond 1024
+        with pytest.raises(F.FsaError, match="EUNSUPPORTED"):
+            F.Plan(*args, "dd", **kw)
+
+
 def test_apply_before_build_is_a_state_error(F):
     p = F.Plan("coulomb3d", (8, 8, 8), (16, 16, 16))
     st = F.lib().fsa_apply(p.handle, ctypes.c_void_p(256), ctypes.c_void_p(256),
