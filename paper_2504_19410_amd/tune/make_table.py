@@ -6,6 +6,8 @@ reported by the device, e.g. gfx950).  Load it with fsa.tune_load(path) or by
 pointing FSA_TUNE_CACHE at it.
 
 Usage (on the GPU): python -m paper_2504_19410_amd.tune.make_table [--reps 7]
+With --add, the shipped table is loaded first and only the extra 2D shapes
+(FP64 log-kernel batch shapes, 2048^2 and 1024^2 grids) are tuned into it.
 """
 import argparse
 import os
@@ -28,6 +30,13 @@ SHAPES_3D = [
 ]
 
 
+# large single 2D grids (2D Yukawa, quasi-2D dipole-dipole, log kernel)
+SHAPES_2D_EXTRA = [
+    ("yukawa2d", (12.0, 12.0), (2048, 2048), 2.0),
+    ("yukawa2d", (12.0, 12.0), (1024, 1024), 2.0),
+]
+
+
 def arch_name():
     name = torch.cuda.get_device_properties(0).gcnArchName
     return name.split(":")[0]
@@ -37,10 +46,19 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--reps", type=int, default=7)
     ap.add_argument("--out", default=None)
+    ap.add_argument("--add", action="store_true",
+                    help="tune only the extra 2D shapes into the shipped table")
     args = ap.parse_args()
-    F.tune_reset()
-    jobs = [(k, L, N, lam, prec) for k, L, N, lam in SHAPES_3D for prec in ("f32", "f64")]
-    jobs += [("log2d", (8.0, 8.0), N, None, "f32") for N in synth.LOG2D_SHAPES]
+    extra = [(k, L, N, lam, prec) for k, L, N, lam in SHAPES_2D_EXTRA for prec in ("f32", "f64")]
+    extra += [("log2d", (8.0, 8.0), N, None, "f64") for N in synth.LOG2D_SHAPES]
+    if args.add:
+        F.tune_load(os.path.join(HERE, f"{arch_name()}.json"))
+        jobs = extra
+    else:
+        F.tune_reset()
+        jobs = [(k, L, N, lam, prec) for k, L, N, lam in SHAPES_3D for prec in ("f32", "f64")]
+        jobs += [("log2d", (8.0, 8.0), N, None, "f32") for N in synth.LOG2D_SHAPES]
+        jobs += extra
     for kind, L, N, lam, prec in jobs:
         plan = F.Plan(kind, L, N, prec, lam=lam).build()
         rho = torch.rand(N, dtype=F.DTYPES[prec], device="cuda")
