@@ -232,19 +232,28 @@ __global__ __launch_bounds__(kDDThreads) void k_dd_pass(const void* __restrict__
         // x (natural order) times T^, back into bit-reversed order for the
         // inverse: every product is formed before any is written back (at
         // most P / blockDim <= 8 per thread)
-        cdd keep[kDDMaxP / kDDThreads];
-        int c = 0;
-        for (int t = threadIdx.x; t < P; t += blockDim.x) {
-            const int a0 = t <= cv.N[0] ? t : P - t;
-            const dd s = trow[a0];
-            cdd v = x[t];
-            v.re = v.re * s;
-            v.im = v.im * s;
-            keep[c++] = v;
+        // (fixed trip counts keep the array in registers)
+        constexpr int kKeep = kDDMaxP / kDDThreads;  // P / blockDim (blockDim = min(P/2, 256))
+        static_assert(kDDMaxP / kDDThreads <= kKeep, "keep array too small");
+        cdd keep[kKeep];
+#pragma unroll
+        for (int r = 0; r < kKeep; ++r) {
+            const int t = threadIdx.x + r * blockDim.x;
+            if (t < P) {
+                const int a0 = t <= cv.N[0] ? t : P - t;
+                const dd s = trow[a0];
+                cdd v = x[t];
+                v.re = v.re * s;
+                v.im = v.im * s;
+                keep[r] = v;
+            }
         }
         __syncthreads();
-        c = 0;
-        for (int t = threadIdx.x; t < P; t += blockDim.x) x[bitrev(t, logP)] = keep[c++];
+#pragma unroll
+        for (int r = 0; r < kKeep; ++r) {
+            const int t = threadIdx.x + r * blockDim.x;
+            if (t < P) x[bitrev(t, logP)] = keep[r];
+        }
         __syncthreads();
     }
     if constexpr (MODE == DD_FWD || MODE == DD_FWD_REAL) dd_fft_lds<false>(x, P, logP, tw);

@@ -153,13 +153,15 @@ __global__ __launch_bounds__((Spec<R, P>::THREADS)) void k_spec(const void* in,
         const int q1 = i1 < mul.N[1] / 2 ? i1 : i1 - mul.N[1];
         const int q2 = i2 < mul.N[2] / 2 ? i2 : i2 - mul.N[2];
         const double k1 = mul.c[1] * q1, k2 = mul.c[2] * q2;
+        // k^T A k = a k0^2 + b k0 + c along the line
+        const double qa = mul.scale * mul.A[0][0];
+        const double qb = mul.scale * 2.0 * (mul.A[0][1] * k1 + mul.A[0][2] * k2);
+        const double qc = mul.scale * (mul.A[1][1] * k1 * k1 + 2.0 * mul.A[1][2] * k1 * k2 +
+                                       mul.A[2][2] * k2 * k2);
         Ff::for_each_last(x, tid, [&](int i0, C& c) {
             const int q0 = i0 < mul.N[0] / 2 ? i0 : i0 - mul.N[0];
-            const double k[3] = {mul.c[0] * q0, k1, k2};
-            double q = 0.0;
-            for (int a = 0; a < 3; ++a)
-                for (int b = 0; b < 3; ++b) q += mul.A[a][b] * k[a] * k[b];
-            c = scale(c, (R)(mul.scale * q));
+            const double k0 = mul.c[0] * q0;
+            c = scale(c, (R)((qa * k0 + qb) * k0 + qc));
         });
         Fi::run_g(x, sc, tid, tw);
         __syncthreads();
