@@ -6,9 +6,10 @@
 // d_nm rho is the spectral derivative of rho on its own N-point grid,
 // periodic on the box: a 3D DFT, the product with -(k.n)(k.m),
 // k_j = pi q_j / L_j (q_j = i_j for i_j < N_j/2, else i_j - N_j), an inverse
-// DFT and the real part.  Five launches on a complex N0 x N1 x N2 array Z in
-// the first workspace array, leaving -3 d_nm rho (real, plan precision) in
-// the second one, where pass A of the Coulomb convolution reads it:
+// DFT and the real part.  Five launches on a complex N0 x N1 x (N2/2 + 1)
+// array Z (the half spectrum, below) in the first workspace array, leaving
+// -3 d_nm rho (real, plan precision) in the second one, where pass A of the
+// Coulomb convolution reads it:
 //   0  rows of rho (last axis, real) -> forward FFT -> Z
 //   1  Z along axis 1, forward
 //   2  Z along axis 0: forward, x 3 (k.n)(k.m) / (N0 N1 N2), inverse
@@ -19,7 +20,16 @@
 // (Sec. 5.3) convolves S = -(3/2)(d_{n_perp n_perp} - n_3^2 Lap) rho, whose
 // transform is (3/2)((k.n_perp)^2 - n_3^2 |k|^2) rho^, in three launches:
 // rows forward, axis 0 forward x factor x inverse, rows inverse.  Both
-// factors are a scale times a quadratic form k^T A k.  Each team of a
+// factors are a scale times a quadratic form f(k) = k^T A k.
+//
+// rho is real, so Z keeps only the bins 0 <= i_last <= N_last/2 of the row
+// transforms (a half spectrum: the other half is the conjugate), and the row
+// inverse rebuilds each row from it.  Taking the real part of the full
+// inverse DFT of f Z equals the inverse of g Z with g(k) = (f(k) + f(k~))/2,
+// k~ the frequency of the bin that pairs with k under conjugation (-q_j,
+// except that the Nyquist index N_j/2 pairs with itself); g is even under
+// that pairing, so the half spectrum times g is consistent, and the axis-0
+// launch multiplies by g.  Each team of a
 // workgroup transforms one line with the team FFT.  Launches along the
 // strided axes stage a tile of WT lines adjacent in memory through LDS, so
 // they read and write rows of WT consecutive elements; the row launches read
@@ -59,10 +69,13 @@ struct Spec {
 };
 
 // Lines of one launch: line (u, v) starts at u * u_stride + v * v_stride
-// (elements), its element t at + t * es; groups take WT consecutive u.
+// (elements), its element t at + t * es; groups take WT consecutive u.  The
+// row launches write (or read, for the inverse) rows of another length:
+// their other array's row (u, v) starts at u * ou_stride + v * ov_stride.
 struct SLines {
     int n_u, n_v;
     long u_stride, v_stride, es;
+    long ou_stride, ov_stride;
 };
 
 // The derivative factor scale * k^T A k of the axis-0 launch, k = (k0, k1,
@@ -93,9 +106,13 @@ __global__ __launch_bounds__((Spec<R, P>::THREADS)) void k_spec(const void* in,
     const int nw = ln.n_u - tu * K::WT < K::WT ? ln.n_u - tu * K::WT : K::WT;
     if constexpr (KIND == ROW_FWD_REAL || KIND == ROW_INV_REAL) {
         // rows are contiguous: each team reads and writes its own row straight
-        // from and to global memory (the team's accesses are consecutive)
+        // from and to global memory (the team's accesses are consecutive);
+        // Z rows hold the half spectrum, H = P/2 + 1 bins
+        constexpr int H = P / 2 + 1;
         const bool act = team < nw;
+        const long u = (long)tu * K::WT + team;
         const long rb = base + team * ln.u_stride;
+        const long ro = u * ln.ou_stride + (long)v * ln.ov_stride;
         C* sc = lds + team * Ff::SCR;
         C x[Ff::V];
         if constexpr (KIND == ROW_FWD_REAL) {
@@ -103,12 +120,18 @@ __global__ __launch_bounds__((Spec<R, P>::THREADS)) void k_spec(const void* in,
                 return act ? mk(((const R*)in)[rb + t], R(0)) : mk(R(0), R(0));
             });
             Ff::run_g(x, sc, tid, tw);
-            if (act) Ff::store_last(x, tid, P, [&](int t, C c) { ((C*)out)[rb + t] = c; });
+            if (act)
+                Ff::store_last(x, tid, P, [&](int t, C c) {
+                    if (t < H) ((C*)out)[ro + t] = c;
+                });
         } else {
-            Fi::load_first(x, tid, P,
-                           [&](int t) { return act ? ((const C*)in)[rb + t] : mk(R(0), R(0)); });
+            // Z[P - t] = conj Z[t] rebuilds the bins above P/2
+            Fi::load_first(x, tid, P, [&](int t) {
+                if (!act) return mk(R(0), R(0));
+                return t < H ? ((const C*)in)[rb + t] : conj(((const C*)in)[rb + P - t]);
+            });
             Fi::run_g(x, sc, tid, tw);
-            if (act) Fi::store_last(x, tid, P, [&](int t, C c) { ((R*)out)[rb + t] = c.x; });
+            if (act) Fi::store_last(x, tid, P, [&](int t, C c) { ((R*)out)[ro + t] = c.x; });
         }
         return;
     }
@@ -148,20 +171,23 @@ __global__ __launch_bounds__((Spec<R, P>::THREADS)) void k_spec(const void* in,
         Ff::store_last(x, tid, P, [&](int t, C c) { tile[t * K::TS + team] = c; });
     } else if constexpr (KIND == COL_MUL) {
         Ff::run_g(x, sc, tid, tw);
-        // line (u = i2, v = i1) along axis 0; the register holds output i0
+        // line (u = i2, v = i1) along axis 0; the register holds output i0.
+        // g = (f(k) + f(k~)) / 2 with f = a k0^2 + b k0 + c along the line
         const int i2 = tu * K::WT + team, i1 = v;
-        const int q1 = i1 < mul.N[1] / 2 ? i1 : i1 - mul.N[1];
-        const int q2 = i2 < mul.N[2] / 2 ? i2 : i2 - mul.N[2];
-        const double k1 = mul.c[1] * q1, k2 = mul.c[2] * q2;
-        // k^T A k = a k0^2 + b k0 + c along the line
-        const double qa = mul.scale * mul.A[0][0];
-        const double qb = mul.scale * 2.0 * (mul.A[0][1] * k1 + mul.A[0][2] * k2);
-        const double qc = mul.scale * (mul.A[1][1] * k1 * k1 + 2.0 * mul.A[1][2] * k1 * k2 +
-                                       mul.A[2][2] * k2 * k2);
+        auto qv = [](int i, int n) { return i < n / 2 ? i : i - n; };
+        auto qp = [&](int i, int n) { return qv(i == 0 ? 0 : n - i, n); };  // the paired bin
+        const double k1 = mul.c[1] * qv(i1, mul.N[1]), k2 = mul.c[2] * qv(i2, mul.N[2]);
+        const double p1 = mul.c[1] * qp(i1, mul.N[1]), p2 = mul.c[2] * qp(i2, mul.N[2]);
+        const double ha = 0.5 * mul.scale * mul.A[0][0];
+        const double hb = mul.scale * (mul.A[0][1] * k1 + mul.A[0][2] * k2);
+        const double hbp = mul.scale * (mul.A[0][1] * p1 + mul.A[0][2] * p2);
+        const double hc = 0.5 * mul.scale *
+                          (mul.A[1][1] * (k1 * k1 + p1 * p1) +
+                           2.0 * mul.A[1][2] * (k1 * k2 + p1 * p2) +
+                           mul.A[2][2] * (k2 * k2 + p2 * p2));
         Ff::for_each_last(x, tid, [&](int i0, C& c) {
-            const int q0 = i0 < mul.N[0] / 2 ? i0 : i0 - mul.N[0];
-            const double k0 = mul.c[0] * q0;
-            c = scale(c, (R)((qa * k0 + qb) * k0 + qc));
+            const double k0 = mul.c[0] * qv(i0, mul.N[0]), p0 = mul.c[0] * qp(i0, mul.N[0]);
+            c = scale(c, (R)(ha * (k0 * k0 + p0 * p0) + hb * k0 + hbp * p0 + hc));
         });
         Fi::run_g(x, sc, tid, tw);
         __syncthreads();
@@ -226,12 +252,14 @@ hipError_t step_2d(const fsa_plan_s* pl, int s, const void* rho, void* z, void* 
     mul.A[2][2] = n1 * n1 - n3sq;
     mul.A[0][2] = mul.A[2][0] = n0 * n1;
     mul.scale = 1.5 / ((double)N0 * (double)N1);
-    const SLines rows{(int)N0, 1, N1, 0, 1};
-    const SLines ax0{(int)N1, 1, 1, 0, N1};
+    const long H1 = N1 / 2 + 1;  // half spectrum of the rows
+    const SLines fwd{(int)N0, 1, N1, 0, 1, H1, 0};  // rho rows -> Z rows
+    const SLines inv{(int)N0, 1, H1, 0, 1, N1, 0};  // Z rows -> source rows
+    const SLines ax0{(int)H1, 1, 1, 0, H1, 0, 0};
     switch (s) {
-    case 0: return go<R, ROW_FWD_REAL>((int)N1, rho, z, rows, tw1, mul, st);
+    case 0: return go<R, ROW_FWD_REAL>((int)N1, rho, z, fwd, tw1, mul, st);
     case 1: return go<R, COL_MUL>((int)N0, z, z, ax0, tw0, mul, st);
-    case 2: return go<R, ROW_INV_REAL>((int)N1, z, dst, rows, tw1, mul, st);
+    case 2: return go<R, ROW_INV_REAL>((int)N1, z, dst, inv, tw1, mul, st);
     }
     return hipErrorInvalidValue;
 }
@@ -257,18 +285,21 @@ hipError_t step_t(const fsa_plan_s* pl, int s, const void* rho, void* z, void* d
         for (int b = 0; b < 3; ++b)
             mul.A[a][b] = 0.5 * (pl->dn[a] * pl->dm[b] + pl->dm[a] * pl->dn[b]);
     mul.scale = 3.0 / prodN;
+    // Z is N0 x N1 x H2, the half spectrum of the rows
+    const long H2 = N2 / 2 + 1;
     // rows: lines along axis 2, groups of consecutive rows
-    const SLines rows{(int)N1, (int)N0, N2, N1 * N2, 1};
+    const SLines fwd{(int)N1, (int)N0, N2, N1 * N2, 1, H2, N1 * H2};  // rho -> Z
+    const SLines inv{(int)N1, (int)N0, H2, N1 * H2, 1, N2, N1 * N2};  // Z -> source
     // axis 1: lines at fixed (i0, i2), groups of consecutive i2
-    const SLines ax1{(int)N2, (int)N0, 1, N1 * N2, N2};
+    const SLines ax1{(int)H2, (int)N0, 1, N1 * H2, H2, 0, 0};
     // axis 0: lines at fixed (i1, i2), groups of consecutive i2
-    const SLines ax0{(int)N2, (int)N1, 1, N2, N1 * N2};
+    const SLines ax0{(int)H2, (int)N1, 1, H2, N1 * H2, 0, 0};
     switch (s) {
-    case 0: return go<R, ROW_FWD_REAL>((int)N2, rho, z, rows, tw2, mul, st);
+    case 0: return go<R, ROW_FWD_REAL>((int)N2, rho, z, fwd, tw2, mul, st);
     case 1: return go<R, COL_FWD>((int)N1, z, z, ax1, tw1, mul, st);
     case 2: return go<R, COL_MUL>((int)N0, z, z, ax0, tw0, mul, st);
     case 3: return go<R, COL_INV>((int)N1, z, z, ax1, tw1, mul, st);
-    case 4: return go<R, ROW_INV_REAL>((int)N2, z, dst, rows, tw2, mul, st);
+    case 4: return go<R, ROW_INV_REAL>((int)N2, z, dst, inv, tw2, mul, st);
     }
     return hipErrorInvalidValue;
 }
