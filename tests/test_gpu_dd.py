@@ -62,6 +62,21 @@ def test_parity_dd(F, kind, L, N):
                                else ["r2c", "conv", "c2r"])
 
 
+@pytest.mark.parametrize("kind,L,N", [
+    ("coulomb2d", (9.0, 2.0), (1024, 16)),        # the longest lines: P = 2048 along axis 0
+    ("coulomb2d", (2.0, 9.0), (16, 1024)),        # ... and along the contiguous axis
+    ("coulomb3d", (2.0, 2.0, 9.0), (8, 8, 1024)),
+    ("coulomb2d", (8.0, 8.0), (512, 512)),
+])
+def test_parity_dd_largest_lengths(F, kind, L, N):
+    rho = rand_dd(N, sum(N) + 1)
+    plan, phi = run_dd(F, kind, L, N, rho)
+    ref = O.solve_quad(kind, L, N, rho, plan.eps)
+    err = R.dd_rel_l2_err(phi, ref)
+    print(f"dd {kind} {N}: rel L2 {err:.3e}")
+    assert err <= TOL_DD
+
+
 def test_dd_tensor_matches_quad(F):
     """The double-double octant against the quad oracle's tensor, built the
     paper's way (T(1) + IDFT(W), then its DFT), through a delta density: the
