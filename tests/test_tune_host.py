@@ -120,3 +120,43 @@ def test_entries_are_kept_per_size_class():
     assert F.tune_get("f32", "conv", 512, 300)[:2] == (1, 0)      # nearest: 2^8
     assert F.tune_get("f32", "conv", 512, 13000)[:2] == (2, 0)    # nearest: 2^17 vs 2^8
     assert F.tune_get("f32", "conv", 1024, 257)[:2] == (0, 0)     # other length: default
+
+
+def test_load_survives_mangled_files(tmp_path):
+    """Random damage to a valid table file (deleted, duplicated, swapped or
+    replaced bytes) either loads or is rejected with FSA_EINVAL; the parser
+    never crashes or hangs, and a rejected file leaves the table untouched."""
+    import random
+    F.tune_reset()
+    F.tune_set("f32", "conv", 512, 1, 0)
+    F.tune_set("f32", "fwd_t", 512, 2, 1)
+    F.tune_set_slabs("f64", (256, 256, 256), 2)
+    good = tmp_path / "good.json"
+    F.tune_save(str(good))
+    text = good.read_text()
+    rng = random.Random(7)
+    alphabet = '{}[]":,.-+eE0123456789 \n\tabcfnrstu\\'
+    for trial in range(300):
+        s = list(text)
+        for _ in range(rng.randint(1, 6)):
+            i = rng.randrange(len(s)) if s else 0
+            op = rng.randrange(4)
+            if op == 0 and s:
+                del s[i]
+            elif op == 1:
+                s.insert(i, rng.choice(alphabet))
+            elif op == 2 and s:
+                s[i] = rng.choice(alphabet)
+            elif s:
+                j = rng.randrange(len(s))
+                s[i], s[j] = s[j], s[i]
+        path = tmp_path / f"m{trial}.json"
+        path.write_text("".join(s))
+        F.tune_reset()
+        F.tune_set("f32", "conv", 512, 1, 0)
+        try:
+            F.tune_load(str(path))
+        except F.FsaError as e:
+            assert "EINVAL" in str(e)
+            assert F.tune_get("f32", "conv", 512)[:2] == (1, 0)
+    F.tune_reset()
