@@ -5,7 +5,8 @@
 // 1e-34 once the tensor is generated in high precision (Sec. 5.1, Table 2).
 // gfx950 has no FP128; double-double (hi + lo, 106 bits, fsa_dd.hpp) is the
 // closest native format.  The method is the same as in FP32/FP64:
-//   tensor  T^[p] = (DCT-I(T(1))[p] + W(|k_p|)) / prod P_j  on the octant,
+//   tensor  T^[p] = (DCT-I(T(1))[p] + W(|k_p|)) / prod P_j  on the octant
+//           (the DCT-I as the real part of the DFT of the even extension),
 //           T(1) = prod h_j U^eps(|n h|), U^eps = erf(r/eps)/(4 pi r) (3D) or
 //           erf(r/eps)/(2 pi r) (2D), W = (1 - e^{-k^2 eps^2/4})/k^2 (3D) or
 //           erf(k eps/2)/k (2D);
@@ -48,15 +49,6 @@ __global__ void k_dd_twiddle(cdd* __restrict__ tw, int P) {
     dd s, c;
     dd_sincos_turn((double)m / (double)P, &s, &c);
     tw[m] = cdd{c, -s};
-}
-
-// c[m] = cos(pi m / N), m < 2N
-__global__ void k_dd_cos(dd* __restrict__ c, int N) {
-    const int m = blockIdx.x * blockDim.x + threadIdx.x;
-    if (m >= 2 * N) return;
-    dd s, co;
-    dd_sincos_turn((double)m / (2.0 * N), &s, &co);
-    c[m] = co;
 }
 
 struct DDGeom {
@@ -102,27 +94,6 @@ __global__ void k_dd_sample(dd* __restrict__ out, DDGeom g) {
         u = g.kind == FSA_COULOMB_3D ? e / (dd_pi() * r * 4.0) : e / (dd_pi() * r * 2.0);
     }
     out[i] = hprod * u;
-}
-
-// DCT-I along axis ax of the octant by its definition,
-// out[p] = sum_{n=0}^{N} c_n in[n] cos(pi p n / N), c_0 = c_N = 1, else 2.
-__global__ void k_dd_dct(const dd* __restrict__ in, dd* __restrict__ out, DDGeom g, int ax,
-                         const dd* __restrict__ cosv) {
-    int D[3] = {g.N[0] + 1, g.d > 1 ? g.N[1] + 1 : 1, g.d > 2 ? g.N[2] + 1 : 1};
-    const long n = (long)D[0] * D[1] * D[2];
-    const long i = blockIdx.x * (long)blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    int a[3];
-    octant_index(i, D, g.d, a);
-    const long stride = ax == 0 ? 1 : (ax == 1 ? D[0] : (long)D[0] * D[1]);
-    const long base = i - (long)a[ax] * stride;
-    const int N = g.N[ax], p = a[ax];
-    dd s = dd_of(0.0);
-    for (int m = 0; m <= N; ++m) {
-        const dd v = in[base + m * stride] * cosv[(int)(((long)p * m) % (2 * N))];
-        s = s + ((m == 0 || m == N) ? v : v * 2.0);
-    }
-    out[i] = s;
 }
 
 // T^ = (DCT(T1) + W(|k|)) / prod P_j
@@ -180,6 +151,39 @@ __device__ void dd_fft_lds(cdd* x, int P, int logP, const cdd* __restrict__ tw) 
 
 __device__ __forceinline__ int bitrev(int t, int logP) {
     return (int)(__brev((unsigned)t) >> (32 - logP));
+}
+
+// DCT-I along axis ax of the octant (D_j = N_j + 1 points per axis), as the
+// real part of the length-2N DFT of each line's even extension (x[m] for
+// m <= N, x[2N - m] above): sum_m c_m x[m] cos(pi p m / N), c_0 = c_N = 1,
+// else 2.  One line per workgroup; tw: the axis' twiddles of length 2N.
+__global__ __launch_bounds__(kDDThreads) void k_dd_dct(const dd* __restrict__ in,
+                                                     dd* __restrict__ out, DDGeom g, int ax,
+                                                     const cdd* __restrict__ tw) {
+    extern __shared__ cdd x[];
+    const int D0 = g.N[0] + 1, D1 = g.d > 1 ? g.N[1] + 1 : 1;
+    const int N = g.N[ax], P = 2 * N;
+    int logP = 0;
+    while ((1 << logP) < P) ++logP;
+    const long l = blockIdx.x;
+    long base, stride;
+    if (ax == 0) {
+        base = l * D0;  // l = a2 D1 + a1
+        stride = 1;
+    } else if (ax == 1) {
+        base = (l / D0) * (long)D1 * D0 + l % D0;  // l = a2 D0 + a0
+        stride = D0;
+    } else {
+        base = l;  // l = a1 D0 + a0
+        stride = (long)D0 * D1;
+    }
+    for (int t = threadIdx.x; t < P; t += blockDim.x) {
+        const int m = t <= N ? t : P - t;
+        x[bitrev(t, logP)] = cdd{in[base + m * stride], dd_of(0.0)};
+    }
+    __syncthreads();
+    dd_fft_lds<false>(x, P, logP, tw);
+    for (int p = threadIdx.x; p <= N; p += blockDim.x) out[base + p * stride] = x[p].re;
 }
 
 // Where a line lives: element t of line l is at base(l) + t * es, with
@@ -287,12 +291,10 @@ hipError_t build_tensor_dd(const fsa_plan_s* pl, hipStream_t st) {
     g.d = pl->d;
     g.eps = pl->kp.eps;
     g.kind = pl->kp.kind;
-    int maxN = 0;
     for (int j = 0; j < 3; ++j) {
         g.N[j] = j < pl->d ? (int)pl->N[j] : 1;
         g.P[j] = 2 * g.N[j];
         g.L[j] = j < pl->d ? pl->L[j] : 1.0;
-        if (j < pl->d && g.N[j] > maxN) maxN = g.N[j];
     }
     // twiddles of every axis
     size_t off = 0;
@@ -303,20 +305,21 @@ hipError_t build_tensor_dd(const fsa_plan_s* pl, hipStream_t st) {
         off += half;
     }
     const long n = (long)pl->tensor_elems;
-    dd *a = nullptr, *b = nullptr, *cosv = nullptr;
+    dd *a = nullptr, *b = nullptr;
     hipError_t e = hipMallocAsync((void**)&a, sizeof(dd) * n, st);
     if (e == hipSuccess) e = hipMallocAsync((void**)&b, sizeof(dd) * n, st);
-    if (e == hipSuccess) e = hipMallocAsync((void**)&cosv, sizeof(dd) * 2 * maxN, st);
     if (e == hipSuccess) {
         const int grid = (int)((n + 255) / 256);
         hipLaunchKernelGGL(k_dd_sample, dim3(grid), dim3(256), 0, st, a, g);
         dd* src = a;
         dd* dst = b;
         for (int ax = 0; ax < pl->d; ++ax) {
-            hipLaunchKernelGGL(k_dd_cos, dim3((2 * g.N[ax] + 255) / 256), dim3(256), 0, st, cosv,
-                               g.N[ax]);
-            hipLaunchKernelGGL(k_dd_dct, dim3(grid), dim3(256), 0, st, (const dd*)src, dst, g, ax,
-                               (const dd*)cosv);
+            const int P = 2 * g.N[ax];
+            const long lines = n / (g.N[ax] + 1);
+            const int threads = P / 2 < kDDThreads ? P / 2 : kDDThreads;
+            hipLaunchKernelGGL(k_dd_dct, dim3((unsigned)lines), dim3(threads),
+                               sizeof(cdd) * (size_t)P, st, (const dd*)src, dst, g, ax,
+                               dd_tw(pl, ax));
             dd* t = src;
             src = dst;
             dst = t;
@@ -327,7 +330,6 @@ hipError_t build_tensor_dd(const fsa_plan_s* pl, hipStream_t st) {
     }
     if (a) (void)hipFreeAsync(a, st);
     if (b) (void)hipFreeAsync(b, st);
-    if (cosv) (void)hipFreeAsync(cosv, st);
     return e;
 }
 
