@@ -19,6 +19,7 @@ import json
 import os
 import platform
 import sys
+import tempfile
 import time
 
 import numpy as np
@@ -431,7 +432,22 @@ def bench_batch(F, torch, hip, synth, steps, warmup, count=256, tune=True):
             pl.apply(r, o, ws1)
     hip.record(e1, stream)
     percall_ms = hip.ms(e0, e1) / steps
-    same = all(torch.equal(a, b) for a, b in zip(outs, outs2))
+    # With its tuned choices a batch group may run another launch variant than
+    # a problem's own plan (the group's size class differs), so the timed
+    # results agree to rounding; under the same choices (all defaults) they
+    # are bitwise equal.
+    tuned_diff = max(float((a.double() - b.double()).norm() / b.double().norm())
+                     for a, b in zip(outs, outs2))
+    with tempfile.TemporaryDirectory() as td:
+        saved = os.path.join(td, "table.json")
+        F.tune_save(saved)
+        F.tune_reset()
+        F.apply_batched(plans, rhos, outs, ws)  # re-captured under the reset table
+        for pl, r, o in zip(plans, rhos, outs2):
+            pl.apply(r, o, ws1)
+        torch.cuda.synchronize()
+        same = all(torch.equal(a, b) for a, b in zip(outs, outs2))
+        F.tune_load(saved)
     hip.destroy(e0)
     hip.destroy(e1)
     pts = sum(p.points for p in probs)
@@ -452,7 +468,8 @@ def bench_batch(F, torch, hip, synth, steps, warmup, count=256, tune=True):
         "per_call_value": pts / (percall_ms * 1e-3),
         "tensor_build_ms_total": build_ms,
         "autotune_s": tune_s,
-        "bitwise_equal_to_per_call": same,
+        "bitwise_equal_to_per_call_same_choices": same,
+        "tuned_max_rel_l2_vs_per_call": tuned_diff,
     }
 
 
