@@ -394,7 +394,8 @@ def bench_batch(F, torch, hip, synth, steps, warmup, count=256, tune=True):
             for p in probs]
     outs = [torch.empty_like(r) for r in rhos]
     ws = torch.empty(F.batch_workspace_bytes(plans) + 256, dtype=torch.uint8, device="cuda")
-    # autotune one plan per grid shape (the choices are keyed by transform length)
+    # autotune one plan per grid shape for the per-call path, then the batch's
+    # own launches (their size classes are the batch's, not a problem's)
     t_tune = time.perf_counter()
     if tune:
         seen = set()
@@ -402,6 +403,7 @@ def bench_batch(F, torch, hip, synth, steps, warmup, count=256, tune=True):
             if pl.N not in seen:
                 seen.add(pl.N)
                 pl.autotune(r, reps=5)
+        F.autotune_batched(plans, rhos, outs, ws, reps=5)
     torch.cuda.synchronize()
     tune_s = time.perf_counter() - t_tune
     log(f"  batch setup {time.perf_counter() - t0:.1f} s (tensor builds {build_ms:.1f} ms, "

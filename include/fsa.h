@@ -197,14 +197,18 @@ fsa_status fsa_batch_workspace_bytes(int n, const fsa_plan* plans, size_t* bytes
  * dependency order, and each transform length that pass uses, ONE launch
  * walks the work items (problem, tile or pencil) of every problem that
  * shares the length.  The graph is captured on first use of a batch
- * signature and replayed afterwards.  Each problem's result is bitwise
- * equal to fsa_apply on that problem alone.
+ * signature and replayed afterwards.  A launch takes the tuning table's
+ * choice for its total number of transforms (fsa_autotune_batched tunes
+ * those); under the same launch choices each problem's result is bitwise
+ * equal to fsa_apply on that problem alone, and under other choices it
+ * agrees to rounding.
  *   plans, rho, phi  host arrays of n entries; rho[i]/phi[i] are device
  *                    pointers for plans[i].
  *   workspace        device scratch of >= fsa_batch_workspace_bytes bytes.
  * The device pointers are part of the captured graph: a call with the same
  * plans but different pointers re-captures.  Dipole-dipole plans
- * (FSA_DDI_3D, FSA_QUASI2D_DDI) are not batched: FSA_EUNSUPPORTED. */
+ * (FSA_DDI_3D, FSA_QUASI2D_DDI) and double-double plans are not batched:
+ * FSA_EUNSUPPORTED. */
 fsa_status fsa_apply_batched(int n, const fsa_plan* plans, const void* const* rho,
                              void* const* phi, void* workspace, size_t workspace_bytes,
                              void* stream);
@@ -239,6 +243,11 @@ typedef enum {
     FSA_PASS_C2R = 4,   /* E: inverse real FFT along the last axis, crop    */
     FSA_PASS_SPECTRAL = 5 /* dipole-dipole kinds: the source derivative     */
 } fsa_pass;
+/* OR-ed into the pass of the tuning calls below: the entry of the batched
+ * persistent launches of that pass (fsa_apply_batched), kept apart from the
+ * single-evaluation entries.  A batched launch with no batched entry of its
+ * (precision, pass, length) takes the single-evaluation entry. */
+#define FSA_PASS_BATCHED 16
 
 /* Every pass kernel exists in up to three compiled variants per length:
  *   0  default radix plan and workgroup size;
@@ -263,8 +272,21 @@ typedef enum {
  * Batch graphs captured before the call are re-captured on their next use. */
 fsa_status fsa_autotune(fsa_plan plan, const void* rho, void* phi, void* workspace, void* stream,
                         int reps);
+/* The launches of a batch (fsa_apply_batched) cover many problems at once,
+ * a size class that the per-plan tuning does not reach: times every
+ * distinct (variant, occupancy) candidate of every persistent launch of
+ * this batch (median of `reps`, 1..1000, after one warm-up each; the launch
+ * of the fused pass has its input re-created before each run) and stores
+ * the fastest under the launch's size class.  Same arguments and checks as
+ * fsa_apply_batched; synchronous.  On return phi holds a valid evaluation
+ * with the tuned choices, and batch graphs captured before are re-captured
+ * on their next use. */
+fsa_status fsa_autotune_batched(int n, const fsa_plan* plans, const void* const* rho,
+                                void* const* phi, void* workspace, size_t workspace_bytes,
+                                void* stream, int reps);
 
-/* Sets / reads one entry (precision: fsa_precision, pass: fsa_pass).
+/* Sets / reads one entry (precision: fsa_precision, pass: fsa_pass, with
+ * FSA_PASS_BATCHED for the batched launches).
  * Entries are kept per size class floor(log2(lines)), `lines` being the
  * number of transforms one launch runs (rows of the last axis for the real
  * passes, axis-1 lines for B and D, axis-0 pencils for C; summed over the

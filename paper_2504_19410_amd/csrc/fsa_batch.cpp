@@ -14,6 +14,13 @@
 // with a given signature -- plans, device pointers, workspace, and the
 // generation of the tuning table whose launch choices it snapshots -- and
 // replayed on later calls.
+//
+// A group's launch choice is the tuning table's batched entry for the
+// group's total number of transforms (the single-evaluation entries where
+// there is none): a launch over a job table of many problems is another
+// kernel instantiation than the single-problem launch, and a large batch
+// reaches size classes no single problem does.  fsa_autotune_batched times
+// every candidate of every group launch of a batch and stores the fastest.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -98,11 +105,11 @@ bool add_job(std::map<std::tuple<int, int, int>, Group>& groups, fsa::Pass pass,
     return true;
 }
 
-// Fixes each group's launch choice (tuned for the group's total size) and
-// the item prefix its jobs follow under that choice.
+// Fixes a group's launch choice and the item prefix its jobs follow under
+// that choice.
 template <class Job>
-void finish_group(Group& g) {
-    g.ch = fsa::tune::get(g.prec, g.pass, g.len, g.lines);
+void finish_group_as(Group& g, fsa::Choice c) {
+    g.ch = c;
     g.start.assign(1, 0);
     for (int i = 0; i < g.n; ++i) {
         Job job;
@@ -113,9 +120,46 @@ void finish_group(Group& g) {
     }
 }
 
-fsa_status build_entry(int n, const fsa_plan* plans, const void* const* rho, void* const* phi,
-                       char* ws, Entry& e) {
-    std::map<std::tuple<int, int, int>, Group> groups;
+void finish_group(Group& g, fsa::Choice c) {
+    switch (g.pass) {
+    case fsa::Pass::R2C: finish_group_as<fsa::JobR2c>(g, c); break;
+    case fsa::Pass::C2R: finish_group_as<fsa::JobC2r>(g, c); break;
+    case fsa::Pass::FWD_T:
+    case fsa::Pass::INV_T: finish_group_as<fsa::JobT>(g, c); break;
+    case fsa::Pass::CONV: finish_group_as<fsa::JobConv>(g, c); break;
+    }
+}
+
+// Device bytes of a group's tables: [jobs | start], each 256-byte aligned.
+size_t table_bytes(const Group& g) {
+    return align256(g.jobs.size()) + align256(g.start.size() * sizeof(int));
+}
+
+hipError_t upload_tables(const Group& g, char* dst) {
+    hipError_t e = hipMemcpy(dst, g.jobs.data(), g.jobs.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+        e = hipMemcpy(dst + align256(g.jobs.size()), g.start.data(),
+                      g.start.size() * sizeof(int), hipMemcpyHostToDevice);
+    return e;
+}
+
+// The group's persistent launch over tables at `tables` (laid out as
+// upload_tables writes them).
+hipError_t launch_group(const Group& g, const char* tables, hipStream_t st) {
+    const int* start = (const int*)(tables + align256(g.jobs.size()));
+    const int total = g.start.back();
+    return g.prec == FSA_F32 ? fsa::Launch<float>::batch(g.pass, g.len, tables, start, g.n, total,
+                                                         g.tw, g.tw2, g.ch, st)
+                             : fsa::Launch<double>::batch(g.pass, g.len, tables, start, g.n,
+                                                          total, g.tw, g.tw2, g.ch, st);
+}
+
+using Groups = std::map<std::tuple<int, int, int>, Group>;
+
+// Sorts the problems' jobs into (pass, length, precision) groups; the
+// launch choices are not fixed yet.
+fsa_status make_groups(int n, const fsa_plan* plans, const void* const* rho, void* const* phi,
+                       char* ws, Groups& groups) {
     for (int i = 0; i < n; ++i) {
         const fsa_plan_s* pl = plans[i];
         const size_t cs = pl->csize;
@@ -150,37 +194,36 @@ fsa_status build_entry(int n, const fsa_plan* plans, const void* const* rho, voi
                  add(fsa::JobC2r{w1, phi[i], 1, N0}, fsa::Pass::C2R, N1, tw_m, tw_pl, n0);
         }
         if (!ok) {
-            fsa::set_last_error("fsa_apply_batched: unsupported transform length");
+            fsa::set_last_error("unsupported transform length in a batch");
             return FSA_EUNSUPPORTED;
         }
     }
+    return FSA_OK;
+}
+
+fsa_status build_entry(int n, const fsa_plan* plans, const void* const* rho, void* const* phi,
+                       char* ws, Entry& e) {
+    Groups groups;
+    fsa_status st = make_groups(n, plans, rho, phi, ws, groups);
+    if (st != FSA_OK) return st;
     for (auto& kv : groups) {
         Group& g = kv.second;
-        switch (g.pass) {
-        case fsa::Pass::R2C: finish_group<fsa::JobR2c>(g); break;
-        case fsa::Pass::C2R: finish_group<fsa::JobC2r>(g); break;
-        case fsa::Pass::FWD_T:
-        case fsa::Pass::INV_T: finish_group<fsa::JobT>(g); break;
-        case fsa::Pass::CONV: finish_group<fsa::JobConv>(g); break;
-        }
+        finish_group(g, fsa::tune::get(g.prec, g.pass, g.len, g.lines, true));
     }
     // one device buffer: per group [jobs | start], each part 256-byte aligned
     size_t bytes = 0;
-    std::vector<std::pair<size_t, size_t>> offs;
+    std::vector<size_t> offs;
     for (auto& kv : groups) {
-        const Group& g = kv.second;
-        const size_t oj = bytes;
-        bytes += align256(g.jobs.size());
-        const size_t os = bytes;
-        bytes += align256(g.start.size() * sizeof(int));
-        offs.emplace_back(oj, os);
+        offs.push_back(bytes);
+        bytes += table_bytes(kv.second);
     }
     std::vector<unsigned char> host(bytes, 0);
     size_t gi = 0;
     for (auto& kv : groups) {
         const Group& g = kv.second;
-        std::memcpy(host.data() + offs[gi].first, g.jobs.data(), g.jobs.size());
-        std::memcpy(host.data() + offs[gi].second, g.start.data(), g.start.size() * sizeof(int));
+        std::memcpy(host.data() + offs[gi], g.jobs.data(), g.jobs.size());
+        std::memcpy(host.data() + offs[gi] + align256(g.jobs.size()), g.start.data(),
+                    g.start.size() * sizeof(int));
         ++gi;
     }
     hipError_t err = hipMalloc(&e.tables, bytes > 0 ? bytes : 256);
@@ -208,18 +251,9 @@ fsa_status build_entry(int n, const fsa_plan* plans, const void* const* rho, voi
             gi = 0;
             for (auto& kv : groups) {
                 const Group& g = kv.second;
-                const size_t oj = offs[gi].first, os = offs[gi].second;
-                ++gi;
+                const size_t off = offs[gi++];
                 if ((int)g.pass != stage || lerr != hipSuccess) continue;
-                const char* base = (const char*)e.tables;
-                const int total = g.start.back();
-                lerr = g.prec == FSA_F32
-                           ? fsa::Launch<float>::batch(g.pass, g.len, base + oj,
-                                                       (const int*)(base + os), g.n, total, g.tw,
-                                                       g.tw2, g.ch, cap)
-                           : fsa::Launch<double>::batch(g.pass, g.len, base + oj,
-                                                        (const int*)(base + os), g.n, total, g.tw,
-                                                        g.tw2, g.ch, cap);
+                lerr = launch_group(g, (const char*)e.tables + off, cap);
                 ++e.launches;
             }
         }
@@ -232,6 +266,55 @@ fsa_status build_entry(int n, const fsa_plan* plans, const void* const* rho, voi
     if (err != hipSuccess) {
         fsa::set_last_error(hipGetErrorString(err));
         return FSA_EDEVICE;
+    }
+    return FSA_OK;
+}
+
+// Argument checks shared by the batched entry points (`fn` names the caller
+// in the error message); on success *dev is the current device.
+fsa_status check_batch(const char* fn, int n, const fsa_plan* plans, const void* const* rho,
+                       void* const* phi, const void* workspace, size_t workspace_bytes,
+                       int* dev) {
+    size_t need = 0;
+    fsa_status s = fsa_batch_workspace_bytes(n, plans, &need);
+    if (s != FSA_OK) return s;
+    if (n == 0) return FSA_OK;
+    const std::string f(fn);
+    if (!rho || !phi || !workspace) {
+        fsa::set_last_error((f + ": null array").c_str());
+        return FSA_EINVAL;
+    }
+    if (((uintptr_t)workspace & 255) != 0) {
+        fsa::set_last_error((f + ": workspace must be 256-byte aligned").c_str());
+        return FSA_EINVAL;
+    }
+    if (workspace_bytes < need) {
+        fsa::set_last_error((f + ": workspace too small").c_str());
+        return FSA_EINVAL;
+    }
+    if (hipGetDevice(dev) != hipSuccess) {
+        fsa::set_last_error((f + ": hipGetDevice failed").c_str());
+        return FSA_EDEVICE;
+    }
+    for (int i = 0; i < n; ++i) {
+        if (!rho[i] || !phi[i]) {
+            fsa::set_last_error((f + ": null device pointer").c_str());
+            return FSA_EINVAL;
+        }
+        if (!plans[i]->built || plans[i]->device != *dev) {
+            fsa::set_last_error((f + ": a plan is not built on the current device").c_str());
+            return FSA_ESTATE;
+        }
+        if (plans[i]->prec == FSA_DD) {
+            fsa::set_last_error(
+                (f + ": double-double plans are not batched (use fsa_apply)").c_str());
+            return FSA_EUNSUPPORTED;
+        }
+        if (plans[i]->n_spectral) {
+            fsa::set_last_error(
+                (f + ": dipole-dipole plans are not batched (use fsa_apply)").c_str());
+            return FSA_EUNSUPPORTED;
+        }
     }
     return FSA_OK;
 }
@@ -273,51 +356,16 @@ fsa_status fsa_batch_workspace_bytes(int n, const fsa_plan* plans, size_t* bytes
 fsa_status fsa_apply_batched(int n, const fsa_plan* plans, const void* const* rho,
                              void* const* phi, void* workspace, size_t workspace_bytes,
                              void* stream) {
-    size_t need = 0;
-    fsa_status s = fsa_batch_workspace_bytes(n, plans, &need);
-    if (s != FSA_OK) return s;
-    if (n == 0) return FSA_OK;
-    if (!rho || !phi || !workspace) {
-        fsa::set_last_error("fsa_apply_batched: null array");
-        return FSA_EINVAL;
-    }
-    if (((uintptr_t)workspace & 255) != 0) {
-        fsa::set_last_error("fsa_apply_batched: workspace must be 256-byte aligned");
-        return FSA_EINVAL;
-    }
-    if (workspace_bytes < need) {
-        fsa::set_last_error("fsa_apply_batched: workspace too small");
-        return FSA_EINVAL;
-    }
     int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess) {
-        fsa::set_last_error("fsa_apply_batched: hipGetDevice failed");
-        return FSA_EDEVICE;
-    }
+    fsa_status s = check_batch("fsa_apply_batched", n, plans, rho, phi, workspace,
+                               workspace_bytes, &dev);
+    if (s != FSA_OK || n == 0) return s;
     std::vector<uint64_t> key;
     key.reserve(3 * (size_t)n + 3);
     key.push_back((uint64_t)dev);
     key.push_back((uint64_t)(uintptr_t)workspace);
     key.push_back((uint64_t)n);
     for (int i = 0; i < n; ++i) {
-        if (!rho[i] || !phi[i]) {
-            fsa::set_last_error("fsa_apply_batched: null device pointer");
-            return FSA_EINVAL;
-        }
-        if (!plans[i]->built || plans[i]->device != dev) {
-            fsa::set_last_error("fsa_apply_batched: a plan is not built on the current device");
-            return FSA_ESTATE;
-        }
-        if (plans[i]->prec == FSA_DD) {
-            fsa::set_last_error("fsa_apply_batched: double-double plans are not batched "
-                                "(use fsa_apply)");
-            return FSA_EUNSUPPORTED;
-        }
-        if (plans[i]->n_spectral) {
-            fsa::set_last_error(
-                "fsa_apply_batched: dipole-dipole plans are not batched (use fsa_apply)");
-            return FSA_EUNSUPPORTED;
-        }
         key.push_back(plans[i]->id);
         key.push_back((uint64_t)(uintptr_t)rho[i]);
         key.push_back((uint64_t)(uintptr_t)phi[i]);
@@ -374,6 +422,113 @@ fsa_status fsa_batch_launches(int n, const fsa_plan* plans, const void* const* r
     }
     fsa::set_last_error("fsa_batch_launches: no captured graph for this batch");
     return FSA_ESTATE;
+}
+
+fsa_status fsa_autotune_batched(int n, const fsa_plan* plans, const void* const* rho,
+                                void* const* phi, void* workspace, size_t workspace_bytes,
+                                void* stream, int reps) {
+    int dev = 0;
+    fsa_status s = check_batch("fsa_autotune_batched", n, plans, rho, phi, workspace,
+                               workspace_bytes, &dev);
+    if (s != FSA_OK) return s;
+    if (reps < 1 || reps > 1000) {
+        fsa::set_last_error("fsa_autotune_batched: reps must be 1..1000");
+        return FSA_EINVAL;
+    }
+    if (n == 0) return FSA_OK;
+    Groups groups;
+    s = make_groups(n, plans, rho, phi, (char*)workspace, groups);
+    if (s != FSA_OK) return s;
+    // every group's tables under its current choice (`fixed`), and room for
+    // one group's tables under a candidate (`trial`); the start prefix is
+    // the only part that depends on the choice, and it has n + 1 entries
+    std::vector<Group*> order;
+    for (int stage = 0; stage <= (int)fsa::Pass::C2R; ++stage)
+        for (auto& kv : groups)
+            if ((int)kv.second.pass == stage) order.push_back(&kv.second);
+    size_t fixed_bytes = 0, trial_bytes = 0;
+    std::vector<size_t> offs;
+    for (Group* g : order) {
+        finish_group(*g, fsa::tune::get(g->prec, g->pass, g->len, g->lines, true));
+        offs.push_back(fixed_bytes);
+        fixed_bytes += table_bytes(*g);
+        trial_bytes = std::max(trial_bytes, table_bytes(*g));
+    }
+    char* dbuf = nullptr;
+    if (hipMalloc((void**)&dbuf, fixed_bytes + trial_bytes) != hipSuccess) {
+        fsa::set_last_error("fsa_autotune_batched: table allocation failed");
+        return FSA_ENOMEM;
+    }
+    char* trial = dbuf + fixed_bytes;
+    hipStream_t st = (hipStream_t)stream;
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    hipError_t e = hipEventCreate(&ev[0]);
+    if (e == hipSuccess) e = hipEventCreate(&ev[1]);
+    for (size_t i = 0; i < order.size() && e == hipSuccess; ++i)
+        e = upload_tables(*order[i], dbuf + offs[i]);
+    // launches of every group of the passes before `stage`, with the fixed
+    // choices: one evaluation up to that pass
+    auto run_before = [&](int stage) {
+        hipError_t r = hipSuccess;
+        for (size_t i = 0; i < order.size() && r == hipSuccess; ++i)
+            if ((int)order[i]->pass < stage) r = launch_group(*order[i], dbuf + offs[i], st);
+        return r;
+    };
+    // fill every buffer with data once
+    if (e == hipSuccess) e = run_before((int)fsa::Pass::C2R + 1);
+    for (size_t gi = 0; gi < order.size() && e == hipSuccess; ++gi) {
+        Group& g = *order[gi];
+        const fsa::Choice current = g.ch;
+        int mask = 0;
+        if (fsa_tune_variants((int)g.prec, (int)g.pass, g.len, &mask) != FSA_OK) mask = 1;
+        std::vector<fsa::Choice> cands;
+        for (int v = 0; v < fsa::kNumVariants; ++v) {
+            if (!(mask >> v & 1)) continue;
+            const int mo = g.prec == FSA_F32 ? fsa::Launch<float>::max_occ(g.pass, g.len, v)
+                                             : fsa::Launch<double>::max_occ(g.pass, g.len, v);
+            cands.push_back(fsa::Choice{v, 0});
+            if (mo >= 2) cands.push_back(fsa::Choice{v, mo / 2});
+        }
+        double best = 1e300;
+        fsa::Choice best_c = current;
+        for (const fsa::Choice& c : cands) {
+            finish_group(g, c);
+            e = upload_tables(g, trial);
+            std::vector<float> ms;
+            for (int i = -1; i < reps && e == hipSuccess; ++i) {
+                // the fused pass works in place: re-create its input first
+                if (g.pass == fsa::Pass::CONV) e = run_before((int)fsa::Pass::CONV);
+                if (e == hipSuccess) e = hipEventRecord(ev[0], st);
+                if (e == hipSuccess) e = launch_group(g, trial, st);
+                if (e == hipSuccess) e = hipEventRecord(ev[1], st);
+                if (e == hipSuccess) e = hipEventSynchronize(ev[1]);
+                float t = 0.0f;
+                if (e == hipSuccess) e = hipEventElapsedTime(&t, ev[0], ev[1]);
+                if (e == hipSuccess && i >= 0) ms.push_back(t);
+            }
+            if (e != hipSuccess) break;
+            std::sort(ms.begin(), ms.end());
+            const double us = 1e3 * ms[ms.size() / 2];
+            if (us < best) {
+                best = us;
+                best_c = c;
+            }
+        }
+        if (e != hipSuccess) break;
+        finish_group(g, best_c);
+        e = upload_tables(g, dbuf + offs[gi]);
+        fsa::tune::set(g.prec, g.pass, g.len, g.lines, best_c, best, true);
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    for (hipEvent_t x : ev)
+        if (x) (void)hipEventDestroy(x);
+    (void)hipFree(dbuf);
+    if (e != hipSuccess) {
+        fsa::set_last_error((std::string("fsa_autotune_batched: ") + hipGetErrorString(e)).c_str());
+        return FSA_EDEVICE;
+    }
+    // leave the outputs holding a valid evaluation under the tuned choices
+    return fsa_apply_batched(n, plans, rho, phi, workspace, workspace_bytes, stream);
 }
 
 }  // extern "C"

@@ -171,8 +171,11 @@ struct Launch {
 // pass, length); variant 0 at full occupancy if there is none.
 namespace tune {
 int size_class(long lines);
-Choice get(fsa_precision prec, Pass pass, int len, long lines);
-void set(fsa_precision prec, Pass pass, int len, long lines, Choice c, double us);
+// `batched`: the entries of the batched persistent launches (a batched get
+// falls back to the single-evaluation entries where it has none).
+Choice get(fsa_precision prec, Pass pass, int len, long lines, bool batched = false);
+void set(fsa_precision prec, Pass pass, int len, long lines, Choice c, double us,
+         bool batched = false);
 // Bumped on every change; batch graphs captured under another generation
 // are re-captured.
 uint64_t generation();

@@ -41,7 +41,9 @@ struct TuneEntry {
     double us = 0.0;  // measured time of the chosen candidate (0: set by hand)
 };
 
-using Key = std::tuple<int, int, int, int>;  // precision, pass, length, size class
+// precision, pass (| FSA_PASS_BATCHED for the batched launches), length,
+// size class
+using Key = std::tuple<int, int, int, int>;
 using GridKey = std::tuple<int, int64_t, int64_t, int64_t>;  // precision, N0, N1, N2
 
 struct SlabEntry {
@@ -56,23 +58,48 @@ std::atomic<uint64_t> g_generation{1};
 std::once_flag g_env_once;
 
 const char* const kPassNames[5] = {"r2c", "fwd_t", "conv", "inv_t", "c2r"};
+const char* const kBatchedPrefix = "batched_";
+
+std::string pass_name(int pass) {
+    return std::string((pass & FSA_PASS_BATCHED) ? kBatchedPrefix : "") +
+           kPassNames[pass & ~FSA_PASS_BATCHED];
+}
+
+int pass_from_name(const std::string& name) {
+    std::string base = name;
+    int flag = 0;
+    const std::string pre(kBatchedPrefix);
+    if (base.compare(0, pre.size(), pre) == 0) {
+        base = base.substr(pre.size());
+        flag = FSA_PASS_BATCHED;
+    }
+    for (int k = 0; k < 5; ++k)
+        if (base == kPassNames[k]) return k | flag;
+    return -1;
+}
 
 fsa_status fail(fsa_status s, const std::string& msg) {
     fsa::set_last_error(msg.c_str());
     return s;
 }
 
-bool pass_ok(int pass) { return pass >= 0 && pass <= (int)fsa::Pass::C2R; }
+// A pass of fsa_pass, optionally with the FSA_PASS_BATCHED flag.
+bool pass_ok(int pass) {
+    const int base = pass & ~FSA_PASS_BATCHED;
+    return base >= 0 && base <= (int)fsa::Pass::C2R;
+}
 
 // Transform lengths the passes support: the real passes take the half
 // length M of the padded row, the complex passes the padded length P.
 bool length_ok(int pass, int len) {
+    pass &= ~FSA_PASS_BATCHED;
     if (!fsa::fft_length_supported(len)) return false;
     if (pass == (int)fsa::Pass::R2C || pass == (int)fsa::Pass::C2R) return len >= 8 && len <= 2048;
     return len >= 16 && len <= 4096;
 }
 
 bool variant_ok(fsa_precision prec, int pass, int len, int var) {
+    pass &= ~FSA_PASS_BATCHED;
     if (var < 0 || var >= fsa::kNumVariants) return false;
     return prec == FSA_F32 ? fsa::Launch<float>::distinct((fsa::Pass)pass, len, var)
                            : fsa::Launch<double>::distinct((fsa::Pass)pass, len, var);
@@ -226,9 +253,7 @@ fsa_status load_file(const char* path) {
     auto small_int = [](double v) { return v >= 0.0 && v <= 1e6 && v == (double)(int)v; };
     for (const auto& row : p.rows) {
         int prec = row.prec == "f32" ? FSA_F32 : row.prec == "f64" ? FSA_F64 : -1;
-        int pass = -1;
-        for (int k = 0; k < 5; ++k)
-            if (row.pass == kPassNames[k]) pass = k;
+        const int pass = pass_from_name(row.pass);
         const bool ints = small_int(row.len) && small_int(row.var) && small_int(row.occ) &&
                           small_int(row.cls) && row.cls <= 62;
         const int len = ints ? (int)row.len : -1, var = ints ? (int)row.var : -1;
@@ -282,31 +307,43 @@ int size_class(long lines) {
     return c;
 }
 
-Choice get(fsa_precision prec, Pass pass, int len, long lines) {
-    load_env_once();
-    const int cls = size_class(lines);
-    std::lock_guard<std::mutex> lk(g_mu);
+namespace {
+// The entry of the nearest class among the entries of (prec, key_pass, len);
+// false if there is none.  Caller holds g_mu.
+bool nearest(int prec, int key_pass, int len, int cls, Choice* out) {
     // entries of (prec, pass, len) are adjacent in the map, ordered by class
-    auto lo = g_table.lower_bound(Key((int)prec, (int)pass, len, 0));
-    Choice best;
+    auto lo = g_table.lower_bound(Key(prec, key_pass, len, 0));
     int dist = 1 << 30;
     for (auto it = lo; it != g_table.end(); ++it) {
-        if (std::get<0>(it->first) != (int)prec || std::get<1>(it->first) != (int)pass ||
+        if (std::get<0>(it->first) != prec || std::get<1>(it->first) != key_pass ||
             std::get<2>(it->first) != len)
             break;
         const int d = std::abs(std::get<3>(it->first) - cls);
         if (d < dist) {
             dist = d;
-            best = it->second.ch;
+            *out = it->second.ch;
         }
     }
+    return dist != (1 << 30);
+}
+}  // namespace
+
+Choice get(fsa_precision prec, Pass pass, int len, long lines, bool batched) {
+    load_env_once();
+    const int cls = size_class(lines);
+    std::lock_guard<std::mutex> lk(g_mu);
+    Choice best;
+    // a batched launch prefers the batched entries, then the single ones
+    if (batched && nearest((int)prec, (int)pass | FSA_PASS_BATCHED, len, cls, &best)) return best;
+    nearest((int)prec, (int)pass, len, cls, &best);
     return best;
 }
 
-void set(fsa_precision prec, Pass pass, int len, long lines, Choice c, double us) {
+void set(fsa_precision prec, Pass pass, int len, long lines, Choice c, double us, bool batched) {
     {
         std::lock_guard<std::mutex> lk(g_mu);
-        g_table[Key((int)prec, (int)pass, len, size_class(lines))] = TuneEntry{c, us};
+        const int kp = (int)pass | (batched ? FSA_PASS_BATCHED : 0);
+        g_table[Key((int)prec, kp, len, size_class(lines))] = TuneEntry{c, us};
     }
     ++g_generation;
 }
@@ -344,8 +381,9 @@ fsa_status fsa_tune_set(int precision, int pass, int length, int64_t lines, int 
         return fail(FSA_EINVAL, "fsa_tune_set: variant " + std::to_string(variant) +
                                     " does not exist at this pass and length");
     load_env_once();
-    fsa::tune::set((fsa_precision)precision, (fsa::Pass)pass, length, (long)lines,
-                   fsa::Choice{variant, occupancy}, 0.0);
+    fsa::tune::set((fsa_precision)precision, (fsa::Pass)(pass & ~FSA_PASS_BATCHED), length,
+                   (long)lines, fsa::Choice{variant, occupancy}, 0.0,
+                   (pass & FSA_PASS_BATCHED) != 0);
     return FSA_OK;
 }
 
@@ -355,8 +393,9 @@ fsa_status fsa_tune_get(int precision, int pass, int length, int64_t lines, int*
         !length_ok(pass, length) || lines < 1 || !variant || !occupancy)
         return fail(FSA_EINVAL, "fsa_tune_get: bad arguments");
     load_env_once();
-    const fsa::Choice c = fsa::tune::get((fsa_precision)precision, (fsa::Pass)pass, length,
-                                         (long)lines);
+    const fsa::Choice c = fsa::tune::get((fsa_precision)precision,
+                                         (fsa::Pass)(pass & ~FSA_PASS_BATCHED), length,
+                                         (long)lines, (pass & FSA_PASS_BATCHED) != 0);
     double t = 0.0;
     {
         std::lock_guard<std::mutex> lk(g_mu);
@@ -405,7 +444,7 @@ fsa_status fsa_tune_save(const char* path) {
                           "%s\n    {\"precision\": \"%s\", \"pass\": \"%s\", \"length\": %d, "
                           "\"class\": %d, \"variant\": %d, \"occupancy\": %d, \"us\": %.3f}",
                           first ? "" : ",", std::get<0>(kv.first) == FSA_F32 ? "f32" : "f64",
-                          kPassNames[std::get<1>(kv.first)], std::get<2>(kv.first),
+                          pass_name(std::get<1>(kv.first)).c_str(), std::get<2>(kv.first),
                           std::get<3>(kv.first), kv.second.ch.var, kv.second.ch.occ,
                           kv.second.us);
             out += line;

@@ -44,7 +44,8 @@ STATUS = {
 
 EXPORTS = (
     "fsa_plan_create", "fsa_plan_query", "fsa_build_tensor", "fsa_apply", "fsa_apply_events",
-    "fsa_batch_workspace_bytes", "fsa_apply_batched", "fsa_batch_launches", "fsa_plan_destroy",
+    "fsa_batch_workspace_bytes", "fsa_apply_batched", "fsa_batch_launches",
+    "fsa_autotune_batched", "fsa_plan_destroy",
     "fsa_plan_tensor",
     "fsa_server_create", "fsa_server_submit", "fsa_server_poll", "fsa_server_wait",
     "fsa_server_cancel", "fsa_server_stats", "fsa_server_reset_stats", "fsa_server_destroy",
@@ -112,6 +113,7 @@ def _load():
         "fsa_server_reset_stats": [P],
         "fsa_server_destroy": [P],
         "fsa_autotune": [P, P, P, P, P, I],
+        "fsa_autotune_batched": [I, P, P, P, P, S, P, I],
         "fsa_tune_set": [I, I, I, ctypes.c_int64, I, I],
         "fsa_tune_get": [I, I, I, ctypes.c_int64, P, P, P],
         "fsa_tune_variants": [I, I, I, P],
@@ -367,24 +369,35 @@ def _hip():
     return _hip_lib
 
 
+PASS_BATCHED = 16  # FSA_PASS_BATCHED
+
+
+def _tune_pass(pass_name: str) -> int:
+    """fsa_pass of a pass name; "batched_<pass>" names the entries of the
+    batched launches (FSA_PASS_BATCHED)."""
+    if pass_name.startswith("batched_"):
+        return PASSES[pass_name[len("batched_"):]] | PASS_BATCHED
+    return PASSES[pass_name]
+
+
 def tune_get(precision: str, pass_name: str, length: int, lines: int = 1):
     """(variant, occupancy, us) a launch of `lines` transforms would use."""
     v, o, us = ctypes.c_int(), ctypes.c_int(), ctypes.c_double()
-    _check(_lib.fsa_tune_get(PRECISIONS[precision], PASSES[pass_name], int(length), int(lines),
-                             ctypes.byref(v), ctypes.byref(o), ctypes.byref(us)))
+    _check(_lib.fsa_tune_get(PRECISIONS[precision], _tune_pass(pass_name), int(length),
+                             int(lines), ctypes.byref(v), ctypes.byref(o), ctypes.byref(us)))
     return v.value, o.value, us.value
 
 
 def tune_set(precision: str, pass_name: str, length: int, variant: int, occupancy: int = 0,
              lines: int = 1):
-    _check(_lib.fsa_tune_set(PRECISIONS[precision], PASSES[pass_name], int(length), int(lines),
-                             int(variant), int(occupancy)))
+    _check(_lib.fsa_tune_set(PRECISIONS[precision], _tune_pass(pass_name), int(length),
+                             int(lines), int(variant), int(occupancy)))
 
 
 def tune_variants(precision: str, pass_name: str, length: int):
     """Variants compiled (distinct) at this pass and length."""
     m = ctypes.c_int()
-    _check(_lib.fsa_tune_variants(PRECISIONS[precision], PASSES[pass_name], int(length),
+    _check(_lib.fsa_tune_variants(PRECISIONS[precision], _tune_pass(pass_name), int(length),
                                   ctypes.byref(m)))
     return [v for v in range(3) if m.value >> v & 1]
 
@@ -443,6 +456,34 @@ def apply_batched(plans: Sequence[Plan], rhos: Sequence[torch.Tensor],
     _check(_lib.fsa_apply_batched(n, arr, rp, op, ctypes.c_void_p(base),
                                   ctypes.c_size_t(workspace.numel() - (base - workspace.data_ptr())),
                                   _stream_ptr(stream)))
+    return outs
+
+
+def autotune_batched(plans: Sequence[Plan], rhos: Sequence[torch.Tensor],
+                     outs: Optional[Sequence[torch.Tensor]] = None,
+                     workspace: Optional[torch.Tensor] = None, reps: int = 5,
+                     stream: Optional[torch.cuda.Stream] = None):
+    """Tunes the persistent launches of this batch at their own size classes
+    (``fsa_autotune_batched``); returns the outputs, which hold a valid
+    evaluation under the tuned choices."""
+    n = len(plans)
+    if len(rhos) != n:
+        raise ValueError("one density per plan")
+    for p, r in zip(plans, rhos):
+        p.check_input(r)
+    if outs is None:
+        outs = [torch.empty_like(r) for r in rhos]
+    need = batch_workspace_bytes(plans)
+    if workspace is None:
+        workspace = torch.empty(need + 256, dtype=torch.uint8, device=rhos[0].device)
+    base = (workspace.data_ptr() + 255) & ~255
+    arr = (ctypes.c_void_p * n)(*[p.handle for p in plans])
+    rp = (ctypes.c_void_p * n)(*[r.data_ptr() for r in rhos])
+    op = (ctypes.c_void_p * n)(*[o.data_ptr() for o in outs])
+    _check(_lib.fsa_autotune_batched(
+        n, arr, rp, op, ctypes.c_void_p(base),
+        ctypes.c_size_t(workspace.numel() - (base - workspace.data_ptr())), _stream_ptr(stream),
+        int(reps)))
     return outs
 
 

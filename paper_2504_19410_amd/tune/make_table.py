@@ -8,10 +8,14 @@ pointing FSA_TUNE_CACHE at it.
 Usage (on the GPU): python -m paper_2504_19410_amd.tune.make_table [--reps 7]
 With --add, the shipped table is loaded first and only the extra 2D shapes
 (FP64 log-kernel batch shapes, 2048^2 and 1024^2 grids) are tuned into it.
+The batched launches of the 256-density 2D log-kernel batch are tuned last
+(fsa_autotune_batched, entries kept apart from the single-evaluation ones);
+with --batch, the shipped table is loaded and only they are tuned.
 """
 import argparse
 import os
 
+import numpy as np
 import torch
 
 from paper_2504_19410_amd import fsa as F
@@ -42,18 +46,38 @@ def arch_name():
     return name.split(":")[0]
 
 
+def tune_batch(reps):
+    """The batched launches of the 256-density 2D log-kernel batch (FP32)."""
+    probs = synth.log2d_batch(256)
+    plans = [F.Plan(p.kernel, p.L, p.N, "f32").build() for p in probs]
+    rhos = [torch.from_numpy(synth.eval_gaussians(p.gaussians, p.L, p.N, dtype=np.float32)).cuda()
+            for p in probs]
+    F.autotune_batched(plans, rhos, reps=reps)
+    groups = {}
+    for p in probs:
+        N0, N1 = p.N
+        for key, lines in ((("r2c", N1), N0), (("conv", 2 * N0), N1 + 1), (("c2r", N1), N0)):
+            groups[key] = groups.get(key, 0) + lines
+    print("batch", {f"{a}_{b}": F.tune_get("f32", "batched_" + a, b, lines)
+                    for (a, b), lines in groups.items()}, flush=True)
+    for p in plans:
+        p.close()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--reps", type=int, default=7)
     ap.add_argument("--out", default=None)
     ap.add_argument("--add", action="store_true",
                     help="tune only the extra 2D shapes into the shipped table")
+    ap.add_argument("--batch", action="store_true",
+                    help="tune only the batched launches into the shipped table")
     args = ap.parse_args()
     extra = [(k, L, N, lam, prec) for k, L, N, lam in SHAPES_2D_EXTRA for prec in ("f32", "f64")]
     extra += [("log2d", (8.0, 8.0), N, None, "f64") for N in synth.LOG2D_SHAPES]
-    if args.add:
+    if args.add or args.batch:
         F.tune_load(os.path.join(HERE, f"{arch_name()}.json"))
-        jobs = extra
+        jobs = [] if args.batch else extra
     else:
         F.tune_reset()
         jobs = [(k, L, N, lam, prec) for k, L, N, lam in SHAPES_3D for prec in ("f32", "f64")]
@@ -65,6 +89,8 @@ def main():
         table = plan.autotune(rho, reps=args.reps)
         print(kind, N, prec, {f"{a}_{b}": v for (a, b), v in table.items()}, flush=True)
         plan.close()
+    if not args.add:
+        tune_batch(args.reps)
     out = args.out or os.path.join(HERE, f"{arch_name()}.json")
     F.tune_save(out)
     print("wrote", out)

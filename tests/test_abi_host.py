@@ -136,6 +136,23 @@ def test_double_double_plans(F):
             F.Plan(*args, "dd", **kw)
 
 
+def test_batch_entry_points_validate_on_the_host(F):
+    """Argument checks of the batched calls that need no device: an empty
+    batch is a no-op, a bad repetition count and missing arrays are EINVAL."""
+    lib = F.lib()
+    assert F.STATUS[lib.fsa_apply_batched(0, None, None, None, None, 0, None)] == "FSA_OK"
+    assert F.STATUS[lib.fsa_autotune_batched(0, None, None, None, None, 0, None, 5)] == "FSA_OK"
+    st = lib.fsa_autotune_batched(0, None, None, None, None, 0, None, 0)
+    assert F.STATUS[st] == "FSA_EINVAL" and b"reps" in lib.fsa_last_error()
+    p = F.Plan("log2d", (8, 8), (32, 32))
+    arr = (ctypes.c_void_p * 1)(p.handle)
+    for fn, extra in ((lib.fsa_apply_batched, ()), (lib.fsa_autotune_batched, (5,))):
+        st = fn(1, arr, None, None, None, 0, None, *extra)
+        assert F.STATUS[st] == "FSA_EINVAL" and b"null array" in lib.fsa_last_error()
+    st = lib.fsa_autotune_batched(-1, arr, None, None, None, 0, None, 5)
+    assert F.STATUS[st] == "FSA_EINVAL"
+
+
 def test_apply_before_build_is_a_state_error(F):
     p = F.Plan("coulomb3d", (8, 8, 8), (16, 16, 16))
     st = F.lib().fsa_apply(p.handle, ctypes.c_void_p(256), ctypes.c_void_p(256),

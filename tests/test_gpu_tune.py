@@ -118,6 +118,41 @@ def test_autotune_keeps_parity_and_batch_bitwise(F, prec, tmp_path):
     assert F.tune_get_slabs(prec, N)[0] == slabs
 
 
+def test_autotune_batched_tunes_the_batch_size_classes(F):
+    """fsa_autotune_batched stores a choice for every launch of the batch
+    among the batched entries, under the launch's own size class (many
+    problems' transforms together), and leaves the single-evaluation entries
+    alone; the tuned batch matches the oracle and its replays are bitwise
+    equal to the outputs the tuner left."""
+    shapes = [((10.0, 6.0), (256, 512)), ((12.0, 8.0), (1024, 256)), ((8.0, 8.0), (512, 512))]
+    cases = [shapes[i % 3] for i in range(9)]
+    plans = [F.Plan("log2d", L, N, "f32").build() for L, N in cases]
+    rhos = [torch.from_numpy(density(L, N, 20 + i)).float().cuda()
+            for i, (L, N) in enumerate(cases)]
+    ws = torch.empty(F.batch_workspace_bytes(plans) + 256, dtype=torch.uint8, device="cuda")
+    tuned = F.autotune_batched(plans, rhos, workspace=ws, reps=2)
+    torch.cuda.synchronize()
+    groups = {}
+    for _, (N0, N1) in cases:
+        for key, lines in ((("r2c", N1), N0), (("conv", 2 * N0), N1 + 1), (("c2r", N1), N0)):
+            groups[key] = groups.get(key, 0) + lines
+    for (name, n), lines in groups.items():
+        v, occ, us = F.tune_get("f32", "batched_" + name, n, lines)
+        assert v in F.tune_variants("f32", name, n) and us > 0.0, (name, n, lines)
+        # the single-evaluation entries are left alone
+        assert F.tune_get("f32", name, n, lines) == (0, 0, 0.0)
+    for i in (0, 1, 2):
+        L, N = cases[i]
+        ref = O.solve("log2d", L, N, rhos[i].double().cpu().numpy(), eps=plans[i].eps)
+        err = rel_l2(tuned[i].double().cpu().numpy(), ref)
+        print(f"tuned batch problem {i} {N}: rel L2 {err:.3e}")
+        assert err <= TOL["f32"]
+    again = F.apply_batched(plans, rhos, workspace=ws)
+    torch.cuda.synchronize()
+    for a, b in zip(tuned, again):
+        assert torch.equal(a, b)
+
+
 def test_batch_recaptures_after_a_table_change(F):
     plan = F.Plan("log2d", (8.0, 8.0), (128, 256), "f32").build()
     rho = torch.from_numpy(density((8.0, 8.0), (128, 256), 9)).float().cuda()

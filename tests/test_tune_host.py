@@ -122,6 +122,32 @@ def test_entries_are_kept_per_size_class():
     assert F.tune_get("f32", "conv", 1024, 257)[:2] == (0, 0)     # other length: default
 
 
+def test_batched_entries_are_kept_apart(tmp_path):
+    """Entries of the batched launches (FSA_PASS_BATCHED) do not change the
+    single-evaluation choices; a batched launch without a batched entry of
+    its (precision, pass, length) takes the single-evaluation entry; both
+    kinds survive a save / load."""
+    F.tune_reset()
+    F.tune_set("f32", "r2c", 256, 0, 0, lines=65536)
+    F.tune_set("f32", "batched_r2c", 256, 1, 2, lines=70400)   # same size class
+    assert F.tune_get("f32", "r2c", 256, 65536) == (0, 0, 0.0)
+    assert F.tune_get("f32", "batched_r2c", 256, 70400)[:2] == (1, 2)
+    F.tune_set("f32", "conv", 2048, 2, 0, lines=1025)
+    assert F.tune_get("f32", "batched_conv", 2048, 73842)[:2] == (2, 0)   # fallback
+    with pytest.raises(F.FsaError, match="EINVAL"):
+        F.tune_set("f32", "batched_conv", 64, 1)    # same variant rules as the pass
+    assert F.tune_variants("f32", "batched_conv", 512) == F.tune_variants("f32", "conv", 512)
+    path = tmp_path / "tune.json"
+    F.tune_save(str(path))
+    names = sorted(e["pass"] for e in json.loads(path.read_text())["entries"])
+    assert names == ["batched_r2c", "conv", "r2c"]
+    F.tune_reset()
+    F.tune_load(str(path))
+    assert F.tune_get("f32", "batched_r2c", 256, 70400)[:2] == (1, 2)
+    assert F.tune_get("f32", "r2c", 256, 65536)[:2] == (0, 0)
+    F.tune_reset()
+
+
 def test_load_survives_mangled_files(tmp_path):
     """Random damage to a valid table file (deleted, duplicated, swapped or
     replaced bytes) either loads or is rejected with FSA_EINVAL; the parser
