@@ -284,6 +284,15 @@ struct Fft {
     static constexpr int first_radix() { return radix(0); }
     static constexpr int last_radix() { return radix(S - 1); }
     static constexpr int first_nbt() { return nbt(0); }
+
+    // Input index of first-stage operand q of thread tid's butterfly b, or -1
+    // where that butterfly does not exist: when NB is not a multiple of T the
+    // last butterfly slot of some threads lies beyond NB, and its operand
+    // "indices" would run past the end of the line.  For q < R/2 every index
+    // is below P/2, the non-zero half of a zero-padded input.
+    FSA_HD static constexpr int first_index(int tid, int b, int q) {
+        return ((nb(0) % T) != 0 && tid + b * T >= nb(0)) ? -1 : tid + b * T + q * nb(0);
+    }
     static constexpr int last_nbt() { return nbt(S - 1); }
 
     // twiddle + butterfly of stage s on the registers

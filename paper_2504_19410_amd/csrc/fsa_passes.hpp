@@ -169,9 +169,11 @@ __global__ __launch_bounds__((R2c<R, M, VAR>::THREADS)) void k_r2c(
 #pragma unroll
             for (int b = 0; b < K::NBT0; ++b)
 #pragma unroll
-                for (int q = 0; q < K::HALF; ++q)
-                    pf[b * K::HALF + q] =
-                        *reinterpret_cast<const C*>(row + 2 * (tid + b * K::T + q * K::NB0));
+                for (int q = 0; q < K::HALF; ++q) {
+                    const int i = F::first_index(tid, b, q);
+                    if (i >= 0) pf[b * K::HALF + q] = *reinterpret_cast<const C*>(row + 2 * i);
+                    else pf[b * K::HALF + q] = mk(R(0), R(0));
+                }
         }
     };
     if (ch.first < ch.last) prefetch(ch.first);
@@ -386,8 +388,10 @@ __global__ __launch_bounds__((FwdT<R, P, VAR>::THREADS)) void k_fwd_t(
 #pragma unroll
             for (int b = 0; b < K::NBT0; ++b)
 #pragma unroll
-                for (int q = 0; q < K::HALF; ++q)
-                    pf[b * K::HALF + q] = in[tid + b * K::T + q * K::NB0];
+                for (int q = 0; q < K::HALF; ++q) {
+                    const int i = F::first_index(tid, b, q);
+                    pf[b * K::HALF + q] = i >= 0 ? in[i] : mk(R(0), R(0));
+                }
         }
     };
     if (ch.first < ch.last) prefetch(ch.first);
@@ -590,7 +594,10 @@ __global__ __launch_bounds__((Conv<R, P, VAR>::THREADS)) void k_conv(
 #pragma unroll
             for (int b = 0; b < K::NBT0; ++b)
 #pragma unroll
-                for (int q = 0; q < K::HALF; ++q) pf[b * K::HALF + q] = pen[tid + b * K::T + q * K::NB0];
+                for (int q = 0; q < K::HALF; ++q) {
+                    const int i = Ff::first_index(tid, b, q);
+                    pf[b * K::HALF + q] = i >= 0 ? pen[i] : mk(R(0), R(0));
+                }
         }
     };
     prefetch(first);

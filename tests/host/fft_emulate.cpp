@@ -128,6 +128,28 @@ static int check() {
             ++fails;
         }
     }
+    // the pass kernels prefetch the non-zero half of a padded line straight
+    // from global memory at first_index: every index must lie in [0, P/2)
+    // (an index beyond it reads past the line, and past the buffer on its last
+    // line) and each must be read exactly once
+    {
+        std::vector<int> hits(P / 2, 0);
+        int bad = 0;
+        for (int t = 0; t < Ff::T; ++t)
+            for (int b = 0; b < Ff::first_nbt(); ++b)
+                for (int q = 0; q < Ff::first_radix() / 2; ++q) {
+                    const int i = Ff::first_index(t, b, q);
+                    if (i < 0) continue;
+                    if (i >= P / 2) ++bad;
+                    else ++hits[i];
+                }
+        for (int h : hits) bad += h != 1;
+        if (bad) {
+            std::printf("FAIL P=%d alt=%d %s prefetch indices (%d bad)\n", P, ALT,
+                        sizeof(R) == 4 ? "f32" : "f64", bad);
+            ++fails;
+        }
+    }
     // forward (half-zero input) -> in-register product -> inverse, keep P/2 outputs
     {
         static C v[Ff::T][Ff::V];

@@ -9,6 +9,7 @@ import pytest
 import torch
 
 from oracle import oracle as O
+from oracle import reference as R
 from paper_2504_19410_amd import synth
 
 pytestmark = pytest.mark.gpu
@@ -223,6 +224,28 @@ def test_parity_largest_lengths(F, kind, L, N, prec):
     err = rel_l2(phi, _LARGEST_REF[key])                               # rho is ~1e-7)
     print(f"{kind} {N} {prec}: rel L2 {err:.3e}")
     assert err <= TOL[prec]
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_table3_workload_192(F, golden, prec):
+    """Table 3's timing workload: 3D Coulomb at 192^3 on [-12,12]^3 (h = 1/8),
+    eps = 0.4, the Case II density (a Laplacian-of-Gaussian pair, sigma^2 =
+    0.8, x0 = (1,1,0)) whose potential is Phi0.  Pass A runs length-192 rows,
+    whose first radix-8 stage has 24 butterflies over 16 threads (the
+    prefetch must skip the missing ones, or the last row reads past rho).
+    FP64 reaches round-off against Phi0, as the paper's row does
+    (3.3394e-16); FP32 its own round-off."""
+    g = golden["fsa_timing_192"]
+    n = g["N"]
+    L, N, sigma, x0 = (12.0,) * 3, (n,) * 3, np.sqrt(0.8), (1.0, 1.0, 0.0)
+    rho = synth.case2_density(L, N, sigma, (1.0, 1.0, 1.0), x0=x0)
+    plan = F.Plan("coulomb3d", L, N, prec, eps=0.4).build()
+    phi = plan.apply(torch.from_numpy(rho).to(F.DTYPES[prec]).cuda())
+    torch.cuda.synchronize()
+    ex = R.case2_phi0(L, N, sigma, (1.0, 1.0, 1.0), x0=x0)
+    err = R.rel_max_err(phi.double().cpu().numpy(), ex)
+    print(f"Table 3 workload {prec}: rel max err {err:.3e} (paper, FP64: {g['err']:.4e})")
+    assert err <= (2e-15 if prec == "f64" else 2e-6)
 
 
 def test_rejects_lengths_beyond_the_maximum(F):
