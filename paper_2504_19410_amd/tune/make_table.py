@@ -10,7 +10,8 @@ With --add, the shipped table is loaded first and only the extra 2D shapes
 (FP64 log-kernel batch shapes, 2048^2 and 1024^2 grids) are tuned into it.
 The batched launches of the 256-density 2D log-kernel batch are tuned last
 (fsa_autotune_batched, entries kept apart from the single-evaluation ones);
-with --batch, the shipped table is loaded and only they are tuned.
+with --batch, the shipped table is loaded and only they are tuned; with
+--table3, only the 192^3 grid of the paper's timing workload.
 """
 import argparse
 import os
@@ -31,6 +32,12 @@ SHAPES_3D = [
     ("coulomb3d", (1.0, 1.0, 8.0), (64, 64, 512), None),
     ("coulomb3d", (8.0, 8.0, 2.0), (256, 256, 64), None),
     ("coulomb3d", (2.0, 2.0, 8.0), (64, 64, 256), None),
+]
+
+
+# the paper's timing workload (Table 3): 192^3 on [-12,12]^3, eps = 0.4
+SHAPES_TABLE3 = [
+    ("coulomb3d", (12.0, 12.0, 12.0), (192, 192, 192), None),
 ]
 
 
@@ -72,15 +79,19 @@ def main():
                     help="tune only the extra 2D shapes into the shipped table")
     ap.add_argument("--batch", action="store_true",
                     help="tune only the batched launches into the shipped table")
+    ap.add_argument("--table3", action="store_true",
+                    help="tune only the 192^3 grid of Table 3 into the shipped table")
     args = ap.parse_args()
+    table3 = [(k, L, N, lam, prec) for k, L, N, lam in SHAPES_TABLE3 for prec in ("f32", "f64")]
     extra = [(k, L, N, lam, prec) for k, L, N, lam in SHAPES_2D_EXTRA for prec in ("f32", "f64")]
     extra += [("log2d", (8.0, 8.0), N, None, "f64") for N in synth.LOG2D_SHAPES]
-    if args.add or args.batch:
+    if args.add or args.batch or args.table3:
         F.tune_load(os.path.join(HERE, f"{arch_name()}.json"))
-        jobs = [] if args.batch else extra
+        jobs = table3 if args.table3 else [] if args.batch else extra
     else:
         F.tune_reset()
         jobs = [(k, L, N, lam, prec) for k, L, N, lam in SHAPES_3D for prec in ("f32", "f64")]
+        jobs += table3
         jobs += [("log2d", (8.0, 8.0), N, None, "f32") for N in synth.LOG2D_SHAPES]
         jobs += extra
     for kind, L, N, lam, prec in jobs:
@@ -89,7 +100,7 @@ def main():
         table = plan.autotune(rho, reps=args.reps)
         print(kind, N, prec, {f"{a}_{b}": v for (a, b), v in table.items()}, flush=True)
         plan.close()
-    if not args.add:
+    if not (args.add or args.table3):
         tune_batch(args.reps)
     out = args.out or os.path.join(HERE, f"{arch_name()}.json")
     F.tune_save(out)
