@@ -625,9 +625,13 @@ def bench_serve(F, torch, hip, synth, duration=3.0, rate=2000.0, budget=200 << 3
     }
 
 
-def cpu_baseline(synth):
+def cpu_baseline(synth, prob, rho64, phis):
     """The FP64 oracle on the host cores: one evaluation of the same Yukawa
-    workload at 128^3 (tensor build + FFT convolution)."""
+    workload at 128^3 (tensor build + FFT convolution).  Then the outputs of
+    the timed 256^3 evaluations (`phis`, per precision) against the oracle:
+    its own tensor for that grid and the direct sum of the discrete
+    convolution at 43 sampled points (40 seeded, the maximum, the first and
+    the last), on the density as each precision received it."""
     from oracle import oracle as O
     cores = O.set_threads(0)
     p = synth.yukawa_problem(1.0, 128, "f64")
@@ -638,7 +642,7 @@ def cpu_baseline(synth):
     O.conv_fft(T, rho)
     t2 = time.perf_counter()
     pts = 128 ** 3
-    return {
+    out = {
         "value": pts / (t2 - t1),
         "unit": "grid pts/s",
         "cores": cores,
@@ -650,6 +654,19 @@ def cpu_baseline(synth):
         "execution_s": t2 - t1,
         "cpu": platform.processor() or platform.machine(),
     }
+    T = O.build_tensor(prob.kernel, prob.L, prob.N, prob.eps, lam=prob.lam)
+    parity = {"points": None, "kind": "oracle tensor, direct sum at sampled points"}
+    for prec, phi in phis.items():
+        rho_used = rho64.astype(np.float32).astype(np.float64) if prec == "f32" else rho64
+        rng = np.random.default_rng(0)
+        idx = np.unique(np.concatenate([rng.choice(phi.size, 40, replace=False),
+                                        [int(np.argmax(np.abs(phi))), 0, phi.size - 1]]))
+        ref = O.conv_direct_points(T, rho_used, idx)
+        got = phi.ravel()[idx].astype(np.float64)
+        parity["points"] = int(idx.size)
+        parity[prec] = {"rel_l2": float(np.linalg.norm(got - ref) / np.linalg.norm(ref)),
+                        "rel_max": float(np.abs(got - ref).max() / np.abs(ref).max())}
+    return out, parity
 
 
 def main():
@@ -737,7 +754,8 @@ def main():
         log(f"  {prec}: {res[prec]['ms_per_step']:.4f} ms/eval, "
             f"{res[prec]['value'] / 1e9:.2f} Gpts/s, passes {res[prec]['pass_ms']}")
     diff = float(np.linalg.norm(phis["f32"] - phis["f64"]) / np.linalg.norm(phis["f64"]))
-    del phis
+    if args.no_cpu:
+        del phis
     sweep = precomp_sweep(F, torch, hip, n=args.n)
     log(f"  precomp vs anisotropy (ms): {sweep['ms_by_anisotropy']}")
     ddi = None
@@ -774,11 +792,13 @@ def main():
                                   budget=2 << 30, per_call=False)
         log(f"  burst server p50/p99 {serve_burst['server']['p50_ms']:.3f}/"
             f"{serve_burst['server']['p99_ms']:.3f} ms")
-    cpu = None
+    cpu = parity = None
     if not args.no_cpu:
         log("cpu baseline (oracle) ...")
-        cpu = cpu_baseline(synth)
+        cpu, parity = cpu_baseline(synth, prob, rho64, phis)
+        del phis
         log(f"  oracle: {cpu['value'] / 1e6:.3f} Mpts/s on {cpu['cores']} threads")
+        log(f"  timed outputs against the oracle: {parity}")
     r32, r64 = res["f32"], res["f64"]
     line = {
         "metric": METRIC,
@@ -801,6 +821,7 @@ def main():
         },
         "roofline": r32["roofline"],
         "cpu_baseline": cpu,
+        "oracle_parity": parity,
         "fp64": {"value": r64["value"], "ms_per_step": r64["ms_per_step"],
                  "roofline": r64["roofline"], "pass_ms": r64["pass_ms"],
                  "model_hbm_frac": r64["model_hbm_frac"], "precomp_ms": r64["precomp_ms"],
