@@ -16,7 +16,7 @@
 //           crop folded into the loads and stores.
 // Unlike the FP32/FP64 path it keeps the whole complex padded spectrum
 // (prod P_j values of 32 bytes) and transforms one line per workgroup with a
-// radix-2 FFT in LDS: this mode is about accuracy, not bandwidth.
+// radix-4 FFT in LDS: this mode is about accuracy, not bandwidth.
 // Arrays of reals are interleaved (hi, lo) pairs; complex values are
 // (re.hi, re.lo, im.hi, im.lo).
 #include <hip/hip_runtime.h>
@@ -41,6 +41,8 @@ __device__ __forceinline__ cdd cconj(cdd a) { return cdd{a.re, -a.im}; }
 
 constexpr int kDDThreads = 256;
 constexpr int kDDMaxP = 2048;
+// threads per line: one per radix-4 butterfly, at most kDDThreads
+constexpr int dd_threads(int P) { return P / 4 < 1 ? 1 : P / 4 < kDDThreads ? P / 4 : kDDThreads; }
 
 // tw[m] = exp(-2 pi i m / P), m < P/2
 __global__ void k_dd_twiddle(cdd* __restrict__ tw, int P) {
@@ -128,22 +130,47 @@ __global__ void k_dd_finalize(const dd* __restrict__ dct, dd* __restrict__ out, 
 }
 
 // ---------------------------------------------------------------------------
-// Evaluation: one line per workgroup, radix-2 FFT in LDS.
+// Evaluation: one line per workgroup, radix-4 steps in LDS.
 // ---------------------------------------------------------------------------
 
-// In-place radix-2 decimation in time on x[0, P) (bit-reversed order in,
-// natural order out); tw[m] = exp(-2 pi i m / P).
+// In-place decimation in time on x[0, P) (bit-reversed order in, natural
+// order out); tw[m] = exp(-2 pi i m / P), m < P/2.  The radix-2 stages run in
+// pairs (len/2, len) as one radix-4 step per group of four points, with one
+// exchange through LDS per pair, after a leading radix-2 stage when log2 P is
+// odd: points i0, i0 + q, i0 + 2q, i0 + 3q (q = len/4, j = i0 mod len < q)
+// take the len/2 stage's twiddle w_len^(2j) on the odd points of each half,
+// then the len stage's w_len^j on the second half, times -i (forward) or +i
+// (inverse) for the upper pair.
 template <bool INV>
 __device__ void dd_fft_lds(cdd* x, int P, int logP, const cdd* __restrict__ tw) {
-    for (int len = 2, lg = 1; len <= P; len <<= 1, ++lg) {
-        const int half = len >> 1, step = P >> lg;
+    int len = 4;
+    if (logP & 1) {
         for (int b = threadIdx.x; b < P / 2; b += blockDim.x) {
-            const int grp = b / half, j = b - grp * half;
-            const int i0 = grp * len + j, i1 = i0 + half;
-            const cdd w = INV ? cconj(tw[j * step]) : tw[j * step];
-            const cdd u = x[i0], v = cmul(x[i1], w);
-            x[i0] = cadd(u, v);
-            x[i1] = csub(u, v);
+            const cdd u = x[2 * b], v = x[2 * b + 1];
+            x[2 * b] = cadd(u, v);
+            x[2 * b + 1] = csub(u, v);
+        }
+        __syncthreads();
+        len = 8;
+    }
+    for (; len <= P; len <<= 2) {
+        const int q = len >> 2, step = P / len;
+        for (int b = threadIdx.x; b < P / 4; b += blockDim.x) {
+            const int g = b / q, j = b - g * q;
+            const int i0 = g * len + j;
+            const cdd w2 = INV ? cconj(tw[2 * j * step]) : tw[2 * j * step];
+            const cdd wa = INV ? cconj(tw[j * step]) : tw[j * step];
+            const cdd a0 = x[i0], a1 = cmul(x[i0 + q], w2);
+            const cdd a2 = x[i0 + 2 * q], a3 = cmul(x[i0 + 3 * q], w2);
+            const cdd b0 = cadd(a0, a1), b1 = csub(a0, a1);
+            const cdd b2 = cadd(a2, a3), b3 = csub(a2, a3);
+            const cdd t2 = cmul(b2, wa);
+            const cdd u3 = cmul(b3, wa);
+            const cdd t3 = INV ? cdd{-u3.im, u3.re} : cdd{u3.im, -u3.re};
+            x[i0] = cadd(b0, t2);
+            x[i0 + 2 * q] = csub(b0, t2);
+            x[i0 + q] = cadd(b1, t3);
+            x[i0 + 3 * q] = csub(b1, t3);
         }
         __syncthreads();
     }
@@ -237,7 +264,7 @@ __global__ __launch_bounds__(kDDThreads) void k_dd_pass(const void* __restrict__
         // inverse: every product is formed before any is written back (at
         // most P / blockDim <= 8 per thread)
         // (fixed trip counts keep the array in registers)
-        constexpr int kKeep = kDDMaxP / kDDThreads;  // P / blockDim (blockDim = min(P/2, 256))
+        constexpr int kKeep = kDDMaxP / kDDThreads;  // P / blockDim (blockDim = min(P/4, 256))
         static_assert(kDDMaxP / kDDThreads <= kKeep, "keep array too small");
         cdd keep[kKeep];
 #pragma unroll
@@ -316,7 +343,7 @@ hipError_t build_tensor_dd(const fsa_plan_s* pl, hipStream_t st) {
         for (int ax = 0; ax < pl->d; ++ax) {
             const int P = 2 * g.N[ax];
             const long lines = n / (g.N[ax] + 1);
-            const int threads = P / 2 < kDDThreads ? P / 2 : kDDThreads;
+            const int threads = dd_threads(P);
             hipLaunchKernelGGL(k_dd_dct, dim3((unsigned)lines), dim3(threads),
                                sizeof(cdd) * (size_t)P, st, (const dd*)src, dst, g, ax,
                                dd_tw(pl, ax));
@@ -433,7 +460,7 @@ hipError_t launch_dd_step(const fsa_plan_s* pl, int k, const void* rho, void* ph
         }
     }
     if (Pa > kDDMaxP || lines <= 0 || lines > 0x7fffffffL) return hipErrorInvalidValue;
-    const int threads = Pa / 2 < kDDThreads ? Pa / 2 : kDDThreads;
+    const int threads = dd_threads(Pa);
     const size_t lds = sizeof(cdd) * (size_t)Pa;
     const cdd* tw = dd_tw(pl, ax);
     const void* src = mode == DD_FWD_REAL ? rho : (const void*)X;
