@@ -153,6 +153,28 @@ def test_autotune_batched_tunes_the_batch_size_classes(F):
         assert torch.equal(a, b)
 
 
+def test_autotune_batched_mixed_kinds_and_precisions(F):
+    """A batch of 3D and 2D problems in both precisions: the fused pass of the
+    3D problems takes its input from pass B, which the tuner re-runs before
+    each timed candidate; every tuned output still matches the oracle."""
+    cases = [("coulomb3d", (6.0, 8.0, 8.0), (32, 64, 128), "f32", None),
+             ("yukawa3d", (8.0, 8.0, 4.0), (64, 32, 32), "f64", 0.8),
+             ("log2d", (10.0, 6.0), (256, 512), "f64", None),
+             ("coulomb3d", (8.0, 8.0, 8.0), (32, 32, 32), "f32", None)]
+    plans = [F.Plan(k, L, N, pr, lam=lam).build() for k, L, N, pr, lam in cases]
+    rhos = [torch.from_numpy(density(L, N, 40 + i)).to(F.DTYPES[pr]).cuda()
+            for i, (k, L, N, pr, lam) in enumerate(cases)]
+    outs = F.autotune_batched(plans, rhos, reps=2)
+    torch.cuda.synchronize()
+    for (k, L, N, pr, lam), pl, r, o in zip(cases, plans, rhos, outs):
+        ref = O.solve(k, L, N, r.double().cpu().numpy(), eps=pl.eps, lam=lam or 0.0)
+        err = rel_l2(o.double().cpu().numpy(), ref)
+        print(f"tuned mixed batch {k} {N} {pr}: rel L2 {err:.3e}")
+        assert err <= TOL[pr]
+    # e.g. the 2D FP64 problem's fused pass (length 512 over 513 pencils)
+    assert F.tune_get("f64", "batched_conv", 512, 513)[2] > 0.0
+
+
 def test_batch_recaptures_after_a_table_change(F):
     plan = F.Plan("log2d", (8.0, 8.0), (128, 256), "f32").build()
     rho = torch.from_numpy(density((8.0, 8.0), (128, 256), 9)).float().cuda()
