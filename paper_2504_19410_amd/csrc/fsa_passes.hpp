@@ -71,20 +71,21 @@ __device__ __forceinline__ void sync_wg_lds() {
 // The lane index, made opaque to the optimiser.  The transforms' LDS and
 // twiddle addresses depend only on it, so the compiler hoists all of them out
 // of a kernel's work loop and keeps them live for the whole loop.  Where their
-// strides do not fold into immediate offsets (lengths 3 * 2^a) and the
-// operands are FP64, that overflows the register file (one wave per SIMD,
-// AGPR spills); there each work item takes a fresh copy of the lane index
-// and recomputes its addresses, at a few VALU instructions per item.
-// Measured on 192^3 and 384^3 FP64 grids: 654 -> 526 us and 6.1 -> 4.2 ms per
-// evaluation.  Elsewhere the addresses fit and the recomputation only costs
-// (FP32 and power-of-two lengths are left as they are).
+// strides do not fold into immediate offsets (lengths 3 * 2^a) and there are
+// many of them (FP64 operands, or FP32 from length 768), that overflows the
+// register file (one wave per SIMD, AGPR spills); there each work item takes
+// a fresh copy of the lane index and recomputes its addresses, at a few VALU
+// instructions per item.  Measured per evaluation: 192^3 FP64 654 -> 526 us,
+// 384^3 FP64 6.1 -> 4.2 ms, 384^3 FP32 3.46 -> 2.77 ms.  Elsewhere the
+// addresses fit and the recomputation only costs (power-of-two lengths, and
+// FP32 below 768: 192^3 FP32 263 -> 289 us, 256^3 FP32 +6%).
 __device__ __forceinline__ int opaque(int x) {
     asm volatile("" : "+v"(x));
     return x;
 }
 template <typename R, int P>
 constexpr bool fresh_lane() {
-    return sizeof(R) == 8 && (P & (P - 1)) != 0;
+    return (P & (P - 1)) != 0 && (sizeof(R) == 8 || P >= 768);
 }
 
 // Contiguous chunk of work items for this workgroup (uniform over the group).
