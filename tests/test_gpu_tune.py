@@ -83,6 +83,46 @@ def test_every_variant_matches_the_oracle(F, kind, L, N, prec):
     assert len(tried) >= 4   # the shapes above exercise non-default variants
 
 
+# every grid length the passes support (2^a and 3 * 2^a, 8 ... 2048): as the
+# long axis of a 2D grid it sets the fused pass's length 2N (axis 0) or the
+# real passes' length N (axis 1); the short axis (12) leaves a partial tile
+LENGTHS = [8, 12, 16, 24, 32, 48, 64, 96, 128, 192, 256, 384, 512, 768, 1024, 1536, 2048]
+
+
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+@pytest.mark.parametrize("axis", [0, 1, "3d"])
+@pytest.mark.parametrize("n", LENGTHS)
+def test_every_length_and_variant_matches_the_oracle(F, n, axis, prec):
+    """Every supported transform length, in every compiled launch variant, at
+    full and reduced occupancy: the lengths 3 * 2^a whose first stage leaves
+    some lanes without a butterfly, the tile edges of the transposing passes
+    (a short axis of 12: not a multiple of the tile widths), and the longest
+    rows and pencils.  axis "3d": a 3D grid (8, n, 12) whose axis 1 sets the
+    transposing passes B and D to length 2n."""
+    kind = "coulomb3d" if axis == "3d" else "log2d"
+    N = (8, n, 12) if axis == "3d" else (n, 12) if axis == 0 else (12, n)
+    L = tuple(0.25 * m for m in N)   # h = 1/2 on every axis
+    plan = F.Plan(kind, L, N, prec, eps=1.0).build()
+    rho = torch.from_numpy(density(L, N, 3 * n + len(N))).to(F.DTYPES[prec]).cuda()
+    ref = O.solve(kind, L, N, rho.double().cpu().numpy(), eps=plan.eps)
+    seen = set()
+    for var in (0, 1, 2):
+        for occ in (0, 1):
+            F.tune_reset()
+            used = []
+            for name, m in plan.passes():
+                v = var if var in F.tune_variants(prec, name, m) else 0
+                F.tune_set(prec, name, m, v, occ)
+                used.append(v)
+            if (tuple(used), occ) in seen:
+                continue
+            seen.add((tuple(used), occ))
+            phi = plan.apply(rho)
+            torch.cuda.synchronize()
+            err = rel_l2(phi.double().cpu().numpy(), ref)
+            assert err <= TOL[prec], (N, used, occ, err)
+
+
 @pytest.mark.parametrize("prec", ["f32", "f64"])
 def test_autotune_keeps_parity_and_batch_bitwise(F, prec, tmp_path):
     kind, L, N = "coulomb3d", (6.0, 8.0, 8.0), (32, 64, 128)
