@@ -99,3 +99,40 @@ def test_batch_rejects_unbuilt_and_small_workspace(F):
     with pytest.raises(F.FsaError, match="EINVAL"):
         ws = torch.empty(1024, dtype=torch.uint8, device="cuda")
         F.apply_batched([a], [r], workspace=ws)
+
+
+LENGTHS = [8, 12, 16, 24, 32, 48, 64, 96, 128, 192, 256, 384, 512, 768, 1024, 1536, 2048]
+
+
+def test_batch_every_length_equals_solo_bitwise(F):
+    """One batch holding every supported grid length on each pass kind (2D
+    grids (n, 12) and (12, n) in FP32, 3D grids (8, n, 12) in FP64): each
+    launch's job table and item prefix cover problems of one length whose
+    short axes leave partial tiles; under the same launch choices every
+    result equals the problem evaluated alone, bit for bit."""
+    F.tune_reset()
+    specs = []
+    for n in LENGTHS:
+        specs.append(("log2d", (0.25 * n, 3.0), (n, 12), "f32", None))
+        specs.append(("log2d", (3.0, 0.25 * n), (12, n), "f32", None))
+        specs.append(("coulomb3d", (2.0, 0.25 * n, 3.0), (8, n, 12), "f64", None))
+    plans, rhos = [], []
+    for i, (kind, L, N, prec, lam) in enumerate(specs):
+        plan = F.Plan(kind, L, N, prec, eps=1.0).build()
+        rng = synth.SplitMix64(700 + i)
+        gs = synth.draw_gaussians(rng, len(N), 2, [-l / 4 for l in L], [l / 4 for l in L],
+                                  [l / 5 for l in L], [l / 3 for l in L], isotropic=False)
+        plans.append(plan)
+        rhos.append(torch.from_numpy(synth.eval_gaussians(gs, L, N)).to(F.DTYPES[prec]).cuda())
+    solo = [p.apply(r) for p, r in zip(plans, rhos)]
+    outs = F.apply_batched(plans, rhos)
+    torch.cuda.synchronize()
+    for i, (a, b) in enumerate(zip(solo, outs)):
+        assert torch.equal(a, b), specs[i]
+    # and one of each kind against the oracle
+    for i in (len(specs) - 3, len(specs) - 1):
+        kind, L, N, prec, lam = specs[i]
+        ref = O.solve(kind, L, N, rhos[i].double().cpu().numpy(), eps=1.0)
+        got = outs[i].double().cpu().numpy()
+        err = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
+        assert err <= (5e-6 if prec == "f32" else 1e-12), (specs[i], err)
