@@ -310,6 +310,36 @@ def _time_apply(plan, rho, torch, hip, steps=20, warmup=5):
     return ms
 
 
+def bench_aniso(F, torch, hip, synth, steps=20):
+    """The anisotropic cigar and pancake densities (Sec. 1, Fig. 1): 3D
+    Coulomb at h = 1/16 on every axis, pancake 256x256x64 on [-8,8]^2 x [-2,2]
+    (rho = exp(-(x^2 + y^2) - gamma^2 z^2)) and cigar 64x64x256 on
+    [-2,2]^2 x [-8,8] (rho = exp(-gamma^2 (x^2 + y^2) - z^2)), eps = R0/8 =
+    0.5, gamma in {4, 16}.  FP32 and FP64 evaluation times (they do not depend
+    on gamma) and the outputs, for the error check against the exact potential
+    in the oracle leg."""
+    out, phis = {}, {}
+    for orient in ("pancake", "cigar"):
+        row = {}
+        for prec in ("f32", "f64"):
+            p4 = synth.anisotropic_coulomb(orient, 4.0, prec)
+            plan = F.Plan(p4.kernel, p4.L, p4.N, prec).build()
+            for gamma in (4.0, 16.0):
+                p = synth.anisotropic_coulomb(orient, gamma, prec)
+                rho = torch.from_numpy(synth.eval_gaussians(p.gaussians, p.L, p.N)).to(
+                    F.DTYPES[prec]).cuda()
+                if gamma == 4.0:
+                    ms = _time_apply(plan, rho, torch, hip, steps=steps)
+                    pts = p.N[0] * p.N[1] * p.N[2]
+                    mb = sum(model_bytes(p.N, prec).values())
+                    row[prec] = {"ms_per_step": round(ms, 4), "value": pts / (ms * 1e-3),
+                                 "model_hbm_frac": mb / (ms * 1e-3) / 8e12}
+                phis[(orient, gamma, prec)] = (p, plan.apply(rho).double().cpu().numpy())
+            plan.close()
+        out[orient] = {"grid": list(p4.N), "box": list(p4.L), **row}
+    return out, phis
+
+
 def bench_table3(F, torch, hip, synth):
     """The paper's timing workload (Table 3, Sec. 5.1 Example 2): 3D Coulomb
     on [-12,12]^3 at h = 1/8 (192^3), eps = 0.4, the Case II density
@@ -625,14 +655,17 @@ def bench_serve(F, torch, hip, synth, duration=3.0, rate=2000.0, budget=200 << 3
     }
 
 
-def cpu_baseline(synth, prob, rho64, phis):
+def cpu_baseline(synth, prob, rho64, phis, aniso_phis):
     """The FP64 oracle on the host cores: one evaluation of the same Yukawa
     workload at 128^3 (tensor build + FFT convolution).  Then the outputs of
     the timed 256^3 evaluations (`phis`, per precision) against the oracle:
     its own tensor for that grid and the direct sum of the discrete
     convolution at 43 sampled points (40 seeded, the maximum, the first and
-    the last), on the density as each precision received it."""
+    the last), on the density as each precision received it; and the cigar /
+    pancake outputs against the exact potential (1-D integral) at 40 seeded
+    points and the maximum."""
     from oracle import oracle as O
+    from oracle import reference as Rf
     cores = O.set_threads(0)
     p = synth.yukawa_problem(1.0, 128, "f64")
     rho = synth.eval_gaussians(p.gaussians, p.L, p.N)
@@ -666,6 +699,14 @@ def cpu_baseline(synth, prob, rho64, phis):
         parity["points"] = int(idx.size)
         parity[prec] = {"rel_l2": float(np.linalg.norm(got - ref) / np.linalg.norm(ref)),
                         "rel_max": float(np.abs(got - ref).max() / np.abs(ref).max())}
+    parity["aniso"] = {}
+    for key, (p, phi) in (aniso_phis or {}).items():
+        rng = np.random.default_rng(1)
+        idx = np.unique(np.append(rng.choice(phi.size, 40, replace=False),
+                                  int(np.argmax(np.abs(phi)))))
+        gs = [(g.amp, g.center, g.width) for g in p.gaussians]
+        ex = Rf.gaussian_sum_potential(p.kernel, gs, p.L, p.N, points=idx)
+        parity["aniso"][key] = float(np.abs(phi.ravel()[idx] - ex).max() / np.abs(ex).max())
     return out, parity
 
 
@@ -765,6 +806,8 @@ def main():
             f"FP64 {ddi['f64']['ms_per_step']:.4f} ms")
     table3 = bench_table3(F, torch, hip, synth)
     log(f"  Table 3 workload (192^3): {table3}")
+    aniso, aniso_phis = bench_aniso(F, torch, hip, synth)
+    log(f"  cigar / pancake: {aniso}")
     general = None
     if not args.no_general:
         general = bench_general(F, torch, hip, n=args.n)
@@ -795,7 +838,9 @@ def main():
     cpu = parity = None
     if not args.no_cpu:
         log("cpu baseline (oracle) ...")
-        cpu, parity = cpu_baseline(synth, prob, rho64, phis)
+        cpu, parity = cpu_baseline(synth, prob, rho64, phis, aniso_phis)
+        for (orient, gamma, prec), e in parity.pop("aniso").items():
+            aniso[orient].setdefault("rel_max_err_vs_exact", {})[f"{prec}_gamma{gamma:g}"] = e
         del phis
         log(f"  oracle: {cpu['value'] / 1e6:.3f} Mpts/s on {cpu['cores']} threads")
         log(f"  timed outputs against the oracle: {parity}")
@@ -847,6 +892,7 @@ def main():
         "paper_context": "FSA Execution 2.24 s / Precomp 2.84 s at 192^3 in FP64, FORTRAN on one "
                          "Xeon Gold 6248R 3.0 GHz (Table 3); other hardware, context only",
         "table3_workload": table3,
+        "cigar_pancake": aniso,
     }
     if args.save_tune:
         F.tune_save(args.save_tune)
