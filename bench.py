@@ -340,6 +340,29 @@ def bench_aniso(F, torch, hip, synth, steps=20):
     return out, phis
 
 
+def bench_yukawa_lambda(F, torch, hip, synth, steps=20):
+    """The Yukawa workload over its screening lengths: lambda in {0.5, 1, 4}
+    on [-8,8]^3 at 128^3 and 256^3, eps = 2, 8 seeded Gaussians, FP32 and FP64
+    (tensors built in FP64 on the GPU).  The evaluation time does not depend
+    on lambda (timed at 128^3; 256^3 is the headline line); the outputs go to
+    the oracle leg for the error against the exact potential."""
+    out, phis = {}, {}
+    for n in (128, 256):
+        for prec in ("f32", "f64"):
+            for lam in (0.5, 1.0, 4.0):
+                p = synth.yukawa_problem(lam, n, prec)
+                plan = F.Plan(p.kernel, p.L, p.N, prec, eps=p.eps, lam=p.lam).build()
+                rho = torch.from_numpy(synth.eval_gaussians(p.gaussians, p.L, p.N)).to(
+                    F.DTYPES[prec]).cuda()
+                if n == 128 and lam == 1.0:
+                    ms = _time_apply(plan, rho, torch, hip, steps=steps)
+                    out[f"{n}_{prec}"] = {"ms_per_step": round(ms, 4),
+                                          "value": n ** 3 / (ms * 1e-3)}
+                phis[(n, lam, prec)] = (p, plan.apply(rho).double().cpu().numpy())
+                plan.close()
+    return out, phis
+
+
 def bench_table3(F, torch, hip, synth):
     """The paper's timing workload (Table 3, Sec. 5.1 Example 2): 3D Coulomb
     on [-12,12]^3 at h = 1/8 (192^3), eps = 0.4, the Case II density
@@ -662,8 +685,8 @@ def cpu_baseline(synth, prob, rho64, phis, aniso_phis):
     its own tensor for that grid and the direct sum of the discrete
     convolution at 43 sampled points (40 seeded, the maximum, the first and
     the last), on the density as each precision received it; and the cigar /
-    pancake outputs against the exact potential (1-D integral) at 40 seeded
-    points and the maximum."""
+    pancake and Yukawa outputs against the exact potential (1-D integral or
+    closed form) at 40 seeded points and the maximum."""
     from oracle import oracle as O
     from oracle import reference as Rf
     cores = O.set_threads(0)
@@ -705,7 +728,7 @@ def cpu_baseline(synth, prob, rho64, phis, aniso_phis):
         idx = np.unique(np.append(rng.choice(phi.size, 40, replace=False),
                                   int(np.argmax(np.abs(phi)))))
         gs = [(g.amp, g.center, g.width) for g in p.gaussians]
-        ex = Rf.gaussian_sum_potential(p.kernel, gs, p.L, p.N, points=idx)
+        ex = Rf.gaussian_sum_potential(p.kernel, gs, p.L, p.N, lam=p.lam, points=idx)
         parity["aniso"][key] = float(np.abs(phi.ravel()[idx] - ex).max() / np.abs(ex).max())
     return out, parity
 
@@ -808,6 +831,12 @@ def main():
     log(f"  Table 3 workload (192^3): {table3}")
     aniso, aniso_phis = bench_aniso(F, torch, hip, synth)
     log(f"  cigar / pancake: {aniso}")
+    yuk, yuk_phis = bench_yukawa_lambda(F, torch, hip, synth)
+    log(f"  Yukawa over lambda: {yuk}")
+    aniso_phis.update({("yukawa",) + k: v for k, v in yuk_phis.items()})
+    del yuk_phis
+    if args.no_cpu:
+        aniso_phis = None  # only the oracle leg reads them
     general = None
     if not args.no_general:
         general = bench_general(F, torch, hip, n=args.n)
@@ -839,8 +868,13 @@ def main():
     if not args.no_cpu:
         log("cpu baseline (oracle) ...")
         cpu, parity = cpu_baseline(synth, prob, rho64, phis, aniso_phis)
-        for (orient, gamma, prec), e in parity.pop("aniso").items():
-            aniso[orient].setdefault("rel_max_err_vs_exact", {})[f"{prec}_gamma{gamma:g}"] = e
+        for key, e in parity.pop("aniso").items():
+            if key[0] == "yukawa":
+                _, n, lam, prec = key
+                yuk.setdefault("rel_max_err_vs_exact", {})[f"{n}_{prec}_lam{lam:g}"] = e
+            else:
+                orient, gamma, prec = key
+                aniso[orient].setdefault("rel_max_err_vs_exact", {})[f"{prec}_gamma{gamma:g}"] = e
         del phis
         log(f"  oracle: {cpu['value'] / 1e6:.3f} Mpts/s on {cpu['cores']} threads")
         log(f"  timed outputs against the oracle: {parity}")
@@ -893,6 +927,7 @@ def main():
                          "Xeon Gold 6248R 3.0 GHz (Table 3); other hardware, context only",
         "table3_workload": table3,
         "cigar_pancake": aniso,
+        "yukawa_lambda": yuk,
     }
     if args.save_tune:
         F.tune_save(args.save_tune)
