@@ -147,12 +147,76 @@ FSA_HD void dft16(cpx<R>* a) {
     }
 }
 
+// multiply by exp(-/+ 2 pi i k / 12) (forward / inverse)
+template <bool INV, int K, typename R>
+FSA_HD cpx<R> w12(cpx<R> a) {
+    constexpr int k = K % 12;
+    const R c = R(0.86602540378443864676372317075294);  // cos(pi/6)
+    const R h = R(0.5);
+    // (cos, sin) of 2 pi k / 12; the forward factor is cos - i sin
+    const R cs = k == 0 ? R(1) : k == 1 ? c : k == 2 ? h : k == 3 ? R(0) : k == 4 ? -h
+               : k == 5 ? -c : k == 6 ? R(-1) : k == 7 ? -c : k == 8 ? -h : k == 9 ? R(0)
+               : k == 10 ? h : c;
+    const R sn = k == 0 ? R(0) : k == 1 ? h : k == 2 ? c : k == 3 ? R(1) : k == 4 ? c
+               : k == 5 ? h : k == 6 ? R(0) : k == 7 ? -h : k == 8 ? -c : k == 9 ? R(-1)
+               : k == 10 ? -c : -h;
+    if constexpr (k == 0) return a;
+    else if constexpr (k == 3 || k == 9) return (k == 3) == !INV ? rot90<false>(a) : rot90<true>(a);
+    else if constexpr (k == 6) return mk(-a.x, -a.y);
+    else {
+        const R s = INV ? sn : -sn;  // w = cs + i s
+        return mk(a.x * cs - a.y * s, a.x * s + a.y * cs);
+    }
+}
+
+// length 6 = 2 x 3: DFT3 of the even and the odd points, combined with w6^k
+template <bool INV, typename R>
+FSA_HD void dft6(cpx<R>* a) {
+    cpx<R> e[3] = {a[0], a[2], a[4]};
+    cpx<R> o[3] = {a[1], a[3], a[5]};
+    dft3<INV>(e);
+    dft3<INV>(o);
+    o[1] = w12<INV, 2>(o[1]);
+    o[2] = w12<INV, 4>(o[2]);
+    for (int q = 0; q < 3; ++q) {
+        a[q] = e[q] + o[q];
+        a[q + 3] = e[q] - o[q];
+    }
+}
+
+// length 12 = 3 x 4: DFT4 of the points r, r + 3, r + 6, r + 9 (r < 3), then
+// for each k1 < 4 the DFT3 over r of w12^(r k1) D_r[k1] gives y[k1 + 4 k2]
+template <bool INV, typename R>
+FSA_HD void dft12(cpx<R>* a) {
+    cpx<R> d[3][4];
+    for (int r = 0; r < 3; ++r) {
+        for (int m = 0; m < 4; ++m) d[r][m] = a[r + 3 * m];
+        dft4<INV>(d[r]);
+    }
+    cpx<R> u[4][3];
+    for (int k1 = 0; k1 < 4; ++k1) u[k1][0] = d[0][k1];
+    u[0][1] = d[1][0];
+    u[1][1] = w12<INV, 1>(d[1][1]);
+    u[2][1] = w12<INV, 2>(d[1][2]);
+    u[3][1] = w12<INV, 3>(d[1][3]);
+    u[0][2] = d[2][0];
+    u[1][2] = w12<INV, 2>(d[2][1]);
+    u[2][2] = w12<INV, 4>(d[2][2]);
+    u[3][2] = w12<INV, 6>(d[2][3]);
+    for (int k1 = 0; k1 < 4; ++k1) {
+        dft3<INV>(u[k1]);
+        for (int k2 = 0; k2 < 3; ++k2) a[k1 + 4 * k2] = u[k1][k2];
+    }
+}
+
 template <int RADIX, bool INV, typename R>
 FSA_HD void dft(cpx<R>* a) {
     if constexpr (RADIX == 2) dft2<INV>(a);
     else if constexpr (RADIX == 3) dft3<INV>(a);
     else if constexpr (RADIX == 4) dft4<INV>(a);
+    else if constexpr (RADIX == 6) dft6<INV>(a);
     else if constexpr (RADIX == 8) dft8<INV>(a);
+    else if constexpr (RADIX == 12) dft12<INV>(a);
     else if constexpr (RADIX == 16) dft16<INV>(a);
     else static_assert(RADIX == 2, "unsupported radix");
 }
@@ -175,19 +239,21 @@ constexpr int ilog2_exact(int x) {
     return ((1 << b) == x) ? b : -1;
 }
 
-// Lengths 2^a (a >= 2) and 3 * 2^a (a >= 2).  The default family (alt = 0)
+// Lengths 2^a (a >= 2) and 3 * 2^a (a >= 2; see make_fft_plan for their
+// families).  For powers of two, the default family (alt = 0)
 // uses power-of-two radices of at most 8 (P < 1024) or 16 (P >= 1024), with
 // the bits spread so that the radix sequence reads the same both ways
 // whenever possible (the inverse runs the radices reversed, so a palindromic
 // plan lets the forward and inverse transforms of the fused pass share one
-// set of twiddles); the factor 3 runs last; T is the largest power of two
+// set of twiddles); a factor 3 runs last, or, with mid3, sits in the middle
+// stage of 2^e . (3 2^mid) . 2^e (mid <= 2); T is the largest power of two
 // with T * E <= P for E = 8 (P < 1024) or 16 operands per thread, capped at
 // 256.  The alternate family (alt = 1) swaps both choices -- radices up to 16
 // and E = 16 below 1024, radices up to 8 and E = 8 from 1024 -- which changes
 // the radix split and the threads per transform; the autotuner times both.
 // It falls back to the default where it would leave teams of fewer than 8
 // threads or more than 16 operands per thread.
-constexpr FftPlan make_fft_plan_rule(int P, int maxbits, int E) {
+constexpr FftPlan make_fft_plan_rule(int P, int maxbits, int E, bool mid3 = false) {
     FftPlan p{};
     p.P = P;
     int m = P, threes = 0;
@@ -196,6 +262,31 @@ constexpr FftPlan make_fft_plan_rule(int P, int maxbits, int E) {
         ++threes;
     }
     const int a = ilog2_exact(m);
+    if (mid3 && threes == 1 && a >= 2) {
+        // 2^e . (3 2^mid) . 2^e, mid <= 2 (radix 3, 6 or 12 in the middle)
+        int mid = a % 2, e = (a - mid) / 2;
+        if (e > maxbits) {
+            mid += 2 * (e - maxbits);
+            e = maxbits;
+        }
+        if (mid <= 2 && e >= 1) {
+            p.r[0] = 1 << e;
+            p.r[1] = 3 << mid;
+            p.r[2] = 1 << e;
+            p.n = 3;
+            int T = 1;
+            while (T * 2 * E <= P && T < 256) T *= 2;
+            p.T = T;
+            int vmax = 0;
+            for (int s = 0; s < 3; ++s) {
+                const int nb = P / p.r[s];
+                const int b = (nb + T - 1) / T;
+                if (b * p.r[s] > vmax) vmax = b * p.r[s];
+            }
+            p.vmax = vmax;
+            return p;
+        }
+    }
     const int nst = (a + maxbits - 1) / maxbits;
     int bits[16] = {};
     if (nst == 3) {
@@ -230,6 +321,15 @@ constexpr FftPlan make_fft_plan_rule(int P, int maxbits, int E) {
 
 constexpr FftPlan make_fft_plan(int P, int alt = 0) {
     const bool big = P >= 1024;
+    if (P % 3 == 0) {
+        // lengths 3 * 2^a: by default three stages with the factor 3 in the
+        // middle one (a palindrome: one LDS exchange fewer, and a fused
+        // forward / inverse pair shares its twiddles); the alternate family
+        // is the power-of-two split with the radix 3 last
+        const FftPlan pal = make_fft_plan_rule(P, big ? 4 : 3, big ? 16 : 8, true);
+        const FftPlan last = make_fft_plan_rule(P, big ? 4 : 3, big ? 16 : 8, false);
+        return alt ? last : pal;
+    }
     const FftPlan def = make_fft_plan_rule(P, big ? 4 : 3, big ? 16 : 8);
     if (!alt) return def;
     const FftPlan p = make_fft_plan_rule(P, big ? 3 : 4, big ? 8 : 16);
