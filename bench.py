@@ -746,6 +746,8 @@ def main():
     ap.add_argument("--no-ddi", action="store_true", help="skip the dipole-dipole timing")
     ap.add_argument("--no-general", action="store_true",
                     help="skip the general-construction timings")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the cigar/pancake, Yukawa-over-lambda and Table 3 workloads")
     ap.add_argument("--serve-only", action="store_true", help="only the served workload")
     ap.add_argument("--serve-seconds", type=float, default=3.0)
     ap.add_argument("--no-tune", action="store_true",
@@ -827,16 +829,18 @@ def main():
         ddi = bench_ddi(F, torch, hip, synth, n=args.n)
         log(f"  dipole-dipole: FP32 {ddi['f32']['ms_per_step']:.4f} ms, "
             f"FP64 {ddi['f64']['ms_per_step']:.4f} ms")
-    table3 = bench_table3(F, torch, hip, synth)
-    log(f"  Table 3 workload (192^3): {table3}")
-    aniso, aniso_phis = bench_aniso(F, torch, hip, synth)
-    log(f"  cigar / pancake: {aniso}")
-    yuk, yuk_phis = bench_yukawa_lambda(F, torch, hip, synth)
-    log(f"  Yukawa over lambda: {yuk}")
-    aniso_phis.update({("yukawa",) + k: v for k, v in yuk_phis.items()})
-    del yuk_phis
-    if args.no_cpu:
-        aniso_phis = None  # only the oracle leg reads them
+    table3 = aniso = yuk = aniso_phis = None
+    if not args.no_extra:
+        table3 = bench_table3(F, torch, hip, synth)
+        log(f"  Table 3 workload (192^3): {table3}")
+        aniso, aniso_phis = bench_aniso(F, torch, hip, synth)
+        log(f"  cigar / pancake: {aniso}")
+        yuk, yuk_phis = bench_yukawa_lambda(F, torch, hip, synth)
+        log(f"  Yukawa over lambda: {yuk}")
+        aniso_phis.update({("yukawa",) + k: v for k, v in yuk_phis.items()})
+        del yuk_phis
+        if args.no_cpu:
+            aniso_phis = None  # only the oracle leg reads them
     general = None
     if not args.no_general:
         general = bench_general(F, torch, hip, n=args.n)
