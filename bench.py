@@ -762,8 +762,8 @@ def main():
                     help="only run the 1 GiB device copy (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print(f"bench.py: this build runs on exactly one GPU (asked for {args.gpus}); the "
-              "multi-GPU sharding of the path is a design only (see DESIGN.md)", file=sys.stderr)
+        print(f"bench.py: this library runs on exactly one GPU (asked for {args.gpus}); "
+              "sharding the path over several GPUs is a design, not implemented", file=sys.stderr)
         sys.exit(2)
     import numpy as np
     import torch

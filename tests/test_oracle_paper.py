@@ -32,7 +32,7 @@ def iso_exact(kind, r, sigma2, lam=0.0):
 
 
 def sig2(v):
-    """Two significant digits, as the survey of printed values requires."""
+    """Rounded to two significant digits: the precision the pins hold the printed values to."""
     return float(f"{v:.1e}")
 
 
