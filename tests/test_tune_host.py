@@ -29,9 +29,12 @@ def test_variant_sets_follow_the_radix_plans():
     # the alternate radix family differs from the default at these lengths
     for n in (128, 256, 512, 1024, 2048, 4096):
         assert 1 in F.tune_variants("f32", "conv", n), n
-    # and falls back to it (so is not compiled) at small lengths
-    for n in (16, 32, 64, 96):
+    # and falls back to it (so is not compiled) at small powers of two
+    for n in (16, 32, 64):
         assert 1 not in F.tune_variants("f32", "conv", n), n
+    # at 3 * 2^a the alternate is the radix-3-last split of the middle-3 plan
+    for n in (24, 48, 96, 192, 384, 768, 1536, 3072):
+        assert 1 in F.tune_variants("f32", "conv", n), n
     for p in F.PASSES:
         assert 0 in F.tune_variants("f64", p, 256)
 
