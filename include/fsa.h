@@ -263,9 +263,10 @@ typedef enum {
  * environment variable FSA_TUNE_CACHE, when that is set and exists. */
 
 /* Times every distinct (variant, occupancy) candidate of every pass of a
- * built plan on `stream` with hipEvents (median of `reps`, 1..1000, after
- * one warm-up each) and stores the fastest in the table; for a 3D plan then
- * times the slab schedules (fsa_tune_set_slabs) and keeps the fastest.
+ * built plan on `stream` with hipEvents (median of `reps`, 1..1000, taken in
+ * rounds that run each candidate once, after a warm-up round) and stores the
+ * fastest in the table; for a 3D plan then times the slab schedules
+ * (fsa_tune_set_slabs) the same way and keeps the fastest.
  * Synchronous.
  *   rho, phi, workspace  device buffers as for fsa_apply; on return phi holds
  *                        a valid evaluation of rho with the tuned choices.
@@ -275,8 +276,8 @@ fsa_status fsa_autotune(fsa_plan plan, const void* rho, void* phi, void* workspa
 /* The launches of a batch (fsa_apply_batched) cover many problems at once,
  * a size class that the per-plan tuning does not reach: times every
  * distinct (variant, occupancy) candidate of every persistent launch of
- * this batch (median of `reps`, 1..1000, after one warm-up each; the launch
- * of the fused pass has its input re-created before each run) and stores
+ * this batch (median of `reps`, 1..1000, in rounds as fsa_autotune; the
+ * launch of the fused pass has its input re-created before each run) and stores
  * the fastest under the launch's size class.  Same arguments and checks as
  * fsa_apply_batched; synchronous.  On return phi holds a valid evaluation
  * with the tuned choices, and batch graphs captured before are re-captured

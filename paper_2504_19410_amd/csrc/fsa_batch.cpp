@@ -455,7 +455,9 @@ fsa_status fsa_autotune_batched(int n, const fsa_plan* plans, const void* const*
         trial_bytes = std::max(trial_bytes, table_bytes(*g));
     }
     char* dbuf = nullptr;
-    if (hipMalloc((void**)&dbuf, fixed_bytes + trial_bytes) != hipSuccess) {
+    // one trial slot per candidate of a group (at most two per variant)
+    constexpr int kMaxCands = 2 * fsa::kNumVariants;
+    if (hipMalloc((void**)&dbuf, fixed_bytes + kMaxCands * trial_bytes) != hipSuccess) {
         fsa::set_last_error("fsa_autotune_batched: table allocation failed");
         return FSA_ENOMEM;
     }
@@ -489,32 +491,41 @@ fsa_status fsa_autotune_batched(int n, const fsa_plan* plans, const void* const*
             cands.push_back(fsa::Choice{v, 0});
             if (mo >= 2) cands.push_back(fsa::Choice{v, mo / 2});
         }
-        double best = 1e300;
-        fsa::Choice best_c = current;
-        for (const fsa::Choice& c : cands) {
-            finish_group(g, c);
-            e = upload_tables(g, trial);
-            std::vector<float> ms;
-            for (int i = -1; i < reps && e == hipSuccess; ++i) {
+        // every candidate's tables in its own trial slot, then `reps` rounds
+        // that run each candidate once (after a warm-up round), so slow drifts
+        // fall on all of them alike; median per candidate
+        const int nc = (int)cands.size();
+        std::vector<Group> trials((size_t)nc, g);
+        for (int c = 0; c < nc && e == hipSuccess; ++c) {
+            finish_group(trials[(size_t)c], cands[(size_t)c]);
+            e = upload_tables(trials[(size_t)c], trial + (size_t)c * trial_bytes);
+        }
+        std::vector<std::vector<float>> ms((size_t)nc);
+        for (int i = -1; i < reps && e == hipSuccess; ++i) {
+            for (int c = 0; c < nc && e == hipSuccess; ++c) {
                 // the fused pass works in place: re-create its input first
                 if (g.pass == fsa::Pass::CONV) e = run_before((int)fsa::Pass::CONV);
                 if (e == hipSuccess) e = hipEventRecord(ev[0], st);
-                if (e == hipSuccess) e = launch_group(g, trial, st);
+                if (e == hipSuccess)
+                    e = launch_group(trials[(size_t)c], trial + (size_t)c * trial_bytes, st);
                 if (e == hipSuccess) e = hipEventRecord(ev[1], st);
                 if (e == hipSuccess) e = hipEventSynchronize(ev[1]);
                 float t = 0.0f;
                 if (e == hipSuccess) e = hipEventElapsedTime(&t, ev[0], ev[1]);
-                if (e == hipSuccess && i >= 0) ms.push_back(t);
-            }
-            if (e != hipSuccess) break;
-            std::sort(ms.begin(), ms.end());
-            const double us = 1e3 * ms[ms.size() / 2];
-            if (us < best) {
-                best = us;
-                best_c = c;
+                if (e == hipSuccess && i >= 0) ms[(size_t)c].push_back(t);
             }
         }
         if (e != hipSuccess) break;
+        double best = 1e300;
+        fsa::Choice best_c = current;
+        for (int c = 0; c < nc; ++c) {
+            std::sort(ms[(size_t)c].begin(), ms[(size_t)c].end());
+            const double us = 1e3 * ms[(size_t)c][ms[(size_t)c].size() / 2];
+            if (us < best) {
+                best = us;
+                best_c = cands[(size_t)c];
+            }
+        }
         finish_group(g, best_c);
         e = upload_tables(g, dbuf + offs[gi]);
         fsa::tune::set(g.prec, g.pass, g.len, g.lines, best_c, best, true);

@@ -543,28 +543,33 @@ fsa_status fsa_autotune(fsa_plan pl, const void* rho, void* phi, void* workspace
                                  fsa::step_choice(pl, steps[i]), st);
         return r;
     };
-    // median time (us) of `reps` timed runs of `body` after one warm-up;
-    // `prep` runs untimed before each
-    auto time_us = [&](auto&& prep, auto&& body, double* us) {
-        std::vector<float> ms;
+    auto nothing = [] { return hipSuccess; };
+    // median time (us) of every candidate over `reps` rounds after a warm-up
+    // round; a round runs each candidate once, so slow drifts of the clock
+    // or of the memory system fall on all of them alike
+    auto time_rounds = [&](int n, auto&& prep, auto&& body, std::vector<double>& us) {
+        std::vector<std::vector<float>> ms((size_t)n);
         hipError_t r = hipSuccess;
         for (int i = -1; i < reps && r == hipSuccess; ++i) {
-            r = prep();
-            if (r == hipSuccess) r = hipEventRecord(ev[0], st);
-            if (r == hipSuccess) r = body();
-            if (r == hipSuccess) r = hipEventRecord(ev[1], st);
-            if (r == hipSuccess) r = hipEventSynchronize(ev[1]);
-            float t = 0.0f;
-            if (r == hipSuccess) r = hipEventElapsedTime(&t, ev[0], ev[1]);
-            if (r == hipSuccess && i >= 0) ms.push_back(t);
+            for (int c = 0; c < n && r == hipSuccess; ++c) {
+                r = prep();
+                if (r == hipSuccess) r = hipEventRecord(ev[0], st);
+                if (r == hipSuccess) r = body(c);
+                if (r == hipSuccess) r = hipEventRecord(ev[1], st);
+                if (r == hipSuccess) r = hipEventSynchronize(ev[1]);
+                float t = 0.0f;
+                if (r == hipSuccess) r = hipEventElapsedTime(&t, ev[0], ev[1]);
+                if (r == hipSuccess && i >= 0) ms[(size_t)c].push_back(t);
+            }
         }
-        if (r == hipSuccess) {
-            std::sort(ms.begin(), ms.end());
-            *us = 1e3 * ms[ms.size() / 2];
-        }
+        us.assign((size_t)n, 0.0);
+        if (r == hipSuccess)
+            for (int c = 0; c < n; ++c) {
+                std::sort(ms[(size_t)c].begin(), ms[(size_t)c].end());
+                us[(size_t)c] = 1e3 * ms[(size_t)c][ms[(size_t)c].size() / 2];
+            }
         return r;
     };
-    auto nothing = [] { return hipSuccess; };
     // one evaluation with the current choices fills every buffer with data
     if (e == hipSuccess) e = run_all(1);
     for (int k = 0; k < np && e == hipSuccess; ++k) {
@@ -586,44 +591,42 @@ fsa_status fsa_autotune(fsa_plan pl, const void* rho, void* phi, void* workspace
             const fsa::Step prev = whole(k - 1);
             return fsa::launch_step(pl, prev, rho, phi, workspace, fsa::step_choice(pl, prev), st);
         };
-        double best = 1e300;
-        fsa::Choice best_c;
-        for (const fsa::Choice& c : cands) {
-            double us = 0.0;
-            e = time_us(prep,
-                        [&] { return fsa::launch_step(pl, whole(k), rho, phi, workspace, c, st); },
-                        &us);
-            if (e != hipSuccess) break;
-            if (us < best) {
-                best = us;
-                best_c = c;
-            }
+        std::vector<double> us;
+        e = time_rounds((int)cands.size(), prep,
+                        [&](int c) {
+                            return fsa::launch_step(pl, whole(k), rho, phi, workspace,
+                                                    cands[(size_t)c], st);
+                        },
+                        us);
+        if (e == hipSuccess) {
+            size_t b = 0;
+            for (size_t c = 1; c < cands.size(); ++c)
+                if (us[c] < us[b]) b = c;
+            fsa::tune::set(pl->prec, pass, len, fsa::step_lines(pl, whole(k)), cands[b], us[b]);
         }
-        if (e == hipSuccess)
-            fsa::tune::set(pl->prec, pass, len, fsa::step_lines(pl, whole(k)), best_c, best);
     }
     // schedule: slabs of bins for the middle passes (3D)
     if (e == hipSuccess && pl->d == 3) {
-        double best = 1e300;
-        int best_s = 1;
+        std::vector<int> counts;
+        for (int slabs = 1; slabs <= fsa::kMaxSlabs && slabs <= H; slabs *= 2)
+            counts.push_back(slabs);
         // evaluations back to back, as a caller streams them
         constexpr int kBack = 4;
-        for (int slabs = 1; slabs <= fsa::kMaxSlabs && slabs <= H && e == hipSuccess; slabs *= 2) {
-            double us = 0.0;
-            e = time_us(nothing,
-                        [&] {
+        std::vector<double> us;
+        e = time_rounds((int)counts.size(), nothing,
+                        [&](int c) {
                             hipError_t r = hipSuccess;
-                            for (int i = 0; i < kBack && r == hipSuccess; ++i) r = run_all(slabs);
+                            for (int i = 0; i < kBack && r == hipSuccess; ++i)
+                                r = run_all(counts[(size_t)c]);
                             return r;
                         },
-                        &us);
-            us /= kBack;
-            if (e == hipSuccess && us < best) {
-                best = us;
-                best_s = slabs;
-            }
+                        us);
+        if (e == hipSuccess) {
+            size_t b = 0;
+            for (size_t c = 1; c < counts.size(); ++c)
+                if (us[c] < us[b]) b = c;
+            fsa::tune::set_slabs(pl, counts[b], us[b] / kBack);
         }
-        if (e == hipSuccess) fsa::tune::set_slabs(pl, best_s, best);
     }
     // leave the caller's buffers holding a valid evaluation
     if (e == hipSuccess) e = run_all(fsa::tune::get_slabs(pl));
