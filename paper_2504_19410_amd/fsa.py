@@ -439,16 +439,7 @@ def apply_batched(plans: Sequence[Plan], rhos: Sequence[torch.Tensor],
                   workspace: Optional[torch.Tensor] = None,
                   stream: Optional[torch.cuda.Stream] = None):
     """Evaluates every (plan, rho) pair in one batched call (``fsa_apply_batched``)."""
-    n = len(plans)
-    if len(rhos) != n:
-        raise ValueError("one density per plan")
-    for p, r in zip(plans, rhos):
-        p.check_input(r)
-    if outs is None:
-        outs = [torch.empty_like(r) for r in rhos]
-    need = batch_workspace_bytes(plans)
-    if workspace is None:
-        workspace = torch.empty(need + 256, dtype=torch.uint8, device=rhos[0].device)
+    n, outs, workspace = _batch_args(plans, rhos, outs, workspace)
     base = (workspace.data_ptr() + 255) & ~255
     arr = (ctypes.c_void_p * n)(*[p.handle for p in plans])
     rp = (ctypes.c_void_p * n)(*[r.data_ptr() for r in rhos])
@@ -459,6 +450,31 @@ def apply_batched(plans: Sequence[Plan], rhos: Sequence[torch.Tensor],
     return outs
 
 
+def _batch_args(plans, rhos, outs, workspace):
+    """Host-side checks of a batch's buffers (the C ABI cannot size-check
+    device pointers): one density and one output per plan, each of the plan's
+    shape, dtype and layout on the device; outputs allocated if not given; a
+    workspace of at least fsa_batch_workspace_bytes after 256-byte alignment."""
+    n = len(plans)
+    if len(rhos) != n:
+        raise ValueError("one density per plan")
+    if outs is not None and len(outs) != n:
+        raise ValueError("one output per plan")
+    for p, r in zip(plans, rhos):
+        p.check_input(r)
+    if outs is None:
+        outs = [torch.empty_like(r) for r in rhos]
+    else:
+        for p, o in zip(plans, outs):
+            p.check_input(o)
+    need = batch_workspace_bytes(plans)
+    if workspace is None:
+        workspace = torch.empty(need + 256, dtype=torch.uint8, device=rhos[0].device)
+    elif not workspace.is_cuda or not workspace.is_contiguous():
+        raise ValueError("the workspace must be a contiguous device tensor")
+    return n, outs, workspace
+
+
 def autotune_batched(plans: Sequence[Plan], rhos: Sequence[torch.Tensor],
                      outs: Optional[Sequence[torch.Tensor]] = None,
                      workspace: Optional[torch.Tensor] = None, reps: int = 5,
@@ -466,16 +482,7 @@ def autotune_batched(plans: Sequence[Plan], rhos: Sequence[torch.Tensor],
     """Tunes the persistent launches of this batch at their own size classes
     (``fsa_autotune_batched``); returns the outputs, which hold a valid
     evaluation under the tuned choices."""
-    n = len(plans)
-    if len(rhos) != n:
-        raise ValueError("one density per plan")
-    for p, r in zip(plans, rhos):
-        p.check_input(r)
-    if outs is None:
-        outs = [torch.empty_like(r) for r in rhos]
-    need = batch_workspace_bytes(plans)
-    if workspace is None:
-        workspace = torch.empty(need + 256, dtype=torch.uint8, device=rhos[0].device)
+    n, outs, workspace = _batch_args(plans, rhos, outs, workspace)
     base = (workspace.data_ptr() + 255) & ~255
     arr = (ctypes.c_void_p * n)(*[p.handle for p in plans])
     rp = (ctypes.c_void_p * n)(*[r.data_ptr() for r in rhos])
@@ -489,7 +496,7 @@ def autotune_batched(plans: Sequence[Plan], rhos: Sequence[torch.Tensor],
 
 def batch_launches(plans: Sequence[Plan], rhos, outs, workspace: torch.Tensor) -> int:
     """Persistent launches in the graph captured for this batch (fsa_batch_launches)."""
-    n = len(plans)
+    n, outs, workspace = _batch_args(plans, rhos, outs, workspace)
     base = (workspace.data_ptr() + 255) & ~255
     arr = (ctypes.c_void_p * n)(*[p.handle for p in plans])
     rp = (ctypes.c_void_p * n)(*[r.data_ptr() for r in rhos])

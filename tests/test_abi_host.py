@@ -153,6 +153,21 @@ def test_batch_entry_points_validate_on_the_host(F):
     assert F.STATUS[st] == "FSA_EINVAL"
 
 
+def test_batch_binding_checks_counts_before_any_launch(F, monkeypatch):
+    """The binding rejects a batch whose density or output count differs from
+    its plan count (ValueError) before it calls into the library."""
+    p = F.Plan("log2d", (8, 8), (32, 32))
+    calls = []
+    monkeypatch.setattr(F, "_check", lambda st: calls.append(st))
+    with pytest.raises(ValueError, match="one output per plan"):
+        F.apply_batched([p], [object()], outs=[object(), object()])
+    with pytest.raises(ValueError, match="one density per plan"):
+        F.autotune_batched([p, p], [object()])
+    with pytest.raises(ValueError, match="one output per plan"):
+        F.batch_launches([p], [object()], [], None)
+    assert calls == []
+
+
 def test_apply_before_build_is_a_state_error(F):
     p = F.Plan("coulomb3d", (8, 8, 8), (16, 16, 16))
     st = F.lib().fsa_apply(p.handle, ctypes.c_void_p(256), ctypes.c_void_p(256),

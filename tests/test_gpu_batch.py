@@ -4,12 +4,12 @@ A batch runs as a captured graph of persistent launches, one per pass and
 transform length; every problem's result must be bitwise equal to the same
 problem evaluated alone, on the first (capturing) call and on replays.
 """
-import numpy as np
 import pytest
 import torch
 
 from oracle import oracle as O
 from paper_2504_19410_amd import synth
+from parity import check
 
 pytestmark = pytest.mark.gpu
 
@@ -85,9 +85,7 @@ def test_batch_log2d_parity_with_oracle(F):
     torch.cuda.synchronize()
     for p, plan, r, o in zip(probs, plans, rhos, outs):
         ref = O.solve(p.kernel, p.L, p.N, r.double().cpu().numpy(), eps=plan.eps)
-        got = o.double().cpu().numpy()
-        err = np.linalg.norm(got - ref) / np.linalg.norm(ref)
-        assert err <= 5e-6, (p.N, err)
+        check(o.double().cpu().numpy(), ref, "f32", f"reduced batch {p.N}")
 
 
 def test_batch_rejects_unbuilt_and_small_workspace(F):
@@ -99,6 +97,28 @@ def test_batch_rejects_unbuilt_and_small_workspace(F):
     with pytest.raises(F.FsaError, match="EINVAL"):
         ws = torch.empty(1024, dtype=torch.uint8, device="cuda")
         F.apply_batched([a], [r], workspace=ws)
+
+
+def test_batch_rejects_mismatched_outputs_on_the_host(F):
+    """Outputs of the wrong dtype, shape or layout raise ValueError before any
+    launch (pass E would otherwise write past a smaller allocation)."""
+    a = F.Plan("log2d", (4.0, 4.0), (32, 32), "f64").build()
+    b = F.Plan("coulomb3d", (4.0, 4.0, 4.0), (16, 16, 16), "f32").build()
+    ra = torch.zeros(32, 32, dtype=torch.float64, device="cuda")
+    rb = torch.zeros(16, 16, 16, device="cuda")
+    bad = [
+        [torch.empty(32, 32, device="cuda"), torch.empty_like(rb)],               # f32 for f64
+        [torch.empty_like(ra), torch.empty(16, 16, 8, device="cuda")],            # smaller grid
+        [torch.empty_like(ra), torch.empty(16, 16, 32, device="cuda")[..., ::2]],  # strided
+        [torch.empty_like(ra)],                                                   # one missing
+    ]
+    for outs in bad:
+        for fn in (F.apply_batched, F.autotune_batched):
+            with pytest.raises(ValueError):
+                fn([a, b], [ra, rb], outs)
+    with pytest.raises(ValueError):
+        F.apply_batched([a, b], [ra, rb], [torch.empty_like(ra), torch.empty_like(rb)],
+                        torch.empty(1 << 20, dtype=torch.uint8))   # host workspace
 
 
 LENGTHS = [8, 12, 16, 24, 32, 48, 64, 96, 128, 192, 256, 384, 512, 768, 1024, 1536, 2048]
@@ -133,6 +153,4 @@ def test_batch_every_length_equals_solo_bitwise(F):
     for i in (len(specs) - 3, len(specs) - 1):
         kind, L, N, prec, lam = specs[i]
         ref = O.solve(kind, L, N, rhos[i].double().cpu().numpy(), eps=1.0)
-        got = outs[i].double().cpu().numpy()
-        err = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
-        assert err <= (5e-6 if prec == "f32" else 1e-12), (specs[i], err)
+        check(outs[i].double().cpu().numpy(), ref, prec, f"batch {kind} {N} {prec}")
