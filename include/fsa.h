@@ -174,6 +174,27 @@ fsa_status fsa_build_tensor(fsa_plan plan, void* stream);
  * FSA_ESTATE if the tensor has not been built. */
 fsa_status fsa_apply(fsa_plan plan, const void* rho, void* phi, void* workspace, void* stream);
 
+/* Capacity of the workspace that fsa_apply_noalloc uses (128 MiB): plans
+ * whose workspace_bytes fit, e.g. every 3D grid up to 128^3 in FP32 and FP64
+ * and every 2D grid up to 2048^2 in FP32 and FP64. */
+#define FSA_NOALLOC_SCRATCH_BYTES ((size_t)128 << 20)
+
+/* For callers that cannot allocate device memory (code under hipGraph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): fsa_apply
+ * with the workspace taken from a static device array of the library,
+ * FSA_NOALLOC_SCRATCH_BYTES long, one per device, held from the first call on
+ * that device until the process ends.  Makes no device or host allocation
+ * (the first call on a device resolves the array's address once).
+ *   rho, phi, stream  as for fsa_apply; the results are bitwise those of
+ *                     fsa_apply with the same launch choices.
+ * FSA_EINVAL if the plan's workspace_bytes exceed FSA_NOALLOC_SCRATCH_BYTES
+ * (nothing is launched), FSA_ESTATE as fsa_apply.  Every call on one device
+ * shares that device's array and may leave data in it (the passes write
+ * every workspace entry they read): calls whose executions overlap on one
+ * device -- on different streams or from different threads without ordering
+ * -- race and give wrong results; order them on one stream. */
+fsa_status fsa_apply_noalloc(fsa_plan plan, const void* rho, void* phi, void* stream);
+
 /* Number of kernel launches of one evaluation with the plan's current
  * schedule (3 in 2D; 2 + 3 x slabs in 3D, see fsa_tune_set_slabs) and, if
  * `passes` is not NULL, the fsa_pass of each launch in order (cap entries

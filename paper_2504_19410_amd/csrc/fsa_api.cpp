@@ -6,6 +6,7 @@
 #include <cstdio>
 #include <cstring>
 #include <atomic>
+#include <mutex>
 #include <new>
 #include <string>
 
@@ -449,6 +450,59 @@ static fsa_status apply_checked(fsa_plan pl, const void* rho, void* phi, void* w
 
 fsa_status fsa_apply(fsa_plan pl, const void* rho, void* phi, void* workspace, void* stream) {
     return apply_checked(pl, rho, phi, workspace, stream, nullptr);
+}
+
+}  // extern "C"
+
+// Workspace of fsa_apply_noalloc: a device array of the library's module,
+// one copy per device, alive until the process ends.  In host code `scratch`
+// names a host-side shadow, not device memory: kernels only ever receive the
+// device address that hipGetSymbolAddress returns for the current device.
+static __device__ __align__(256) unsigned char scratch[FSA_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+
+constexpr int kMaxScratchDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_dev[kMaxScratchDevices] = {};
+
+// Device address of `scratch` on device `dev` (which must be current),
+// resolved once per device.
+fsa_status scratch_address(int dev, void** out) {
+    if (dev < 0 || dev >= kMaxScratchDevices)
+        return fail(FSA_EUNSUPPORTED, "fsa_apply_noalloc: device %d beyond the %d supported", dev,
+                    kMaxScratchDevices);
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        void* ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return hip_fail(e, "fsa_apply_noalloc: hipGetSymbolAddress");
+        if (!ptr || ((uintptr_t)ptr & 255) != 0)
+            return fail(FSA_EDEVICE, "fsa_apply_noalloc: scratch address %p unusable", ptr);
+        g_scratch_dev[dev] = ptr;
+    }
+    *out = g_scratch_dev[dev];
+    return FSA_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+fsa_status fsa_apply_noalloc(fsa_plan pl, const void* rho, void* phi, void* stream) {
+    if (!pl) return fail(FSA_EINVAL, "fsa_apply_noalloc: null plan");
+    if (pl->ws_bytes > (size_t)FSA_NOALLOC_SCRATCH_BYTES)
+        return fail(FSA_EINVAL,
+                    "fsa_apply_noalloc: the plan needs %zu bytes of workspace, the static scratch "
+                    "holds %zu (use fsa_apply with a caller workspace)",
+                    pl->ws_bytes, (size_t)FSA_NOALLOC_SCRATCH_BYTES);
+    int dev = 0;
+    const hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "fsa_apply_noalloc: hipGetDevice");
+    void* ws = nullptr;
+    const fsa_status st = scratch_address(dev, &ws);
+    if (st != FSA_OK) return st;
+    return apply_checked(pl, rho, phi, ws, stream, nullptr);
 }
 
 fsa_status fsa_plan_launches(fsa_plan pl, int* n, int* passes, int cap) {

@@ -37,6 +37,9 @@ KIND_DIM = {"coulomb3d": 3, "yukawa3d": 3, "biharmonic3d": 3,
 PRECISIONS = {"f32": 0, "f64": 1, "dd": 2}
 DTYPES = {"f32": torch.float32, "f64": torch.float64, "dd": torch.float64}
 
+# FSA_NOALLOC_SCRATCH_BYTES: the workspace capacity of fsa_apply_noalloc
+NOALLOC_SCRATCH_BYTES = 128 << 20
+
 STATUS = {
     0: "FSA_OK", 1: "FSA_EINVAL", 2: "FSA_EUNSUPPORTED", 3: "FSA_ENOMEM",
     4: "FSA_EDEVICE", 5: "FSA_ESTATE", 6: "FSA_EBUDGET", 7: "FSA_ECANCELLED",
@@ -44,6 +47,7 @@ STATUS = {
 
 EXPORTS = (
     "fsa_plan_create", "fsa_plan_query", "fsa_build_tensor", "fsa_apply", "fsa_apply_events",
+    "fsa_apply_noalloc",
     "fsa_batch_workspace_bytes", "fsa_apply_batched", "fsa_batch_launches",
     "fsa_autotune_batched", "fsa_plan_destroy",
     "fsa_plan_tensor",
@@ -99,6 +103,7 @@ def _load():
         "fsa_build_tensor": [P, P],
         "fsa_apply": [P, P, P, P, P],
         "fsa_apply_events": [P, P, P, P, P, P, I],
+        "fsa_apply_noalloc": [P, P, P, P],
         "fsa_batch_workspace_bytes": [I, P, P],
         "fsa_apply_batched": [I, P, P, P, P, S, P],
         "fsa_batch_launches": [I, P, P, P, P, P],
@@ -256,6 +261,19 @@ class Plan:
         _check(_lib.fsa_apply(self._h, ctypes.c_void_p(rho.data_ptr()),
                               ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(self._ws_ptr(ws)),
                               _stream_ptr(stream)))
+        return out
+
+    def apply_noalloc(self, rho: torch.Tensor, out: Optional[torch.Tensor] = None,
+                      stream: Optional[torch.cuda.Stream] = None) -> torch.Tensor:
+        """``fsa_apply_noalloc``: as apply, with the library's static device
+        scratch as the workspace (no allocation when ``out`` is given)."""
+        self.check_input(rho)
+        if out is None:
+            out = torch.empty_like(rho)
+        else:
+            self.check_input(out)
+        _check(_lib.fsa_apply_noalloc(self._h, ctypes.c_void_p(rho.data_ptr()),
+                                      ctypes.c_void_p(out.data_ptr()), _stream_ptr(stream)))
         return out
 
     @property
