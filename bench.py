@@ -66,17 +66,23 @@ class Hip:
     def __init__(self):
         self.lib = ctypes.CDLL("libamdhip64.so")
         P = ctypes.c_void_p
-        self.lib.hipEventCreate.argtypes = [ctypes.POINTER(P)]
+        self.lib.hipEventCreateWithFlags.argtypes = [ctypes.POINTER(P), ctypes.c_uint]
         self.lib.hipEventRecord.argtypes = [P, P]
         self.lib.hipEventSynchronize.argtypes = [P]
         self.lib.hipEventElapsedTime.argtypes = [ctypes.POINTER(ctypes.c_float), P, P]
         self.lib.hipEventDestroy.argtypes = [P]
 
+    # hipEventDisableSystemFence: a timing event that does not write back and
+    # invalidate the caches when it is recorded (a default event does, which
+    # leaves the next kernel a cold L2 and a ~10 us gap, and so changes the
+    # time it measures)
+    TIMING_FLAGS = 0x20000000
+
     def event(self):
         e = ctypes.c_void_p()
-        rc = self.lib.hipEventCreate(ctypes.byref(e))
+        rc = self.lib.hipEventCreateWithFlags(ctypes.byref(e), self.TIMING_FLAGS)
         if rc != 0:
-            raise RuntimeError(f"hipEventCreate failed ({rc})")
+            raise RuntimeError(f"hipEventCreateWithFlags failed ({rc})")
         return e
 
     def record(self, e, stream):
@@ -189,10 +195,11 @@ def bench_precision(F, torch, hip, prob, rho64, prec, steps, warmup, tune=True):
         if plan.d == 3:
             tuned[("slabs", 0)] = F.tune_get_slabs(prec, plan.N)
     timing = timed_evals(lambda: plan.apply(rho, out, ws), torch, hip, steps, warmup)
-    # per-pass durations: the same K evaluations with events around each
-    # launch (the 3D middle passes launch once per slab of the schedule)
+    # per-pass durations: the same K evaluations, each launch recording a start
+    # and an end event with its own execution (the 3D middle passes launch
+    # once per slab of the schedule)
     launches = plan.launches()
-    evs = [[hip.event() for _ in range(len(launches) + 1)] for _ in range(steps)]
+    evs = [[hip.event() for _ in range(2 * len(launches))] for _ in range(steps)]
     for k in range(steps):
         plan.apply_events(rho, out, evs[k], ws)
     torch.cuda.synchronize()
@@ -204,7 +211,7 @@ def bench_precision(F, torch, hip, prob, rho64, prec, steps, warmup, tune=True):
         pass_launches[by_short[ln]] += 1
     for k in range(steps):
         for i, ln in enumerate(launches):
-            pass_ms[by_short[ln]] += hip.ms(evs[k][i], evs[k][i + 1]) / steps
+            pass_ms[by_short[ln]] += hip.ms(evs[k][2 * i], evs[k][2 * i + 1]) / steps
     for row in evs:
         for e in row:
             hip.destroy(e)

@@ -201,12 +201,15 @@ fsa_status fsa_apply_noalloc(fsa_plan plan, const void* rho, void* phi, void* st
  * available). */
 fsa_status fsa_plan_launches(fsa_plan plan, int* n, int* passes, int cap);
 
-/* Profiling variant of fsa_apply: the same kernels on the same stream, plus
- * hipEventRecord(events[i], stream) before launch i and of events[n] after
- * the last launch (n from fsa_plan_launches), so a caller can time every
- * launch with hipEventElapsedTime.  The events are hipEvent_t handles created
- * by the caller; n_events must equal n + 1.  For profiling tools and
- * benchmarks. */
+/* Profiling variant of fsa_apply: the same kernels on the same stream, with
+ * hipEventRecord(events[2i], stream) right before launch i (of n, from
+ * fsa_plan_launches) and hipEventRecord(events[2i + 1], stream) right after
+ * it, so that hipEventElapsedTime(events[2i], events[2i + 1]) times launch i.
+ * A pair of NULL entries leaves launch i untimed.  The events are hipEvent_t
+ * handles created by the caller; n_events must equal 2n.  Events created
+ * with hipEventDisableSystemFence disturb the timed work least (a default
+ * event writes back and invalidates the caches when it is recorded, so the
+ * next launch starts cold).  For profiling tools and benchmarks. */
 fsa_status fsa_apply_events(fsa_plan plan, const void* rho, void* phi, void* workspace,
                             void* stream, void* const* events, int n_events);
 

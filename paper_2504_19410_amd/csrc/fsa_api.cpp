@@ -403,18 +403,20 @@ Choice step_choice(const fsa_plan_s* pl, const Step& s) {
 
 // Enqueues one evaluation: pass A, then passes B, C, D per slab of bins p2
 // (3D; the slab count is the tuned schedule of the grid), then pass E, each
-// with its tuned launch choice.  With events, records ev[i] before launch i
-// and one more after the last.
+// with its tuned launch choice.  With events, records ev[2i] right before
+// launch i and ev[2i + 1] right after it (a null pair: launch i untimed).
 static hipError_t apply_impl(const fsa_plan_s* pl, const void* rho, void* phi, void* ws,
                              hipStream_t st, hipEvent_t const* ev) {
     Step steps[kMaxSteps];
     const int ns = schedule(pl, tune::get_slabs(pl), steps);
     hipError_t e = hipSuccess;
     for (int i = 0; i < ns && e == hipSuccess; ++i) {
-        if (ev) e = hipEventRecord(ev[i], st);
-        if (e == hipSuccess) e = launch_step(pl, steps[i], rho, phi, ws, step_choice(pl, steps[i]), st);
+        const bool timed = ev && ev[2 * i];
+        if (timed) e = hipEventRecord(ev[2 * i], st);
+        if (e == hipSuccess)
+            e = launch_step(pl, steps[i], rho, phi, ws, step_choice(pl, steps[i]), st);
+        if (e == hipSuccess && timed) e = hipEventRecord(ev[2 * i + 1], st);
     }
-    if (e == hipSuccess && ev) e = hipEventRecord(ev[ns], st);
     return e;
 }
 
@@ -530,12 +532,13 @@ fsa_status fsa_apply_events(fsa_plan pl, const void* rho, void* phi, void* works
                             void* stream, void* const* events, int n_events) {
     if (!pl || !events) return fail(FSA_EINVAL, "fsa_apply_events: null argument");
     fsa::Step steps[fsa::kMaxSteps];
-    const int need = fsa::schedule(pl, fsa::tune::get_slabs(pl), steps) + 1;
+    const int need = 2 * fsa::schedule(pl, fsa::tune::get_slabs(pl), steps);
     if (n_events != need)
-        return fail(FSA_EINVAL, "fsa_apply_events: need %d events (launches + 1), got %d", need,
+        return fail(FSA_EINVAL, "fsa_apply_events: need %d events (2 per launch), got %d", need,
                     n_events);
-    for (int i = 0; i < need; ++i)
-        if (!events[i]) return fail(FSA_EINVAL, "fsa_apply_events: null event %d", i);
+    for (int i = 0; i < need; i += 2)
+        if (!events[i] != !events[i + 1])
+            return fail(FSA_EINVAL, "fsa_apply_events: launch %d has one null event", i / 2);
     return apply_checked(pl, rho, phi, workspace, stream, (hipEvent_t const*)events);
 }
 

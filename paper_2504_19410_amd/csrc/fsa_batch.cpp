@@ -464,8 +464,10 @@ fsa_status fsa_autotune_batched(int n, const fsa_plan* plans, const void* const*
     char* trial = dbuf + fixed_bytes;
     hipStream_t st = (hipStream_t)stream;
     hipEvent_t ev[2] = {nullptr, nullptr};
-    hipError_t e = hipEventCreate(&ev[0]);
-    if (e == hipSuccess) e = hipEventCreate(&ev[1]);
+    // timing events without the system-scope fence of a default event, whose
+    // cache write-back and invalidation would give the timed launch a cold L2
+    hipError_t e = hipEventCreateWithFlags(&ev[0], hipEventDisableSystemFence);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&ev[1], hipEventDisableSystemFence);
     for (size_t i = 0; i < order.size() && e == hipSuccess; ++i)
         e = upload_tables(*order[i], dbuf + offs[i]);
     // launches of every group of the passes before `stage`, with the fixed

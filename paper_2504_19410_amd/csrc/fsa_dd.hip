@@ -467,27 +467,21 @@ hipError_t launch_dd_step(const fsa_plan_s* pl, int k, const void* rho, void* ph
     void* dst = mode == DD_INV_REAL ? phi : (void*)X;
     switch (mode) {
     case DD_FWD_REAL:
-        hipLaunchKernelGGL(k_dd_pass<DD_FWD_REAL>, dim3((unsigned)lines), dim3(threads), lds, st,
-                           src, dst, li, lo, Pa, lg, n_in, n_out, tw, cv);
-        break;
+        return launch_kernel(k_dd_pass<DD_FWD_REAL>, dim3((unsigned)lines), dim3(threads), lds, st,
+                             src, dst, li, lo, Pa, lg, n_in, n_out, tw, cv);
     case DD_FWD:
-        hipLaunchKernelGGL(k_dd_pass<DD_FWD>, dim3((unsigned)lines), dim3(threads), lds, st, src,
-                           dst, li, lo, Pa, lg, n_in, n_out, tw, cv);
-        break;
+        return launch_kernel(k_dd_pass<DD_FWD>, dim3((unsigned)lines), dim3(threads), lds, st,
+                             src, dst, li, lo, Pa, lg, n_in, n_out, tw, cv);
     case DD_CONV:
-        hipLaunchKernelGGL(k_dd_pass<DD_CONV>, dim3((unsigned)lines), dim3(threads), lds, st,
-                           src, dst, li, lo, Pa, lg, n_in, n_out, tw, cv);
-        break;
+        return launch_kernel(k_dd_pass<DD_CONV>, dim3((unsigned)lines), dim3(threads), lds, st,
+                             src, dst, li, lo, Pa, lg, n_in, n_out, tw, cv);
     case DD_INV:
-        hipLaunchKernelGGL(k_dd_pass<DD_INV>, dim3((unsigned)lines), dim3(threads), lds, st, src,
-                           dst, li, lo, Pa, lg, n_in, n_out, tw, cv);
-        break;
+        return launch_kernel(k_dd_pass<DD_INV>, dim3((unsigned)lines), dim3(threads), lds, st,
+                             src, dst, li, lo, Pa, lg, n_in, n_out, tw, cv);
     default:
-        hipLaunchKernelGGL(k_dd_pass<DD_INV_REAL>, dim3((unsigned)lines), dim3(threads), lds, st,
-                           src, dst, li, lo, Pa, lg, n_in, n_out, tw, cv);
-        break;
+        return launch_kernel(k_dd_pass<DD_INV_REAL>, dim3((unsigned)lines), dim3(threads), lds, st,
+                             src, dst, li, lo, Pa, lg, n_in, n_out, tw, cv);
     }
-    return hipGetLastError();
 }
 
 }  // namespace fsa

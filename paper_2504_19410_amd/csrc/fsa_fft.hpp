@@ -209,6 +209,64 @@ FSA_HD void dft12(cpx<R>* a) {
     }
 }
 
+// DFTs of R points whose upper half a[R/2 .. R-1] is zero (the first stage of
+// a zero-padded transform): the butterflies of dft<R> without the additions of
+// the zero operands (x + 0 is not x in IEEE arithmetic when x = -0, so the
+// compiler keeps them otherwise).
+template <bool INV, typename R>
+FSA_HD void dft4_zh(cpx<R>* a) {
+    const cpx<R> a0 = a[0], a1 = a[1], t3 = rot90<INV>(a[1]);
+    a[0] = a0 + a1;
+    a[2] = a0 - a1;
+    a[1] = a0 + t3;
+    a[3] = a0 - t3;
+}
+
+template <bool INV, typename R>
+FSA_HD void dft8_zh(cpx<R>* a) {
+    cpx<R> e[4] = {a[0], a[2]}, o[4] = {a[1], a[3]};
+    dft4_zh<INV>(e);
+    dft4_zh<INV>(o);
+    o[1] = w8<INV, 1>(o[1]);
+    o[2] = w8<INV, 2>(o[2]);
+    o[3] = w8<INV, 3>(o[3]);
+    for (int q = 0; q < 4; ++q) {
+        a[q] = e[q] + o[q];
+        a[q + 4] = e[q] - o[q];
+    }
+}
+
+template <bool INV, typename R>
+FSA_HD void dft16_zh(cpx<R>* a) {
+    cpx<R> e[8], o[8];
+    for (int q = 0; q < 4; ++q) {
+        e[q] = a[2 * q];
+        o[q] = a[2 * q + 1];
+    }
+    dft8_zh<INV>(e);
+    dft8_zh<INV>(o);
+    const R c1 = R(0.92387953251128675612818318939679);  // cos(pi/8)
+    const R s1 = R(0.38268343236508977172845998403040);  // sin(pi/8)
+    const R h = R(0.70710678118654752440084436210485);
+    const R sg = INV ? R(1) : R(-1);
+    const cpx<R> tw[8] = {mk(R(1), R(0)), mk(c1, sg * s1), mk(h, sg * h), mk(s1, sg * c1),
+                          mk(R(0), sg),   mk(-s1, sg * c1), mk(-h, sg * h), mk(-c1, sg * s1)};
+    for (int q = 1; q < 8; ++q) o[q] = cmul(o[q], tw[q]);
+    for (int q = 0; q < 8; ++q) {
+        a[q] = e[q] + o[q];
+        a[q + 8] = e[q] - o[q];
+    }
+}
+
+template <int RADIX, bool INV, typename R>
+FSA_HD void dft_zh(cpx<R>* a) {
+    if constexpr (RADIX == 2) a[1] = a[0];
+    else if constexpr (RADIX == 4) dft4_zh<INV>(a);
+    else if constexpr (RADIX == 8) dft8_zh<INV>(a);
+    else if constexpr (RADIX == 16) dft16_zh<INV>(a);
+    else static_assert(RADIX == 2, "zero-half first stage: radix 2, 4, 8 or 16");
+}
+
 template <int RADIX, bool INV, typename R>
 FSA_HD void dft(cpx<R>* a) {
     if constexpr (RADIX == 2) dft2<INV>(a);
@@ -353,6 +411,21 @@ constexpr bool fft_length_supported(long P) {
     return (m & (m - 1)) == 0;
 }
 
+#if defined(__HIPCC__)
+// Team index of the calling thread for teams of T threads.  A team of
+// T >= 64 threads spans whole waves (wave64), so its index is the same on
+// every lane of a wave; reading it from the first lane lets the compiler know
+// that, and the work-item, pencil and tensor-row arithmetic derived from it
+// runs once per wave on the scalar unit instead of on every lane.
+template <int T>
+__device__ __forceinline__ int team_index() {
+    const int t = (int)threadIdx.x / T;
+    if constexpr (T % 64 == 0) return __builtin_amdgcn_readfirstlane(t);
+    else return t;
+}
+
+#endif
+
 // ---------------------------------------------------------------------------
 // Team transform of length P, direction INV.
 // ---------------------------------------------------------------------------
@@ -395,8 +468,9 @@ struct Fft {
     }
     static constexpr int last_nbt() { return nbt(S - 1); }
 
-    // twiddle + butterfly of stage s on the registers
-    template <int s>
+    // twiddle + butterfly of stage s on the registers (ZH: stage 0 with the
+    // upper half of every butterfly's operands zero, see dft_zh)
+    template <int s, bool ZH = false>
     FSA_HD static void compute(C (&v)[V], int tid, const C* __restrict__ tw) {
         constexpr int RAD = radix(s), NS = ns(s), NB = nb(s), NBT = nbt(s);
         constexpr int STEP = P_ / (NS * RAD);
@@ -412,7 +486,8 @@ struct Fft {
                     v[b * RAD + q] = INV ? cmulc(v[b * RAD + q], w) : cmul(v[b * RAD + q], w);
                 }
             }
-            dft<RAD, INV>(&v[b * RAD]);
+            if constexpr (ZH && s == 0) dft_zh<RAD, INV>(&v[b * RAD]);
+            else dft<RAD, INV>(&v[b * RAD]);
         }
     }
 
@@ -449,7 +524,7 @@ struct Fft {
     }
 
     // stage s with twiddles from registers laid out like load_tw's
-    template <int s>
+    template <int s, bool ZH = false>
     FSA_HD static void compute_r(C (&v)[V], int tid, const C (&w)[NTW]) {
         constexpr int RAD = radix(s), NS = ns(s), NB = nb(s), NBT = nbt(s), OFF = tw_off(s);
 #pragma unroll
@@ -463,7 +538,8 @@ struct Fft {
                     v[b * RAD + q] = INV ? cmulc(v[b * RAD + q], t) : cmul(v[b * RAD + q], t);
                 }
             }
-            dft<RAD, INV>(&v[b * RAD]);
+            if constexpr (ZH && s == 0) dft_zh<RAD, INV>(&v[b * RAD]);
+            else dft<RAD, INV>(&v[b * RAD]);
         }
     }
 
@@ -613,9 +689,11 @@ struct Fft {
     }
 
     // twiddles from the (cached) global table, LDS-only synchronisation
+    // (ZH: the upper half of every first-stage operand set is zero)
+    template <bool ZH = false>
     static __device__ __forceinline__ void run_g(C (&v)[V], C* scr, int tid,
                                                  const C* __restrict__ tw) {
-        compute<0>(v, tid, tw);
+        compute<0, ZH>(v, tid, tw);
         run_g_from<1>(v, scr, tid, tw);
     }
 
@@ -627,8 +705,9 @@ struct Fft {
     static constexpr bool REG_TW = reg_tw(56);
 
     // run() with register twiddles and LDS-only synchronisation
+    template <bool ZH = false>
     static __device__ __forceinline__ void run_r(C (&v)[V], C* scr, int tid, const C (&w)[NTW]) {
-        compute_r<0>(v, tid, w);
+        compute_r<0, ZH>(v, tid, w);
         run_r_from<1>(v, scr, tid, w);
     }
 

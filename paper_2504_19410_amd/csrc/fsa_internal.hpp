@@ -14,6 +14,14 @@ struct fsa_plan_s;
 
 namespace fsa {
 
+// Launches a kernel and returns the launch status.
+template <typename... Params, typename... Args>
+inline hipError_t launch_kernel(void (*kernel)(Params...), dim3 grid, dim3 block,
+                                unsigned shmem, hipStream_t st, Args... args) {
+    hipLaunchKernelGGL(kernel, grid, block, shmem, st, static_cast<Params>(args)...);
+    return hipGetLastError();
+}
+
 struct KernelParams {
     int kind;
     double lam;

@@ -55,9 +55,8 @@ hipError_t go_r2c(const S& src, const void* tw, const void* tw2, int occ, hipStr
         return hipErrorInvalidValue;
     } else {
         static const int per_cu = blocks_per_cu(k_r2c<R, M, VAR, S>, K::THREADS);
-        hipLaunchKernelGGL((k_r2c<R, M, VAR, S>), dim3(persistent_grid(per_cu, occ, src.total)),
-                           dim3(K::THREADS), 0, st, src, (const cpx<R>*)tw, (const cpx<R>*)tw2);
-        return hipGetLastError();
+        return launch_kernel(k_r2c<R, M, VAR, S>, dim3(persistent_grid(per_cu, occ, src.total)),
+                             dim3(K::THREADS), 0, st, src, (const cpx<R>*)tw, (const cpx<R>*)tw2);
     }
 }
 
@@ -68,9 +67,8 @@ hipError_t go_c2r(const S& src, const void* tw, const void* tw2, int occ, hipStr
         return hipErrorInvalidValue;
     } else {
         static const int per_cu = blocks_per_cu(k_c2r<R, M, VAR, S>, K::THREADS);
-        hipLaunchKernelGGL((k_c2r<R, M, VAR, S>), dim3(persistent_grid(per_cu, occ, src.total)),
-                           dim3(K::THREADS), 0, st, src, (const cpx<R>*)tw, (const cpx<R>*)tw2);
-        return hipGetLastError();
+        return launch_kernel(k_c2r<R, M, VAR, S>, dim3(persistent_grid(per_cu, occ, src.total)),
+                             dim3(K::THREADS), 0, st, src, (const cpx<R>*)tw, (const cpx<R>*)tw2);
     }
 }
 
@@ -81,10 +79,9 @@ hipError_t go_fwd_t(const S& src, const void* tw, int occ, hipStream_t st) {
         return hipErrorInvalidValue;
     } else {
         static const int per_cu = blocks_per_cu(k_fwd_t<R, P, VAR, S>, K::THREADS);
-        hipLaunchKernelGGL((k_fwd_t<R, P, VAR, S>),
-                           dim3(persistent_grid(per_cu, occ, src.total)), dim3(K::THREADS), 0, st,
-                           src, (const cpx<R>*)tw);
-        return hipGetLastError();
+        return launch_kernel(k_fwd_t<R, P, VAR, S>,
+                             dim3(persistent_grid(per_cu, occ, src.total)), dim3(K::THREADS), 0, st,
+                             src, (const cpx<R>*)tw);
     }
 }
 
@@ -95,10 +92,9 @@ hipError_t go_inv_t(const S& src, const void* tw, int occ, hipStream_t st) {
         return hipErrorInvalidValue;
     } else {
         static const int per_cu = blocks_per_cu(k_inv_t<R, P, VAR, S>, K::THREADS);
-        hipLaunchKernelGGL((k_inv_t<R, P, VAR, S>),
-                           dim3(persistent_grid(per_cu, occ, src.total)), dim3(K::THREADS), 0, st,
-                           src, (const cpx<R>*)tw);
-        return hipGetLastError();
+        return launch_kernel(k_inv_t<R, P, VAR, S>,
+                             dim3(persistent_grid(per_cu, occ, src.total)), dim3(K::THREADS), 0, st,
+                             src, (const cpx<R>*)tw);
     }
 }
 
@@ -109,10 +105,9 @@ hipError_t go_conv(const S& src, const void* tw, int occ, hipStream_t st) {
         return hipErrorInvalidValue;
     } else {
         static const int per_cu = blocks_per_cu(k_conv<R, P, VAR, S>, K::THREADS);
-        hipLaunchKernelGGL((k_conv<R, P, VAR, S>),
-                           dim3(persistent_grid(per_cu, occ, cdiv(src.total, K::TPW))),
-                           dim3(K::THREADS), 0, st, src, (const cpx<R>*)tw);
-        return hipGetLastError();
+        return launch_kernel(k_conv<R, P, VAR, S>,
+                             dim3(persistent_grid(per_cu, occ, cdiv(src.total, K::TPW))),
+                             dim3(K::THREADS), 0, st, src, (const cpx<R>*)tw);
     }
 }
 

@@ -165,7 +165,7 @@ __global__ __launch_bounds__((R2c<R, M, VAR>::THREADS)) void k_r2c(
     using F = typename K::F;
     using C = cpx<R>;
     __shared__ C lds[K::LDS];
-    const int team = threadIdx.x / K::T, tid0 = threadIdx.x % K::T;
+    const int team = team_index<K::T>(), tid0 = threadIdx.x % K::T;
     const int tid = tid0;
     C* scr = lds + team * F::SCR;
     C w[F::REG_TW ? F::NTW : 1];
@@ -213,8 +213,8 @@ __global__ __launch_bounds__((R2c<R, M, VAR>::THREADS)) void k_r2c(
             for (int q = 0; q < K::R0; ++q)
                 v[b * K::R0 + q] = (q < K::HALF && active) ? pf[b * K::HALF + q] : mk(R(0), R(0));
         if (item + 1 < ch.last) prefetch(item + 1);
-        if constexpr (F::REG_TW) F::run_r(v, scr, tid, w);
-        else F::run_g(v, scr, tid, twM);
+        if constexpr (F::REG_TW) F::template run_r<true>(v, scr, tid, w);
+        else F::template run_g<true>(v, scr, tid, twM);
         F::store_last(v, tid, M, [&](int k, C z) { scr[F::pad(k)] = z; });
         F::sync_lds();
         C x[K::NX];
@@ -280,7 +280,7 @@ __global__ __launch_bounds__((C2r<R, M, VAR>::THREADS)) void k_c2r(
     using F = typename K::F;
     using C = cpx<R>;
     __shared__ C lds[K::LDS];
-    const int team = threadIdx.x / K::T, tid0 = threadIdx.x % K::T;
+    const int team = team_index<K::T>(), tid0 = threadIdx.x % K::T;
     const int tid = tid0;
     C* scr = lds + team * F::SCR;
     C w[F::REG_TW ? F::NTW : 1];
@@ -395,7 +395,7 @@ __global__ __launch_bounds__((FwdT<R, P, VAR>::THREADS)) void k_fwd_t(
     using C = cpx<R>;
     constexpr int N1 = P / 2;
     __shared__ C lds[K::LDS];
-    const int team = threadIdx.x / K::T, tid0 = threadIdx.x % K::T;
+    const int team = team_index<K::T>(), tid0 = threadIdx.x % K::T;
     const int tid = tid0;
     C* scr = lds + team * F::SCR;
     C w[F::REG_TW ? F::NTW : 1];
@@ -436,8 +436,8 @@ __global__ __launch_bounds__((FwdT<R, P, VAR>::THREADS)) void k_fwd_t(
             for (int q = 0; q < K::R0; ++q)
                 v[b * K::R0 + q] = (q < K::HALF && active) ? pf[b * K::HALF + q] : mk(R(0), R(0));
         if (item + 1 < ch.last) prefetch(item + 1);
-        if constexpr (F::REG_TW) F::run_r(v, scr, tid, w);
-        else F::run_g(v, scr, tid, tw);
+        if constexpr (F::REG_TW) F::template run_r<true>(v, scr, tid, w);
+        else F::template run_g<true>(v, scr, tid, tw);
         sync_wg_lds();
         F::store_last(v, tid, P, [&](int p1, C c) { lds[p1 * K::TS + team] = c; });
         sync_wg_lds();
@@ -479,7 +479,7 @@ __global__ __launch_bounds__((InvT<R, P, VAR>::THREADS)) void k_inv_t(
     using C = cpx<R>;
     constexpr int N1 = P / 2;
     __shared__ C lds[K::LDS];
-    const int team = threadIdx.x / K::T, tid0 = threadIdx.x % K::T;
+    const int team = team_index<K::T>(), tid0 = threadIdx.x % K::T;
     const int tid = tid0;
     C* scr = lds + team * F::SCR;
     C w[F::REG_TW ? F::NTW : 1];
@@ -595,7 +595,7 @@ __global__ __launch_bounds__((Conv<R, P, VAR>::THREADS)) void k_conv(
     using C = cpx<R>;
     constexpr int N0 = P / 2;
     __shared__ C lds[K::LDS];
-    const int team = threadIdx.x / K::T, tid0 = threadIdx.x % K::T;
+    const int team = team_index<K::T>(), tid0 = threadIdx.x % K::T;
     const int tid = tid0;
     C* scr = lds + team * Ff::SCR;
 
@@ -613,8 +613,10 @@ __global__ __launch_bounds__((Conv<R, P, VAR>::THREADS)) void k_conv(
     const int chunk = (total + slots - 1) / slots;
     const int first = (blockIdx.x * K::TPW + team) * chunk;
 
-    C pf[K::NPF];
-    auto prefetch = [&](int item) {
+    // two prefetch buffers used in turn: item i + 1 loads into one while item
+    // i computes from the other, so no register copies are needed
+    C pfa[K::NPF], pfb[K::NPF];
+    auto prefetch = [&](C (&pf)[K::NPF], int item) {
         if (item < total) {
             int loc;
             const JobConv jb = src.get(item, loc);
@@ -629,8 +631,7 @@ __global__ __launch_bounds__((Conv<R, P, VAR>::THREADS)) void k_conv(
                 }
         }
     };
-    prefetch(first);
-    for (int it = 0; it < chunk; ++it) {
+    auto process = [&](const C (&pf)[K::NPF], int it) {
         const int tid = fresh_lane<R, P>() ? opaque(tid0) : tid0;  // per item: fresh_lane
         const int item = first + it;
         const bool active = item < total;
@@ -642,7 +643,6 @@ __global__ __launch_bounds__((Conv<R, P, VAR>::THREADS)) void k_conv(
 #pragma unroll
             for (int q = 0; q < K::R0; ++q)
                 v[b * K::R0 + q] = q < K::HALF ? pf[b * K::HALF + q] : mk(R(0), R(0));
-        if (it + 1 < chunk) prefetch(item + 1);
         const int qp = conv_item_to_pencil(loc, jb.P1, jb.N1) + jb.p2_lo * jb.P1;
         const int p2 = qp / jb.P1, p1 = qp - p2 * jb.P1;
         const int a1 = p1 <= jb.N1 ? p1 : jb.P1 - p1;
@@ -652,8 +652,8 @@ __global__ __launch_bounds__((Conv<R, P, VAR>::THREADS)) void k_conv(
             int i = 0;
             Ff::for_each_last(v, tid, [&](int p0, C&) { tv[i++] = trow[p0 <= N0 ? p0 : P - p0]; });
         }
-        if constexpr (REG) Ff::run_r(v, scr, tid, wf);
-        else Ff::run_g(v, scr, tid, tw);
+        if constexpr (REG) Ff::template run_r<true>(v, scr, tid, wf);
+        else Ff::template run_g<true>(v, scr, tid, tw);
         {
             int i = 0;
             Ff::for_each_last(v, tid, [&](int, C& c) { c = scale(c, tv[i++]); });
@@ -665,6 +665,14 @@ __global__ __launch_bounds__((Conv<R, P, VAR>::THREADS)) void k_conv(
             C* pen = (C*)jb.data + (size_t)qp * N0;
             Fi::store_last(v, tid, N0, [&](int i, C c) { pen[i] = c; });
         }
+    };
+    prefetch(pfa, first);
+    for (int it = 0; it < chunk; it += 2) {
+        if (it + 1 < chunk) prefetch(pfb, first + it + 1);
+        process(pfa, it);
+        if (it + 1 >= chunk) break;
+        if (it + 2 < chunk) prefetch(pfa, first + it + 2);
+        process(pfb, it + 1);
     }
 }
 

@@ -99,7 +99,7 @@ __global__ __launch_bounds__((Spec<R, P>::THREADS)) void k_spec(const void* in,
     using C = cpx<R>;
     __shared__ C lds[K::LDS];
     C* const tile = lds;  // [t][w], also the teams' scratch while they transform
-    const int team = threadIdx.x / K::T, tid = threadIdx.x % K::T;
+    const int team = team_index<K::T>(), tid = threadIdx.x % K::T;
     const int ntu = (ln.n_u + K::WT - 1) / K::WT;
     const int tu = blockIdx.x % ntu, v = blockIdx.x / ntu;
     const long base = (long)tu * K::WT * ln.u_stride + (long)v * ln.v_stride;
@@ -217,9 +217,8 @@ hipError_t go(int P, const void* in, void* out, SLines ln, const void* tw, const
     case p: {                                                                                   \
         using K = Spec<R, p>;                                                                   \
         const int groups = (ln.n_u + K::WT - 1) / K::WT * ln.n_v;                               \
-        hipLaunchKernelGGL((k_spec<R, p, KIND>), dim3(groups), dim3(K::THREADS), 0, st, in,     \
-                           out, ln, (const cpx<R>*)tw, mul);                                    \
-        return hipGetLastError();                                                               \
+        return launch_kernel(k_spec<R, p, KIND>, dim3(groups), dim3(K::THREADS), 0, st, in, out, \
+                             ln, (const cpx<R>*)tw, mul);                                       \
     }
         FSA_SPEC_CASE(8) FSA_SPEC_CASE(12) FSA_SPEC_CASE(16) FSA_SPEC_CASE(24) FSA_SPEC_CASE(32)
         FSA_SPEC_CASE(48) FSA_SPEC_CASE(64) FSA_SPEC_CASE(96) FSA_SPEC_CASE(128)

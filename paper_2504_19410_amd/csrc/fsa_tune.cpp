@@ -529,8 +529,10 @@ fsa_status fsa_autotune(fsa_plan pl, const void* rho, void* phi, void* workspace
     load_env_once();
     hipStream_t st = (hipStream_t)stream;
     hipEvent_t ev[2] = {nullptr, nullptr};
-    hipError_t e = hipEventCreate(&ev[0]);
-    if (e == hipSuccess) e = hipEventCreate(&ev[1]);
+    // timing events without the system-scope fence of a default event, whose
+    // cache write-back and invalidation would give the timed launch a cold L2
+    hipError_t e = hipEventCreateWithFlags(&ev[0], hipEventDisableSystemFence);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&ev[1], hipEventDisableSystemFence);
     const int np = fsa::n_passes(pl);
     const int H = (int)pl->H;
     auto whole = [&](int k) { return fsa::Step{k, 0, H}; };

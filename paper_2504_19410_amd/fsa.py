@@ -333,7 +333,9 @@ class Plan:
     def apply_events(self, rho: torch.Tensor, out: torch.Tensor, events,
                      workspace: Optional[torch.Tensor] = None,
                      stream: Optional[torch.cuda.Stream] = None) -> torch.Tensor:
-        """fsa_apply with caller-created hipEvent_t handles recorded around each pass."""
+        """fsa_apply with caller-created hipEvent_t handles, two per launch,
+        recorded right before and right after each launch (None, None: that
+        launch untimed)."""
         self.check_input(rho)
         self.check_input(out)
         ws = workspace if workspace is not None else self.workspace()

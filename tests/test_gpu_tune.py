@@ -253,18 +253,36 @@ def test_apply_events_follow_the_schedule(F):
     assert n == 14
     lib = ctypes.CDLL("libamdhip64.so")
     evs = []
-    for _ in range(n + 1):
+    for _ in range(2 * n):
         e = ctypes.c_void_p()
         assert lib.hipEventCreate(ctypes.byref(e)) == 0
         evs.append(e.value)
     out = torch.empty_like(rho)
     with pytest.raises(F.FsaError, match="EINVAL"):
-        plan.apply_events(rho, out, evs[:n])          # one event short
+        plan.apply_events(rho, out, evs[:-1])          # one event short
     plan.apply_events(rho, out, evs)
     torch.cuda.synchronize()
     ref = plan.apply(rho)
     torch.cuda.synchronize()
     assert torch.equal(out, ref)
+    # every launch's pair brackets it: positive durations that follow each
+    # other in stream order
+    f = ctypes.c_float()
+    for i in range(n):
+        assert lib.hipEventElapsedTime(ctypes.byref(f), ctypes.c_void_p(evs[2 * i]),
+                                       ctypes.c_void_p(evs[2 * i + 1])) == 0
+        assert f.value > 0.0
+        if i:
+            assert lib.hipEventElapsedTime(ctypes.byref(f), ctypes.c_void_p(evs[2 * i - 1]),
+                                           ctypes.c_void_p(evs[2 * i])) == 0
+            assert f.value >= 0.0
+    # a null pair leaves its launch untimed; one null event of a pair is EINVAL
+    part = [e if i // 2 == 2 else None for i, e in enumerate(evs)]
+    plan.apply_events(rho, out, part)
+    torch.cuda.synchronize()
+    assert torch.equal(out, ref)
+    with pytest.raises(F.FsaError, match="one null event"):
+        plan.apply_events(rho, out, [e if i != 3 else None for i, e in enumerate(evs)])
     for e in evs:
         lib.hipEventDestroy(ctypes.c_void_p(e))
 
