@@ -62,6 +62,28 @@ def model_bytes(N, prec):
     return {"A_r2c": M * r + X, "C_conv": 2 * X + Tb, "E_c2r": X + M * r}
 
 
+def precomp_model(N, prec):
+    """Algorithmic HBM bytes and nominal FLOPs of one tensor build (Precomp).
+
+    Bytes: the octant (prod_j (N_j + 1) values) is written in FP64 by the
+    first axis' DCT (which generates T(1) itself), read and written by each
+    middle axis, read by the last axis, which writes the tensor in the plan
+    precision.  FLOPs: 5 P log2 P per complex FFT of length P = 2 N_j, one
+    FFT per pair of lines of each axis (the special functions of T(1) and W
+    are not counted)."""
+    D = [n + 1 for n in N]
+    octant = 1
+    for x in D:
+        octant *= x
+    r = 4 if prec == "f32" else 8
+    nbytes = (8 + 16 * (len(N) - 2) + 8 + r) * octant
+    flops = 0.0
+    for j, n in enumerate(N):
+        P = 2 * n
+        flops += (octant / D[j]) / 2 * 5 * P * math.log2(P)
+    return nbytes, flops
+
+
 class Hip:
     def __init__(self):
         self.lib = ctypes.CDLL("libamdhip64.so")
@@ -176,14 +198,11 @@ def bench_precision(F, torch, hip, prob, rho64, prec, steps, warmup, tune=True):
     dtype = F.DTYPES[prec]
     stream = torch.cuda.current_stream()
     plan = F.Plan(prob.kernel, prob.L, prob.N, prec, eps=prob.eps, lam=prob.lam)
-    # Precomp: tensor generation, timed with events on the same stream
+    # Precomp: tensor generation, timed with events on the same stream (the
+    # first build also allocates the tensor and twiddles; median of 9 builds)
     e0, e1 = hip.event(), hip.event()
-    plan.build()  # first build also allocates the tensor and twiddles
-    torch.cuda.synchronize()
-    hip.record(e0, stream)
     plan.build()
-    hip.record(e1, stream)
-    precomp_ms = hip.ms(e0, e1)
+    precomp_ms = timed_evals(lambda: plan.build(), torch, hip, 9, 2, settle_s=0.1)["median_ms"]
     rho = torch.from_numpy(rho64).to(dtype).cuda()
     out = torch.empty_like(rho)
     ws = plan.workspace()
@@ -233,9 +252,14 @@ def bench_precision(F, torch, hip, prob, rho64, prec, steps, warmup, tune=True):
     dom_key = f"{dom_pass}_{prec}_{dom_len}_v{dom_var}"
     slabs = F.tune_get_slabs(prec, plan.N)[0] if plan.d == 3 else 1
     traffic = measured_traffic(dom_key, prec, slabs)
+    pb, pf = precomp_model(prob.N, prec)
     return {
         "value": pts / (ms * 1e-3),
         "ms_per_step": ms,
+        "precomp": {"ms": precomp_ms, "model_bytes": pb, "nominal_fft_flops": pf,
+                    "achieved_GBps": pb / (precomp_ms * 1e-3) / 1e9,
+                    "hbm_frac": pb / (precomp_ms * 1e-3) / HBM_PEAK_BPS,
+                    "fp64_frac": pf / (precomp_ms * 1e-3) / 78.6e12},
         "mean_ms_per_step": timing["mean_ms"],
         "first_ms": timing["first_ms"],
         "wall_ms_per_step": timing["wall_ms"] / steps,
@@ -265,26 +289,15 @@ def bench_precision(F, torch, hip, prob, rho64, prec, steps, warmup, tune=True):
     }, phi
 
 
-def precomp_sweep(F, torch, hip, n=256, gammas=(1, 2, 4, 8, 16), reps=3):
+def precomp_sweep(F, torch, hip, n=256, gammas=(1, 2, 4, 8, 16), reps=5):
     """Tensor generation (Precomp) time against anisotropy: 3D Coulomb on
     [-8,8]^2 x [-8/g, 8/g] at n^3 (h_z = h/g), eps = R0/8; the paper reports
     FSA's precomputation as independent of the anisotropy (Sec. 5.1)."""
-    stream = torch.cuda.current_stream()
     out = {}
     for g in gammas:
-        plan = F.Plan("coulomb3d", (8.0, 8.0, 8.0 / g), (n, n, n), "f32").build()
-        torch.cuda.synchronize()
-        e0, e1 = hip.event(), hip.event()
-        ts = []
-        for _ in range(reps):
-            hip.record(e0, stream)
-            plan.build()
-            hip.record(e1, stream)
-            ts.append(hip.ms(e0, e1))
-        hip.destroy(e0)
-        hip.destroy(e1)
+        plan = F.Plan("coulomb3d", (8.0, 8.0, 8.0 / g), (n, n, n), "f32")
+        out[str(g)] = round(_time_build(plan, torch, hip, reps), 3)
         plan.close()
-        out[str(g)] = round(sorted(ts)[reps // 2], 3)
     return {"grid": [n, n, n], "kernel": "coulomb3d", "ms_by_anisotropy": out}
 
 
@@ -306,20 +319,10 @@ def bench_ddi(F, torch, hip, synth, n=256, steps=50, warmup=10):
             "unit": "grid pts/s", **out}
 
 
-def _time_build(plan, torch, hip, reps=3):
-    stream = torch.cuda.current_stream()
+def _time_build(plan, torch, hip, reps=5):
+    """Median event-timed tensor build (see timed_evals)."""
     plan.build()
-    torch.cuda.synchronize()
-    e0, e1 = hip.event(), hip.event()
-    ts = []
-    for _ in range(reps):
-        hip.record(e0, stream)
-        plan.build()
-        hip.record(e1, stream)
-        ts.append(hip.ms(e0, e1))
-    hip.destroy(e0)
-    hip.destroy(e1)
-    return sorted(ts)[reps // 2]
+    return timed_evals(lambda: plan.build(), torch, hip, reps, 1, settle_s=0.05)["median_ms"]
 
 
 def _time_apply(plan, rho, torch, hip, steps=20, warmup=5, settle_s=0.05):
@@ -927,7 +930,7 @@ def main():
                 "pass_ms": r["pass_ms"], "model_bytes_per_step": r["model_bytes_per_step"],
                 "model_hbm_frac": r["model_hbm_frac"],
                 "model_copy_frac": r["model_bytes_per_step"] / (r["ms_per_step"] * 1e-3) / copy_bps,
-                "precomp_ms": r["precomp_ms"], "tuned": r["tuned"]}
+                "precomp_ms": r["precomp_ms"], "precomp": r["precomp"], "tuned": r["tuned"]}
 
     line = {
         "metric": METRIC,
@@ -966,6 +969,7 @@ def main():
         "model_bytes_per_step": r64["model_bytes_per_step"],
         "model_hbm_frac": r64["model_hbm_frac"],
         "precomp_ms": r64["precomp_ms"],
+        "precomp": r64["precomp"],
         "precomp_vs_anisotropy": sweep,
         "ddi": ddi,
         "general": general,

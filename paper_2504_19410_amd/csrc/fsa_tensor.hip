@@ -340,39 +340,42 @@ __device__ double d_what_cheb(const double* __restrict__ cf, double dk, int nq, 
     return c[0] + s * b1 - b2;
 }
 
-struct Oct {
-    int D0, D1, D2;
-    __device__ void split(long i, int& a0, int& a1, int& a2) const {
-        a0 = (int)(i % D0);
-        const long r = i / D0;
-        a1 = (int)(r % D1);
-        a2 = (int)(r / D1);
-    }
-    __device__ long size() const { return (long)D0 * D1 * D2; }
+// W of the general construction: Chebyshev coefficients cf of nq panels of
+// width dk (null for the closed forms).
+struct WTable {
+    const double* cf;
+    double dk;
+    int nq;
 };
-
-__global__ void k_sample(double* __restrict__ out, Oct o, double h0, double h1, double h2,
-                         double hprod, KernelParams kp) {
-    const long n = o.size();
-    for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n;
-         i += (long)gridDim.x * blockDim.x) {
-        int a0, a1, a2;
-        o.split(i, a0, a1, a2);
-        const double x = a0 * h0, y = a1 * h1, z = a2 * h2;
-        const double r = sqrt(x * x + y * y + z * z);
-        out[i] = hprod * (kp.general ? d_ueps_general(kp, r) : d_ueps(kp, r));
-    }
-}
 
 // DCT-I of every octant line along one axis, as the real part of the
 // length-2N DFT of the line's even extension (x[n] for n <= N, x[2N - n]
 // above), which is sum_n c_n x[n] cos(pi p n / N), c_0 = c_N = 1, else 2.
-// A workgroup takes WT lines that are adjacent in the array, stages them
-// through LDS (coalesced along the contiguous direction), and each of its
-// teams runs the FP64 team FFT of length P = 2N on one line.
+// The even extension of a real line has a real DFT, so two lines share one
+// complex transform: line a in the real part, line b in the imaginary part,
+// and DFT(a + i b) = DFT(a) + i DFT(b) returns both, exactly, in its real and
+// imaginary parts.  A workgroup takes WT lines that are adjacent in the
+// array, stages them through LDS (coalesced along the contiguous direction),
+// and each of its WT/2 teams runs the FP64 team FFT of length P = 2N on one
+// pair.  The first axis generates its input instead of reading it:
+// T(1)_n = prod_j h_j U^eps(|n h|) (eq. Tensor1 / TensorAnis); the last axis
+// adds W(|k|) (eq. FouTran, or the general construction's table), scales by
+// 1 / prod_j P_j and writes the tensor in the plan precision.
+enum class DctStage { FIRST, MID, LAST };
+
+// The tile of lines and the teams' FFT scratch share one LDS array (the
+// tile is dead while the transforms run), so its size is the larger of the
+// two.
+constexpr int dct_lds_bytes(int wt, int scr, int D) {
+    return (wt / 2) * scr * 16 > D * (wt + 1) * 8 ? (wt / 2) * scr * 16 : D * (wt + 1) * 8;
+}
+
 constexpr int dct_lines_per_group(int T, int scr, int D) {
-    int wt = 8;
-    while (wt > 1 && (wt * T > 1024 || wt * scr * 16 + D * (wt + 1) * 8 > 160 * 1024)) wt /= 2;
+    // up to 16 lines (128-byte rows on the strided axes); at most 1024
+    // threads; LDS within half a CU's 160 KB where possible so that two
+    // workgroups share a CU
+    int wt = 16;
+    while (wt > 2 && ((wt / 2) * T > 1024 || dct_lds_bytes(wt, scr, D) > 80 * 1024)) wt /= 2;
     return wt;
 }
 
@@ -382,27 +385,72 @@ struct Dct {
     static constexpr int N = P / 2, D = N + 1;
     static constexpr int T = F::T;
     static constexpr int WT = dct_lines_per_group(T, F::SCR, D);
+    static constexpr int TEAMS = WT / 2;
     static constexpr int TS = WT + 1;
-    static constexpr int THREADS = WT * T;
+    static constexpr int THREADS = TEAMS * T;
+    static constexpr int LDS_C = (dct_lds_bytes(WT, F::SCR, D) + 15) / 16;  // complex slots
+    static_assert(LDS_C * 16 <= 160 * 1024, "DCT workgroup exceeds the LDS");
 };
 
 // Lines of one axis: line (u, v) starts at u * u_stride + v * v_stride and
-// its element t sits at + t * es; groups take WT consecutive u.
+// its element t sits at + t * es; groups take WT consecutive u.  Octant
+// coordinates: a[ax] = t, and (u, v) are the other two in increasing order.
 struct Lines {
     int n_u, n_v;
     long u_stride, v_stride, es;
+    int ax;
 };
 
-template <int P>
+// Generation of T(1) (first axis) and the finishing of T^ (last axis).
+// When the mesh is the same on every axis, |n h|^2 = h^2 m and |k|^2 = c^2 m
+// with the integer m = sum_j a_j^2, and T(1) and W take one value per m:
+// t1_tab[m] = hprod U^eps(h sqrt m) and w_tab[m] = W(c sqrt m) are computed
+// once (k_radial) and looked up, instead of evaluating the special functions
+// at every octant point (a 256^3 octant has 1.7e7 points and 196 609 values
+// of m).
+struct DctEnds {
+    KernelParams kp;
+    double h[3], hprod;          // T(1) = hprod U^eps(|(a_j h_j)|)
+    double c[3], inv_prod_p;     // k_j = a_j c_j; T^ = (DCT + W(|k|)) inv_prod_p
+    WTable wt;
+    const double* t1_tab;        // radial tables (null: evaluate directly)
+    const double* w_tab;
+    void* out;                   // the tensor, float or double
+};
+
+// T(1) or W at r = step sqrt(m), m = 0 .. n-1
+template <bool T1>
+__global__ void k_radial(double* __restrict__ tab, long n, double step, DctEnds ends) {
+    const long m = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    if (m >= n) return;
+    const double r = step * sqrt((double)m);
+    if constexpr (T1) {
+        tab[m] = ends.hprod * (ends.kp.general ? d_ueps_general(ends.kp, r) : d_ueps(ends.kp, r));
+    } else {
+        tab[m] = ends.wt.cf ? d_what_cheb(ends.wt.cf, ends.wt.dk, ends.wt.nq, r)
+                            : d_what(ends.kp, r);
+    }
+}
+
+__device__ __forceinline__ void octant_coords(const Lines& ln, int u, int v, int t, int (&a)[3]) {
+    if (ln.ax == 0) { a[0] = t; a[1] = u; a[2] = v; }
+    else if (ln.ax == 1) { a[0] = u; a[1] = t; a[2] = v; }
+    else { a[0] = u; a[1] = v; a[2] = t; }
+}
+
+// TAB: the first / last axis looks T(1) / W up in the radial table.
+template <int P, DctStage STAGE, typename R, bool TAB>
 __global__ __launch_bounds__(Dct<P>::THREADS) void k_dct(const double* __restrict__ in,
                                                         double* __restrict__ out, Lines ln,
-                                                        const cpx<double>* __restrict__ tw) {
+                                                        const cpx<double>* __restrict__ tw,
+                                                        DctEnds ends) {
     using K = Dct<P>;
     using F = typename K::F;
     using C = cpx<double>;
-    __shared__ C scr[K::WT * F::SCR];
-    __shared__ double tile[K::D * K::TS];
-    const int team = threadIdx.x / K::T, tid = threadIdx.x % K::T;
+    __shared__ C lds[K::LDS_C];
+    C* scr = lds;                                   // teams' FFT scratch ...
+    double* tile = reinterpret_cast<double*>(lds);  // ... and the tile, in turn
+    const int team = team_index<K::T>(), tid = threadIdx.x % K::T;
     const int ntu = (ln.n_u + K::WT - 1) / K::WT;
     const int tu = blockIdx.x % ntu, v = blockIdx.x / ntu;
     const long base = (long)tu * K::WT * ln.u_stride + (long)v * ln.v_stride;
@@ -417,38 +465,122 @@ __global__ __launch_bounds__(Dct<P>::THREADS) void k_dct(const double* __restric
             w = e - t * K::WT;
         }
     };
-    for (int e = threadIdx.x; e < K::D * K::WT; e += K::THREADS) {
+    // Tile elements e = threadIdx.x + k THREADS, k < EPT: the load and the
+    // store loops visit the same elements in the same order.  Direct
+    // evaluation takes one element per iteration (the special functions need
+    // many registers, and unrolled copies would cost the FFT its occupancy);
+    // table lookups and plain copies are unrolled so that their loads are in
+    // flight together, and the last axis gathers its W values here, so that
+    // they arrive while the transforms run.
+    constexpr int EPT = (K::D * K::WT + K::THREADS - 1) / K::THREADS;
+    constexpr bool DIRECT = !TAB && STAGE == DctStage::FIRST;
+    auto load_one = [&](int e) {
         int t, w;
         at(e, t, w);
-        tile[t * K::TS + w] = w < nw ? in[base + w * ln.u_stride + t * ln.es] : 0.0;
+        double x = 0.0;
+        if (w < nw) {
+            if constexpr (STAGE == DctStage::FIRST) {
+                int a[3];
+                octant_coords(ln, tu * K::WT + w, v, t, a);
+                if constexpr (TAB) {
+                    x = ends.t1_tab[a[0] * a[0] + a[1] * a[1] + a[2] * a[2]];
+                } else {
+                    const double x0 = a[0] * ends.h[0], x1 = a[1] * ends.h[1],
+                                 x2 = a[2] * ends.h[2];
+                    const double r = sqrt(x0 * x0 + x1 * x1 + x2 * x2);
+                    x = ends.hprod * (ends.kp.general ? d_ueps_general(ends.kp, r)
+                                                      : d_ueps(ends.kp, r));
+                }
+            } else {
+                x = in[base + w * ln.u_stride + t * ln.es];
+            }
+        }
+        tile[t * K::TS + w] = x;
+    };
+    constexpr bool WGATHER = TAB && STAGE == DctStage::LAST;
+    double wv[WGATHER ? EPT : 1];
+    if constexpr (DIRECT) {
+#pragma unroll 1
+        for (int k = 0; k < EPT; ++k) {
+            const int e = threadIdx.x + k * K::THREADS;
+            if (e < K::D * K::WT) load_one(e);
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < EPT; ++k) {
+            const int e = threadIdx.x + k * K::THREADS;
+            if (e < K::D * K::WT) {
+                load_one(e);
+                if constexpr (WGATHER) {
+                    int t, w, a[3];
+                    at(e, t, w);
+                    octant_coords(ln, tu * K::WT + w, v, t, a);
+                    wv[k] = w < nw ? ends.w_tab[a[0] * a[0] + a[1] * a[1] + a[2] * a[2]] : 0.0;
+                }
+            }
+        }
     }
     __syncthreads();
-    C x[F::V];
-    F::load_first(x, tid, P, [&](int i) {
+    C z[F::V];
+    F::load_first(z, tid, P, [&](int i) {
         const int t = i <= K::N ? i : P - i;
-        return mk(tile[t * K::TS + team], 0.0);
+        return mk(tile[t * K::TS + 2 * team], tile[t * K::TS + 2 * team + 1]);
     });
     __syncthreads();
-    F::run_g(x, scr + team * F::SCR, tid, tw);
-    F::store_last(x, tid, K::D, [&](int p, C c) { tile[p * K::TS + team] = c.x; });
+    F::run_g(z, scr + team * F::SCR, tid, tw);
     __syncthreads();
-    for (int e = threadIdx.x; e < K::D * K::WT; e += K::THREADS) {
+    F::store_last(z, tid, K::D, [&](int p, C c) {
+        tile[p * K::TS + 2 * team] = c.x;
+        tile[p * K::TS + 2 * team + 1] = c.y;
+    });
+    __syncthreads();
+    auto store_one = [&](int e, int k) {
         int t, w;
         at(e, t, w);
-        if (w < nw) out[base + w * ln.u_stride + t * ln.es] = tile[t * K::TS + w];
+        if (w >= nw) return;
+        const long o = base + w * ln.u_stride + t * ln.es;
+        if constexpr (STAGE == DctStage::LAST) {
+            double wk;
+            if constexpr (TAB) {
+                wk = wv[k];
+            } else {
+                int a[3];
+                octant_coords(ln, tu * K::WT + w, v, t, a);
+                const double k0 = a[0] * ends.c[0], k1 = a[1] * ends.c[1], k2 = a[2] * ends.c[2];
+                const double kk = sqrt(k0 * k0 + k1 * k1 + k2 * k2);
+                wk = ends.wt.cf ? d_what_cheb(ends.wt.cf, ends.wt.dk, ends.wt.nq, kk)
+                                : d_what(ends.kp, kk);
+            }
+            ((R*)ends.out)[o] = (R)((tile[t * K::TS + w] + wk) * ends.inv_prod_p);
+        } else {
+            out[o] = tile[t * K::TS + w];
+        }
+    };
+    if constexpr (!TAB && STAGE == DctStage::LAST) {
+#pragma unroll 1
+        for (int k = 0; k < EPT; ++k) {
+            const int e = threadIdx.x + k * K::THREADS;
+            if (e < K::D * K::WT) store_one(e, k);
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < EPT; ++k) {
+            const int e = threadIdx.x + k * K::THREADS;
+            if (e < K::D * K::WT) store_one(e, k);
+        }
     }
 }
 
+template <DctStage STAGE, typename R, bool TAB>
 hipError_t dct_axis(const double* in, double* out, Lines ln, int N, const void* tw,
-                    hipStream_t st) {
+                    const DctEnds& ends, hipStream_t st) {
     switch (2 * N) {
 #define FSA_DCT_CASE(p)                                                                         \
     case p: {                                                                                   \
         using K = Dct<p>;                                                                       \
         const int groups = (ln.n_u + K::WT - 1) / K::WT * ln.n_v;                               \
-        hipLaunchKernelGGL(k_dct<p>, dim3(groups), dim3(K::THREADS), 0, st, in, out, ln,        \
-                           (const cpx<double>*)tw);                                             \
-        return hipGetLastError();                                                               \
+        return launch_kernel(k_dct<p, STAGE, R, TAB>, dim3(groups), dim3(K::THREADS), 0, st,    \
+                             in, out, ln, (const cpx<double>*)tw, ends);                         \
     }
         FSA_DCT_CASE(16) FSA_DCT_CASE(24) FSA_DCT_CASE(32) FSA_DCT_CASE(48) FSA_DCT_CASE(64)
         FSA_DCT_CASE(96) FSA_DCT_CASE(128) FSA_DCT_CASE(192) FSA_DCT_CASE(256) FSA_DCT_CASE(384)
@@ -457,29 +589,6 @@ hipError_t dct_axis(const double* in, double* out, Lines ln, int N, const void* 
 #undef FSA_DCT_CASE
     }
     return hipErrorInvalidValue;
-}
-
-// W of the general construction: Chebyshev coefficients cf of nq panels of
-// width dk (null for the closed forms).
-struct WTable {
-    const double* cf;
-    double dk;
-    int nq;
-};
-
-template <typename R>
-__global__ void k_finalize(const double* __restrict__ dct, R* __restrict__ out, Oct o, double c0,
-                           double c1, double c2, double inv_prod_p, KernelParams kp, WTable wt) {
-    const long n = o.size();
-    for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n;
-         i += (long)gridDim.x * blockDim.x) {
-        int a0, a1, a2;
-        o.split(i, a0, a1, a2);
-        const double kx = a0 * c0, ky = a1 * c1, kz = a2 * c2;
-        const double k = sqrt(kx * kx + ky * ky + kz * kz);
-        const double w = wt.cf ? d_what_cheb(wt.cf, wt.dk, wt.nq, k) : d_what(kp, k);
-        out[i] = (R)((dct[i] + w) * inv_prod_p);
-    }
 }
 
 // Gauss-Legendre nodes and weights by Newton's method on the Legendre
@@ -570,11 +679,6 @@ __global__ void k_twiddle(cpx<R>* __restrict__ tw, int n) {
     }
 }
 
-int grid_for(long n, int block) {
-    const long g = (n + block - 1) / block;
-    return (int)(g < 65536 ? (g < 1 ? 1 : g) : 65536);
-}
-
 }  // namespace
 
 hipError_t build_twiddles(fsa_precision prec, int n, void* out, hipStream_t st) {
@@ -589,63 +693,94 @@ hipError_t build_twiddles(fsa_precision prec, int n, void* out, hipStream_t st) 
 hipError_t build_tensor_device(const KernelParams& kp, int d, const double* L, const int64_t* N,
                                const double* h, fsa_precision prec, void* tensor_out,
                                hipStream_t st) {
-    // octant extents, axis 0 innermost; a 2D plan has D2 = 1
-    Oct o{(int)N[0] + 1, (int)N[1] + 1, d == 3 ? (int)N[2] + 1 : 1};
-    const long n = (long)o.D0 * o.D1 * o.D2;
+    // octant extents D_j = N_j + 1, axis 0 innermost; a 2D plan has D2 = 1
+    const long D0 = N[0] + 1, D1 = N[1] + 1, D2 = d == 3 ? N[2] + 1 : 1;
+    const long n = D0 * D1 * D2;
     int maxN = 0;
     for (int j = 0; j < d; ++j) maxN = (int)N[j] > maxN ? (int)N[j] : maxN;
-    double *a = nullptr, *b = nullptr;
-    void* tw = nullptr;
-    hipError_t e = hipMallocAsync((void**)&a, sizeof(double) * n, st);
-    if (e == hipSuccess) e = hipMallocAsync((void**)&b, sizeof(double) * n, st);
-    if (e == hipSuccess) e = hipMallocAsync(&tw, 2 * sizeof(double) * 2 * maxN, st);
-    if (e != hipSuccess) {
-        if (a) (void)hipFreeAsync(a, st);
-        if (b) (void)hipFreeAsync(b, st);
-        return e;
-    }
-    const int block = 256, grid = grid_for(n, block);
-    const double h2 = d == 3 ? h[2] : 1.0;
-    const double hprod = h[0] * h[1] * h2;
-    hipLaunchKernelGGL(k_sample, dim3(grid), dim3(block), 0, st, a, o, h[0], h[1],
-                       d == 3 ? h[2] : 0.0, hprod, kp);
-    double* src = a;
-    double* dst = b;
-    const long D0 = o.D0, D1 = o.D1, D2 = o.D2;
-    for (int ax = 0; ax < d && e == hipSuccess; ++ax) {
-        // lines along axis ax; groups take lines adjacent in memory
-        Lines ln;
-        if (ax == 0) ln = Lines{(int)D1, (int)D2, D0, D0 * D1, 1};
-        else if (ax == 1) ln = Lines{(int)D0, (int)D2, 1, D0 * D1, D0};
-        else ln = Lines{(int)D0, (int)D1, 1, D0, D0 * D1};
-        e = build_twiddles(FSA_F64, (int)(2 * N[ax]), tw, st);
-        if (e == hipSuccess) e = dct_axis(src, dst, ln, (int)N[ax], tw, st);
-        double* t = src;
-        src = dst;
-        dst = t;
-    }
+    // the general construction's W table first (the last axis reads it)
     WTable wt{nullptr, 0.0, 0};
     std::vector<void*> wbufs;
-    if (e == hipSuccess && kp.general) e = build_w_table(kp, d, L, N, st, &wt, &wbufs);
+    hipError_t e = kp.general ? build_w_table(kp, d, L, N, st, &wt, &wbufs) : hipSuccess;
+    // intermediate octants between the axes: one for 2D, two for 3D
+    double *a = nullptr, *b = nullptr;
+    void* tw = nullptr;
+    if (e == hipSuccess) e = hipMallocAsync((void**)&a, sizeof(double) * n, st);
+    if (e == hipSuccess && d == 3) e = hipMallocAsync((void**)&b, sizeof(double) * n, st);
+    if (e == hipSuccess) e = hipMallocAsync(&tw, 2 * sizeof(double) * 2 * maxN, st);
+    DctEnds ends{};
+    ends.kp = kp;
     double prodP = 1.0;
-    for (int j = 0; j < d; ++j) prodP *= 2.0 * (double)N[j];
-    const double c0 = kPi / (2.0 * L[0]), c1 = kPi / (2.0 * L[1]);
-    const double c2 = d == 3 ? kPi / (2.0 * L[2]) : 0.0;
-    if (e == hipSuccess) {
-        if (prec == FSA_F32)
-            hipLaunchKernelGGL(k_finalize<float>, dim3(grid), dim3(block), 0, st,
-                               (const double*)src, (float*)tensor_out, o, c0, c1, c2,
-                               1.0 / prodP, kp, wt);
-        else
-            hipLaunchKernelGGL(k_finalize<double>, dim3(grid), dim3(block), 0, st,
-                               (const double*)src, (double*)tensor_out, o, c0, c1, c2,
-                               1.0 / prodP, kp, wt);
-        e = hipGetLastError();
+    for (int j = 0; j < 3; ++j) {
+        ends.h[j] = j < d ? h[j] : 0.0;
+        ends.c[j] = j < d ? kPi / (2.0 * L[j]) : 0.0;
+        if (j < d) prodP *= 2.0 * (double)N[j];
     }
+    ends.hprod = h[0] * h[1] * (d == 3 ? h[2] : 1.0);
+    ends.inv_prod_p = 1.0 / prodP;
+    ends.wt = wt;
+    ends.out = tensor_out;
+    // radial tables where the mesh (for T(1)) or the frequency step (for W)
+    // is the same on every axis and the table is much smaller than the octant
+    long msum = 0;
+    bool same_h = true, same_c = true;
+    for (int j = 0; j < d; ++j) {
+        msum += N[j] * N[j];
+        same_h = same_h && h[j] == h[0];
+        same_c = same_c && L[j] == L[0];
+    }
+    const long ntab = msum + 1;
+    const bool small = ntab * 4 <= n;
+    double *t1_tab = nullptr, *w_tab = nullptr;
+    if (e == hipSuccess && small && same_h) {
+        e = hipMallocAsync((void**)&t1_tab, sizeof(double) * ntab, st);
+        if (e == hipSuccess)
+            e = launch_kernel(k_radial<true>, dim3((unsigned)((ntab + 255) / 256)), dim3(256), 0,
+                              st, t1_tab, ntab, h[0], ends);
+    }
+    if (e == hipSuccess && small && same_c) {
+        e = hipMallocAsync((void**)&w_tab, sizeof(double) * ntab, st);
+        if (e == hipSuccess)
+            e = launch_kernel(k_radial<false>, dim3((unsigned)((ntab + 255) / 256)), dim3(256), 0,
+                              st, w_tab, ntab, ends.c[0], ends);
+    }
+    ends.t1_tab = t1_tab;
+    ends.w_tab = w_tab;
+    // lines along axis ax; groups take lines adjacent in memory
+    auto lines = [&](int ax) {
+        if (ax == 0) return Lines{(int)D1, (int)D2, D0, D0 * D1, 1, 0};
+        if (ax == 1) return Lines{(int)D0, (int)D2, 1, D0 * D1, D0, 1};
+        return Lines{(int)D0, (int)D1, 1, D0, D0 * D1, 2};
+    };
+    // axes from the last (strided) to axis 0 (contiguous): the axis that
+    // only writes takes the long strides, the last one reads and writes
+    // contiguous rows
+    for (int step = 0; step < d && e == hipSuccess; ++step) {
+        const int ax = d - 1 - step;
+        e = build_twiddles(FSA_F64, (int)(2 * N[ax]), tw, st);
+        if (e != hipSuccess) break;
+        const Lines ln = lines(ax);
+        const int nn = (int)N[ax];
+        const double* last_in = d == 3 ? b : a;
+        if (step == 0)
+            e = t1_tab ? dct_axis<DctStage::FIRST, double, true>(nullptr, a, ln, nn, tw, ends, st)
+                       : dct_axis<DctStage::FIRST, double, false>(nullptr, a, ln, nn, tw, ends, st);
+        else if (step < d - 1)
+            e = dct_axis<DctStage::MID, double, false>(a, b, ln, nn, tw, ends, st);
+        else if (prec == FSA_F32)
+            e = w_tab ? dct_axis<DctStage::LAST, float, true>(last_in, nullptr, ln, nn, tw, ends, st)
+                      : dct_axis<DctStage::LAST, float, false>(last_in, nullptr, ln, nn, tw, ends, st);
+        else
+            e = w_tab
+                    ? dct_axis<DctStage::LAST, double, true>(last_in, nullptr, ln, nn, tw, ends, st)
+                    : dct_axis<DctStage::LAST, double, false>(last_in, nullptr, ln, nn, tw, ends, st);
+    }
+    if (t1_tab) (void)hipFreeAsync(t1_tab, st);
+    if (w_tab) (void)hipFreeAsync(w_tab, st);
     for (void* p : wbufs) (void)hipFreeAsync(p, st);
-    (void)hipFreeAsync(a, st);
-    (void)hipFreeAsync(b, st);
-    (void)hipFreeAsync(tw, st);
+    if (a) (void)hipFreeAsync(a, st);
+    if (b) (void)hipFreeAsync(b, st);
+    if (tw) (void)hipFreeAsync(tw, st);
     return e;
 }
 
