@@ -106,11 +106,15 @@ struct Chunk {
 // transform length (device table of jobs plus the prefix of their item
 // counts), so one persistent launch covers the pass for every problem.
 // ---------------------------------------------------------------------------
+// A caller walks its items in increasing order and keeps a cursor per walk
+// (the job of its previous item, -1 before the first): the lookup then
+// advances from the cursor over the job starts it passes, instead of a
+// binary search of dependent loads for every item.
 template <class Job>
 struct JobOne {
     Job job;
     int total;
-    __device__ __forceinline__ Job get(int item, int& local) const {
+    __device__ __forceinline__ Job get(int item, int& local, int& /*cursor*/) const {
         local = item;
         return job;
     }
@@ -121,13 +125,21 @@ struct JobList {
     const Job* jobs;
     const int* start;  // start[i] = first item of job i; start[n] = total
     int n, total;
-    __device__ __forceinline__ Job get(int item, int& local) const {
-        int lo = 0, hi = n - 1;
-        while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (start[mid] <= item) lo = mid;
-            else hi = mid - 1;
+    __device__ __forceinline__ Job get(int item, int& local, int& cursor) const {
+        int lo;
+        if (cursor >= 0 && start[cursor] <= item) {
+            lo = cursor;
+            while (lo + 1 < n && start[lo + 1] <= item) ++lo;
+        } else {
+            lo = 0;
+            int hi = n - 1;
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (start[mid] <= item) lo = mid;
+                else hi = mid - 1;
+            }
         }
+        cursor = lo;
         local = item - start[lo];
         return jobs[lo];
     }
@@ -180,9 +192,10 @@ __global__ __launch_bounds__((R2c<R, M, VAR>::THREADS)) void k_r2c(
     }
     const Chunk ch(src.total);
     C pf[K::NBT0 * K::HALF];
+    int cur_pf = -1, cur_it = -1;  // job cursors of the prefetch and the item walks
     auto prefetch = [&](int item) {
         int loc;
-        const JobR2c jb = src.get(item, loc);
+        const JobR2c jb = src.get(item, loc, cur_pf);
         const int ntile = cdiv(jb.n_inner, K::WT);
         const int outer = loc / ntile, inner = (loc - outer * ntile) * K::WT + team;
         if (inner < jb.n_inner) {
@@ -201,7 +214,7 @@ __global__ __launch_bounds__((R2c<R, M, VAR>::THREADS)) void k_r2c(
     for (int item = ch.first; item < ch.last; ++item) {
         const int tid = fresh_lane<R, M>() ? opaque(tid0) : tid0;  // per item: fresh_lane
         int loc;
-        const JobR2c jb = src.get(item, loc);
+        const JobR2c jb = src.get(item, loc, cur_it);
         const int n_inner = jb.n_inner;
         const int ntile = cdiv(n_inner, K::WT);
         const int outer = loc / ntile, col0 = (loc - outer * ntile) * K::WT;
@@ -295,9 +308,10 @@ __global__ __launch_bounds__((C2r<R, M, VAR>::THREADS)) void k_c2r(
                    ? ((const C*)jb.in)[((size_t)outer * K::H + k) * jb.n_inner + col0 + ww]
                    : mk(R(0), R(0));
     };
+    int cur_pf = -1, cur_it = -1;  // job cursors of the prefetch and the item walks
     auto prefetch = [&](int item) {
         int loc;
-        const JobC2r jb = src.get(item, loc);
+        const JobC2r jb = src.get(item, loc, cur_pf);
         const int ntile = cdiv(jb.n_inner, K::WT);
         const int outer = loc / ntile, col0 = (loc - outer * ntile) * K::WT;
 #pragma unroll
@@ -309,7 +323,7 @@ __global__ __launch_bounds__((C2r<R, M, VAR>::THREADS)) void k_c2r(
     for (int item = ch.first; item < ch.last; ++item) {
         const int tid = fresh_lane<R, M>() ? opaque(tid0) : tid0;  // per item: fresh_lane
         int loc;
-        const JobC2r jb = src.get(item, loc);
+        const JobC2r jb = src.get(item, loc, cur_it);
         const int n_inner = jb.n_inner;
         const int ntile = cdiv(n_inner, K::WT);
         const int outer = loc / ntile, col0 = (loc - outer * ntile) * K::WT;
@@ -402,9 +416,10 @@ __global__ __launch_bounds__((FwdT<R, P, VAR>::THREADS)) void k_fwd_t(
     if constexpr (F::REG_TW) F::load_tw(w, tid, tw);
     const Chunk ch(src.total);
     C pf[K::NBT0 * K::HALF];
+    int cur_pf = -1, cur_it = -1;  // job cursors of the prefetch and the item walks
     auto prefetch = [&](int item) {
         int loc;
-        const JobT jb = src.get(item, loc);
+        const JobT jb = src.get(item, loc, cur_pf);
         const int ntile = cdiv(jb.N0, K::WT);
         const int t2 = loc / ntile, i0 = (loc - t2 * ntile) * K::WT + team;
         const int p2 = jb.p2_lo + t2;
@@ -423,7 +438,7 @@ __global__ __launch_bounds__((FwdT<R, P, VAR>::THREADS)) void k_fwd_t(
     for (int item = ch.first; item < ch.last; ++item) {
         const int tid = fresh_lane<R, P>() ? opaque(tid0) : tid0;  // per item: fresh_lane
         int loc;
-        const JobT jb = src.get(item, loc);
+        const JobT jb = src.get(item, loc, cur_it);
         const int N0 = jb.N0;
         const int ntile = cdiv(N0, K::WT);
         const int t2 = loc / ntile, col0 = (loc - t2 * ntile) * K::WT;
@@ -492,9 +507,10 @@ __global__ __launch_bounds__((InvT<R, P, VAR>::THREADS)) void k_inv_t(
                    ? ((const C*)jb.in)[((size_t)p2 * P + p1) * jb.N0 + col0 + ww]
                    : mk(R(0), R(0));
     };
+    int cur_pf = -1, cur_it = -1;  // job cursors of the prefetch and the item walks
     auto prefetch = [&](int item) {
         int loc;
-        const JobT jb = src.get(item, loc);
+        const JobT jb = src.get(item, loc, cur_pf);
         const int ntile = cdiv(jb.N0, K::WT);
         const int t2 = loc / ntile, col0 = (loc - t2 * ntile) * K::WT;
 #pragma unroll
@@ -507,7 +523,7 @@ __global__ __launch_bounds__((InvT<R, P, VAR>::THREADS)) void k_inv_t(
     for (int item = ch.first; item < ch.last; ++item) {
         const int tid = fresh_lane<R, P>() ? opaque(tid0) : tid0;  // per item: fresh_lane
         int loc;
-        const JobT jb = src.get(item, loc);
+        const JobT jb = src.get(item, loc, cur_it);
         const int N0 = jb.N0;
         const int ntile = cdiv(N0, K::WT);
         const int t2 = loc / ntile, col0 = (loc - t2 * ntile) * K::WT;
@@ -613,13 +629,12 @@ __global__ __launch_bounds__((Conv<R, P, VAR>::THREADS)) void k_conv(
     const int chunk = (total + slots - 1) / slots;
     const int first = (blockIdx.x * K::TPW + team) * chunk;
 
-    // two prefetch buffers used in turn: item i + 1 loads into one while item
-    // i computes from the other, so no register copies are needed
-    C pfa[K::NPF], pfb[K::NPF];
-    auto prefetch = [&](C (&pf)[K::NPF], int item) {
+    C pf[K::NPF];
+    int cur_pf = -1, cur_it = -1;  // job cursors of the prefetch and the item walks
+    auto prefetch = [&](int item) {
         if (item < total) {
             int loc;
-            const JobConv jb = src.get(item, loc);
+            const JobConv jb = src.get(item, loc, cur_pf);
             const int qp = conv_item_to_pencil(loc, jb.P1, jb.N1) + jb.p2_lo * jb.P1;
             const C* pen = (const C*)jb.data + (size_t)qp * N0;
 #pragma unroll
@@ -631,18 +646,20 @@ __global__ __launch_bounds__((Conv<R, P, VAR>::THREADS)) void k_conv(
                 }
         }
     };
-    auto process = [&](const C (&pf)[K::NPF], int it) {
+    prefetch(first);
+    for (int it = 0; it < chunk; ++it) {
         const int tid = fresh_lane<R, P>() ? opaque(tid0) : tid0;  // per item: fresh_lane
         const int item = first + it;
         const bool active = item < total;
         int loc;
-        const JobConv jb = src.get(active ? item : 0, loc);
+        const JobConv jb = src.get(active ? item : 0, loc, cur_it);
         C v[Ff::V];
 #pragma unroll
         for (int b = 0; b < K::NBT0; ++b)
 #pragma unroll
             for (int q = 0; q < K::R0; ++q)
                 v[b * K::R0 + q] = q < K::HALF ? pf[b * K::HALF + q] : mk(R(0), R(0));
+        if (it + 1 < chunk) prefetch(item + 1);
         const int qp = conv_item_to_pencil(loc, jb.P1, jb.N1) + jb.p2_lo * jb.P1;
         const int p2 = qp / jb.P1, p1 = qp - p2 * jb.P1;
         const int a1 = p1 <= jb.N1 ? p1 : jb.P1 - p1;
@@ -665,14 +682,6 @@ __global__ __launch_bounds__((Conv<R, P, VAR>::THREADS)) void k_conv(
             C* pen = (C*)jb.data + (size_t)qp * N0;
             Fi::store_last(v, tid, N0, [&](int i, C c) { pen[i] = c; });
         }
-    };
-    prefetch(pfa, first);
-    for (int it = 0; it < chunk; it += 2) {
-        if (it + 1 < chunk) prefetch(pfb, first + it + 1);
-        process(pfa, it);
-        if (it + 1 >= chunk) break;
-        if (it + 2 < chunk) prefetch(pfa, first + it + 2);
-        process(pfb, it + 1);
     }
 }
 
