@@ -584,14 +584,17 @@ def bench_batch(F, torch, hip, synth, steps, warmup, count=256, tune=True):
 
 
 def bench_serve(F, torch, hip, synth, duration=3.0, rate=2000.0, budget=200 << 30,
-                inflight=32, streams=8, per_call=True):
+                inflight=16, streams=4, per_call=True, fp64_fraction=0.05):
     """Served workload: seeded Poisson arrivals (mean `rate` req/s) of 3D
     Coulomb / Yukawa requests on {64^3, 128^3, 256^3, 512x64x64, 64x64x512}
     grids with 1-8 Gaussian densities, 5% FP64, tensors cached under an HBM
-    budget (200 GiB by default); latency = completion - submission.  The same arrival stream is
-    also replayed through the plain per-call path (one synchronous
-    fsa_apply at a time), in FP64 and in FP32."""
-    reqs = synth.serve_stream(seed=5000, rate=rate, duration=duration)
+    budget (200 GiB by default).  Every latency is completion - scheduled
+    arrival (time.monotonic, the server's clock), so any wait before a
+    request is submitted counts.  The same arrival stream is replayed through
+    the plain per-call path (one synchronous fsa_apply at a time, tensors
+    cached): in FP64, in FP32, and in each request's own precision."""
+    reqs = synth.serve_stream(seed=5000, rate=rate, duration=duration,
+                              fp64_fraction=fp64_fraction)
     kinds = {}
     for _, p in reqs:
         kinds.setdefault((p.N, p.L, p.precision), p)
@@ -602,6 +605,7 @@ def bench_serve(F, torch, hip, synth, duration=3.0, rate=2000.0, budget=200 << 3
         dens[key] = torch.from_numpy(synth.eval_gaussians(p.gaussians, p.L, p.N)).to(dt).cuda()
         pool = inflight + 8 if p.points <= 128 ** 3 else 12
         outs[key] = [[torch.empty_like(dens[key]), None] for _ in range(pool)]
+    clock_offset_us = (F.Server.clock() - time.monotonic()) * 1e6
     srv = F.Server(budget, max_inflight=inflight, n_streams=streams)
     # warm the tensor cache: one request per distinct tensor key, untimed
     seen = set()
@@ -617,6 +621,8 @@ def bench_serve(F, torch, hip, synth, duration=3.0, rate=2000.0, budget=200 << 3
     srv.reset_stats()
 
     def take(key):
+        # an output buffer no pending request writes (the wait counts in the
+        # latency, which runs from the scheduled arrival)
         pool = outs[key]
         while True:
             for slot in pool:
@@ -624,31 +630,27 @@ def bench_serve(F, torch, hip, synth, duration=3.0, rate=2000.0, budget=200 << 3
                     return slot
             time.sleep(20e-6)
 
-    t0 = time.perf_counter()
+    t0 = time.monotonic()
     tickets = []
     late = 0
     for t_arr, p in reqs:
-        while time.perf_counter() - t0 < t_arr:
+        while time.monotonic() - t0 < t_arr:
             pass
-        if time.perf_counter() - t0 > t_arr + 1e-3:
+        if time.monotonic() - t0 > t_arr + 1e-3:
             late += 1
         key = (p.N, p.L, p.precision)
         slot = take(key)
         slot[1] = srv.submit(p.kernel, p.L, p.N, dens[key], slot[0], precision=p.precision,
-                             lam=p.lam or None)
+                             lam=p.lam or None, arrival=t0 + t_arr)
         tickets.append(slot[1])
     bad = sum(srv.wait(t) != "FSA_OK" for t in tickets)
     st = srv.stats()
     srv.close()
 
-    per_call_ok = per_call
-
-    def per_call(prec_override):
+    def per_call_path(prec_override):
         plans = {}
         ws = {}
         lat = []
-        e0, e1 = hip.event(), hip.event()
-        stream = torch.cuda.current_stream()
         for _, p in reqs:  # build plans and time nothing yet
             prec = prec_override or p.precision
             k = (p.kernel, p.lam, p.N, p.L, prec)
@@ -661,9 +663,9 @@ def bench_serve(F, torch, hip, synth, duration=3.0, rate=2000.0, budget=200 << 3
                 inputs[(key[0], key[1], prec)] = d.to(F.DTYPES[prec])
         torch.cuda.synchronize()
         out_cache = {}
-        t0 = time.perf_counter()
+        t0 = time.monotonic()
         for t_arr, p in reqs:
-            while time.perf_counter() - t0 < t_arr:
+            while time.monotonic() - t0 < t_arr:
                 pass
             prec = prec_override or p.precision
             k = (p.kernel, p.lam, p.N, p.L, prec)
@@ -671,33 +673,35 @@ def bench_serve(F, torch, hip, synth, duration=3.0, rate=2000.0, budget=200 << 3
             o = out_cache.setdefault((p.N, p.L, prec), torch.empty_like(x))
             plans[k].apply(x, o, ws[k])
             torch.cuda.synchronize()
-            lat.append((time.perf_counter() - t0 - t_arr) * 1e3)
-        span = time.perf_counter() - t0
-        hip.destroy(e0)
-        hip.destroy(e1)
+            lat.append((time.monotonic() - t0 - t_arr) * 1e3)
+        span = time.monotonic() - t0
         for pl in plans.values():
             pl.close()
-        lat.sort()
         n = len(lat)
         return {"p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
                 "throughput_rps": n / span, "requests": n}
 
-    fp64 = per_call("f64") if per_call_ok else None
-    fp32 = per_call("f32") if per_call_ok else None
+    fp64 = per_call_path("f64") if per_call else None
+    fp32 = per_call_path("f32") if per_call else None
+    mixed = per_call_path(None) if per_call else None
     pts = sum(p.points for _, p in reqs)
     return {
         "workload": f"Poisson arrivals at {rate:.0f} req/s for {duration:.1f} s (seed 5000): "
                     "3D Coulomb (1/2) / Yukawa lam in {0.5,1,4}; grids 64^3, 128^3, 256^3, "
-                    f"512x64x64, 64x64x512; 5% FP64; HBM budget {budget / 2**30:.0f} GiB",
+                    f"512x64x64, 64x64x512; {100 * fp64_fraction:.0f}% FP64; "
+                    f"HBM budget {budget / 2**30:.0f} GiB",
+        "latency": "completion - scheduled arrival, every path",
         "requests": len(reqs),
         "grid_points": pts,
         "server": {"p50_ms": st["p50_ms"], "p99_ms": st["p99_ms"],
                    "throughput_rps": st["throughput_rps"], "gpts_per_s": st["gpts_per_s"],
                    "failed": bad, "late_submissions": late, "cache_hits": st["cache_hits"],
                    "cache_misses": st["cache_misses"], "hbm_peak_GB": st["hbm_peak"] / 1e9,
-                   "max_inflight": inflight, "streams": streams},
+                   "max_inflight": inflight, "streams": streams,
+                   "clock_offset_us": clock_offset_us},
         "per_call_fp64": fp64,
         "per_call_fp32": fp32,
+        "per_call_requested_precision": mixed,
     }
 
 
@@ -836,6 +840,12 @@ def main():
         return
     if args.serve_only:
         sv = bench_serve(F, torch, hip, synth, duration=args.serve_seconds)
+        sv["server_one_stream"] = bench_serve(F, torch, hip, synth, duration=args.serve_seconds,
+                                              inflight=4, streams=1, per_call=False)["server"]
+        # the same arrivals with every request in FP32: the server beside
+        # per_call_fp32, which runs exactly these requests
+        sv["server_all_fp32"] = bench_serve(F, torch, hip, synth, duration=args.serve_seconds,
+                                               per_call=False, fp64_fraction=0.0)["server"]
         log(f"  serve: {json.dumps(sv)}")
         burst = bench_serve(F, torch, hip, synth, duration=1.0, rate=6000.0, budget=2 << 30)
         log(f"  burst: {json.dumps(burst)}")
@@ -899,12 +909,20 @@ def main():
     if not args.no_serve:
         log("served workload (Poisson arrivals) ...")
         serve = bench_serve(F, torch, hip, synth, duration=args.serve_seconds)
+        serve["server_one_stream"] = bench_serve(F, torch, hip, synth,
+                                                 duration=args.serve_seconds, inflight=4,
+                                                 streams=1, per_call=False)["server"]
+        # the same arrivals with every request in FP32: the server beside
+        # per_call_fp32, which runs exactly these requests
+        serve["server_all_fp32"] = bench_serve(F, torch, hip, synth,
+                                               duration=args.serve_seconds,
+                                               per_call=False, fp64_fraction=0.0)["server"]
         log(f"  server p50/p99 {serve['server']['p50_ms']:.3f}/{serve['server']['p99_ms']:.3f} ms, "
             f"per-call FP64 p50/p99 {serve['per_call_fp64']['p50_ms']:.3f}/"
             f"{serve['per_call_fp64']['p99_ms']:.3f} ms")
         log("burst: 6000 req/s for 1 s under a 2 GB HBM budget ...")
         serve_burst = bench_serve(F, torch, hip, synth, duration=1.0, rate=6000.0,
-                                  budget=2 << 30, per_call=False)
+                                  budget=2 << 30)
         log(f"  burst server p50/p99 {serve_burst['server']['p50_ms']:.3f}/"
             f"{serve_burst['server']['p99_ms']:.3f} ms")
     cpu = parity = None

@@ -352,7 +352,9 @@ fsa_status fsa_tune_reset(void);
 typedef struct fsa_server_s* fsa_server;
 
 typedef struct {
-    double p50_ms, p99_ms;      /* latency: completion - submit              */
+    double p50_ms, p99_ms;      /* latency: completion - arrival (the arrival
+                                   time given to fsa_server_submit_at, else the
+                                   submission time), queueing included       */
     double throughput_rps;      /* completed requests per second of uptime   */
     double gpts_per_s;          /* output grid points per second of uptime   */
     uint64_t done, rejected, cancelled, cache_hits, cache_misses;
@@ -362,7 +364,13 @@ typedef struct {
 /* Creates a server on the current device.
  *   hbm_budget_bytes  cap on cached tensors + in-flight workspaces.
  *   max_inflight      concurrent requests on the device (slots, >= 1).
- *   n_streams         device streams the slots rotate over (>= 1). */
+ *   n_streams         device streams the slots rotate over (>= 1).
+ * Requests of at least 2^23 grid points run in turn on the first stream, the
+ * others rotate over the rest (with n_streams = 1 everything runs in turn).
+ * A submitting thread admits and launches its request itself when a slot and
+ * the budget allow; one host thread per stream sleeps until that stream's
+ * oldest request finishes (a blocking-sync event), then admits what the freed
+ * slot allows.  No thread polls. */
 fsa_status fsa_server_create(size_t hbm_budget_bytes, int max_inflight, int n_streams,
                              fsa_server* out);
 
@@ -374,8 +382,25 @@ fsa_status fsa_server_submit(fsa_server s, const fsa_kernel* k, int d, const dou
                              const int64_t* N, fsa_precision p, const void* rho, void* phi,
                              uint64_t* ticket);
 
+/* As fsa_server_submit, for a request that arose at t_arrival (seconds on
+ * the clock of fsa_server_clock, CLOCK_MONOTONIC; < 0: now): its latency in
+ * fsa_stats is counted from then, so time the caller spent before
+ * submitting (a client-side queue, a full buffer pool) is included. */
+fsa_status fsa_server_submit_at(fsa_server s, const fsa_kernel* k, int d, const double* L,
+                                const int64_t* N, fsa_precision p, const void* rho, void* phi,
+                                double t_arrival, uint64_t* ticket);
+/* The server's clock: seconds of the host's monotonic clock (CLOCK_MONOTONIC,
+ * the clock of Python's time.monotonic). */
+fsa_status fsa_server_clock(double* t);
+
 fsa_status fsa_server_poll(fsa_server s, uint64_t ticket, int* done, fsa_status* result);
+/* Blocks until the request has finished; *result receives its status. */
 fsa_status fsa_server_wait(fsa_server s, uint64_t ticket, fsa_status* result);
+/* As fsa_server_wait for at most timeout_ms (< 0: no limit): *done = 1 and
+ * *result set if the request finished, *done = 0 if the time ran out (the
+ * request stays queued or in flight; fsa_server_cancel drops a queued one). */
+fsa_status fsa_server_wait_for(fsa_server s, uint64_t ticket, double timeout_ms, int* done,
+                               fsa_status* result);
 /* Cancels a request that has not been launched yet (FSA_ESTATE otherwise). */
 fsa_status fsa_server_cancel(fsa_server s, uint64_t ticket);
 fsa_status fsa_server_stats(fsa_server s, fsa_stats* out);

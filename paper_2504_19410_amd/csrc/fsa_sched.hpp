@@ -13,6 +13,9 @@
 #pragma once
 
 #include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <condition_variable>
 #include <cstddef>
 #include <cstdint>
 #include <deque>
@@ -22,6 +25,7 @@
 #include <memory>
 #include <mutex>
 #include <string>
+#include <thread>
 #include <unordered_map>
 #include <vector>
 
@@ -70,7 +74,9 @@ struct Request {
     Key key;
     const void* rho = nullptr;
     void* phi = nullptr;
-    double t_submit = 0, t_admit = 0, t_done = 0;
+    // t_arrival: when the request arose (the caller's, else the submission
+    // time); latency = t_done - t_arrival, queueing before submission included
+    double t_arrival = 0, t_submit = 0, t_admit = 0, t_done = 0;
     int slot = -1;
     bool done = false;
     Status result = ST_OK;
@@ -86,9 +92,14 @@ public:
     virtual Status build_plan(const PlanInfo& p, std::string* err) = 0;
     virtual void destroy_plan(const PlanInfo& p) = 0;
     // asynchronous evaluation; the backend must later report its completion
-    // through Scheduler::complete (from a thread that does not hold the
-    // scheduler busy: the server drains a completion queue)
+    // through Scheduler::complete
     virtual Status launch(const Request& r, const PlanInfo& p, int slot, std::string* err) = 0;
+};
+
+struct Completion {
+    uint64_t ticket;
+    Status status;
+    double t_done;
 };
 
 struct Stats {
@@ -110,8 +121,9 @@ public:
     }
 
     // Queues a request.  ST_EBUDGET if it could never fit: its workspace plus
-    // its tensor exceed the whole budget.
-    Status submit(const Key& k, const void* rho, void* phi, uint64_t* ticket, std::string* err) {
+    // its tensor exceed the whole budget.  t_arrival < 0: now.
+    Status submit(const Key& k, const void* rho, void* phi, uint64_t* ticket, std::string* err,
+                  double t_arrival = -1.0) {
         std::lock_guard<std::mutex> lk(mu_);
         PlanInfo probe;
         size_t tensor_bytes, ws_bytes;
@@ -142,6 +154,7 @@ public:
         r.rho = rho;
         r.phi = phi;
         r.t_submit = be_->now();
+        r.t_arrival = t_arrival >= 0 ? t_arrival : r.t_submit;
         reqs_[r.ticket] = r;
         queue_.push_back(r.ticket);
         *ticket = r.ticket;
@@ -149,48 +162,27 @@ public:
     }
 
     // Admits and launches as many queued requests as slots and budget allow,
-    // in arrival order (the head of the queue is never overtaken).  Returns
-    // the number launched.
+    // in arrival order except for the bounded bypass of admit_locked, from
+    // any thread; returns the number this call launched.  One pump runs at a
+    // time: a caller that finds another pump running leaves a request for
+    // it and returns, and the running pump goes round again, so a request
+    // queued before a pump() call is always considered.  The state lock is
+    // released while the backend builds a tensor or launches, so
+    // submissions, completions and polls are not held up by device calls.
     int pump() {
-        std::lock_guard<std::mutex> lk(mu_);
-        int launched = 0;
-        while (!queue_.empty() && !free_slots_.empty()) {
-            Request& r = reqs_[queue_.front()];
-            Entry& e = cache_[r.key];
-            const size_t need = e.info.workspace_bytes + (e.built ? 0 : e.info.tensor_bytes);
-            if (in_use_ + need > budget_ && !evict_for(need, r.key)) break;
-            queue_.pop_front();
-            std::string err;
-            if (!e.built) {
-                ++misses_;
-                Status s = be_->build_plan(e.info, &err);
-                if (s != ST_OK) {
-                    finish_locked(r, s);
-                    continue;
-                }
-                e.built = true;
-                in_use_ += e.info.tensor_bytes;
-            } else {
-                ++hits_;
-            }
-            in_use_ += e.info.workspace_bytes;
-            peak_ = std::max(peak_, in_use_);
-            ++e.refs;
-            touch(r.key);
-            r.slot = free_slots_.back();
-            free_slots_.pop_back();
-            r.t_admit = be_->now();
-            ++inflight_;
-            Status s = be_->launch(r, e.info, r.slot, &err);
-            if (s != ST_OK) {
-                release_locked(r);
-                finish_locked(r, s);
-                continue;
-            }
-            ++launched;
+        pending_.store(true);
+        int total = 0;
+        while (pending_.load()) {
+            std::unique_lock<std::mutex> pl(pump_mu_, std::try_to_lock);
+            if (!pl.owns_lock()) return total;  // the running pump sees pending_
+            pending_.store(false);
+            total += pump_locked();
         }
-        return launched;
+        return total;
     }
+
+    // A launched request's work has finished at time t_done (backend clock).
+    void complete(const Completion& c) { complete(c.ticket, c.status, c.t_done); }
 
     // A launched request's work has finished at time t_done (backend clock).
     void complete(uint64_t ticket, Status s, double t_done) {
@@ -314,6 +306,106 @@ private:
         uint64_t lru = 0;
     };
 
+    // An admission decided under the state lock and carried out without it.
+    struct Admission {
+        Request req;
+        PlanInfo info;
+        bool build = false;
+    };
+
+    // Admits the next request if a slot and budget allow: reserves the slot,
+    // the workspace and (on a miss) the tensor, and marks the entry built and
+    // referenced, so no other admission builds or evicts it.
+    //   The head of the queue goes first.  When it does not fit, cached
+    // tensors are evicted for it only if nothing is in flight (in-flight
+    // requests will free their workspaces; evicting now would only make
+    // later requests rebuild).  While it waits, a request among the next
+    // kBypassWindow whose tensor is cached and which fits without eviction
+    // may go ahead, at most kMaxBypass times per head, so that small requests
+    // keep the device busy without starving a large one.
+    static constexpr int kBypassWindow = 16, kMaxBypass = 64;
+    bool admit_locked(Admission* a) {
+        while (!queue_.empty() && !free_slots_.empty()) {
+            size_t pos = 0;
+            {
+                Request& h = reqs_[queue_.front()];
+                Entry& e = cache_[h.key];
+                const size_t need = e.info.workspace_bytes + (e.built ? 0 : e.info.tensor_bytes);
+                const bool fits = in_use_ + need <= budget_ ||
+                                  (inflight_ == 0 && evict_for(need, h.key));
+                if (!fits) {
+                    if (bypassed_ >= kMaxBypass) return false;
+                    pos = 0;
+                    for (size_t i = 1; i < queue_.size() && i <= (size_t)kBypassWindow; ++i) {
+                        const Request& c = reqs_[queue_[i]];
+                        const Entry& ce = cache_[c.key];
+                        if (ce.built && in_use_ + ce.info.workspace_bytes <= budget_) {
+                            pos = i;
+                            break;
+                        }
+                    }
+                    if (pos == 0) return false;
+                    ++bypassed_;
+                } else {
+                    bypassed_ = 0;
+                }
+            }
+            Request& r = reqs_[queue_[pos]];
+            Entry& e = cache_[r.key];
+            queue_.erase(queue_.begin() + (long)pos);
+            a->build = !e.built;
+            if (a->build) {
+                ++misses_;
+                e.built = true;
+                in_use_ += e.info.tensor_bytes;
+            } else {
+                ++hits_;
+            }
+            in_use_ += e.info.workspace_bytes;
+            peak_ = std::max(peak_, in_use_);
+            ++e.refs;
+            touch(r.key);
+            r.slot = free_slots_.back();
+            free_slots_.pop_back();
+            r.t_admit = be_->now();
+            ++inflight_;
+            a->req = r;
+            a->info = e.info;
+            return true;
+        }
+        return false;
+    }
+
+    int pump_locked() {
+        int launched = 0;
+        for (;;) {
+            Admission a;
+            {
+                std::lock_guard<std::mutex> lk(mu_);
+                if (!admit_locked(&a)) break;
+            }
+            std::string err;
+            Status s = a.build ? be_->build_plan(a.info, &err) : ST_OK;
+            const bool built = s == ST_OK;
+            if (s == ST_OK) s = be_->launch(a.req, a.info, a.req.slot, &err);
+            std::lock_guard<std::mutex> lk(mu_);
+            if (!built) {  // the tensor never came to be: undo its reservation
+                Entry& e = cache_[a.req.key];
+                e.built = false;
+                in_use_ -= e.info.tensor_bytes;
+            }
+            if (s != ST_OK) {
+                Request& r = reqs_[a.req.ticket];
+                r.slot = a.req.slot;
+                release_locked(r);
+                finish_locked(r, s);
+                continue;
+            }
+            ++launched;
+        }
+        return launched;
+    }
+
     void touch(const Key& k) { cache_[k].lru = ++lru_clock_; }
 
     void drop_if_unused_unbuilt(const Key& k) {
@@ -377,7 +469,7 @@ private:
         if (s == ST_OK) {
             ++done_ok_;
             points_ += (double)r.key.points();
-            lat_ms_.push_back((r.t_done - r.t_submit) * 1e3);
+            lat_ms_.push_back((r.t_done - r.t_arrival) * 1e3);
             last_done_ = std::max(last_done_, r.t_done);
         }
     }
@@ -386,17 +478,112 @@ private:
     size_t budget_;
     int slots_;
     double t0_;
+    std::mutex pump_mu_;  // taken before mu_, never while holding it
+    std::atomic<bool> pending_{false};
     std::mutex mu_;
     std::map<Key, Entry> cache_;
     std::unordered_map<uint64_t, Request> reqs_;
     std::deque<uint64_t> queue_;
     std::vector<int> free_slots_;
     uint64_t next_ticket_ = 1, lru_clock_ = 0;
+    int bypassed_ = 0;  // admissions ahead of the current head
     size_t in_use_ = 0, peak_ = 0;
     int inflight_ = 0;
     uint64_t done_ok_ = 0, rejected_ = 0, cancelled_ = 0, hits_ = 0, misses_ = 0;
     double points_ = 0, last_done_ = 0;
     std::vector<double> lat_ms_;
+};
+
+// Where a served scheduler learns of completions: one in-order queue of
+// launched requests per device stream.
+class CompletionSource {
+public:
+    virtual ~CompletionSource() = default;
+    virtual int n_queues() const = 0;
+    // Blocks until the oldest request launched on queue q has finished and
+    // returns it; false once stop() has been called and q is empty.
+    virtual bool wait_next(int q, Completion* out) = 0;
+    // Wakes every wait_next on an empty queue for good.
+    virtual void stop() = 0;
+    // Called first on every waiter thread (e.g. to select the device).
+    virtual void thread_init() {}
+};
+
+// The threads of a served scheduler.  A submitting thread queues its request
+// and pumps (admits and launches) itself, so an idle server starts a request
+// without a thread hand-off; one waiter thread per device queue sleeps until
+// that queue's oldest request finishes, records the completion and pumps the
+// requests that the freed slot and budget admit.  No thread polls.
+class Runner {
+public:
+    Runner(Scheduler* s, CompletionSource* src) : s_(s), src_(src) {
+        for (int q = 0; q < src_->n_queues(); ++q)
+            waiters_.emplace_back([this, q] { wait_loop(q); });
+    }
+    ~Runner() { shutdown(); }
+
+    Status submit(const Key& k, const void* rho, void* phi, uint64_t* ticket, std::string* err,
+                  double t_arrival = -1.0) {
+        const Status st = s_->submit(k, rho, phi, ticket, err, t_arrival);
+        if (st != ST_OK) return st;
+        s_->pump();
+        notify_done();  // a request may have failed at admission
+        return ST_OK;
+    }
+
+    // Waits until the request has finished (true) or timeout_s has passed
+    // (false; timeout_s < 0: no limit).  ST_EINVAL for an unknown ticket.
+    Status wait(uint64_t ticket, double timeout_s, bool* done, Status* result) {
+        const auto t_end = std::chrono::steady_clock::now() +
+                           std::chrono::duration_cast<std::chrono::steady_clock::duration>(
+                               std::chrono::duration<double>(timeout_s < 0 ? 0.0 : timeout_s));
+        std::unique_lock<std::mutex> lk(done_mu_);
+        for (;;) {
+            const Status st = s_->poll(ticket, done, result);
+            if (st != ST_OK || *done) return st;
+            if (timeout_s >= 0 && std::chrono::steady_clock::now() >= t_end) return ST_OK;
+            // completions and admission failures notify; the timed wait is a
+            // safety net only (system_clock: pthread_cond_timedwait, which
+            // thread sanitizers intercept; the deadline above is steady)
+            done_cv_.wait_until(lk,
+                                std::chrono::system_clock::now() + std::chrono::milliseconds(2));
+        }
+    }
+
+    // Cancels what is queued, lets what is in flight finish, joins the threads.
+    void shutdown() {
+        if (down_) return;
+        down_ = true;
+        s_->cancel_all();
+        notify_done();
+        src_->stop();
+        for (auto& t : waiters_) t.join();
+        waiters_.clear();
+    }
+
+    void notify_done() {
+        std::lock_guard<std::mutex> lk(done_mu_);
+        done_cv_.notify_all();
+    }
+
+private:
+    void wait_loop(int q) {
+        src_->thread_init();
+        Completion c;
+        while (src_->wait_next(q, &c)) {
+            s_->complete(c);
+            notify_done();
+            s_->pump();
+            notify_done();
+        }
+    }
+
+    Scheduler* s_;
+    CompletionSource* src_;
+    std::vector<std::thread> waiters_;
+    std::mutex done_mu_;
+    std::condition_variable done_cv_;
+    bool down_ = false;
 };
 
 }  // namespace sched

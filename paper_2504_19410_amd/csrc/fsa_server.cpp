@@ -1,23 +1,26 @@
 // fsa_server.cpp -- the served variant: continuous batching of convolution
-// requests on one GPU under an HBM budget (scheduling logic in fsa_sched.hpp).
+// requests on one GPU under an HBM budget (scheduling logic and threads in
+// fsa_sched.hpp).
 //
 // Device side of a request: on its slot's stream the request waits for its
 // cached tensor's build event, runs the evaluation passes in the slot's
 // resident workspace and records a completion event.  A slot's workspace is
 // sized to the largest request it has run (grown, rarely, between requests,
-// when the slot is idle), so the steady state allocates nothing.  Requests on different slots run concurrently on the device.  A
-// server thread polls the in-flight events (time-stamping completions as it
-// sees them) and admits queued requests.
+// when the slot is idle), so the steady state allocates nothing.  Requests
+// on different slots run concurrently on the device.  Completion events are
+// created with hipEventBlockingSync: the waiter thread of each stream sleeps
+// in hipEventSynchronize until its oldest request finishes (woken by the
+// device's interrupt a few microseconds after the kernel ends), instead of
+// a thread polling every event.
 #include <hip/hip_runtime.h>
 
-#include <atomic>
 #include <chrono>
 #include <condition_variable>
 #include <cstring>
+#include <deque>
 #include <map>
 #include <memory>
 #include <mutex>
-#include <thread>
 #include <vector>
 
 #include "fsa_internal.hpp"
@@ -29,9 +32,11 @@ void set_last_error(const char* msg);
 
 namespace {
 
+using fsa::sched::Completion;
 using fsa::sched::Key;
 using fsa::sched::PlanInfo;
 using fsa::sched::Request;
+using fsa::sched::Runner;
 using fsa::sched::Scheduler;
 using Status = fsa::sched::Status;
 
@@ -40,13 +45,7 @@ double steady_now() {
         .count();
 }
 
-struct Completion {
-    uint64_t ticket;
-    Status status;
-    double t_done;
-};
-
-class HipBackend : public fsa::sched::Backend {
+class HipBackend : public fsa::sched::Backend, public fsa::sched::CompletionSource {
 public:
     HipBackend(int device, int n_streams) : device_(device) {
         for (int i = 0; i < n_streams; ++i) {
@@ -54,6 +53,7 @@ public:
             if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) == hipSuccess)
                 streams_.push_back(s);
         }
+        queues_ = std::vector<Queue>(streams_.size());
         (void)hipStreamCreateWithFlags(&build_stream_, hipStreamNonBlocking);
     }
     ~HipBackend() override {
@@ -119,8 +119,25 @@ public:
         fsa_plan_destroy(pl);
     }
 
+    // Large requests (at least kLargePoints grid points, e.g. 256^3) run one
+    // after another on stream 0; the others rotate over the remaining
+    // streams.  Two large requests sharing the device would each take about
+    // twice as long, so running them in turn keeps the tail latency of the
+    // large ones at their own run time, while small requests, which leave
+    // most of the device idle, still overlap with them and each other.
+    static constexpr int64_t kLargePoints = int64_t(1) << 23;
+    size_t stream_of(const Request& r, int slot) const {
+        const size_t n = streams_.size();
+        if (n == 1) return 0;
+        if (r.key.points() >= kLargePoints) return 0;
+        return 1 + (size_t)slot % (n - 1);
+    }
+
+    // Called by the scheduler's pump, one at a time, with the slot reserved
+    // for this request (its previous request has completed).
     Status launch(const Request& r, const PlanInfo& p, int slot, std::string* err) override {
-        hipStream_t st = streams_[(size_t)slot % streams_.size()];
+        const size_t q = stream_of(r, slot);
+        hipStream_t st = streams_[q];
         fsa_plan pl = (fsa_plan)p.handle;
         hipEvent_t ev = nullptr;
         {
@@ -160,45 +177,60 @@ public:
             if (err) *err = "completion event";
             return fsa::sched::ST_EDEVICE;
         }
-        std::lock_guard<std::mutex> lk(c_mu_);
-        inflight_.push_back(Inflight{r.ticket, done});
+        Queue& qu = queues_[q];
+        {
+            std::lock_guard<std::mutex> lk(qu.mu);
+            qu.fifo.push_back(Inflight{r.ticket, done});
+        }
+        qu.cv.notify_one();
         return fsa::sched::ST_OK;
     }
 
-    // Completed requests, in the order the server thread observed them.
-    std::vector<Completion> take_completions() {
-        std::vector<Completion> out;
-        std::lock_guard<std::mutex> lk(c_mu_);
-        for (size_t i = 0; i < inflight_.size();) {
-            const hipError_t q = hipEventQuery(inflight_[i].ev);
-            if (q == hipErrorNotReady) {
-                ++i;
-                continue;
-            }
-            out.push_back(Completion{inflight_[i].ticket,
-                                     q == hipSuccess ? fsa::sched::ST_OK : fsa::sched::ST_EDEVICE,
-                                     steady_now()});
-            free_events_.push_back(inflight_[i].ev);
-            inflight_[i] = inflight_.back();
-            inflight_.pop_back();
+    // CompletionSource: requests on one stream finish in launch order.
+    int n_queues() const override { return (int)streams_.size(); }
+
+    bool wait_next(int q, Completion* out) override {
+        Queue& qu = queues_[(size_t)q];
+        Inflight f;
+        {
+            std::unique_lock<std::mutex> lk(qu.mu);
+            qu.cv.wait(lk, [&] { return !qu.fifo.empty() || stopped_.load(); });
+            if (qu.fifo.empty()) return false;
+            f = qu.fifo.front();
+            qu.fifo.pop_front();
         }
-        return out;
+        const hipError_t e = hipEventSynchronize(f.ev);  // sleeps; no polling
+        out->ticket = f.ticket;
+        out->status = e == hipSuccess ? fsa::sched::ST_OK : fsa::sched::ST_EDEVICE;
+        out->t_done = steady_now();
+        std::lock_guard<std::mutex> lk(ev_pool_mu_);
+        free_events_.push_back(f.ev);
+        return true;
     }
-    bool any_inflight() {
-        std::lock_guard<std::mutex> lk(c_mu_);
-        return !inflight_.empty();
+
+    void stop() override {
+        stopped_.store(true);
+        for (Queue& qu : queues_) {
+            std::lock_guard<std::mutex> lk(qu.mu);
+            qu.cv.notify_all();
+        }
     }
-    std::mutex c_mu_;
-    std::condition_variable* wake = nullptr;
+
+    void thread_init() override { (void)hipSetDevice(device_); }
 
 private:
     struct Inflight {
-        uint64_t ticket;
-        hipEvent_t ev;
+        uint64_t ticket = 0;
+        hipEvent_t ev = nullptr;
+    };
+    struct Queue {
+        std::mutex mu;
+        std::condition_variable cv;
+        std::deque<Inflight> fifo;
     };
     hipEvent_t take_event() {
         {
-            std::lock_guard<std::mutex> lk(c_mu_);
+            std::lock_guard<std::mutex> lk(ev_pool_mu_);
             if (!free_events_.empty()) {
                 hipEvent_t e = free_events_.back();
                 free_events_.pop_back();
@@ -206,19 +238,23 @@ private:
             }
         }
         hipEvent_t e = nullptr;
-        if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) return nullptr;
-        std::lock_guard<std::mutex> lk(c_mu_);
+        if (hipEventCreateWithFlags(&e, hipEventDisableTiming | hipEventBlockingSync) !=
+            hipSuccess)
+            return nullptr;
+        std::lock_guard<std::mutex> lk(ev_pool_mu_);
         all_events_.push_back(e);
         return e;
     }
 
-    std::vector<Inflight> inflight_;
-    std::vector<void*> slot_ws_;  // resident workspace per slot
-    std::vector<size_t> slot_bytes_;
-    std::vector<hipEvent_t> free_events_, all_events_;
     int device_;
     std::vector<hipStream_t> streams_;
+    std::vector<Queue> queues_;
+    std::atomic<bool> stopped_{false};
     hipStream_t build_stream_ = nullptr;
+    std::vector<void*> slot_ws_;  // resident workspace per slot (pump thread only)
+    std::vector<size_t> slot_bytes_;
+    std::mutex ev_pool_mu_;
+    std::vector<hipEvent_t> free_events_, all_events_;
     std::mutex ev_mu_;
     std::map<fsa_plan, hipEvent_t> built_;
 };
@@ -229,38 +265,7 @@ struct fsa_server_s {
     int device = 0;
     std::unique_ptr<HipBackend> be;
     std::unique_ptr<Scheduler> sched;
-    std::thread worker;
-    std::atomic<bool> stop{false};
-    std::condition_variable wake;       // new submissions / completions (with be->c_mu_)
-    std::mutex done_mu;                 // for waiters
-    std::condition_variable done_cv;
-
-    void run() {
-        (void)hipSetDevice(device);
-        for (;;) {
-            std::vector<Completion> done = be->take_completions();
-            for (const Completion& c : done) sched->complete(c.ticket, c.status, c.t_done);
-            if (!done.empty()) {
-                std::lock_guard<std::mutex> lk(done_mu);
-                done_cv.notify_all();
-            }
-            sched->pump();
-            {
-                std::lock_guard<std::mutex> lk(done_mu);
-                done_cv.notify_all();  // requests finished at admission (errors)
-            }
-            if (stop.load() && sched->idle()) break;
-            if (be->any_inflight()) {
-                // completions are observed by polling: spin (yielding) while
-                // work is in flight; a timed sleep would add the kernel's
-                // timer slack (tens of microseconds) to every latency
-                std::this_thread::yield();
-                continue;
-            }
-            std::unique_lock<std::mutex> lk(be->c_mu_);
-            wake.wait_for(lk, std::chrono::microseconds(500));
-        }
-    }
+    std::unique_ptr<Runner> runner;
 };
 
 extern "C" {
@@ -281,17 +286,15 @@ fsa_status fsa_server_create(size_t hbm_budget_bytes, int max_inflight, int n_st
         fsa::set_last_error("fsa_server_create: stream creation failed");
         return FSA_EDEVICE;
     }
-    s->be->wake = &s->wake;
     s->sched = std::make_unique<Scheduler>(s->be.get(), hbm_budget_bytes, max_inflight);
-    fsa_server_s* raw = s.get();
-    s->worker = std::thread([raw] { raw->run(); });
+    s->runner = std::make_unique<Runner>(s->sched.get(), s->be.get());
     *out = s.release();
     return FSA_OK;
 }
 
-fsa_status fsa_server_submit(fsa_server s, const fsa_kernel* k, int d, const double* L,
-                             const int64_t* N, fsa_precision p, const void* rho, void* phi,
-                             uint64_t* ticket) {
+fsa_status fsa_server_submit_at(fsa_server s, const fsa_kernel* k, int d, const double* L,
+                                const int64_t* N, fsa_precision p, const void* rho, void* phi,
+                                double t_arrival, uint64_t* ticket) {
     if (!s || !k || !L || !N || !rho || !phi || !ticket || d < 2 || d > 3) {
         fsa::set_last_error("fsa_server_submit: bad arguments");
         return FSA_EINVAL;
@@ -318,15 +321,26 @@ fsa_status fsa_server_submit(fsa_server s, const fsa_kernel* k, int d, const dou
         key.N[j] = N[j];
     }
     std::string err;
-    Status st = s->sched->submit(key, rho, phi, ticket, &err);
+    const Status st = s->runner->submit(key, rho, phi, ticket, &err, t_arrival);
     if (st != fsa::sched::ST_OK) {
         fsa::set_last_error(err.c_str());
         return (fsa_status)st;
     }
-    {
-        std::lock_guard<std::mutex> lk(s->be->c_mu_);
-        s->wake.notify_all();
+    return FSA_OK;
+}
+
+fsa_status fsa_server_submit(fsa_server s, const fsa_kernel* k, int d, const double* L,
+                             const int64_t* N, fsa_precision p, const void* rho, void* phi,
+                             uint64_t* ticket) {
+    return fsa_server_submit_at(s, k, d, L, N, p, rho, phi, -1.0, ticket);
+}
+
+fsa_status fsa_server_clock(double* t) {
+    if (!t) {
+        fsa::set_last_error("fsa_server_clock: null argument");
+        return FSA_EINVAL;
     }
+    *t = steady_now();
     return FSA_OK;
 }
 
@@ -346,25 +360,27 @@ fsa_status fsa_server_poll(fsa_server s, uint64_t ticket, int* done, fsa_status*
     return FSA_OK;
 }
 
-fsa_status fsa_server_wait(fsa_server s, uint64_t ticket, fsa_status* result) {
-    if (!s) {
+fsa_status fsa_server_wait_for(fsa_server s, uint64_t ticket, double timeout_ms, int* done,
+                               fsa_status* result) {
+    if (!s || !done) {
         fsa::set_last_error("fsa_server_wait: bad arguments");
         return FSA_EINVAL;
     }
-    for (;;) {
-        bool d = false;
-        Status r = fsa::sched::ST_OK;
-        if (s->sched->poll(ticket, &d, &r) != fsa::sched::ST_OK) {
-            fsa::set_last_error("fsa_server_wait: unknown ticket");
-            return FSA_EINVAL;
-        }
-        if (d) {
-            if (result) *result = (fsa_status)r;
-            return FSA_OK;
-        }
-        std::unique_lock<std::mutex> lk(s->done_mu);
-        s->done_cv.wait_for(lk, std::chrono::microseconds(500));
+    bool d = false;
+    Status r = fsa::sched::ST_OK;
+    if (s->runner->wait(ticket, timeout_ms < 0 ? -1.0 : timeout_ms * 1e-3, &d, &r) !=
+        fsa::sched::ST_OK) {
+        fsa::set_last_error("fsa_server_wait: unknown ticket");
+        return FSA_EINVAL;
     }
+    *done = d ? 1 : 0;
+    if (d && result) *result = (fsa_status)r;
+    return FSA_OK;
+}
+
+fsa_status fsa_server_wait(fsa_server s, uint64_t ticket, fsa_status* result) {
+    int done = 0;
+    return fsa_server_wait_for(s, ticket, -1.0, &done, result);
 }
 
 fsa_status fsa_server_cancel(fsa_server s, uint64_t ticket) {
@@ -381,8 +397,7 @@ fsa_status fsa_server_cancel(fsa_server s, uint64_t ticket) {
         fsa::set_last_error("fsa_server_cancel: unknown ticket");
         return FSA_EINVAL;
     }
-    std::lock_guard<std::mutex> lk(s->done_mu);
-    s->done_cv.notify_all();
+    s->runner->notify_done();
     return FSA_OK;
 }
 
@@ -417,14 +432,9 @@ fsa_status fsa_server_reset_stats(fsa_server s) {
 
 fsa_status fsa_server_destroy(fsa_server s) {
     if (!s) return FSA_OK;
-    s->sched->cancel_all();
-    s->stop.store(true);
-    {
-        std::lock_guard<std::mutex> lk(s->be->c_mu_);
-        s->wake.notify_all();
-    }
-    if (s->worker.joinable()) s->worker.join();
+    s->runner->shutdown();     // cancels the queue, lets in-flight work finish
     (void)hipDeviceSynchronize();
+    s->runner.reset();
     s->sched.reset();  // destroys cached plans through the backend
     s->be.reset();
     delete s;

@@ -51,7 +51,8 @@ EXPORTS = (
     "fsa_batch_workspace_bytes", "fsa_apply_batched", "fsa_batch_launches",
     "fsa_autotune_batched", "fsa_plan_destroy",
     "fsa_plan_tensor",
-    "fsa_server_create", "fsa_server_submit", "fsa_server_poll", "fsa_server_wait",
+    "fsa_server_create", "fsa_server_submit", "fsa_server_submit_at", "fsa_server_clock",
+    "fsa_server_poll", "fsa_server_wait", "fsa_server_wait_for",
     "fsa_server_cancel", "fsa_server_stats", "fsa_server_reset_stats", "fsa_server_destroy",
     "fsa_plan_launches",
     "fsa_autotune", "fsa_tune_set", "fsa_tune_get", "fsa_tune_variants", "fsa_tune_save",
@@ -111,8 +112,12 @@ def _load():
         "fsa_plan_tensor": [P, P, P],
         "fsa_server_create": [S, I, I, ctypes.POINTER(P)],
         "fsa_server_submit": [P, ctypes.POINTER(_Kernel), I, P, P, I, P, P, P],
+        "fsa_server_submit_at": [P, ctypes.POINTER(_Kernel), I, P, P, I, P, P, ctypes.c_double,
+                                 P],
+        "fsa_server_clock": [P],
         "fsa_server_poll": [P, ctypes.c_uint64, P, P],
         "fsa_server_wait": [P, ctypes.c_uint64, P],
+        "fsa_server_wait_for": [P, ctypes.c_uint64, ctypes.c_double, P, P],
         "fsa_server_cancel": [P, ctypes.c_uint64],
         "fsa_server_stats": [P, ctypes.POINTER(Stats)],
         "fsa_server_reset_stats": [P],
@@ -540,9 +545,12 @@ class Server:
 
     def submit(self, kernel: str, L: Sequence[float], N: Sequence[int], rho: torch.Tensor,
                phi: torch.Tensor, precision: str = "f32", eps: Optional[float] = None,
-               lam: Optional[float] = None, general: bool = False) -> int:
+               lam: Optional[float] = None, general: bool = False,
+               arrival: Optional[float] = None) -> int:
         """Queues phi = U * rho; returns a ticket.  rho and phi must stay alive
-        (and phi untouched) until the ticket completes."""
+        (and phi untouched) until the ticket completes.  arrival: when the
+        request arose, in seconds of time.monotonic() (fsa_server_clock);
+        latency is counted from it (default: now)."""
         d = len(N)
         if tuple(rho.shape) != tuple(N) or tuple(phi.shape) != tuple(N):
             raise ValueError("rho/phi shape must equal N")
@@ -554,9 +562,11 @@ class Server:
         Ls = (ctypes.c_double * d)(*[float(x) for x in L])
         Ns = (ctypes.c_int64 * d)(*[int(n) for n in N])
         t = ctypes.c_uint64()
-        _check(_lib.fsa_server_submit(self._h, ctypes.byref(k), d, Ls, Ns, PRECISIONS[precision],
-                                      ctypes.c_void_p(rho.data_ptr()),
-                                      ctypes.c_void_p(phi.data_ptr()), ctypes.byref(t)))
+        _check(_lib.fsa_server_submit_at(self._h, ctypes.byref(k), d, Ls, Ns,
+                                         PRECISIONS[precision], ctypes.c_void_p(rho.data_ptr()),
+                                         ctypes.c_void_p(phi.data_ptr()),
+                                         -1.0 if arrival is None else float(arrival),
+                                         ctypes.byref(t)))
         return t.value
 
     def poll(self, ticket: int):
@@ -566,10 +576,23 @@ class Server:
                                     ctypes.byref(st)))
         return bool(done.value), (STATUS[st.value] if done.value else None)
 
-    def wait(self, ticket: int) -> str:
+    def wait(self, ticket: int, timeout_ms: Optional[float] = None) -> Optional[str]:
+        """Status name once the request finished; None if timeout_ms ran out."""
         st = ctypes.c_int()
-        _check(_lib.fsa_server_wait(self._h, ctypes.c_uint64(ticket), ctypes.byref(st)))
-        return STATUS[st.value]
+        if timeout_ms is None:
+            _check(_lib.fsa_server_wait(self._h, ctypes.c_uint64(ticket), ctypes.byref(st)))
+            return STATUS[st.value]
+        done = ctypes.c_int()
+        _check(_lib.fsa_server_wait_for(self._h, ctypes.c_uint64(ticket), float(timeout_ms),
+                                        ctypes.byref(done), ctypes.byref(st)))
+        return STATUS[st.value] if done.value else None
+
+    @staticmethod
+    def clock() -> float:
+        """The server clock (seconds; the clock of time.monotonic)."""
+        t = ctypes.c_double()
+        _check(_lib.fsa_server_clock(ctypes.byref(t)))
+        return t.value
 
     def cancel(self, ticket: int):
         _check(_lib.fsa_server_cancel(self._h, ctypes.c_uint64(ticket)))

@@ -101,6 +101,28 @@ static void test_head_of_line_order() {
     CHECK(be.launched[1] == b && be.launched[2] == c);
 }
 
+static void test_bypass_of_a_blocked_head() {
+    Fake be;
+    Scheduler s(&be, 10000, 8);
+    uint64_t a, warm, big, small1, small2;
+    // a cached small key first
+    CHECK(s.submit(key(3, 1, 1), nullptr, nullptr, &warm, nullptr) == ST_OK);
+    CHECK(s.pump() == 1);
+    s.complete(warm, ST_OK, 0.001);
+    CHECK(s.submit(key(1, 1, 5), nullptr, nullptr, &a, nullptr) == ST_OK);    // 6000 (+1000 cached)
+    CHECK(s.pump() == 1);                                                        // in use 7000
+    CHECK(s.submit(key(2, 1, 5), nullptr, nullptr, &big, nullptr) == ST_OK);  // needs 6000: waits
+    CHECK(s.submit(key(3, 1, 1), nullptr, nullptr, &small1, nullptr) == ST_OK);  // cached, 1000
+    CHECK(s.submit(key(4, 1, 1), nullptr, nullptr, &small2, nullptr) == ST_OK);  // not cached
+    CHECK(s.pump() == 1);  // small1 passes the blocked head; small2 (a miss) does not
+    CHECK(be.launched.back() == small1);
+    CHECK(be.destroyed == 0);  // nothing evicted while work is in flight
+    s.complete(a, ST_OK, 0.002);
+    s.complete(small1, ST_OK, 0.003);
+    CHECK(s.pump() == 2);  // the head, then small2
+    CHECK(be.launched[be.launched.size() - 2] == big && be.launched.back() == small2);
+}
+
 static void test_reject_and_cancel() {
     Fake be;
     Scheduler s(&be, 10000, 1);
@@ -207,6 +229,7 @@ int main() {
     test_head_of_line_order();
     test_reject_and_cancel();
     test_cache_eviction_lru();
+    test_bypass_of_a_blocked_head();
     test_failure_isolation();
     test_slots_and_latency();
     test_cancel_all();
