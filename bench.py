@@ -845,7 +845,7 @@ def main():
         # the same arrivals with every request in FP32: the server beside
         # per_call_fp32, which runs exactly these requests
         sv["server_all_fp32"] = bench_serve(F, torch, hip, synth, duration=args.serve_seconds,
-                                               per_call=False, fp64_fraction=0.0)["server"]
+                                            per_call=False, fp64_fraction=0.0)["server"]
         log(f"  serve: {json.dumps(sv)}")
         burst = bench_serve(F, torch, hip, synth, duration=1.0, rate=6000.0, budget=2 << 30)
         log(f"  burst: {json.dumps(burst)}")

@@ -69,6 +69,7 @@ const char* fsa_last_error(void) { return g_last_error.c_str(); }
 
 fsa_status fsa_plan_create(const fsa_kernel* k, int d, const double* L, const int64_t* N,
                            fsa_precision p, fsa_plan* out) {
+    fsa::Range range("fsa_plan_create");
     if (!k || !L || !N || !out) return fail(FSA_EINVAL, "fsa_plan_create: null argument");
     const int kd = kernel_dim(k->kind);
     if (kd == 0) return fail(FSA_EINVAL, "fsa_plan_create: unknown kernel kind %d", k->kind);
@@ -212,6 +213,7 @@ fsa_status fsa_plan_query(fsa_plan pl, double* eps_used, double* h, size_t* tens
 }
 
 fsa_status fsa_build_tensor(fsa_plan pl, void* stream) {
+    fsa::Range range("fsa_build_tensor");
     if (!pl) return fail(FSA_EINVAL, "fsa_build_tensor: null plan");
     hipStream_t st = (hipStream_t)stream;
     int dev = 0;
@@ -407,10 +409,17 @@ Choice step_choice(const fsa_plan_s* pl, const Step& s) {
 // launch i and ev[2i + 1] right after it (a null pair: launch i untimed).
 static hipError_t apply_impl(const fsa_plan_s* pl, const void* rho, void* phi, void* ws,
                              hipStream_t st, hipEvent_t const* ev) {
+    static const char* const kPassRange[6] = {"fsa pass A r2c", "fsa pass B fwd_t",
+                                              "fsa pass C conv", "fsa pass D inv_t",
+                                              "fsa pass E c2r", "fsa spectral"};
+    Range range("fsa_apply");
     Step steps[kMaxSteps];
     const int ns = schedule(pl, tune::get_slabs(pl), steps);
     hipError_t e = hipSuccess;
     for (int i = 0; i < ns && e == hipSuccess; ++i) {
+        int kind = steps[i].k >= kSpectralStep ? 5 : steps[i].k;
+        if (kind < 5 && pl->prec != FSA_DD && pl->d == 2) kind = kind == 0 ? 0 : kind == 1 ? 2 : 4;
+        Range pass_range(kPassRange[kind]);
         const bool timed = ev && ev[2 * i];
         if (timed) e = hipEventRecord(ev[2 * i], st);
         if (e == hipSuccess)

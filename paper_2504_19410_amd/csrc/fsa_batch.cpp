@@ -238,6 +238,7 @@ fsa_status build_entry(int n, const fsa_plan* plans, const void* const* rho, voi
         return FSA_EDEVICE;
     }
     // capture the stage-ordered launches on a private stream
+    fsa::Range range("fsa_apply_batched capture");
     hipStream_t cap = nullptr;
     err = hipStreamCreateWithFlags(&cap, hipStreamNonBlocking);
     if (err != hipSuccess) {
@@ -356,6 +357,7 @@ fsa_status fsa_batch_workspace_bytes(int n, const fsa_plan* plans, size_t* bytes
 fsa_status fsa_apply_batched(int n, const fsa_plan* plans, const void* const* rho,
                              void* const* phi, void* workspace, size_t workspace_bytes,
                              void* stream) {
+    fsa::Range range("fsa_apply_batched");
     int dev = 0;
     fsa_status s = check_batch("fsa_apply_batched", n, plans, rho, phi, workspace,
                                workspace_bytes, &dev);
@@ -392,6 +394,7 @@ fsa_status fsa_apply_batched(int n, const fsa_plan* plans, const void* const* rh
         g_cache.push_back(std::move(e));
         hit = g_cache.back().get();
     }
+    fsa::Range replay("fsa_apply_batched replay");
     hipError_t err = hipGraphLaunch(hit->exec, (hipStream_t)stream);
     if (err != hipSuccess) {
         fsa::set_last_error(hipGetErrorString(err));

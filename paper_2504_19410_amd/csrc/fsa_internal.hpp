@@ -2,6 +2,7 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <rocprofiler-sdk-roctx/roctx.h>
 
 #include <cstddef>
 #include <cstdint>
@@ -13,6 +14,16 @@
 struct fsa_plan_s;
 
 namespace fsa {
+
+// A named host-side range for profilers (roctx: rocprofv3 --marker-trace
+// shows it on the calling thread's timeline); costs a library call when no
+// tool is attached.
+struct Range {
+    explicit Range(const char* name) { roctxRangePushA(name); }
+    ~Range() { roctxRangePop(); }
+    Range(const Range&) = delete;
+    Range& operator=(const Range&) = delete;
+};
 
 // Launches a kernel and returns the launch status.
 template <typename... Params, typename... Args>

@@ -88,6 +88,7 @@ public:
     }
 
     Status build_plan(const PlanInfo& p, std::string* err) override {
+    fsa::Range range("fsa_server tensor build");
         fsa_plan pl = (fsa_plan)p.handle;
         fsa_status s = fsa_build_tensor(pl, build_stream_);
         if (s != FSA_OK) {
@@ -136,6 +137,7 @@ public:
     // Called by the scheduler's pump, one at a time, with the slot reserved
     // for this request (its previous request has completed).
     Status launch(const Request& r, const PlanInfo& p, int slot, std::string* err) override {
+    fsa::Range range("fsa_server launch");
         const size_t q = stream_of(r, slot);
         hipStream_t st = streams_[q];
         fsa_plan pl = (fsa_plan)p.handle;
@@ -295,6 +297,7 @@ fsa_status fsa_server_create(size_t hbm_budget_bytes, int max_inflight, int n_st
 fsa_status fsa_server_submit_at(fsa_server s, const fsa_kernel* k, int d, const double* L,
                                 const int64_t* N, fsa_precision p, const void* rho, void* phi,
                                 double t_arrival, uint64_t* ticket) {
+    fsa::Range range("fsa_server_submit");
     if (!s || !k || !L || !N || !rho || !phi || !ticket || d < 2 || d > 3) {
         fsa::set_last_error("fsa_server_submit: bad arguments");
         return FSA_EINVAL;

@@ -515,6 +515,7 @@ fsa_status fsa_tune_get_slabs(int precision, const int64_t* N, int* slabs, doubl
 
 fsa_status fsa_autotune(fsa_plan pl, const void* rho, void* phi, void* workspace, void* stream,
                         int reps) {
+    fsa::Range range("fsa_autotune");
     if (!pl || !rho || !phi || !workspace)
         return fail(FSA_EINVAL, "fsa_autotune: null argument");
     if (!pl->built) return fail(FSA_ESTATE, "fsa_autotune: tensor not built");
