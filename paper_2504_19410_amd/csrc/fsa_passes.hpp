@@ -88,15 +88,40 @@ constexpr bool fresh_lane() {
     return (P & (P - 1)) != 0 && (sizeof(R) == 8 || P >= 768);
 }
 
-// Contiguous chunk of work items for this workgroup (uniform over the group).
-struct Chunk {
-    int first, last;
-    __device__ Chunk(int items) {
-        const int c = (items + (int)gridDim.x - 1) / (int)gridDim.x;
-        first = (int)blockIdx.x * c;
-        last = first + c < items ? first + c : items;
+// The work items one workgroup visits, in order: first, first + stride, ...
+// below last (uniform over the group).
+//   Default: a contiguous chunk per workgroup.
+//   XCD (for tiles whose rows are narrower than a 128-byte cache line, so
+// that neighbouring tiles share lines): the dispatcher deals workgroups to
+// the 8 XCDs in turn (workgroup g runs on XCD g mod 8), and each XCD has its
+// own L2.  Each XCD takes a contiguous eighth of the items, which its
+// workgroups visit side by side (workgroup g, the s-th of its XCD, takes
+// items s, s + G/8, ... of that eighth): neighbouring tiles are in flight at
+// the same time under one L2, so a shared line is read from memory once
+// instead of once per tile.
+struct Walk {
+    int first, last, stride;
+    template <bool XCD>
+    __device__ static Walk make(int items) {
+        const int G = (int)gridDim.x, g = (int)blockIdx.x;
+        if (XCD && G >= 8 && (G & 7) == 0) {
+            const int per = (items + 7) / 8, x = g & 7, s = g >> 3;
+            const int lo = x * per, hi = lo + per < items ? lo + per : items;
+            return Walk{lo + s, hi, G >> 3};
+        }
+        const int c = (items + G - 1) / G;
+        const int first = g * c;
+        return Walk{first, first + c < items ? first + c : items, 1};
     }
 };
+
+// Whether a transposing tile of WT lines of complex values of `csize` bytes
+// reads and writes rows narrower than a cache line.  Pass A takes the XCD walk
+// then (2D batch, rows of 1024: 300 -> 280 us, HBM fetches 1.075 -> 1.013 x
+// the algorithmic bytes); the other transposing passes keep their chunks:
+// pass E at the same length lost its re-reads (2.3 -> 1.0 x) but ran slower
+// (292 -> 354 us), every workgroup of an XCD reading the same lines at once.
+constexpr bool narrow_rows(int wt, int csize) { return wt * csize < 128; }
 
 // ---------------------------------------------------------------------------
 // Work sources.  A pass kernel walks global work items; a source maps an
@@ -190,7 +215,7 @@ __global__ __launch_bounds__((R2c<R, M, VAR>::THREADS)) void k_r2c(
             w2[i] = tw2M[k < K::H ? k : 0];
         }
     }
-    const Chunk ch(src.total);
+    const Walk ch = Walk::make<narrow_rows(K::WT, (int)sizeof(C))>(src.total);
     C pf[K::NBT0 * K::HALF];
     int cur_pf = -1, cur_it = -1;  // job cursors of the prefetch and the item walks
     auto prefetch = [&](int item) {
@@ -211,7 +236,7 @@ __global__ __launch_bounds__((R2c<R, M, VAR>::THREADS)) void k_r2c(
         }
     };
     if (ch.first < ch.last) prefetch(ch.first);
-    for (int item = ch.first; item < ch.last; ++item) {
+    for (int item = ch.first; item < ch.last; item += ch.stride) {
         const int tid = fresh_lane<R, M>() ? opaque(tid0) : tid0;  // per item: fresh_lane
         int loc;
         const JobR2c jb = src.get(item, loc, cur_it);
@@ -225,7 +250,7 @@ __global__ __launch_bounds__((R2c<R, M, VAR>::THREADS)) void k_r2c(
 #pragma unroll
             for (int q = 0; q < K::R0; ++q)
                 v[b * K::R0 + q] = (q < K::HALF && active) ? pf[b * K::HALF + q] : mk(R(0), R(0));
-        if (item + 1 < ch.last) prefetch(item + 1);
+        if (item + ch.stride < ch.last) prefetch(item + ch.stride);
         if constexpr (F::REG_TW) F::template run_r<true>(v, scr, tid, w);
         else F::template run_g<true>(v, scr, tid, twM);
         F::store_last(v, tid, M, [&](int k, C z) { scr[F::pad(k)] = z; });
@@ -300,7 +325,7 @@ __global__ __launch_bounds__((C2r<R, M, VAR>::THREADS)) void k_c2r(
     if constexpr (F::REG_TW) F::load_tw(w, tid, twM);
     C w2[F::REG_TW ? F::V : 1];  // e^{-i pi k / M} at this thread's first-stage indices k
     if constexpr (F::REG_TW) F::load_first(w2, tid, M, [&](int k) { return tw2M[k]; });
-    const Chunk ch(src.total);
+    const Walk ch = Walk::make<false>(src.total);
     C tp[K::PREFETCH ? K::NT : 1];
     auto tile_elem = [&](const JobC2r& jb, int outer, int col0, int e) {
         const int k = e / K::WT, ww = e - k * K::WT;
@@ -320,7 +345,7 @@ __global__ __launch_bounds__((C2r<R, M, VAR>::THREADS)) void k_c2r(
     if constexpr (K::PREFETCH) {
         if (ch.first < ch.last) prefetch(ch.first);
     }
-    for (int item = ch.first; item < ch.last; ++item) {
+    for (int item = ch.first; item < ch.last; item += ch.stride) {
         const int tid = fresh_lane<R, M>() ? opaque(tid0) : tid0;  // per item: fresh_lane
         int loc;
         const JobC2r jb = src.get(item, loc, cur_it);
@@ -342,7 +367,7 @@ __global__ __launch_bounds__((C2r<R, M, VAR>::THREADS)) void k_c2r(
         }
         sync_wg_lds();
         if constexpr (K::PREFETCH) {
-            if (item + 1 < ch.last) prefetch(item + 1);
+            if (item + ch.stride < ch.last) prefetch(item + ch.stride);
         }
         C v[F::V];
         F::load_first_at(v, tid, M, [&](int k, int pos) {
@@ -414,7 +439,7 @@ __global__ __launch_bounds__((FwdT<R, P, VAR>::THREADS)) void k_fwd_t(
     C* scr = lds + team * F::SCR;
     C w[F::REG_TW ? F::NTW : 1];
     if constexpr (F::REG_TW) F::load_tw(w, tid, tw);
-    const Chunk ch(src.total);
+    const Walk ch = Walk::make<false>(src.total);
     C pf[K::NBT0 * K::HALF];
     int cur_pf = -1, cur_it = -1;  // job cursors of the prefetch and the item walks
     auto prefetch = [&](int item) {
@@ -435,7 +460,7 @@ __global__ __launch_bounds__((FwdT<R, P, VAR>::THREADS)) void k_fwd_t(
         }
     };
     if (ch.first < ch.last) prefetch(ch.first);
-    for (int item = ch.first; item < ch.last; ++item) {
+    for (int item = ch.first; item < ch.last; item += ch.stride) {
         const int tid = fresh_lane<R, P>() ? opaque(tid0) : tid0;  // per item: fresh_lane
         int loc;
         const JobT jb = src.get(item, loc, cur_it);
@@ -450,7 +475,7 @@ __global__ __launch_bounds__((FwdT<R, P, VAR>::THREADS)) void k_fwd_t(
 #pragma unroll
             for (int q = 0; q < K::R0; ++q)
                 v[b * K::R0 + q] = (q < K::HALF && active) ? pf[b * K::HALF + q] : mk(R(0), R(0));
-        if (item + 1 < ch.last) prefetch(item + 1);
+        if (item + ch.stride < ch.last) prefetch(item + ch.stride);
         if constexpr (F::REG_TW) F::template run_r<true>(v, scr, tid, w);
         else F::template run_g<true>(v, scr, tid, tw);
         sync_wg_lds();
@@ -499,7 +524,7 @@ __global__ __launch_bounds__((InvT<R, P, VAR>::THREADS)) void k_inv_t(
     C* scr = lds + team * F::SCR;
     C w[F::REG_TW ? F::NTW : 1];
     if constexpr (F::REG_TW) F::load_tw(w, tid, tw);
-    const Chunk ch(src.total);
+    const Walk ch = Walk::make<false>(src.total);
     C tp[K::PREFETCH ? K::NT : 1];
     auto tile_elem = [&](const JobT& jb, int p2, int col0, int e) {
         const int p1 = e / K::WT, ww = e - p1 * K::WT;
@@ -520,7 +545,7 @@ __global__ __launch_bounds__((InvT<R, P, VAR>::THREADS)) void k_inv_t(
     if constexpr (K::PREFETCH) {
         if (ch.first < ch.last) prefetch(ch.first);
     }
-    for (int item = ch.first; item < ch.last; ++item) {
+    for (int item = ch.first; item < ch.last; item += ch.stride) {
         const int tid = fresh_lane<R, P>() ? opaque(tid0) : tid0;  // per item: fresh_lane
         int loc;
         const JobT jb = src.get(item, loc, cur_it);
@@ -543,7 +568,7 @@ __global__ __launch_bounds__((InvT<R, P, VAR>::THREADS)) void k_inv_t(
         }
         sync_wg_lds();
         if constexpr (K::PREFETCH) {
-            if (item + 1 < ch.last) prefetch(item + 1);
+            if (item + ch.stride < ch.last) prefetch(item + ch.stride);
         }
         C v[F::V];
         F::load_first(v, tid, P, [&](int p1) { return lds[p1 * K::TS + team]; });
