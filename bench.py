@@ -289,6 +289,59 @@ def bench_precision(F, torch, hip, prob, rho64, prec, steps, warmup, tune=True):
     }, phi
 
 
+def bench_conv_variants(F, torch, hip, prob, rho64, tune_file, steps=40):
+    """Pass C of the bench workload in every compiled variant of its kernel
+    at full occupancy, the other passes as the table has them: event pairs
+    around the pass-C launches only, median per launch over `steps`
+    evaluations after a settle phase.  Variant 3 exchanges the operands
+    between the last two stages of each 512-point transform across lanes
+    (DPP and lane swaps) instead of through the LDS."""
+    out = {}
+    for prec in ("f32", "f64"):
+        plan = F.Plan(prob.kernel, prob.L, prob.N, prec, eps=prob.eps, lam=prob.lam).build()
+        rho = torch.from_numpy(rho64).to(F.DTYPES[prec]).cuda()
+        phi = torch.empty_like(rho)
+        ws = plan.workspace()
+        name, length = plan.passes()[2]
+        launches = plan.launches()
+        ci = [i for i, ln in enumerate(launches) if ln == name]
+        lines = plan.pass_lines()[2] // len(ci)
+        keep = F.tune_get(prec, name, length, lines)
+        bytes_launch = model_bytes(prob.N, prec)["C_conv"] / len(ci)
+        res = {}
+        for var in F.tune_variants(prec, name, length):
+            F.tune_set(prec, name, length, var, 0, lines)
+            timed_evals(lambda: plan.apply(rho, phi, ws), torch, hip, 5, 5, settle_s=0.1)
+            per = []
+            for _ in range(steps):
+                evs = [None] * (2 * len(launches))
+                for i in ci:
+                    evs[2 * i], evs[2 * i + 1] = hip.event(), hip.event()
+                plan.apply_events(rho, phi, evs, ws)
+                torch.cuda.synchronize()
+                for i in ci:
+                    per.append(hip.ms(evs[2 * i], evs[2 * i + 1]))
+                    hip.destroy(evs[2 * i])
+                    hip.destroy(evs[2 * i + 1])
+            us = float(np.median(per)) * 1e3
+            res[f"v{var}"] = {"us_per_launch": round(us, 2),
+                              "GBps": round(bytes_launch / (us * 1e-6) / 1e9, 1),
+                              "frac": round(bytes_launch / (us * 1e-6) / HBM_PEAK_BPS, 4)}
+        if tune_file:
+            F.tune_load(tune_file)
+        else:
+            F.tune_set(prec, name, length, keep[0], keep[1], lines)
+        plan.close()
+        out[prec] = {"launches_per_step": len(ci), "variants": res}
+    out["variants"] = {"v0": "default plan and workgroup", "v1": "alternate radix family",
+                       "v2": "half-size workgroups",
+                       "v3": "default plan, last exchange of each transform across lanes "
+                             "(DPP row rotation + v_permlane16/32_swap) instead of LDS",
+                       "v4": "default plan, first forward stage as FP32 16x16x4 MFMA "
+                             "products (operands loaded in the MFMA layout)"}
+    return out
+
+
 def precomp_sweep(F, torch, hip, n=256, gammas=(1, 2, 4, 8, 16), reps=5):
     """Tensor generation (Precomp) time against anisotropy: 3D Coulomb on
     [-8,8]^2 x [-8/g, 8/g] at n^3 (h_z = h/g), eps = R0/8; the paper reports
@@ -873,6 +926,8 @@ def main():
         del phis
     sweep = precomp_sweep(F, torch, hip, n=args.n)
     log(f"  precomp vs anisotropy (ms): {sweep['ms_by_anisotropy']}")
+    conv_vars = bench_conv_variants(F, torch, hip, prob, rho64, args.tune_file)
+    log(f"  pass C by variant: {json.dumps(conv_vars)}")
     ddi = None
     if not args.no_ddi:
         ddi = bench_ddi(F, torch, hip, synth, n=args.n)
@@ -989,6 +1044,7 @@ def main():
         "precomp_ms": r64["precomp_ms"],
         "precomp": r64["precomp"],
         "precomp_vs_anisotropy": sweep,
+        "pass_c_variants": conv_vars,
         "ddi": ddi,
         "general": general,
         "double_double": dd,

@@ -273,11 +273,16 @@ typedef enum {
  * (precision, pass, length) takes the single-evaluation entry. */
 #define FSA_PASS_BATCHED 16
 
-/* Every pass kernel exists in up to three compiled variants per length:
+/* Every pass kernel exists in up to five compiled variants per length:
  *   0  default radix plan and workgroup size;
  *   1  alternate radix family (another radix split and number of threads
  *      per transform);
- *   2  half-size workgroups (half the lines per tile, or teams per group).
+ *   2  half-size workgroups (half the lines per tile, or teams per group);
+ *   3  the default plan with the stage exchanges that only trade register
+ *      and lane bits of a one-wave team done across lanes (DPP and lane
+ *      swaps) instead of through the LDS (the fused pass at length 512);
+ *   4  the default plan with the first forward stage of the fused pass as
+ *      a matrix product on the matrix cores (FP32 MFMA; length 512).
  * and its persistent grid may use `occupancy` resident workgroups per CU
  * (0 = as many as fit).  The library keeps one process-wide table of
  * choices; untuned entries use variant 0 at full occupancy.  fsa_apply,

@@ -28,9 +28,13 @@ SOURCES = [
     "fsa_launch_f32_v0.hip",
     "fsa_launch_f32_v1.hip",
     "fsa_launch_f32_v2.hip",
+    "fsa_launch_f32_v3.hip",
+    "fsa_launch_f32_v4.hip",
     "fsa_launch_f64_v0.hip",
     "fsa_launch_f64_v1.hip",
     "fsa_launch_f64_v2.hip",
+    "fsa_launch_f64_v3.hip",
+    "fsa_launch_f64_v4.hip",
 ]
 
 CXXFLAGS = [

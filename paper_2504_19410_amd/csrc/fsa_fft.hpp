@@ -430,7 +430,7 @@ __device__ __forceinline__ int team_index() {
 // Team transform of length P, direction INV.
 // ---------------------------------------------------------------------------
 
-template <typename R, int P_, bool INV, int ALT = 0>
+template <typename R, int P_, bool INV, int ALT = 0, int XCH = 0>
 struct Fft {
     using C = cpx<R>;
     static constexpr int P = P_;
@@ -541,6 +541,92 @@ struct Fft {
             if constexpr (ZH && s == 0) dft_zh<RAD, INV>(&v[b * RAD]);
             else dft<RAD, INV>(&v[b * RAD]);
         }
+    }
+
+    // ---- exchanges in registers (XCH = 1) ----------------------------------
+    // The exchange before stage s only trades the register index with lane
+    // bits where the team is one wave (T = 64) whose threads run one radix-8
+    // butterfly at stages s-1 and s, with ns(s-1) = 8: thread j leaves its
+    // output q at y[(j / 8) 64 + j % 8 + 8 q], and thread j' = 8 a + b reads
+    // its input q' at y[j' + 64 q'], which is output a of thread 8 q' + b.
+    // So register bit i trades places with lane bit 3 + i (i = 0, 1, 2), and
+    // with XCH = 1 that exchange is done across lanes instead of through the
+    // LDS: for each pair of registers that differ in bit i, the lanes whose
+    // bit 3 + i is set take the partner lane's upper register and give it
+    // their lower one (swap_bit).  Everywhere else the exchange stays in LDS.
+    static constexpr bool reg_exchange(int s) {
+        return XCH == 1 && T == 64 && s >= 1 && s < S && radix(s - 1) == 8 && radix(s) == 8 &&
+               nbt(s - 1) == 1 && nbt(s) == 1 && ns(s - 1) == 8;
+    }
+    static constexpr bool has_reg_exchange() {
+        for (int s = 1; s < S; ++s)
+            if (reg_exchange(s)) return true;
+        return false;
+    }
+    struct Words {
+        unsigned w[sizeof(C) / 4];
+    };
+    static constexpr int NW = (int)(sizeof(C) / 4);
+
+    // The same exchange on the registers of the whole team, v[lane][q]: the
+    // pair swap of every register bit with its lane bit, one bit at a time
+    // (the host emulation of swap_bit).
+    static void reg_exchange_team(C (*v)[V]) {
+        for (int rb = 0; rb < 3; ++rb) {
+            const int lb = 3 + rb;
+            for (int q = 0; q < 8; ++q) {
+                if ((q >> rb) & 1) continue;
+                const int q1 = q | (1 << rb);
+                C na[64], nb[64];
+                for (int l = 0; l < 64; ++l) {
+                    const int p = l ^ (1 << lb);
+                    const bool hi = (l >> lb) & 1;
+                    na[l] = hi ? v[p][q1] : v[l][q];
+                    nb[l] = hi ? v[l][q1] : v[p][q];
+                }
+                for (int l = 0; l < 64; ++l) {
+                    v[l][q] = na[l];
+                    v[l][q1] = nb[l];
+                }
+            }
+        }
+    }
+
+    // ---- the first forward stage as a matrix product (FP32 16x16x4 MFMA) --
+    // For a one-wave team of one radix-8 butterfly per thread (length 512)
+    // whose operands q >= 4 are zero (the zero-padded input): butterfly j
+    // takes x[j + 64 q], q < 4, and gives y[j][k] = sum_q x[j + 64 q]
+    // e^{-2 pi i q k / 8}.  In real form, Y = A X with X (8 x 64: real and
+    // imaginary part of each operand, row u = 2 q + part) and Y (16 x 64:
+    // row m = 2 k + part).  The MFMA computes D (16 x 16) += A (16 x 4)
+    // B (4 x 16); lane l gives A[l % 16][l / 16] and B[l / 16][l % 16] and
+    // holds D[4 (l / 16) + r][l % 16], r = 0..3.  Butterflies 16 g .. 16 g +
+    // 15 form column block g, rows u = 4 ks .. 4 ks + 3 K step ks.
+    static constexpr bool mfma_first_ok() {
+        return !INV && T == 64 && radix(0) == 8 && nbt(0) == 1 && P_ == 512;
+    }
+    // lane's A operand at K step ks
+    FSA_HD static float mfma0_a(int lane, int ks) {
+        const float h = 0.70710678118654752f;  // cos and sin of 2 pi n / 8
+        const float cs[8] = {1.f, h, 0.f, -h, -1.f, -h, 0.f, h};
+        const float sn[8] = {0.f, h, 1.f, h, 0.f, -h, -1.f, -h};
+        const int m = lane % 16, u = 4 * ks + lane / 16;
+        const int n = ((u / 2) * (m / 2)) % 8;
+        // (a + i b) e^{-i t} = (a cos t + b sin t) + i (b cos t - a sin t)
+        if (m % 2 == 0) return (u % 2 == 0) ? cs[n] : sn[n];
+        return (u % 2 == 0) ? -sn[n] : cs[n];
+    }
+    // input index whose part mfma0_part(lane) is lane's B operand for column
+    // block g, K step ks (always < P / 2)
+    FSA_HD static int mfma0_b_index(int lane, int g, int ks) {
+        return 16 * g + lane % 16 + 64 * (2 * ks + (lane / 16) / 2);
+    }
+    FSA_HD static int mfma0_part(int lane) { return (lane / 16) % 2; }
+    // D registers 2 h, 2 h + 1 (real, imaginary) of lane, column block g:
+    // output k = 2 (lane / 16) + h of butterfly j = 16 g + lane % 16, which
+    // the stage-0 store puts at scratch slot pad(8 j + k)
+    FSA_HD static int mfma0_slot(int lane, int g, int h) {
+        return pad(8 * (16 * g + lane % 16) + 2 * (lane / 16) + h);
     }
 
     // the inverse of a palindromic plan has the forward's (radix, NS) per
@@ -662,14 +748,66 @@ struct Fft {
         asm volatile("" ::: "memory");
     }
 
+    // Register bit RB trades places with lane bit 3 + RB (see reg_exchange):
+    // lane bit 5 by v_permlane32_swap, lane bit 4 by v_permlane16_swap (each
+    // swaps the upper half-wave, or the odd rows of 16 lanes, of its first
+    // register with the lower half, or even rows, of its second), lane bit 3
+    // by a DPP rotation of each 16-lane row by 8 (lane l reads lane l ^ 8)
+    // and two selects.  Per 32-bit word of each value.
+    template <int RB>
+    static __device__ __forceinline__ void swap_bit(C (&v)[V], int lane) {
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            if ((q >> RB) & 1) continue;
+            constexpr int D = 1 << RB;
+            Words a = __builtin_bit_cast(Words, v[q]), b = __builtin_bit_cast(Words, v[q + D]);
+#pragma unroll
+            for (int w = 0; w < NW; ++w) {
+                if constexpr (RB == 2) {
+                    const auto r = __builtin_amdgcn_permlane32_swap(a.w[w], b.w[w], false, false);
+                    a.w[w] = r[0];
+                    b.w[w] = r[1];
+                } else if constexpr (RB == 1) {
+                    const auto r = __builtin_amdgcn_permlane16_swap(a.w[w], b.w[w], false, false);
+                    a.w[w] = r[0];
+                    b.w[w] = r[1];
+                } else {
+                    const unsigned ta =
+                        (unsigned)__builtin_amdgcn_update_dpp(0, (int)a.w[w], 0x128, 0xf, 0xf, false);
+                    const unsigned tb =
+                        (unsigned)__builtin_amdgcn_update_dpp(0, (int)b.w[w], 0x128, 0xf, 0xf, false);
+                    const bool hi = (lane >> 3) & 1;
+                    const unsigned na = hi ? tb : a.w[w], nb = hi ? b.w[w] : ta;
+                    a.w[w] = na;
+                    b.w[w] = nb;
+                }
+            }
+            v[q] = __builtin_bit_cast(C, a);
+            v[q + D] = __builtin_bit_cast(C, b);
+        }
+    }
+
+    // the exchange before stage s: in registers where reg_exchange(s), else
+    // through the scratch with LDS-only synchronisation
     template <int s>
-    static __device__ __forceinline__ void run_r_from(C (&v)[V], C* scr, int tid,
-                                                      const C (&w)[NTW]) {
-        if constexpr (s < S) {
+    static __device__ __forceinline__ void exchange(C (&v)[V], C* scr, int tid) {
+        if constexpr (reg_exchange(s)) {
+            swap_bit<0>(v, tid);
+            swap_bit<1>(v, tid);
+            swap_bit<2>(v, tid);
+        } else {
             store<s - 1>(v, scr, tid);
             sync_lds();
             load<s>(v, scr, tid);
             sync_lds();
+        }
+    }
+
+    template <int s>
+    static __device__ __forceinline__ void run_r_from(C (&v)[V], C* scr, int tid,
+                                                      const C (&w)[NTW]) {
+        if constexpr (s < S) {
+            exchange<s>(v, scr, tid);
             compute_r<s>(v, tid, w);
             run_r_from<s + 1>(v, scr, tid, w);
         }
@@ -679,10 +817,7 @@ struct Fft {
     static __device__ __forceinline__ void run_g_from(C (&v)[V], C* scr, int tid,
                                                       const C* __restrict__ tw) {
         if constexpr (s < S) {
-            store<s - 1>(v, scr, tid);
-            sync_lds();
-            load<s>(v, scr, tid);
-            sync_lds();
+            exchange<s>(v, scr, tid);
             compute<s>(v, tid, tw);
             run_g_from<s + 1>(v, scr, tid, tw);
         }
@@ -715,10 +850,16 @@ struct Fft {
     static __device__ __forceinline__ void run_from(C (&v)[V], C* scr, int tid,
                                                     const C* __restrict__ tw) {
         if constexpr (s < S) {
-            store<s - 1>(v, scr, tid);
-            sync();
-            load<s>(v, scr, tid);
-            sync();
+            if constexpr (reg_exchange(s)) {
+                swap_bit<0>(v, tid);
+                swap_bit<1>(v, tid);
+                swap_bit<2>(v, tid);
+            } else {
+                store<s - 1>(v, scr, tid);
+                sync();
+                load<s>(v, scr, tid);
+                sync();
+            }
             compute<s>(v, tid, tw);
             run_from<s + 1>(v, scr, tid, tw);
         }

@@ -81,13 +81,15 @@ hipError_t build_tensor_device(const KernelParams& kp, int d, const double* L, c
 hipError_t build_twiddles(fsa_precision prec, int n, void* out, hipStream_t st);
 
 // Launch configuration of one pass: compile-time variant (0 default, 1
-// alternate radix family, 2 half-size workgroups) and the number of resident
-// workgroups per CU the persistent grid uses (0: as many as fit).
+// alternate radix family, 2 half-size workgroups, 3 exchanges across lanes,
+// 4 first stage on the matrix cores)
+// and the number of resident workgroups per CU the persistent grid uses (0:
+// as many as fit).
 struct Choice {
     int var = 0;
     int occ = 0;
 };
-constexpr int kNumVariants = 3;
+constexpr int kNumVariants = 5;
 
 // Pass launchers of one variant (fsa_launch_<prec>_v<var>.hip).  Complex
 // arrays are interleaved (re, im) of R.  Each returns hipErrorInvalidValue
@@ -127,6 +129,8 @@ struct Launch {
     case 0: return LaunchV<R, 0>::call;                         \
     case 1: return LaunchV<R, 1>::call;                         \
     case 2: return LaunchV<R, 2>::call;                         \
+    case 3: return LaunchV<R, 3>::call;                         \
+    case 4: return LaunchV<R, 4>::call;                         \
     }                                                           \
     return hipErrorInvalidValue;
     static hipError_t r2c(int M, const R* rho, void* out, int n_outer, int n_inner,
@@ -161,6 +165,8 @@ struct Launch {
         case 0: return LaunchV<R, 0>::items(pass, len, job);
         case 1: return LaunchV<R, 1>::items(pass, len, job);
         case 2: return LaunchV<R, 2>::items(pass, len, job);
+        case 3: return LaunchV<R, 3>::items(pass, len, job);
+        case 4: return LaunchV<R, 4>::items(pass, len, job);
         }
         return -1;
     }
@@ -169,6 +175,8 @@ struct Launch {
         case 0: return LaunchV<R, 0>::distinct(pass, len);
         case 1: return LaunchV<R, 1>::distinct(pass, len);
         case 2: return LaunchV<R, 2>::distinct(pass, len);
+        case 3: return LaunchV<R, 3>::distinct(pass, len);
+        case 4: return LaunchV<R, 4>::distinct(pass, len);
         }
         return false;
     }
@@ -177,6 +185,8 @@ struct Launch {
         case 0: return LaunchV<R, 0>::max_occ(pass, len);
         case 1: return LaunchV<R, 1>::max_occ(pass, len);
         case 2: return LaunchV<R, 2>::max_occ(pass, len);
+        case 3: return LaunchV<R, 3>::max_occ(pass, len);
+        case 4: return LaunchV<R, 4>::max_occ(pass, len);
         }
         return 0;
     }

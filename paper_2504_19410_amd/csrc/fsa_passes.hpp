@@ -54,11 +54,17 @@ constexpr int cdiv(int a, int b) { return (a + b - 1) / b; }
 // radix family of make_fft_plan (another radix split and number of threads
 // per transform).  2: half-size workgroups (half the lines per tile, or half
 // the teams per workgroup): less LDS and fewer threads per group, more
-// resident groups per CU.  A variant that comes out identical to variant 0
-// at some length is marked not DISTINCT and never instantiated there.
-constexpr int kVariants = 3;
+// resident groups per CU.  3: the default plan with the stage exchanges
+// that only trade register and lane bits done across lanes instead of
+// through the LDS (Fft::reg_exchange; the fused pass at length 512).  4:
+// the default plan with the first forward stage of the fused pass as a
+// matrix product on the matrix cores (FP32, length 512; Conv::MFMA0).  A
+// variant that comes out identical to variant 0 at some length is marked
+// not DISTINCT and never instantiated there.
+constexpr int kVariants = 5;
 constexpr int var_alt(int var) { return var == 1 ? 1 : 0; }
 constexpr int var_cap(int var, int cap) { return var == 2 ? cap / 2 : cap; }
+constexpr int var_xch(int var) { return var == 3 ? 1 : 0; }
 
 // Workgroup barrier that orders LDS only: global loads in flight (prefetch)
 // and global stores keep flying.
@@ -304,8 +310,11 @@ struct C2r {
     static constexpr int LDS = cmax(WT * F::SCR, H * TS);
     static constexpr int THREADS = WT * T;
     static constexpr int NT = (H * WT + THREADS - 1) / THREADS;  // tile elements per thread
-    // prefetch the next tile into registers only if it fits ~48 VGPRs
-    static constexpr bool PREFETCH = NT * (int)(sizeof(C) / 4) <= 48;
+    // prefetch the next tile into registers only if it fits ~48 VGPRs, and
+    // not beside the 16 operands per thread of an FP32 plan at M = 2048 (the
+    // prefetch pushed that kernel past 256 VGPRs into scratch)
+    static constexpr bool PREFETCH =
+        NT * (int)(sizeof(C) / 4) <= 48 && !(sizeof(R) == 4 && F::V >= 16 && M >= 2048);
     static constexpr int R0 = F::first_radix(), NB0 = F::first_stride(), NBT0 = F::first_nbt();
     static constexpr bool DISTINCT =
         VAR == 0 || (VAR == 1 ? fft_alt_distinct(M) : WT != C2r<R, M, 0>::WT);
@@ -598,8 +607,8 @@ __global__ __launch_bounds__((InvT<R, P, VAR>::THREADS)) void k_inv_t(
 // ---------------------------------------------------------------------------
 template <typename R, int P, int VAR = 0>
 struct Conv {
-    using Ff = Fft<R, P, false, var_alt(VAR)>;
-    using Fi = Fft<R, P, true, var_alt(VAR)>;
+    using Ff = Fft<R, P, false, var_alt(VAR), var_xch(VAR)>;
+    using Fi = Fft<R, P, true, var_alt(VAR), var_xch(VAR)>;
     using C = cpx<R>;
     static constexpr int T = Ff::T;
     static constexpr int TPW = cmax(1, var_cap(VAR, 256) / T);  // teams per workgroup
@@ -613,8 +622,17 @@ struct Conv {
     static constexpr int NPF = NBT0 * HALF;
     static_assert(R0 % 2 == 0, "the zero half must be whole first-stage operands");
     static_assert(Ff::last_radix() == Fi::first_radix(), "register hand-off");
+    // Variant 4: the first forward stage as a matrix product on the matrix
+    // cores (Fft::mfma_first_ok: FP32, length 512): four pairs of FP32
+    // 16x16x4 MFMAs over the 64 butterflies, operands loaded from HBM
+    // straight into the B layout, outputs stored to the LDS where the
+    // stage-0 store puts them; the transform goes on from stage 1.
+    static constexpr bool MFMA0 = VAR == 4 && sizeof(R) == 4 && Ff::mfma_first_ok();
     static constexpr bool DISTINCT =
-        VAR == 0 || (VAR == 1 ? fft_alt_distinct(P) : TPW != Conv<R, P, 0>::TPW);
+        VAR == 0 || (VAR == 1   ? fft_alt_distinct(P)
+                     : VAR == 2 ? TPW != Conv<R, P, 0>::TPW
+                     : VAR == 3 ? Ff::has_reg_exchange()
+                                : MFMA0);
 };
 
 // work item t -> pencil, ordered (p2; p1 = 0, N1, 1, P1-1, 2, P1-2, ...)
@@ -654,7 +672,18 @@ __global__ __launch_bounds__((Conv<R, P, VAR>::THREADS)) void k_conv(
     const int chunk = (total + slots - 1) / slots;
     const int first = (blockIdx.x * K::TPW + team) * chunk;
 
-    C pf[K::NPF];
+    C pf[K::MFMA0 ? 1 : K::NPF];
+    // variant 4: this lane's B operands (butterfly group g, K step ks at
+    // pb[2 g + ks]) and A operands (K step ks), see Conv::MFMA0.  Lane l
+    // gives B row l / 16 (operand q = 2 ks + (l / 16) / 2, its real part for
+    // even l / 16, imaginary for odd) of column l % 16 (butterfly 16 g +
+    // l % 16), and A entry (l % 16, 4 ks + l / 16).
+    float pb[K::MFMA0 ? 8 : 1];
+    float am[2] = {0.f, 0.f};
+    if constexpr (K::MFMA0) {
+        am[0] = Ff::mfma0_a(tid, 0);
+        am[1] = Ff::mfma0_a(tid, 1);
+    }
     int cur_pf = -1, cur_it = -1;  // job cursors of the prefetch and the item walks
     auto prefetch = [&](int item) {
         if (item < total) {
@@ -662,13 +691,22 @@ __global__ __launch_bounds__((Conv<R, P, VAR>::THREADS)) void k_conv(
             const JobConv jb = src.get(item, loc, cur_pf);
             const int qp = conv_item_to_pencil(loc, jb.P1, jb.N1) + jb.p2_lo * jb.P1;
             const C* pen = (const C*)jb.data + (size_t)qp * N0;
+            if constexpr (K::MFMA0) {
+                const R* pr = (const R*)pen;
 #pragma unroll
-            for (int b = 0; b < K::NBT0; ++b)
+                for (int g = 0; g < 4; ++g)
 #pragma unroll
-                for (int q = 0; q < K::HALF; ++q) {
-                    const int i = Ff::first_index(tid, b, q);
-                    pf[b * K::HALF + q] = i >= 0 ? pen[i] : mk(R(0), R(0));
-                }
+                    for (int ks = 0; ks < 2; ++ks)
+                        pb[2 * g + ks] = pr[2 * Ff::mfma0_b_index(tid, g, ks) + Ff::mfma0_part(tid)];
+            } else {
+#pragma unroll
+                for (int b = 0; b < K::NBT0; ++b)
+#pragma unroll
+                    for (int q = 0; q < K::HALF; ++q) {
+                        const int i = Ff::first_index(tid, b, q);
+                        pf[b * K::HALF + q] = i >= 0 ? pen[i] : mk(R(0), R(0));
+                    }
+            }
         }
     };
     prefetch(first);
@@ -679,11 +717,22 @@ __global__ __launch_bounds__((Conv<R, P, VAR>::THREADS)) void k_conv(
         int loc;
         const JobConv jb = src.get(active ? item : 0, loc, cur_it);
         C v[Ff::V];
+        typedef float v4f __attribute__((ext_vector_type(4)));
+        v4f d[K::MFMA0 ? 4 : 1];
+        if constexpr (K::MFMA0) {
 #pragma unroll
-        for (int b = 0; b < K::NBT0; ++b)
+            for (int g = 0; g < 4; ++g) {
+                d[g] = v4f{0.f, 0.f, 0.f, 0.f};
+                d[g] = __builtin_amdgcn_mfma_f32_16x16x4f32(am[0], pb[2 * g], d[g], 0, 0, 0);
+                d[g] = __builtin_amdgcn_mfma_f32_16x16x4f32(am[1], pb[2 * g + 1], d[g], 0, 0, 0);
+            }
+        } else {
 #pragma unroll
-            for (int q = 0; q < K::R0; ++q)
-                v[b * K::R0 + q] = q < K::HALF ? pf[b * K::HALF + q] : mk(R(0), R(0));
+            for (int b = 0; b < K::NBT0; ++b)
+#pragma unroll
+                for (int q = 0; q < K::R0; ++q)
+                    v[b * K::R0 + q] = q < K::HALF ? pf[b * K::HALF + q] : mk(R(0), R(0));
+        }
         if (it + 1 < chunk) prefetch(item + 1);
         const int qp = conv_item_to_pencil(loc, jb.P1, jb.N1) + jb.p2_lo * jb.P1;
         const int p2 = qp / jb.P1, p1 = qp - p2 * jb.P1;
@@ -694,8 +743,27 @@ __global__ __launch_bounds__((Conv<R, P, VAR>::THREADS)) void k_conv(
             int i = 0;
             Ff::for_each_last(v, tid, [&](int p0, C&) { tv[i++] = trow[p0 <= N0 ? p0 : P - p0]; });
         }
-        if constexpr (REG) Ff::template run_r<true>(v, scr, tid, wf);
-        else Ff::template run_g<true>(v, scr, tid, tw);
+        if constexpr (K::MFMA0) {
+#pragma unroll
+            for (int g = 0; g < 4; ++g) {
+                scr[Ff::mfma0_slot(tid, g, 0)] = mk(d[g][0], d[g][1]);
+                scr[Ff::mfma0_slot(tid, g, 1)] = mk(d[g][2], d[g][3]);
+            }
+            Ff::sync_lds();
+            Ff::template load<1>(v, scr, tid);
+            Ff::sync_lds();
+            if constexpr (REG) {
+                Ff::template compute_r<1>(v, tid, wf);
+                Ff::template run_r_from<2>(v, scr, tid, wf);
+            } else {
+                Ff::template compute<1>(v, tid, tw);
+                Ff::template run_g_from<2>(v, scr, tid, tw);
+            }
+        } else if constexpr (REG) {
+            Ff::template run_r<true>(v, scr, tid, wf);
+        } else {
+            Ff::template run_g<true>(v, scr, tid, tw);
+        }
         {
             int i = 0;
             Ff::for_each_last(v, tid, [&](int, C& c) { c = scale(c, tv[i++]); });

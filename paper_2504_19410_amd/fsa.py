@@ -35,6 +35,8 @@ KIND_DIM = {"coulomb3d": 3, "yukawa3d": 3, "biharmonic3d": 3,
 # "dd": double-double, each real an interleaved (hi, lo) pair of float64, so
 # rho / phi tensors have shape N + (2,)
 PRECISIONS = {"f32": 0, "f64": 1, "dd": 2}
+# compiled launch variants of the pass kernels (fsa_tune_variants bit mask)
+NUM_VARIANTS = 5
 DTYPES = {"f32": torch.float32, "f64": torch.float64, "dd": torch.float64}
 
 # FSA_NOALLOC_SCRATCH_BYTES: the workspace capacity of fsa_apply_noalloc
@@ -424,7 +426,7 @@ def tune_variants(precision: str, pass_name: str, length: int):
     m = ctypes.c_int()
     _check(_lib.fsa_tune_variants(PRECISIONS[precision], _tune_pass(pass_name), int(length),
                                   ctypes.byref(m)))
-    return [v for v in range(3) if m.value >> v & 1]
+    return [v for v in range(NUM_VARIANTS) if m.value >> v & 1]
 
 
 def tune_set_slabs(precision: str, N, slabs: int):

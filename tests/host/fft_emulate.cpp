@@ -4,7 +4,9 @@
 // implied by finishing a phase for all threads before the next), for every
 // supported length, forward and inverse, and compares with a long-double DFT
 // written from its definition.  Also checks the forward -> inverse register
-// hand-off that the fused convolution pass relies on.  Exit status 0 = pass.
+// hand-off that the fused convolution pass relies on, and the plans whose
+// exchanges trade register and lane bits across lanes (XCH = 1), with the
+// lane swaps emulated on the whole team.  Exit status 0 = pass.
 #include <cmath>
 #include <cstdio>
 #include <vector>
@@ -35,11 +37,21 @@ struct Roots {
     }
 };
 
+// the exchange before stage s: across lanes where the plan does it there
+template <typename F, int s>
+static void emu_exchange(typename F::C (*v)[F::V], typename F::C* scr) {
+    if constexpr (F::reg_exchange(s)) {
+        F::reg_exchange_team(v);
+    } else {
+        for (int t = 0; t < F::T; ++t) F::template store<s - 1>(v[t], scr, t);
+        for (int t = 0; t < F::T; ++t) F::template load<s>(v[t], scr, t);
+    }
+}
+
 template <typename F, int s>
 static void emu_from(typename F::C (*v)[F::V], typename F::C* scr, const typename F::C* tw) {
     if constexpr (s < F::S) {
-        for (int t = 0; t < F::T; ++t) F::template store<s - 1>(v[t], scr, t);
-        for (int t = 0; t < F::T; ++t) F::template load<s>(v[t], scr, t);
+        emu_exchange<F, s>(v, scr);
         for (int t = 0; t < F::T; ++t) F::template compute<s>(v[t], t, tw);
         emu_from<F, s + 1>(v, scr, tw);
     }
@@ -50,8 +62,7 @@ template <typename F, int s>
 static void emu_r_from(typename F::C (*v)[F::V], typename F::C* scr,
                        const std::vector<std::vector<typename F::C>>& w) {
     if constexpr (s < F::S) {
-        for (int t = 0; t < F::T; ++t) F::template store<s - 1>(v[t], scr, t);
-        for (int t = 0; t < F::T; ++t) F::template load<s>(v[t], scr, t);
+        emu_exchange<F, s>(v, scr);
         for (int t = 0; t < F::T; ++t)
             F::template compute_r<s>(v[t], t,
                                      *reinterpret_cast<const typename F::C(*)[F::NTW]>(w[t].data()));
@@ -77,10 +88,10 @@ static void emu_run(typename F::C (*v)[F::V], const typename F::C* tw) {
     emu_r_from<F, 1>(v, scr.data(), w);
 }
 
-template <typename R, int P, int ALT>
+template <typename R, int P, int ALT, int XCH = 0>
 static int check() {
-    using Ff = Fft<R, P, false, ALT>;
-    using Fi = Fft<R, P, true, ALT>;
+    using Ff = Fft<R, P, false, ALT, XCH>;
+    using Fi = Fft<R, P, true, ALT, XCH>;
     static_assert(Ff::T == Fi::T && Ff::V == Fi::V, "same team shape");
     static_assert(Ff::last_radix() == Fi::first_radix(), "register hand-off");
     using C = cpx<R>;
@@ -210,10 +221,96 @@ static int check_all() {
     return (check_both<R, Ps>() + ...);
 }
 
+// the plans with exchanges across lanes: exactly the one-wave 8 * 8 * 8 plan
+template <typename R>
+static int check_lane_exchange() {
+    int f = 0;
+    static_assert(Fft<R, 512, false, 0, 1>::has_reg_exchange() &&
+                      Fft<R, 512, true, 0, 1>::has_reg_exchange(),
+                  "length 512 exchanges across lanes");
+    static_assert(!Fft<R, 256, false, 0, 1>::has_reg_exchange() &&
+                      !Fft<R, 1024, false, 0, 1>::has_reg_exchange() &&
+                      !Fft<R, 384, false, 0, 1>::has_reg_exchange(),
+                  "no other length does");
+    f += check<R, 512, 0, 1>();
+    return f;
+}
+
+// The first forward stage as the matrix product of the fused pass's variant
+// 4 (Fft::mfma0_*): every lane's A and B operands from the helpers, the
+// 16x16x4 products with the MFMA's lane layouts (A[l % 16][l / 16] and
+// B[l / 16][l % 16] from lane l, D[4 (l / 16) + r][l % 16] in its register
+// r), the outputs stored to the scratch slots the helpers name; compared
+// with the radix-8 stage 0 (zero upper half) and its store.
+static int check_mfma_first_stage() {
+    using F = Fft<float, 512, false, 0>;
+    static_assert(F::mfma_first_ok(), "512-point one-wave plan");
+    static_assert(!Fft<float, 256, false, 0>::mfma_first_ok() &&
+                      !Fft<float, 1024, false, 0>::mfma_first_ok() &&
+                      !Fft<float, 512, true, 0>::mfma_first_ok(),
+                  "only the forward 512-point plan");
+    using C = cpx<float>;
+    std::vector<C> x(512, mk<float>(0, 0));
+    for (int i = 0; i < 256; ++i)
+        x[i] = mk<float>((float)std::sin(0.37 * i + 0.1), (float)std::cos(1.1 * i * i + 0.3));
+    // reference: stage 0 on the VALU path, then its store
+    static C v[F::T][F::V];
+    std::vector<C> ref(F::SCR, mk<float>(0, 0)), got(F::SCR, mk<float>(0, 0));
+    const auto tw = twiddles<float>(512);
+    for (int t = 0; t < F::T; ++t) {
+        F::load_first(v[t], t, 256, [&](int i) { return x[i]; });
+        F::compute<0, true>(v[t], t, tw.data());
+        F::store<0>(v[t], ref.data(), t);
+    }
+    std::vector<int> hits(F::SCR, 0);
+    int bad = 0;
+    for (int g = 0; g < 4; ++g) {
+        float A[16][8] = {}, B[8][16] = {};
+        for (int l = 0; l < 64; ++l)
+            for (int ks = 0; ks < 2; ++ks) {
+                A[l % 16][4 * ks + l / 16] = F::mfma0_a(l, ks);
+                const int i = F::mfma0_b_index(l, g, ks);
+                if (i < 0 || i >= 256) ++bad;
+                const C c = x[i < 0 || i >= 256 ? 0 : i];
+                B[4 * ks + l / 16][l % 16] = F::mfma0_part(l) ? c.y : c.x;
+            }
+        for (int l = 0; l < 64; ++l) {
+            float d[4];
+            for (int r = 0; r < 4; ++r) {
+                double acc = 0;
+                for (int u = 0; u < 8; ++u) acc += (double)A[4 * (l / 16) + r][u] * B[u][l % 16];
+                d[r] = (float)acc;
+            }
+            for (int h = 0; h < 2; ++h) {
+                const int slot = F::mfma0_slot(l, g, h);
+                if (slot < 0 || slot >= F::SCR) { ++bad; continue; }
+                got[slot] = mk<float>(d[2 * h], d[2 * h + 1]);
+                ++hits[slot];
+            }
+        }
+    }
+    double err = 0, mag = 0;
+    int slots = 0;
+    for (int i = 0; i < F::SCR; ++i) {
+        if (hits[i] > 1) ++bad;
+        if (!hits[i]) continue;
+        ++slots;
+        err = std::fmax(err, std::hypot(got[i].x - ref[i].x, got[i].y - ref[i].y));
+        mag = std::fmax(mag, std::hypot(ref[i].x, ref[i].y));
+    }
+    if (bad || slots != 512 || !(err <= 4e-6 * mag)) {
+        std::printf("FAIL mfma first stage: bad %d slots %d err %g mag %g\n", bad, slots, err, mag);
+        return 1;
+    }
+    return 0;
+}
+
 int main() {
     int f = 0;
+    f += check_mfma_first_stage();
     for (int mode = 0; mode < 2; ++mode) {
     g_register_twiddles = mode == 1;
+    f += check_lane_exchange<float>() + check_lane_exchange<double>();
     f += check_all<double, 8, 12, 16, 24, 32, 48, 64, 96, 128, 192, 256, 384, 512, 768, 1024, 1536,
                    2048, 3072, 4096>();
     f += check_all<float, 8, 12, 16, 24, 32, 48, 64, 96, 128, 192, 256, 384, 512, 768, 1024, 1536,

@@ -59,7 +59,7 @@ def test_every_variant_matches_the_oracle(F, kind, L, N, prec):
     rho = torch.from_numpy(density(L, N, sum(N))).to(F.DTYPES[prec]).cuda()
     ref = O.solve(kind, L, N, rho.double().cpu().numpy(), eps=plan.eps, lam=lam or 0.0)
     tried = set()
-    for var in (0, 1, 2):
+    for var in range(F.NUM_VARIANTS):
         for occ in (0, 1):
             F.tune_reset()
             used = []
@@ -100,7 +100,7 @@ def test_every_length_and_variant_matches_the_oracle(F, n, axis, prec):
     rho = torch.from_numpy(density(L, N, 3 * n + len(N))).to(F.DTYPES[prec]).cuda()
     ref = O.solve(kind, L, N, rho.double().cpu().numpy(), eps=plan.eps)
     seen = set()
-    for var in (0, 1, 2):
+    for var in range(F.NUM_VARIANTS):
         for occ in (0, 1):
             F.tune_reset()
             used = []

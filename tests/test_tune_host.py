@@ -189,3 +189,16 @@ def test_load_survives_mangled_files(tmp_path):
             assert "EINVAL" in str(e)
             assert F.tune_get("f32", "conv", 512)[:2] == (1, 0)
     F.tune_reset()
+
+
+def test_lane_exchange_and_matrix_core_variants_only_at_512():
+    """Variant 3 (exchanges across lanes) exists only for the fused pass at
+    length 512, the one-wave 8 * 8 * 8 plan, in both precisions; variant 4
+    (first stage on the matrix cores) only there in FP32."""
+    for prec in ("f32", "f64"):
+        for p in (256, 384, 512, 768, 1024, 2048):
+            assert (3 in F.tune_variants(prec, "conv", p)) == (p == 512), (prec, p)
+            assert (4 in F.tune_variants(prec, "conv", p)) == (p == 512 and prec == "f32"), (prec, p)
+        for name in ("r2c", "c2r", "fwd_t", "inv_t"):
+            for n in (256, 512, 1024):
+                assert not {3, 4} & set(F.tune_variants(prec, name, n)), (prec, name, n)
