@@ -50,7 +50,8 @@ typedef enum {
     FSA_EDEVICE = 4,       /* a HIP runtime call or kernel failed            */
     FSA_ESTATE = 5,        /* call out of order (e.g. apply before build)    */
     FSA_EBUDGET = 6,       /* server: request can never fit the HBM budget   */
-    FSA_ECANCELLED = 7     /* server: request was cancelled                  */
+    FSA_ECANCELLED = 7,    /* server: request was cancelled                  */
+    FSA_ETIMEDOUT = 8      /* server: request waited past the queue timeout  */
 } fsa_status;
 
 /* Kernels U(r) with their FSA split (Table 1; eqs. KerAppr, lnrAppr):
@@ -364,6 +365,7 @@ typedef struct {
     double gpts_per_s;          /* output grid points per second of uptime   */
     uint64_t done, rejected, cancelled, cache_hits, cache_misses;
     size_t hbm_in_use, hbm_peak;
+    uint64_t timed_out;         /* finished FSA_ETIMEDOUT in the queue       */
 } fsa_stats;
 
 /* Creates a server on the current device.
@@ -408,6 +410,16 @@ fsa_status fsa_server_wait_for(fsa_server s, uint64_t ticket, double timeout_ms,
                                fsa_status* result);
 /* Cancels a request that has not been launched yet (FSA_ESTATE otherwise). */
 fsa_status fsa_server_cancel(fsa_server s, uint64_t ticket);
+/* Requests still queued (not launched) timeout_ms after their arrival finish
+ * with FSA_ETIMEDOUT, so that a burst beyond the device's rate sheds load
+ * instead of growing the queue without bound; 0 (the default) or less: no
+ * limit.  A launched request always runs to completion (a kernel is not
+ * preempted).  Checked whenever the queue is pumped (submissions and
+ * completions) or a request is polled or waited for.  A device error
+ * reported by a request's completion event fails that request with
+ * FSA_EDEVICE; a fault that ends the device context fails every later one
+ * the same way. */
+fsa_status fsa_server_set_queue_timeout(fsa_server s, double timeout_ms);
 fsa_status fsa_server_stats(fsa_server s, fsa_stats* out);
 /* Starts a new statistics window: clears latency samples, counters and the
  * HBM peak; cached tensors and queued or in-flight requests are kept. */

@@ -33,7 +33,7 @@ namespace fsa {
 namespace sched {
 
 enum Status { ST_OK = 0, ST_EINVAL = 1, ST_EUNSUPPORTED = 2, ST_ENOMEM = 3, ST_EDEVICE = 4, ST_ESTATE = 5,
-              ST_EBUDGET = 6, ST_ECANCELLED = 7 };
+              ST_EBUDGET = 6, ST_ECANCELLED = 7, ST_ETIMEDOUT = 8 };
 
 // Identity of a kernel tensor: everything that determines it.
 struct Key {
@@ -106,6 +106,7 @@ struct Stats {
     double p50_ms = 0, p99_ms = 0, throughput_rps = 0, gpts_per_s = 0;
     uint64_t done = 0, rejected = 0, cancelled = 0, cache_hits = 0, cache_misses = 0;
     size_t hbm_in_use = 0, hbm_peak = 0;
+    uint64_t timed_out = 0;  // queued past the queue timeout (ST_ETIMEDOUT)
 };
 
 class Scheduler {
@@ -195,11 +196,22 @@ public:
 
     Status poll(uint64_t ticket, bool* done, Status* result) {
         std::lock_guard<std::mutex> lk(mu_);
+        expire_locked();
         auto it = reqs_.find(ticket);
         if (it == reqs_.end()) return ST_EINVAL;
         *done = it->second.done;
         if (it->second.done && result) *result = it->second.result;
         return ST_OK;
+    }
+
+    // Requests still queued this long after their arrival finish with
+    // ST_ETIMEDOUT instead of launching (seconds; <= 0: no limit).  A
+    // launched request runs to completion.  Checked whenever the queue is
+    // pumped or a request is polled.
+    void set_queue_timeout(double seconds) {
+        std::lock_guard<std::mutex> lk(mu_);
+        queue_timeout_ = seconds;
+        expire_locked();
     }
 
     // Cancels a request that is still queued (ST_ESTATE once it has launched).
@@ -234,7 +246,7 @@ public:
     void reset_stats() {
         std::lock_guard<std::mutex> lk(mu_);
         lat_ms_.clear();
-        done_ok_ = rejected_ = cancelled_ = hits_ = misses_ = 0;
+        done_ok_ = rejected_ = cancelled_ = hits_ = misses_ = timed_out_ = 0;
         points_ = 0;
         t0_ = be_->now();
         last_done_ = t0_;
@@ -262,6 +274,7 @@ public:
         s.throughput_rps = done_ok_ ? (double)done_ok_ / up : 0.0;
         s.gpts_per_s = done_ok_ ? (double)points_ / up / 1e9 : 0.0;
         s.rejected = rejected_;
+        s.timed_out = timed_out_;
         s.cancelled = cancelled_;
         s.cache_hits = hits_;
         s.cache_misses = misses_;
@@ -325,6 +338,7 @@ private:
     // keep the device busy without starving a large one.
     static constexpr int kBypassWindow = 16, kMaxBypass = 64;
     bool admit_locked(Admission* a) {
+        expire_locked();
         while (!queue_.empty() && !free_slots_.empty()) {
             size_t pos = 0;
             {
@@ -449,6 +463,24 @@ private:
         return true;
     }
 
+    // Finishes the queued requests that have waited longer than the queue
+    // timeout since their arrival.
+    void expire_locked() {
+        if (queue_timeout_ <= 0 || queue_.empty()) return;
+        const double now = be_->now();
+        for (size_t i = 0; i < queue_.size();) {
+            Request& r = reqs_[queue_[i]];
+            if (now - r.t_arrival > queue_timeout_) {
+                queue_.erase(queue_.begin() + (long)i);
+                ++timed_out_;
+                finish_locked(r, ST_ETIMEDOUT);
+                drop_if_unused_unbuilt(r.key);
+            } else {
+                ++i;
+            }
+        }
+    }
+
     void release_locked(Request& r) {
         auto it = cache_.find(r.key);
         if (it != cache_.end()) {
@@ -489,7 +521,8 @@ private:
     int bypassed_ = 0;  // admissions ahead of the current head
     size_t in_use_ = 0, peak_ = 0;
     int inflight_ = 0;
-    uint64_t done_ok_ = 0, rejected_ = 0, cancelled_ = 0, hits_ = 0, misses_ = 0;
+    uint64_t done_ok_ = 0, rejected_ = 0, cancelled_ = 0, hits_ = 0, misses_ = 0, timed_out_ = 0;
+    double queue_timeout_ = 0;  // seconds; <= 0: none
     double points_ = 0, last_done_ = 0;
     std::vector<double> lat_ms_;
 };

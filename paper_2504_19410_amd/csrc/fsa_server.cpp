@@ -421,6 +421,17 @@ fsa_status fsa_server_stats(fsa_server s, fsa_stats* out) {
     out->cache_misses = st.cache_misses;
     out->hbm_in_use = st.hbm_in_use;
     out->hbm_peak = st.hbm_peak;
+    out->timed_out = st.timed_out;
+    return FSA_OK;
+}
+
+fsa_status fsa_server_set_queue_timeout(fsa_server s, double timeout_ms) {
+    if (!s || !(timeout_ms == timeout_ms)) {
+        fsa::set_last_error("fsa_server_set_queue_timeout: bad arguments");
+        return FSA_EINVAL;
+    }
+    s->sched->set_queue_timeout(timeout_ms > 0 ? timeout_ms * 1e-3 : 0.0);
+    s->runner->notify_done();  // waiters of requests that just timed out
     return FSA_OK;
 }
 

@@ -45,6 +45,7 @@ NOALLOC_SCRATCH_BYTES = 128 << 20
 STATUS = {
     0: "FSA_OK", 1: "FSA_EINVAL", 2: "FSA_EUNSUPPORTED", 3: "FSA_ENOMEM",
     4: "FSA_EDEVICE", 5: "FSA_ESTATE", 6: "FSA_EBUDGET", 7: "FSA_ECANCELLED",
+    8: "FSA_ETIMEDOUT",
 }
 
 EXPORTS = (
@@ -55,7 +56,8 @@ EXPORTS = (
     "fsa_plan_tensor",
     "fsa_server_create", "fsa_server_submit", "fsa_server_submit_at", "fsa_server_clock",
     "fsa_server_poll", "fsa_server_wait", "fsa_server_wait_for",
-    "fsa_server_cancel", "fsa_server_stats", "fsa_server_reset_stats", "fsa_server_destroy",
+    "fsa_server_cancel", "fsa_server_set_queue_timeout", "fsa_server_stats",
+    "fsa_server_reset_stats", "fsa_server_destroy",
     "fsa_plan_launches",
     "fsa_autotune", "fsa_tune_set", "fsa_tune_get", "fsa_tune_variants", "fsa_tune_save",
     "fsa_tune_load", "fsa_tune_reset", "fsa_tune_set_slabs", "fsa_tune_get_slabs",
@@ -85,7 +87,7 @@ class Stats(ctypes.Structure):
                 ("done", ctypes.c_uint64), ("rejected", ctypes.c_uint64),
                 ("cancelled", ctypes.c_uint64), ("cache_hits", ctypes.c_uint64),
                 ("cache_misses", ctypes.c_uint64), ("hbm_in_use", ctypes.c_size_t),
-                ("hbm_peak", ctypes.c_size_t)]
+                ("hbm_peak", ctypes.c_size_t), ("timed_out", ctypes.c_uint64)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -121,6 +123,7 @@ def _load():
         "fsa_server_wait": [P, ctypes.c_uint64, P],
         "fsa_server_wait_for": [P, ctypes.c_uint64, ctypes.c_double, P, P],
         "fsa_server_cancel": [P, ctypes.c_uint64],
+        "fsa_server_set_queue_timeout": [P, ctypes.c_double],
         "fsa_server_stats": [P, ctypes.POINTER(Stats)],
         "fsa_server_reset_stats": [P],
         "fsa_server_destroy": [P],
@@ -598,6 +601,11 @@ class Server:
 
     def cancel(self, ticket: int):
         _check(_lib.fsa_server_cancel(self._h, ctypes.c_uint64(ticket)))
+
+    def set_queue_timeout(self, timeout_ms: float):
+        """Queued requests older than timeout_ms (from arrival) finish with
+        FSA_ETIMEDOUT instead of launching; 0 turns the limit off."""
+        _check(_lib.fsa_server_set_queue_timeout(self._h, float(timeout_ms)))
 
     def stats(self) -> dict:
         s = Stats()

@@ -1,8 +1,9 @@
 // Host-only tests of the server's scheduling core (fsa_sched.hpp) with a
 // scripted backend and a virtual clock: admission order and HBM budget,
 // continuous admission as completions free resources, rejection of requests
-// that can never fit, cancellation, the tensor cache (hits, misses, LRU
-// eviction), failure isolation, slot limits and latency percentiles.
+// that can never fit, cancellation, queue timeouts, the tensor cache (hits,
+// misses, LRU eviction), failure isolation, slot limits and latency
+// percentiles.
 // Exit status 0 = all checks passed.
 #include <cmath>
 #include <cstdio>
@@ -224,7 +225,45 @@ static void test_cancel_all() {
     CHECK(s.idle());
 }
 
+// Requests that wait in the queue past the timeout (from their arrival)
+// finish ST_ETIMEDOUT without launching; a launched one is never timed out;
+// the limit can be turned off again.
+static void test_queue_timeout() {
+    Fake be;
+    Scheduler s(&be, 1 << 30, 1);  // one slot: everything after the first waits
+    s.set_queue_timeout(0.010);
+    uint64_t a, b, c, d;
+    CHECK(s.submit(key(1, 1, 1), nullptr, nullptr, &a, nullptr) == ST_OK);
+    CHECK(s.pump() == 1);
+    be.t = 0.002;
+    CHECK(s.submit(key(1, 1, 1), nullptr, nullptr, &b, nullptr) == ST_OK);  // arrives 0.002
+    CHECK(s.submit(key(1, 1, 1), nullptr, nullptr, &c, nullptr, 0.008) == ST_OK);
+    be.t = 0.013;  // b has waited 11 ms, c 5 ms; a (launched) is still running
+    bool done = false;
+    Status res = ST_OK;
+    CHECK(s.poll(b, &done, &res) == ST_OK && done && res == ST_ETIMEDOUT);
+    CHECK(s.poll(c, &done, &res) == ST_OK && !done);
+    CHECK(s.poll(a, &done, &res) == ST_OK && !done);
+    s.complete(a, ST_OK, 0.014);
+    be.t = 0.014;
+    CHECK(s.pump() == 1 && be.launched.back() == c);
+    CHECK(s.stats().timed_out == 1 && s.stats().done == 1);
+    // a queued request past the limit is dropped at the next pump as well
+    CHECK(s.submit(key(1, 1, 1), nullptr, nullptr, &d, nullptr) == ST_OK);
+    be.t = 0.030;
+    CHECK(s.pump() == 0);
+    CHECK(s.poll(d, &done, &res) == ST_OK && done && res == ST_ETIMEDOUT);
+    CHECK(s.stats().timed_out == 2);
+    s.complete(c, ST_OK, 0.031);
+    s.set_queue_timeout(0);  // off: a long wait is fine
+    CHECK(s.submit(key(1, 1, 1), nullptr, nullptr, &d, nullptr) == ST_OK);
+    be.t = 10.0;
+    CHECK(s.pump() == 1 && be.launched.back() == d);
+    CHECK(be.launched.size() == 3);
+}
+
 int main() {
+    test_queue_timeout();
     test_budget_fifo_continuous();
     test_head_of_line_order();
     test_reject_and_cancel();

@@ -5,8 +5,9 @@
 // scripted service time on the host clock, and wakes the waiter of that
 // queue when the oldest one has finished.  Client threads submit requests of
 // several sizes under a budget that forces admission waits and evictions,
-// poll, wait with and without timeouts, and cancel; then the server shuts
-// down with work in flight.  Checks: every request ends OK or cancelled,
+// poll, wait with and without timeouts, and cancel; a burst runs under a
+// queue timeout shorter than its backlog; then the server shuts down with
+// work in flight.  Checks: every request ends OK, cancelled or timed out,
 // each exactly once; no request runs before its tensor is built; the budget
 // is never exceeded; the statistics add up.  Exit status 0 = all passed.
 #include <atomic>
@@ -199,6 +200,28 @@ int main() {
                 CHECK(run.wait(t, 10.0, &done, &res) == ST_OK);
                 CHECK(done && (res == ST_OK || res == ST_ECANCELLED));
             }
+        // a queue timeout shorter than the backlog: submitters on several
+        // threads, every request ends OK or timed out, each exactly once
+        sched.set_queue_timeout(2e-4);
+        std::vector<std::vector<uint64_t>> late(4);
+        std::vector<std::thread> bursts;
+        for (int c = 0; c < 4; ++c)
+            bursts.emplace_back([&, c] {
+                for (int i = 0; i < 30; ++i) {
+                    uint64_t t = 0;
+                    std::string err;
+                    CHECK(run.submit(key_of(i + c), &dev, &dev, &t, &err) == ST_OK);
+                    late[c].push_back(t);
+                }
+                for (uint64_t t : late[c]) {
+                    bool done = false;
+                    Status res = ST_OK;
+                    CHECK(run.wait(t, 10.0, &done, &res) == ST_OK);
+                    CHECK(done && (res == ST_OK || res == ST_ETIMEDOUT));
+                }
+            });
+        for (auto& t : bursts) t.join();
+        sched.set_queue_timeout(0);
         for (int i = 0; i < 40; ++i) {
             uint64_t t = 0;
             std::string err;
@@ -211,13 +234,16 @@ int main() {
     for (auto& v : cancelled) n_cancel += v.size();
     CHECK(s.done == (uint64_t)dev.completed.load());
     CHECK(dev.launched.load() == dev.completed.load());
-    CHECK(s.done + s.cancelled >= 8 * 150);
+    CHECK(s.done + s.cancelled + s.timed_out >= 8 * 150 + 4 * 30);
     CHECK(s.cancelled >= n_cancel);
     CHECK(s.hbm_peak <= budget && peak_seen.load() <= budget);
     CHECK(s.cache_misses == (uint64_t)dev.built.load());
     CHECK(s.p50_ms > 0 && s.p99_ms >= s.p50_ms);
-    std::printf("%s (%d failures): %llu done, %llu cancelled, %d builds, peak %zu of %zu\n",
+    CHECK(s.timed_out > 0);  // the burst outran its queue timeout
+    std::printf("%s (%d failures): %llu done, %llu cancelled, %llu timed out, %d builds, "
+                "peak %zu of %zu\n",
                 g_fail.load() ? "FAILED" : "OK", g_fail.load(), (unsigned long long)s.done,
-                (unsigned long long)s.cancelled, dev.built.load(), s.hbm_peak, budget);
+                (unsigned long long)s.cancelled, (unsigned long long)s.timed_out, dev.built.load(),
+                s.hbm_peak, budget);
     return g_fail.load() ? 1 : 0;
 }

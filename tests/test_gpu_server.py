@@ -85,3 +85,33 @@ def test_budget_rejection_and_cancel(F):
     assert res.count("FSA_ECANCELLED") == cancelled >= 1
     assert srv.stats()["rejected"] == 1
     srv.close()
+
+
+def test_queue_timeout_sheds_waiting_requests(F):
+    """With one slot and a 20 us queue timeout, requests of ~50 us each queue
+    up behind each other: the later ones finish FSA_ETIMEDOUT without
+    launching (their outputs stay untouched), the launched ones equal the
+    solo evaluation; with the limit off again every request runs."""
+    spec = ("coulomb3d", (8.0, 8.0, 8.0), (128, 128, 128), "f32", None)
+    srv = F.Server(8 << 30, max_inflight=1, n_streams=1)
+    rho = density(spec, 5)
+    warm = torch.empty_like(rho)
+    assert srv.wait(srv.submit(spec[0], spec[1], spec[2], rho, warm)) == "FSA_OK"
+    ref = solo(F, spec, rho)
+    srv.set_queue_timeout(0.02)
+    outs = [torch.full_like(rho, float("nan")) for _ in range(12)]
+    ts = [srv.submit(spec[0], spec[1], spec[2], rho, o) for o in outs]
+    res = [srv.wait(t) for t in ts]
+    torch.cuda.synchronize()
+    assert set(res) <= {"FSA_OK", "FSA_ETIMEDOUT"}, res
+    assert res[0] == "FSA_OK" and "FSA_ETIMEDOUT" in res, res
+    for o, r in zip(outs, res):
+        if r == "FSA_OK":
+            assert torch.equal(o, ref)
+        else:
+            assert torch.isnan(o).all()
+    assert srv.stats()["timed_out"] == res.count("FSA_ETIMEDOUT")
+    srv.set_queue_timeout(0)
+    ts = [srv.submit(spec[0], spec[1], spec[2], rho, o) for o in outs]
+    assert [srv.wait(t) for t in ts] == ["FSA_OK"] * len(outs)
+    srv.close()
