@@ -214,26 +214,33 @@ def bench_precision(F, torch, hip, prob, rho64, prec, steps, warmup, tune=True):
         if plan.d == 3:
             tuned[("slabs", 0)] = F.tune_get_slabs(prec, plan.N)
     timing = timed_evals(lambda: plan.apply(rho, out, ws), torch, hip, steps, warmup)
-    # per-pass durations: the same K evaluations, each launch recording a start
-    # and an end event with its own execution (the 3D middle passes launch
-    # once per slab of the schedule)
+    # per-pass durations: for each pass, K more evaluations with a start and
+    # an end event recorded around that pass's launches only (the 3D middle
+    # passes launch once per slab of the schedule); the pass's time is the
+    # median over the evaluations of the sum over its launches.  Events
+    # around every launch of one evaluation would put two event packets
+    # between consecutive kernels and stretch each interval by a few us.
     launches = plan.launches()
-    evs = [[hip.event() for _ in range(2 * len(launches))] for _ in range(steps)]
-    for k in range(steps):
-        plan.apply_events(rho, out, evs[k], ws)
-    torch.cuda.synchronize()
     names = PASS_NAMES_3D if plan.d == 3 else PASS_NAMES_2D
     by_short = {n.split("_", 1)[1]: n for n in names}
     pass_ms = {n: 0.0 for n in names}
     pass_launches = {n: 0 for n in names}
     for i, ln in enumerate(launches):
         pass_launches[by_short[ln]] += 1
-    for k in range(steps):
-        for i, ln in enumerate(launches):
-            pass_ms[by_short[ln]] += hip.ms(evs[k][2 * i], evs[k][2 * i + 1]) / steps
-    for row in evs:
-        for e in row:
-            hip.destroy(e)
+    for name in names:
+        idx = [i for i, ln in enumerate(launches) if by_short[ln] == name]
+        per = []
+        for k in range(steps):
+            evs = [None] * (2 * len(launches))
+            for i in idx:
+                evs[2 * i], evs[2 * i + 1] = hip.event(), hip.event()
+            plan.apply_events(rho, out, evs, ws)
+            torch.cuda.synchronize()
+            per.append(sum(hip.ms(evs[2 * i], evs[2 * i + 1]) for i in idx))
+            for i in idx:
+                hip.destroy(evs[2 * i])
+                hip.destroy(evs[2 * i + 1])
+        pass_ms[name] = float(np.median(per))
     hip.destroy(e0)
     hip.destroy(e1)
     phi = out.double().cpu().numpy()
