@@ -498,7 +498,12 @@ fsa_status fsa_autotune_batched(int n, const fsa_plan* plans, const void* const*
         }
         // every candidate's tables in its own trial slot, then `reps` rounds
         // that run each candidate once (after a warm-up round), so slow drifts
-        // fall on all of them alike; median per candidate
+        // fall on all of them alike; median per candidate.  Each run is a
+        // whole evaluation of the batch with this group's launch replaced by
+        // the candidate and timed alone: the launches before it leave the
+        // caches as a replay of the batch does (a group timed on its own,
+        // over and over, found its input in the Infinity Cache and favoured
+        // the variants that gain from that).
         const int nc = (int)cands.size();
         std::vector<Group> trials((size_t)nc, g);
         for (int c = 0; c < nc && e == hipSuccess; ++c) {
@@ -508,12 +513,16 @@ fsa_status fsa_autotune_batched(int n, const fsa_plan* plans, const void* const*
         std::vector<std::vector<float>> ms((size_t)nc);
         for (int i = -1; i < reps && e == hipSuccess; ++i) {
             for (int c = 0; c < nc && e == hipSuccess; ++c) {
-                // the fused pass works in place: re-create its input first
-                if (g.pass == fsa::Pass::CONV) e = run_before((int)fsa::Pass::CONV);
-                if (e == hipSuccess) e = hipEventRecord(ev[0], st);
-                if (e == hipSuccess)
-                    e = launch_group(trials[(size_t)c], trial + (size_t)c * trial_bytes, st);
-                if (e == hipSuccess) e = hipEventRecord(ev[1], st);
+                for (size_t oi = 0; oi < order.size() && e == hipSuccess; ++oi) {
+                    if (oi != gi) {
+                        e = launch_group(*order[oi], dbuf + offs[oi], st);
+                        continue;
+                    }
+                    e = hipEventRecord(ev[0], st);
+                    if (e == hipSuccess)
+                        e = launch_group(trials[(size_t)c], trial + (size_t)c * trial_bytes, st);
+                    if (e == hipSuccess) e = hipEventRecord(ev[1], st);
+                }
                 if (e == hipSuccess) e = hipEventSynchronize(ev[1]);
                 float t = 0.0f;
                 if (e == hipSuccess) e = hipEventElapsedTime(&t, ev[0], ev[1]);

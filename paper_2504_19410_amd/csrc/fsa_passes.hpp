@@ -620,6 +620,13 @@ struct Conv {
     static constexpr int NBT0 = Ff::first_nbt();
     static constexpr int HALF = R0 / 2;  // first-stage operands with index < P/2
     static constexpr int NPF = NBT0 * HALF;
+    // The next pencil's operands are prefetched into registers, except for
+    // FP32 plans of 16 operands per thread up to length 2048: there the
+    // operands, twiddles and tensor values already take ~165 VGPRs, and the
+    // prefetch held the kernel at two waves per SIMD instead of three (the
+    // 2D batch's fused pass at 2048: 490 -> 428 us; at 4096 the kernel stays
+    // at two waves either way and keeps the prefetch)
+    static constexpr bool PREFETCH = !(sizeof(R) == 4 && Ff::V >= 16 && P <= 2048);
     static_assert(R0 % 2 == 0, "the zero half must be whole first-stage operands");
     static_assert(Ff::last_radix() == Fi::first_radix(), "register hand-off");
     // Variant 4: the first forward stage as a matrix product on the matrix
@@ -672,7 +679,7 @@ __global__ __launch_bounds__((Conv<R, P, VAR>::THREADS)) void k_conv(
     const int chunk = (total + slots - 1) / slots;
     const int first = (blockIdx.x * K::TPW + team) * chunk;
 
-    C pf[K::MFMA0 ? 1 : K::NPF];
+    C pf[(K::MFMA0 || !K::PREFETCH) ? 1 : K::NPF];
     // variant 4: this lane's B operands (butterfly group g, K step ks at
     // pb[2 g + ks]) and A operands (K step ks), see Conv::MFMA0.  Lane l
     // gives B row l / 16 (operand q = 2 ks + (l / 16) / 2, its real part for
@@ -709,7 +716,7 @@ __global__ __launch_bounds__((Conv<R, P, VAR>::THREADS)) void k_conv(
             }
         }
     };
-    prefetch(first);
+    if constexpr (K::PREFETCH) prefetch(first);
     for (int it = 0; it < chunk; ++it) {
         const int tid = fresh_lane<R, P>() ? opaque(tid0) : tid0;  // per item: fresh_lane
         const int item = first + it;
@@ -726,14 +733,26 @@ __global__ __launch_bounds__((Conv<R, P, VAR>::THREADS)) void k_conv(
                 d[g] = __builtin_amdgcn_mfma_f32_16x16x4f32(am[0], pb[2 * g], d[g], 0, 0, 0);
                 d[g] = __builtin_amdgcn_mfma_f32_16x16x4f32(am[1], pb[2 * g + 1], d[g], 0, 0, 0);
             }
-        } else {
+        } else if constexpr (K::PREFETCH) {
 #pragma unroll
             for (int b = 0; b < K::NBT0; ++b)
 #pragma unroll
                 for (int q = 0; q < K::R0; ++q)
                     v[b * K::R0 + q] = q < K::HALF ? pf[b * K::HALF + q] : mk(R(0), R(0));
+        } else {  // this pencil's non-zero half, loaded now
+            const int qp0 = conv_item_to_pencil(loc, jb.P1, jb.N1) + jb.p2_lo * jb.P1;
+            const C* pen = (const C*)jb.data + (size_t)qp0 * N0;
+#pragma unroll
+            for (int b = 0; b < K::NBT0; ++b)
+#pragma unroll
+                for (int q = 0; q < K::R0; ++q) {
+                    const int i = q < K::HALF ? Ff::first_index(tid, b, q) : -1;
+                    v[b * K::R0 + q] = (active && i >= 0) ? pen[i] : mk(R(0), R(0));
+                }
         }
-        if (it + 1 < chunk) prefetch(item + 1);
+        if constexpr (K::PREFETCH) {
+            if (it + 1 < chunk) prefetch(item + 1);
+        }
         const int qp = conv_item_to_pencil(loc, jb.P1, jb.N1) + jb.p2_lo * jb.P1;
         const int p2 = qp / jb.P1, p1 = qp - p2 * jb.P1;
         const int a1 = p1 <= jb.N1 ? p1 : jb.P1 - p1;
