@@ -294,7 +294,8 @@ typedef enum {
 
 /* Times every distinct (variant, occupancy) candidate of every pass of a
  * built plan on `stream` with hipEvents (median of `reps`, 1..1000, taken in
- * rounds that run each candidate once, after a warm-up round) and stores the
+ * rounds that run each candidate once, after a warm-up round; each candidate
+ * runs inside a whole evaluation, only its own launch timed) and stores the
  * fastest in the table; for a 3D plan then times the slab schedules
  * (fsa_tune_set_slabs) the same way and keeps the fastest.
  * Synchronous.

@@ -1,12 +1,13 @@
 // fsa_tune.cpp -- the autotuner and its table of launch choices.
 //
-// Every pass kernel is compiled in up to three variants per transform length
+// Every pass kernel is compiled in up to five variants per transform length
 // (default; alternate radix family, i.e. another radix split and number of
 // threads per transform; half-size workgroups, i.e. fewer lines per tile or
-// teams per group).  At run time the persistent grid can also use fewer
-// resident workgroups per CU than fit.  fsa_autotune times every distinct
-// (variant, occupancy) candidate of every pass of a plan on the device with
-// hipEvents and keeps the fastest per (precision, pass, length) in a
+// teams per group; exchanges across lanes; first stage on the matrix cores).
+// At run time the persistent grid can also use fewer resident workgroups per
+// CU than fit.  fsa_autotune times every distinct (variant, occupancy)
+// candidate of every pass of a plan on the device with hipEvents, each inside
+// a whole evaluation, and keeps the fastest per (precision, pass, length) in a
 // process-wide table; for a 3D grid it then times the schedule, i.e. how many
 // slabs of bins p2 the middle passes B, C, D are run in (B, C, D of one slab
 // back to back, so the slab's spectrum can stay in the memory-side cache
@@ -550,7 +551,9 @@ fsa_status fsa_autotune(fsa_plan pl, const void* rho, void* phi, void* workspace
     // median time (us) of every candidate over `reps` rounds after a warm-up
     // round; a round runs each candidate once, so slow drifts of the clock
     // or of the memory system fall on all of them alike
-    auto time_rounds = [&](int n, auto&& prep, auto&& body, std::vector<double>& us) {
+    // (prep and post run untimed before and after each timed body)
+    auto time_rounds = [&](int n, auto&& prep, auto&& body, auto&& post,
+                           std::vector<double>& us) {
         std::vector<std::vector<float>> ms((size_t)n);
         hipError_t r = hipSuccess;
         for (int i = -1; i < reps && r == hipSuccess; ++i) {
@@ -559,6 +562,7 @@ fsa_status fsa_autotune(fsa_plan pl, const void* rho, void* phi, void* workspace
                 if (r == hipSuccess) r = hipEventRecord(ev[0], st);
                 if (r == hipSuccess) r = body(c);
                 if (r == hipSuccess) r = hipEventRecord(ev[1], st);
+                if (r == hipSuccess) r = post();
                 if (r == hipSuccess) r = hipEventSynchronize(ev[1]);
                 float t = 0.0f;
                 if (r == hipSuccess) r = hipEventElapsedTime(&t, ev[0], ev[1]);
@@ -587,20 +591,26 @@ fsa_status fsa_autotune(fsa_plan pl, const void* rho, void* phi, void* workspace
             cands.push_back(fsa::Choice{v, 0});
             if (mo >= 2) cands.push_back(fsa::Choice{v, mo / 2});
         }
-        // the fused pass works in place: its producer re-creates the input
-        // before each run
-        auto prep = [&] {
-            if (pass != fsa::Pass::CONV) return hipSuccess;
-            const fsa::Step prev = whole(k - 1);
-            return fsa::launch_step(pl, prev, rho, phi, workspace, fsa::step_choice(pl, prev), st);
+        // Each candidate is timed inside a whole evaluation: the passes
+        // before it run first (which also re-creates the input of the
+        // in-place fused pass) and the passes after it once it is timed, so
+        // the caches hold what they hold when evaluations follow each other.
+        // (A pass timed on its own, over and over, finds its input in the
+        // Infinity Cache and favours the variants that gain from that.)
+        auto run_range = [&](int from, int to) {
+            hipError_t r = hipSuccess;
+            for (int j = from; j < to && r == hipSuccess; ++j)
+                r = fsa::launch_step(pl, whole(j), rho, phi, workspace,
+                                     fsa::step_choice(pl, whole(j)), st);
+            return r;
         };
         std::vector<double> us;
-        e = time_rounds((int)cands.size(), prep,
-                        [&](int c) {
-                            return fsa::launch_step(pl, whole(k), rho, phi, workspace,
-                                                    cands[(size_t)c], st);
-                        },
-                        us);
+        e = time_rounds(
+            (int)cands.size(), [&] { return run_range(0, k); },
+            [&](int c) {
+                return fsa::launch_step(pl, whole(k), rho, phi, workspace, cands[(size_t)c], st);
+            },
+            [&] { return run_range(k + 1, np); }, us);
         if (e == hipSuccess) {
             size_t b = 0;
             for (size_t c = 1; c < cands.size(); ++c)
@@ -623,7 +633,7 @@ fsa_status fsa_autotune(fsa_plan pl, const void* rho, void* phi, void* workspace
                                 r = run_all(counts[(size_t)c]);
                             return r;
                         },
-                        us);
+                        nothing, us);
         if (e == hipSuccess) {
             size_t b = 0;
             for (size_t c = 1; c < counts.size(); ++c)
