@@ -372,10 +372,12 @@ constexpr int dct_lds_bytes(int wt, int scr, int D) {
 
 constexpr int dct_lines_per_group(int T, int scr, int D) {
     // up to 16 lines (128-byte rows on the strided axes); at most 1024
-    // threads; LDS within half a CU's 160 KB where possible so that two
-    // workgroups share a CU
+    // threads; LDS within a quarter of a CU's 160 KB where possible, so that
+    // four workgroups share a CU (with two, 74 KB each at length 512, the
+    // finishing axis took 164 us instead of 157 and the generation of an
+    // anisotropic T(1) 184 us instead of 160)
     int wt = 16;
-    while (wt > 2 && ((wt / 2) * T > 1024 || dct_lds_bytes(wt, scr, D) > 80 * 1024)) wt /= 2;
+    while (wt > 2 && ((wt / 2) * T > 1024 || dct_lds_bytes(wt, scr, D) > 40 * 1024)) wt /= 2;
     return wt;
 }
 
