@@ -162,7 +162,10 @@ fsa_status fsa_plan_query(fsa_plan plan, double* eps_used, double* h, size_t* te
  * k_j = pi p_j / (2 L_j); since T(2) = IDFT(W) (eq. Tensor2), DFT(T(2)) = W
  * exactly.  T^ is real and even in every p_j (Sec. 2.3), so only the octant
  * 0 <= p_j <= N_j is stored, in the plan precision.  The library allocates
- * and owns it.  May be called again (rebuilds in place). */
+ * and owns it, with the plan's twiddle tables and, for a 3D plan whose box
+ * has equal sides, an order of the (N_1 + 1)(N_2 + 1) lines of axis 0
+ * (4 bytes each, computed by the first build, reused by later ones).  May be
+ * called again (rebuilds in place). */
 fsa_status fsa_build_tensor(fsa_plan plan, void* stream);
 
 /* One evaluation (Execution in the paper's terms): phi = crop(IDFT(T^ .

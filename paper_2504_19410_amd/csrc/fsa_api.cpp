@@ -263,7 +263,8 @@ fsa_status fsa_build_tensor(fsa_plan pl, void* stream) {
     if (e == hipSuccess && pl->n_spectral)
         e = fsa::build_twiddles(pl->prec, (int)pl->N[1], tw + pl->tw_off_n1 * pl->csize, st);
     if (e != hipSuccess) return hip_fail(e, "fsa_build_tensor: twiddle kernels");
-    e = fsa::build_tensor_device(pl->kp, pl->d, pl->L, pl->N, pl->h, pl->prec, pl->tensor, st);
+    e = fsa::build_tensor_device(pl->kp, pl->d, pl->L, pl->N, pl->h, pl->prec, pl->tensor,
+                                 &pl->line_order, st);
     if (e == hipErrorOutOfMemory)
         return fail(FSA_ENOMEM, "fsa_build_tensor: temporary FP64 octant: %s",
                     hipGetErrorString(e));
@@ -563,13 +564,17 @@ fsa_status fsa_plan_destroy(fsa_plan pl) {
     if (!pl) return FSA_OK;
     fsa::batch_forget_plan(pl->id);
     hipError_t e = hipSuccess;
-    if (pl->tensor || pl->twiddles) {
+    if (pl->tensor || pl->twiddles || pl->line_order) {
         int cur = 0;
         (void)hipGetDevice(&cur);
         if (pl->device >= 0 && pl->device != cur) (void)hipSetDevice(pl->device);
         if (pl->tensor) e = hipFree(pl->tensor);
         if (pl->twiddles) {
             hipError_t e2 = hipFree(pl->twiddles);
+            if (e == hipSuccess) e = e2;
+        }
+        if (pl->line_order) {
+            hipError_t e2 = hipFree(pl->line_order);
             if (e == hipSuccess) e = e2;
         }
         if (pl->device >= 0 && pl->device != cur) (void)hipSetDevice(cur);

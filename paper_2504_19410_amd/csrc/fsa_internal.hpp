@@ -73,10 +73,13 @@ hipError_t build_tensor_dd(const fsa_plan_s* pl, hipStream_t st);
 hipError_t launch_dd_step(const fsa_plan_s* pl, int k, const void* rho, void* phi, void* ws,
                           hipStream_t st);
 
-// Tensor generation (fsa_tensor.hip).
+// Tensor generation (fsa_tensor.hip).  line_order: the caller's cache of the
+// order in which the last axis of a 3D build takes its lines (it depends on
+// the grid sizes only): filled with a new device allocation by the first build
+// that uses it, reused after that, freed by the caller.
 hipError_t build_tensor_device(const KernelParams& kp, int d, const double* L, const int64_t* N,
                                const double* h, fsa_precision prec, void* tensor_out,
-                               hipStream_t st);
+                               int** line_order, hipStream_t st);
 // tw[m] = exp(-2 pi i m / n), m in [0, n), computed in FP64, stored in prec.
 hipError_t build_twiddles(fsa_precision prec, int n, void* out, hipStream_t st);
 
@@ -271,5 +274,6 @@ struct fsa_plan_s {
     int device = -1;
     void* tensor = nullptr;
     void* twiddles = nullptr;
+    int* line_order = nullptr;  // the tensor build's line order (3D cubic boxes), kept
     bool built = false;
 };

@@ -401,6 +401,7 @@ struct Lines {
     int n_u, n_v;
     long u_stride, v_stride, es;
     int ax;
+    const int* rows;  // optional: the order in which tiles take the lines (k_row_order)
 };
 
 // Generation of T(1) (first axis) and the finishing of T^ (last axis).
@@ -434,14 +435,55 @@ __global__ void k_radial(double* __restrict__ tab, long n, double step, DctEnds 
     }
 }
 
+// Order of the lines of the contiguous axis 0 of a 3D octant by
+// c = a1^2 + a2^2 (ties by a1), for the last axis when it reads W from the
+// radial table.  Along a line W is read at m = a0^2 + c; lines with nearly
+// equal c read nearly the same entries at each a0, so a tile of 8 such lines,
+// walked with 8 values of a0 per 8 lines in one 64-lane gather, touches a few
+// cache lines of the table per instruction instead of one per lane (with 8
+// adjacent lines c spreads over 14 a1 and every lane reads its own line).
+// The rank of a line is the count of lines before it, summed over the
+// columns b1: the b2 with b2^2 < c - b1^2 are 0 .. ceil(sqrt(c - b1^2)) - 1,
+// plus the tie b2^2 = c - b1^2 when b1 < a1.  So no sort is needed:
+// rows[rank] = a1 + D1 a2, a permutation of 0 .. D1 D2 - 1.  Eight lanes
+// share a line (lane q sums the columns q, q + 8, ...), so the grid holds
+// enough waves to hide the loop's latency; c < 2^24 for every supported
+// grid (D <= 2049), so x converts to float exactly and the FP32 square
+// root is at most one off before the integer correction.
+constexpr int kRankLanes = 8;
+__global__ __launch_bounds__(256) void k_row_order(int* __restrict__ rows, int d1, int d2) {
+    const int gid = blockIdx.x * blockDim.x + threadIdx.x;
+    const int n = d1 * d2, r = gid / kRankLanes, q = gid % kRankLanes;
+    const bool live = r < n;
+    const int a1 = live ? r % d1 : 0, a2 = live ? r / d1 : 0, c = a1 * a1 + a2 * a2;
+    int rank = 0;
+    for (int b1 = q; b1 < d1; b1 += kRankLanes) {
+        const int x = c - b1 * b1;
+        if (x < 0) break;
+        int s = (int)sqrtf((float)x);  // floor(sqrt(x)) after the corrections
+        while (s * s > x) --s;
+        while ((s + 1) * (s + 1) <= x) ++s;
+        const bool square = s * s == x;
+        const int lt = square ? s : s + 1;  // b2 = 0 .. lt - 1 have b2^2 < x
+        rank += lt < d2 ? lt : d2;
+        rank += (square && b1 < a1 && s < d2) ? 1 : 0;
+    }
+#pragma unroll
+    for (int m = 1; m < kRankLanes; m *= 2) rank += __shfl_xor(rank, m, kRankLanes);
+    if (live && q == 0 && rank < n) rows[rank] = r;
+}
+
 __device__ __forceinline__ void octant_coords(const Lines& ln, int u, int v, int t, int (&a)[3]) {
     if (ln.ax == 0) { a[0] = t; a[1] = u; a[2] = v; }
     else if (ln.ax == 1) { a[0] = u; a[1] = t; a[2] = v; }
     else { a[0] = u; a[1] = v; a[2] = t; }
 }
 
-// TAB: the first / last axis looks T(1) / W up in the radial table.
-template <int P, DctStage STAGE, typename R, bool TAB>
+// TAB: the first / last axis looks T(1) / W up in the radial table.  ROWS:
+// tiles take the lines in the order of ln.rows (the contiguous axis only,
+// whose lines are whole rows), and the tile is walked with the line index
+// fastest.
+template <int P, DctStage STAGE, typename R, bool TAB, bool ROWS = false>
 __global__ __launch_bounds__(Dct<P>::THREADS) void k_dct(const double* __restrict__ in,
                                                         double* __restrict__ out, Lines ln,
                                                         const cpx<double>* __restrict__ tw,
@@ -453,6 +495,7 @@ __global__ __launch_bounds__(Dct<P>::THREADS) void k_dct(const double* __restric
     C* scr = lds;                                   // teams' FFT scratch ...
     double* tile = reinterpret_cast<double*>(lds);  // ... and the tile, in turn
     const int team = team_index<K::T>(), tid = threadIdx.x % K::T;
+    static_assert(!ROWS || K::THREADS % K::WT == 0, "a thread keeps one line of the tile");
     const int ntu = (ln.n_u + K::WT - 1) / K::WT;
     // Tiles of the strided axes in XCD order: the dispatcher deals
     // workgroups to the 8 XCDs in turn, each with its own L2, and a tile's
@@ -465,13 +508,32 @@ __global__ __launch_bounds__(Dct<P>::THREADS) void k_dct(const double* __restric
     // is rounded up to a multiple of 8; the extra groups have no tile.
     const int per = (int)gridDim.x / 8;
     const int ti = ln.es != 1 ? ((int)blockIdx.x % 8) * per + (int)blockIdx.x / 8 : (int)blockIdx.x;
-    if (ti >= ntu * ln.n_v) return;
-    const int tu = ti % ntu, v = ti / ntu;
-    const long base = (long)tu * K::WT * ln.u_stride + (long)v * ln.v_stride;
-    const int nw = ln.n_u - tu * K::WT < K::WT ? ln.n_u - tu * K::WT : K::WT;
+    int tu, v, nw;
+    long base;
+    if constexpr (ROWS) {
+        // line w = threadIdx.x % WT of the tile is rows[ti WT + w], at (u, v)
+        const int nrow = ln.n_u * ln.n_v;
+        if (ti * K::WT >= nrow) return;
+        nw = nrow - ti * K::WT < K::WT ? nrow - ti * K::WT : K::WT;
+        const int w = (int)threadIdx.x % K::WT;
+        int r = ln.rows[ti * K::WT + (w < nw ? w : 0)];
+        if ((unsigned)r >= (unsigned)nrow) r = 0;  // a permutation of the lines; never taken
+        tu = r % ln.n_u;
+        v = r / ln.n_u;
+        base = (long)tu * ln.u_stride + (long)v * ln.v_stride;
+    } else {
+        if (ti >= ntu * ln.n_v) return;
+        tu = ti % ntu;
+        v = ti / ntu;
+        base = (long)tu * K::WT * ln.u_stride + (long)v * ln.v_stride;
+        nw = ln.n_u - tu * K::WT < K::WT ? ln.n_u - tu * K::WT : K::WT;
+    }
+    // line w of the tile: u = tu WT + w at v, or (ROWS) this thread's (tu, v)
+    auto line_off = [&](int w) { return ROWS ? base : base + w * ln.u_stride; };
+    auto line_u = [&](int w) { return ROWS ? tu : tu * K::WT + w; };
     // element e of the tile -> (t, w), contiguous direction fastest
     auto at = [&](int e, int& t, int& w) {
-        if (ln.es == 1) {
+        if (!ROWS && ln.es == 1) {
             w = e / K::D;
             t = e - w * K::D;
         } else {
@@ -495,7 +557,7 @@ __global__ __launch_bounds__(Dct<P>::THREADS) void k_dct(const double* __restric
         if (w < nw) {
             if constexpr (STAGE == DctStage::FIRST) {
                 int a[3];
-                octant_coords(ln, tu * K::WT + w, v, t, a);
+                octant_coords(ln, line_u(w), v, t, a);
                 if constexpr (TAB) {
                     x = ends.t1_tab[a[0] * a[0] + a[1] * a[1] + a[2] * a[2]];
                 } else {
@@ -506,7 +568,7 @@ __global__ __launch_bounds__(Dct<P>::THREADS) void k_dct(const double* __restric
                                                       : d_ueps(ends.kp, r));
                 }
             } else {
-                x = in[base + w * ln.u_stride + t * ln.es];
+                x = in[line_off(w) + t * ln.es];
             }
         }
         tile[t * K::TS + w] = x;
@@ -528,7 +590,7 @@ __global__ __launch_bounds__(Dct<P>::THREADS) void k_dct(const double* __restric
                 if constexpr (WGATHER) {
                     int t, w, a[3];
                     at(e, t, w);
-                    octant_coords(ln, tu * K::WT + w, v, t, a);
+                    octant_coords(ln, line_u(w), v, t, a);
                     wv[k] = w < nw ? ends.w_tab[a[0] * a[0] + a[1] * a[1] + a[2] * a[2]] : 0.0;
                 }
             }
@@ -552,14 +614,14 @@ __global__ __launch_bounds__(Dct<P>::THREADS) void k_dct(const double* __restric
         int t, w;
         at(e, t, w);
         if (w >= nw) return;
-        const long o = base + w * ln.u_stride + t * ln.es;
+        const long o = line_off(w) + t * ln.es;
         if constexpr (STAGE == DctStage::LAST) {
             double wk;
             if constexpr (TAB) {
                 wk = wv[k];
             } else {
                 int a[3];
-                octant_coords(ln, tu * K::WT + w, v, t, a);
+                octant_coords(ln, line_u(w), v, t, a);
                 const double k0 = a[0] * ends.c[0], k1 = a[1] * ends.c[1], k2 = a[2] * ends.c[2];
                 const double kk = sqrt(k0 * k0 + k1 * k1 + k2 * k2);
                 wk = ends.wt.cf ? d_what_cheb(ends.wt.cf, ends.wt.dk, ends.wt.nq, kk)
@@ -585,16 +647,21 @@ __global__ __launch_bounds__(Dct<P>::THREADS) void k_dct(const double* __restric
     }
 }
 
-template <DctStage STAGE, typename R, bool TAB>
+// ROWS: take the lines in the order of ln.rows where the length's workgroup
+// allows it (a whole number of tiles' lines per thread block), else in
+// memory order.
+template <DctStage STAGE, typename R, bool TAB, bool ROWS = false>
 hipError_t dct_axis(const double* in, double* out, Lines ln, int N, const void* tw,
                     const DctEnds& ends, hipStream_t st) {
     switch (2 * N) {
 #define FSA_DCT_CASE(p)                                                                         \
     case p: {                                                                                   \
         using K = Dct<p>;                                                                       \
-        const int groups = ((ln.n_u + K::WT - 1) / K::WT * ln.n_v + 7) / 8 * 8;                 \
-        return launch_kernel(k_dct<p, STAGE, R, TAB>, dim3(groups), dim3(K::THREADS), 0, st,    \
-                             in, out, ln, (const cpx<double>*)tw, ends);                         \
+        constexpr bool RW = ROWS && K::THREADS % K::WT == 0;                                    \
+        const int tiles = RW ? (ln.n_u * ln.n_v + K::WT - 1) / K::WT                            \
+                             : (ln.n_u + K::WT - 1) / K::WT * ln.n_v;                            \
+        return launch_kernel(k_dct<p, STAGE, R, TAB, RW>, dim3((tiles + 7) / 8 * 8),            \
+                             dim3(K::THREADS), 0, st, in, out, ln, (const cpx<double>*)tw, ends); \
     }
         FSA_DCT_CASE(16) FSA_DCT_CASE(24) FSA_DCT_CASE(32) FSA_DCT_CASE(48) FSA_DCT_CASE(64)
         FSA_DCT_CASE(96) FSA_DCT_CASE(128) FSA_DCT_CASE(192) FSA_DCT_CASE(256) FSA_DCT_CASE(384)
@@ -706,7 +773,7 @@ hipError_t build_twiddles(fsa_precision prec, int n, void* out, hipStream_t st) 
 
 hipError_t build_tensor_device(const KernelParams& kp, int d, const double* L, const int64_t* N,
                                const double* h, fsa_precision prec, void* tensor_out,
-                               hipStream_t st) {
+                               int** line_order, hipStream_t st) {
     // octant extents D_j = N_j + 1, axis 0 innermost; a 2D plan has D2 = 1
     const long D0 = N[0] + 1, D1 = N[1] + 1, D2 = d == 3 ? N[2] + 1 : 1;
     const long n = D0 * D1 * D2;
@@ -760,11 +827,25 @@ hipError_t build_tensor_device(const KernelParams& kp, int d, const double* L, c
     }
     ends.t1_tab = t1_tab;
     ends.w_tab = w_tab;
-    // lines along axis ax; groups take lines adjacent in memory
+    // the order of the rows of axis 0, where the last axis (axis 0) of a 3D
+    // build reads W from the radial table: computed once, kept by the caller
+    if (e == hipSuccess && w_tab && d == 3 && !*line_order) {
+        int* order = nullptr;
+        e = hipMalloc((void**)&order, sizeof(int) * D1 * D2);
+        if (e == hipSuccess) {
+            e = launch_kernel(k_row_order, dim3((unsigned)((D1 * D2 * kRankLanes + 255) / 256)),
+                              dim3(256), 0, st, order, (int)D1, (int)D2);
+            if (e == hipSuccess) *line_order = order;
+            else (void)hipFree(order);
+        }
+    }
+    int* rows = w_tab && d == 3 ? *line_order : nullptr;
+    // lines along axis ax; groups take lines adjacent in memory (or, on
+    // axis 0, in the order of rows)
     auto lines = [&](int ax) {
-        if (ax == 0) return Lines{(int)D1, (int)D2, D0, D0 * D1, 1, 0};
-        if (ax == 1) return Lines{(int)D0, (int)D2, 1, D0 * D1, D0, 1};
-        return Lines{(int)D0, (int)D1, 1, D0, D0 * D1, 2};
+        if (ax == 0) return Lines{(int)D1, (int)D2, D0, D0 * D1, 1, 0, rows};
+        if (ax == 1) return Lines{(int)D0, (int)D2, 1, D0 * D1, D0, 1, nullptr};
+        return Lines{(int)D0, (int)D1, 1, D0, D0 * D1, 2, nullptr};
     };
     // axes from the last (strided) to axis 0 (contiguous): the axis that
     // only writes takes the long strides, the last one reads and writes
@@ -782,12 +863,13 @@ hipError_t build_tensor_device(const KernelParams& kp, int d, const double* L, c
         else if (step < d - 1)
             e = dct_axis<DctStage::MID, double, false>(a, b, ln, nn, tw, ends, st);
         else if (prec == FSA_F32)
-            e = w_tab ? dct_axis<DctStage::LAST, float, true>(last_in, nullptr, ln, nn, tw, ends, st)
-                      : dct_axis<DctStage::LAST, float, false>(last_in, nullptr, ln, nn, tw, ends, st);
+            e = rows    ? dct_axis<DctStage::LAST, float, true, true>(last_in, nullptr, ln, nn, tw, ends, st)
+                : w_tab ? dct_axis<DctStage::LAST, float, true>(last_in, nullptr, ln, nn, tw, ends, st)
+                        : dct_axis<DctStage::LAST, float, false>(last_in, nullptr, ln, nn, tw, ends, st);
         else
-            e = w_tab
-                    ? dct_axis<DctStage::LAST, double, true>(last_in, nullptr, ln, nn, tw, ends, st)
-                    : dct_axis<DctStage::LAST, double, false>(last_in, nullptr, ln, nn, tw, ends, st);
+            e = rows    ? dct_axis<DctStage::LAST, double, true, true>(last_in, nullptr, ln, nn, tw, ends, st)
+                : w_tab ? dct_axis<DctStage::LAST, double, true>(last_in, nullptr, ln, nn, tw, ends, st)
+                        : dct_axis<DctStage::LAST, double, false>(last_in, nullptr, ln, nn, tw, ends, st);
     }
     if (t1_tab) (void)hipFreeAsync(t1_tab, st);
     if (w_tab) (void)hipFreeAsync(w_tab, st);

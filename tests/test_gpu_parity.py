@@ -79,10 +79,14 @@ def test_parity_rough_density(F, kind, L, N, prec):
 
 @pytest.mark.parametrize("kind,L,N,lam", [("coulomb3d", (3.0, 5.0, 4.0), (24, 16, 32), None),
                                            ("yukawa3d", (4.0, 4.0, 4.0), (16, 16, 16), 2.0),
+                                           ("yukawa3d", (4.0, 4.0, 4.0), (16, 24, 32), 1.0),
                                            ("log2d", (8.0, 6.0), (48, 32), None),
                                            ("biharmonic2d", (3.0, 4.0), (16, 24), None)])
 def test_tensor_matches_oracle_dft(F, kind, L, N, lam):
-    """The GPU spectral octant equals DFT(T(1) + T(2)) / prod P of the oracle."""
+    """The GPU spectral octant equals DFT(T(1) + T(2)) / prod P of the oracle.
+    The 3D Yukawa boxes are cubes, so W comes from the radial table and the
+    last axis takes its rows ordered by a1^2 + a2^2 (a square and a
+    rectangular set of rows)."""
     plan = F.Plan(kind, L, N, "f64", lam=lam).build()
     got = plan.tensor().numpy()
     T = O.build_tensor(kind, L, N, plan.eps, lam=lam or 0.0)
@@ -92,6 +96,22 @@ def test_tensor_matches_oracle_dft(F, kind, L, N, lam):
     ref = np.transpose(octant, tuple(reversed(range(len(N)))))
     assert got.shape == ref.shape
     assert np.max(np.abs(got - ref)) <= 1e-13 * np.max(np.abs(ref))
+
+
+@pytest.mark.parametrize("N", [(16, 24, 32), (48, 48, 48)])
+def test_tensor_rebuild_is_bitwise_identical(F, N):
+    """A rebuild (which reuses the line order the first build of a cubic box
+    computed) writes the same tensor, bit for bit, as the first build and as
+    a fresh plan's first build."""
+    L = (4.0, 4.0, 4.0)
+    plan = F.Plan("yukawa3d", L, N, "f64", lam=1.0).build()
+    first = plan.tensor().clone()
+    plan.build()
+    again = plan.tensor().clone()
+    fresh = F.Plan("yukawa3d", L, N, "f64", lam=1.0).build().tensor().clone()
+    torch.cuda.synchronize()
+    assert torch.equal(first, again)
+    assert torch.equal(first, fresh)
 
 
 @pytest.mark.parametrize("prec", ["f32", "f64"])
