@@ -665,6 +665,38 @@ struct Fft {
         }
     }
 
+    // One component (PART 0: real, 1: imaginary) of store<s> / load<s>,
+    // through a real scratch of SCR values: an exchange done one component
+    // at a time needs half the LDS of one done with complex values.
+    template <int s, int PART>
+    FSA_HD static void store_part(const C (&v)[V], R* scr, int tid) {
+        constexpr int RAD = radix(s), NS = ns(s), NB = nb(s), NBT = nbt(s);
+#pragma unroll
+        for (int b = 0; b < NBT; ++b) {
+            const int j = tid + b * T;
+            if ((NB % T) != 0 && j >= NB) continue;
+            const int k = j % NS;
+            const int base = (j / NS) * NS * RAD + k;
+#pragma unroll
+            for (int q = 0; q < RAD; ++q)
+                scr[pad(base + q * NS)] = PART ? v[b * RAD + q].y : v[b * RAD + q].x;
+        }
+    }
+    template <int s, int PART>
+    FSA_HD static void load_part(C (&v)[V], const R* scr, int tid) {
+        constexpr int RAD = radix(s), NB = nb(s), NBT = nbt(s);
+#pragma unroll
+        for (int b = 0; b < NBT; ++b) {
+            const int j = tid + b * T;
+            if ((NB % T) != 0 && j >= NB) continue;
+#pragma unroll
+            for (int q = 0; q < RAD; ++q) {
+                if constexpr (PART) v[b * RAD + q].y = scr[pad(j + q * NB)];
+                else v[b * RAD + q].x = scr[pad(j + q * NB)];
+            }
+        }
+    }
+
     // first-stage operands from an arbitrary source: v = f(index) for
     // index < n_in, zero beyond (zero-padded inputs)
     template <class F>
@@ -821,6 +853,38 @@ struct Fft {
             compute<s>(v, tid, tw);
             run_g_from<s + 1>(v, scr, tid, tw);
         }
+    }
+
+    // The exchange before stage s through a real scratch, the real parts
+    // first and then the imaginary parts (load_part<s, 0> leaves the
+    // imaginary parts of the previous stage in place for store_part<s-1, 1>).
+    template <int s>
+    static __device__ __forceinline__ void exchange_split(C (&v)[V], R* scr, int tid) {
+        store_part<s - 1, 0>(v, scr, tid);
+        sync_lds();
+        load_part<s, 0>(v, scr, tid);
+        sync_lds();
+        store_part<s - 1, 1>(v, scr, tid);
+        sync_lds();
+        load_part<s, 1>(v, scr, tid);
+        sync_lds();
+    }
+
+    template <int s>
+    static __device__ __forceinline__ void run_g_split_from(C (&v)[V], R* scr, int tid,
+                                                            const C* __restrict__ tw) {
+        if constexpr (s < S) {
+            exchange_split<s>(v, scr, tid);
+            compute<s>(v, tid, tw);
+            run_g_split_from<s + 1>(v, scr, tid, tw);
+        }
+    }
+
+    // run_g with every exchange through a real scratch of SCR values
+    static __device__ __forceinline__ void run_g_split(C (&v)[V], R* scr, int tid,
+                                                       const C* __restrict__ tw) {
+        compute<0>(v, tid, tw);
+        run_g_split_from<1>(v, scr, tid, tw);
     }
 
     // twiddles from the (cached) global table, LDS-only synchronisation

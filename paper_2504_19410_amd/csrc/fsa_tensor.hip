@@ -365,19 +365,21 @@ enum class DctStage { FIRST, MID, LAST };
 
 // The tile of lines and the teams' FFT scratch share one LDS array (the
 // tile is dead while the transforms run), so its size is the larger of the
-// two.
+// two.  The teams exchange one component at a time (Fft::run_g_split), so a
+// team's scratch holds SCR doubles.
 constexpr int dct_lds_bytes(int wt, int scr, int D) {
-    return (wt / 2) * scr * 16 > D * (wt + 1) * 8 ? (wt / 2) * scr * 16 : D * (wt + 1) * 8;
+    return (wt / 2) * scr * 8 > D * (wt + 1) * 8 ? (wt / 2) * scr * 8 : D * (wt + 1) * 8;
 }
 
 constexpr int dct_lines_per_group(int T, int scr, int D) {
     // up to 16 lines (128-byte rows on the strided axes); at most 1024
-    // threads; LDS within a quarter of a CU's 160 KB where possible, so that
-    // four workgroups share a CU (with two, 74 KB each at length 512, the
-    // finishing axis took 164 us instead of 157 and the generation of an
-    // anisotropic T(1) 184 us instead of 160)
+    // threads; LDS within a fifth of a CU's 160 KB where possible, so that
+    // five workgroups can share a CU (at length 512: 8 lines, 18.5 KB; with
+    // 16 lines and two workgroups per CU the finishing axis took 164 us
+    // instead of 157 and the generation of an anisotropic T(1) 184 us
+    // instead of 160)
     int wt = 16;
-    while (wt > 2 && ((wt / 2) * T > 1024 || dct_lds_bytes(wt, scr, D) > 40 * 1024)) wt /= 2;
+    while (wt > 2 && ((wt / 2) * T > 1024 || dct_lds_bytes(wt, scr, D) > 32 * 1024)) wt /= 2;
     return wt;
 }
 
@@ -390,8 +392,8 @@ struct Dct {
     static constexpr int TEAMS = WT / 2;
     static constexpr int TS = WT + 1;
     static constexpr int THREADS = TEAMS * T;
-    static constexpr int LDS_C = (dct_lds_bytes(WT, F::SCR, D) + 15) / 16;  // complex slots
-    static_assert(LDS_C * 16 <= 160 * 1024, "DCT workgroup exceeds the LDS");
+    static constexpr int LDS_D = (dct_lds_bytes(WT, F::SCR, D) + 7) / 8;  // doubles
+    static_assert(LDS_D * 8 <= 160 * 1024, "DCT workgroup exceeds the LDS");
 };
 
 // Lines of one axis: line (u, v) starts at u * u_stride + v * v_stride and
@@ -491,9 +493,9 @@ __global__ __launch_bounds__(Dct<P>::THREADS) void k_dct(const double* __restric
     using K = Dct<P>;
     using F = typename K::F;
     using C = cpx<double>;
-    __shared__ C lds[K::LDS_C];
-    C* scr = lds;                                   // teams' FFT scratch ...
-    double* tile = reinterpret_cast<double*>(lds);  // ... and the tile, in turn
+    __shared__ double lds[K::LDS_D];
+    double* scr = lds;   // teams' FFT scratch ...
+    double* tile = lds;  // ... and the tile, in turn
     const int team = team_index<K::T>(), tid = threadIdx.x % K::T;
     static_assert(!ROWS || K::THREADS % K::WT == 0, "a thread keeps one line of the tile");
     const int ntu = (ln.n_u + K::WT - 1) / K::WT;
@@ -546,8 +548,10 @@ __global__ __launch_bounds__(Dct<P>::THREADS) void k_dct(const double* __restric
     // evaluation takes one element per iteration (the special functions need
     // many registers, and unrolled copies would cost the FFT its occupancy);
     // table lookups and plain copies are unrolled so that their loads are in
-    // flight together, and the last axis gathers its W values here, so that
-    // they arrive while the transforms run.
+    // flight together.  The last axis looks its W values up in the store
+    // loop, three elements at a time: gathered before the transforms, they
+    // stayed live across the FFT (113 instead of 77 VGPRs at length 512, four
+    // waves per SIMD instead of six).
     constexpr int EPT = (K::D * K::WT + K::THREADS - 1) / K::THREADS;
     constexpr bool DIRECT = !TAB && STAGE == DctStage::FIRST;
     auto load_one = [&](int e) {
@@ -573,8 +577,6 @@ __global__ __launch_bounds__(Dct<P>::THREADS) void k_dct(const double* __restric
         }
         tile[t * K::TS + w] = x;
     };
-    constexpr bool WGATHER = TAB && STAGE == DctStage::LAST;
-    double wv[WGATHER ? EPT : 1];
     if constexpr (DIRECT) {
 #pragma unroll 1
         for (int k = 0; k < EPT; ++k) {
@@ -585,15 +587,7 @@ __global__ __launch_bounds__(Dct<P>::THREADS) void k_dct(const double* __restric
 #pragma unroll
         for (int k = 0; k < EPT; ++k) {
             const int e = threadIdx.x + k * K::THREADS;
-            if (e < K::D * K::WT) {
-                load_one(e);
-                if constexpr (WGATHER) {
-                    int t, w, a[3];
-                    at(e, t, w);
-                    octant_coords(ln, line_u(w), v, t, a);
-                    wv[k] = w < nw ? ends.w_tab[a[0] * a[0] + a[1] * a[1] + a[2] * a[2]] : 0.0;
-                }
-            }
+            if (e < K::D * K::WT) load_one(e);
         }
     }
     __syncthreads();
@@ -603,7 +597,7 @@ __global__ __launch_bounds__(Dct<P>::THREADS) void k_dct(const double* __restric
         return mk(tile[t * K::TS + 2 * team], tile[t * K::TS + 2 * team + 1]);
     });
     __syncthreads();
-    F::run_g(z, scr + team * F::SCR, tid, tw);
+    F::run_g_split(z, scr + team * F::SCR, tid, tw);
     __syncthreads();
     F::store_last(z, tid, K::D, [&](int p, C c) {
         tile[p * K::TS + 2 * team] = c.x;
@@ -617,11 +611,11 @@ __global__ __launch_bounds__(Dct<P>::THREADS) void k_dct(const double* __restric
         const long o = line_off(w) + t * ln.es;
         if constexpr (STAGE == DctStage::LAST) {
             double wk;
+            int a[3];
+            octant_coords(ln, line_u(w), v, t, a);
             if constexpr (TAB) {
-                wk = wv[k];
+                wk = ends.w_tab[a[0] * a[0] + a[1] * a[1] + a[2] * a[2]];
             } else {
-                int a[3];
-                octant_coords(ln, line_u(w), v, t, a);
                 const double k0 = a[0] * ends.c[0], k1 = a[1] * ends.c[1], k2 = a[2] * ends.c[2];
                 const double kk = sqrt(k0 * k0 + k1 * k1 + k2 * k2);
                 wk = ends.wt.cf ? d_what_cheb(ends.wt.cf, ends.wt.dk, ends.wt.nq, kk)
@@ -634,6 +628,12 @@ __global__ __launch_bounds__(Dct<P>::THREADS) void k_dct(const double* __restric
     };
     if constexpr (!TAB && STAGE == DctStage::LAST) {
 #pragma unroll 1
+        for (int k = 0; k < EPT; ++k) {
+            const int e = threadIdx.x + k * K::THREADS;
+            if (e < K::D * K::WT) store_one(e, k);
+        }
+    } else if constexpr (STAGE == DctStage::LAST) {
+#pragma unroll 3
         for (int k = 0; k < EPT; ++k) {
             const int e = threadIdx.x + k * K::THREADS;
             if (e < K::D * K::WT) store_one(e, k);

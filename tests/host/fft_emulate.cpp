@@ -6,7 +6,10 @@
 // written from its definition.  Also checks the forward -> inverse register
 // hand-off that the fused convolution pass relies on, and the plans whose
 // exchanges trade register and lane bits across lanes (XCH = 1), with the
-// lane swaps emulated on the whole team.  Exit status 0 = pass.
+// lane swaps emulated on the whole team.  Every length runs three ways:
+// twiddles from the table, twiddles from registers, and the exchanges one
+// component at a time through a real scratch (exchange_split, used by the
+// tensor build).  Exit status 0 = pass.
 #include <cmath>
 #include <cstdio>
 #include <vector>
@@ -37,11 +40,22 @@ struct Roots {
     }
 };
 
-// the exchange before stage s: across lanes where the plan does it there
+static bool g_split_exchange = false;
+
+// the exchange before stage s: across lanes where the plan does it there;
+// with g_split_exchange one component at a time through a real scratch (the
+// tensor build's exchange_split), the real parts first
 template <typename F, int s>
 static void emu_exchange(typename F::C (*v)[F::V], typename F::C* scr) {
     if constexpr (F::reg_exchange(s)) {
         F::reg_exchange_team(v);
+    } else if (g_split_exchange) {
+        using R = decltype(scr->x);
+        R* rs = reinterpret_cast<R*>(scr);
+        for (int t = 0; t < F::T; ++t) F::template store_part<s - 1, 0>(v[t], rs, t);
+        for (int t = 0; t < F::T; ++t) F::template load_part<s, 0>(v[t], rs, t);
+        for (int t = 0; t < F::T; ++t) F::template store_part<s - 1, 1>(v[t], rs, t);
+        for (int t = 0; t < F::T; ++t) F::template load_part<s, 1>(v[t], rs, t);
     } else {
         for (int t = 0; t < F::T; ++t) F::template store<s - 1>(v[t], scr, t);
         for (int t = 0; t < F::T; ++t) F::template load<s>(v[t], scr, t);
@@ -308,8 +322,9 @@ static int check_mfma_first_stage() {
 int main() {
     int f = 0;
     f += check_mfma_first_stage();
-    for (int mode = 0; mode < 2; ++mode) {
+    for (int mode = 0; mode < 3; ++mode) {
     g_register_twiddles = mode == 1;
+    g_split_exchange = mode == 2;
     f += check_lane_exchange<float>() + check_lane_exchange<double>();
     f += check_all<double, 8, 12, 16, 24, 32, 48, 64, 96, 128, 192, 256, 384, 512, 768, 1024, 1536,
                    2048, 3072, 4096>();
