@@ -82,7 +82,10 @@ public:
         size_t tb = 0, wb = 0;
         fsa_plan_query(pl, nullptr, nullptr, &tb, &wb);
         out->handle = pl;
-        out->tensor_bytes = tb + pl->tw_elems * pl->csize;  // tensor + twiddle tables
+        // tensor + twiddle tables + (3D, an upper bound) the tensor build's
+        // line order, kept by plans whose box has equal sides
+        const size_t order = k.d == 3 ? sizeof(int) * (size_t)(k.N[1] + 1) * (size_t)(k.N[2] + 1) : 0;
+        out->tensor_bytes = tb + pl->tw_elems * pl->csize + order;
         out->workspace_bytes = wb + 256;                      // + alignment slack
         return fsa::sched::ST_OK;
     }
