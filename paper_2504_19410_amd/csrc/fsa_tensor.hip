@@ -301,7 +301,7 @@ __global__ __launch_bounds__(256) void k_wq_sum(const double* __restrict__ g,
     }
     red[threadIdx.x] = s;
     __syncthreads();
-    for (int w = 128; w > 0; w >>= 1) {
+    for (unsigned w = 128; w > 0; w >>= 1) {
         if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
         __syncthreads();
     }
@@ -604,7 +604,7 @@ __global__ __launch_bounds__(Dct<P>::THREADS) void k_dct(const double* __restric
         tile[p * K::TS + 2 * team + 1] = c.y;
     });
     __syncthreads();
-    auto store_one = [&](int e, int k) {
+    auto store_one = [&](int e) {
         int t, w;
         at(e, t, w);
         if (w >= nw) return;
@@ -630,19 +630,19 @@ __global__ __launch_bounds__(Dct<P>::THREADS) void k_dct(const double* __restric
 #pragma unroll 1
         for (int k = 0; k < EPT; ++k) {
             const int e = threadIdx.x + k * K::THREADS;
-            if (e < K::D * K::WT) store_one(e, k);
+            if (e < K::D * K::WT) store_one(e);
         }
     } else if constexpr (STAGE == DctStage::LAST) {
 #pragma unroll 3
         for (int k = 0; k < EPT; ++k) {
             const int e = threadIdx.x + k * K::THREADS;
-            if (e < K::D * K::WT) store_one(e, k);
+            if (e < K::D * K::WT) store_one(e);
         }
     } else {
 #pragma unroll
         for (int k = 0; k < EPT; ++k) {
             const int e = threadIdx.x + k * K::THREADS;
-            if (e < K::D * K::WT) store_one(e, k);
+            if (e < K::D * K::WT) store_one(e);
         }
     }
 }
