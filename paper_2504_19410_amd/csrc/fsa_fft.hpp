@@ -305,13 +305,14 @@ constexpr int ilog2_exact(int x) {
 // plan lets the forward and inverse transforms of the fused pass share one
 // set of twiddles); a factor 3 runs last, or, with mid3, sits in the middle
 // stage of 2^e . (3 2^mid) . 2^e (mid <= 2); T is the largest power of two
-// with T * E <= P for E = 8 (P < 1024) or 16 operands per thread, capped at
-// 256.  The alternate family (alt = 1) swaps both choices -- radices up to 16
+// with T * E <= P (or <= span, which lets threads idle in some stages) for
+// E = 8 (P < 1024) or 16 operands per thread, capped at 256.  The alternate
+// family (alt = 1) swaps both choices -- radices up to 16
 // and E = 16 below 1024, radices up to 8 and E = 8 from 1024 -- which changes
 // the radix split and the threads per transform; the autotuner times both.
 // It falls back to the default where it would leave teams of fewer than 8
 // threads or more than 16 operands per thread.
-constexpr FftPlan make_fft_plan_rule(int P, int maxbits, int E, bool mid3 = false) {
+constexpr FftPlan make_fft_plan_rule(int P, int maxbits, int E, bool mid3 = false, int span = 0) {
     FftPlan p{};
     p.P = P;
     int m = P, threes = 0;
@@ -333,7 +334,7 @@ constexpr FftPlan make_fft_plan_rule(int P, int maxbits, int E, bool mid3 = fals
             p.r[2] = 1 << e;
             p.n = 3;
             int T = 1;
-            while (T * 2 * E <= P && T < 256) T *= 2;
+            while (T * 2 * E <= (span ? span : P) && T < 256) T *= 2;
             p.T = T;
             int vmax = 0;
             for (int s = 0; s < 3; ++s) {
@@ -382,11 +383,18 @@ constexpr FftPlan make_fft_plan(int P, int alt = 0) {
     if (P % 3 == 0) {
         // lengths 3 * 2^a: by default three stages with the factor 3 in the
         // middle one (a palindrome: one LDS exchange fewer, and a fused
-        // forward / inverse pair shares its twiddles); the alternate family
-        // is the power-of-two split with the radix 3 last
+        // forward / inverse pair shares its twiddles).  The alternate family
+        // from 192 is the same palindrome on a team of twice the threads
+        // (T E <= 4P/3): the outer radix-2^e stages then leave a quarter of
+        // the threads idle, but each thread holds half the operands (at 384:
+        // 64 threads of 8 instead of 32 of 16, 184 -> 146 VGPRs in the FP64
+        // fused pass); below 192 it is the power-of-two split with the radix
+        // 3 last
         const FftPlan pal = make_fft_plan_rule(P, big ? 4 : 3, big ? 16 : 8, true);
         const FftPlan last = make_fft_plan_rule(P, big ? 4 : 3, big ? 16 : 8, false);
-        return alt ? last : pal;
+        const FftPlan wide = make_fft_plan_rule(P, big ? 4 : 3, big ? 16 : 8, true, 4 * P / 3);
+        if (!alt) return pal;
+        return P >= 192 && wide.T > pal.T && wide.vmax <= 16 ? wide : last;
     }
     const FftPlan def = make_fft_plan_rule(P, big ? 4 : 3, big ? 16 : 8);
     if (!alt) return def;
