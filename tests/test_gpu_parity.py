@@ -80,13 +80,15 @@ def test_parity_rough_density(F, kind, L, N, prec):
 @pytest.mark.parametrize("kind,L,N,lam", [("coulomb3d", (3.0, 5.0, 4.0), (24, 16, 32), None),
                                            ("yukawa3d", (4.0, 4.0, 4.0), (16, 16, 16), 2.0),
                                            ("yukawa3d", (4.0, 4.0, 4.0), (16, 24, 32), 1.0),
+                                           ("coulomb3d", (4.0, 6.0, 4.0), (16, 96, 24), None),
                                            ("log2d", (8.0, 6.0), (48, 32), None),
                                            ("biharmonic2d", (3.0, 4.0), (16, 24), None)])
 def test_tensor_matches_oracle_dft(F, kind, L, N, lam):
     """The GPU spectral octant equals DFT(T(1) + T(2)) / prod P of the oracle.
     The 3D Yukawa boxes are cubes, so W comes from the radial table and the
     last axis takes its rows ordered by a1^2 + a2^2 (a square and a
-    rectangular set of rows)."""
+    rectangular set of rows); the 16 x 96 x 24 Coulomb grid transforms its
+    middle axis at length 192 (3 * 2^6)."""
     plan = F.Plan(kind, L, N, "f64", lam=lam).build()
     got = plan.tensor().numpy()
     T = O.build_tensor(kind, L, N, plan.eps, lam=lam or 0.0)
