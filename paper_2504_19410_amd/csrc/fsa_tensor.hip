@@ -287,11 +287,13 @@ __device__ double cheb_node(int q, int l, double dk) {
     return dk * (q + 0.5 * (1.0 + cospi((double)l / kCheb)));
 }
 
+// out[node] = sum_i g_i J0(kappa r_i) (2D) or sin(kappa r_i)/(kappa r_i) (3D)
+// at the Chebyshev points node = node0 + blockIdx.x
 __global__ __launch_bounds__(256) void k_wq_sum(const double* __restrict__ g,
                                                 const double* __restrict__ rn, int n, int d,
-                                                double dk, double* __restrict__ out) {
+                                                double dk, int node0, double* __restrict__ out) {
     __shared__ double red[256];
-    const int node = blockIdx.x;
+    const int node = node0 + (int)blockIdx.x;
     const double kap = cheb_node(node / (kCheb + 1), node % (kCheb + 1), dk);
     double s = 0.0;
     for (int i = threadIdx.x; i < n; i += 256) {
@@ -716,25 +718,44 @@ hipError_t build_w_table(const KernelParams& kp, int d, const double* L, const i
     const double kmax = std::sqrt(k2);
     // U - U^eps is below 1e-20 of its scale beyond R_end
     const double r_end = win ? 13.0 * eps : 7.0 * eps;
-    // panel width: the oscillation (kmax w <= 6), the window and erfc (eps/4),
-    // the Yukawa decay and the quasi-2D kernel's scale eta
-    double w = std::fmin(6.0 / kmax, 0.25 * eps);
-    if (kp.kind == FSA_YUKAWA_3D || kp.kind == FSA_YUKAWA_2D) w = std::fmin(w, 4.0 / kp.lam);
-    if (kp.kind == FSA_QUASI2D_DDI) w = std::fmin(w, 0.5 * kp.eta);
-    QMesh m{};
-    m.n_uni = (int)std::ceil(r_end / w);
-    m.wu = r_end / m.n_uni;
-    m.sigma = 0.15;
-    // 2D kernels with a logarithm at r = 0: grade the first panel
-    const bool log0 = kp.kind == FSA_LOG_2D || kp.kind == FSA_BIHARMONIC_2D ||
-                      kp.kind == FSA_YUKAWA_2D || kp.kind == FSA_QUASI2D_DDI;
-    m.graded = log0 ? 14 : 0;
-    const int n_nodes = (m.graded ? m.n_uni + m.graded : m.n_uni) * kGl;
     // |k| panels of width 0.5/eps, kCheb + 1 Chebyshev-Lobatto points each
     wt->dk = 0.5 / eps;
     wt->nq = (int)std::ceil(kmax / wt->dk);
     if (wt->nq < 1) wt->nq = 1;
     const int n_k = wt->nq * (kCheb + 1);
+    // In 2D (J0, whose evaluations dominate the build) the |k| panels fall
+    // into 8 bands of equal width, and each band has quadrature nodes of its
+    // own, spaced for the largest |k| of the band:
+    // panel width w with k_top w <= 6 (16 Gauss-Legendre nodes per panel
+    // then integrate J0(k r) or sin(k r)/(k r) to far below double rounding),
+    // and at most eps/4 (the window and erfc), 4/lam (the Yukawa decay) and
+    // eta/2 (the quasi-2D kernel's scale).  The sum costs nodes x points, and
+    // a band of low |k| needs a fraction of the nodes the top band does (2D
+    // Yukawa 2048^2: 1.63 -> 1.33 ms per build).  In 3D, sin(x)/x is cheap and
+    // one band is faster (eight took the 256^3 Yukawa build 0.41 -> 0.46 ms).
+    // 2D kernels with a logarithm at r = 0 grade their first panel.
+    const bool log0 = kp.kind == FSA_LOG_2D || kp.kind == FSA_BIHARMONIC_2D ||
+                      kp.kind == FSA_YUKAWA_2D || kp.kind == FSA_QUASI2D_DDI;
+    constexpr int kBands = 8;
+    const int bands = d == 2 ? kBands : 1;
+    QMesh mesh[kBands];
+    int q0[kBands + 1], off[kBands + 1];
+    q0[0] = 0;
+    off[0] = 0;
+    for (int b = 0; b < bands; ++b) {
+        q0[b + 1] = (int)(((long)wt->nq * (b + 1) + bands - 1) / bands);
+        const double ktop = std::fmin(kmax, q0[b + 1] * wt->dk);
+        double w = std::fmin(6.0 / ktop, 0.25 * eps);
+        if (kp.kind == FSA_YUKAWA_3D || kp.kind == FSA_YUKAWA_2D) w = std::fmin(w, 4.0 / kp.lam);
+        if (kp.kind == FSA_QUASI2D_DDI) w = std::fmin(w, 0.5 * kp.eta);
+        QMesh& m = mesh[b];
+        m.n_uni = (int)std::ceil(r_end / w);
+        m.wu = r_end / m.n_uni;
+        m.sigma = 0.15;
+        m.graded = log0 ? 14 : 0;
+        off[b + 1] = off[b] + (q0[b + 1] > q0[b] ? (m.graded ? m.n_uni + m.graded : m.n_uni) * kGl : 0);
+    }
+    const int n_nodes = off[bands];
     double *g = nullptr, *rn = nullptr, *v = nullptr, *cf = nullptr;
     hipError_t e = hipMallocAsync((void**)&g, sizeof(double) * n_nodes, st);
     if (e == hipSuccess) bufs->push_back(g), e = hipMallocAsync((void**)&rn, sizeof(double) * n_nodes, st);
@@ -743,10 +764,15 @@ hipError_t build_w_table(const KernelParams& kp, int d, const double* L, const i
     if (e != hipSuccess) return e;
     bufs->push_back(cf);
     const Gl16 gl = gauss_legendre16();
-    hipLaunchKernelGGL(k_wq_nodes, dim3((n_nodes + 255) / 256), dim3(256), 0, st, g, rn, m, gl,
-                       d, kp);
-    hipLaunchKernelGGL(k_wq_sum, dim3(n_k), dim3(256), 0, st, (const double*)g,
-                       (const double*)rn, n_nodes, d, wt->dk, v);
+    for (int b = 0; b < bands; ++b) {
+        const int nb = off[b + 1] - off[b], np = q0[b + 1] - q0[b];
+        if (np <= 0) continue;
+        hipLaunchKernelGGL(k_wq_nodes, dim3((nb + 255) / 256), dim3(256), 0, st, g + off[b],
+                           rn + off[b], mesh[b], gl, d, kp);
+        hipLaunchKernelGGL(k_wq_sum, dim3(np * (kCheb + 1)), dim3(256), 0, st,
+                           (const double*)(g + off[b]), (const double*)(rn + off[b]), nb, d,
+                           wt->dk, q0[b] * (kCheb + 1), v);
+    }
     hipLaunchKernelGGL(k_cheb, dim3((n_k + 255) / 256), dim3(256), 0, st, (const double*)v, cf,
                        wt->nq);
     wt->cf = cf;
