@@ -151,6 +151,32 @@ def test_autotune_keeps_parity_and_batch_bitwise(F, prec, tmp_path):
     assert F.tune_get_slabs(prec, N)[0] == slabs
 
 
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_batched_alternate_plans_at_lengths_3_2a(F, prec):
+    """Transforms of lengths 3 * 2^a from 192, where the alternate radix
+    family runs the mid-3 palindrome on a team of twice the threads, in the
+    batched (job table) kernels: every such launch on that family, each
+    result bitwise equal to its solo run and within the oracle tolerance."""
+    shapes = [((8.0, 6.0), (192, 96)), ((6.0, 8.0), (96, 192))]
+    plans, rhos, forced = [], [], 0
+    for i, (L, N) in enumerate(shapes):
+        p = F.Plan("log2d", L, N, prec).build()
+        for (name, n), lines in zip(p.passes(), p.pass_lines()):
+            if n % 3 == 0 and n >= 192 and 1 in F.tune_variants(prec, name, n):
+                F.tune_set(prec, name, n, 1, 0, lines)
+                forced += 1
+        plans.append(p)
+        rhos.append(torch.from_numpy(density(L, N, 40 + i)).to(F.DTYPES[prec]).cuda())
+    assert forced >= 4   # conv 384; r2c, conv and c2r at 192
+    solo = [p.apply(r) for p, r in zip(plans, rhos)]
+    outs = F.apply_batched(plans, rhos)
+    torch.cuda.synchronize()
+    for p, r, a, b in zip(plans, rhos, solo, outs):
+        assert torch.equal(a, b)
+        ref = O.solve("log2d", p.L, p.N, r.double().cpu().numpy(), eps=p.eps)
+        check(b.double().cpu().numpy(), ref, prec, f"batched alt {p.N} {prec}")
+
+
 def test_autotune_batched_tunes_the_batch_size_classes(F):
     """fsa_autotune_batched stores a choice for every launch of the batch
     among the batched entries, under the launch's own size class (many
