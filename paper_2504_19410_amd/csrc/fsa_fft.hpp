@@ -381,20 +381,21 @@ constexpr FftPlan make_fft_plan_rule(int P, int maxbits, int E, bool mid3 = fals
 constexpr FftPlan make_fft_plan(int P, int alt = 0) {
     const bool big = P >= 1024;
     if (P % 3 == 0) {
-        // lengths 3 * 2^a: by default three stages with the factor 3 in the
-        // middle one (a palindrome: one LDS exchange fewer, and a fused
-        // forward / inverse pair shares its twiddles).  The alternate family
-        // from 192 is the same palindrome on a team of twice the threads
-        // (T E <= 4P/3): the outer radix-2^e stages then leave a quarter of
-        // the threads idle, but each thread holds half the operands (at 384:
-        // 64 threads of 8 instead of 32 of 16, 184 -> 146 VGPRs in the FP64
-        // fused pass); below 192 it is the power-of-two split with the radix
-        // 3 last
+        // lengths 3 * 2^a: three stages with the factor 3 in the middle one
+        // (a palindrome: one LDS exchange fewer, and a fused forward /
+        // inverse pair shares its twiddles).  From 192 the default runs it on
+        // a team of twice the threads (T E <= 4P/3): the outer radix-2^e
+        // stages then leave a quarter of the threads idle, but each thread
+        // holds half the operands (at 384: 64 threads of 8 instead of 32 of
+        // 16, 184 -> 146 VGPRs in the FP64 fused pass, 240 -> 127 us at
+        // 192^3), and the alternate family is the palindrome on the narrower
+        // team; below 192 the default is that palindrome and the alternate
+        // the power-of-two split with the radix 3 last
         const FftPlan pal = make_fft_plan_rule(P, big ? 4 : 3, big ? 16 : 8, true);
         const FftPlan last = make_fft_plan_rule(P, big ? 4 : 3, big ? 16 : 8, false);
         const FftPlan wide = make_fft_plan_rule(P, big ? 4 : 3, big ? 16 : 8, true, 4 * P / 3);
-        if (!alt) return pal;
-        return P >= 192 && wide.T > pal.T && wide.vmax <= 16 ? wide : last;
+        if (P >= 192 && wide.T > pal.T && wide.vmax <= 16) return alt ? pal : wide;
+        return alt ? last : pal;
     }
     const FftPlan def = make_fft_plan_rule(P, big ? 4 : 3, big ? 16 : 8);
     if (!alt) return def;

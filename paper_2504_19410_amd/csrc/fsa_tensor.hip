@@ -385,12 +385,12 @@ constexpr int dct_lines_per_group(int T, int scr, int D) {
     return wt;
 }
 
-// Lengths 3 * 2^a from 192 take the alternate radix family: the mid-3
-// palindrome on a team of twice the threads, half the operands per thread
-// (at 384: 162 -> 66 VGPRs in the generating and middle axes)
+// The default radix family (at lengths 3 * 2^a from 192 the mid-3
+// palindrome on the wider team: at 384, 66 instead of 162 VGPRs in the
+// generating and middle axes)
 template <int P>
 struct Dct {
-    using F = Fft<double, P, false, (P % 3 == 0 && P >= 192) ? 1 : 0>;
+    using F = Fft<double, P, false>;
     static constexpr int N = P / 2, D = N + 1;
     static constexpr int T = F::T;
     static constexpr int WT = dct_lines_per_group(T, F::SCR, D);

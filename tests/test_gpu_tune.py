@@ -151,19 +151,20 @@ def test_autotune_keeps_parity_and_batch_bitwise(F, prec, tmp_path):
     assert F.tune_get_slabs(prec, N)[0] == slabs
 
 
+@pytest.mark.parametrize("variant", [0, 1])
 @pytest.mark.parametrize("prec", ["f32", "f64"])
-def test_batched_alternate_plans_at_lengths_3_2a(F, prec):
-    """Transforms of lengths 3 * 2^a from 192, where the alternate radix
-    family runs the mid-3 palindrome on a team of twice the threads, in the
-    batched (job table) kernels: every such launch on that family, each
-    result bitwise equal to its solo run and within the oracle tolerance."""
+def test_batched_plans_at_lengths_3_2a(F, prec, variant):
+    """Transforms of lengths 3 * 2^a from 192 in the batched (job table)
+    kernels, every such launch on one radix family (0: the mid-3 palindrome
+    on the wider team, 1: on the narrower one): each result bitwise equal to
+    its solo run and within the oracle tolerance."""
     shapes = [((8.0, 6.0), (192, 96)), ((6.0, 8.0), (96, 192))]
     plans, rhos, forced = [], [], 0
     for i, (L, N) in enumerate(shapes):
         p = F.Plan("log2d", L, N, prec).build()
         for (name, n), lines in zip(p.passes(), p.pass_lines()):
-            if n % 3 == 0 and n >= 192 and 1 in F.tune_variants(prec, name, n):
-                F.tune_set(prec, name, n, 1, 0, lines)
+            if n % 3 == 0 and n >= 192 and variant in F.tune_variants(prec, name, n):
+                F.tune_set(prec, name, n, variant, 0, lines)
                 forced += 1
         plans.append(p)
         rhos.append(torch.from_numpy(density(L, N, 40 + i)).to(F.DTYPES[prec]).cuda())
@@ -174,7 +175,7 @@ def test_batched_alternate_plans_at_lengths_3_2a(F, prec):
     for p, r, a, b in zip(plans, rhos, solo, outs):
         assert torch.equal(a, b)
         ref = O.solve("log2d", p.L, p.N, r.double().cpu().numpy(), eps=p.eps)
-        check(b.double().cpu().numpy(), ref, prec, f"batched alt {p.N} {prec}")
+        check(b.double().cpu().numpy(), ref, prec, f"batched v{variant} {p.N} {prec}")
 
 
 def test_autotune_batched_tunes_the_batch_size_classes(F):
