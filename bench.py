@@ -126,7 +126,7 @@ class Hip:
 
 def kernel_source_hash():
     h = hashlib.sha256()
-    for f in ("fsa_fft.hpp", "fsa_passes.hpp", "fsa_launch.hpp"):
+    for f in ("fsa_fft.hpp", "fsa_walk.hpp", "fsa_passes.hpp", "fsa_launch.hpp"):
         with open(os.path.join(ROOT, "paper_2504_19410_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]

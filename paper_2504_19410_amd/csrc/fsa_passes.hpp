@@ -28,6 +28,7 @@
 
 #include "fsa_fft.hpp"
 #include "fsa_jobs.hpp"
+#include "fsa_walk.hpp"
 
 namespace fsa {
 
@@ -94,40 +95,21 @@ constexpr bool fresh_lane() {
     return (P & (P - 1)) != 0 && (sizeof(R) == 8 || P >= 768);
 }
 
-// The work items one workgroup visits, in order: first, first + stride, ...
-// below last (uniform over the group).
-//   Default: a contiguous chunk per workgroup.
-//   XCD (for tiles whose rows are narrower than a 128-byte cache line, so
-// that neighbouring tiles share lines): the dispatcher deals workgroups to
-// the 8 XCDs in turn (workgroup g runs on XCD g mod 8), and each XCD has its
-// own L2.  Each XCD takes a contiguous eighth of the items, which its
-// workgroups visit side by side (workgroup g, the s-th of its XCD, takes
-// items s, s + G/8, ... of that eighth): neighbouring tiles are in flight at
-// the same time under one L2, so a shared line is read from memory once
-// instead of once per tile.
-struct Walk {
-    int first, last, stride;
-    template <bool XCD>
-    __device__ static Walk make(int items) {
-        const int G = (int)gridDim.x, g = (int)blockIdx.x;
-        if (XCD && G >= 8 && (G & 7) == 0) {
-            const int per = (items + 7) / 8, x = g & 7, s = g >> 3;
-            const int lo = x * per, hi = lo + per < items ? lo + per : items;
-            return Walk{lo + s, hi, G >> 3};
-        }
-        const int c = (items + G - 1) / G;
-        const int first = g * c;
-        return Walk{first, first + c < items ? first + c : items, 1};
-    }
-};
-
 // Whether a transposing tile of WT lines of complex values of `csize` bytes
 // reads and writes rows narrower than a cache line.  Pass A takes the XCD walk
 // then (2D batch, rows of 1024: 300 -> 280 us, HBM fetches 1.075 -> 1.013 x
-// the algorithmic bytes); the other transposing passes keep their chunks:
-// pass E at the same length lost its re-reads (2.3 -> 1.0 x) but ran slower
-// (292 -> 354 us), every workgroup of an XCD reading the same lines at once.
+// the algorithmic bytes).  Pass E of the same rows ran slower under the XCD
+// walk (292 -> 354 us, every workgroup of an XCD reading the same lines at
+// once) and takes the pair walk instead: fetches 2.3 -> 1.09 x the
+// algorithmic bytes at the same time (the Infinity Cache had served the
+// re-reads).  The other transposing passes keep their chunks.
 constexpr bool narrow_rows(int wt, int csize) { return wt * csize < 128; }
+
+// This workgroup's walk over `items` items of the launch.
+template <int MODE>
+__device__ __forceinline__ Walk walk_of(int items) {
+    return Walk::make<MODE>(items, (int)gridDim.x, (int)blockIdx.x);
+}
 
 // ---------------------------------------------------------------------------
 // Work sources.  A pass kernel walks global work items; a source maps an
@@ -221,7 +203,8 @@ __global__ __launch_bounds__((R2c<R, M, VAR>::THREADS)) void k_r2c(
             w2[i] = tw2M[k < K::H ? k : 0];
         }
     }
-    const Walk ch = Walk::make<narrow_rows(K::WT, (int)sizeof(C))>(src.total);
+    const Walk ch =
+        walk_of<narrow_rows(K::WT, (int)sizeof(C)) ? kWalkXcd : kWalkChunk>(src.total);
     C pf[K::NBT0 * K::HALF];
     int cur_pf = -1, cur_it = -1;  // job cursors of the prefetch and the item walks
     auto prefetch = [&](int item) {
@@ -334,7 +317,8 @@ __global__ __launch_bounds__((C2r<R, M, VAR>::THREADS)) void k_c2r(
     if constexpr (F::REG_TW) F::load_tw(w, tid, twM);
     C w2[F::REG_TW ? F::V : 1];  // e^{-i pi k / M} at this thread's first-stage indices k
     if constexpr (F::REG_TW) F::load_first(w2, tid, M, [&](int k) { return tw2M[k]; });
-    const Walk ch = Walk::make<false>(src.total);
+    const Walk ch =
+        walk_of<narrow_rows(K::WT, (int)sizeof(C)) ? kWalkPair : kWalkChunk>(src.total);
     C tp[K::PREFETCH ? K::NT : 1];
     auto tile_elem = [&](const JobC2r& jb, int outer, int col0, int e) {
         const int k = e / K::WT, ww = e - k * K::WT;
@@ -448,7 +432,7 @@ __global__ __launch_bounds__((FwdT<R, P, VAR>::THREADS)) void k_fwd_t(
     C* scr = lds + team * F::SCR;
     C w[F::REG_TW ? F::NTW : 1];
     if constexpr (F::REG_TW) F::load_tw(w, tid, tw);
-    const Walk ch = Walk::make<false>(src.total);
+    const Walk ch = walk_of<kWalkChunk>(src.total);
     C pf[K::NBT0 * K::HALF];
     int cur_pf = -1, cur_it = -1;  // job cursors of the prefetch and the item walks
     auto prefetch = [&](int item) {
@@ -533,7 +517,7 @@ __global__ __launch_bounds__((InvT<R, P, VAR>::THREADS)) void k_inv_t(
     C* scr = lds + team * F::SCR;
     C w[F::REG_TW ? F::NTW : 1];
     if constexpr (F::REG_TW) F::load_tw(w, tid, tw);
-    const Walk ch = Walk::make<false>(src.total);
+    const Walk ch = walk_of<kWalkChunk>(src.total);
     C tp[K::PREFETCH ? K::NT : 1];
     auto tile_elem = [&](const JobT& jb, int p2, int col0, int e) {
         const int p1 = e / K::WT, ww = e - p1 * K::WT;

@@ -183,3 +183,14 @@ def test_team_fft_emulation(tmp_path):
     r = subprocess.run([str(exe)], capture_output=True, text=True, timeout=300)
     assert r.returncode == 0, r.stdout + r.stderr
     assert "OK" in r.stdout
+
+
+def test_work_walks_partition_the_items(tmp_path):
+    """Every work walk of the persistent pass kernels visits each item once,
+    in increasing order per workgroup (tests/host/walk_check.cpp)."""
+    exe = tmp_path / "walk_check"
+    src = os.path.join(ROOT, "tests", "host", "walk_check.cpp")
+    subprocess.run(["g++", "-O2", "-std=c++17", src, "-o", str(exe)], check=True)
+    r = subprocess.run([str(exe)], capture_output=True, text=True, timeout=300)
+    assert r.returncode == 0, r.stdout + r.stderr
+    assert "OK" in r.stdout
